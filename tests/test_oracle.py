@@ -1,0 +1,442 @@
+"""Pins of the CPU oracle against what the mathematics fixes.
+
+None of these re-type the oracle's formulas: each checks a property that an
+independent route determines (exact rational lattice moments, Fourier
+eigenvalues of the stencil, the variational derivative of a discrete free
+energy, a thermodynamic and a mechanical identity of the stress, exact
+conservation and permutation properties, lattice symmetries, and closed-form
+hydrodynamic decay rates).  A dropped term, a wrong sign, a wrong weight or a
+transposed index in the oracle breaks at least one of them.
+"""
+from fractions import Fraction
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import lbinputs
+import oracle
+import oracle.reverse as R
+
+
+def _params(shape, **kw):
+    base = dict(lbinputs.SPINODAL_PARAMS)
+    base.update(kw)
+    return oracle.Params(*shape, **base)
+
+
+# ---------------------------------------------------------------- lattice --
+
+def test_lattice_exact_moments():
+    """D3Q19 isotropy up to 4th order, in exact rational arithmetic."""
+    c, w = oracle.lattice()
+    wf = [Fraction(x).limit_denominator(1000) for x in w]
+    # the float weights are exactly the rationals they stand for
+    for x, q in zip(w, wf):
+        assert float(q) == x
+    assert sorted(set(wf)) == [Fraction(1, 36), Fraction(1, 18), Fraction(1, 3)]
+    # 1 rest + 6 faces + 12 edges, closed under negation, all distinct
+    c2 = (c * c).sum(1)
+    assert sorted(c2.tolist()) == [0] + [1] * 6 + [2] * 12
+    assert len({tuple(v) for v in c.tolist()}) == 19
+    for v in c.tolist():
+        assert [-x for x in v] in c.tolist()
+    assert sum(wf) == 1
+    for a in range(3):
+        assert sum(wi * int(ci[a]) for wi, ci in zip(wf, c)) == 0
+        for b in range(3):
+            m2 = sum(wi * int(ci[a]) * int(ci[b]) for wi, ci in zip(wf, c))
+            assert m2 == (Fraction(1, 3) if a == b else 0)
+            for g in range(3):
+                assert sum(wi * int(ci[a] * ci[b] * ci[g]) for wi, ci in zip(wf, c)) == 0
+    # fourth order: sum w c_a c_b c_c c_d = (1/9)(d_ab d_cd + d_ac d_bd + d_ad d_bc)
+    for a in range(3):
+        for b in range(3):
+            for g in range(3):
+                for d in range(3):
+                    m4 = sum(wi * int(ci[a] * ci[b] * ci[g] * ci[d]) for wi, ci in zip(wf, c))
+                    iso = Fraction(1, 9) * ((a == b) * (g == d) + (a == g) * (b == d)
+                                            + (a == d) * (b == g))
+                    assert m4 == iso
+    # weights depend only on |c|^2 and the velocity order is rest, +-x, +-y, +-z, edges
+    assert c[0].tolist() == [0, 0, 0]
+    assert c[1:7].tolist() == [[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]]
+
+
+# ---------------------------------------------------------------- stencil --
+
+@pytest.mark.parametrize("shape,mode", [((8, 10, 12), (1, 2, 3)), ((16, 5, 7), (3, 1, 2))])
+def test_stencil_fourier_eigenvalues(shape, mode):
+    """D_a cos(q.x) = -sin(q_a) sin(q.x);  lap cos(q.x) = -sum 2(1-cos q_a) cos(q.x)."""
+    p = _params(shape)
+    q = [2 * math.pi * m / n for m, n in zip(mode, shape)]
+    xs = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    arg = sum(qa * xa for qa, xa in zip(q, xs))
+    grad, lap = oracle.gradients(p, np.cos(arg))
+    for a in range(3):
+        np.testing.assert_allclose(grad[a], -math.sin(q[a]) * np.sin(arg), atol=1e-14)
+    lam = -sum(2 * (1 - math.cos(qa)) for qa in q)
+    np.testing.assert_allclose(lap, lam * np.cos(arg), atol=1e-13)
+
+
+def test_stencil_axis_identity():
+    """A field varying along one axis only has a gradient along that axis only."""
+    shape = (6, 7, 9)
+    p = _params(shape)
+    for axis in range(3):
+        prof = np.random.default_rng(axis).standard_normal(shape[axis])
+        sl = [None, None, None]
+        sl[axis] = slice(None)
+        phi = np.broadcast_to(prof[tuple(sl)], shape).copy()
+        grad, lap = oracle.gradients(p, phi)
+        for a in range(3):
+            if a != axis:
+                assert np.all(grad[a] == 0.0)
+        expect = 0.5 * (np.roll(prof, -1) - np.roll(prof, 1))
+        np.testing.assert_allclose(grad[axis], np.broadcast_to(expect[tuple(sl)], shape), atol=1e-15)
+
+
+# ------------------------------------------------------- chemical stress --
+
+def test_mu_is_variational_derivative():
+    """mu = dF/dphi for F = sum_x [A/2 phi^2 + B/4 phi^4 + kappa/2 sum_a (phi(x+e_a)-phi(x))^2].
+
+    The forward-difference gradient energy has exactly the 7-point Laplacian
+    as its variational derivative, so this pins mu's sign, powers and the
+    stencil at once (autograd on F, a different function from mu).
+    """
+    shape = (7, 8, 9)
+    p = _params(shape, A=-0.031, B=0.047, kappa=0.013)
+    phi = lbinputs.random_field(shape, 11)
+    t = torch.tensor(phi, requires_grad=True)
+    F = (0.5 * p.A * t ** 2 + 0.25 * p.B * t ** 4).sum()
+    for a in range(3):
+        F = F + 0.5 * p.kappa * ((torch.roll(t, -1, a) - t) ** 2).sum()
+    F.backward()
+    grad, lap = oracle.gradients(p, phi)
+    mu, _ = oracle.chemical(p, phi, grad, lap)
+    np.testing.assert_allclose(mu, t.grad.numpy(), rtol=0, atol=1e-15)
+
+
+def test_pressure_isotropic_part_is_thermodynamic():
+    """tr(Pi)/3 - kappa|grad phi|^2/3 = phi mu - psi (bulk pressure p0 = phi mu - psi)."""
+    shape = (6, 7, 8)
+    p = _params(shape, A=-0.02, B=0.03, kappa=0.011)
+    phi = lbinputs.random_field(shape, 5)
+    grad, lap = oracle.gradients(p, phi)
+    mu, pi = oracle.chemical(p, phi, grad, lap)
+    g2 = (grad ** 2).sum(0)
+    psi = 0.5 * p.A * phi ** 2 + 0.25 * p.B * phi ** 4 + 0.5 * p.kappa * g2
+    tr = pi[0] + pi[3] + pi[5]
+    np.testing.assert_allclose((tr - p.kappa * g2) / 3.0, phi * mu - psi, atol=1e-16)
+
+
+def test_gibbs_duhem_mechanical_identity():
+    """d_b Pi_ab = phi d_a mu in the continuum: on a smooth field the lattice
+    versions agree to O(k^2), while any sign/term error leaves an O(1) gap."""
+    n = 48
+    p = _params((n, n, n), A=-0.05, B=0.05, kappa=0.02)
+    k = 2 * math.pi / n
+    x, y, z = np.meshgrid(*[np.arange(n)] * 3, indexing="ij")
+    phi = (0.5 * np.sin(k * x) + 0.3 * np.cos(k * y + 0.4) + 0.2 * np.sin(k * z + 1.1)
+           + 0.25 * np.sin(k * (x + y)) + 0.15 * np.cos(k * (y - z)))
+    grad, lap = oracle.gradients(p, phi)
+    mu, pi = oracle.chemical(p, phi, grad, lap)
+    full = {(0, 0): pi[0], (0, 1): pi[1], (0, 2): pi[2], (1, 1): pi[3], (1, 2): pi[4],
+            (2, 2): pi[5]}
+
+    def comp(a, b):
+        return full[(min(a, b), max(a, b))]
+
+    def d(field, a):
+        return 0.5 * (np.roll(field, -1, a) - np.roll(field, 1, a))
+
+    scale = max(np.abs(phi * d(mu, a)).max() for a in range(3))
+    for a in range(3):
+        div = sum(d(comp(a, b), b) for b in range(3))
+        err = np.abs(div - phi * d(mu, a)).max()
+        assert err < 0.02 * scale, (a, err, scale)
+
+
+def test_chemical_hand_values():
+    """Bulk phases phi = +-sqrt(-A/B): mu = 0 and Pi = (A/2 + 3B/4) I = 0.0015625 I."""
+    shape = (4, 4, 4)
+    p = _params(shape)
+    for s in (1.0, -1.0):
+        phi = np.full(shape, s)
+        grad, lap = oracle.gradients(p, phi)
+        mu, pi = oracle.chemical(p, phi, grad, lap)
+        assert np.all(grad == 0) and np.all(lap == 0)
+        np.testing.assert_allclose(mu, 0.0, atol=1e-18)
+        np.testing.assert_allclose(pi[[0, 3, 5]], 0.0015625, rtol=1e-14)
+        np.testing.assert_allclose(pi[[1, 2, 4]], 0.0, atol=0)
+
+
+# ----------------------------------------------------------- equilibria --
+
+def _moment_checks(p, rho, j, phi, mu, pi6, feq, geq):
+    c, _ = oracle.lattice()
+    c = c.astype(np.float64)
+    u = np.asarray(j) / rho
+    pim = np.array([[pi6[0], pi6[1], pi6[2]], [pi6[1], pi6[3], pi6[4]], [pi6[2], pi6[4], pi6[5]]])
+    np.testing.assert_allclose(feq.sum(), rho, rtol=1e-15)
+    np.testing.assert_allclose(feq @ c, j, atol=1e-16)
+    m2 = np.einsum("i,ia,ib->ab", feq, c, c)
+    np.testing.assert_allclose(m2, rho / 3.0 * np.eye(3) + pim + rho * np.outer(u, u),
+                               atol=2e-16)
+    np.testing.assert_allclose(geq.sum(), phi, atol=2e-16)
+    np.testing.assert_allclose(geq @ c, phi * u, atol=2e-17)
+    m2g = np.einsum("i,ia,ib->ab", geq, c, c)
+    np.testing.assert_allclose(m2g, p.gamma * mu * np.eye(3) + phi * np.outer(u, u), atol=2e-17)
+
+
+def test_equilibrium_moments_exact():
+    """sum feq (1, c, cc) = (rho, j, rho/3 I + Pi + rho u u); same for g with Gamma mu I + phi u u."""
+    rng = np.random.default_rng(7)
+    p = _params((3, 3, 3), gamma=0.37)
+    for _ in range(50):
+        rho = 1.0 + 0.1 * rng.standard_normal()
+        j = 0.05 * rng.standard_normal(3)
+        phi = rng.uniform(-1, 1)
+        mu = 0.01 * rng.standard_normal()
+        pi6 = 0.01 * rng.standard_normal(6)
+        feq, geq = oracle.equilibrium_site(p, rho, j, phi, mu, pi6)
+        _moment_checks(p, rho, j, phi, mu, pi6, feq, geq)
+
+
+def test_equilibrium_rest_state():
+    """rho0 at rest with phi = 0, Pi = 0: feq = w rho0 and geq = 0."""
+    p = _params((3, 3, 3))
+    _, w = oracle.lattice()
+    feq, geq = oracle.equilibrium_site(p, 1.0, np.zeros(3), 0.0, 0.0, np.zeros(6))
+    np.testing.assert_allclose(feq, w, rtol=1e-15)
+    np.testing.assert_allclose(geq, 0.0, atol=0)
+
+
+# ----------------------------------------------------------- collision --
+
+def test_collision_conserves_per_site_and_tau1_gives_equilibrium():
+    shape = (4, 5, 6)
+    c, _ = oracle.lattice()
+    for tf, tg in ((0.8, 1.3), (1.0, 1.0)):
+        p = _params(shape, tau_f=tf, tau_g=tg)
+        rng = np.random.default_rng(3)
+        f0, g0 = oracle.init(p, lbinputs.spinodal_phi0(shape, seed=9))
+        f = f0 + 0.01 * rng.standard_normal(f0.shape) / 19
+        g = g0 + 0.01 * rng.standard_normal(g0.shape) / 19
+        phi = oracle.order_parameter(p, g)
+        grad, lap = oracle.gradients(p, phi)
+        mu, pi = oracle.chemical(p, phi, grad, lap)
+        fs, gs = oracle.collide(p, f, g, phi, mu, pi)
+        np.testing.assert_allclose(fs.sum(0), f.sum(0), atol=1e-15)
+        np.testing.assert_allclose(np.einsum("ia,ixyz->axyz", c, fs),
+                                   np.einsum("ia,ixyz->axyz", c, f), atol=1e-16)
+        np.testing.assert_allclose(gs.sum(0), g.sum(0), atol=1e-16)
+        if tf == 1.0:
+            s = (1, 2, 3)
+            rho = f[(slice(None),) + s].sum()
+            j = c.T @ f[(slice(None),) + s]
+            feq, geq = oracle.equilibrium_site(p, rho, j, phi[s], mu[s], pi[(slice(None),) + s])
+            np.testing.assert_allclose(fs[(slice(None),) + s], feq, atol=1e-16)
+            np.testing.assert_allclose(gs[(slice(None),) + s], geq, atol=1e-16)
+
+
+# ----------------------------------------------------------- streaming --
+
+def test_stream_moves_delta_to_x_plus_c():
+    shape = (5, 6, 7)
+    p = _params(shape)
+    c, _ = oracle.lattice()
+    x0 = (4, 0, 3)
+    for i in range(19):
+        d = np.zeros((19,) + shape)
+        d[(i,) + x0] = 1.0
+        out = oracle.stream(p, d)
+        dest = tuple((x0[a] + c[i, a]) % shape[a] for a in range(3))
+        assert out[(i,) + dest] == 1.0
+        assert out.sum() == 1.0
+
+
+def test_stream_is_permutation_and_L_steps_are_identity():
+    shape = (4, 4, 4)
+    p = _params(shape)
+    d = lbinputs.random_field((19,) + shape, 21)
+    out = oracle.stream(p, d)
+    for i in range(19):
+        assert np.array_equal(np.sort(out[i].ravel()), np.sort(d[i].ravel()))
+    cur = d
+    for _ in range(4):
+        cur = oracle.stream(p, cur)
+    assert np.array_equal(cur, d)  # bit-exact round trip
+
+
+# ------------------------------------------------------------ full step --
+
+def _perturbed_state(p, seed):
+    f, g = oracle.init(p, lbinputs.spinodal_phi0(p.shape, seed=seed))
+    rng = np.random.default_rng(seed)
+    f = f + 1e-3 * rng.standard_normal(f.shape) * oracle.lattice()[1][:, None, None, None]
+    return f, g
+
+
+def test_global_conservation():
+    """sum rho, sum phi and total momentum are conserved to round-off."""
+    p = _params((6, 7, 8), tau_f=0.8, tau_g=1.3)
+    f, g = _perturbed_state(p, 4)
+    s0 = oracle.sums(p, f, g)
+    assert abs(s0[2]) + abs(s0[3]) + abs(s0[4]) > 1e-4  # non-trivial momentum
+    f2, g2 = oracle.run(p, f, g, 40)
+    s1 = oracle.sums(p, f2, g2)
+    np.testing.assert_allclose(s1, s0, rtol=0, atol=1e-12)
+
+
+def test_uniform_equilibrium_is_fixed_point():
+    shape = (4, 5, 3)
+    p = _params(shape, tau_f=0.8, tau_g=1.3)
+    phib = 0.3
+    mu = p.A * phib + p.B * phib ** 3
+    iso = 0.5 * p.A * phib ** 2 + 0.75 * p.B * phib ** 4
+    feq, geq = oracle.equilibrium_site(p, 1.0, np.zeros(3), phib, mu,
+                                       np.array([iso, 0, 0, iso, 0, iso]))
+    f = np.broadcast_to(feq[:, None, None, None], (19,) + shape).copy()
+    g = np.broadcast_to(geq[:, None, None, None], (19,) + shape).copy()
+    f2, g2 = oracle.run(p, f, g, 10)
+    # a few ulp of round-off per step (sum of the 19 equilibria vs rho)
+    np.testing.assert_allclose(f2, f, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(g2, g, rtol=1e-14, atol=1e-17)
+
+
+def test_periodic_shift_invariance_bit_exact():
+    shape = (5, 6, 7)
+    p = _params(shape, tau_f=0.8, tau_g=1.3)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=3)
+    f, g = oracle.run(p, *oracle.init(p, phi0), 6)
+    sh = (2, -1, 3)
+    fs, gs = oracle.run(p, *oracle.init(p, np.roll(phi0, sh, (0, 1, 2))), 6)
+    assert np.array_equal(fs, np.roll(f, sh, (1, 2, 3)))
+    assert np.array_equal(gs, np.roll(g, sh, (1, 2, 3)))
+
+
+def test_cubic_symmetry_equivariance():
+    """Swapping x and y, or reflecting x, maps the solution to the transformed one."""
+    shape = (6, 6, 5)
+    p = _params(shape, tau_f=0.8, tau_g=1.3)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=8)
+    f, g = oracle.run(p, *oracle.init(p, phi0), 8)
+    rho, u, phi = oracle.moments(p, f, g)
+    # swap x <-> y
+    f2, g2 = oracle.run(p, *oracle.init(p, phi0.transpose(1, 0, 2).copy()), 8)
+    rho2, u2, phi2 = oracle.moments(p, f2, g2)
+    np.testing.assert_allclose(phi2, phi.transpose(1, 0, 2), atol=1e-14)
+    np.testing.assert_allclose(u2[0], u[1].transpose(1, 0, 2), atol=1e-15)
+    np.testing.assert_allclose(u2[1], u[0].transpose(1, 0, 2), atol=1e-15)
+    # reflect x -> -x (mod L)
+    ref = lambda a: np.roll(a[::-1], 1, 0)  # noqa: E731  x -> (L - x) mod L
+    f3, g3 = oracle.run(p, *oracle.init(p, ref(phi0).copy()), 8)
+    rho3, u3, phi3 = oracle.moments(p, f3, g3)
+    np.testing.assert_allclose(phi3, ref(phi), atol=1e-14)
+    np.testing.assert_allclose(u3[0], -ref(u[0]), atol=1e-15)
+    np.testing.assert_allclose(u3[2], ref(u[2]), atol=1e-15)
+    np.testing.assert_allclose(rho3, ref(rho), atol=1e-14)
+
+
+def test_two_transcriptions_agree():
+    """The per-site C loops and the whole-lattice torch re-expression agree."""
+    shape = (5, 6, 7)
+    p = _params(shape, tau_f=0.8, tau_g=1.3)
+    f, g = _perturbed_state(p, 12)
+    fc, gc = oracle.run(p, f, g, 15)
+    tf, tg = torch.tensor(f), torch.tensor(g)
+    for _ in range(15):
+        tf, tg = R.step(tf, tg, p.A, p.B, p.kappa, p.gamma, p.tau_f, p.tau_g)
+    np.testing.assert_allclose(tf.numpy(), fc, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(tg.numpy(), gc, rtol=0, atol=1e-15)
+
+
+# ------------------------------------------ hydrodynamic closed forms --
+
+def test_shear_wave_decays_with_bgk_viscosity():
+    """u_y = U sin(kx) decays as exp(-nu k^2 t) with nu = (tau_f - 1/2)/3."""
+    n = 32
+    shape = (n, 3, 3)
+    p = _params(shape, tau_f=0.8, tau_g=1.0)
+    k = 2 * math.pi / n
+    U = 1e-5
+    f = np.zeros((19,) + shape)
+    for x in range(n):
+        feq, _ = oracle.equilibrium_site(p, 1.0, np.array([0.0, U * math.sin(k * x), 0.0]),
+                                         0.0, 0.0, np.zeros(6))
+        f[:, x] = feq[:, None, None]
+    g = np.zeros_like(f)
+
+    def amp(f):
+        rho, u, _ = oracle.moments(p, f, g)
+        return 2.0 / n * (u[1][:, 0, 0] * np.sin(k * np.arange(n))).sum()
+
+    f1, _ = oracle.run(p, f, g, 20)
+    f2, _ = oracle.run(p, f1, g, 300)
+    nu_meas = -math.log(amp(f2) / amp(f1)) / (300 * k * k)
+    nu = (p.tau_f - 0.5) / 3.0
+    assert abs(nu_meas / nu - 1) < 5e-3, nu_meas
+
+
+def test_order_parameter_relaxes_by_cahn_hilliard():
+    """Small phi = eps cos(kx), A > 0: decay rate M k^2 (A + kappa k^2), M = Gamma (tau_g - 1/2)."""
+    n = 32
+    shape = (n, 3, 3)
+    p = _params(shape, A=0.1, B=0.0, kappa=0.004, tau_g=1.0, gamma=0.5)
+    k = 2 * math.pi / n
+    phi0 = 1e-4 * np.broadcast_to(np.cos(k * np.arange(n))[:, None, None], shape).copy()
+    f, g = oracle.init(p, phi0)
+
+    def amp(g):
+        phi = g.sum(0)[:, 0, 0]
+        return 2.0 / n * (phi * np.cos(k * np.arange(n))).sum()
+
+    f1, g1 = oracle.run(p, f, g, 30)
+    f2, g2 = oracle.run(p, f1, g1, 400)
+    rate = -math.log(amp(g2) / amp(g1)) / 400
+    M = p.gamma * (p.tau_g - 0.5)
+    expect = M * k * k * (p.A + p.kappa * k * k)
+    assert abs(rate / expect - 1) < 0.02, (rate, expect)
+
+
+# ----------------------------------------------- reverse-mode gradients --
+
+def test_reverse_mode_matches_central_differences():
+    """torch autograd through the re-expressed step vs central differences of
+    the C oracle's forward run (8^3, 20 steps)."""
+    shape = (8, 8, 8)
+    T = 20
+    p = _params(shape, tau_f=0.8, tau_g=1.3)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=77)
+    tgt = lbinputs.lamellar_target(shape, 8, lbinputs.interface_width(p.A, p.kappa))
+
+    def loss(phi0_, A=p.A, B=p.B, kappa=p.kappa):
+        q = oracle.Params(*shape, A=A, B=B, kappa=kappa, gamma=p.gamma, tau_f=p.tau_f,
+                          tau_g=p.tau_g, rho0=p.rho0)
+        f, g = oracle.run(q, *oracle.init(q, phi0_), T)
+        return 0.5 * ((g.sum(0) - tgt) ** 2).sum()
+
+    L, gphi, gA, gB, gk = R.loss_and_grads(phi0, tgt, p.A, p.B, p.kappa, T, p.gamma,
+                                           p.tau_f, p.tau_g, p.rho0)
+    assert abs(L - loss(phi0)) < 1e-12 * abs(L)
+    v = lbinputs.random_field(shape, 5)
+    h = 1e-4
+    fd = (loss(phi0 + h * v) - loss(phi0 - h * v)) / (2 * h)
+    assert abs(fd - (gphi * v).sum()) < 1e-7 * abs(fd), (fd, (gphi * v).sum())
+    # single-site component
+    e = np.zeros(shape)
+    e[3, 4, 5] = 1.0
+    fd = (loss(phi0 + h * e) - loss(phi0 - h * e)) / (2 * h)
+    assert abs(fd - gphi[3, 4, 5]) < 1e-6 * max(abs(fd), 1e-3)
+    # L depends on B only through phi^3 (phi ~ 0.05), so B takes a larger step
+    # to stay clear of round-off; the other two are nearly linear.
+    for name, val, gv, rel in (("A", p.A, gA, 1e-4), ("B", p.B, gB, 1e-1),
+                               ("kappa", p.kappa, gk, 1e-4)):
+        hh = rel * abs(val)
+        lp = loss(phi0, **{name: val + hh})
+        lm = loss(phi0, **{name: val - hh})
+        fd = (lp - lm) / (2 * hh)
+        assert abs(fd - gv) < 1e-6 * abs(fd), (name, fd, gv)
