@@ -1,0 +1,241 @@
+"""Throughput of the D3Q19 binary-fluid LB step on one MI355X.
+
+Default workload: the 256^3 periodic tanh droplet (radius 64, width
+sqrt(-2 kappa/A), +-1e-3 seeded noise) with A=-0.00625, B=0.00625,
+kappa=0.004, tau_f=tau_g=1, Gamma=0.5, stepped in FP32 deviation storage (the
+headline line) and in FP64 on the same input; plus the adjoint/forward cost
+of the reverse mode (64^3 FP64 and 128^3 FP32 rollouts) and the oracle timed
+on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line.  A "step" is one full timestep of the lattice (order
+parameter, gradients, chemical stress, collision of f and g, propagation).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# Algorithmic HBM bytes per lattice-site update of one step.  The method must
+# read and write the 19 f and 19 g populations once (76 words); the current
+# two-kernel step also reads g once more to form phi and writes/reads phi.
+def step_bytes_per_site(elem_bytes: int) -> dict:
+    return {"method_min": 76 * elem_bytes,
+            "phi_kernel": 19 * elem_bytes + elem_bytes,
+            "collide_kernel": 76 * elem_bytes + elem_bytes}
+
+
+def time_steps(lb, steps: int, warmup: int):
+    import torch
+    lb.step(warmup)
+    lb.synchronize()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(lb.stream)
+    lb.step(steps)
+    e1.record(lb.stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def copy_probe_gbps(nbytes: int) -> float:
+    """Plain device-to-device copy bandwidth (read + write) at a footprint
+    like the step's: the practical HBM ceiling (the paper's STREAM method)."""
+    import torch
+    n = nbytes // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def adjoint_ratio(shape, T, interval, precision, phi0, tgt, params):
+    """(forward ms for T plain steps, backward ms incl. recompute, grads)."""
+    import torch
+    from paper_1609_01479_amd import LB
+    from paper_1609_01479_amd.rollout import rollout
+    dev = torch.device("cuda:0")
+    lb = LB(shape, precision=precision, device=dev, **params)
+    lb.init_phi(phi0)
+    fwd_ms = time_steps(lb, T, 0)
+    del lb
+    p0 = torch.tensor(phi0, dtype=torch.float64, device=dev, requires_grad=True)
+    th = [torch.tensor(params[k], dtype=torch.float64, device=dev, requires_grad=True)
+          for k in ("A", "B", "kappa")]
+    rest = {k: params[k] for k in ("gamma", "tau_f", "tau_g", "rho0")}
+    phiT = rollout(p0, *th, T, interval=interval, precision=precision, **rest)
+    loss = 0.5 * ((phiT - torch.tensor(tgt, device=dev)) ** 2).sum()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    bwd_ms = (time.perf_counter() - t0) * 1e3
+    grads = (p0.grad.detach().cpu().numpy(), [float(t.grad) for t in th])
+    return fwd_ms, bwd_ms, grads
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lbinputs
+    from paper_1609_01479_amd import LB
+
+    n = args.size
+    shape = (n, n, n)
+    params = dict(lbinputs.SPINODAL_PARAMS)
+    xi = lbinputs.interface_width(params["A"], params["kappa"])
+    radius = n / 4.0
+    log(f"droplet {shape} radius {radius} xi {xi:.5f}")
+    phi0 = lbinputs.droplet_phi0(shape, radius, xi, noise=1e-3, seed=lbinputs.SEED_DROPLET)
+    nsites = n ** 3
+    total = args.warmup + args.steps
+
+    runs = {}
+    precs = ["fp32_dev"] + ([] if args.no_fp64 else ["fp64"])
+    for prec in precs:
+        lb = LB(shape, precision=prec, device="cuda:0", **params)
+        lb.init_phi(phi0)
+        s0 = lb.sums().cpu().numpy()
+        log(f"{prec}: warmup {args.warmup}, timing {args.steps} steps")
+        ms = time_steps(lb, args.steps, args.warmup)
+        s1 = lb.sums().cpu().numpy()
+        rho, u, phi = lb.moments()
+        torch.cuda.synchronize()
+        runs[prec] = dict(ms=ms, elem=int(lb.sizes.elem_bytes), sums0=s0, sums1=s1,
+                          u=u.cpu().numpy(), phi=phi.cpu().numpy())
+        log(f"{prec}: {ms:.1f} ms -> {nsites * args.steps / (ms * 1e-3) / 1e6:.1f} MLUPS")
+        del lb, rho, u, phi
+        torch.cuda.empty_cache()
+
+    prim = runs["fp32_dev"]
+    ms_step = prim["ms"] / args.steps
+    mlups = nsites / (ms_step * 1e-3) / 1e6
+
+    def roof(run):
+        e = run["elem"]
+        b = step_bytes_per_site(e)
+        per_step = b["phi_kernel"] + b["collide_kernel"]
+        t = run["ms"] / args.steps * 1e-3
+        achieved = per_step * nsites / t / 1e9
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "effective_GBps": round(b["method_min"] * nsites / t / 1e9, 1),
+                "bytes_per_site": per_step, "kernel": "step (phi + collide kernels)"}
+
+    out = {
+        "metric": "MLUPS & % peak HBM GB/s, D3Q19 binary 256^3: FP32 vs FP64; adjoint/forward cost",
+        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded tanh droplet + noise)",
+        "config": {"workload": f"D3Q19 binary-fluid droplet {n}^3 periodic, FP32 deviation storage",
+                   "lattice": list(shape), "radius": radius, "xi": round(xi, 6),
+                   "noise": 1e-3, "seed": lbinputs.SEED_DROPLET, **params},
+        "roofline": roof(prim),
+    }
+    prim_sums = prim["sums1"] - prim["sums0"]
+    out["fp32_mass_drift"] = float(prim_sums[0])
+    if "fp64" in runs:
+        r64 = runs["fp64"]
+        ms64 = r64["ms"] / args.steps
+        out["fp64"] = {"value": round(nsites / (ms64 * 1e-3) / 1e6, 1), "unit": "MLUPS",
+                       "ms_per_step": round(ms64, 4), "roofline": roof(r64),
+                       "mass_drift": float(r64["sums1"][0] - r64["sums0"][0])}
+        out["fp32_over_fp64_speedup"] = round(ms64 / ms_step, 3)
+        dphi = np.abs(prim["phi"] - r64["phi"])
+        du = np.abs(prim["u"] - r64["u"])
+        out["fp32_vs_fp64_error"] = {"after_steps": total,
+                                     "phi_max": float(dphi.max()),
+                                     "phi_rms": float(np.sqrt((dphi ** 2).mean())),
+                                     "u_max": float(du.max()),
+                                     "u_rms": float(np.sqrt((du ** 2).mean()))}
+    del runs
+
+    out["copy_probe_GBps"] = round(copy_probe_gbps(2 * 1024 ** 3), 1)
+
+    if not args.no_adjoint:
+        adj = {}
+        for name, nn, T, k, prec in (("64^3_fp64_T200", 64, 200, 15, "fp64"),
+                                     ("128^3_fp32_T1000", 128, 1000, 32, "fp32_dev")):
+            sh = (nn, nn, nn)
+            ph0 = lbinputs.spinodal_phi0(sh)
+            tgt = lbinputs.lamellar_target(sh, 32, xi)
+            log(f"adjoint {name}")
+            fwd, bwd, g = adjoint_ratio(sh, T, k, prec, ph0, tgt, params)
+            entry = {"forward_ms": round(fwd, 2), "backward_ms": round(bwd, 2),
+                     "adjoint_over_forward": round(bwd / fwd, 3), "interval": k}
+            if prec == "fp32_dev":
+                _, _, g64 = adjoint_ratio(sh, T, k, "fp64", ph0, tgt, params)
+                entry["grad_rel_err_vs_fp64"] = {
+                    "phi0_l2": float(np.linalg.norm(g[0] - g64[0]) / np.linalg.norm(g64[0])),
+                    "A": g[1][0] / g64[1][0] - 1, "B": g[1][1] / g64[1][1] - 1,
+                    "kappa": g[1][2] / g64[1][2] - 1}
+            adj[name] = entry
+            torch.cuda.empty_cache()
+        out["adjoint"] = adj
+
+    if not args.no_cpu_baseline:
+        import oracle
+        p = oracle.Params(*shape, **params)
+        f, g = oracle.init(p, phi0)
+        cores = len(os.sched_getaffinity(0))
+        log(f"oracle: 1 step at {shape} on {cores} threads")
+        t0 = time.perf_counter()
+        oracle.run(p, f, g, 1)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(nsites / dt / 1e6, 3), "unit": "MLUPS",
+                               "cores": cores, "kind": "oracle",
+                               "sample": f"1 FP64 step of the same {n}^3 droplet lattice "
+                                         f"({dt:.1f} s)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * lb.h -- C ABI of the MI355X (gfx950) D3Q19 binary-fluid lattice-Boltzmann
+ * library.
+ *
+ * One timestep is the Ludwig timestep of Gray & Stratford, "A Lightweight
+ * Approach to Performance Portability with targetDP" (Sec. 2.1.1: order
+ * parameter gradients, chemical stress, collision, propagation) for a
+ * symmetric binary fluid:
+ *
+ *   phi = sum_i g_i                         order parameter
+ *   d_a phi, lap phi                        7-point central differences
+ *   mu  = A phi + B phi^3 - kappa lap phi   chemical potential
+ *   Pi  = [A/2 phi^2 + 3B/4 phi^4 - kappa phi lap phi - kappa/2 |grad phi|^2] I
+ *         + kappa grad phi grad phi         chemical stress
+ *   rho = sum_i f_i, j = sum_i f_i c_i, u = j/rho
+ *   f_i^eq = w_i [rho + 3 c_i.j + 9/2 Q_i:(Pi + rho u u)]
+ *   g_i^eq = w_i [phi + 3 phi c_i.u + 9/2 Q_i:((Gamma mu - phi/3) I + phi u u)]
+ *   f_i <- f_i - (f_i - f_i^eq)/tau_f,  g_i <- g_i - (g_i - g_i^eq)/tau_g
+ *   f_i(x + c_i, t+1) = f_i*(x, t)          periodic propagation (same for g)
+ *
+ * with Q_i = c_i c_i - I/3, weights 1/3 (rest), 1/18 (6 faces), 1/36 (12
+ * edges).  Velocity order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 =
+ * (+x+y),(-x-y),(+x-y),(-x+y),(+x+z),(-x-z),(+x-z),(-x+z),(+y+z),(-y-z),
+ * (+y-z),(-y+z).
+ *
+ * The host call sequence follows the paper's host model (Sec. 3.2.3, Fig. 2:
+ * allocate, copy in, launch, synchronise, copy out, reduce): the caller owns
+ * every device byte (sized by lb_query_sizes), lb_init_phi is the copy-in,
+ * lb_step the launches, lb_moments / lb_sums the copy-out and the reduction
+ * (the paper's targetDoubleSum).
+ *
+ * Conventions shared by every call:
+ *  - Public fields are dense C-order arrays of shape (nx, ny, nz): site
+ *    (x, y, z) is element (x*ny + y)*nz + z, so z is contiguous.  Vector
+ *    fields are three such planes (x, y, z components), distributions 19.
+ *  - Pointers named *_dev are device pointers (hipMalloc or torch CUDA
+ *    tensors); all other pointers are host pointers.
+ *  - Device buffers must be 256-byte aligned (LB_EALIGN otherwise).
+ *  - Every call is asynchronous and ordered on the context's HIP stream; the
+ *    caller synchronises.  Argument errors are reported synchronously before
+ *    anything is launched; launch errors through hipGetLastError (LB_EHIP);
+ *    device faults surface at the caller's next synchronisation.
+ *  - A context is not reentrant: one context per stream, one thread at a
+ *    time.  The library never allocates or frees device memory and keeps only
+ *    borrowed pointers, which must outlive the context.
+ *  - lb_last_error() returns a thread-local text for the last failure.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_ABI_VERSION 1
+#define LB_NVEL 19
+
+typedef enum {
+    LB_OK = 0,
+    LB_EINVAL = 1, /* bad argument value (tau <= 1/2, rho0 <= 0, NULL, ...) */
+    LB_ESHAPE = 2, /* bad lattice extents                                     */
+    LB_EALIGN = 3, /* device pointer not 256-byte aligned                     */
+    LB_EHIP = 4,   /* a HIP runtime call or kernel launch failed              */
+    LB_ESTATE = 5  /* call not valid in the context's state (e.g. no adjoint) */
+} lb_status;
+
+typedef enum {
+    LB_FP64 = 0,    /* distributions stored and collided in FP64            */
+    LB_FP32_DEV = 1 /* FP32 storage of f_i - w_i rho0 and of g_i, FP32
+                       collision; FP64 reductions and parameter gradients   */
+} lb_precision;
+
+/* Lattice and model.  nx, ny, nz >= 1 with nx*ny*nz < 2^31 (periodic in all
+ * three directions); tau_f, tau_g > 1/2; rho0 > 0. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double A, B, kappa; /* free energy A/2 phi^2 + B/4 phi^4 + kappa/2 |grad phi|^2 */
+    double gamma;       /* mobility parameter Gamma in g^eq                         */
+    double tau_f, tau_g;
+    double rho0;        /* rest density of the initial state                        */
+    int32_t precision;  /* lb_precision                                             */
+} lb_params;
+
+/* Sizes in bytes of the caller-owned device buffers (lb_query_sizes). */
+typedef struct {
+    size_t elem_bytes;        /* 8 (LB_FP64) or 4 (LB_FP32_DEV)                         */
+    size_t stride_elems;      /* padded per-component stride of a distribution          */
+    size_t state_bytes;       /* one time level: f then g, 2*19*stride elements         */
+    size_t phi_bytes;         /* order-parameter work field                             */
+    size_t scratch_bytes;     /* reduction partials                                     */
+    size_t adj_bytes;         /* one adjoint time level (lambda_f, lambda_g, lambda_phi) */
+    size_t adj_scratch_bytes; /* adjoint stencil cotangents and parameter partials      */
+} lb_sizes;
+
+/* Caller-owned device memory.  state[0..1] are the two time levels the step
+ * ping-pongs between; the adjoint buffers may be NULL if lb_adjoint_* is never
+ * called. */
+typedef struct {
+    void *state[2];
+    void *phi;
+    void *scratch;
+    void *adj[2];
+    void *adj_scratch;
+} lb_buffers;
+
+typedef struct lb_ctx lb_ctx;
+
+/* Library ABI version (LB_ABI_VERSION). */
+int32_t lb_abi_version(void);
+
+/* Buffer sizes for the given parameters.  Host only; launches nothing.
+ * Returns LB_ESHAPE / LB_EINVAL for parameters lb_create would reject. */
+lb_status lb_query_sizes(const lb_params *p, lb_sizes *out);
+
+/* Create a context on the current HIP device, bound to hip_stream (a
+ * hipStream_t; NULL = the null stream).  Copies *p and *b.  The state is
+ * undefined until lb_init_phi, lb_set_state or lb_import_dist. */
+lb_status lb_create(const lb_params *p, const lb_buffers *b, void *hip_stream, lb_ctx **out);
+
+/* Free the host-side context (never the caller's device memory). NULL is a no-op. */
+void lb_destroy(lb_ctx *ctx);
+
+/* Rebind the context to another stream. */
+lb_status lb_set_stream(lb_ctx *ctx, void *hip_stream);
+
+/* Initial state from phi0_dev (FP64, nx*ny*nz): rho = rho0 and u = 0
+ * (f_i = w_i rho0), all of phi0 in the rest population (g_0 = phi0,
+ * g_i = 0 for i > 0).  Resets the time-level index. */
+lb_status lb_init_phi(lb_ctx *ctx, const double *phi0_dev);
+
+/* Advance nsteps >= 0 timesteps (asynchronous). */
+lb_status lb_step(lb_ctx *ctx, int32_t nsteps);
+
+/* Moments of the current (post-propagation) state, as dense FP64 device
+ * arrays: rho_dev (N), u_dev (3N: x, y, z planes), phi_dev (N).  Any pointer
+ * may be NULL to skip that output. */
+lb_status lb_moments(lb_ctx *ctx, double *rho_dev, double *u_dev, double *phi_dev);
+
+/* Global sums of the current state in FP64, written to out5_dev:
+ * [sum rho, sum phi, sum j_x, sum j_y, sum j_z].  Deterministic: fixed
+ * per-block order, then one fixed-order pass over the block partials. */
+lb_status lb_sums(lb_ctx *ctx, double *out5_dev);
+
+/* Copy the current time level (state_bytes, opaque internal layout) to /
+ * from a caller buffer: lossless checkpoint and restore. */
+lb_status lb_get_state(lb_ctx *ctx, void *dst_dev);
+lb_status lb_set_state(lb_ctx *ctx, const void *src_dev);
+
+/* Current state as dense FP64 post-propagation distributions, each of shape
+ * (19, nx, ny, nz); either pointer may be NULL. */
+lb_status lb_export_dist(lb_ctx *ctx, double *f_dev, double *g_dev);
+
+/* Set the current state from dense FP64 post-propagation distributions
+ * (19, nx, ny, nz).  In LB_FP32_DEV the values are rounded to FP32 after
+ * subtracting w_i rho0 from f_i. */
+lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
+
+/* ---- reverse mode ------------------------------------------------------
+ * The adjoint carries lambda_t = dL/d(state at time t) in the context's
+ * adjoint buffers (FP64 in LB_FP64, FP32 in LB_FP32_DEV).  For a loss on the
+ * final order parameter:
+ *   lb_adjoint_seed(dL/dphi_T)  then, for t = T-1 .. 0,
+ *   lb_adjoint_step(state_t)    (state_t as saved by lb_get_state at time t)
+ * and lb_adjoint_phi0 gives dL/dphi0.  Requires adj[0], adj[1], adj_scratch. */
+
+/* lambda_T from dphi_dev = dL/dphi_T (FP64, N): dL/dg_i = dphi for every i,
+ * dL/df_i = 0. */
+lb_status lb_adjoint_seed(lb_ctx *ctx, const double *dphi_dev);
+
+/* One reverse step: lambda_t = J(state_t)^T lambda_{t+1}, where J is the
+ * Jacobian of one timestep at state_t (state_bytes buffer from lb_get_state).
+ * dtheta3_dev (FP64[3], device) is incremented by the step's contribution to
+ * [dL/dA, dL/dB, dL/dkappa]; it may be NULL. */
+lb_status lb_adjoint_step(lb_ctx *ctx, const void *state_t_dev, double *dtheta3_dev);
+
+/* dL/dphi0 (FP64, N) of the initial state built by lb_init_phi, from the
+ * current lambda_0. */
+lb_status lb_adjoint_phi0(lb_ctx *ctx, double *dphi0_dev);
+
+/* Text for a status code, and the thread-local detail of the last failure. */
+const char *lb_status_string(lb_status s);
+const char *lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

@@ -1,0 +1,284 @@
+// C-ABI host layer: argument validation, buffer layout and launch sequencing
+// for the kernels in lb_kernels.hip.  See include/lb.h for the contract.
+#include "lb.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "lb_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lb_status fail(lb_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+lb_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(LB_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kAdjComponents = 2 * LB_NVEL + 1;  // lambda_f, lambda_g, lambda_phi
+constexpr int kAdjScratchComponents = 5;         // a, b_x, b_y, b_z, c
+
+// Per-component stride: N rounded up to 256 elements, plus a 256-element
+// skew so the 19 component streams of a kernel do not start at the same
+// offset modulo large powers of two (HBM channel interleave).
+size_t stride_for(long long n)
+{
+    const size_t r = (size_t(n) + 255) / 256 * 256;
+    return r + 256;
+}
+
+bool aligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) % kAlign) == 0; }
+
+lb_status validate(const lb_params* p)
+{
+    if (!p) return fail(LB_EINVAL, "params is NULL");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+        return fail(LB_ESHAPE, "extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
+    const long long n = (long long)p->nx * p->ny * p->nz;
+    if (n >= (1LL << 31) - 4096)  // site indices are 32-bit in the kernels
+        return fail(LB_ESHAPE, "lattice of %lld sites is too large", n);
+    if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5))
+        return fail(LB_EINVAL, "tau_f and tau_g must exceed 1/2 (got %g, %g)", p->tau_f, p->tau_g);
+    if (!(p->rho0 > 0.0)) return fail(LB_EINVAL, "rho0 must be positive (got %g)", p->rho0);
+    if (p->precision != LB_FP64 && p->precision != LB_FP32_DEV)
+        return fail(LB_EINVAL, "unknown precision %d", p->precision);
+    return LB_OK;
+}
+
+}  // namespace
+
+struct lb_ctx {
+    lb_params p;
+    lb_sizes sz;
+    lb_buffers b;
+    hipStream_t stream;
+    lbk::KParams kp;
+    bool fp32;
+    int cur;      // time level holding the current state
+    int adj_cur;  // adjoint level holding the current lambda
+    bool has_adj;
+};
+
+extern "C" {
+
+int32_t lb_abi_version(void) { return LB_ABI_VERSION; }
+
+const char* lb_status_string(lb_status s)
+{
+    switch (s) {
+        case LB_OK: return "ok";
+        case LB_EINVAL: return "invalid argument";
+        case LB_ESHAPE: return "invalid lattice shape";
+        case LB_EALIGN: return "device pointer not 256-byte aligned";
+        case LB_EHIP: return "HIP runtime error";
+        case LB_ESTATE: return "call not valid in this state";
+    }
+    return "unknown status";
+}
+
+const char* lb_last_error(void) { return g_err; }
+
+lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
+{
+    lb_status st = validate(p);
+    if (st != LB_OK) return st;
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    const long long n = (long long)p->nx * p->ny * p->nz;
+    const size_t e = p->precision == LB_FP64 ? 8 : 4;
+    const size_t stride = stride_for(n);
+    out->elem_bytes = e;
+    out->stride_elems = stride;
+    out->state_bytes = 2 * LB_NVEL * stride * e;
+    out->phi_bytes = stride * e;
+    out->scratch_bytes = size_t(lbk::kMaxPartialBlocks) * 8 * 8;
+    out->adj_bytes = size_t(kAdjComponents) * stride * e;
+    out->adj_scratch_bytes = size_t(kAdjScratchComponents) * stride * e;
+    return LB_OK;
+}
+
+lb_status lb_create(const lb_params* p, const lb_buffers* b, void* hip_stream, lb_ctx** out)
+{
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    lb_sizes sz;
+    lb_status st = lb_query_sizes(p, &sz);
+    if (st != LB_OK) return st;
+    if (!b) return fail(LB_EINVAL, "buffers is NULL");
+    const void* req[] = {b->state[0], b->state[1], b->phi, b->scratch};
+    for (const void* q : req) {
+        if (!q) return fail(LB_EINVAL, "state[0], state[1], phi and scratch are required");
+        if (!aligned(q)) return fail(LB_EALIGN, "buffer %p is not 256-byte aligned", q);
+    }
+    const bool any_adj = b->adj[0] || b->adj[1] || b->adj_scratch;
+    const bool all_adj = b->adj[0] && b->adj[1] && b->adj_scratch;
+    if (any_adj && !all_adj)
+        return fail(LB_EINVAL, "adj[0], adj[1] and adj_scratch must be given together");
+    if (all_adj && (!aligned(b->adj[0]) || !aligned(b->adj[1]) || !aligned(b->adj_scratch)))
+        return fail(LB_EALIGN, "adjoint buffers must be 256-byte aligned");
+    if (b->state[0] == b->state[1]) return fail(LB_EINVAL, "state[0] and state[1] alias");
+
+    lb_ctx* c = new (std::nothrow) lb_ctx;
+    if (!c) return fail(LB_EINVAL, "out of host memory");
+    c->p = *p;
+    c->sz = sz;
+    c->b = *b;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->fp32 = p->precision == LB_FP32_DEV;
+    c->cur = 0;
+    c->adj_cur = 0;
+    c->has_adj = all_adj;
+    lbk::KParams& k = c->kp;
+    k.nx = p->nx;
+    k.ny = p->ny;
+    k.nz = p->nz;
+    k.nsites = p->nx * p->ny * p->nz;
+    k.stride = (long long)sz.stride_elems;
+    k.A = p->A;
+    k.B = p->B;
+    k.kappa = p->kappa;
+    k.gamma = p->gamma;
+    k.omega_f = 1.0 / p->tau_f;
+    k.omega_g = 1.0 / p->tau_g;
+    k.rho0 = p->rho0;
+    *out = c;
+    return LB_OK;
+}
+
+void lb_destroy(lb_ctx* ctx) { delete ctx; }
+
+lb_status lb_set_stream(lb_ctx* ctx, void* hip_stream)
+{
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return LB_OK;
+}
+
+lb_status lb_init_phi(lb_ctx* ctx, const double* phi0_dev)
+{
+    if (!ctx || !phi0_dev) return fail(LB_EINVAL, "ctx and phi0_dev are required");
+    ctx->cur = 0;
+    hipError_t e = lbk::launch_init(ctx->kp, ctx->fp32, ctx->b.state[0], phi0_dev, ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_init_phi");
+}
+
+lb_status lb_step(lb_ctx* ctx, int32_t nsteps)
+{
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0 (got %d)", nsteps);
+    for (int32_t t = 0; t < nsteps; t++) {
+        hipError_t e = lbk::launch_step(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur],
+                                        ctx->b.state[1 - ctx->cur], ctx->b.phi, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "lb_step");
+        ctx->cur = 1 - ctx->cur;
+    }
+    return LB_OK;
+}
+
+lb_status lb_moments(lb_ctx* ctx, double* rho_dev, double* u_dev, double* phi_dev)
+{
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    int nb = 0;
+    hipError_t e = lbk::launch_moments(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], rho_dev, u_dev,
+                                       phi_dev, static_cast<double*>(ctx->b.scratch), &nb, ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_moments");
+}
+
+lb_status lb_sums(lb_ctx* ctx, double* out5_dev)
+{
+    if (!ctx || !out5_dev) return fail(LB_EINVAL, "ctx and out5_dev are required");
+    int nb = 0;
+    double* part = static_cast<double*>(ctx->b.scratch);
+    hipError_t e = lbk::launch_moments(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], nullptr, nullptr,
+                                       nullptr, part, &nb, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "lb_sums (partials)");
+    e = lbk::launch_sums_final(part, nb, 5, out5_dev, false, ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_sums (final)");
+}
+
+lb_status lb_get_state(lb_ctx* ctx, void* dst_dev)
+{
+    if (!ctx || !dst_dev) return fail(LB_EINVAL, "ctx and dst_dev are required");
+    hipError_t e = hipMemcpyAsync(dst_dev, ctx->b.state[ctx->cur], ctx->sz.state_bytes,
+                                  hipMemcpyDeviceToDevice, ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_get_state");
+}
+
+lb_status lb_set_state(lb_ctx* ctx, const void* src_dev)
+{
+    if (!ctx || !src_dev) return fail(LB_EINVAL, "ctx and src_dev are required");
+    hipError_t e = hipMemcpyAsync(ctx->b.state[ctx->cur], src_dev, ctx->sz.state_bytes,
+                                  hipMemcpyDeviceToDevice, ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_set_state");
+}
+
+lb_status lb_export_dist(lb_ctx* ctx, double* f_dev, double* g_dev)
+{
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    if (!f_dev && !g_dev) return LB_OK;
+    hipError_t e = lbk::launch_export(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], f_dev, g_dev,
+                                      ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_export_dist");
+}
+
+lb_status lb_import_dist(lb_ctx* ctx, const double* f_dev, const double* g_dev)
+{
+    if (!ctx || !f_dev || !g_dev) return fail(LB_EINVAL, "ctx, f_dev and g_dev are required");
+    hipError_t e = lbk::launch_import(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], f_dev, g_dev,
+                                      ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_import_dist");
+}
+
+lb_status lb_adjoint_seed(lb_ctx* ctx, const double* dphi_dev)
+{
+    if (!ctx || !dphi_dev) return fail(LB_EINVAL, "ctx and dphi_dev are required");
+    if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
+    ctx->adj_cur = 0;
+    hipError_t e = lbk::launch_adj_seed(ctx->kp, ctx->fp32, ctx->b.adj[0], dphi_dev, ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_seed");
+}
+
+lb_status lb_adjoint_step(lb_ctx* ctx, const void* state_t_dev, double* dtheta3_dev)
+{
+    if (!ctx || !state_t_dev) return fail(LB_EINVAL, "ctx and state_t_dev are required");
+    if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
+    if (!aligned(state_t_dev)) return fail(LB_EALIGN, "state_t_dev is not 256-byte aligned");
+    int nb = 0;
+    double* part = static_cast<double*>(ctx->b.scratch);
+    hipError_t e = lbk::launch_adj_step(ctx->kp, ctx->fp32, state_t_dev, ctx->b.phi,
+                                        ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
+                                        ctx->b.adj_scratch, part, &nb, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "lb_adjoint_step");
+    ctx->adj_cur = 1 - ctx->adj_cur;
+    if (dtheta3_dev) {
+        e = lbk::launch_sums_final(part, nb, 3, dtheta3_dev, true, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "lb_adjoint_step (parameter sums)");
+    }
+    return LB_OK;
+}
+
+lb_status lb_adjoint_phi0(lb_ctx* ctx, double* dphi0_dev)
+{
+    if (!ctx || !dphi0_dev) return fail(LB_EINVAL, "ctx and dphi0_dev are required");
+    if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
+    hipError_t e = lbk::launch_adj_phi0(ctx->kp, ctx->fp32, ctx->b.adj[ctx->adj_cur], dphi0_dev,
+                                        ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_phi0");
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+"""Python front end of the C ABI: device memory (torch tensors) and streams.
+
+Every step of the computation runs in the HIP kernels behind the C ABI; this
+module only allocates the caller-owned device buffers, passes pointers and
+the stream handle, and wraps results as torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import LB_FP32_DEV, LB_FP64, NVEL, check
+
+
+def _precision_code(precision) -> int:
+    if precision in ("fp64", "f64", LB_FP64):
+        return LB_FP64
+    if precision in ("fp32", "fp32_dev", "f32", LB_FP32_DEV):
+        return LB_FP32_DEV
+    raise ValueError(f"unknown precision {precision!r}")
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class LB:
+    """One D3Q19 binary-fluid lattice on one GPU.
+
+    shape: (nx, ny, nz) periodic extents.  Model parameters as in lb.h.
+    precision: "fp64" or "fp32_dev" (FP32 deviation storage).
+    adjoint: also allocate the reverse-mode buffers.
+    """
+
+    def __init__(self, shape, *, A=-0.00625, B=0.00625, kappa=0.004, gamma=0.5, tau_f=1.0,
+                 tau_g=1.0, rho0=1.0, precision="fp64", adjoint=False, device=None,
+                 stream: torch.cuda.Stream | None = None):
+        L = _abi.lib()
+        nx, ny, nz = (int(v) for v in shape)
+        self.shape = (nx, ny, nz)
+        self.nsites = nx * ny * nz
+        self.precision = _precision_code(precision)
+        self.params = _abi.LbParams(nx, ny, nz, float(A), float(B), float(kappa), float(gamma),
+                                    float(tau_f), float(tau_g), float(rho0), self.precision)
+        self.sizes = _abi.LbSizes()
+        check(L.lb_query_sizes(ctypes.byref(self.params), ctypes.byref(self.sizes)),
+              "lb_query_sizes")
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        sz = self.sizes
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            alloc = lambda n: torch.empty(int(n), dtype=torch.uint8, device=self.device)  # noqa: E731
+            self.state_buf = [alloc(sz.state_bytes), alloc(sz.state_bytes)]
+            self.phi_buf = alloc(sz.phi_bytes)
+            self.scratch = alloc(sz.scratch_bytes)
+            self.adj_buf = [alloc(sz.adj_bytes), alloc(sz.adj_bytes)] if adjoint else [None, None]
+            self.adj_scratch = alloc(sz.adj_scratch_bytes) if adjoint else None
+        bufs = _abi.LbBuffers()
+        bufs.state[0] = self.state_buf[0].data_ptr()
+        bufs.state[1] = self.state_buf[1].data_ptr()
+        bufs.phi = self.phi_buf.data_ptr()
+        bufs.scratch = self.scratch.data_ptr()
+        if adjoint:
+            bufs.adj[0] = self.adj_buf[0].data_ptr()
+            bufs.adj[1] = self.adj_buf[1].data_ptr()
+            bufs.adj_scratch = self.adj_scratch.data_ptr()
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(L.lb_create(ctypes.byref(self.params), ctypes.byref(bufs),
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx)),
+                  "lb_create")
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            _abi.lib().lb_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, name, *args):
+        with torch.cuda.device(self.device):
+            check(getattr(_abi.lib(), name)(self._ctx, *args), name)
+
+    def _dev64(self, a, shape=None) -> torch.Tensor:
+        t = torch.as_tensor(a)
+        t = t.to(device=self.device, dtype=torch.float64, non_blocking=False).contiguous()
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
+
+    def _out(self, *shape) -> torch.Tensor:
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            return torch.empty(shape, dtype=torch.float64, device=self.device)
+
+    def _sync_inputs(self):
+        # inputs produced on torch's current stream must be visible to ours
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    # -- forward ------------------------------------------------------------
+    def init_phi(self, phi0) -> None:
+        t = self._dev64(phi0, self.shape)
+        self._sync_inputs()
+        self._call("lb_init_phi", _ptr(t))
+        t.record_stream(self.stream)
+
+    def step(self, nsteps: int = 1) -> None:
+        self._call("lb_step", ctypes.c_int32(int(nsteps)))
+
+    def moments(self):
+        """(rho (nx,ny,nz), u (3,nx,ny,nz), phi (nx,ny,nz)) as FP64 device tensors."""
+        rho = self._out(*self.shape)
+        u = self._out(3, *self.shape)
+        phi = self._out(*self.shape)
+        self._call("lb_moments", _ptr(rho), _ptr(u), _ptr(phi))
+        return rho, u, phi
+
+    def phi(self) -> torch.Tensor:
+        out = self._out(*self.shape)
+        self._call("lb_moments", None, None, _ptr(out))
+        return out
+
+    def sums(self) -> torch.Tensor:
+        """[sum rho, sum phi, sum jx, sum jy, sum jz] (FP64 device tensor)."""
+        out = self._out(5)
+        self._call("lb_sums", _ptr(out))
+        return out
+
+    def get_state(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+                out = torch.empty(int(self.sizes.state_bytes), dtype=torch.uint8, device=self.device)
+        self._call("lb_get_state", _ptr(out))
+        return out
+
+    def set_state(self, src: torch.Tensor) -> None:
+        if src.numel() * src.element_size() != self.sizes.state_bytes:
+            raise ValueError("state buffer has the wrong size")
+        self._sync_inputs()
+        self._call("lb_set_state", _ptr(src))
+
+    def export_dist(self):
+        """Dense post-propagation (f, g), each FP64 (19, nx, ny, nz)."""
+        f = self._out(NVEL, *self.shape)
+        g = self._out(NVEL, *self.shape)
+        self._call("lb_export_dist", _ptr(f), _ptr(g))
+        return f, g
+
+    def import_dist(self, f, g) -> None:
+        tf = self._dev64(f, (NVEL,) + self.shape)
+        tg = self._dev64(g, (NVEL,) + self.shape)
+        self._sync_inputs()
+        self._call("lb_import_dist", _ptr(tf), _ptr(tg))
+        tf.record_stream(self.stream)
+        tg.record_stream(self.stream)
+
+    # -- reverse mode -------------------------------------------------------
+    def adjoint_seed(self, dphi) -> None:
+        t = self._dev64(dphi, self.shape)
+        self._sync_inputs()
+        self._call("lb_adjoint_seed", _ptr(t))
+        t.record_stream(self.stream)
+
+    def adjoint_step(self, state_t: torch.Tensor, dtheta: torch.Tensor | None = None) -> None:
+        self._call("lb_adjoint_step", _ptr(state_t), _ptr(dtheta))
+
+    def adjoint_phi0(self) -> torch.Tensor:
+        out = self._out(*self.shape)
+        self._call("lb_adjoint_phi0", _ptr(out))
+        return out
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+def to_numpy(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy()

@@ -1,0 +1,88 @@
+"""Reverse mode of a T-step rollout as a torch.autograd.Function.
+
+forward(phi0, A, B, kappa) runs T timesteps on the GPU and returns phi_T.
+backward(dL/dphi_T) returns dL/dphi0 and dL/d(A, B, kappa) from the
+hand-written adjoint kernels (lb_adjoint_step), with checkpointing and
+recomputation: the forward keeps the state every k steps (k = ceil(sqrt(T))
+by default); the backward restores each checkpoint in reverse order,
+recomputes the k states of its segment, and walks the adjoint back through
+them.  Memory: ceil(T/k) + k states instead of T.
+
+All state copies are lossless (lb_get_state / lb_set_state), and the forward
+step is deterministic, so the recomputed states are bit-identical to the
+forward's.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from .lb import LB
+
+
+def default_interval(nsteps: int) -> int:
+    return max(1, math.ceil(math.sqrt(nsteps)))
+
+
+class _Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, phi0, A, B, kappa, cfg):
+        T = int(cfg["nsteps"])
+        k = int(cfg.get("interval") or default_interval(T))
+        lb = LB(phi0.shape, A=float(A), B=float(B), kappa=float(kappa),
+                gamma=cfg.get("gamma", 0.5), tau_f=cfg.get("tau_f", 1.0),
+                tau_g=cfg.get("tau_g", 1.0), rho0=cfg.get("rho0", 1.0),
+                precision=cfg.get("precision", "fp64"), adjoint=True, device=phi0.device)
+        lb.init_phi(phi0.detach())
+        ckpts = []
+        t = 0
+        while t < T:
+            ckpts.append(lb.get_state())
+            n = min(k, T - t)
+            lb.step(n)
+            t += n
+        phiT = lb.phi()
+        ctx.lb = lb
+        ctx.ckpts = ckpts
+        ctx.T = T
+        ctx.k = k
+        return phiT
+
+    @staticmethod
+    def backward(ctx, gphi):
+        lb, ckpts, T, k = ctx.lb, ctx.ckpts, ctx.T, ctx.k
+        dtheta = torch.zeros(3, dtype=torch.float64, device=lb.device)
+        lb.adjoint_seed(gphi.detach())
+        seg_states = []
+        for seg in reversed(range(len(ckpts))):
+            t0 = seg * k
+            t1 = min(T, t0 + k)
+            lb.set_state(ckpts[seg])
+            # states S_t for t0 <= t < t1 (reuse the buffers of the previous segment)
+            for j, t in enumerate(range(t0, t1)):
+                if j > 0:
+                    lb.step(1)
+                if j < len(seg_states):
+                    lb.get_state(seg_states[j])
+                else:
+                    seg_states.append(lb.get_state())
+            for t in reversed(range(t0, t1)):
+                lb.adjoint_step(seg_states[t - t0], dtheta)
+        dphi0 = lb.adjoint_phi0()
+        ctx.lb = None
+        ctx.ckpts = None
+        return dphi0, dtheta[0], dtheta[1], dtheta[2], None
+
+
+def rollout(phi0: torch.Tensor, A, B, kappa, nsteps: int, *, interval: int | None = None,
+            gamma=0.5, tau_f=1.0, tau_g=1.0, rho0=1.0, precision="fp64") -> torch.Tensor:
+    """phi after `nsteps` steps from the state (rho0, u = 0, phi0); differentiable
+    in phi0 (FP64 device tensor (nx, ny, nz)) and in A, B, kappa (tensors or
+    floats)."""
+    dev = phi0.device
+    as_t = lambda v: v if torch.is_tensor(v) else torch.tensor(float(v), dtype=torch.float64,  # noqa: E731
+                                                               device=dev)
+    cfg = dict(nsteps=nsteps, interval=interval, gamma=gamma, tau_f=tau_f, tau_g=tau_g,
+               rho0=rho0, precision=precision)
+    return _Rollout.apply(phi0, as_t(A), as_t(B), as_t(kappa), cfg)

@@ -1,0 +1,103 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU.  No
+compute call is made here."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lb.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_1609_01479_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.fail("liblbmi.so is not built (run __graft_entry__.build())")
+    return _abi
+
+
+def test_header_declares_the_binding_surface(abi):
+    assert _declared_functions() == sorted(abi.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(abi):
+    L = abi.lib()
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+    assert L.lb_abi_version() == 1
+
+
+def _params(abi, **kw):
+    base = dict(nx=8, ny=8, nz=8, A=-0.00625, B=0.00625, kappa=0.004, gamma=0.5, tau_f=1.0,
+                tau_g=1.0, rho0=1.0, precision=abi.LB_FP64)
+    base.update(kw)
+    return abi.LbParams(**base)
+
+
+def _query(abi, **kw):
+    s = abi.LbSizes()
+    return abi.lib().lb_query_sizes(ctypes.byref(_params(abi, **kw)), ctypes.byref(s)), s
+
+
+def test_query_sizes(abi):
+    st, s = _query(abi, nx=16, ny=16, nz=16)
+    assert st == abi.LB_OK
+    assert s.elem_bytes == 8 and s.stride_elems >= 4096 and s.stride_elems % 256 == 0
+    assert s.state_bytes == 2 * 19 * s.stride_elems * 8
+    st, s32 = _query(abi, nx=16, ny=16, nz=16, precision=abi.LB_FP32_DEV)
+    assert st == abi.LB_OK and s32.elem_bytes == 4 and s32.state_bytes * 2 == s.state_bytes
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nx=0), "LB_ESHAPE"), (dict(ny=-3), "LB_ESHAPE"),
+    (dict(nx=2048, ny=2048, nz=1024), "LB_ESHAPE"),
+    (dict(tau_f=0.5), "LB_EINVAL"), (dict(tau_g=0.2), "LB_EINVAL"),
+    (dict(tau_f=float("nan")), "LB_EINVAL"), (dict(rho0=0.0), "LB_EINVAL"),
+    (dict(precision=7), "LB_EINVAL"),
+])
+def test_bad_parameters_rejected(abi, kw, code):
+    st, _ = _query(abi, **kw)
+    assert st == getattr(abi, code)
+    assert abi.lib().lb_last_error().decode()
+
+
+def test_create_validates_buffers_without_launching(abi):
+    """Argument errors return before any HIP call: NULL and misaligned buffers."""
+    L = abi.lib()
+    p = _params(abi)
+    ctx = ctypes.c_void_p()
+    b = abi.LbBuffers()
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_EINVAL
+    b.state[0], b.state[1], b.phi, b.scratch = 0x1000, 0x2000, 0x3000, 0x4008
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_EALIGN
+    b.scratch = 0x4000
+    b.adj[0] = 0x5000
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_EINVAL
+    b.adj[0] = 0
+    b.state[1] = b.state[0]
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_EINVAL
+    # a valid set of (fake, never dereferenced) pointers creates a host context
+    b.state[1] = 0x2000
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
+    assert ctx.value
+    assert L.lb_step(ctx, -1) == abi.LB_EINVAL
+    assert L.lb_adjoint_seed(ctx, ctypes.c_void_p(0x1000)) == abi.LB_ESTATE
+    L.lb_destroy(ctx)
+    L.lb_destroy(None)
+
+
+def test_status_strings(abi):
+    L = abi.lib()
+    for code in range(6):
+        assert L.lb_status_string(code)

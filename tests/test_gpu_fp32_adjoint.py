@@ -1,0 +1,128 @@
+"""FP32 deviation storage and the hand-written adjoint, against the FP64 GPU
+path and the oracle's reverse mode."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import lbinputs
+import oracle
+import oracle.reverse as R
+from tests._gpu import gpu_state, make_lb, oracle_params, oracle_state, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def test_fp32_dev_matches_oracle_short():
+    """FP32 storage follows the FP64 oracle to FP32 rounding over 10 steps."""
+    shape = (16, 16, 16)
+    phi0 = lbinputs.spinodal_phi0(shape)
+    lb = make_lb(shape, precision="fp32_dev", tau_f=0.8, tau_g=1.3)
+    lb.init_phi(phi0)
+    lb.step(10)
+    f, g, rho, u, phi = gpu_state(lb)
+    p = oracle_params(shape, tau_f=0.8, tau_g=1.3)
+    rf, rg, rrho, ru, rphi = oracle_state(p, *oracle.run(p, *oracle.init(p, phi0), 10))
+    assert np.abs(phi - rphi).max() <= 1e-6
+    assert np.abs(rho - rrho).max() <= 1e-6
+    assert np.abs(u - ru).max() <= 1e-7
+
+
+def test_fp32_dev_droplet_phi_error_vs_fp64():
+    """A tanh droplet with noise, 400 steps: max |phi32 - phi64| <= 1e-5."""
+    shape = (48, 48, 48)
+    xi = lbinputs.interface_width(lbinputs.SPINODAL_PARAMS["A"], lbinputs.SPINODAL_PARAMS["kappa"])
+    phi0 = lbinputs.droplet_phi0(shape, 12.0, xi)
+    out = {}
+    for prec in ("fp64", "fp32_dev"):
+        lb = make_lb(shape, precision=prec)
+        lb.init_phi(phi0)
+        lb.step(400)
+        out[prec] = gpu_state(lb)
+    err_phi = np.abs(out["fp32_dev"][4] - out["fp64"][4]).max()
+    err_u = np.abs(out["fp32_dev"][3] - out["fp64"][3]).max()
+    print(f"[fp32] droplet 48^3 x 400: max|dphi|={err_phi:.3e} max|du|={err_u:.3e}", flush=True)
+    assert err_phi <= 1e-5
+    assert err_u <= 1e-6
+
+
+def test_fp32_sums_conserved():
+    shape = (32, 32, 32)
+    lb = make_lb(shape, precision="fp32_dev", tau_f=0.8, tau_g=1.3)
+    lb.init_phi(lbinputs.spinodal_phi0(shape))
+    s0 = lb.sums().cpu().numpy()
+    lb.step(100)
+    s1 = lb.sums().cpu().numpy()
+    # mass deviations and phi are stored in FP32 (~1e-7 relative per value)
+    assert abs(s1[0] - s0[0]) < 1e-6 * shape[0] ** 3
+    assert abs(s1[1] - s0[1]) < 1e-6 * shape[0] ** 3
+    assert np.abs(s1[2:]).max() < 1e-6 * shape[0] ** 3
+
+
+# ---------------------------------------------------------------- adjoint --
+
+def _gpu_grads(shape, T, phi0, tgt, interval=None, precision="fp64", **kw):
+    from paper_1609_01479_amd.rollout import rollout
+    pr = dict(lbinputs.SPINODAL_PARAMS)
+    pr.update(kw)
+    dev = torch.device("cuda:0")
+    p0 = torch.tensor(phi0, dtype=torch.float64, device=dev, requires_grad=True)
+    A = torch.tensor(pr["A"], dtype=torch.float64, device=dev, requires_grad=True)
+    B = torch.tensor(pr["B"], dtype=torch.float64, device=dev, requires_grad=True)
+    kap = torch.tensor(pr["kappa"], dtype=torch.float64, device=dev, requires_grad=True)
+    phiT = rollout(p0, A, B, kap, T, interval=interval, gamma=pr["gamma"], tau_f=pr["tau_f"],
+                   tau_g=pr["tau_g"], rho0=pr["rho0"], precision=precision)
+    loss = 0.5 * ((phiT - torch.tensor(tgt, device=dev)) ** 2).sum()
+    loss.backward()
+    return (float(loss), p0.grad.cpu().numpy(), float(A.grad), float(B.grad), float(kap.grad))
+
+
+@pytest.mark.parametrize("interval", [None, 1, 7, 20])
+def test_adjoint_matches_oracle_reverse_mode_8cubed(interval):
+    """8^3 x 20 steps, tau != 1: dL/dphi0 and dL/d(A, B, kappa) vs autograd
+    through the oracle's re-expression (itself pinned to central differences)."""
+    shape = (8, 8, 8)
+    T = 20
+    kw = dict(tau_f=0.8, tau_g=1.3)
+    pr = dict(lbinputs.SPINODAL_PARAMS, **kw)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=77)
+    tgt = lbinputs.lamellar_target(shape, 8, lbinputs.interface_width(pr["A"], pr["kappa"]))
+    print(f"[adjoint] 8^3 x {T} interval={interval}", flush=True)
+    L, gphi, gA, gB, gk = _gpu_grads(shape, T, phi0, tgt, interval=interval, **kw)
+    rL, rphi, rA, rB, rk = R.loss_and_grads(phi0, tgt, pr["A"], pr["B"], pr["kappa"], T,
+                                            pr["gamma"], pr["tau_f"], pr["tau_g"], pr["rho0"])
+    assert abs(L - rL) <= 1e-12 * abs(rL)
+    assert rel_err(gphi, rphi) <= 1e-10, rel_err(gphi, rphi)
+    for name, a, b in (("A", gA, rA), ("B", gB, rB), ("kappa", gk, rk)):
+        assert abs(a - b) <= 1e-9 * abs(b), (name, a, b)
+
+
+def test_adjoint_noncubic_default_taus():
+    shape = (6, 5, 7)
+    T = 12
+    pr = dict(lbinputs.SPINODAL_PARAMS)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=3, amp=0.4)
+    tgt = lbinputs.random_field(shape, 10)
+    L, gphi, gA, gB, gk = _gpu_grads(shape, T, phi0, tgt, interval=4)
+    rL, rphi, rA, rB, rk = R.loss_and_grads(phi0, tgt, pr["A"], pr["B"], pr["kappa"], T,
+                                            pr["gamma"], pr["tau_f"], pr["tau_g"], pr["rho0"])
+    assert rel_err(gphi, rphi) <= 1e-10
+    for a, b in ((gA, rA), (gB, rB), (gk, rk)):
+        assert abs(a - b) <= 1e-9 * abs(b)
+
+
+def test_adjoint_fp32_close_to_fp64():
+    shape = (16, 16, 16)
+    T = 40
+    pr = dict(lbinputs.SPINODAL_PARAMS)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=12)
+    tgt = lbinputs.lamellar_target(shape, 8, lbinputs.interface_width(pr["A"], pr["kappa"]))
+    g64 = _gpu_grads(shape, T, phi0, tgt, precision="fp64")
+    g32 = _gpu_grads(shape, T, phi0, tgt, precision="fp32_dev")
+    e_phi = np.linalg.norm(g32[1] - g64[1]) / np.linalg.norm(g64[1])
+    print(f"[adjoint fp32] rel L2 err dphi0 = {e_phi:.3e}; "
+          f"A {g32[2]/g64[2]-1:.2e} B {g32[3]/g64[3]-1:.2e} kappa {g32[4]/g64[4]-1:.2e}", flush=True)
+    assert e_phi <= 1e-4
+    for a, b in zip(g32[2:], g64[2:]):
+        assert abs(a - b) <= 1e-3 * abs(b)

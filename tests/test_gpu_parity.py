@@ -1,0 +1,155 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar (FP64): for every output field F (f, g, rho, u, phi),
+max_x |F_gpu - F_oracle| / max_x |F_oracle| <= 1e-12 after up to 100 steps.
+Integer/permutation work (propagation, import/export, checkpoints) is
+compared bit for bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import lbinputs
+import oracle
+from tests._gpu import gpu_state, make_lb, oracle_params, oracle_state, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+NAMES = ("f", "g", "rho", "u", "phi")
+
+
+def _run_both(shape, steps, phi0=None, **kw):
+    print(f"[parity] shape={shape} steps={steps} params={kw}", flush=True)
+    phi0 = lbinputs.spinodal_phi0(shape) if phi0 is None else phi0
+    lb = make_lb(shape, **kw)
+    lb.init_phi(phi0)
+    lb.step(steps)
+    got = gpu_state(lb)
+    p = oracle_params(shape, **kw)
+    ref = oracle_state(p, *oracle.run(p, *oracle.init(p, phi0), steps))
+    return got, ref
+
+
+@pytest.mark.parametrize("steps", [0, 1, 10, 100])
+def test_spinodal_16cubed_fp64(steps):
+    """16^3 spinodal decomposition, phi0 ~ U(-0.05, 0.05), default parameters."""
+    got, ref = _run_both((16, 16, 16), steps)
+    for name, a, b in zip(NAMES, got, ref):
+        assert rel_err(a, b) <= TOL, (name, rel_err(a, b))
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (8, 4, 12), (3, 5, 131), (17, 9, 70)])
+def test_noncubic_and_ragged_tau_not_one(shape):
+    """Non-cubic lattices (axis swaps) and ragged tails; tau != 1 exercises the
+    non-equilibrium part of the BGK update."""
+    got, ref = _run_both(shape, 30, tau_f=0.8, tau_g=1.3)
+    for name, a, b in zip(NAMES, got, ref):
+        assert rel_err(a, b) <= TOL, (name, shape, rel_err(a, b))
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 2, 2), (1, 1, 300), (1, 7, 1), (2, 3, 1)])
+def test_degenerate_lattices(shape):
+    """Extents 1 and 2: neighbours coincide with the site or with each other."""
+    phi0 = lbinputs.spinodal_phi0(shape, seed=99, amp=0.5)
+    got, ref = _run_both(shape, 12, phi0=phi0, tau_f=0.9, tau_g=1.2)
+    for name, a, b in zip(NAMES, got, ref):
+        assert rel_err(a, b) <= TOL, (name, shape, rel_err(a, b))
+
+
+def test_arbitrary_state_one_step():
+    """A random non-equilibrium state imported through the ABI, one step."""
+    shape = (6, 7, 9)
+    p = oracle_params(shape, tau_f=0.7, tau_g=1.6, gamma=0.3)
+    f0, g0 = oracle.init(p, lbinputs.spinodal_phi0(shape, seed=4, amp=0.8))
+    rng = np.random.default_rng(1)
+    f0 = f0 * (1 + 0.2 * rng.standard_normal(f0.shape))
+    g0 = g0 + 0.05 * rng.standard_normal(g0.shape)
+    lb = make_lb(shape, tau_f=0.7, tau_g=1.6, gamma=0.3)
+    lb.import_dist(f0, g0)
+    lb.step(3)
+    got = gpu_state(lb)
+    ref = oracle_state(p, *oracle.run(p, f0, g0, 3))
+    for name, a, b in zip(NAMES, got, ref):
+        assert rel_err(a, b) <= TOL, (name, rel_err(a, b))
+
+
+def test_import_export_round_trip_bit_exact():
+    shape = (5, 4, 67)
+    f = lbinputs.random_field((19,) + shape, 3)
+    g = lbinputs.random_field((19,) + shape, 4)
+    lb = make_lb(shape)
+    lb.import_dist(f, g)
+    f2, g2, *_ = gpu_state(lb)
+    assert np.array_equal(f2, f) and np.array_equal(g2, g)
+
+
+def test_state_layout_shift_and_restore_bit_exact():
+    """Importing a periodically shifted state exports the shifted state, and a
+    saved time level restores bit for bit."""
+    shape = (4, 5, 6)
+    f = lbinputs.random_field((19,) + shape, 8)
+    g = lbinputs.random_field((19,) + shape, 9)
+    lb = make_lb(shape)
+    lb.import_dist(f, g)
+    st = lb.get_state().clone()
+    lb2 = make_lb(shape)
+    sh = (1, -2, 3)
+    lb2.import_dist(np.roll(f, sh, (1, 2, 3)), np.roll(g, sh, (1, 2, 3)))
+    fa, ga, *_ = gpu_state(lb)
+    fb, gb, *_ = gpu_state(lb2)
+    assert np.array_equal(np.roll(fa, sh, (1, 2, 3)), fb)
+    assert np.array_equal(np.roll(ga, sh, (1, 2, 3)), gb)
+    lb.step(2)
+    lb.set_state(st)
+    assert np.array_equal(gpu_state(lb)[0], f)
+
+
+def test_shift_invariance_bit_exact():
+    shape = (8, 6, 70)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=5)
+    sh = (3, -1, 17)
+    a = make_lb(shape, tau_f=0.8, tau_g=1.3)
+    a.init_phi(phi0)
+    a.step(20)
+    b = make_lb(shape, tau_f=0.8, tau_g=1.3)
+    b.init_phi(np.roll(phi0, sh, (0, 1, 2)))
+    b.step(20)
+    fa, ga, *_ = gpu_state(a)
+    fb, gb, *_ = gpu_state(b)
+    assert np.array_equal(np.roll(fa, sh, (1, 2, 3)), fb)
+    assert np.array_equal(np.roll(ga, sh, (1, 2, 3)), gb)
+
+
+def test_determinism_and_checkpoint_restore_bit_exact():
+    shape = (16, 16, 16)
+    phi0 = lbinputs.spinodal_phi0(shape)
+    a = make_lb(shape, tau_f=0.8, tau_g=1.3)
+    a.init_phi(phi0)
+    a.step(7)
+    ck = a.get_state().clone()
+    a.step(13)
+    ra = gpu_state(a)
+    a.set_state(ck)
+    a.step(13)
+    rb = gpu_state(a)
+    for x, y in zip(ra, rb):
+        assert np.array_equal(x, y)
+
+
+def test_conservation_and_sums_match_oracle():
+    shape = (12, 10, 14)
+    p = oracle_params(shape, tau_f=0.8, tau_g=1.3)
+    f0, g0 = oracle.init(p, lbinputs.spinodal_phi0(shape, seed=6))
+    rng = np.random.default_rng(2)
+    f0 = f0 * (1 + 0.01 * rng.standard_normal(f0.shape))
+    lb = make_lb(shape, tau_f=0.8, tau_g=1.3)
+    lb.import_dist(f0, g0)
+    s0 = lb.sums().cpu().numpy()
+    ref0 = oracle.sums(p, f0, g0)
+    np.testing.assert_allclose(s0, ref0, rtol=1e-13, atol=1e-13)
+    lb.step(50)
+    s1 = lb.sums().cpu().numpy()
+    np.testing.assert_allclose(s1, s0, rtol=0, atol=1e-11)
