@@ -31,13 +31,14 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# Algorithmic HBM bytes per lattice-site update of one step.  The method must
-# read and write the 19 f and 19 g populations once (76 words); the current
-# two-kernel step also reads g once more to form phi and writes/reads phi.
+# Algorithmic HBM bytes per lattice-site update of one step (one launch of the
+# single-pass kernel processes every site once).  The method must read and
+# write the 19 f and 19 g populations once (76 words of the storage type); in
+# FP32 mode the stored time level also carries the FP64 reference order
+# parameter (read once, written once: 16 B).
 def step_bytes_per_site(elem_bytes: int) -> dict:
-    return {"method_min": 76 * elem_bytes,
-            "phi_kernel": 19 * elem_bytes + elem_bytes,
-            "collide_kernel": 76 * elem_bytes + elem_bytes}
+    extra = 16 if elem_bytes == 4 else 0
+    return {"method_min": 76 * elem_bytes, "kernel": 76 * elem_bytes + extra}
 
 
 def time_steps(lb, steps: int, warmup: int):
@@ -161,13 +162,13 @@ def main():
     def roof(run):
         e = run["elem"]
         b = step_bytes_per_site(e)
-        per_step = b["phi_kernel"] + b["collide_kernel"]
+        per_step = b["kernel"]
         t = run["ms"] / args.steps * 1e-3
         achieved = per_step * nsites / t / 1e9
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                 "effective_GBps": round(b["method_min"] * nsites / t / 1e9, 1),
-                "bytes_per_site": per_step, "kernel": "step (phi + collide kernels)"}
+                "bytes_per_site": per_step, "kernel": "k_step_fused"}
 
     out = {
         "metric": "MLUPS & % peak HBM GB/s, D3Q19 binary 256^3: FP32 vs FP64; adjoint/forward cost",

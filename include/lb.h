@@ -69,9 +69,19 @@ typedef enum {
 
 typedef enum {
     LB_FP64 = 0,    /* distributions stored and collided in FP64            */
-    LB_FP32_DEV = 1 /* FP32 storage of f_i - w_i rho0 and of g_i, FP32
-                       collision; FP64 reductions and parameter gradients   */
+    LB_FP32_DEV = 1 /* FP32 storage of deviations and FP32 collision:
+                       f_i - w_i rho0, and g_i - r_i phi_c with the FP64
+                       order parameter phi_c of the site's last collision
+                       (r_i phi = the order-parameter equilibrium at rest
+                       with mu = 0); FP64 phi, reductions and parameter
+                       gradients                                             */
 } lb_precision;
+
+typedef enum {
+    LB_KERNEL_FUSED = 0,   /* one pass per step: phi, gradients, stress,
+                              collision and propagation in one kernel      */
+    LB_KERNEL_TWO_PASS = 1 /* a phi pass, then the stencil/collision pass  */
+} lb_kernel;
 
 /* Lattice and model.  nx, ny, nz >= 1 with nx*ny*nz < 2^31 (periodic in all
  * three directions); tau_f, tau_g > 1/2; rho0 > 0. */
@@ -82,14 +92,17 @@ typedef struct {
     double tau_f, tau_g;
     double rho0;        /* rest density of the initial state                        */
     int32_t precision;  /* lb_precision                                             */
+    int32_t kernel;     /* lb_kernel (same results; a performance choice)           */
+    int32_t segment_x;  /* planes per workgroup in the fused kernel; <= 0: automatic */
 } lb_params;
 
 /* Sizes in bytes of the caller-owned device buffers (lb_query_sizes). */
 typedef struct {
     size_t elem_bytes;        /* 8 (LB_FP64) or 4 (LB_FP32_DEV)                         */
     size_t stride_elems;      /* padded per-component stride of a distribution          */
-    size_t state_bytes;       /* one time level: f then g, 2*19*stride elements         */
-    size_t phi_bytes;         /* order-parameter work field                             */
+    size_t state_bytes;       /* one time level: f, g (2*19*stride elements) and, in
+                                 LB_FP32_DEV, phi_c (stride FP64 values)                */
+    size_t phi_bytes;         /* FP64 order-parameter work field                        */
     size_t scratch_bytes;     /* reduction partials                                     */
     size_t adj_bytes;         /* one adjoint time level (lambda_f, lambda_g, lambda_phi) */
     size_t adj_scratch_bytes; /* adjoint stencil cotangents and parameter partials      */

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "liblbmi.so")
 NVEL = 19
 LB_OK, LB_EINVAL, LB_ESHAPE, LB_EALIGN, LB_EHIP, LB_ESTATE = range(6)
 LB_FP64, LB_FP32_DEV = 0, 1
+LB_KERNEL_FUSED, LB_KERNEL_TWO_PASS = 0, 1
 
 # Every symbol include/lb.h declares.
 EXPORTS = ("lb_abi_version", "lb_query_sizes", "lb_create", "lb_destroy", "lb_set_stream",
@@ -28,7 +29,8 @@ class LbParams(ctypes.Structure):
                 ("A", ctypes.c_double), ("B", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("tau_f", ctypes.c_double),
                 ("tau_g", ctypes.c_double), ("rho0", ctypes.c_double),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("segment_x", ctypes.c_int32)]
 
 
 class LbSizes(ctypes.Structure):

@@ -1,0 +1,239 @@
+// Reverse-mode kernels: one adjoint timestep lambda_t = J(s_t)^T lambda_{t+1}
+// of the D3Q19 binary-fluid step, hand-derived.
+//
+// One forward step is  s_{t+1} = P(C(s_t)), P the propagation (a permutation)
+// and C the collision, which is local except through phi's stencil.  With
+// Lambda = omega * lambda* (lambda* the cotangent of the post-collision
+// populations) the collision's transposed Jacobian needs only the weighted
+// moments of Lambda:
+//   S0 = sum w L_f,  S1 = sum w L_f c,  S2 = sum w L_f (c c - I/3)   (f part)
+//   T0, T1, T2 the same for L_g                                      (g part)
+// because f_eq and g_eq are Hermite expansions in (rho, j, Pi) and
+// (phi, u, mu).  Writing Phi = sum_i L_f,i f_eq,i + L_g,i g_eq,i:
+//   dPhi/drho  = S0 - 9/2 S2:uu - 3 phi T1.u/rho - 9 phi T2:uu/rho
+//   dPhi/dj    = 3 S1 + 9 S2.u + 3 phi T1/rho + 9 phi T2.u/rho
+//   dPhi/dphi  = 9/2 trS2 (A phi + 3B phi^3 - kappa lap) + T0 + 3 T1.u
+//                + 9/2 (Gamma (A + 3B phi^2) - 1/3) trT2 + 9/2 T2:uu
+//   dPhi/d(d_a phi) = 9/2 kappa (2 (S2 grad)_a - trS2 d_a phi)
+//   dPhi/d(lap)     = -9/2 kappa (phi trS2 + Gamma trT2)
+//   dPhi/dA = 9/2 (trS2 phi^2/2 + Gamma phi trT2)
+//   dPhi/dB = 9/2 (trS2 3 phi^4/4 + Gamma phi^3 trT2)
+//   dPhi/dkappa = 9/2 (trS2 (-phi lap - |grad|^2/2) + grad.S2.grad - Gamma lap trT2)
+// and then lambda_f,i = (1 - omega_f) lambda*_f,i + dPhi/drho + c_i . dPhi/dj,
+// lambda_g,i = (1 - omega_g) lambda*_g,i + lambda_phi, where lambda_phi
+// collects the phi cotangents through the transposed stencil
+// (D_a^T = -D_a, lap^T = lap on the periodic lattice).
+//
+// An adjoint level stores 39 components of `stride` elements:
+//   lf[19] = dL/df_i(x), lg[19] = the part of dL/dg_i(x) specific to i,
+//   lp = dL/dphi(x), so that dL/dg_i(x) = lg_i(x) + lp(x).
+// adj_scratch holds a (direct dPhi/dphi), b_x, b_y, b_z, c per site.
+#include "lb_device.h"
+
+namespace lbk {
+
+using namespace dev;
+
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_seed(KParams p, T* __restrict__ adj,
+                                                     const double* __restrict__ dphi)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+#pragma unroll
+    for (int i = 0; i < 2 * NV; i++) adj[i * p.stride + s] = T(0);
+    adj[2 * NV * p.stride + s] = T(dphi[s]);
+}
+
+// Transposed propagation (gather lambda*_i(x) = lambda_i(x + c_i)), then the
+// transposed local collision Jacobian at x with the forward locals recomputed
+// from the saved state; writes lf, lg of the previous level, the stencil
+// cotangents, and block partials of d/d(A, B, kappa).
+template <typename T, bool DEV>
+__global__ __launch_bounds__(kBlock) void k_adj_local(KParams p, const T* __restrict__ F,
+                                                      const double* __restrict__ phi,
+                                                      const T* __restrict__ an,
+                                                      T* __restrict__ ap, T* __restrict__ sc,
+                                                      double* __restrict__ partials)
+{
+    double dth[3] = {0.0, 0.0, 0.0};
+    const long long S = p.stride;
+    for (int s = blockIdx.x * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
+        const Geo q = geo_of(p, s);
+        T lf[NV], lg[NV], f[NV];
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            const int d = push_site(p, q, i);
+            lf[i] = an[i * S + d];
+            lg[i] = an[(NV + i) * S + d] + an[2 * NV * S + d];
+            f[i] = F[i * S + pull_site(p, q, i)];
+        }
+        const Stencil st = stencil(phi[s], phi[site_of(p, q.xp, q.y, q.z)],
+                                   phi[site_of(p, q.xm, q.y, q.z)],
+                                   phi[site_of(p, q.x, q.yp, q.z)],
+                                   phi[site_of(p, q.x, q.ym, q.z)],
+                                   phi[site_of(p, q.x, q.y, q.zp)],
+                                   phi[site_of(p, q.x, q.y, q.zm)]);
+        const T A = T(p.A), B = T(p.B), kap = T(p.kappa), gam = T(p.gamma);
+        const T omf = T(p.omega_f), omg = T(p.omega_g);
+        const Moments<T> m = moments_of<T, DEV>(p, f);
+        const T ri = T(1) / m.rho;
+        const T ux = m.jx * ri, uy = m.jy * ri, uz = m.jz * ri;
+        const T phi_c = T(st.phi), gx = T(st.gx), gy = T(st.gy), gz = T(st.gz), lap = T(st.lap);
+
+        T s0 = 0, s1x = 0, s1y = 0, s1z = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
+        T t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            const T wl = T(weight(i)) * omf * lf[i];
+            const T wg = T(weight(i)) * omg * lg[i];
+            s0 += wl;
+            t0 += wg;
+            if (CX[i]) { s1x += CX[i] * wl; t1x += CX[i] * wg; sxx += wl; txx += wg; }
+            if (CY[i]) { s1y += CY[i] * wl; t1y += CY[i] * wg; syy += wl; tyy += wg; }
+            if (CZ[i]) { s1z += CZ[i] * wl; t1z += CZ[i] * wg; szz += wl; tzz += wg; }
+            if (CX[i] * CY[i]) { sxy += CX[i] * CY[i] * wl; txy += CX[i] * CY[i] * wg; }
+            if (CX[i] * CZ[i]) { sxz += CX[i] * CZ[i] * wl; txz += CX[i] * CZ[i] * wg; }
+            if (CY[i] * CZ[i]) { syz += CY[i] * CZ[i] * wl; tyz += CY[i] * CZ[i] * wg; }
+        }
+        const T third = T(1.0 / 3.0);
+        sxx -= third * s0; syy -= third * s0; szz -= third * s0;
+        txx -= third * t0; tyy -= third * t0; tzz -= third * t0;
+        const T trs = sxx + syy + szz, trt = txx + tyy + tzz;
+        const T s2ux = sxx * ux + sxy * uy + sxz * uz;
+        const T s2uy = sxy * ux + syy * uy + syz * uz;
+        const T s2uz = sxz * ux + syz * uy + szz * uz;
+        const T t2ux = txx * ux + txy * uy + txz * uz;
+        const T t2uy = txy * ux + tyy * uy + tyz * uz;
+        const T t2uz = txz * ux + tyz * uy + tzz * uz;
+        const T s2uu = s2ux * ux + s2uy * uy + s2uz * uz;
+        const T t2uu = t2ux * ux + t2uy * uy + t2uz * uz;
+        const T t1u = t1x * ux + t1y * uy + t1z * uz;
+        const T s2gx = sxx * gx + sxy * gy + sxz * gz;
+        const T s2gy = sxy * gx + syy * gy + syz * gz;
+        const T s2gz = sxz * gx + syz * gy + szz * gz;
+        const T gsg = s2gx * gx + s2gy * gy + s2gz * gz;
+        const T h = T(4.5);
+        const T pr = phi_c * ri;
+
+        const T arho = s0 - h * s2uu - T(3) * pr * t1u - T(9) * pr * t2uu;
+        const T ajx = T(3) * s1x + T(9) * s2ux + T(3) * pr * t1x + T(9) * pr * t2ux;
+        const T ajy = T(3) * s1y + T(9) * s2uy + T(3) * pr * t1y + T(9) * pr * t2uy;
+        const T ajz = T(3) * s1z + T(9) * s2uz + T(3) * pr * t1z + T(9) * pr * t2uz;
+        const T cf = T(1) - omf, cg = T(1) - omg;
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            T v = cf * lf[i] + arho;
+            if (CX[i]) v += CX[i] * ajx;
+            if (CY[i]) v += CY[i] * ajy;
+            if (CZ[i]) v += CZ[i] * ajz;
+            ap[i * S + s] = v;
+            ap[(NV + i) * S + s] = cg * lg[i];
+        }
+        const T phi2 = phi_c * phi_c;
+        const T a_dir = h * trs * (A * phi_c + T(3) * B * phi2 * phi_c - kap * lap) + t0
+                      + T(3) * t1u + h * (gam * (A + T(3) * B * phi2) - third) * trt + h * t2uu;
+        const T hk = h * kap;
+        sc[0 * S + s] = a_dir;
+        sc[1 * S + s] = hk * (T(2) * s2gx - trs * gx);
+        sc[2 * S + s] = hk * (T(2) * s2gy - trs * gy);
+        sc[3 * S + s] = hk * (T(2) * s2gz - trs * gz);
+        sc[4 * S + s] = -hk * (phi_c * trs + gam * trt);
+        const double g2 = st.gx * st.gx + st.gy * st.gy + st.gz * st.gz;
+        const double dtrs = double(trs), dtrt = double(trt), dph = st.phi;
+        dth[0] += 4.5 * (dtrs * 0.5 * dph * dph + p.gamma * dph * dtrt);
+        dth[1] += 4.5 * (dtrs * 0.75 * dph * dph * dph * dph + p.gamma * dph * dph * dph * dtrt);
+        dth[2] += 4.5 * (dtrs * (-dph * st.lap - 0.5 * g2) + double(gsg) - p.gamma * st.lap * dtrt);
+    }
+    block_partials<3>(dth, partials);
+}
+
+// lp(x) = a(x) - sum_a D_a b_a (x) + lap c (x)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_stencil(KParams p, const T* __restrict__ sc,
+                                                        T* __restrict__ ap)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    const Geo q = geo_of(p, s);
+    const long long S = p.stride;
+    const int xp = site_of(p, q.xp, q.y, q.z), xm = site_of(p, q.xm, q.y, q.z);
+    const int yp = site_of(p, q.x, q.yp, q.z), ym = site_of(p, q.x, q.ym, q.z);
+    const int zp = site_of(p, q.x, q.y, q.zp), zm = site_of(p, q.x, q.y, q.zm);
+    const T* a = sc;
+    const T* bx = sc + S;
+    const T* by = sc + 2 * S;
+    const T* bz = sc + 3 * S;
+    const T* c = sc + 4 * S;
+    const T cc = c[s];
+    const T divb = T(0.5) * (bx[xp] - bx[xm]) + T(0.5) * (by[yp] - by[ym]) + T(0.5) * (bz[zp] - bz[zm]);
+    const T lapc = (c[xp] + c[xm] - T(2) * cc) + (c[yp] + c[ym] - T(2) * cc) + (c[zp] + c[zm] - T(2) * cc);
+    ap[2 * NV * S + s] = a[s] - divb + lapc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_phi0(KParams p, const T* __restrict__ adj,
+                                                     double* __restrict__ out)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    out[s] = double(adj[NV * p.stride + s]) + double(adj[2 * NV * p.stride + s]);
+}
+
+int grid_for(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
+
+int reduction_grid(const KParams& p)
+{
+    const int g = grid_for(p);
+    return g < kMaxPartialBlocks ? g : kMaxPartialBlocks;
+}
+
+}  // namespace
+
+hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, const double* dphi, hipStream_t s)
+{
+    if (fp32)
+        k_adj_seed<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<float*>(adj), dphi);
+    else
+        k_adj_seed<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<double*>(adj), dphi);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state, double* phi,
+                           const void* adj_next, void* adj_prev, void* adj_scratch,
+                           double* partials, int* nblocks_out, hipStream_t s)
+{
+    hipError_t e = launch_phi(p, fp32, state, phi, s);
+    if (e != hipSuccess) return e;
+    const int nb = reduction_grid(p);
+    *nblocks_out = nb;
+    if (fp32) {
+        k_adj_local<float, true><<<nb, kBlock, 0, s>>>(p, static_cast<const float*>(state), phi,
+                                                       static_cast<const float*>(adj_next),
+                                                       static_cast<float*>(adj_prev),
+                                                       static_cast<float*>(adj_scratch), partials);
+        k_adj_stencil<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const float*>(adj_scratch),
+                                                            static_cast<float*>(adj_prev));
+    } else {
+        k_adj_local<double, false><<<nb, kBlock, 0, s>>>(p, static_cast<const double*>(state), phi,
+                                                         static_cast<const double*>(adj_next),
+                                                         static_cast<double*>(adj_prev),
+                                                         static_cast<double*>(adj_scratch), partials);
+        k_adj_stencil<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const double*>(adj_scratch),
+                                                             static_cast<double*>(adj_prev));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_phi0(const KParams& p, bool fp32, const void* adj, double* dphi0, hipStream_t s)
+{
+    if (fp32)
+        k_adj_phi0<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const float*>(adj), dphi0);
+    else
+        k_adj_phi0<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const double*>(adj), dphi0);
+    return hipGetLastError();
+}
+
+}  // namespace lbk

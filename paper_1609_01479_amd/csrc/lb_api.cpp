@@ -58,6 +58,8 @@ lb_status validate(const lb_params* p)
     if (!(p->rho0 > 0.0)) return fail(LB_EINVAL, "rho0 must be positive (got %g)", p->rho0);
     if (p->precision != LB_FP64 && p->precision != LB_FP32_DEV)
         return fail(LB_EINVAL, "unknown precision %d", p->precision);
+    if (p->kernel != LB_KERNEL_FUSED && p->kernel != LB_KERNEL_TWO_PASS)
+        return fail(LB_EINVAL, "unknown kernel variant %d", p->kernel);
     return LB_OK;
 }
 
@@ -69,6 +71,7 @@ struct lb_ctx {
     lb_buffers b;
     hipStream_t stream;
     lbk::KParams kp;
+    lbk::TileCfg tc;
     bool fp32;
     int cur;      // time level holding the current state
     int adj_cur;  // adjoint level holding the current lambda
@@ -104,8 +107,9 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     const size_t stride = stride_for(n);
     out->elem_bytes = e;
     out->stride_elems = stride;
-    out->state_bytes = 2 * LB_NVEL * stride * e;
-    out->phi_bytes = stride * e;
+    // f and g, plus the FP64 reference order parameter in FP32 mode
+    out->state_bytes = 2 * LB_NVEL * stride * e + (p->precision == LB_FP32_DEV ? stride * 8 : 0);
+    out->phi_bytes = stride * 8;
     out->scratch_bytes = size_t(lbk::kMaxPartialBlocks) * 8 * 8;
     out->adj_bytes = size_t(kAdjComponents) * stride * e;
     out->adj_scratch_bytes = size_t(kAdjScratchComponents) * stride * e;
@@ -156,6 +160,7 @@ lb_status lb_create(const lb_params* p, const lb_buffers* b, void* hip_stream, l
     k.omega_f = 1.0 / p->tau_f;
     k.omega_g = 1.0 / p->tau_g;
     k.rho0 = p->rho0;
+    c->tc = lbk::tile_config(k, p->segment_x);
     *out = c;
     return LB_OK;
 }
@@ -182,8 +187,9 @@ lb_status lb_step(lb_ctx* ctx, int32_t nsteps)
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
     if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0 (got %d)", nsteps);
     for (int32_t t = 0; t < nsteps; t++) {
-        hipError_t e = lbk::launch_step(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur],
-                                        ctx->b.state[1 - ctx->cur], ctx->b.phi, ctx->stream);
+        hipError_t e = lbk::launch_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel,
+                                        ctx->b.state[ctx->cur], ctx->b.state[1 - ctx->cur],
+                                        static_cast<double*>(ctx->b.phi), ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "lb_step");
         ctx->cur = 1 - ctx->cur;
     }
@@ -260,7 +266,8 @@ lb_status lb_adjoint_step(lb_ctx* ctx, const void* state_t_dev, double* dtheta3_
     if (!aligned(state_t_dev)) return fail(LB_EALIGN, "state_t_dev is not 256-byte aligned");
     int nb = 0;
     double* part = static_cast<double*>(ctx->b.scratch);
-    hipError_t e = lbk::launch_adj_step(ctx->kp, ctx->fp32, state_t_dev, ctx->b.phi,
+    hipError_t e = lbk::launch_adj_step(ctx->kp, ctx->fp32, state_t_dev,
+                                        static_cast<double*>(ctx->b.phi),
                                         ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
                                         ctx->b.adj_scratch, part, &nb, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "lb_adjoint_step");

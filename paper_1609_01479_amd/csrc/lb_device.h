@@ -1,0 +1,298 @@
+// Device-side building blocks shared by the forward and adjoint kernels:
+// the D3Q19 lattice, periodic site geometry, the pull of a stored time level,
+// and the local physics (order-parameter stencil, chemical potential and
+// stress, equilibria, BGK).
+//
+// Stored time level (pre-propagation, post-collision values at site y):
+//   FP64 mode  (T = double, DEV = REF = false):
+//       F_i(y) = f*_i(y),  G_i(y) = g*_i(y)
+//   FP32 mode  (T = float,  DEV = REF = true):
+//       F_i(y) = f*_i(y) - w_i rho0                      (FP32)
+//       G_i(y) = g*_i(y) - r_i phi_c(y)                  (FP32)
+//       phi_c(y) = the order parameter the collision at y used (FP64)
+//   with r_i = w_i (1 - 3/2 (|c_i|^2 - 1)) = (5/6, 1/18, -1/72): r_i phi is
+//   the order-parameter equilibrium of a fluid at rest with mu = 0, so both
+//   stored deviations are small in the bulk phases and FP32 rounding does not
+//   accumulate into the O(1) order parameter.  sum_i r_i = 1.
+// Post-propagation values at x are the pull  f_i(x) = f*_i(x - c_i).
+#pragma once
+
+#include "lb_internal.h"
+
+namespace lbk {
+namespace dev {
+
+constexpr int kBlock = 256;
+
+// D3Q19 velocities: rest, +-x, +-y, +-z, 12 edges (ABI order).
+constexpr int CX[NV] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[NV] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[NV] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+__host__ __device__ constexpr double weight(int i)
+{
+    return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+// rest-state order-parameter equilibrium weights r_i
+__host__ __device__ constexpr double rweight(int i)
+{
+    return i == 0 ? 5.0 / 6.0 : (i < 7 ? 1.0 / 18.0 : -1.0 / 72.0);
+}
+
+// ---------------------------------------------------------------------------
+// Periodic geometry.
+
+struct Geo {
+    int x, y, z, xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ int wrapm(int v, int n) { return v == 0 ? n - 1 : v - 1; }
+__device__ __forceinline__ int wrapp(int v, int n) { return v == n - 1 ? 0 : v + 1; }
+
+__device__ __forceinline__ Geo geo_xyz(const KParams& p, int x, int y, int z)
+{
+    Geo q;
+    q.x = x; q.y = y; q.z = z;
+    q.xm = wrapm(x, p.nx); q.xp = wrapp(x, p.nx);
+    q.ym = wrapm(y, p.ny); q.yp = wrapp(y, p.ny);
+    q.zm = wrapm(z, p.nz); q.zp = wrapp(z, p.nz);
+    return q;
+}
+
+__device__ __forceinline__ Geo geo_of(const KParams& p, int s)
+{
+    const int z = s % p.nz;
+    const int t = s / p.nz;
+    return geo_xyz(p, t / p.ny, t % p.ny, z);
+}
+
+__device__ __forceinline__ int site_of(const KParams& p, int x, int y, int z)
+{
+    return (x * p.ny + y) * p.nz + z;
+}
+
+__device__ __forceinline__ int minus_c(int c, int v, int vm, int vp) { return c > 0 ? vm : (c < 0 ? vp : v); }
+__device__ __forceinline__ int plus_c(int c, int v, int vm, int vp) { return c > 0 ? vp : (c < 0 ? vm : v); }
+
+// x - c_i and x + c_i
+__device__ __forceinline__ int pull_site(const KParams& p, const Geo& q, int i)
+{
+    return site_of(p, minus_c(CX[i], q.x, q.xm, q.xp), minus_c(CY[i], q.y, q.ym, q.yp),
+                   minus_c(CZ[i], q.z, q.zm, q.zp));
+}
+__device__ __forceinline__ int push_site(const KParams& p, const Geo& q, int i)
+{
+    return site_of(p, plus_c(CX[i], q.x, q.xm, q.xp), plus_c(CY[i], q.y, q.ym, q.yp),
+                   plus_c(CZ[i], q.z, q.zm, q.zp));
+}
+
+// ---------------------------------------------------------------------------
+// Pull of the order-parameter populations.  d[i] = g_i(x) in FP64:
+//   FP64 mode: G_i(x - c_i);  FP32 mode: G_i(x - c_i) + r_i phi_c(x - c_i).
+// Returns phi(x) = sum_i d[i], summed in index order (every kernel forms phi
+// through this function, so a site's phi is bit-identical everywhere).
+template <typename T, bool REF>
+__device__ __forceinline__ double pull_g(const KParams& p, const Geo& q, const T* __restrict__ G,
+                                         const double* __restrict__ phic, double* d)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        const int n = pull_site(p, q, i);
+        const double gv = double(G[i * p.stride + n]);
+        d[i] = REF ? __builtin_fma(rweight(i), phic[n], gv) : gv;
+        acc += d[i];
+    }
+    return acc;
+}
+
+template <typename T, bool REF>
+__device__ __forceinline__ double phi_at(const KParams& p, const Geo& q, const T* __restrict__ G,
+                                         const double* __restrict__ phic)
+{
+    double d[NV];
+    return pull_g<T, REF>(p, q, G, phic, d);
+}
+
+// ---------------------------------------------------------------------------
+// Local physics.
+
+// Order-parameter derivatives from the 7 stencil values (FP64 differences).
+struct Stencil {
+    double phi, gx, gy, gz, lap;
+};
+
+__device__ __forceinline__ Stencil stencil(double c, double xp, double xm, double yp, double ym,
+                                           double zp, double zm)
+{
+    Stencil s;
+    s.phi = c;
+    s.gx = 0.5 * (xp - xm);
+    s.gy = 0.5 * (yp - ym);
+    s.gz = 0.5 * (zp - zm);
+    s.lap = (xp + xm - 2.0 * c) + (yp + ym - 2.0 * c) + (zp + zm - 2.0 * c);
+    return s;
+}
+
+template <typename T>
+struct Moments {
+    T b;  // sum of the stored f (rho, or rho - rho0 in DEV)
+    T rho, jx, jy, jz;
+};
+
+template <typename T, bool DEV>
+__device__ __forceinline__ Moments<T> moments_of(const KParams& p, const T* f)
+{
+    Moments<T> m;
+    T b = f[0];
+#pragma unroll
+    for (int i = 1; i < NV; i++) b += f[i];
+    m.b = b;
+    m.rho = DEV ? T(p.rho0) + b : b;
+    m.jx = (f[1] - f[2]) + (f[7] - f[8]) + (f[9] - f[10]) + (f[11] - f[12]) + (f[13] - f[14]);
+    m.jy = (f[3] - f[4]) + (f[7] - f[8]) - (f[9] - f[10]) + (f[15] - f[16]) + (f[17] - f[18]);
+    m.jz = (f[5] - f[6]) + (f[11] - f[12]) - (f[13] - f[14]) + (f[15] - f[16]) - (f[17] - f[18]);
+    return m;
+}
+
+// BGK collision of one site, in place on f[] (stored convention: raw or
+// deviation) and g[] (FP64 mode: g_i; FP32 mode: g_i - r_i phi).
+//   mu = A phi + B phi^3 - kappa lap,  Pi = iso I + kappa grad grad,
+//   f_eq = w [b + 3 c.j + 9/2 Q:(Pi + j j / rho)]           (b = sum f stored)
+//   g_eq = w [phi + 3 phi c.u + 9/2 (Gamma mu - phi/3)(|c|^2 - 1)
+//             + 9/2 phi ((c.u)^2 - |u|^2/3)]
+//   g_eq - r phi = w [3 phi c.u + 9/2 Gamma mu (|c|^2 - 1) + 9/2 phi ((c.u)^2 - |u|^2/3)]
+template <typename T, bool DEV, bool REF>
+__device__ __forceinline__ void collide(const KParams& p, T* f, T* g, const Stencil& st)
+{
+    const T A = T(p.A), B = T(p.B), kap = T(p.kappa), gam = T(p.gamma);
+    const T omf = T(p.omega_f), omg = T(p.omega_g);
+    const T phi = T(st.phi), gx = T(st.gx), gy = T(st.gy), gz = T(st.gz), lap = T(st.lap);
+    const T phi2 = phi * phi;
+    const T mu = A * phi + B * phi2 * phi - kap * lap;
+    const T iso = T(0.5) * A * phi2 + T(0.75) * B * phi2 * phi2 - kap * phi * lap
+                - T(0.5) * kap * (gx * gx + gy * gy + gz * gz);
+
+    const Moments<T> m = moments_of<T, DEV>(p, f);
+    const T b = m.b, jx = m.jx, jy = m.jy, jz = m.jz;
+    const T ri = T(1) / m.rho;
+    const T ux = jx * ri, uy = jy * ri, uz = jz * ri;
+
+    // M = Pi + rho u u
+    const T mxx = iso + kap * gx * gx + jx * ux;
+    const T myy = iso + kap * gy * gy + jy * uy;
+    const T mzz = iso + kap * gz * gz + jz * uz;
+    const T mxy = kap * gx * gy + jx * uy;
+    const T mxz = kap * gx * gz + jx * uz;
+    const T myz = kap * gy * gz + jy * uz;
+    const T tm = (mxx + myy + mzz) * T(1.0 / 3.0);
+
+    const T h = T(4.5);
+    const T w0 = T(weight(0)), wf = T(weight(1)), we = T(weight(7));
+    const T wf3 = T(3.0 * weight(1)), we3 = T(3.0 * weight(7));
+
+    T eq[NV];
+    eq[0] = w0 * (b - h * tm);
+    {
+        const T sx = wf * (b + h * (mxx - tm)), ax = wf3 * jx;
+        const T sy = wf * (b + h * (myy - tm)), ay = wf3 * jy;
+        const T sz = wf * (b + h * (mzz - tm)), az = wf3 * jz;
+        eq[1] = sx + ax; eq[2] = sx - ax;
+        eq[3] = sy + ay; eq[4] = sy - ay;
+        eq[5] = sz + az; eq[6] = sz - az;
+    }
+    {
+        const T dxy = mxx + myy - tm, dxz = mxx + mzz - tm, dyz = myy + mzz - tm;
+        const T s7 = we * (b + h * (dxy + T(2) * mxy)), a7 = we3 * (jx + jy);
+        const T s9 = we * (b + h * (dxy - T(2) * mxy)), a9 = we3 * (jx - jy);
+        const T s11 = we * (b + h * (dxz + T(2) * mxz)), a11 = we3 * (jx + jz);
+        const T s13 = we * (b + h * (dxz - T(2) * mxz)), a13 = we3 * (jx - jz);
+        const T s15 = we * (b + h * (dyz + T(2) * myz)), a15 = we3 * (jy + jz);
+        const T s17 = we * (b + h * (dyz - T(2) * myz)), a17 = we3 * (jy - jz);
+        eq[7] = s7 + a7;     eq[8] = s7 - a7;
+        eq[9] = s9 + a9;     eq[10] = s9 - a9;
+        eq[11] = s11 + a11;  eq[12] = s11 - a11;
+        eq[13] = s13 + a13;  eq[14] = s13 - a13;
+        eq[15] = s15 + a15;  eq[16] = s15 - a15;
+        eq[17] = s17 + a17;  eq[18] = s17 - a17;
+    }
+#pragma unroll
+    for (int i = 0; i < NV; i++) f[i] += omf * (eq[i] - f[i]);
+
+    const T uu3 = (ux * ux + uy * uy + uz * uz) * T(1.0 / 3.0);
+    const T hp = h * phi;
+    // rest, face and edge parts of (g_eq or g_eq - r phi) without the c.u terms
+    T e0, ef, ee;
+    if (REF) {
+        const T hgm = h * gam * mu;
+        e0 = w0 * (-hgm - hp * uu3);
+        ef = -hp * uu3;          // times wf below, plus hp (c.u)^2
+        ee = hgm - hp * uu3;     // times we below, plus hp (c.u)^2
+    } else {
+        const T sg = gam * mu - phi * T(1.0 / 3.0);
+        e0 = w0 * (phi - h * sg - hp * uu3);
+        ef = phi - hp * uu3;
+        ee = phi + h * sg - hp * uu3;
+    }
+    eq[0] = e0;
+    {
+        const T p3f = wf3 * phi;
+        const T sx = wf * (ef + hp * ux * ux);
+        const T sy = wf * (ef + hp * uy * uy);
+        const T sz = wf * (ef + hp * uz * uz);
+        eq[1] = sx + p3f * ux; eq[2] = sx - p3f * ux;
+        eq[3] = sy + p3f * uy; eq[4] = sy - p3f * uy;
+        eq[5] = sz + p3f * uz; eq[6] = sz - p3f * uz;
+    }
+    {
+        const T p3e = we3 * phi;
+        const T c7 = ux + uy, c9 = ux - uy, c11 = ux + uz, c13 = ux - uz, c15 = uy + uz,
+                c17 = uy - uz;
+        const T s7 = we * (ee + hp * c7 * c7), s9 = we * (ee + hp * c9 * c9);
+        const T s11 = we * (ee + hp * c11 * c11), s13 = we * (ee + hp * c13 * c13);
+        const T s15 = we * (ee + hp * c15 * c15), s17 = we * (ee + hp * c17 * c17);
+        eq[7] = s7 + p3e * c7;     eq[8] = s7 - p3e * c7;
+        eq[9] = s9 + p3e * c9;     eq[10] = s9 - p3e * c9;
+        eq[11] = s11 + p3e * c11;  eq[12] = s11 - p3e * c11;
+        eq[13] = s13 + p3e * c13;  eq[14] = s13 - p3e * c13;
+        eq[15] = s15 + p3e * c15;  eq[16] = s15 - p3e * c15;
+        eq[17] = s17 + p3e * c17;  eq[18] = s17 - p3e * c17;
+    }
+#pragma unroll
+    for (int i = 0; i < NV; i++) g[i] += omg * (eq[i] - g[i]);
+}
+
+// Pre-collision order-parameter populations in the stored convention from the
+// pulled FP64 values d[] and the site's phi.
+template <typename T, bool REF>
+__device__ __forceinline__ void g_local(const double* d, double phi, T* g)
+{
+#pragma unroll
+    for (int i = 0; i < NV; i++) g[i] = REF ? T(d[i] - rweight(i) * phi) : T(d[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Block reduction of K FP64 values (fixed order): wavefront butterfly, then
+// the block's waves in order.  Thread 0 writes component k to
+// out[k*gridDim.x + blockIdx.x].  Needs blockDim.x == kBlock.
+template <int K>
+__device__ __forceinline__ void block_partials(double (&v)[K], double* out)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] += __shfl_xor(v[k], off, 64);
+    __shared__ double sm[K][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; k++) sm[k][wid] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            out[k * gridDim.x + blockIdx.x] = (sm[k][0] + sm[k][1]) + (sm[k][2] + sm[k][3]);
+}
+
+}  // namespace dev
+}  // namespace lbk

@@ -20,11 +20,25 @@ struct KParams {
     double rho0;
 };
 
+// Launch geometry of the single-pass step: (y, z) tiles times x segments.
+struct TileCfg {
+    int nty, ntz, ntiles;  // tiles along y, along z, total
+    int sx, nseg;          // planes per x segment, number of segments
+};
+
+// segment_x <= 0 picks the segment length automatically.
+TileCfg tile_config(const KParams& p, int segment_x);
+
 // All launchers enqueue on `s` and return hipGetLastError().
 // `fp32` selects the FP32 deviation-storage instantiation; otherwise FP64.
+// A time level (`state`) is F[19][stride], G[19][stride] and, in FP32 mode,
+// phi_c[stride] (FP64).  Order-parameter fields (`phi`) are FP64.
 hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* phi0, hipStream_t s);
-hipError_t launch_step(const KParams& p, bool fp32, const void* src, void* dst, void* phi,
-                       hipStream_t s);
+// variant 0: single-pass fused step; 1: phi pass + collision pass.
+hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
+                       const void* src, void* dst, double* phi_work, hipStream_t s);
+// phi(x) of the post-propagation state held in `state`.
+hipError_t launch_phi(const KParams& p, bool fp32, const void* state, double* phi, hipStream_t s);
 hipError_t launch_moments(const KParams& p, bool fp32, const void* state, double* rho, double* u,
                           double* phi, double* partials, int* nblocks_out, hipStream_t s);
 hipError_t launch_sums_final(const double* partials, int nblocks, int ncomp, double* out,
@@ -37,7 +51,7 @@ hipError_t launch_import(const KParams& p, bool fp32, void* state, const double*
 // Reverse mode.
 hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, const double* dphi,
                            hipStream_t s);
-hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state, void* phi,
+hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state, double* phi,
                            const void* adj_next, void* adj_prev, void* adj_scratch,
                            double* partials, int* nblocks_out, hipStream_t s);
 hipError_t launch_adj_phi0(const KParams& p, bool fp32, const void* adj, double* dphi0,

@@ -1,305 +1,195 @@
-// HIP kernels (gfx950) for the D3Q19 symmetric binary-fluid LB step and its
-// adjoint.
+// Forward kernels (gfx950) of the D3Q19 symmetric binary-fluid LB step.
 //
-// Storage (both precisions): a time level is f then g, each 19 components of
-// `stride` elements (structure of arrays, the layout the paper finds best for
-// GPUs, Sec. 4: coalesced access per component).  Component i of site s is
-// element i*stride + s, with s = (x*ny + y)*nz + z.  A time level holds the
-// post-collision, pre-propagation values f*_i(x); propagation is realised as
-// a pull: the post-propagation value at x is f_i(x) = f*_i(x - c_i), read by
-// the next kernel that needs it.  Periodic wrap is index arithmetic, so no
-// halo copies exist.
+// The step of the paper's Ludwig timestep (Sec. 2.1.1) -- order-parameter
+// gradients, chemical stress, collision, propagation -- runs as ONE kernel,
+// k_step_fused: each workgroup owns a (y, z) tile of 4 x 64 sites and marches
+// along x over a segment of planes.  For plane x it needs phi at planes
+// x-1, x, x+1 (7-point stencil); phi(x+1) is formed from the pulled g of
+// plane x+1, which the same threads keep in registers for plane x+1's own
+// collision one iteration later.  phi on the tile's (y, z) halo ring is
+// formed by extra pulls that mostly hit in cache (the neighbouring tiles read
+// the same lines).  phi planes live in a 4-slot LDS ring.  Every population
+// is therefore read once and written once per step from HBM: the method's
+// minimum traffic, instead of a separate phi pass plus a collision pass.
 //
-// T = double: FP64 storage and arithmetic.  T = float with DEV = true: the
-// FP32 deviation mode, where f is stored as f_i - w_i rho0 (g raw) and the
-// collision works on deviations, so the O(1) rest part never enters FP32
-// rounding; reductions stay FP64.
-#include "lb_internal.h"
+// k_phi + k_step_2s are the two-pass variant (phi kernel, then the fused
+// stencil/collision/propagation kernel), kept for comparison.
+#include "lb_device.h"
 
 namespace lbk {
+
+using namespace dev;
+
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int TZ = 64;  // tile extent along z (contiguous): one wavefront row
+constexpr int TY = kBlock / TZ;
 
-// D3Q19 velocities: rest, +-x, +-y, +-z, 12 edges (same order as the ABI).
-constexpr int CX[NV] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-constexpr int CY[NV] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-constexpr int CZ[NV] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-
-__host__ __device__ constexpr double weight(int i)
-{
-    return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
-}
-
-// Site coordinates with periodic neighbours along each axis.
-struct Geo {
-    int x, y, z, xm, xp, ym, yp, zm, zp;
-};
-
-__device__ __forceinline__ Geo geo_of(const KParams& p, int s)
-{
-    Geo q;
-    q.z = s % p.nz;
-    const int t = s / p.nz;
-    q.y = t % p.ny;
-    q.x = t / p.ny;
-    q.xm = q.x == 0 ? p.nx - 1 : q.x - 1;
-    q.xp = q.x == p.nx - 1 ? 0 : q.x + 1;
-    q.ym = q.y == 0 ? p.ny - 1 : q.y - 1;
-    q.yp = q.y == p.ny - 1 ? 0 : q.y + 1;
-    q.zm = q.z == 0 ? p.nz - 1 : q.z - 1;
-    q.zp = q.z == p.nz - 1 ? 0 : q.z + 1;
-    return q;
-}
-
-__device__ __forceinline__ int site_of(const KParams& p, int x, int y, int z)
-{
-    return (x * p.ny + y) * p.nz + z;
-}
-
-// Coordinate v - c (pull source) and v + c (push destination) for c in {-1,0,1}.
-__device__ __forceinline__ int minus_c(int c, int v, int vm, int vp) { return c > 0 ? vm : (c < 0 ? vp : v); }
-__device__ __forceinline__ int plus_c(int c, int v, int vm, int vp) { return c > 0 ? vp : (c < 0 ? vm : v); }
-
-// Site x - c_i and x + c_i.
-__device__ __forceinline__ int pull_site(const KParams& p, const Geo& q, int i)
-{
-    return site_of(p, minus_c(CX[i], q.x, q.xm, q.xp), minus_c(CY[i], q.y, q.ym, q.yp),
-                   minus_c(CZ[i], q.z, q.zm, q.zp));
-}
-__device__ __forceinline__ int push_site(const KParams& p, const Geo& q, int i)
-{
-    return site_of(p, plus_c(CX[i], q.x, q.xm, q.xp), plus_c(CY[i], q.y, q.ym, q.yp),
-                   plus_c(CZ[i], q.z, q.zm, q.zp));
-}
-
-// ---------------------------------------------------------------------------
-// Local physics at one site.
-
-// Order-parameter derivatives from the 7 stencil values.
 template <typename T>
-struct Stencil {
-    T phi, gx, gy, gz, lap;
+struct Lvl {
+    T* F;
+    T* G;
+    double* phic;  // FP32 mode only
 };
 
 template <typename T>
-__device__ __forceinline__ Stencil<T> stencil(T c, T xp, T xm, T yp, T ym, T zp, T zm)
+Lvl<T> level(void* state, const KParams& p, bool ref)
 {
-    Stencil<T> s;
-    s.phi = c;
-    s.gx = T(0.5) * (xp - xm);
-    s.gy = T(0.5) * (yp - ym);
-    s.gz = T(0.5) * (zp - zm);
-    s.lap = (xp + xm - T(2) * c) + (yp + ym - T(2) * c) + (zp + zm - T(2) * c);
-    return s;
-}
-
-// Momentum moments of the 19 stored populations (raw, or deviations in DEV).
-template <typename T>
-struct Moments {
-    T b;           // sum f (rho, or rho - rho0 in DEV)
-    T rho, jx, jy, jz;
-};
-
-template <typename T, bool DEV>
-__device__ __forceinline__ Moments<T> moments_of(const KParams& p, const T* f)
-{
-    Moments<T> m;
-    T b = f[0];
-#pragma unroll
-    for (int i = 1; i < NV; i++) b += f[i];
-    m.b = b;
-    m.rho = DEV ? T(p.rho0) + b : b;
-    m.jx = (f[1] - f[2]) + (f[7] - f[8]) + (f[9] - f[10]) + (f[11] - f[12]) + (f[13] - f[14]);
-    m.jy = (f[3] - f[4]) + (f[7] - f[8]) - (f[9] - f[10]) + (f[15] - f[16]) + (f[17] - f[18]);
-    m.jz = (f[5] - f[6]) + (f[11] - f[12]) - (f[13] - f[14]) + (f[15] - f[16]) - (f[17] - f[18]);
-    return m;
-}
-
-// BGK collision of f and g in place.
-//   mu = A phi + B phi^3 - kappa lap, Pi = iso I + kappa grad grad,
-//   f_eq = w [b + 3 c.j + 9/2 Q:(Pi + j j / rho)],
-//   g_eq = w [phi + 3 phi c.u + 9/2 (Gamma mu - phi/3)(|c|^2 - 1)
-//             + 9/2 phi ((c.u)^2 - |u|^2/3)].
-template <typename T, bool DEV>
-__device__ __forceinline__ void collide(const KParams& p, T* f, T* g, const Stencil<T>& st)
-{
-    const T A = T(p.A), B = T(p.B), kap = T(p.kappa), gam = T(p.gamma);
-    const T omf = T(p.omega_f), omg = T(p.omega_g);
-    const T phi = st.phi, gx = st.gx, gy = st.gy, gz = st.gz, lap = st.lap;
-    const T phi2 = phi * phi;
-    const T mu = A * phi + B * phi2 * phi - kap * lap;
-    const T iso = T(0.5) * A * phi2 + T(0.75) * B * phi2 * phi2 - kap * phi * lap
-                - T(0.5) * kap * (gx * gx + gy * gy + gz * gz);
-
-    const Moments<T> m = moments_of<T, DEV>(p, f);
-    const T b = m.b, jx = m.jx, jy = m.jy, jz = m.jz;
-    const T ri = T(1) / m.rho;
-    const T ux = jx * ri, uy = jy * ri, uz = jz * ri;
-
-    // M = Pi + rho u u
-    const T mxx = iso + kap * gx * gx + jx * ux;
-    const T myy = iso + kap * gy * gy + jy * uy;
-    const T mzz = iso + kap * gz * gz + jz * uz;
-    const T mxy = kap * gx * gy + jx * uy;
-    const T mxz = kap * gx * gz + jx * uz;
-    const T myz = kap * gy * gz + jy * uz;
-    const T tm = (mxx + myy + mzz) * T(1.0 / 3.0);
-
-    const T h = T(4.5);
-    const T w0 = T(weight(0)), wf = T(weight(1)), we = T(weight(7));
-    const T wf3 = T(3.0 * weight(1)), we3 = T(3.0 * weight(7));
-
-    T eq[NV];
-    eq[0] = w0 * (b - h * tm);
-    {
-        const T sx = wf * (b + h * (mxx - tm)), ax = wf3 * jx;
-        const T sy = wf * (b + h * (myy - tm)), ay = wf3 * jy;
-        const T sz = wf * (b + h * (mzz - tm)), az = wf3 * jz;
-        eq[1] = sx + ax; eq[2] = sx - ax;
-        eq[3] = sy + ay; eq[4] = sy - ay;
-        eq[5] = sz + az; eq[6] = sz - az;
-    }
-    {
-        const T dxy = mxx + myy - tm, dxz = mxx + mzz - tm, dyz = myy + mzz - tm;
-        const T s7 = we * (b + h * (dxy + T(2) * mxy)), a7 = we3 * (jx + jy);
-        const T s9 = we * (b + h * (dxy - T(2) * mxy)), a9 = we3 * (jx - jy);
-        const T s11 = we * (b + h * (dxz + T(2) * mxz)), a11 = we3 * (jx + jz);
-        const T s13 = we * (b + h * (dxz - T(2) * mxz)), a13 = we3 * (jx - jz);
-        const T s15 = we * (b + h * (dyz + T(2) * myz)), a15 = we3 * (jy + jz);
-        const T s17 = we * (b + h * (dyz - T(2) * myz)), a17 = we3 * (jy - jz);
-        eq[7] = s7 + a7;     eq[8] = s7 - a7;
-        eq[9] = s9 + a9;     eq[10] = s9 - a9;
-        eq[11] = s11 + a11;  eq[12] = s11 - a11;
-        eq[13] = s13 + a13;  eq[14] = s13 - a13;
-        eq[15] = s15 + a15;  eq[16] = s15 - a15;
-        eq[17] = s17 + a17;  eq[18] = s17 - a17;
-    }
-#pragma unroll
-    for (int i = 0; i < NV; i++) f[i] += omf * (eq[i] - f[i]);
-
-    const T sg = gam * mu - phi * T(1.0 / 3.0);
-    const T uu3 = (ux * ux + uy * uy + uz * uz) * T(1.0 / 3.0);
-    const T hp = h * phi;
-    eq[0] = w0 * (phi - h * sg - hp * uu3);
-    {
-        const T p3f = wf3 * phi;
-        const T sx = wf * (phi + hp * (ux * ux - uu3));
-        const T sy = wf * (phi + hp * (uy * uy - uu3));
-        const T sz = wf * (phi + hp * (uz * uz - uu3));
-        eq[1] = sx + p3f * ux; eq[2] = sx - p3f * ux;
-        eq[3] = sy + p3f * uy; eq[4] = sy - p3f * uy;
-        eq[5] = sz + p3f * uz; eq[6] = sz - p3f * uz;
-    }
-    {
-        const T p3e = we3 * phi;
-        const T base = phi + h * sg - hp * uu3;
-        const T c7 = ux + uy, c9 = ux - uy, c11 = ux + uz, c13 = ux - uz, c15 = uy + uz,
-                c17 = uy - uz;
-        const T s7 = we * (base + hp * c7 * c7), s9 = we * (base + hp * c9 * c9);
-        const T s11 = we * (base + hp * c11 * c11), s13 = we * (base + hp * c13 * c13);
-        const T s15 = we * (base + hp * c15 * c15), s17 = we * (base + hp * c17 * c17);
-        eq[7] = s7 + p3e * c7;     eq[8] = s7 - p3e * c7;
-        eq[9] = s9 + p3e * c9;     eq[10] = s9 - p3e * c9;
-        eq[11] = s11 + p3e * c11;  eq[12] = s11 - p3e * c11;
-        eq[13] = s13 + p3e * c13;  eq[14] = s13 - p3e * c13;
-        eq[15] = s15 + p3e * c15;  eq[16] = s15 - p3e * c15;
-        eq[17] = s17 + p3e * c17;  eq[18] = s17 - p3e * c17;
-    }
-#pragma unroll
-    for (int i = 0; i < NV; i++) g[i] += omg * (eq[i] - g[i]);
+    T* base = static_cast<T*>(state);
+    Lvl<T> l;
+    l.F = base;
+    l.G = base + NV * p.stride;
+    l.phic = ref ? reinterpret_cast<double*>(base + 2 * NV * p.stride) : nullptr;
+    return l;
 }
 
 // ---------------------------------------------------------------------------
-// Block reduction of K FP64 values: wavefront butterfly (fixed order), then
-// the 4 wave results in a fixed order.  Thread 0 writes component k of this
-// block to out[k*nblocks + blockIdx.x].
-template <int K>
-__device__ __forceinline__ void block_partials(double (&v)[K], double* out)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int k = 0; k < K; k++) v[k] += __shfl_xor(v[k], off, 64);
-    __shared__ double sm[K][kBlock / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < K; k++) sm[k][wid] = v[k];
-    __syncthreads();
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int k = 0; k < K; k++)
-            out[k * gridDim.x + blockIdx.x] = (sm[k][0] + sm[k][1]) + (sm[k][2] + sm[k][3]);
-}
 
-// ---------------------------------------------------------------------------
-// Forward kernels.
-
-template <typename T, bool DEV>
-__global__ __launch_bounds__(kBlock) void k_init(KParams p, T* __restrict__ f, T* __restrict__ g,
+template <typename T, bool DEV, bool REF>
+__global__ __launch_bounds__(kBlock) void k_init(KParams p, T* __restrict__ F, T* __restrict__ G,
+                                                 double* __restrict__ phic,
                                                  const double* __restrict__ phi0)
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
+    const double ph = phi0[s];
 #pragma unroll
     for (int i = 0; i < NV; i++) {
-        f[i * p.stride + s] = DEV ? T(0) : T(weight(i) * p.rho0);
-        g[i * p.stride + s] = i == 0 ? T(phi0[s]) : T(0);
+        F[i * p.stride + s] = DEV ? T(0) : T(weight(i) * p.rho0);
+        const double gi = i == 0 ? ph : 0.0;
+        G[i * p.stride + s] = REF ? T(gi - rweight(i) * ph) : T(gi);
     }
+    if (REF) phic[s] = ph;
 }
 
-// phi(x) = sum_i g_i(x) of the post-propagation state, i.e. sum_i g*_i(x - c_i).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_phi(KParams p, const T* __restrict__ g,
-                                                T* __restrict__ phi)
+// phi(x) = sum_i g_i(x) of the post-propagation state (FP64).
+template <typename T, bool REF>
+__global__ __launch_bounds__(kBlock) void k_phi(KParams p, const T* __restrict__ G,
+                                                const double* __restrict__ phic,
+                                                double* __restrict__ phi)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    phi[s] = phi_at<T, REF>(p, geo_of(p, s), G, phic);
+}
+
+// Two-pass variant, second pass: stencil + chemical stress + collision, one
+// site per thread; phi of the new state comes from k_phi.
+template <typename T, bool DEV, bool REF>
+__global__ __launch_bounds__(kBlock) void k_step_2s(KParams p, const T* __restrict__ sF,
+                                                    const T* __restrict__ sG,
+                                                    const double* __restrict__ sphic,
+                                                    const double* __restrict__ phi,
+                                                    T* __restrict__ dF, T* __restrict__ dG)
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
     const Geo q = geo_of(p, s);
-    T acc = T(0);
-#pragma unroll
-    for (int i = 0; i < NV; i++) acc += g[i * p.stride + pull_site(p, q, i)];
-    phi[s] = acc;
-}
-
-// Gradients + chemical stress + collision + propagation (as the pull of the
-// next step) for one site per thread.
-template <typename T, bool DEV>
-__global__ __launch_bounds__(kBlock) void k_step(KParams p, const T* __restrict__ sf,
-                                                 const T* __restrict__ sg,
-                                                 const T* __restrict__ phi,
-                                                 T* __restrict__ df, T* __restrict__ dg)
-{
-    const int s = blockIdx.x * kBlock + threadIdx.x;
-    if (s >= p.nsites) return;
-    const Geo q = geo_of(p, s);
-    const Stencil<T> st = stencil<T>(phi[s], phi[site_of(p, q.xp, q.y, q.z)],
-                                     phi[site_of(p, q.xm, q.y, q.z)],
-                                     phi[site_of(p, q.x, q.yp, q.z)],
-                                     phi[site_of(p, q.x, q.ym, q.z)],
-                                     phi[site_of(p, q.x, q.y, q.zp)],
-                                     phi[site_of(p, q.x, q.y, q.zm)]);
     T f[NV], g[NV];
 #pragma unroll
-    for (int i = 0; i < NV; i++) {
-        const int n = pull_site(p, q, i);
-        f[i] = sf[i * p.stride + n];
-        g[i] = sg[i * p.stride + n];
-    }
-    collide<T, DEV>(p, f, g, st);
+    for (int i = 0; i < NV; i++) f[i] = sF[i * p.stride + pull_site(p, q, i)];
+    double d[NV];
+    const double pc = pull_g<T, REF>(p, q, sG, sphic, d);
+    const Stencil st = stencil(pc, phi[site_of(p, q.xp, q.y, q.z)], phi[site_of(p, q.xm, q.y, q.z)],
+                               phi[site_of(p, q.x, q.yp, q.z)], phi[site_of(p, q.x, q.ym, q.z)],
+                               phi[site_of(p, q.x, q.y, q.zp)], phi[site_of(p, q.x, q.y, q.zm)]);
+    g_local<T, REF>(d, pc, g);
+    collide<T, DEV, REF>(p, f, g, st);
 #pragma unroll
     for (int i = 0; i < NV; i++) {
-        df[i * p.stride + s] = f[i];
-        dg[i * p.stride + s] = g[i];
+        dF[i * p.stride + s] = f[i];
+        dG[i * p.stride + s] = g[i];
+    }
+}
+
+// Single-pass step (see the file comment).  Block -> (segment, tile) with
+// an XCD-aware order: consecutive workgroup ids go round-robin over the 8
+// XCDs, so ids are remapped to give each XCD a contiguous run of tiles,
+// y-adjacent tiles first, whose halo rows then meet in the same L2.
+template <typename T, bool DEV, bool REF>
+__global__ __launch_bounds__(kBlock) void k_step_fused(KParams p, TileCfg tc,
+                                                       const T* __restrict__ sF,
+                                                       const T* __restrict__ sG,
+                                                       const double* __restrict__ sphic,
+                                                       T* __restrict__ dF, T* __restrict__ dG,
+                                                       double* __restrict__ dphic)
+{
+    __shared__ double ph[4][TY + 2][TZ + 2];
+
+    int b = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int tile = b % tc.ntiles, seg = b / tc.ntiles;
+    const int y0 = (tile % tc.nty) * TY, z0 = (tile / tc.nty) * TZ;
+    const int x0 = seg * tc.sx;
+    const int x1 = min(x0 + tc.sx, p.nx);
+    const int tya = min(TY, p.ny - y0), tza = min(TZ, p.nz - z0);
+    const int lz = threadIdx.x % TZ, ly = threadIdx.x / TZ;
+    const bool active = lz < tza && ly < tya;
+    const int y = y0 + ly, z = z0 + lz;
+
+    // halo ring: rows y0-1 and y0+tya, then columns z0-1 and z0+tza
+    const int r = threadIdx.x;
+    const int nring = 2 * tza + 2 * tya;
+    const bool ring = r < nring;
+    int rly, rlz;
+    if (r < tza) { rly = 0; rlz = r + 1; }
+    else if (r < 2 * tza) { rly = tya + 1; rlz = r - tza + 1; }
+    else if (r < 2 * tza + tya) { rly = r - 2 * tza + 1; rlz = 0; }
+    else { rly = r - 2 * tza - tya + 1; rlz = tza + 1; }
+    int ry = y0 + rly - 1, rz = z0 + rlz - 1;
+    ry = ry < 0 ? ry + p.ny : (ry >= p.ny ? ry - p.ny : ry);
+    rz = rz < 0 ? rz + p.nz : (rz >= p.nz ? rz - p.nz : rz);
+
+    double dcur[NV], dnext[NV];
+    // warm-up: phi at planes x0-1 (slot 0) and x0 (slot 1); keep g of plane x0
+    const int xb = x0 == 0 ? p.nx - 1 : x0 - 1;
+    if (active) ph[0][ly + 1][lz + 1] = pull_g<T, REF>(p, geo_xyz(p, xb, y, z), sG, sphic, dcur);
+    if (ring) ph[0][rly][rlz] = phi_at<T, REF>(p, geo_xyz(p, xb, ry, rz), sG, sphic);
+    if (active) ph[1][ly + 1][lz + 1] = pull_g<T, REF>(p, geo_xyz(p, x0, y, z), sG, sphic, dcur);
+    if (ring) ph[1][rly][rlz] = phi_at<T, REF>(p, geo_xyz(p, x0, ry, rz), sG, sphic);
+
+    for (int x = x0; x < x1; x++) {
+        const int k = x - x0 + 2;  // slot counter of plane x+1
+        const int sn = k & 3, sc = (k - 1) & 3, sp = (k - 2) & 3;
+        const int xn = x == p.nx - 1 ? 0 : x + 1;
+        T f[NV];
+        Geo qc;
+        if (active) {
+            qc = geo_xyz(p, x, y, z);
+#pragma unroll
+            for (int i = 0; i < NV; i++) f[i] = sF[i * p.stride + pull_site(p, qc, i)];
+            ph[sn][ly + 1][lz + 1] = pull_g<T, REF>(p, geo_xyz(p, xn, y, z), sG, sphic, dnext);
+        }
+        if (ring) ph[sn][rly][rlz] = phi_at<T, REF>(p, geo_xyz(p, xn, ry, rz), sG, sphic);
+        __syncthreads();
+        if (active) {
+            const double c = ph[sc][ly + 1][lz + 1];
+            const Stencil st = stencil(c, ph[sn][ly + 1][lz + 1], ph[sp][ly + 1][lz + 1],
+                                       ph[sc][ly + 2][lz + 1], ph[sc][ly][lz + 1],
+                                       ph[sc][ly + 1][lz + 2], ph[sc][ly + 1][lz]);
+            T g[NV];
+            g_local<T, REF>(dcur, c, g);
+            collide<T, DEV, REF>(p, f, g, st);
+            const int s = site_of(p, x, y, z);
+#pragma unroll
+            for (int i = 0; i < NV; i++) {
+                dF[i * p.stride + s] = f[i];
+                dG[i * p.stride + s] = g[i];
+            }
+            if (REF) dphic[s] = c;
+#pragma unroll
+            for (int i = 0; i < NV; i++) dcur[i] = dnext[i];
+        }
     }
 }
 
 // Dense FP64 moments of the post-propagation state and block partials of
-// [rho, phi, jx, jy, jz] (grid-stride; FP64 accumulation).
-template <typename T, bool DEV>
-__global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restrict__ f,
-                                                    const T* __restrict__ g,
+// [rho, phi, jx, jy, jz] (grid-stride, FP64 accumulation).
+template <typename T, bool DEV, bool REF>
+__global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restrict__ F,
+                                                    const T* __restrict__ G,
+                                                    const double* __restrict__ phic,
                                                     double* __restrict__ rho_out,
                                                     double* __restrict__ u_out,
                                                     double* __restrict__ phi_out,
@@ -308,13 +198,10 @@ __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restri
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int s = blockIdx.x * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
         const Geo q = geo_of(p, s);
-        double fv[NV], ph = 0.0;
+        double fv[NV];
 #pragma unroll
-        for (int i = 0; i < NV; i++) {
-            const int n = pull_site(p, q, i);
-            fv[i] = double(f[i * p.stride + n]);
-            ph += double(g[i * p.stride + n]);
-        }
+        for (int i = 0; i < NV; i++) fv[i] = double(F[i * p.stride + pull_site(p, q, i)]);
+        const double ph = phi_at<T, REF>(p, q, G, phic);
         double b = 0.0;
 #pragma unroll
         for (int i = 0; i < NV; i++) b += fv[i];
@@ -342,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restri
     block_partials<5>(acc, partials);
 }
 
-// out[k] (+)= sum over nblocks partials of component k, one block, fixed order.
+// out[k] (+)= sum over nblocks partials of component k; one block, fixed order.
 __global__ __launch_bounds__(kBlock) void k_sums_final(const double* __restrict__ partials,
                                                        int nblocks, int ncomp,
                                                        double* __restrict__ out, int accumulate)
@@ -362,210 +249,51 @@ __global__ __launch_bounds__(kBlock) void k_sums_final(const double* __restrict_
     }
 }
 
-template <typename T, bool DEV>
-__global__ __launch_bounds__(kBlock) void k_export(KParams p, const T* __restrict__ sf,
-                                                   const T* __restrict__ sg,
-                                                   double* __restrict__ f,
-                                                   double* __restrict__ g)
+template <typename T, bool DEV, bool REF>
+__global__ __launch_bounds__(kBlock) void k_export(KParams p, const T* __restrict__ F,
+                                                   const T* __restrict__ G,
+                                                   const double* __restrict__ phic,
+                                                   double* __restrict__ f, double* __restrict__ g)
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
     const Geo q = geo_of(p, s);
+    if (f)
 #pragma unroll
-    for (int i = 0; i < NV; i++) {
-        const int n = pull_site(p, q, i);
-        if (f) f[(long long)i * p.nsites + s] = double(sf[i * p.stride + n]) + (DEV ? weight(i) * p.rho0 : 0.0);
-        if (g) g[(long long)i * p.nsites + s] = double(sg[i * p.stride + n]);
+        for (int i = 0; i < NV; i++)
+            f[(long long)i * p.nsites + s] =
+                double(F[i * p.stride + pull_site(p, q, i)]) + (DEV ? weight(i) * p.rho0 : 0.0);
+    if (g) {
+        double d[NV];
+        pull_g<T, REF>(p, q, G, phic, d);
+#pragma unroll
+        for (int i = 0; i < NV; i++) g[(long long)i * p.nsites + s] = d[i];
     }
 }
 
-// Stored (pre-propagation) value at y is the post-propagation value at y + c_i.
-template <typename T, bool DEV>
-__global__ __launch_bounds__(kBlock) void k_import(KParams p, T* __restrict__ sf, T* __restrict__ sg,
+// Stored value at y is the post-propagation value at y + c_i.  In FP32 mode
+// the reference phi_c(y) is the dense input's sum_i g_i(y).
+template <typename T, bool DEV, bool REF>
+__global__ __launch_bounds__(kBlock) void k_import(KParams p, T* __restrict__ F, T* __restrict__ G,
+                                                   double* __restrict__ phic,
                                                    const double* __restrict__ f,
                                                    const double* __restrict__ g)
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
     const Geo q = geo_of(p, s);
+    double ref = 0.0;
+    if (REF) {
+#pragma unroll
+        for (int i = 0; i < NV; i++) ref += g[(long long)i * p.nsites + s];
+        phic[s] = ref;
+    }
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         const long long n = push_site(p, q, i) + (long long)i * p.nsites;
-        sf[i * p.stride + s] = T(f[n] - (DEV ? weight(i) * p.rho0 : 0.0));
-        sg[i * p.stride + s] = T(g[n]);
+        F[i * p.stride + s] = T(f[n] - (DEV ? weight(i) * p.rho0 : 0.0));
+        G[i * p.stride + s] = T(REF ? g[n] - rweight(i) * ref : g[n]);
     }
-}
-
-// ---------------------------------------------------------------------------
-// Reverse mode.
-//
-// An adjoint time level holds 39 components of `stride` elements:
-//   lf[19]: dL/df_i(x)            (post-propagation populations)
-//   lg[19]: the part of dL/dg_i(x) that is not common to all i
-//   lp    : the common part, dL/dphi(x)
-// so that dL/dg_i(x) = lg_i(x) + lp(x).  adj_scratch holds the stencil
-// cotangents a (direct dL/dphi), b_a (dL/d(d_a phi)), c (dL/d lap phi).
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj_seed(KParams p, T* __restrict__ adj,
-                                                     const double* __restrict__ dphi)
-{
-    const int s = blockIdx.x * kBlock + threadIdx.x;
-    if (s >= p.nsites) return;
-#pragma unroll
-    for (int i = 0; i < 2 * NV; i++) adj[i * p.stride + s] = T(0);
-    adj[2 * NV * p.stride + s] = T(dphi[s]);
-}
-
-// Transposed propagation (gather lambda*_i(x) = lambda_i(x + c_i)), then the
-// transposed local collision Jacobian at x, recomputing the forward locals
-// from the saved state.  Writes lf, lg of the previous level and the stencil
-// cotangents; block partials of d/d(A, B, kappa).
-template <typename T, bool DEV>
-__global__ __launch_bounds__(kBlock) void k_adj_local(KParams p, const T* __restrict__ sf,
-                                                      const T* __restrict__ sg,
-                                                      const T* __restrict__ phi,
-                                                      const T* __restrict__ an,
-                                                      T* __restrict__ ap,
-                                                      T* __restrict__ sc,
-                                                      double* __restrict__ partials)
-{
-    double dth[3] = {0.0, 0.0, 0.0};
-    const long long S = p.stride;
-    for (int s = blockIdx.x * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
-        const Geo q = geo_of(p, s);
-        T lf[NV], lg[NV], f[NV], g[NV];
-#pragma unroll
-        for (int i = 0; i < NV; i++) {
-            const int d = push_site(p, q, i);
-            lf[i] = an[i * S + d];
-            lg[i] = an[(NV + i) * S + d] + an[2 * NV * S + d];
-            const int n = pull_site(p, q, i);
-            f[i] = sf[i * S + n];
-            g[i] = sg[i * S + n];
-        }
-        (void)g;
-        const Stencil<T> st = stencil<T>(phi[s], phi[site_of(p, q.xp, q.y, q.z)],
-                                         phi[site_of(p, q.xm, q.y, q.z)],
-                                         phi[site_of(p, q.x, q.yp, q.z)],
-                                         phi[site_of(p, q.x, q.ym, q.z)],
-                                         phi[site_of(p, q.x, q.y, q.zp)],
-                                         phi[site_of(p, q.x, q.y, q.zm)]);
-        const T A = T(p.A), B = T(p.B), kap = T(p.kappa), gam = T(p.gamma);
-        const T omf = T(p.omega_f), omg = T(p.omega_g);
-        const Moments<T> m = moments_of<T, DEV>(p, f);
-        const T rho = m.rho, ri = T(1) / rho;
-        const T ux = m.jx * ri, uy = m.jy * ri, uz = m.jz * ri;
-        const T phi_c = st.phi, gx = st.gx, gy = st.gy, gz = st.gz, lap = st.lap;
-
-        // Weighted moments of Lambda = omega * lambda*:
-        //   S0 = sum w L, S1 = sum w L c, S2 = sum w L (c c - I/3)  (f part)
-        //   T0, T1, T2 likewise for the g part.
-        T s0 = 0, s1x = 0, s1y = 0, s1z = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
-        T t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
-#pragma unroll
-        for (int i = 0; i < NV; i++) {
-            const T wl = T(weight(i)) * omf * lf[i];
-            const T wg = T(weight(i)) * omg * lg[i];
-            s0 += wl; t0 += wg;
-            if (CX[i]) { s1x += CX[i] * wl; t1x += CX[i] * wg; }
-            if (CY[i]) { s1y += CY[i] * wl; t1y += CY[i] * wg; }
-            if (CZ[i]) { s1z += CZ[i] * wl; t1z += CZ[i] * wg; }
-            if (CX[i]) { sxx += wl; txx += wg; }
-            if (CY[i]) { syy += wl; tyy += wg; }
-            if (CZ[i]) { szz += wl; tzz += wg; }
-            if (CX[i] * CY[i]) { sxy += CX[i] * CY[i] * wl; txy += CX[i] * CY[i] * wg; }
-            if (CX[i] * CZ[i]) { sxz += CX[i] * CZ[i] * wl; txz += CX[i] * CZ[i] * wg; }
-            if (CY[i] * CZ[i]) { syz += CY[i] * CZ[i] * wl; tyz += CY[i] * CZ[i] * wg; }
-        }
-        const T third = T(1.0 / 3.0);
-        sxx -= third * s0; syy -= third * s0; szz -= third * s0;
-        txx -= third * t0; tyy -= third * t0; tzz -= third * t0;
-        const T trs = sxx + syy + szz, trt = txx + tyy + tzz;
-        // S2.u, T2.u, S2:uu, T2:uu, S2.grad, grad.S2.grad
-        const T s2ux = sxx * ux + sxy * uy + sxz * uz;
-        const T s2uy = sxy * ux + syy * uy + syz * uz;
-        const T s2uz = sxz * ux + syz * uy + szz * uz;
-        const T t2ux = txx * ux + txy * uy + txz * uz;
-        const T t2uy = txy * ux + tyy * uy + tyz * uz;
-        const T t2uz = txz * ux + tyz * uy + tzz * uz;
-        const T s2uu = s2ux * ux + s2uy * uy + s2uz * uz;
-        const T t2uu = t2ux * ux + t2uy * uy + t2uz * uz;
-        const T t1u = t1x * ux + t1y * uy + t1z * uz;
-        const T s2gx = sxx * gx + sxy * gy + sxz * gz;
-        const T s2gy = sxy * gx + syy * gy + syz * gz;
-        const T s2gz = sxz * gx + syz * gy + szz * gz;
-        const T gsg = s2gx * gx + s2gy * gy + s2gz * gz;
-        const T h = T(4.5);
-        const T pr = phi_c * ri;
-
-        // d/d rho and d/d j of sum Lambda_f f_eq + Lambda_g g_eq
-        const T arho = s0 - h * s2uu - T(3) * pr * t1u - T(9) * pr * t2uu;
-        const T ajx = T(3) * s1x + T(9) * s2ux + T(3) * pr * t1x + T(9) * pr * t2ux;
-        const T ajy = T(3) * s1y + T(9) * s2uy + T(3) * pr * t1y + T(9) * pr * t2uy;
-        const T ajz = T(3) * s1z + T(9) * s2uz + T(3) * pr * t1z + T(9) * pr * t2uz;
-        const T cf = T(1) - omf, cg = T(1) - omg;
-#pragma unroll
-        for (int i = 0; i < NV; i++) {
-            T v = cf * lf[i] + arho;
-            if (CX[i]) v += CX[i] * ajx;
-            if (CY[i]) v += CY[i] * ajy;
-            if (CZ[i]) v += CZ[i] * ajz;
-            ap[i * S + s] = v;
-            ap[(NV + i) * S + s] = cg * lg[i];
-        }
-        // stencil cotangents
-        const T phi2 = phi_c * phi_c;
-        const T a_dir = h * trs * (A * phi_c + T(3) * B * phi2 * phi_c - kap * lap) + t0
-                      + T(3) * t1u + h * (gam * (A + T(3) * B * phi2) - third) * trt + h * t2uu;
-        const T hk = h * kap;
-        sc[0 * S + s] = a_dir;
-        sc[1 * S + s] = hk * (T(2) * s2gx - trs * gx);
-        sc[2 * S + s] = hk * (T(2) * s2gy - trs * gy);
-        sc[3 * S + s] = hk * (T(2) * s2gz - trs * gz);
-        sc[4 * S + s] = -hk * (phi_c * trs + gam * trt);
-        // parameter cotangents (FP64 accumulation)
-        const double g2 = double(gx) * gx + double(gy) * gy + double(gz) * gz;
-        const double dtrs = double(trs), dtrt = double(trt), dph = double(phi_c);
-        dth[0] += 4.5 * (dtrs * 0.5 * dph * dph + p.gamma * dph * dtrt);
-        dth[1] += 4.5 * (dtrs * 0.75 * dph * dph * dph * dph + p.gamma * dph * dph * dph * dtrt);
-        dth[2] += 4.5 * (dtrs * (-dph * double(lap) - 0.5 * g2) + double(gsg)
-                         - p.gamma * double(lap) * dtrt);
-    }
-    block_partials<3>(dth, partials);
-}
-
-// lp(x) = a(x) - sum_a D_a b_a (x) + lap c (x): the transposed stencil
-// (D_a^T = -D_a, lap^T = lap on the periodic lattice).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj_stencil(KParams p, const T* __restrict__ sc,
-                                                        T* __restrict__ ap)
-{
-    const int s = blockIdx.x * kBlock + threadIdx.x;
-    if (s >= p.nsites) return;
-    const Geo q = geo_of(p, s);
-    const long long S = p.stride;
-    const int xp = site_of(p, q.xp, q.y, q.z), xm = site_of(p, q.xm, q.y, q.z);
-    const int yp = site_of(p, q.x, q.yp, q.z), ym = site_of(p, q.x, q.ym, q.z);
-    const int zp = site_of(p, q.x, q.y, q.zp), zm = site_of(p, q.x, q.y, q.zm);
-    const T* a = sc;
-    const T* bx = sc + S;
-    const T* by = sc + 2 * S;
-    const T* bz = sc + 3 * S;
-    const T* c = sc + 4 * S;
-    const T cc = c[s];
-    const T divb = T(0.5) * (bx[xp] - bx[xm]) + T(0.5) * (by[yp] - by[ym]) + T(0.5) * (bz[zp] - bz[zm]);
-    const T lapc = (c[xp] + c[xm] - T(2) * cc) + (c[yp] + c[ym] - T(2) * cc) + (c[zp] + c[zm] - T(2) * cc);
-    ap[2 * NV * S + s] = a[s] - divb + lapc;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj_phi0(KParams p, const T* __restrict__ adj,
-                                                     double* __restrict__ out)
-{
-    const int s = blockIdx.x * kBlock + threadIdx.x;
-    if (s >= p.nsites) return;
-    out[s] = double(adj[NV * p.stride + s]) + double(adj[2 * NV * p.stride + s]);
 }
 
 int grid_for(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
@@ -576,42 +304,85 @@ int reduction_grid(const KParams& p)
     return g < kMaxPartialBlocks ? g : kMaxPartialBlocks;
 }
 
-template <typename T>
-T* fpart(void* state) { return static_cast<T*>(state); }
-template <typename T>
-T* gpart(void* state, const KParams& p) { return static_cast<T*>(state) + NV * p.stride; }
-template <typename T>
-const T* fpart(const void* state) { return static_cast<const T*>(state); }
-template <typename T>
-const T* gpart(const void* state, const KParams& p) { return static_cast<const T*>(state) + NV * p.stride; }
+// Instantiation dispatch: FP64 mode <double, false, false>, FP32 mode <float, true, true>.
+#define LB_DISPATCH(fp32, CALL64, CALL32) \
+    do {                                  \
+        if (fp32) {                       \
+            using T = float;              \
+            constexpr bool DEV = true;    \
+            constexpr bool REF = true;    \
+            CALL32;                       \
+        } else {                          \
+            using T = double;             \
+            constexpr bool DEV = false;   \
+            constexpr bool REF = false;   \
+            CALL64;                       \
+        }                                 \
+    } while (0)
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Launchers.
+TileCfg tile_config(const KParams& p, int segment_x)
+{
+    TileCfg tc;
+    tc.nty = (p.ny + TY - 1) / TY;
+    tc.ntz = (p.nz + TZ - 1) / TZ;
+    tc.ntiles = tc.nty * tc.ntz;
+    int sx = segment_x;
+    if (sx <= 0) {
+        // aim for ~2048 workgroups (8 per CU) with segments of at least 8 planes
+        const long long want = (long long)p.nx * tc.ntiles / 2048;
+        sx = int(want < 8 ? 8 : want);
+    }
+    if (sx > p.nx) sx = p.nx;
+    tc.sx = sx;
+    tc.nseg = (p.nx + sx - 1) / sx;
+    return tc;
+}
 
 hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* phi0, hipStream_t s)
 {
-    if (fp32)
-        k_init<float, true><<<grid_for(p), kBlock, 0, s>>>(p, fpart<float>(state), gpart<float>(state, p), phi0);
-    else
-        k_init<double, false><<<grid_for(p), kBlock, 0, s>>>(p, fpart<double>(state), gpart<double>(state, p), phi0);
+#define CALL                                                                                   \
+    {                                                                                          \
+        Lvl<T> l = level<T>(state, p, REF);                                                    \
+        k_init<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, l.F, l.G, l.phic, phi0);        \
+    }
+    LB_DISPATCH(fp32, CALL, CALL);
+#undef CALL
     return hipGetLastError();
 }
 
-hipError_t launch_step(const KParams& p, bool fp32, const void* src, void* dst, void* phi, hipStream_t s)
+hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
+                       const void* src, void* dst, double* phi_work, hipStream_t s)
 {
-    if (fp32) {
-        k_phi<float><<<grid_for(p), kBlock, 0, s>>>(p, gpart<float>(src, p), static_cast<float*>(phi));
-        k_step<float, true><<<grid_for(p), kBlock, 0, s>>>(p, fpart<float>(src), gpart<float>(src, p),
-                                                           static_cast<const float*>(phi),
-                                                           fpart<float>(dst), gpart<float>(dst, p));
-    } else {
-        k_phi<double><<<grid_for(p), kBlock, 0, s>>>(p, gpart<double>(src, p), static_cast<double*>(phi));
-        k_step<double, false><<<grid_for(p), kBlock, 0, s>>>(p, fpart<double>(src), gpart<double>(src, p),
-                                                             static_cast<const double*>(phi),
-                                                             fpart<double>(dst), gpart<double>(dst, p));
+#define CALL                                                                                    \
+    {                                                                                           \
+        Lvl<T> a = level<T>(const_cast<void*>(src), p, REF);                                    \
+        Lvl<T> d = level<T>(dst, p, REF);                                                       \
+        if (variant == 0) {                                                                     \
+            k_step_fused<T, DEV, REF><<<tc.ntiles * tc.nseg, kBlock, 0, s>>>(                   \
+                p, tc, a.F, a.G, a.phic, d.F, d.G, d.phic);                                     \
+        } else {                                                                                \
+            double* phin = REF ? d.phic : phi_work;                                             \
+            k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);                 \
+            k_step_2s<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phin,    \
+                                                                  d.F, d.G);                    \
+        }                                                                                       \
     }
+    LB_DISPATCH(fp32, CALL, CALL);
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_phi(const KParams& p, bool fp32, const void* state, double* phi, hipStream_t s)
+{
+#define CALL                                                                              \
+    {                                                                                     \
+        Lvl<T> a = level<T>(const_cast<void*>(state), p, REF);                            \
+        k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phi);                \
+    }
+    LB_DISPATCH(fp32, CALL, CALL);
+#undef CALL
     return hipGetLastError();
 }
 
@@ -620,10 +391,14 @@ hipError_t launch_moments(const KParams& p, bool fp32, const void* state, double
 {
     const int nb = reduction_grid(p);
     *nblocks_out = nb;
-    if (fp32)
-        k_moments<float, true><<<nb, kBlock, 0, s>>>(p, fpart<float>(state), gpart<float>(state, p), rho, u, phi, partials);
-    else
-        k_moments<double, false><<<nb, kBlock, 0, s>>>(p, fpart<double>(state), gpart<double>(state, p), rho, u, phi, partials);
+#define CALL                                                                                  \
+    {                                                                                         \
+        Lvl<T> a = level<T>(const_cast<void*>(state), p, REF);                                \
+        k_moments<T, DEV, REF><<<nb, kBlock, 0, s>>>(p, a.F, a.G, a.phic, rho, u, phi,       \
+                                                     partials);                               \
+    }
+    LB_DISPATCH(fp32, CALL, CALL);
+#undef CALL
     return hipGetLastError();
 }
 
@@ -634,68 +409,29 @@ hipError_t launch_sums_final(const double* partials, int nblocks, int ncomp, dou
     return hipGetLastError();
 }
 
-hipError_t launch_export(const KParams& p, bool fp32, const void* state, double* f, double* g, hipStream_t s)
-{
-    if (fp32)
-        k_export<float, true><<<grid_for(p), kBlock, 0, s>>>(p, fpart<float>(state), gpart<float>(state, p), f, g);
-    else
-        k_export<double, false><<<grid_for(p), kBlock, 0, s>>>(p, fpart<double>(state), gpart<double>(state, p), f, g);
-    return hipGetLastError();
-}
-
-hipError_t launch_import(const KParams& p, bool fp32, void* state, const double* f, const double* g,
+hipError_t launch_export(const KParams& p, bool fp32, const void* state, double* f, double* g,
                          hipStream_t s)
 {
-    if (fp32)
-        k_import<float, true><<<grid_for(p), kBlock, 0, s>>>(p, fpart<float>(state), gpart<float>(state, p), f, g);
-    else
-        k_import<double, false><<<grid_for(p), kBlock, 0, s>>>(p, fpart<double>(state), gpart<double>(state, p), f, g);
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, const double* dphi, hipStream_t s)
-{
-    if (fp32)
-        k_adj_seed<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<float*>(adj), dphi);
-    else
-        k_adj_seed<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<double*>(adj), dphi);
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state, void* phi,
-                           const void* adj_next, void* adj_prev, void* adj_scratch,
-                           double* partials, int* nblocks_out, hipStream_t s)
-{
-    const int nb = reduction_grid(p);
-    *nblocks_out = nb;
-    if (fp32) {
-        k_phi<float><<<grid_for(p), kBlock, 0, s>>>(p, gpart<float>(state, p), static_cast<float*>(phi));
-        k_adj_local<float, true><<<nb, kBlock, 0, s>>>(p, fpart<float>(state), gpart<float>(state, p),
-                                                       static_cast<const float*>(phi),
-                                                       static_cast<const float*>(adj_next),
-                                                       static_cast<float*>(adj_prev),
-                                                       static_cast<float*>(adj_scratch), partials);
-        k_adj_stencil<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const float*>(adj_scratch),
-                                                            static_cast<float*>(adj_prev));
-    } else {
-        k_phi<double><<<grid_for(p), kBlock, 0, s>>>(p, gpart<double>(state, p), static_cast<double*>(phi));
-        k_adj_local<double, false><<<nb, kBlock, 0, s>>>(p, fpart<double>(state), gpart<double>(state, p),
-                                                         static_cast<const double*>(phi),
-                                                         static_cast<const double*>(adj_next),
-                                                         static_cast<double*>(adj_prev),
-                                                         static_cast<double*>(adj_scratch), partials);
-        k_adj_stencil<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const double*>(adj_scratch),
-                                                             static_cast<double*>(adj_prev));
+#define CALL                                                                                  \
+    {                                                                                         \
+        Lvl<T> a = level<T>(const_cast<void*>(state), p, REF);                                \
+        k_export<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, f, g);      \
     }
+    LB_DISPATCH(fp32, CALL, CALL);
+#undef CALL
     return hipGetLastError();
 }
 
-hipError_t launch_adj_phi0(const KParams& p, bool fp32, const void* adj, double* dphi0, hipStream_t s)
+hipError_t launch_import(const KParams& p, bool fp32, void* state, const double* f,
+                         const double* g, hipStream_t s)
 {
-    if (fp32)
-        k_adj_phi0<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const float*>(adj), dphi0);
-    else
-        k_adj_phi0<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const double*>(adj), dphi0);
+#define CALL                                                                                  \
+    {                                                                                         \
+        Lvl<T> a = level<T>(state, p, REF);                                                   \
+        k_import<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, f, g);      \
+    }
+    LB_DISPATCH(fp32, CALL, CALL);
+#undef CALL
     return hipGetLastError();
 }
 

@@ -33,18 +33,21 @@ class LB:
     shape: (nx, ny, nz) periodic extents.  Model parameters as in lb.h.
     precision: "fp64" or "fp32_dev" (FP32 deviation storage).
     adjoint: also allocate the reverse-mode buffers.
+    kernel: "fused" (one pass per step) or "two_pass" (phi pass + collision pass).
+    segment_x: x planes per workgroup of the fused kernel (0 = automatic).
     """
 
     def __init__(self, shape, *, A=-0.00625, B=0.00625, kappa=0.004, gamma=0.5, tau_f=1.0,
                  tau_g=1.0, rho0=1.0, precision="fp64", adjoint=False, device=None,
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, kernel="fused", segment_x=0):
         L = _abi.lib()
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
         self.nsites = nx * ny * nz
         self.precision = _precision_code(precision)
         self.params = _abi.LbParams(nx, ny, nz, float(A), float(B), float(kappa), float(gamma),
-                                    float(tau_f), float(tau_g), float(rho0), self.precision)
+                                    float(tau_f), float(tau_g), float(rho0), self.precision,
+                                    {"fused": 0, "two_pass": 1}[kernel], int(segment_x))
         self.sizes = _abi.LbSizes()
         check(L.lb_query_sizes(ctypes.byref(self.params), ctypes.byref(self.sizes)),
               "lb_query_sizes")

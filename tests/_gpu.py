@@ -24,14 +24,25 @@ def oracle_params(shape, **kw):
     return oracle.Params(*shape, **params(shape, **kw))
 
 
-def rel_err(a, ref) -> float:
-    """max |a - ref| / max |ref| (field scale; phi and u cross zero)."""
+def rel_err(a, ref, floor: float = 0.0) -> float:
+    """max |a - ref| / max(max |ref|, floor): per-site error over the field's
+    scale (phi and u cross zero, so a pointwise relative error is undefined)."""
     a = np.asarray(a, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
-    scale = np.abs(ref).max()
+    scale = max(float(np.abs(ref).max()), floor)
     if scale == 0.0:
         return float(np.abs(a).max())
     return float(np.abs(a - ref).max() / scale)
+
+
+# The velocity is a difference of O(rho) populations (j = sum_i f_i c_i), so
+# its rounding error is O(eps) in lattice units whatever |u| is; its scale is
+# therefore at least the lattice speed 1.
+FLOORS = {"f": 0.0, "g": 0.0, "rho": 0.0, "u": 1.0, "phi": 0.0}
+
+
+def field_errors(got, ref, names=("f", "g", "rho", "u", "phi")):
+    return {n: rel_err(a, b, FLOORS[n]) for n, a, b in zip(names, got, ref)}
 
 
 def gpu_state(lb):

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(abi):
 
 def _params(abi, **kw):
     base = dict(nx=8, ny=8, nz=8, A=-0.00625, B=0.00625, kappa=0.004, gamma=0.5, tau_f=1.0,
-                tau_g=1.0, rho0=1.0, precision=abi.LB_FP64)
+                tau_g=1.0, rho0=1.0, precision=abi.LB_FP64, kernel=0, segment_x=0)
     base.update(kw)
     return abi.LbParams(**base)
 
@@ -56,7 +56,10 @@ def test_query_sizes(abi):
     assert s.elem_bytes == 8 and s.stride_elems >= 4096 and s.stride_elems % 256 == 0
     assert s.state_bytes == 2 * 19 * s.stride_elems * 8
     st, s32 = _query(abi, nx=16, ny=16, nz=16, precision=abi.LB_FP32_DEV)
-    assert st == abi.LB_OK and s32.elem_bytes == 4 and s32.state_bytes * 2 == s.state_bytes
+    assert st == abi.LB_OK and s32.elem_bytes == 4
+    # FP32: f and g in FP32 plus the FP64 reference order parameter
+    assert s32.state_bytes == 2 * 19 * s32.stride_elems * 4 + s32.stride_elems * 8
+    assert s32.phi_bytes == s32.stride_elems * 8
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -64,7 +67,7 @@ def test_query_sizes(abi):
     (dict(nx=2048, ny=2048, nz=1024), "LB_ESHAPE"),
     (dict(tau_f=0.5), "LB_EINVAL"), (dict(tau_g=0.2), "LB_EINVAL"),
     (dict(tau_f=float("nan")), "LB_EINVAL"), (dict(rho0=0.0), "LB_EINVAL"),
-    (dict(precision=7), "LB_EINVAL"),
+    (dict(precision=7), "LB_EINVAL"), (dict(kernel=2), "LB_EINVAL"),
 ])
 def test_bad_parameters_rejected(abi, kw, code):
     st, _ = _query(abi, **kw)
