@@ -193,6 +193,14 @@ lb_status lb_adjoint_step(lb_ctx *ctx, const void *state_t_dev, double *dtheta3_
  * current lambda_0. */
 lb_status lb_adjoint_phi0(lb_ctx *ctx, double *dphi0_dev);
 
+/* ---- measurement ------------------------------------------------------ */
+
+/* Streaming copy of `bytes` (a multiple of 16) from src_dev to dst_dev on
+ * hip_stream: the practical HBM ceiling the step is measured against (the
+ * STREAM calibration of the paper's roofline analysis, Sec. 4).  Buffers must
+ * be 256-byte aligned and must not overlap. */
+lb_status lb_copy_probe(const void *src_dev, void *dst_dev, size_t bytes, void *hip_stream);
+
 /* Text for a status code, and the thread-local detail of the last failure. */
 const char *lb_status_string(lb_status s);
 const char *lb_last_error(void);

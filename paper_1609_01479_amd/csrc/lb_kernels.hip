@@ -14,6 +14,8 @@
 //
 // k_phi + k_step_2s are the two-pass variant (phi kernel, then the fused
 // stencil/collision/propagation kernel), kept for comparison.
+#include <type_traits>
+
 #include "lb_device.h"
 
 namespace lbk {
@@ -102,10 +104,25 @@ __global__ __launch_bounds__(kBlock) void k_step_2s(KParams p, const T* __restri
     }
 }
 
+// Wrap a coordinate v in [-2n, 3n) onto [0, n).
+__device__ __forceinline__ int wrapg(int v, int n)
+{
+    if (v < 0) return v + n < 0 ? v + 2 * n : v + n;
+    if (v >= n) return v - n >= n ? v - 2 * n : v - n;
+    return v;
+}
+
 // Single-pass step (see the file comment).  Block -> (segment, tile) with
 // an XCD-aware order: consecutive workgroup ids go round-robin over the 8
 // XCDs, so ids are remapped to give each XCD a contiguous run of tiles,
 // y-adjacent tiles first, whose halo rows then meet in the same L2.
+//
+// FP32 mode additionally stages the reference field phi_c of the source
+// level in LDS, one plane per iteration with a 2-site (y, z) halo (the halo
+// ring's own pulls reach 2 sites out), in a 6-slot ring: plane x+3 is
+// prefetched while planes x-1..x+2 are in use.  Each pulled population then
+// costs one FP32 global load; its reference term r_i phi_c(x - c_i) comes
+// from LDS.
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_step_fused(KParams p, TileCfg tc,
                                                        const T* __restrict__ sF,
@@ -114,7 +131,12 @@ __global__ __launch_bounds__(kBlock) void k_step_fused(KParams p, TileCfg tc,
                                                        T* __restrict__ dF, T* __restrict__ dG,
                                                        double* __restrict__ dphic)
 {
+    constexpr int PCS = REF ? 6 : 1, PCY = REF ? TY + 4 : 1, PCZ = REF ? TZ + 4 : 1;
     __shared__ double ph[4][TY + 2][TZ + 2];
+    __shared__ double pc[PCS][PCY][PCZ];
+    // value kept per direction between the phi pull and the collision:
+    // the stored FP32 deviation (FP32 mode) or the FP64 population
+    using K = typename std::conditional<REF, T, double>::type;
 
     int b = blockIdx.x;
     const int nb = gridDim.x;
@@ -137,31 +159,69 @@ __global__ __launch_bounds__(kBlock) void k_step_fused(KParams p, TileCfg tc,
     else if (r < 2 * tza) { rly = tya + 1; rlz = r - tza + 1; }
     else if (r < 2 * tza + tya) { rly = r - 2 * tza + 1; rlz = 0; }
     else { rly = r - 2 * tza - tya + 1; rlz = tza + 1; }
-    int ry = y0 + rly - 1, rz = z0 + rlz - 1;
-    ry = ry < 0 ? ry + p.ny : (ry >= p.ny ? ry - p.ny : ry);
-    rz = rz < 0 ? rz + p.nz : (rz >= p.nz ? rz - p.nz : rz);
+    const int ry = wrapg(y0 + rly - 1, p.ny), rz = wrapg(z0 + rlz - 1, p.nz);
 
-    double dcur[NV], dnext[NV];
-    // warm-up: phi at planes x0-1 (slot 0) and x0 (slot 1); keep g of plane x0
-    const int xb = x0 == 0 ? p.nx - 1 : x0 - 1;
-    if (active) ph[0][ly + 1][lz + 1] = pull_g<T, REF>(p, geo_xyz(p, xb, y, z), sG, sphic, dcur);
-    if (ring) ph[0][rly][rlz] = phi_at<T, REF>(p, geo_xyz(p, xb, ry, rz), sG, sphic);
-    if (active) ph[1][ly + 1][lz + 1] = pull_g<T, REF>(p, geo_xyz(p, x0, y, z), sG, sphic, dcur);
-    if (ring) ph[1][rly][rlz] = phi_at<T, REF>(p, geo_xyz(p, x0, ry, rz), sG, sphic);
+    // plane indices run from x0-2 to x1+2: wrap them with a full modulo (nx may be 1)
+    auto xw = [&](int X) { return ((X % p.nx) + p.nx) % p.nx; };
+    // phi_c plane X (logical index X - x0 + 2) into its LDS slot; cell
+    // (cy, cz) holds site (y0 + cy - 2, z0 + cz - 2)
+    auto load_pc = [&](int X) {
+        if (REF) {
+            const int slot = (X - x0 + 2) % PCS;
+            const int W = tza + 4, n = W * (tya + 4);
+            const int xx = xw(X);
+            for (int t = threadIdx.x; t < n; t += kBlock) {
+                const int cy = t / W, cz = t - cy * W;
+                pc[slot % PCS][REF ? cy : 0][REF ? cz : 0] =
+                    sphic[site_of(p, xx, wrapg(y0 + cy - 2, p.ny), wrapg(z0 + cz - 2, p.nz))];
+            }
+        }
+    };
+    // g_i at a site of plane X as FP64, from the kept value kv of direction i;
+    // (cy, cz) is the site's phi_c cell
+    auto gval = [&](int X, int i, int cy, int cz, K kv) -> double {
+        if (REF) {
+            const int slot = (X - CX[i] - x0 + 2) % PCS;
+            return __builtin_fma(rweight(i), pc[slot % PCS][REF ? cy - CY[i] : 0][REF ? cz - CZ[i] : 0],
+                                 double(kv));
+        }
+        return double(kv);
+    };
+    // pull of plane X at (yy, zz): kept values into kv[] (if non-null), returns phi
+    auto pull_phi = [&](int X, int yy, int zz, int cy, int cz, K* kv) -> double {
+        const Geo q = geo_xyz(p, xw(X), yy, zz);
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            const K v = K(sG[i * p.stride + pull_site(p, q, i)]);
+            if (kv) kv[i] = v;
+            acc += gval(X, i, cy, cz, v);
+        }
+        return acc;
+    };
+
+    K kcur[NV], knext[NV];
+    // warm-up: phi_c planes x0-2 .. x0+2, then phi at planes x0-1 (slot 0)
+    // and x0 (slot 1), keeping plane x0's populations
+    for (int X = x0 - 2; X <= x0 + 2; X++) load_pc(X);
+    if (REF) __syncthreads();
+    if (active) ph[0][ly + 1][lz + 1] = pull_phi(x0 - 1, y, z, ly + 2, lz + 2, nullptr);
+    if (ring) ph[0][rly][rlz] = pull_phi(x0 - 1, ry, rz, rly + 1, rlz + 1, nullptr);
+    if (active) ph[1][ly + 1][lz + 1] = pull_phi(x0, y, z, ly + 2, lz + 2, kcur);
+    if (ring) ph[1][rly][rlz] = pull_phi(x0, ry, rz, rly + 1, rlz + 1, nullptr);
 
     for (int x = x0; x < x1; x++) {
-        const int k = x - x0 + 2;  // slot counter of plane x+1
+        const int k = x - x0 + 2;  // phi slot counter of plane x+1
         const int sn = k & 3, sc = (k - 1) & 3, sp = (k - 2) & 3;
-        const int xn = x == p.nx - 1 ? 0 : x + 1;
+        load_pc(x + 3);
         T f[NV];
-        Geo qc;
         if (active) {
-            qc = geo_xyz(p, x, y, z);
+            const Geo qc = geo_xyz(p, x, y, z);
 #pragma unroll
             for (int i = 0; i < NV; i++) f[i] = sF[i * p.stride + pull_site(p, qc, i)];
-            ph[sn][ly + 1][lz + 1] = pull_g<T, REF>(p, geo_xyz(p, xn, y, z), sG, sphic, dnext);
+            ph[sn][ly + 1][lz + 1] = pull_phi(x + 1, y, z, ly + 2, lz + 2, knext);
         }
-        if (ring) ph[sn][rly][rlz] = phi_at<T, REF>(p, geo_xyz(p, xn, ry, rz), sG, sphic);
+        if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, ry, rz, rly + 1, rlz + 1, nullptr);
         __syncthreads();
         if (active) {
             const double c = ph[sc][ly + 1][lz + 1];
@@ -169,7 +229,11 @@ __global__ __launch_bounds__(kBlock) void k_step_fused(KParams p, TileCfg tc,
                                        ph[sc][ly + 2][lz + 1], ph[sc][ly][lz + 1],
                                        ph[sc][ly + 1][lz + 2], ph[sc][ly + 1][lz]);
             T g[NV];
-            g_local<T, REF>(dcur, c, g);
+#pragma unroll
+            for (int i = 0; i < NV; i++) {
+                const double d = gval(x, i, ly + 2, lz + 2, kcur[i]);
+                g[i] = REF ? T(d - rweight(i) * c) : T(d);
+            }
             collide<T, DEV, REF>(p, f, g, st);
             const int s = site_of(p, x, y, z);
 #pragma unroll
@@ -179,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_step_fused(KParams p, TileCfg tc,
             }
             if (REF) dphic[s] = c;
 #pragma unroll
-            for (int i = 0; i < NV; i++) dcur[i] = dnext[i];
+            for (int i = 0; i < NV; i++) kcur[i] = knext[i];
         }
     }
 }

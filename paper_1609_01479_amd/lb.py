@@ -188,3 +188,30 @@ class LB:
 
 def to_numpy(t: torch.Tensor) -> np.ndarray:
     return t.detach().cpu().numpy()
+
+
+def copy_probe_gbps(nbytes: int, reps: int = 20, device="cuda:0") -> float:
+    """Bandwidth (read + write bytes / time) of the library's streaming copy
+    kernel over `nbytes` -- the practical HBM ceiling."""
+    dev = torch.device(device)
+    nbytes = nbytes // 256 * 256
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream(dev)
+    L = _abi.lib()
+    call = lambda: check(L.lb_copy_probe(ctypes.c_void_p(a.data_ptr()),  # noqa: E731
+                                         ctypes.c_void_p(b.data_ptr()), ctypes.c_size_t(nbytes),
+                                         ctypes.c_void_p(stream.cuda_stream)), "lb_copy_probe")
+    for _ in range(3):
+        call()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        call()
+    e1.record(stream)
+    e1.synchronize()
+    if not torch.equal(a[:1024], b[:1024]):
+        raise RuntimeError("copy probe produced wrong data")
+    ms = e0.elapsed_time(e1) / reps
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9

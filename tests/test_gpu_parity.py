@@ -174,3 +174,23 @@ def test_kernel_variants_and_segments_agree(prec):
             assert np.array_equal(a, b), key
     errs = field_errors(out[("two_pass", 0)], ref)
     assert max(errs.values()) <= (1e-14 if prec == "fp64" else 1e-6), errs
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 2, 2), (1, 1, 300), (1, 7, 1), (2, 3, 1), (3, 5, 131)])
+def test_degenerate_lattices_fp32(shape):
+    """FP32 storage on extents 1 and 2 and a ragged tail: the single-pass
+    kernel's LDS reference planes wrap onto themselves; it must agree with the
+    two-pass variant (global reads) and follow the oracle to FP32 rounding."""
+    phi0 = lbinputs.spinodal_phi0(shape, seed=98, amp=0.5)
+    out = {}
+    for kernel in ("fused", "two_pass"):
+        lb = make_lb(shape, precision="fp32_dev", tau_f=0.9, tau_g=1.2, kernel=kernel)
+        lb.init_phi(phi0)
+        lb.step(12)
+        out[kernel] = gpu_state(lb)
+    errs = field_errors(out["fused"], out["two_pass"])
+    assert max(errs.values()) <= 1e-6, errs
+    p = oracle_params(shape, tau_f=0.9, tau_g=1.2)
+    ref = oracle_state(p, *oracle.run(p, *oracle.init(p, phi0), 12))
+    errs = field_errors(out["fused"], ref)
+    assert errs["phi"] <= 1e-6 and errs["rho"] <= 1e-6 and errs["u"] <= 1e-7, errs

@@ -440,3 +440,29 @@ def test_reverse_mode_matches_central_differences():
         lm = loss(phi0, **{name: val - hh})
         fd = (lp - lm) / (2 * hh)
         assert abs(fd - gv) < 1e-6 * abs(fd), (name, fd, gv)
+
+
+def test_one_step_depends_on_radius_two():
+    """One step at x depends only on the state within L-inf distance 2 of x:
+    stepping a small periodic window cut around x reproduces the full-lattice
+    step at x bit for bit (the full-size GPU parity tests rely on this)."""
+    shape = (9, 10, 11)
+    p = _params(shape, tau_f=0.8, tau_g=1.3)
+    f, g = _perturbed_state(p, 31)
+    g = g + 0.05 * lbinputs.random_field(g.shape, 32)
+    fn, gn = oracle.step(p, f, g)
+    for r in (2, 3):
+        w = 2 * r + 1
+        pw = _params((w, w, w), tau_f=0.8, tau_g=1.3)
+        for site in [(0, 0, 0), (8, 9, 10), (4, 5, 6), (1, 9, 0)]:
+            idx = [np.arange(c - r, c + r + 1) % n for c, n in zip(site, shape)]
+            cut = lambda a: a[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]]  # noqa: E731
+            fo, go = oracle.step(pw, cut(f), cut(g))
+            assert np.array_equal(fo[:, r, r, r], fn[(slice(None),) + site])
+            assert np.array_equal(go[:, r, r, r], gn[(slice(None),) + site])
+    # radius 1 is not enough (the stencil of the pulled neighbours reaches 2)
+    pw = _params((3, 3, 3), tau_f=0.8, tau_g=1.3)
+    idx = [np.arange(c - 1, c + 2) % n for c, n in zip((4, 5, 6), shape)]
+    fo, _ = oracle.step(pw, f[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]],
+                        g[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]])
+    assert not np.array_equal(fo[:, 1, 1, 1], fn[:, 4, 5, 6])
