@@ -147,6 +147,13 @@ lb_status lb_init_phi(lb_ctx *ctx, const double *phi0_dev);
 /* Advance nsteps >= 0 timesteps (asynchronous). */
 lb_status lb_step(lb_ctx *ctx, int32_t nsteps);
 
+/* One timestep from the caller's time level src_dev to dst_dev (both
+ * state_bytes, as written by lb_get_state or a previous lb_step_from),
+ * without touching the context's current level.  Used by the reverse mode to
+ * recompute the states of a checkpoint segment in place.  src_dev and dst_dev
+ * must differ. */
+lb_status lb_step_from(lb_ctx *ctx, const void *src_dev, void *dst_dev);
+
 /* Moments of the current (post-propagation) state, as dense FP64 device
  * arrays: rho_dev (N), u_dev (3N: x, y, z planes), phi_dev (N).  Any pointer
  * may be NULL to skip that output. */

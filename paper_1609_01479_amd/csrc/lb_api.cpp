@@ -196,6 +196,17 @@ lb_status lb_step(lb_ctx* ctx, int32_t nsteps)
     return LB_OK;
 }
 
+lb_status lb_step_from(lb_ctx* ctx, const void* src_dev, void* dst_dev)
+{
+    if (!ctx || !src_dev || !dst_dev) return fail(LB_EINVAL, "ctx, src_dev and dst_dev are required");
+    if (src_dev == dst_dev) return fail(LB_EINVAL, "src_dev and dst_dev must differ");
+    if (!aligned(src_dev) || !aligned(dst_dev))
+        return fail(LB_EALIGN, "src_dev and dst_dev must be 256-byte aligned");
+    hipError_t e = lbk::launch_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel, src_dev, dst_dev,
+                                    static_cast<double*>(ctx->b.phi), ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_step_from");
+}
+
 lb_status lb_moments(lb_ctx* ctx, double* rho_dev, double* u_dev, double* phi_dev)
 {
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");

@@ -2,7 +2,7 @@
 //
 // The step of the paper's Ludwig timestep (Sec. 2.1.1) -- order-parameter
 // gradients, chemical stress, collision, propagation -- runs as ONE kernel,
-// k_step_fused: each workgroup owns a (y, z) tile of 4 x 64 sites and marches
+// k_step_fused_f32 / _f64: each workgroup owns a (y, z) tile of sites and marches
 // along x over a segment of planes.  For plane x it needs phi at planes
 // x-1, x, x+1 (7-point stencil); phi(x+1) is formed from the pulled g of
 // plane x+1, which the same threads keep in registers for plane x+1's own
@@ -24,8 +24,36 @@ using namespace dev;
 
 namespace {
 
-constexpr int TZ = 64;  // tile extent along z (contiguous): one wavefront row
+// Tuning knobs of the single-pass kernel (compile-time; defaults are the
+// measured best on MI355X).
+#ifndef LB_TZ
+#define LB_TZ 64  // tile extent along z (contiguous)
+#endif
+#ifndef LB_RING_SPREAD
+#define LB_RING_SPREAD 0  // 1: spread halo-ring sites evenly over the waves
+#endif
+#ifndef LB_PREFETCH_F
+#define LB_PREFETCH_F 0  // 1: load plane x+1's f while plane x is stored
+#endif
+#ifndef LB_NT_STORE
+#define LB_NT_STORE 0  // 1: nontemporal stores of the new time level
+#endif
+#ifndef LB_WPE32
+#define LB_WPE32 0  // >0: waves-per-EU hint for the FP32 instantiation
+#endif
+#ifndef LB_WPE64
+#define LB_WPE64 0  // >0: waves-per-EU hint for the FP64 instantiation
+#endif
+
+constexpr int TZ = LB_TZ;
 constexpr int TY = kBlock / TZ;
+
+template <typename T>
+__device__ __forceinline__ void store_out(T* ptr, T v)
+{
+    if (LB_NT_STORE) __builtin_nontemporal_store(v, ptr);
+    else *ptr = v;
+}
 
 template <typename T>
 struct Lvl {
@@ -124,12 +152,12 @@ __device__ __forceinline__ int wrapg(int v, int n)
 // costs one FP32 global load; its reference term r_i phi_c(x - c_i) comes
 // from LDS.
 template <typename T, bool DEV, bool REF>
-__global__ __launch_bounds__(kBlock) void k_step_fused(KParams p, TileCfg tc,
-                                                       const T* __restrict__ sF,
-                                                       const T* __restrict__ sG,
-                                                       const double* __restrict__ sphic,
-                                                       T* __restrict__ dF, T* __restrict__ dG,
-                                                       double* __restrict__ dphic)
+__device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg& tc,
+                                                const T* __restrict__ sF,
+                                                const T* __restrict__ sG,
+                                                const double* __restrict__ sphic,
+                                                T* __restrict__ dF, T* __restrict__ dG,
+                                                double* __restrict__ dphic)
 {
     constexpr int PCS = REF ? 6 : 1, PCY = REF ? TY + 4 : 1, PCZ = REF ? TZ + 4 : 1;
     __shared__ double ph[4][TY + 2][TZ + 2];
@@ -151,7 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_step_fused(KParams p, TileCfg tc,
     const int y = y0 + ly, z = z0 + lz;
 
     // halo ring: rows y0-1 and y0+tya, then columns z0-1 and z0+tza
-    const int r = threadIdx.x;
+    const int r = LB_RING_SPREAD ? (threadIdx.x & 63) * (kBlock / 64) + (threadIdx.x >> 6)
+                                 : int(threadIdx.x);
     const int nring = 2 * tza + 2 * tya;
     const bool ring = r < nring;
     int rly, rlz;
@@ -210,15 +239,20 @@ __global__ __launch_bounds__(kBlock) void k_step_fused(KParams p, TileCfg tc,
     if (active) ph[1][ly + 1][lz + 1] = pull_phi(x0, y, z, ly + 2, lz + 2, kcur);
     if (ring) ph[1][rly][rlz] = pull_phi(x0, ry, rz, rly + 1, rlz + 1, nullptr);
 
+    T f[NV];
+    auto load_f = [&](int X) {
+        const Geo qc = geo_xyz(p, X, y, z);
+#pragma unroll
+        for (int i = 0; i < NV; i++) f[i] = sF[i * p.stride + pull_site(p, qc, i)];
+    };
+    if (LB_PREFETCH_F && active) load_f(x0);
+
     for (int x = x0; x < x1; x++) {
         const int k = x - x0 + 2;  // phi slot counter of plane x+1
         const int sn = k & 3, sc = (k - 1) & 3, sp = (k - 2) & 3;
         load_pc(x + 3);
-        T f[NV];
         if (active) {
-            const Geo qc = geo_xyz(p, x, y, z);
-#pragma unroll
-            for (int i = 0; i < NV; i++) f[i] = sF[i * p.stride + pull_site(p, qc, i)];
+            if (!LB_PREFETCH_F) load_f(x);
             ph[sn][ly + 1][lz + 1] = pull_phi(x + 1, y, z, ly + 2, lz + 2, knext);
         }
         if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, ry, rz, rly + 1, rlz + 1, nullptr);
@@ -238,15 +272,54 @@ __global__ __launch_bounds__(kBlock) void k_step_fused(KParams p, TileCfg tc,
             const int s = site_of(p, x, y, z);
 #pragma unroll
             for (int i = 0; i < NV; i++) {
-                dF[i * p.stride + s] = f[i];
-                dG[i * p.stride + s] = g[i];
+                store_out(dF + i * p.stride + s, f[i]);
+                store_out(dG + i * p.stride + s, g[i]);
             }
-            if (REF) dphic[s] = c;
+            if (REF) store_out(dphic + s, c);
 #pragma unroll
             for (int i = 0; i < NV; i++) kcur[i] = knext[i];
+            if (LB_PREFETCH_F && x + 1 < x1) load_f(x + 1);
         }
     }
 }
+
+#if LB_WPE32 > 0
+#define LB_ATTR32 __attribute__((amdgpu_waves_per_eu(LB_WPE32)))
+#else
+#define LB_ATTR32
+#endif
+#if LB_WPE64 > 0
+#define LB_ATTR64 __attribute__((amdgpu_waves_per_eu(LB_WPE64)))
+#else
+#define LB_ATTR64
+#endif
+
+__global__ __launch_bounds__(kBlock) LB_ATTR32 void k_step_fused_f32(
+    KParams p, TileCfg tc, const float* __restrict__ sF, const float* __restrict__ sG,
+    const double* __restrict__ sphic, float* __restrict__ dF, float* __restrict__ dG,
+    double* __restrict__ dphic)
+{
+    step_fused_body<float, true, true>(p, tc, sF, sG, sphic, dF, dG, dphic);
+}
+
+__global__ __launch_bounds__(kBlock) LB_ATTR64 void k_step_fused_f64(
+    KParams p, TileCfg tc, const double* __restrict__ sF, const double* __restrict__ sG,
+    const double* __restrict__ sphic, double* __restrict__ dF, double* __restrict__ dG,
+    double* __restrict__ dphic)
+{
+    step_fused_body<double, false, false>(p, tc, sF, sG, sphic, dF, dG, dphic);
+}
+
+template <typename T>
+struct Fused;
+template <>
+struct Fused<float> {
+    static constexpr auto kernel = k_step_fused_f32;
+};
+template <>
+struct Fused<double> {
+    static constexpr auto kernel = k_step_fused_f64;
+};
 
 // Dense FP64 moments of the post-propagation state and block partials of
 // [rho, phi, jx, jy, jz] (grid-stride, FP64 accumulation).
@@ -424,7 +497,7 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
         Lvl<T> a = level<T>(const_cast<void*>(src), p, REF);                                    \
         Lvl<T> d = level<T>(dst, p, REF);                                                       \
         if (variant == 0) {                                                                     \
-            k_step_fused<T, DEV, REF><<<tc.ntiles * tc.nseg, kBlock, 0, s>>>(                   \
+            Fused<T>::kernel<<<tc.ntiles * tc.nseg, kBlock, 0, s>>>(                            \
                 p, tc, a.F, a.G, a.phic, d.F, d.G, d.phic);                                     \
         } else {                                                                                \
             double* phin = REF ? d.phic : phi_work;                                             \

@@ -120,6 +120,18 @@ class LB:
     def step(self, nsteps: int = 1) -> None:
         self._call("lb_step", ctypes.c_int32(int(nsteps)))
 
+    def new_state(self) -> torch.Tensor:
+        """An uninitialised device buffer of one time level (state_bytes)."""
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            return torch.empty(int(self.sizes.state_bytes), dtype=torch.uint8, device=self.device)
+
+    def step_from(self, src: torch.Tensor, dst: torch.Tensor) -> None:
+        """One step from the time level in `src` into `dst` (caller buffers)."""
+        for t in (src, dst):
+            if t.numel() * t.element_size() != self.sizes.state_bytes:
+                raise ValueError("state buffer has the wrong size")
+        self._call("lb_step_from", _ptr(src), _ptr(dst))
+
     def moments(self):
         """(rho (nx,ny,nz), u (3,nx,ny,nz), phi (nx,ny,nz)) as FP64 device tensors."""
         rho = self._out(*self.shape)
@@ -141,8 +153,7 @@ class LB:
 
     def get_state(self, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:
-            with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
-                out = torch.empty(int(self.sizes.state_bytes), dtype=torch.uint8, device=self.device)
+            out = self.new_state()
         self._call("lb_get_state", _ptr(out))
         return out
 

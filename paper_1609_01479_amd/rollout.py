@@ -4,9 +4,10 @@ forward(phi0, A, B, kappa) runs T timesteps on the GPU and returns phi_T.
 backward(dL/dphi_T) returns dL/dphi0 and dL/d(A, B, kappa) from the
 hand-written adjoint kernels (lb_adjoint_step), with checkpointing and
 recomputation: the forward keeps the state every k steps (k = ceil(sqrt(T))
-by default); the backward restores each checkpoint in reverse order,
-recomputes the k states of its segment, and walks the adjoint back through
-them.  Memory: ceil(T/k) + k states instead of T.
+by default); the backward takes each checkpoint in reverse order,
+recomputes the k - 1 later states of its segment with lb_step_from (each
+written once, straight into its segment buffer), and walks the adjoint back
+through them.  Memory: ceil(T/k) + k - 1 states instead of T.
 
 All state copies are lossless (lb_get_state / lb_set_state), and the forward
 step is deterministic, so the recomputed states are bit-identical to the
@@ -54,21 +55,17 @@ class _Rollout(torch.autograd.Function):
         lb, ckpts, T, k = ctx.lb, ctx.ckpts, ctx.T, ctx.k
         dtheta = torch.zeros(3, dtype=torch.float64, device=lb.device)
         lb.adjoint_seed(gphi.detach())
-        seg_states = []
-        for seg in reversed(range(len(ckpts))):
-            t0 = seg * k
+        # segment buffers: the checkpoint itself is the segment's first state;
+        # the others are recomputed in place by one step each (no copies)
+        seg = [None] + [lb.new_state() for _ in range(min(k, T) - 1)]
+        for si in reversed(range(len(ckpts))):
+            t0 = si * k
             t1 = min(T, t0 + k)
-            lb.set_state(ckpts[seg])
-            # states S_t for t0 <= t < t1 (reuse the buffers of the previous segment)
-            for j, t in enumerate(range(t0, t1)):
-                if j > 0:
-                    lb.step(1)
-                if j < len(seg_states):
-                    lb.get_state(seg_states[j])
-                else:
-                    seg_states.append(lb.get_state())
+            seg[0] = ckpts[si]
+            for j in range(1, t1 - t0):
+                lb.step_from(seg[j - 1], seg[j])
             for t in reversed(range(t0, t1)):
-                lb.adjoint_step(seg_states[t - t0], dtheta)
+                lb.adjoint_step(seg[t - t0], dtheta)
         dphi0 = lb.adjoint_phi0()
         ctx.lb = None
         ctx.ckpts = None

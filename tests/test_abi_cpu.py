@@ -95,6 +95,9 @@ def test_create_validates_buffers_without_launching(abi):
     assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
     assert ctx.value
     assert L.lb_step(ctx, -1) == abi.LB_EINVAL
+    assert L.lb_step_from(ctx, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000)) == abi.LB_EINVAL
+    assert L.lb_step_from(ctx, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2010)) == abi.LB_EALIGN
+    assert L.lb_step_from(ctx, None, ctypes.c_void_p(0x2000)) == abi.LB_EINVAL
     assert L.lb_adjoint_seed(ctx, ctypes.c_void_p(0x1000)) == abi.LB_ESTATE
     L.lb_destroy(ctx)
     L.lb_destroy(None)
