@@ -147,6 +147,13 @@ lb_status lb_init_phi(lb_ctx *ctx, const double *phi0_dev);
 /* Advance nsteps >= 0 timesteps (asynchronous). */
 lb_status lb_step(lb_ctx *ctx, int32_t nsteps);
 
+/* lb_step that also reduces, inside each step, the FP64 conserved sums of
+ * the state the step starts from: sums_dev (device, 5*nsteps FP64) receives
+ * [sum rho, sum phi, sum j_x, sum j_y, sum j_z] for each step t at
+ * sums_dev[5t..5t+4] (the targetDoubleSum of the paper's host model,
+ * Sec. 3.2.3; deterministic, as lb_sums). */
+lb_status lb_step_sums(lb_ctx *ctx, int32_t nsteps, double *sums_dev);
+
 /* One timestep from the caller's time level src_dev to dst_dev (both
  * state_bytes, as written by lb_get_state or a previous lb_step_from),
  * without touching the context's current level.  Used by the reverse mode to

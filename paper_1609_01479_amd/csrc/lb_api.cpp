@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 
 #include "lb_internal.h"
@@ -110,7 +111,14 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     // f and g, plus the FP64 reference order parameter in FP32 mode
     out->state_bytes = 2 * LB_NVEL * stride * e + (p->precision == LB_FP32_DEV ? stride * 8 : 0);
     out->phi_bytes = stride * 8;
-    out->scratch_bytes = size_t(lbk::kMaxPartialBlocks) * 8 * 8;
+    // block partials of the reductions: 5 FP64 per block of the largest grid
+    lbk::KParams k{};
+    k.nx = p->nx;
+    k.ny = p->ny;
+    k.nz = p->nz;
+    const lbk::TileCfg tc = lbk::tile_config(k, p->segment_x);
+    const size_t nparts = std::max<size_t>(size_t(tc.ntiles) * tc.nseg, lbk::kMaxPartialBlocks);
+    out->scratch_bytes = nparts * 5 * 8;
     out->adj_bytes = size_t(kAdjComponents) * stride * e;
     out->adj_scratch_bytes = size_t(kAdjScratchComponents) * stride * e;
     return LB_OK;
@@ -182,18 +190,28 @@ lb_status lb_init_phi(lb_ctx* ctx, const double* phi0_dev)
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_init_phi");
 }
 
-lb_status lb_step(lb_ctx* ctx, int32_t nsteps)
+static lb_status step_n(lb_ctx* ctx, int32_t nsteps, double* sums_dev, const char* name)
 {
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
     if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0 (got %d)", nsteps);
     for (int32_t t = 0; t < nsteps; t++) {
         hipError_t e = lbk::launch_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel,
                                         ctx->b.state[ctx->cur], ctx->b.state[1 - ctx->cur],
-                                        static_cast<double*>(ctx->b.phi), ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "lb_step");
+                                        static_cast<double*>(ctx->b.phi),
+                                        static_cast<double*>(ctx->b.scratch),
+                                        sums_dev ? sums_dev + 5 * size_t(t) : nullptr, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, name);
         ctx->cur = 1 - ctx->cur;
     }
     return LB_OK;
+}
+
+lb_status lb_step(lb_ctx* ctx, int32_t nsteps) { return step_n(ctx, nsteps, nullptr, "lb_step"); }
+
+lb_status lb_step_sums(lb_ctx* ctx, int32_t nsteps, double* sums_dev)
+{
+    if (!sums_dev) return fail(LB_EINVAL, "sums_dev is required");
+    return step_n(ctx, nsteps, sums_dev, "lb_step_sums");
 }
 
 lb_status lb_step_from(lb_ctx* ctx, const void* src_dev, void* dst_dev)
@@ -203,7 +221,7 @@ lb_status lb_step_from(lb_ctx* ctx, const void* src_dev, void* dst_dev)
     if (!aligned(src_dev) || !aligned(dst_dev))
         return fail(LB_EALIGN, "src_dev and dst_dev must be 256-byte aligned");
     hipError_t e = lbk::launch_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel, src_dev, dst_dev,
-                                    static_cast<double*>(ctx->b.phi), ctx->stream);
+                                    static_cast<double*>(ctx->b.phi), nullptr, nullptr, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_step_from");
 }
 

@@ -35,8 +35,13 @@ TileCfg tile_config(const KParams& p, int segment_x);
 // phi_c[stride] (FP64).  Order-parameter fields (`phi`) are FP64.
 hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* phi0, hipStream_t s);
 // variant 0: single-pass fused step; 1: phi pass + collision pass.
+// If sums_out is non-null, also writes the 5 FP64 conserved sums
+// [rho, phi, jx, jy, jz] of the source level to sums_out, through block
+// partials in `partials` (at least 5 * max(tc.ntiles * tc.nseg,
+// kMaxPartialBlocks) doubles).
 hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
-                       const void* src, void* dst, double* phi_work, hipStream_t s);
+                       const void* src, void* dst, double* phi_work, double* partials,
+                       double* sums_out, hipStream_t s);
 // phi(x) of the post-propagation state held in `state`.
 hipError_t launch_phi(const KParams& p, bool fp32, const void* state, double* phi, hipStream_t s);
 hipError_t launch_moments(const KParams& p, bool fp32, const void* state, double* rho, double* u,

@@ -157,7 +157,8 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
                                                 const T* __restrict__ sG,
                                                 const double* __restrict__ sphic,
                                                 T* __restrict__ dF, T* __restrict__ dG,
-                                                double* __restrict__ dphic)
+                                                double* __restrict__ dphic,
+                                                double* __restrict__ partials)
 {
     constexpr int PCS = REF ? 6 : 1, PCY = REF ? TY + 4 : 1, PCZ = REF ? TZ + 4 : 1;
     __shared__ double ph[4][TY + 2][TZ + 2];
@@ -239,6 +240,8 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     if (active) ph[1][ly + 1][lz + 1] = pull_phi(x0, y, z, ly + 2, lz + 2, kcur);
     if (ring) ph[1][rly][rlz] = pull_phi(x0, ry, rz, rly + 1, rlz + 1, nullptr);
 
+    // conserved sums of the source level (FP64), if requested
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     T f[NV];
     auto load_f = [&](int X) {
         const Geo qc = geo_xyz(p, X, y, z);
@@ -268,6 +271,14 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
                 const double d = gval(x, i, ly + 2, lz + 2, kcur[i]);
                 g[i] = REF ? T(d - rweight(i) * c) : T(d);
             }
+            if (partials) {
+                const Moments<T> m = moments_of<T, DEV>(p, f);
+                acc[0] += DEV ? p.rho0 + double(m.b) : double(m.rho);
+                acc[1] += c;
+                acc[2] += double(m.jx);
+                acc[3] += double(m.jy);
+                acc[4] += double(m.jz);
+            }
             collide<T, DEV, REF>(p, f, g, st);
             const int s = site_of(p, x, y, z);
 #pragma unroll
@@ -281,6 +292,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
             if (LB_PREFETCH_F && x + 1 < x1) load_f(x + 1);
         }
     }
+    if (partials) block_partials<5>(acc, partials);
 }
 
 #if LB_WPE32 > 0
@@ -297,17 +309,17 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
 __global__ __launch_bounds__(kBlock) LB_ATTR32 void k_step_fused_f32(
     KParams p, TileCfg tc, const float* __restrict__ sF, const float* __restrict__ sG,
     const double* __restrict__ sphic, float* __restrict__ dF, float* __restrict__ dG,
-    double* __restrict__ dphic)
+    double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<float, true, true>(p, tc, sF, sG, sphic, dF, dG, dphic);
+    step_fused_body<float, true, true>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
 }
 
 __global__ __launch_bounds__(kBlock) LB_ATTR64 void k_step_fused_f64(
     KParams p, TileCfg tc, const double* __restrict__ sF, const double* __restrict__ sG,
     const double* __restrict__ sphic, double* __restrict__ dF, double* __restrict__ dG,
-    double* __restrict__ dphic)
+    double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<double, false, false>(p, tc, sF, sG, sphic, dF, dG, dphic);
+    step_fused_body<double, false, false>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
 }
 
 template <typename T>
@@ -490,16 +502,24 @@ hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* p
 }
 
 hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
-                       const void* src, void* dst, double* phi_work, hipStream_t s)
+                       const void* src, void* dst, double* phi_work, double* partials,
+                       double* sums_out, hipStream_t s)
 {
+    int nparts = 0;
 #define CALL                                                                                    \
     {                                                                                           \
         Lvl<T> a = level<T>(const_cast<void*>(src), p, REF);                                    \
         Lvl<T> d = level<T>(dst, p, REF);                                                       \
         if (variant == 0) {                                                                     \
-            Fused<T>::kernel<<<tc.ntiles * tc.nseg, kBlock, 0, s>>>(                            \
-                p, tc, a.F, a.G, a.phic, d.F, d.G, d.phic);                                     \
+            nparts = tc.ntiles * tc.nseg;                                                       \
+            Fused<T>::kernel<<<nparts, kBlock, 0, s>>>(p, tc, a.F, a.G, a.phic, d.F, d.G,       \
+                                                        d.phic, sums_out ? partials : nullptr); \
         } else {                                                                                \
+            if (sums_out) {                                                                     \
+                nparts = reduction_grid(p);                                                     \
+                k_moments<T, DEV, REF><<<nparts, kBlock, 0, s>>>(p, a.F, a.G, a.phic, nullptr,  \
+                                                                 nullptr, nullptr, partials);   \
+            }                                                                                   \
             double* phin = REF ? d.phic : phi_work;                                             \
             k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);                 \
             k_step_2s<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phin,    \
@@ -508,6 +528,7 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
     }
     LB_DISPATCH(fp32, CALL, CALL);
 #undef CALL
+    if (sums_out) k_sums_final<<<1, kBlock, 0, s>>>(partials, nparts, 5, sums_out, 0);
     return hipGetLastError();
 }
 

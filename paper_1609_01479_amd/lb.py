@@ -120,6 +120,16 @@ class LB:
     def step(self, nsteps: int = 1) -> None:
         self._call("lb_step", ctypes.c_int32(int(nsteps)))
 
+    def step_sums(self, nsteps: int, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Advance nsteps and return the (nsteps, 5) FP64 device tensor of the
+        conserved sums [rho, phi, jx, jy, jz] of each step's starting state."""
+        if out is None:
+            out = self._out(int(nsteps), 5)
+        if out.dtype != torch.float64 or out.numel() < 5 * nsteps or not out.is_contiguous():
+            raise ValueError("out must be a contiguous FP64 tensor of 5*nsteps values")
+        self._call("lb_step_sums", ctypes.c_int32(int(nsteps)), _ptr(out))
+        return out
+
     def new_state(self) -> torch.Tensor:
         """An uninitialised device buffer of one time level (state_bytes)."""
         with torch.cuda.device(self.device), torch.cuda.stream(self.stream):

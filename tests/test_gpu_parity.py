@@ -213,3 +213,28 @@ def test_step_from_matches_step_bit_exact(prec):
     lb.set_state(c)
     for x, y in zip(gpu_state(lb), ref):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec,kernel", [("fp64", "fused"), ("fp64", "two_pass"),
+                                         ("fp32_dev", "fused"), ("fp32_dev", "two_pass")])
+def test_step_sums_history(prec, kernel):
+    """lb_step_sums: row t holds the conserved sums of the state step t starts
+    from (against lb_sums of that state and the oracle); the step itself is
+    unchanged (bit-identical to lb_step)."""
+    shape = (11, 9, 70)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=23, amp=0.3)
+    kw = dict(tau_f=0.8, tau_g=1.3)
+    a = make_lb(shape, precision=prec, kernel=kernel, **kw)
+    a.init_phi(phi0)
+    b = make_lb(shape, precision=prec, kernel=kernel, **kw)
+    b.init_phi(phi0)
+    hist = a.step_sums(5).cpu().numpy()
+    for t in range(5):
+        ref = b.sums().cpu().numpy()
+        np.testing.assert_allclose(hist[t], ref, rtol=1e-13, atol=1e-13)
+        b.step(1)
+    for x, y in zip(gpu_state(a), gpu_state(b)):
+        assert np.array_equal(x, y)
+    p = oracle_params(shape, **kw)
+    f0, g0 = oracle.init(p, phi0)
+    np.testing.assert_allclose(hist[0], oracle.sums(p, f0, g0), rtol=1e-12, atol=1e-12)
