@@ -41,6 +41,9 @@ namespace {
 #ifndef LB_WPE32
 #define LB_WPE32 0  // >0: waves-per-EU hint for the FP32 instantiation
 #endif
+#ifndef LB_RELOAD_G
+#define LB_RELOAD_G 0  // 1: re-read plane x's g (an L2 hit) instead of keeping it
+#endif
 #ifndef LB_WPE64
 #define LB_WPE64 0  // >0: waves-per-EU hint for the FP64 instantiation
 #endif
@@ -256,7 +259,12 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
         load_pc(x + 3);
         if (active) {
             if (!LB_PREFETCH_F) load_f(x);
-            ph[sn][ly + 1][lz + 1] = pull_phi(x + 1, y, z, ly + 2, lz + 2, knext);
+            if (LB_RELOAD_G) {
+                const Geo qc = geo_xyz(p, x, y, z);
+#pragma unroll
+                for (int i = 0; i < NV; i++) kcur[i] = K(sG[i * p.stride + pull_site(p, qc, i)]);
+            }
+            ph[sn][ly + 1][lz + 1] = pull_phi(x + 1, y, z, ly + 2, lz + 2, LB_RELOAD_G ? nullptr : knext);
         }
         if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, ry, rz, rly + 1, rlz + 1, nullptr);
         __syncthreads();
@@ -287,8 +295,9 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
                 store_out(dG + i * p.stride + s, g[i]);
             }
             if (REF) store_out(dphic + s, c);
+            if (!LB_RELOAD_G)
 #pragma unroll
-            for (int i = 0; i < NV; i++) kcur[i] = knext[i];
+                for (int i = 0; i < NV; i++) kcur[i] = knext[i];
             if (LB_PREFETCH_F && x + 1 < x1) load_f(x + 1);
         }
     }
