@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_local(KParams p, const T* __rest
                                                       double* __restrict__ partials)
 {
     double dth[3] = {0.0, 0.0, 0.0};
-    const long long S = p.stride;
+    const unsigned S = p.stride;
     for (int s = blockIdx.x * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
         const Geo q = geo_of(p, s);
         T lf[NV], lg[NV], f[NV];
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_stencil(KParams p, const T* __re
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
     const Geo q = geo_of(p, s);
-    const long long S = p.stride;
+    const unsigned S = p.stride;
     const int xp = site_of(p, q.xp, q.y, q.z), xm = site_of(p, q.xm, q.y, q.z);
     const int yp = site_of(p, q.x, q.yp, q.z), ym = site_of(p, q.x, q.ym, q.z);
     const int zp = site_of(p, q.x, q.y, q.zp), zm = site_of(p, q.x, q.y, q.zm);

@@ -52,8 +52,10 @@ lb_status validate(const lb_params* p)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LB_ESHAPE, "extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
     const long long n = (long long)p->nx * p->ny * p->nz;
-    if (n >= (1LL << 31) - 4096)  // site indices are 32-bit in the kernels
-        return fail(LB_ESHAPE, "lattice of %lld sites is too large", n);
+    // element offsets in the kernels are 32-bit: component * stride + site with
+    // up to 39 components (an adjoint level)
+    if ((long long)(stride_for(n)) * 39 >= (1LL << 32))
+        return fail(LB_ESHAPE, "lattice of %lld sites is too large (limit ~1.1e8 sites)", n);
     if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5))
         return fail(LB_EINVAL, "tau_f and tau_g must exceed 1/2 (got %g, %g)", p->tau_f, p->tau_g);
     if (!(p->rho0 > 0.0)) return fail(LB_EINVAL, "rho0 must be positive (got %g)", p->rho0);
@@ -116,7 +118,7 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     k.nx = p->nx;
     k.ny = p->ny;
     k.nz = p->nz;
-    const lbk::TileCfg tc = lbk::tile_config(k, p->segment_x);
+    const lbk::TileCfg tc = lbk::tile_config(k, p->segment_x, p->precision == LB_FP32_DEV);
     const size_t nparts = std::max<size_t>(size_t(tc.ntiles) * tc.nseg, lbk::kMaxPartialBlocks);
     out->scratch_bytes = nparts * 5 * 8;
     out->adj_bytes = size_t(kAdjComponents) * stride * e;
@@ -160,7 +162,7 @@ lb_status lb_create(const lb_params* p, const lb_buffers* b, void* hip_stream, l
     k.ny = p->ny;
     k.nz = p->nz;
     k.nsites = p->nx * p->ny * p->nz;
-    k.stride = (long long)sz.stride_elems;
+    k.stride = unsigned(sz.stride_elems);
     k.A = p->A;
     k.B = p->B;
     k.kappa = p->kappa;
@@ -168,7 +170,7 @@ lb_status lb_create(const lb_params* p, const lb_buffers* b, void* hip_stream, l
     k.omega_f = 1.0 / p->tau_f;
     k.omega_g = 1.0 / p->tau_g;
     k.rho0 = p->rho0;
-    c->tc = lbk::tile_config(k, p->segment_x);
+    c->tc = lbk::tile_config(k, p->segment_x, c->fp32);
     *out = c;
     return LB_OK;
 }

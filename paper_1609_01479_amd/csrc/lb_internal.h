@@ -14,7 +14,9 @@ constexpr int NV = 19;
 struct KParams {
     int nx, ny, nz;
     int nsites;            // nx*ny*nz
-    long long stride;      // elements per distribution component
+    unsigned stride;       // elements per distribution component; every element
+                           // offset in a kernel (component * stride + site, at
+                           // most 39 components) fits in 32 bits
     double A, B, kappa, gamma;
     double omega_f, omega_g;  // 1/tau
     double rho0;
@@ -27,7 +29,7 @@ struct TileCfg {
 };
 
 // segment_x <= 0 picks the segment length automatically.
-TileCfg tile_config(const KParams& p, int segment_x);
+TileCfg tile_config(const KParams& p, int segment_x, bool fp32);
 
 // All launchers enqueue on `s` and return hipGetLastError().
 // `fp32` selects the FP32 deviation-storage instantiation; otherwise FP64.

@@ -24,39 +24,25 @@ using namespace dev;
 
 namespace {
 
-// Tuning knobs of the single-pass kernel (compile-time; defaults are the
-// measured best on MI355X).
-#ifndef LB_TZ
-#define LB_TZ 64  // tile extent along z (contiguous)
+// Tile of the single-pass kernel: TZ contiguous z-sites per row (one
+// wavefront row), TYB thread rows per 256-thread workgroup; a thread owns SY
+// rows (SY = 2 in FP32 mode: twice the bytes in flight per workgroup and a
+// halo ring of 28% instead of 53% of the tile).
+constexpr int TZ = 64;
+constexpr int TYB = kBlock / TZ;
+#ifndef LB_SY32
+#define LB_SY32 2
 #endif
-#ifndef LB_RING_SPREAD
-#define LB_RING_SPREAD 0  // 1: spread halo-ring sites evenly over the waves
+constexpr int SY32 = LB_SY32;
+#ifndef LB_XCD_REMAP
+#define LB_XCD_REMAP 1
 #endif
-#ifndef LB_PREFETCH_F
-#define LB_PREFETCH_F 0  // 1: load plane x+1's f while plane x is stored
+#ifndef LB_ZFAST
+#define LB_ZFAST 0
 #endif
-#ifndef LB_NT_STORE
-#define LB_NT_STORE 0  // 1: nontemporal stores of the new time level
-#endif
-#ifndef LB_WPE32
-#define LB_WPE32 0  // >0: waves-per-EU hint for the FP32 instantiation
-#endif
-#ifndef LB_RELOAD_G
-#define LB_RELOAD_G 0  // 1: re-read plane x's g (an L2 hit) instead of keeping it
-#endif
-#ifndef LB_WPE64
-#define LB_WPE64 0  // >0: waves-per-EU hint for the FP64 instantiation
-#endif
+constexpr int SY64 = 1;
 
-constexpr int TZ = LB_TZ;
-constexpr int TY = kBlock / TZ;
 
-template <typename T>
-__device__ __forceinline__ void store_out(T* ptr, T v)
-{
-    if (LB_NT_STORE) __builtin_nontemporal_store(v, ptr);
-    else *ptr = v;
-}
 
 template <typename T>
 struct Lvl {
@@ -71,8 +57,8 @@ Lvl<T> level(void* state, const KParams& p, bool ref)
     T* base = static_cast<T*>(state);
     Lvl<T> l;
     l.F = base;
-    l.G = base + NV * p.stride;
-    l.phic = ref ? reinterpret_cast<double*>(base + 2 * NV * p.stride) : nullptr;
+    l.G = base + size_t(NV) * p.stride;
+    l.phic = ref ? reinterpret_cast<double*>(base + size_t(2 * NV) * p.stride) : nullptr;
     return l;
 }
 
@@ -154,7 +140,52 @@ __device__ __forceinline__ int wrapg(int v, int n)
 // prefetched while planes x-1..x+2 are in use.  Each pulled population then
 // costs one FP32 global load; its reference term r_i phi_c(x - c_i) comes
 // from LDS.
-template <typename T, bool DEV, bool REF>
+// Addressing: a thread's (y, z) never changes while it marches along x, so
+// the 9 (y - cy, z - cz) byte offsets of its pulls are computed once; a plane
+// and a component each contribute a uniform byte offset.  When a whole
+// 19-component array is smaller than 4 GiB (SMALL) one 32-bit byte offset
+// per load (component + plane + row) on a single base pointer suffices;
+// larger lattices keep a uniform base pointer per component instead.
+template <bool SMALL, typename T>
+__device__ __forceinline__ T ldc(const T* __restrict__ base, unsigned stride, int i, unsigned off)
+{
+    if (SMALL) {
+        const unsigned o = unsigned(i) * stride * unsigned(sizeof(T)) + off;
+        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + o);
+    }
+    const char* b = reinterpret_cast<const char*>(base + size_t(i) * stride);
+    return *reinterpret_cast<const T*>(b + off);
+}
+template <bool SMALL, typename T>
+__device__ __forceinline__ void stc(T* __restrict__ base, unsigned stride, int i, unsigned off, T v)
+{
+    if (SMALL) {
+        const unsigned o = unsigned(i) * stride * unsigned(sizeof(T)) + off;
+        *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + o) = v;
+        return;
+    }
+    char* b = reinterpret_cast<char*>(base + size_t(i) * stride);
+    *reinterpret_cast<T*>(b + off) = v;
+}
+
+// byte offsets of the 9 rows/columns (y + dy, z + dz), dy, dz in {-1, 0, 1}
+struct Yz9 {
+    unsigned o[3][3];
+};
+template <typename T>
+__device__ __forceinline__ Yz9 yz9(const KParams& p, int y, int z)
+{
+    const int ys[3] = {wrapm(y, p.ny), y, wrapp(y, p.ny)};
+    const int zs[3] = {wrapm(z, p.nz), z, wrapp(z, p.nz)};
+    Yz9 r;
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) r.o[a][c] = unsigned(ys[a] * p.nz + zs[c]) * unsigned(sizeof(T));
+    return r;
+}
+
+template <typename T, bool DEV, bool REF, int SY, bool SMALL>
 __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg& tc,
                                                 const T* __restrict__ sF,
                                                 const T* __restrict__ sG,
@@ -163,28 +194,40 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
                                                 double* __restrict__ dphic,
                                                 double* __restrict__ partials)
 {
+    constexpr int TY = TYB * SY;  // site rows of the tile
     constexpr int PCS = REF ? 6 : 1, PCY = REF ? TY + 4 : 1, PCZ = REF ? TZ + 4 : 1;
     __shared__ double ph[4][TY + 2][TZ + 2];
     __shared__ double pc[PCS][PCY][PCZ];
     // value kept per direction between the phi pull and the collision:
     // the stored FP32 deviation (FP32 mode) or the FP64 population
     using K = typename std::conditional<REF, T, double>::type;
+    const unsigned S = p.stride;
 
     int b = blockIdx.x;
     const int nb = gridDim.x;
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    if (LB_XCD_REMAP && (nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
     const int tile = b % tc.ntiles, seg = b / tc.ntiles;
-    const int y0 = (tile % tc.nty) * TY, z0 = (tile / tc.nty) * TZ;
+    const int y0 = (LB_ZFAST ? tile / tc.ntz : tile % tc.nty) * TY;
+    const int z0 = (LB_ZFAST ? tile % tc.ntz : tile / tc.nty) * TZ;
     const int x0 = seg * tc.sx;
     const int x1 = min(x0 + tc.sx, p.nx);
     const int tya = min(TY, p.ny - y0), tza = min(TZ, p.nz - z0);
-    const int lz = threadIdx.x % TZ, ly = threadIdx.x / TZ;
-    const bool active = lz < tza && ly < tya;
-    const int y = y0 + ly, z = z0 + lz;
+    const int lz = threadIdx.x % TZ, lyb = threadIdx.x / TZ;
+    const int z = z0 + lz;
+    const int plane = p.ny * p.nz;
+    // this thread's rows: ly[k] = lyb + k*TYB
+    int ly[SY];
+    bool active[SY];
+    Yz9 rows[SY];
+#pragma unroll
+    for (int k = 0; k < SY; k++) {
+        ly[k] = lyb + k * TYB;
+        active[k] = lz < tza && ly[k] < tya;
+        rows[k] = yz9<T>(p, active[k] ? y0 + ly[k] : 0, active[k] ? z : 0);
+    }
 
     // halo ring: rows y0-1 and y0+tya, then columns z0-1 and z0+tza
-    const int r = LB_RING_SPREAD ? (threadIdx.x & 63) * (kBlock / 64) + (threadIdx.x >> 6)
-                                 : int(threadIdx.x);
+    const int r = threadIdx.x;
     const int nring = 2 * tza + 2 * tya;
     const bool ring = r < nring;
     int rly, rlz;
@@ -193,153 +236,182 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     else if (r < 2 * tza + tya) { rly = r - 2 * tza + 1; rlz = 0; }
     else { rly = r - 2 * tza - tya + 1; rlz = tza + 1; }
     const int ry = wrapg(y0 + rly - 1, p.ny), rz = wrapg(z0 + rlz - 1, p.nz);
+    const Yz9 rrow = yz9<T>(p, ry, rz);
 
-    // plane indices run from x0-2 to x1+2: wrap them with a full modulo (nx may be 1)
-    auto xw = [&](int X) { return ((X % p.nx) + p.nx) % p.nx; };
-    // phi_c plane X (logical index X - x0 + 2) into its LDS slot; cell
-    // (cy, cz) holds site (y0 + cy - 2, z0 + cz - 2)
-    auto load_pc = [&](int X) {
+    // plane indices run from x0-2 to x1+2 (nx may be 1): wrap without
+    // division or branches (valid on [-2nx, 4nx))
+    auto xw = [&](int X) {
+        X += X < 0 ? p.nx : 0;
+        X += X < 0 ? p.nx : 0;
+        X -= X >= p.nx ? p.nx : 0;
+        X -= X >= p.nx ? p.nx : 0;
+        X -= X >= p.nx ? p.nx : 0;
+        return X;
+    };
+    // byte base of plane X in a T array
+    auto pbase = [&](int X) { return unsigned(xw(X) * plane) * unsigned(sizeof(T)); };
+
+    // LDS slot of phi_c plane X is (X - x0 + 2) mod 6; `sl` below is the slot
+    // of a site's own plane and sl +- 1 (mod 6) those of its neighbours
+    auto add6 = [](int a, int d) {
+        const int v = a + d;
+        return v >= PCS ? v - PCS : (v < 0 ? v + PCS : v);
+    };
+    // phi_c plane X into LDS slot `slot`; cell (cy, cz) holds site
+    // (y0 + cy - 2, z0 + cz - 2)
+    auto load_pc = [&](int X, int slot) {
         if (REF) {
-            const int slot = (X - x0 + 2) % PCS;
             const int W = tza + 4, n = W * (tya + 4);
             const int xx = xw(X);
             for (int t = threadIdx.x; t < n; t += kBlock) {
                 const int cy = t / W, cz = t - cy * W;
-                pc[slot % PCS][REF ? cy : 0][REF ? cz : 0] =
+                pc[REF ? slot : 0][REF ? cy : 0][REF ? cz : 0] =
                     sphic[site_of(p, xx, wrapg(y0 + cy - 2, p.ny), wrapg(z0 + cz - 2, p.nz))];
             }
         }
     };
-    // g_i at a site of plane X as FP64, from the kept value kv of direction i;
-    // (cy, cz) is the site's phi_c cell
-    auto gval = [&](int X, int i, int cy, int cz, K kv) -> double {
-        if (REF) {
-            const int slot = (X - CX[i] - x0 + 2) % PCS;
-            return __builtin_fma(rweight(i), pc[slot % PCS][REF ? cy - CY[i] : 0][REF ? cz - CZ[i] : 0],
+    // g_i at a site as FP64, from the kept value kv of direction i; sl3 are the
+    // slots of the planes X-1, X, X+1 and (cy, cz) the site's phi_c cell
+    auto gval = [&](const int* sl3, int i, int cy, int cz, K kv) -> double {
+        if (REF)
+            return __builtin_fma(rweight(i),
+                                 pc[REF ? sl3[1 - CX[i]] : 0][REF ? cy - CY[i] : 0][REF ? cz - CZ[i] : 0],
                                  double(kv));
-        }
         return double(kv);
     };
-    // pull of plane X at (yy, zz): kept values into kv[] (if non-null), returns phi
-    auto pull_phi = [&](int X, int yy, int zz, int cy, int cz, K* kv) -> double {
-        const Geo q = geo_xyz(p, xw(X), yy, zz);
+    // pull of plane X (slot sl) for a site with row offsets yz: kept values
+    // into kv[] (if non-null), returns phi
+    auto pull_phi = [&](int X, int sl, const Yz9& yz, int cy, int cz, K* kv) -> double {
+        const unsigned pb[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
+        const int sl3[3] = {add6(sl, -1), sl, add6(sl, 1)};
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            const K v = K(sG[i * p.stride + pull_site(p, q, i)]);
+            const unsigned off = pb[1 - CX[i]] + yz.o[1 - CY[i]][1 - CZ[i]];
+            const K v = K(ldc<SMALL>(sG, S, i, off));
             if (kv) kv[i] = v;
-            acc += gval(X, i, cy, cz, v);
+            acc += gval(sl3, i, cy, cz, v);
         }
         return acc;
     };
 
-    K kcur[NV], knext[NV];
+    K kcur[SY][NV], knext[SY][NV];
     // warm-up: phi_c planes x0-2 .. x0+2, then phi at planes x0-1 (slot 0)
     // and x0 (slot 1), keeping plane x0's populations
-    for (int X = x0 - 2; X <= x0 + 2; X++) load_pc(X);
+    for (int X = x0 - 2; X <= x0 + 2; X++) load_pc(X, X - x0 + 2);
     if (REF) __syncthreads();
-    if (active) ph[0][ly + 1][lz + 1] = pull_phi(x0 - 1, y, z, ly + 2, lz + 2, nullptr);
-    if (ring) ph[0][rly][rlz] = pull_phi(x0 - 1, ry, rz, rly + 1, rlz + 1, nullptr);
-    if (active) ph[1][ly + 1][lz + 1] = pull_phi(x0, y, z, ly + 2, lz + 2, kcur);
-    if (ring) ph[1][rly][rlz] = pull_phi(x0, ry, rz, rly + 1, rlz + 1, nullptr);
+#pragma unroll
+    for (int k = 0; k < SY; k++)
+        if (active[k])
+            ph[0][ly[k] + 1][lz + 1] = pull_phi(x0 - 1, 1, rows[k], ly[k] + 2, lz + 2, nullptr);
+    if (ring) ph[0][rly][rlz] = pull_phi(x0 - 1, 1, rrow, rly + 1, rlz + 1, nullptr);
+#pragma unroll
+    for (int k = 0; k < SY; k++)
+        if (active[k])
+            ph[1][ly[k] + 1][lz + 1] = pull_phi(x0, 2, rows[k], ly[k] + 2, lz + 2, kcur[k]);
+    if (ring) ph[1][rly][rlz] = pull_phi(x0, 2, rrow, rly + 1, rlz + 1, nullptr);
 
     // conserved sums of the source level (FP64), if requested
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    T f[NV];
-    auto load_f = [&](int X) {
-        const Geo qc = geo_xyz(p, X, y, z);
-#pragma unroll
-        for (int i = 0; i < NV; i++) f[i] = sF[i * p.stride + pull_site(p, qc, i)];
-    };
-    if (LB_PREFETCH_F && active) load_f(x0);
 
-    for (int x = x0; x < x1; x++) {
-        const int k = x - x0 + 2;  // phi slot counter of plane x+1
-        const int sn = k & 3, sc = (k - 1) & 3, sp = (k - 2) & 3;
-        load_pc(x + 3);
-        if (active) {
-            if (!LB_PREFETCH_F) load_f(x);
-            if (LB_RELOAD_G) {
-                const Geo qc = geo_xyz(p, x, y, z);
+    int slx = 2;  // phi_c slot of plane x
+    for (int x = x0; x < x1; x++, slx = add6(slx, 1)) {
+        const int kk = x - x0 + 2;  // phi slot counter of plane x+1
+        const int sn = kk & 3, sc = (kk - 1) & 3, sp = (kk - 2) & 3;
+        const int slx3[3] = {add6(slx, -1), slx, add6(slx, 1)};
+        load_pc(x + 3, add6(slx, 3));
+        const unsigned pbx[3] = {pbase(x - 1), pbase(x), pbase(x + 1)};
+        T f[SY][NV];
 #pragma unroll
-                for (int i = 0; i < NV; i++) kcur[i] = K(sG[i * p.stride + pull_site(p, qc, i)]);
-            }
-            ph[sn][ly + 1][lz + 1] = pull_phi(x + 1, y, z, ly + 2, lz + 2, LB_RELOAD_G ? nullptr : knext);
+        for (int k = 0; k < SY; k++) {
+            if (!active[k]) continue;
+#pragma unroll
+            for (int i = 0; i < NV; i++)
+                f[k][i] = ldc<SMALL>(sF, S, i, pbx[1 - CX[i]] + rows[k].o[1 - CY[i]][1 - CZ[i]]);
         }
-        if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, ry, rz, rly + 1, rlz + 1, nullptr);
+#pragma unroll
+        for (int k = 0; k < SY; k++)
+            if (active[k])
+                ph[sn][ly[k] + 1][lz + 1] =
+                    pull_phi(x + 1, slx3[2], rows[k], ly[k] + 2, lz + 2, knext[k]);
+        if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, slx3[2], rrow, rly + 1, rlz + 1, nullptr);
         __syncthreads();
-        if (active) {
-            const double c = ph[sc][ly + 1][lz + 1];
-            const Stencil st = stencil(c, ph[sn][ly + 1][lz + 1], ph[sp][ly + 1][lz + 1],
-                                       ph[sc][ly + 2][lz + 1], ph[sc][ly][lz + 1],
-                                       ph[sc][ly + 1][lz + 2], ph[sc][ly + 1][lz]);
+#pragma unroll
+        for (int k = 0; k < SY; k++) {
+            if (!active[k]) continue;
+            const int l = ly[k];
+            const double c = ph[sc][l + 1][lz + 1];
+            const Stencil st = stencil(c, ph[sn][l + 1][lz + 1], ph[sp][l + 1][lz + 1],
+                                       ph[sc][l + 2][lz + 1], ph[sc][l][lz + 1],
+                                       ph[sc][l + 1][lz + 2], ph[sc][l + 1][lz]);
             T g[NV];
 #pragma unroll
             for (int i = 0; i < NV; i++) {
-                const double d = gval(x, i, ly + 2, lz + 2, kcur[i]);
+                const double d = gval(slx3, i, l + 2, lz + 2, kcur[k][i]);
                 g[i] = REF ? T(d - rweight(i) * c) : T(d);
             }
             if (partials) {
-                const Moments<T> m = moments_of<T, DEV>(p, f);
-                acc[0] += DEV ? p.rho0 + double(m.b) : double(m.rho);
+                // moments of the stored values, formed in FP64
+                double bs = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+                for (int i = 0; i < NV; i++) {
+                    const double v = double(f[k][i]);
+                    bs += v;
+                    if (CX[i]) jx += CX[i] * v;
+                    if (CY[i]) jy += CY[i] * v;
+                    if (CZ[i]) jz += CZ[i] * v;
+                }
+                acc[0] += DEV ? p.rho0 + bs : bs;
                 acc[1] += c;
-                acc[2] += double(m.jx);
-                acc[3] += double(m.jy);
-                acc[4] += double(m.jz);
+                acc[2] += jx;
+                acc[3] += jy;
+                acc[4] += jz;
             }
-            collide<T, DEV, REF>(p, f, g, st);
-            const int s = site_of(p, x, y, z);
+            collide<T, DEV, REF>(p, f[k], g, st);
+            const unsigned so = pbx[1] + rows[k].o[1][1];
 #pragma unroll
             for (int i = 0; i < NV; i++) {
-                store_out(dF + i * p.stride + s, f[i]);
-                store_out(dG + i * p.stride + s, g[i]);
+                stc<SMALL>(dF, S, i, so, f[k][i]);
+                stc<SMALL>(dG, S, i, so, g[i]);
             }
-            if (REF) store_out(dphic + s, c);
-            if (!LB_RELOAD_G)
+            if (REF) dphic[so / unsigned(sizeof(T))] = c;
 #pragma unroll
-                for (int i = 0; i < NV; i++) kcur[i] = knext[i];
-            if (LB_PREFETCH_F && x + 1 < x1) load_f(x + 1);
+            for (int i = 0; i < NV; i++) kcur[k][i] = knext[k][i];
         }
     }
     if (partials) block_partials<5>(acc, partials);
 }
 
-#if LB_WPE32 > 0
-#define LB_ATTR32 __attribute__((amdgpu_waves_per_eu(LB_WPE32)))
-#else
-#define LB_ATTR32
-#endif
-#if LB_WPE64 > 0
-#define LB_ATTR64 __attribute__((amdgpu_waves_per_eu(LB_WPE64)))
-#else
-#define LB_ATTR64
-#endif
-
-__global__ __launch_bounds__(kBlock) LB_ATTR32 void k_step_fused_f32(
+template <bool SMALL>
+__global__ __launch_bounds__(kBlock) void k_step_fused_f32(
     KParams p, TileCfg tc, const float* __restrict__ sF, const float* __restrict__ sG,
     const double* __restrict__ sphic, float* __restrict__ dF, float* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<float, true, true>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
+    step_fused_body<float, true, true, SY32, SMALL>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
 }
 
-__global__ __launch_bounds__(kBlock) LB_ATTR64 void k_step_fused_f64(
+template <bool SMALL>
+__global__ __launch_bounds__(kBlock) void k_step_fused_f64(
     KParams p, TileCfg tc, const double* __restrict__ sF, const double* __restrict__ sG,
     const double* __restrict__ sphic, double* __restrict__ dF, double* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<double, false, false>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
+    step_fused_body<double, false, false, SY64, SMALL>(p, tc, sF, sG, sphic, dF, dG, dphic,
+                                                       partials);
 }
 
 template <typename T>
 struct Fused;
 template <>
 struct Fused<float> {
-    static constexpr auto kernel = k_step_fused_f32;
+    static constexpr auto small = k_step_fused_f32<true>;
+    static constexpr auto large = k_step_fused_f32<false>;
 };
 template <>
 struct Fused<double> {
-    static constexpr auto kernel = k_step_fused_f64;
+    static constexpr auto small = k_step_fused_f64<true>;
+    static constexpr auto large = k_step_fused_f64<false>;
 };
 
 // Dense FP64 moments of the post-propagation state and block partials of
@@ -478,18 +550,29 @@ int reduction_grid(const KParams& p)
         }                                 \
     } while (0)
 
+// a 19-component array addressed with 32-bit byte offsets
+bool small_arrays(const KParams& p, size_t elem)
+{
+    return size_t(NV) * p.stride * elem < (size_t(1) << 32);
+}
+
 }  // namespace
 
-TileCfg tile_config(const KParams& p, int segment_x)
+TileCfg tile_config(const KParams& p, int segment_x, bool fp32)
 {
+    const int ty = TYB * (fp32 ? SY32 : SY64);
     TileCfg tc;
-    tc.nty = (p.ny + TY - 1) / TY;
+    tc.nty = (p.ny + ty - 1) / ty;
     tc.ntz = (p.nz + TZ - 1) / TZ;
     tc.ntiles = tc.nty * tc.ntz;
     int sx = segment_x;
     if (sx <= 0) {
-        // aim for ~2048 workgroups (8 per CU) with segments of at least 8 planes
-        const long long want = (long long)p.nx * tc.ntiles / 2048;
+        // measured on MI355X at 256^3: the FP32 kernel wants ~2048 workgroups
+        // (it is latency-bound and needs many in flight); the FP64 kernel
+        // streams best with one workgroup per tile column (~256), i.e. the
+        // fewest concurrent DRAM streams.  Segments of at least 8 planes.
+        const long long target = fp32 ? 2048 : 256;
+        const long long want = (long long)p.nx * tc.ntiles / target;
         sx = int(want < 8 ? 8 : want);
     }
     if (sx > p.nx) sx = p.nx;
@@ -521,8 +604,9 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
         Lvl<T> d = level<T>(dst, p, REF);                                                       \
         if (variant == 0) {                                                                     \
             nparts = tc.ntiles * tc.nseg;                                                       \
-            Fused<T>::kernel<<<nparts, kBlock, 0, s>>>(p, tc, a.F, a.G, a.phic, d.F, d.G,       \
-                                                        d.phic, sums_out ? partials : nullptr); \
+            auto kern = small_arrays(p, sizeof(T)) ? Fused<T>::small : Fused<T>::large;        \
+            kern<<<nparts, kBlock, 0, s>>>(p, tc, a.F, a.G, a.phic, d.F, d.G, d.phic,           \
+                                           sums_out ? partials : nullptr);                      \
         } else {                                                                                \
             if (sums_out) {                                                                     \
                 nparts = reduction_grid(p);                                                     \

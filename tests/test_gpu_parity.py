@@ -237,4 +237,6 @@ def test_step_sums_history(prec, kernel):
         assert np.array_equal(x, y)
     p = oracle_params(shape, **kw)
     f0, g0 = oracle.init(p, phi0)
-    np.testing.assert_allclose(hist[0], oracle.sums(p, f0, g0), rtol=1e-12, atol=1e-12)
+    # FP32 storage rounds the initial populations once (relative ~1e-9 here)
+    tol = 1e-12 if prec == "fp64" else 1e-7
+    np.testing.assert_allclose(hist[0], oracle.sums(p, f0, g0), rtol=tol, atol=tol)
