@@ -70,11 +70,11 @@ typedef enum {
 typedef enum {
     LB_FP64 = 0,    /* distributions stored and collided in FP64            */
     LB_FP32_DEV = 1 /* FP32 storage of deviations and FP32 collision:
-                       f_i - w_i rho0, and g_i - r_i phi_c with the FP64
-                       order parameter phi_c of the site's last collision
-                       (r_i phi = the order-parameter equilibrium at rest
-                       with mu = 0); FP64 phi, reductions and parameter
-                       gradients                                             */
+                       f_i - w_i rho0, and g_i - r_i phi_c, where phi_c is
+                       the FP64 order parameter of the last collision at
+                       the site the population moves TO (r_i phi = the
+                       order-parameter equilibrium at rest with mu = 0);
+                       FP64 phi, reductions and parameter gradients          */
 } lb_precision;
 
 typedef enum {
@@ -181,8 +181,9 @@ lb_status lb_set_state(lb_ctx *ctx, const void *src_dev);
 lb_status lb_export_dist(lb_ctx *ctx, double *f_dev, double *g_dev);
 
 /* Set the current state from dense FP64 post-propagation distributions
- * (19, nx, ny, nz).  In LB_FP32_DEV the values are rounded to FP32 after
- * subtracting w_i rho0 from f_i. */
+ * (19, nx, ny, nz).  In LB_FP32_DEV phi_c(x) becomes sum_i g_i(x) and the
+ * values are rounded to FP32 after subtracting w_i rho0 from f_i and
+ * r_i phi_c(x) from g_i(x). */
 lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
 
 /* ---- reverse mode ------------------------------------------------------

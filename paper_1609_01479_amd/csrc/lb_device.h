@@ -7,13 +7,17 @@
 //   FP64 mode  (T = double, DEV = REF = false):
 //       F_i(y) = f*_i(y),  G_i(y) = g*_i(y)
 //   FP32 mode  (T = float,  DEV = REF = true):
-//       F_i(y) = f*_i(y) - w_i rho0                      (FP32)
-//       G_i(y) = g*_i(y) - r_i phi_c(y)                  (FP32)
-//       phi_c(y) = the order parameter the collision at y used (FP64)
+//       F_i(y) = f*_i(y) - w_i rho0                          (FP32)
+//       G_i(y) = g*_i(y) - r_i phi_c(y + c_i)                (FP32)
+//       phi_c(x) = the order parameter of x's last collision (FP64)
 //   with r_i = w_i (1 - 3/2 (|c_i|^2 - 1)) = (5/6, 1/18, -1/72): r_i phi is
-//   the order-parameter equilibrium of a fluid at rest with mu = 0, so both
-//   stored deviations are small in the bulk phases and FP32 rounding does not
-//   accumulate into the O(1) order parameter.  sum_i r_i = 1.
+//   the order-parameter equilibrium of a fluid at rest with mu = 0 and
+//   sum_i r_i = 1.  Each stored g deviation is referenced to the order
+//   parameter of the site it propagates TO, so the pull at x needs only x's
+//   own phi_c:  g_i(x) = G_i(x - c_i) + r_i phi_c(x),
+//   phi(x) = phi_c(x) + sum_i G_i(x - c_i).  Both stored deviations are small
+//   in the bulk phases, so FP32 rounding does not accumulate into the O(1)
+//   order parameter.
 // Post-propagation values at x are the pull  f_i(x) = f*_i(x - c_i).
 #pragma once
 
@@ -88,30 +92,48 @@ __device__ __forceinline__ int push_site(const KParams& p, const Geo& q, int i)
 
 // ---------------------------------------------------------------------------
 // Pull of the order-parameter populations.  d[i] = g_i(x) in FP64:
-//   FP64 mode: G_i(x - c_i);  FP32 mode: G_i(x - c_i) + r_i phi_c(x - c_i).
-// Returns phi(x) = sum_i d[i], summed in index order (every kernel forms phi
-// through this function, so a site's phi is bit-identical everywhere).
+//   FP64 mode: G_i(x - c_i);  FP32 mode: G_i(x - c_i) + r_i phi_c(x).
+// Returns phi(x): the index-order FP64 sum of the pulled values (FP64 mode),
+// or phi_c(x) plus the index-order FP64 sum of the pulled deviations (FP32
+// mode).  Every kernel forms phi this way, so a site's phi is bit-identical
+// everywhere.
 template <typename T, bool REF>
 __device__ __forceinline__ double pull_g(const KParams& p, const Geo& q, const T* __restrict__ G,
                                          const double* __restrict__ phic, double* d)
 {
     double acc = 0.0;
+    const double pc = REF ? phic[site_of(p, q.x, q.y, q.z)] : 0.0;
 #pragma unroll
     for (int i = 0; i < NV; i++) {
-        const int n = pull_site(p, q, i);
-        const double gv = double(G[i * p.stride + n]);
-        d[i] = REF ? __builtin_fma(rweight(i), phic[n], gv) : gv;
-        acc += d[i];
+        const double gv = double(G[i * p.stride + pull_site(p, q, i)]);
+        if (d) d[i] = REF ? __builtin_fma(rweight(i), pc, gv) : gv;
+        acc += gv;
     }
-    return acc;
+    return REF ? pc + acc : acc;
 }
 
 template <typename T, bool REF>
 __device__ __forceinline__ double phi_at(const KParams& p, const Geo& q, const T* __restrict__ G,
                                          const double* __restrict__ phic)
 {
-    double d[NV];
-    return pull_g<T, REF>(p, q, G, phic, d);
+    return pull_g<T, REF>(p, q, G, phic, nullptr);
+}
+
+// FP32 mode: pre-collision deviation g_i(x) - r_i phi(x) of the pulled
+// stored value G = G_i(x - c_i), with dphi = phi(x) - phi_c(x).
+template <typename T>
+__device__ __forceinline__ T pre_collision_dev(int i, T G, double dphi)
+{
+    return T(double(G) - rweight(i) * dphi);
+}
+
+// FP32 mode: the stored value of direction i at y from the collided
+// deviation h* = g* - r_i phi(y) and the order parameter at y and at the
+// destination y + c_i:  G_i(y) = h* + r_i (phi(y) - phi(y + c_i)).
+template <typename T>
+__device__ __forceinline__ T to_dest_ref(int i, T hstar, double phi_here, double phi_dest)
+{
+    return T(__builtin_fma(rweight(i), phi_here - phi_dest, double(hstar)));
 }
 
 // ---------------------------------------------------------------------------
@@ -260,15 +282,6 @@ __device__ __forceinline__ void collide(const KParams& p, T* f, T* g, const Sten
     }
 #pragma unroll
     for (int i = 0; i < NV; i++) g[i] += omg * (eq[i] - g[i]);
-}
-
-// Pre-collision order-parameter populations in the stored convention from the
-// pulled FP64 values d[] and the site's phi.
-template <typename T, bool REF>
-__device__ __forceinline__ void g_local(const double* d, double phi, T* g)
-{
-#pragma unroll
-    for (int i = 0; i < NV; i++) g[i] = REF ? T(d[i] - rweight(i) * phi) : T(d[i]);
 }
 
 // ---------------------------------------------------------------------------

@@ -2,18 +2,19 @@
 //
 // The step of the paper's Ludwig timestep (Sec. 2.1.1) -- order-parameter
 // gradients, chemical stress, collision, propagation -- runs as ONE kernel,
-// k_step_fused_f32 / _f64: each workgroup owns a (y, z) tile of sites and marches
-// along x over a segment of planes.  For plane x it needs phi at planes
-// x-1, x, x+1 (7-point stencil); phi(x+1) is formed from the pulled g of
-// plane x+1, which the same threads keep in registers for plane x+1's own
+// k_step_fused_f32 / _f64: each workgroup owns a (y, z) tile of 4 x 64 sites
+// and marches along x over a segment of planes.  For plane x it needs phi at
+// planes x-1, x, x+1 (7-point stencil); phi(x+1) is formed from the pulled g
+// of plane x+1, which the same threads keep in registers for plane x+1's own
 // collision one iteration later.  phi on the tile's (y, z) halo ring is
 // formed by extra pulls that mostly hit in cache (the neighbouring tiles read
 // the same lines).  phi planes live in a 4-slot LDS ring.  Every population
 // is therefore read once and written once per step from HBM: the method's
 // minimum traffic, instead of a separate phi pass plus a collision pass.
 //
-// k_phi + k_step_2s are the two-pass variant (phi kernel, then the fused
-// stencil/collision/propagation kernel), kept for comparison.
+// k_phi + k_step_2s are the two-pass variant (phi kernel, then the
+// stencil/collision/propagation kernel), kept for comparison; both variants
+// produce bit-identical levels.
 #include <type_traits>
 
 #include "lb_device.h"
@@ -25,24 +26,9 @@ using namespace dev;
 namespace {
 
 // Tile of the single-pass kernel: TZ contiguous z-sites per row (one
-// wavefront row), TYB thread rows per 256-thread workgroup; a thread owns SY
-// rows (SY = 2 in FP32 mode: twice the bytes in flight per workgroup and a
-// halo ring of 28% instead of 53% of the tile).
+// wavefront row), TY rows per 256-thread workgroup.
 constexpr int TZ = 64;
-constexpr int TYB = kBlock / TZ;
-#ifndef LB_SY32
-#define LB_SY32 2
-#endif
-constexpr int SY32 = LB_SY32;
-#ifndef LB_XCD_REMAP
-#define LB_XCD_REMAP 1
-#endif
-#ifndef LB_ZFAST
-#define LB_ZFAST 0
-#endif
-constexpr int SY64 = 1;
-
-
+constexpr int TY = kBlock / TZ;
 
 template <typename T>
 struct Lvl {
@@ -64,6 +50,9 @@ Lvl<T> level(void* state, const KParams& p, bool ref)
 
 // ---------------------------------------------------------------------------
 
+// Post-propagation state rho = rho0, u = 0, g_0 = phi0, g_{i>0} = 0.  In FP32
+// mode phi_c = phi0, and the stored deviation of direction i at y is
+// g_i(y + c_i) - r_i phi0(y + c_i).
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_init(KParams p, T* __restrict__ F, T* __restrict__ G,
                                                  double* __restrict__ phic,
@@ -71,14 +60,18 @@ __global__ __launch_bounds__(kBlock) void k_init(KParams p, T* __restrict__ F, T
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
-    const double ph = phi0[s];
+    const Geo q = geo_of(p, s);
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         F[i * p.stride + s] = DEV ? T(0) : T(weight(i) * p.rho0);
-        const double gi = i == 0 ? ph : 0.0;
-        G[i * p.stride + s] = REF ? T(gi - rweight(i) * ph) : T(gi);
+        if (REF) {
+            const double pd = phi0[push_site(p, q, i)];
+            G[i * p.stride + s] = T((i == 0 ? pd : 0.0) - rweight(i) * pd);
+        } else {
+            G[i * p.stride + s] = i == 0 ? T(phi0[s]) : T(0);
+        }
     }
-    if (REF) phic[s] = ph;
+    if (REF) phic[s] = phi0[s];
 }
 
 // phi(x) = sum_i g_i(x) of the post-propagation state (FP64).
@@ -93,7 +86,8 @@ __global__ __launch_bounds__(kBlock) void k_phi(KParams p, const T* __restrict__
 }
 
 // Two-pass variant, second pass: stencil + chemical stress + collision, one
-// site per thread; phi of the new state comes from k_phi.
+// site per thread; phi of the post-propagation source level (all sites)
+// comes from k_phi.
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_step_2s(KParams p, const T* __restrict__ sF,
                                                     const T* __restrict__ sG,
@@ -106,18 +100,24 @@ __global__ __launch_bounds__(kBlock) void k_step_2s(KParams p, const T* __restri
     const Geo q = geo_of(p, s);
     T f[NV], g[NV];
 #pragma unroll
-    for (int i = 0; i < NV; i++) f[i] = sF[i * p.stride + pull_site(p, q, i)];
-    double d[NV];
-    const double pc = pull_g<T, REF>(p, q, sG, sphic, d);
-    const Stencil st = stencil(pc, phi[site_of(p, q.xp, q.y, q.z)], phi[site_of(p, q.xm, q.y, q.z)],
+    for (int i = 0; i < NV; i++) {
+        f[i] = sF[i * p.stride + pull_site(p, q, i)];
+        g[i] = sG[i * p.stride + pull_site(p, q, i)];
+    }
+    const double c = phi[s];
+    const Stencil st = stencil(c, phi[site_of(p, q.xp, q.y, q.z)], phi[site_of(p, q.xm, q.y, q.z)],
                                phi[site_of(p, q.x, q.yp, q.z)], phi[site_of(p, q.x, q.ym, q.z)],
                                phi[site_of(p, q.x, q.y, q.zp)], phi[site_of(p, q.x, q.y, q.zm)]);
-    g_local<T, REF>(d, pc, g);
+    if (REF) {
+        const double dphi = c - sphic[s];
+#pragma unroll
+        for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, g[i], dphi);
+    }
     collide<T, DEV, REF>(p, f, g, st);
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         dF[i * p.stride + s] = f[i];
-        dG[i * p.stride + s] = g[i];
+        dG[i * p.stride + s] = REF ? to_dest_ref(i, g[i], c, phi[push_site(p, q, i)]) : g[i];
     }
 }
 
@@ -129,17 +129,6 @@ __device__ __forceinline__ int wrapg(int v, int n)
     return v;
 }
 
-// Single-pass step (see the file comment).  Block -> (segment, tile) with
-// an XCD-aware order: consecutive workgroup ids go round-robin over the 8
-// XCDs, so ids are remapped to give each XCD a contiguous run of tiles,
-// y-adjacent tiles first, whose halo rows then meet in the same L2.
-//
-// FP32 mode additionally stages the reference field phi_c of the source
-// level in LDS, one plane per iteration with a 2-site (y, z) halo (the halo
-// ring's own pulls reach 2 sites out), in a 6-slot ring: plane x+3 is
-// prefetched while planes x-1..x+2 are in use.  Each pulled population then
-// costs one FP32 global load; its reference term r_i phi_c(x - c_i) comes
-// from LDS.
 // Addressing: a thread's (y, z) never changes while it marches along x, so
 // the 9 (y - cy, z - cz) byte offsets of its pulls are computed once; a plane
 // and a component each contribute a uniform byte offset.  When a whole
@@ -185,7 +174,16 @@ __device__ __forceinline__ Yz9 yz9(const KParams& p, int y, int z)
     return r;
 }
 
-template <typename T, bool DEV, bool REF, int SY, bool SMALL>
+// Single-pass step (see the file comment).  Block -> (segment, tile) with
+// an XCD-aware order: consecutive workgroup ids go round-robin over the 8
+// XCDs, so ids are remapped to give each XCD a contiguous run of tiles,
+// y-adjacent tiles first, whose halo rows then meet in the same L2.
+//
+// FP32 mode: the pull of a site needs only its own phi_c (one FP64 load per
+// site); the store of direction i needs phi at the destination y + c_i, which
+// the LDS phi ring already holds (its halo then includes the tile's 4 corner
+// cells, for the directions with c_x = 0 and c_y, c_z != 0).
+template <typename T, bool DEV, bool REF, bool SMALL>
 __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg& tc,
                                                 const T* __restrict__ sF,
                                                 const T* __restrict__ sG,
@@ -194,51 +192,44 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
                                                 double* __restrict__ dphic,
                                                 double* __restrict__ partials)
 {
-    constexpr int TY = TYB * SY;  // site rows of the tile
-    constexpr int PCS = REF ? 6 : 1, PCY = REF ? TY + 4 : 1, PCZ = REF ? TZ + 4 : 1;
     __shared__ double ph[4][TY + 2][TZ + 2];
-    __shared__ double pc[PCS][PCY][PCZ];
-    // value kept per direction between the phi pull and the collision:
-    // the stored FP32 deviation (FP32 mode) or the FP64 population
+    // value kept per direction between the phi pull and the collision: the
+    // stored FP32 deviation (FP32 mode) or the FP64 population
     using K = typename std::conditional<REF, T, double>::type;
     const unsigned S = p.stride;
 
     int b = blockIdx.x;
     const int nb = gridDim.x;
-    if (LB_XCD_REMAP && (nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
     const int tile = b % tc.ntiles, seg = b / tc.ntiles;
-    const int y0 = (LB_ZFAST ? tile / tc.ntz : tile % tc.nty) * TY;
-    const int z0 = (LB_ZFAST ? tile % tc.ntz : tile / tc.nty) * TZ;
+    const int y0 = (tile % tc.nty) * TY, z0 = (tile / tc.nty) * TZ;
     const int x0 = seg * tc.sx;
     const int x1 = min(x0 + tc.sx, p.nx);
     const int tya = min(TY, p.ny - y0), tza = min(TZ, p.nz - z0);
-    const int lz = threadIdx.x % TZ, lyb = threadIdx.x / TZ;
-    const int z = z0 + lz;
+    const int lz = threadIdx.x % TZ, ly = threadIdx.x / TZ;
+    const bool active = lz < tza && ly < tya;
     const int plane = p.ny * p.nz;
-    // this thread's rows: ly[k] = lyb + k*TYB
-    int ly[SY];
-    bool active[SY];
-    Yz9 rows[SY];
-#pragma unroll
-    for (int k = 0; k < SY; k++) {
-        ly[k] = lyb + k * TYB;
-        active[k] = lz < tza && ly[k] < tya;
-        rows[k] = yz9<T>(p, active[k] ? y0 + ly[k] : 0, active[k] ? z : 0);
-    }
+    // lanes outside the lattice hold a valid site's offsets and do nothing
+    const Yz9 row = yz9<T>(p, active ? y0 + ly : 0, active ? z0 + lz : 0);
+    const unsigned rowsite = row.o[1][1] / unsigned(sizeof(T));
 
-    // halo ring: rows y0-1 and y0+tya, then columns z0-1 and z0+tza
+    // halo ring: rows y0-1 and y0+tya, columns z0-1 and z0+tza, and in FP32
+    // mode the 4 corners
     const int r = threadIdx.x;
-    const int nring = 2 * tza + 2 * tya;
+    const int nside = 2 * tza + 2 * tya;
+    const int nring = nside + (REF ? 4 : 0);
     const bool ring = r < nring;
     int rly, rlz;
     if (r < tza) { rly = 0; rlz = r + 1; }
     else if (r < 2 * tza) { rly = tya + 1; rlz = r - tza + 1; }
     else if (r < 2 * tza + tya) { rly = r - 2 * tza + 1; rlz = 0; }
-    else { rly = r - 2 * tza - tya + 1; rlz = tza + 1; }
+    else if (r < nside) { rly = r - 2 * tza - tya + 1; rlz = tza + 1; }
+    else { rly = ((r - nside) & 1) ? tya + 1 : 0; rlz = ((r - nside) & 2) ? tza + 1 : 0; }
     const int ry = wrapg(y0 + rly - 1, p.ny), rz = wrapg(z0 + rlz - 1, p.nz);
-    const Yz9 rrow = yz9<T>(p, ry, rz);
+    const Yz9 rrow = yz9<T>(p, ring ? ry : 0, ring ? rz : 0);
+    const unsigned rsite = rrow.o[1][1] / unsigned(sizeof(T));
 
-    // plane indices run from x0-2 to x1+2 (nx may be 1): wrap without
+    // plane indices run from x0-2 to x1+1 (nx may be 1): wrap without
     // division or branches (valid on [-2nx, 4nx))
     auto xw = [&](int X) {
         X += X < 0 ? p.nx : 0;
@@ -250,112 +241,72 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     };
     // byte base of plane X in a T array
     auto pbase = [&](int X) { return unsigned(xw(X) * plane) * unsigned(sizeof(T)); };
-
-    // LDS slot of phi_c plane X is (X - x0 + 2) mod 6; `sl` below is the slot
-    // of a site's own plane and sl +- 1 (mod 6) those of its neighbours
-    auto add6 = [](int a, int d) {
-        const int v = a + d;
-        return v >= PCS ? v - PCS : (v < 0 ? v + PCS : v);
-    };
-    // phi_c plane X into LDS slot `slot`; cell (cy, cz) holds site
-    // (y0 + cy - 2, z0 + cz - 2)
-    auto load_pc = [&](int X, int slot) {
-        if (REF) {
-            const int W = tza + 4, n = W * (tya + 4);
-            const int xx = xw(X);
-            for (int t = threadIdx.x; t < n; t += kBlock) {
-                const int cy = t / W, cz = t - cy * W;
-                pc[REF ? slot : 0][REF ? cy : 0][REF ? cz : 0] =
-                    sphic[site_of(p, xx, wrapg(y0 + cy - 2, p.ny), wrapg(z0 + cz - 2, p.nz))];
-            }
-        }
-    };
-    // g_i at a site as FP64, from the kept value kv of direction i; sl3 are the
-    // slots of the planes X-1, X, X+1 and (cy, cz) the site's phi_c cell
-    auto gval = [&](const int* sl3, int i, int cy, int cz, K kv) -> double {
-        if (REF)
-            return __builtin_fma(rweight(i),
-                                 pc[REF ? sl3[1 - CX[i]] : 0][REF ? cy - CY[i] : 0][REF ? cz - CZ[i] : 0],
-                                 double(kv));
-        return double(kv);
-    };
-    // pull of plane X (slot sl) for a site with row offsets yz: kept values
-    // into kv[] (if non-null), returns phi
-    auto pull_phi = [&](int X, int sl, const Yz9& yz, int cy, int cz, K* kv) -> double {
+    // pull of plane X for a site with row offsets yz and in-plane index
+    // `site`: kept values into kv[] and the site's phi_c into *pc (if
+    // non-null); returns phi
+    auto pull_phi = [&](int X, const Yz9& yz, unsigned site, K* kv, double* pc) -> double {
         const unsigned pb[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
-        const int sl3[3] = {add6(sl, -1), sl, add6(sl, 1)};
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            const unsigned off = pb[1 - CX[i]] + yz.o[1 - CY[i]][1 - CZ[i]];
-            const K v = K(ldc<SMALL>(sG, S, i, off));
+            const K v = K(ldc<SMALL>(sG, S, i, pb[1 - CX[i]] + yz.o[1 - CY[i]][1 - CZ[i]]));
             if (kv) kv[i] = v;
-            acc += gval(sl3, i, cy, cz, v);
+            acc += double(v);
+        }
+        if (REF) {
+            const double c = sphic[pb[1] / unsigned(sizeof(T)) + site];
+            if (pc) *pc = c;
+            return c + acc;
         }
         return acc;
     };
 
-    K kcur[SY][NV], knext[SY][NV];
-    // warm-up: phi_c planes x0-2 .. x0+2, then phi at planes x0-1 (slot 0)
-    // and x0 (slot 1), keeping plane x0's populations
-    for (int X = x0 - 2; X <= x0 + 2; X++) load_pc(X, X - x0 + 2);
-    if (REF) __syncthreads();
-#pragma unroll
-    for (int k = 0; k < SY; k++)
-        if (active[k])
-            ph[0][ly[k] + 1][lz + 1] = pull_phi(x0 - 1, 1, rows[k], ly[k] + 2, lz + 2, nullptr);
-    if (ring) ph[0][rly][rlz] = pull_phi(x0 - 1, 1, rrow, rly + 1, rlz + 1, nullptr);
-#pragma unroll
-    for (int k = 0; k < SY; k++)
-        if (active[k])
-            ph[1][ly[k] + 1][lz + 1] = pull_phi(x0, 2, rows[k], ly[k] + 2, lz + 2, kcur[k]);
-    if (ring) ph[1][rly][rlz] = pull_phi(x0, 2, rrow, rly + 1, rlz + 1, nullptr);
+    K kcur[NV], knext[NV];
+    double pccur = 0.0, pcnext = 0.0;
+    // warm-up: phi at planes x0-1 (slot 0) and x0 (slot 1), keeping plane
+    // x0's populations
+    if (active) ph[0][ly + 1][lz + 1] = pull_phi(x0 - 1, row, rowsite, nullptr, nullptr);
+    if (ring) ph[0][rly][rlz] = pull_phi(x0 - 1, rrow, rsite, nullptr, nullptr);
+    if (active) ph[1][ly + 1][lz + 1] = pull_phi(x0, row, rowsite, kcur, &pccur);
+    if (ring) ph[1][rly][rlz] = pull_phi(x0, rrow, rsite, nullptr, nullptr);
 
     // conserved sums of the source level (FP64), if requested
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
-    int slx = 2;  // phi_c slot of plane x
-    for (int x = x0; x < x1; x++, slx = add6(slx, 1)) {
+    for (int x = x0; x < x1; x++) {
         const int kk = x - x0 + 2;  // phi slot counter of plane x+1
         const int sn = kk & 3, sc = (kk - 1) & 3, sp = (kk - 2) & 3;
-        const int slx3[3] = {add6(slx, -1), slx, add6(slx, 1)};
-        load_pc(x + 3, add6(slx, 3));
         const unsigned pbx[3] = {pbase(x - 1), pbase(x), pbase(x + 1)};
-        T f[SY][NV];
-#pragma unroll
-        for (int k = 0; k < SY; k++) {
-            if (!active[k]) continue;
+        T f[NV];
+        if (active) {
 #pragma unroll
             for (int i = 0; i < NV; i++)
-                f[k][i] = ldc<SMALL>(sF, S, i, pbx[1 - CX[i]] + rows[k].o[1 - CY[i]][1 - CZ[i]]);
+                f[i] = ldc<SMALL>(sF, S, i, pbx[1 - CX[i]] + row.o[1 - CY[i]][1 - CZ[i]]);
+            ph[sn][ly + 1][lz + 1] = pull_phi(x + 1, row, rowsite, knext, &pcnext);
         }
-#pragma unroll
-        for (int k = 0; k < SY; k++)
-            if (active[k])
-                ph[sn][ly[k] + 1][lz + 1] =
-                    pull_phi(x + 1, slx3[2], rows[k], ly[k] + 2, lz + 2, knext[k]);
-        if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, slx3[2], rrow, rly + 1, rlz + 1, nullptr);
+        if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, rrow, rsite, nullptr, nullptr);
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < SY; k++) {
-            if (!active[k]) continue;
-            const int l = ly[k];
-            const double c = ph[sc][l + 1][lz + 1];
-            const Stencil st = stencil(c, ph[sn][l + 1][lz + 1], ph[sp][l + 1][lz + 1],
-                                       ph[sc][l + 2][lz + 1], ph[sc][l][lz + 1],
-                                       ph[sc][l + 1][lz + 2], ph[sc][l + 1][lz]);
+        if (active) {
+            const int psl[3] = {sp, sc, sn};  // phi slots of planes x-1, x, x+1
+            const double c = ph[sc][ly + 1][lz + 1];
+            const Stencil st = stencil(c, ph[sn][ly + 1][lz + 1], ph[sp][ly + 1][lz + 1],
+                                       ph[sc][ly + 2][lz + 1], ph[sc][ly][lz + 1],
+                                       ph[sc][ly + 1][lz + 2], ph[sc][ly + 1][lz]);
             T g[NV];
+            if (REF) {
+                const double dphi = c - pccur;
 #pragma unroll
-            for (int i = 0; i < NV; i++) {
-                const double d = gval(slx3, i, l + 2, lz + 2, kcur[k][i]);
-                g[i] = REF ? T(d - rweight(i) * c) : T(d);
+                for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, T(kcur[i]), dphi);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NV; i++) g[i] = T(kcur[i]);
             }
             if (partials) {
                 // moments of the stored values, formed in FP64
                 double bs = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
                 for (int i = 0; i < NV; i++) {
-                    const double v = double(f[k][i]);
+                    const double v = double(f[i]);
                     bs += v;
                     if (CX[i]) jx += CX[i] * v;
                     if (CY[i]) jy += CY[i] * v;
@@ -367,16 +318,20 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
                 acc[3] += jy;
                 acc[4] += jz;
             }
-            collide<T, DEV, REF>(p, f[k], g, st);
-            const unsigned so = pbx[1] + rows[k].o[1][1];
+            collide<T, DEV, REF>(p, f, g, st);
+            const unsigned so = pbx[1] + row.o[1][1];
 #pragma unroll
             for (int i = 0; i < NV; i++) {
-                stc<SMALL>(dF, S, i, so, f[k][i]);
-                stc<SMALL>(dG, S, i, so, g[i]);
+                stc<SMALL>(dF, S, i, so, f[i]);
+                const T gi = REF ? to_dest_ref(i, g[i], c,
+                                               ph[psl[1 + CX[i]]][ly + 1 + CY[i]][lz + 1 + CZ[i]])
+                                 : g[i];
+                stc<SMALL>(dG, S, i, so, gi);
             }
             if (REF) dphic[so / unsigned(sizeof(T))] = c;
 #pragma unroll
-            for (int i = 0; i < NV; i++) kcur[k][i] = knext[k][i];
+            for (int i = 0; i < NV; i++) kcur[i] = knext[i];
+            pccur = pcnext;
         }
     }
     if (partials) block_partials<5>(acc, partials);
@@ -388,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_step_fused_f32(
     const double* __restrict__ sphic, float* __restrict__ dF, float* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<float, true, true, SY32, SMALL>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
+    step_fused_body<float, true, true, SMALL>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
 }
 
 template <bool SMALL>
@@ -397,8 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_step_fused_f64(
     const double* __restrict__ sphic, double* __restrict__ dF, double* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<double, false, false, SY64, SMALL>(p, tc, sF, sG, sphic, dF, dG, dphic,
-                                                       partials);
+    step_fused_body<double, false, false, SMALL>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
 }
 
 template <typename T>
@@ -501,28 +455,36 @@ __global__ __launch_bounds__(kBlock) void k_export(KParams p, const T* __restric
     }
 }
 
-// Stored value at y is the post-propagation value at y + c_i.  In FP32 mode
-// the reference phi_c(y) is the dense input's sum_i g_i(y).
+// FP32 mode, first half of an import: the reference phi_c(x) = sum_i g_i(x)
+// of the dense post-propagation input.
+__global__ __launch_bounds__(kBlock) void k_import_ref(KParams p, double* __restrict__ phic,
+                                                       const double* __restrict__ g)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; i++) acc += g[(long long)i * p.nsites + s];
+    phic[s] = acc;
+}
+
+// The stored value of direction i at y is the post-propagation value at
+// y + c_i (FP32 mode: minus w_i rho0 for f, minus r_i phi_c(y + c_i) for g).
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_import(KParams p, T* __restrict__ F, T* __restrict__ G,
-                                                   double* __restrict__ phic,
+                                                   const double* __restrict__ phic,
                                                    const double* __restrict__ f,
                                                    const double* __restrict__ g)
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
     const Geo q = geo_of(p, s);
-    double ref = 0.0;
-    if (REF) {
-#pragma unroll
-        for (int i = 0; i < NV; i++) ref += g[(long long)i * p.nsites + s];
-        phic[s] = ref;
-    }
 #pragma unroll
     for (int i = 0; i < NV; i++) {
-        const long long n = push_site(p, q, i) + (long long)i * p.nsites;
+        const int d = push_site(p, q, i);
+        const long long n = d + (long long)i * p.nsites;
         F[i * p.stride + s] = T(f[n] - (DEV ? weight(i) * p.rho0 : 0.0));
-        G[i * p.stride + s] = T(REF ? g[n] - rweight(i) * ref : g[n]);
+        G[i * p.stride + s] = T(REF ? g[n] - rweight(i) * phic[d] : g[n]);
     }
 }
 
@@ -541,11 +503,13 @@ int reduction_grid(const KParams& p)
             using T = float;              \
             constexpr bool DEV = true;    \
             constexpr bool REF = true;    \
+            (void)DEV;                    \
             CALL32;                       \
         } else {                          \
             using T = double;             \
             constexpr bool DEV = false;   \
             constexpr bool REF = false;   \
+            (void)DEV;                    \
             CALL64;                       \
         }                                 \
     } while (0)
@@ -560,17 +524,16 @@ bool small_arrays(const KParams& p, size_t elem)
 
 TileCfg tile_config(const KParams& p, int segment_x, bool fp32)
 {
-    const int ty = TYB * (fp32 ? SY32 : SY64);
     TileCfg tc;
-    tc.nty = (p.ny + ty - 1) / ty;
+    tc.nty = (p.ny + TY - 1) / TY;
     tc.ntz = (p.nz + TZ - 1) / TZ;
     tc.ntiles = tc.nty * tc.ntz;
     int sx = segment_x;
     if (sx <= 0) {
         // measured on MI355X at 256^3: the FP32 kernel wants ~2048 workgroups
-        // (it is latency-bound and needs many in flight); the FP64 kernel
-        // streams best with one workgroup per tile column (~256), i.e. the
-        // fewest concurrent DRAM streams.  Segments of at least 8 planes.
+        // (it needs many in flight); the FP64 kernel streams best with one
+        // workgroup per tile column (~256), i.e. the fewest concurrent DRAM
+        // streams.  Segments of at least 8 planes.
         const long long target = fp32 ? 2048 : 256;
         const long long want = (long long)p.nx * tc.ntiles / target;
         sx = int(want < 8 ? 8 : want);
@@ -679,6 +642,7 @@ hipError_t launch_import(const KParams& p, bool fp32, void* state, const double*
 #define CALL                                                                                  \
     {                                                                                         \
         Lvl<T> a = level<T>(state, p, REF);                                                   \
+        if (REF) k_import_ref<<<grid_for(p), kBlock, 0, s>>>(p, a.phic, g);                   \
         k_import<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, f, g);      \
     }
     LB_DISPATCH(fp32, CALL, CALL);
