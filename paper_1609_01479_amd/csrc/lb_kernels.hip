@@ -30,6 +30,12 @@ namespace {
 // 4 x 128 tiles of 512 threads beat 4 x 64 and 8 x 64; the longer z runs
 // give each component stream 512-byte (FP32) contiguous row pieces).
 constexpr int kFused = 512;
+#ifndef LB_PIPE32
+#define LB_PIPE32 true
+#endif
+#ifndef LB_PIPE64
+#define LB_PIPE64 false
+#endif
 constexpr int TZ = 128;
 constexpr int TY = kFused / TZ;
 // one thread per halo-ring cell (2 rows, 2 columns, 4 corners)
@@ -126,6 +132,33 @@ __global__ __launch_bounds__(kBlock) void k_step_2s(KParams p, const T* __restri
     }
 }
 
+// Register copy the compiler cannot merge away: the source register is free
+// once the copy has executed, so a load issued after it can land in that
+// register.  The memory clobber keeps later loads after the copy.
+__device__ __forceinline__ float vcopy(float v)
+{
+    float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v) : "memory");
+    return r;
+}
+__device__ __forceinline__ double vcopy(double v)
+{
+    double r;
+    asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "v"(v) : "memory");
+    return r;
+}
+
+// Workgroup barrier for LDS traffic only: every wave's LDS writes have
+// completed (lgkmcnt) before any wave passes.  Unlike __syncthreads() it
+// does not first wait for the wave's outstanding global loads and stores,
+// which the single-pass kernel keeps in flight across the barrier (no
+// global data written in a launch is read back in it).  The clobber keeps
+// the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // Wrap a coordinate v in [-2n, 3n) onto [0, n).
 __device__ __forceinline__ int wrapg(int v, int n)
 {
@@ -193,7 +226,7 @@ __device__ __forceinline__ Yz9 yz9(const KParams& p, int y, int z)
 // site); the store of direction i needs phi at the destination y + c_i, which
 // the LDS phi ring already holds (its halo then includes the tile's 4 corner
 // cells, for the directions with c_x = 0 and c_y, c_z != 0).
-template <typename T, bool DEV, bool REF, bool SMALL>
+template <typename T, bool DEV, bool REF, bool SMALL, bool PIPE>
 __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg& tc,
                                                 const T* __restrict__ sF,
                                                 const T* __restrict__ sG,
@@ -224,17 +257,20 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     const unsigned rowsite = row.o[1][1] / unsigned(sizeof(T));
 
     // halo ring: rows y0-1 and y0+tya, columns z0-1 and z0+tza, and in FP32
-    // mode the 4 corners
-    const int r = threadIdx.x;
+    // mode the 4 corners; cell r at LDS position (rly, rlz)
     const int nside = 2 * tza + 2 * tya;
     const int nring = nside + (REF ? 4 : 0);
+    auto ring_cell = [&](int r, int& a, int& c) {
+        if (r < tza) { a = 0; c = r + 1; }
+        else if (r < 2 * tza) { a = tya + 1; c = r - tza + 1; }
+        else if (r < 2 * tza + tya) { a = r - 2 * tza + 1; c = 0; }
+        else if (r < nside) { a = r - 2 * tza - tya + 1; c = tza + 1; }
+        else { a = ((r - nside) & 1) ? tya + 1 : 0; c = ((r - nside) & 2) ? tza + 1 : 0; }
+    };
+    const int r = threadIdx.x;
     const bool ring = r < nring;
     int rly, rlz;
-    if (r < tza) { rly = 0; rlz = r + 1; }
-    else if (r < 2 * tza) { rly = tya + 1; rlz = r - tza + 1; }
-    else if (r < 2 * tza + tya) { rly = r - 2 * tza + 1; rlz = 0; }
-    else if (r < nside) { rly = r - 2 * tza - tya + 1; rlz = tza + 1; }
-    else { rly = ((r - nside) & 1) ? tya + 1 : 0; rlz = ((r - nside) & 2) ? tza + 1 : 0; }
+    ring_cell(r, rly, rlz);
     const int ry = wrapg(y0 + rly - 1, p.ny), rz = wrapg(z0 + rlz - 1, p.nz);
     const Yz9 rrow = yz9<T>(p, ring ? ry : 0, ring ? rz : 0);
     const unsigned rsite = rrow.o[1][1] / unsigned(sizeof(T));
@@ -254,7 +290,8 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     // pull of plane X for a site with row offsets yz and in-plane index
     // `site`: kept values into kv[] and the site's phi_c into *pc (if
     // non-null); returns phi
-    auto pull_phi = [&](int X, const Yz9& yz, unsigned site, K* kv, double* pc) -> double {
+    auto pull_phi = [&](int X, const Yz9& yz, unsigned site, K* kv, double* pc)
+                        __attribute__((always_inline)) -> double {
         const unsigned pb[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
         double acc = 0.0;
 #pragma unroll
@@ -271,77 +308,168 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
         return acc;
     };
 
-    K kcur[NV], knext[NV];
-    double pccur = 0.0, pcnext = 0.0;
-    // warm-up: phi at planes x0-1 (slot 0) and x0 (slot 1), keeping plane
-    // x0's populations
-    if (active) ph[0][ly + 1][lz + 1] = pull_phi(x0 - 1, row, rowsite, nullptr, nullptr);
-    if (ring) ph[0][rly][rlz] = pull_phi(x0 - 1, rrow, rsite, nullptr, nullptr);
-    if (active) ph[1][ly + 1][lz + 1] = pull_phi(x0, row, rowsite, kcur, &pccur);
-    if (ring) ph[1][rly][rlz] = pull_phi(x0, rrow, rsite, nullptr, nullptr);
-
     // conserved sums of the source level (FP64), if requested
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
-    for (int x = x0; x < x1; x++) {
-        const int kk = x - x0 + 2;  // phi slot counter of plane x+1
-        const int sn = kk & 3, sc = (kk - 1) & 3, sp = (kk - 2) & 3;
-        const unsigned pbx[3] = {pbase(x - 1), pbase(x), pbase(x + 1)};
-        T f[NV];
-        if (active) {
+    // collision of this thread's site at plane x and the stores of its new
+    // values, from the pulled f[], the kept g values kc[] (and the site's
+    // phi_c pcc), with phi of planes x-1, x, x+1 in LDS slots sp, sc, sn
+    auto update = [&](int x, T* f, const K* kc, double pcc, int sp, int sc, int sn)
+                      __attribute__((always_inline)) {
+        const int psl[3] = {sp, sc, sn};
+        const double c = ph[sc][ly + 1][lz + 1];
+        const Stencil st = stencil(c, ph[sn][ly + 1][lz + 1], ph[sp][ly + 1][lz + 1],
+                                   ph[sc][ly + 2][lz + 1], ph[sc][ly][lz + 1],
+                                   ph[sc][ly + 1][lz + 2], ph[sc][ly + 1][lz]);
+        T g[NV];
+        if (REF) {
+            const double dphi = c - pcc;
 #pragma unroll
-            for (int i = 0; i < NV; i++)
-                f[i] = ldc<SMALL>(sF, S, i, pbx[1 - CX[i]] + row.o[1 - CY[i]][1 - CZ[i]]);
-            ph[sn][ly + 1][lz + 1] = pull_phi(x + 1, row, rowsite, knext, &pcnext);
+            for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, T(kc[i]), dphi);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; i++) g[i] = T(kc[i]);
         }
-        if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, rrow, rsite, nullptr, nullptr);
-        __syncthreads();
-        if (active) {
-            const int psl[3] = {sp, sc, sn};  // phi slots of planes x-1, x, x+1
-            const double c = ph[sc][ly + 1][lz + 1];
-            const Stencil st = stencil(c, ph[sn][ly + 1][lz + 1], ph[sp][ly + 1][lz + 1],
-                                       ph[sc][ly + 2][lz + 1], ph[sc][ly][lz + 1],
-                                       ph[sc][ly + 1][lz + 2], ph[sc][ly + 1][lz]);
-            T g[NV];
-            if (REF) {
-                const double dphi = c - pccur;
-#pragma unroll
-                for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, T(kcur[i]), dphi);
-            } else {
-#pragma unroll
-                for (int i = 0; i < NV; i++) g[i] = T(kcur[i]);
-            }
-            if (partials) {
-                // moments of the stored values, formed in FP64
-                double bs = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-                for (int i = 0; i < NV; i++) {
-                    const double v = double(f[i]);
-                    bs += v;
-                    if (CX[i]) jx += CX[i] * v;
-                    if (CY[i]) jy += CY[i] * v;
-                    if (CZ[i]) jz += CZ[i] * v;
-                }
-                acc[0] += DEV ? p.rho0 + bs : bs;
-                acc[1] += c;
-                acc[2] += jx;
-                acc[3] += jy;
-                acc[4] += jz;
-            }
-            collide<T, DEV, REF>(p, f, g, st);
-            const unsigned so = pbx[1] + row.o[1][1];
+        if (partials) {
+            // moments of the stored values, formed in FP64
+            double bs = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
             for (int i = 0; i < NV; i++) {
-                stc<SMALL>(dF, S, i, so, f[i]);
-                const T gi = REF ? to_dest_ref(i, g[i], c,
-                                               ph[psl[1 + CX[i]]][ly + 1 + CY[i]][lz + 1 + CZ[i]])
-                                 : g[i];
-                stc<SMALL>(dG, S, i, so, gi);
+                const double v = double(f[i]);
+                bs += v;
+                if (CX[i]) jx += CX[i] * v;
+                if (CY[i]) jy += CY[i] * v;
+                if (CZ[i]) jz += CZ[i] * v;
             }
-            if (REF) dphic[so / unsigned(sizeof(T))] = c;
+            acc[0] += DEV ? p.rho0 + bs : bs;
+            acc[1] += c;
+            acc[2] += jx;
+            acc[3] += jy;
+            acc[4] += jz;
+        }
+        collide<T, DEV, REF>(p, f, g, st);
+        const unsigned so = pbase(x) + row.o[1][1];
 #pragma unroll
-            for (int i = 0; i < NV; i++) kcur[i] = knext[i];
-            pccur = pcnext;
+        for (int i = 0; i < NV; i++) {
+            stc<SMALL>(dF, S, i, so, f[i]);
+            const T gi = REF ? to_dest_ref(i, g[i], c,
+                                           ph[psl[1 + CX[i]]][ly + 1 + CY[i]][lz + 1 + CZ[i]])
+                             : g[i];
+            stc<SMALL>(dG, S, i, so, gi);
+        }
+        if (REF) dphic[so / unsigned(sizeof(T))] = c;
+    };
+
+    // Software-pipelined march (full tiles): the loads of plane x+2's g
+    // (interior and ring) and phi_c and of plane x+1's f are issued before
+    // plane x's collision and stores and consumed one iteration later, so
+    // the workgroup keeps them in flight across its arithmetic and stores.
+    // The path is branch-free -- every lane of a full tile is a site, the
+    // ring cells are spread evenly over all waves (spare lanes repeat a cell
+    // of their wave), the last iteration's prefetch of planes beyond the
+    // segment is issued and left unused -- so the compiler's completion waits
+    // follow the issue order exactly: each wait covers loads issued a whole
+    // iteration earlier, never the stores issued since.
+    const bool full = tya == TY && tza == TZ;
+    if (PIPE && full) {
+        constexpr int NW = kFused / 64;
+        constexpr int RPW = (2 * TZ + 2 * TY + 4 + NW - 1) / NW;  // ring cells per wave
+        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        int qly, qlz;
+        ring_cell(min(w * RPW + (lane < RPW ? lane : 0), nring - 1), qly, qlz);
+        const Yz9 qrow = yz9<T>(p, wrapg(y0 + qly - 1, p.ny), wrapg(z0 + qlz - 1, p.nz));
+        const unsigned qsite = qrow.o[1][1] / unsigned(sizeof(T));
+
+        T fq[NV], fc[NV];
+        K gq[NV], rq[NV], kn[NV], kcur[NV];
+        double pq = 0.0, rpq = 0.0, pcn = 0.0, pccur = 0.0;
+        // g and phi_c of plane X+1 (interior, ring); f(X)
+        auto issue = [&](int X) __attribute__((always_inline)) {
+            const unsigned pf[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
+            const unsigned pg[3] = {pf[1], pf[2], pbase(X + 2)};
+            // issue order fixed (scheduling barriers): interior g, ring g,
+            // f -- the order in which the next iteration consumes them
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < NV; i++)
+                gq[i] = K(ldc<SMALL>(sG, S, i, pg[1 - CX[i]] + row.o[1 - CY[i]][1 - CZ[i]]));
+            if (REF) pq = sphic[pg[1] / unsigned(sizeof(T)) + rowsite];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < NV; i++)
+                rq[i] = K(ldc<SMALL>(sG, S, i, pg[1 - CX[i]] + qrow.o[1 - CY[i]][1 - CZ[i]]));
+            if (REF) rpq = sphic[pg[1] / unsigned(sizeof(T)) + qsite];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < NV; i++)
+                fq[i] = ldc<SMALL>(sF, S, i, pf[1 - CX[i]] + row.o[1 - CY[i]][1 - CZ[i]]);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        ph[0][ly + 1][lz + 1] = pull_phi(x0 - 1, row, rowsite, nullptr, nullptr);
+        ph[0][qly][qlz] = pull_phi(x0 - 1, qrow, qsite, nullptr, nullptr);
+        ph[1][ly + 1][lz + 1] = pull_phi(x0, row, rowsite, kcur, &pccur);
+        ph[1][qly][qlz] = pull_phi(x0, qrow, qsite, nullptr, nullptr);
+        issue(x0);
+        // enter the loop with these loads completed (an empty asm reading
+        // each register makes the compiler wait for it here): the waits at
+        // the loop's top then follow its steady state -- loads issued an
+        // iteration ago, stores issued since -- not this entry path
+#pragma unroll
+        for (int i = 0; i < NV; i++) asm volatile("" ::"v"(gq[i]), "v"(rq[i]), "v"(fq[i]));
+        asm volatile("" ::"v"(pq), "v"(rpq));
+        for (int x = x0; x < x1; x++) {
+            const int kk = x - x0 + 2;  // phi slot counter of plane x+1
+            const int sn = kk & 3, sc = (kk - 1) & 3, sp = (kk - 2) & 3;
+            // phi of plane x+1 from the loads issued one iteration ago, in
+            // the index order every kernel uses
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int i = 0; i < NV; i++) a += double(gq[i]);
+            ph[sn][ly + 1][lz + 1] = REF ? pq + a : a;
+#pragma unroll
+            for (int i = 0; i < NV; i++) b += double(rq[i]);
+            ph[sn][qly][qlz] = REF ? rpq + b : b;
+            lds_barrier();
+#pragma unroll
+            for (int i = 0; i < NV; i++) {
+                fc[i] = vcopy(fq[i]);
+                kn[i] = vcopy(gq[i]);
+            }
+            pcn = vcopy(pq);
+            issue(x + 1);
+            update(x, fc, kcur, pccur, sp, sc, sn);
+#pragma unroll
+            for (int i = 0; i < NV; i++) kcur[i] = kn[i];
+            pccur = pcn;
+        }
+    } else {
+        K kcur[NV], knext[NV];
+        double pccur = 0.0, pcnext = 0.0;
+        // warm-up: phi at planes x0-1 (slot 0) and x0 (slot 1), keeping
+        // plane x0's populations
+        if (active) ph[0][ly + 1][lz + 1] = pull_phi(x0 - 1, row, rowsite, nullptr, nullptr);
+        if (ring) ph[0][rly][rlz] = pull_phi(x0 - 1, rrow, rsite, nullptr, nullptr);
+        if (active) ph[1][ly + 1][lz + 1] = pull_phi(x0, row, rowsite, kcur, &pccur);
+        if (ring) ph[1][rly][rlz] = pull_phi(x0, rrow, rsite, nullptr, nullptr);
+        for (int x = x0; x < x1; x++) {
+            const int kk = x - x0 + 2;  // phi slot counter of plane x+1
+            const int sn = kk & 3, sc = (kk - 1) & 3, sp = (kk - 2) & 3;
+            const unsigned pbx[3] = {pbase(x - 1), pbase(x), pbase(x + 1)};
+            T f[NV];
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < NV; i++)
+                    f[i] = ldc<SMALL>(sF, S, i, pbx[1 - CX[i]] + row.o[1 - CY[i]][1 - CZ[i]]);
+                ph[sn][ly + 1][lz + 1] = pull_phi(x + 1, row, rowsite, knext, &pcnext);
+            }
+            if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, rrow, rsite, nullptr, nullptr);
+            lds_barrier();
+            if (active) {
+                update(x, f, kcur, pccur, sp, sc, sn);
+#pragma unroll
+                for (int i = 0; i < NV; i++) kcur[i] = knext[i];
+                pccur = pcnext;
+            }
         }
     }
     if (partials) block_partials<5, kFused>(acc, partials);
@@ -353,7 +481,7 @@ __global__ __launch_bounds__(kFused) void k_step_fused_f32(
     const double* __restrict__ sphic, float* __restrict__ dF, float* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<float, true, true, SMALL>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
+    step_fused_body<float, true, true, SMALL, LB_PIPE32>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
 }
 
 template <bool SMALL>
@@ -362,7 +490,7 @@ __global__ __launch_bounds__(kFused) void k_step_fused_f64(
     const double* __restrict__ sphic, double* __restrict__ dF, double* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<double, false, false, SMALL>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
+    step_fused_body<double, false, false, SMALL, LB_PIPE64>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
 }
 
 template <typename T>
@@ -436,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_sums_final(const double* __restrict_
         __syncthreads();
         for (int w = kBlock / 2; w > 0; w >>= 1) {
             if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
-            __syncthreads();
+            lds_barrier();
         }
         if (threadIdx.x == 0) out[k] = accumulate ? out[k] + sm[0] : sm[0];
         __syncthreads();

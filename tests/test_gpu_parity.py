@@ -21,10 +21,10 @@ TOL = 1e-12
 NAMES = ("f", "g", "rho", "u", "phi")
 
 
-def _run_both(shape, steps, phi0=None, **kw):
-    print(f"[parity] shape={shape} steps={steps} params={kw}", flush=True)
+def _run_both(shape, steps, phi0=None, precision="fp64", **kw):
+    print(f"[parity] shape={shape} steps={steps} {precision} params={kw}", flush=True)
     phi0 = lbinputs.spinodal_phi0(shape) if phi0 is None else phi0
-    lb = make_lb(shape, **kw)
+    lb = make_lb(shape, precision=precision, **kw)
     lb.init_phi(phi0)
     lb.step(steps)
     got = gpu_state(lb)
@@ -156,11 +156,14 @@ def test_conservation_and_sums_match_oracle():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_dev"])
-def test_kernel_variants_and_segments_agree(prec):
+@pytest.mark.parametrize("shape", [(13, 10, 70), (13, 8, 256)])
+def test_kernel_variants_and_segments_agree(prec, shape):
     """The single-pass kernel is independent of its x-segment length (bit for
     bit: every site's arithmetic is the same), and agrees with the two-pass
-    variant."""
-    shape = (13, 10, 70)
+    variant.  (13, 8, 256) is made of full 4 x 128 tiles only, which the FP32
+    kernel marches with its software-pipelined path; (13, 10, 70) of ragged
+    tiles only."""
+    print(f"[variants] {prec} {shape}", flush=True)
     phi0 = lbinputs.spinodal_phi0(shape, seed=21, amp=0.3)
     out = {}
     for kernel, sx in (("fused", 0), ("fused", 1), ("fused", 3), ("fused", 13), ("two_pass", 0)):
@@ -176,11 +179,27 @@ def test_kernel_variants_and_segments_agree(prec):
     assert max(errs.values()) <= (1e-14 if prec == "fp64" else 1e-6), errs
 
 
+@pytest.mark.parametrize("shape", [(12, 8, 128), (10, 6, 320), (3, 4, 128)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_dev"])
+def test_full_and_mixed_tiles(prec, shape):
+    """Lattices made of full 4 x 128 tiles (the FP32 kernel's pipelined,
+    branch-free march), and of full and ragged tiles in one launch, against
+    the oracle: FP64 to 1e-12, FP32 storage to its rounding."""
+    phi0 = lbinputs.spinodal_phi0(shape, seed=31, amp=0.4)
+    got, ref = _run_both(shape, 20, phi0=phi0, precision=prec, tau_f=0.8, tau_g=1.3)
+    errs = field_errors(got, ref)
+    if prec == "fp64":
+        assert max(errs.values()) <= TOL, errs
+    else:
+        assert errs["phi"] <= 1e-6 and errs["rho"] <= 1e-6 and errs["u"] <= 1e-7, errs
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 1), (2, 2, 2), (1, 1, 300), (1, 7, 1), (2, 3, 1), (3, 5, 131)])
 def test_degenerate_lattices_fp32(shape):
     """FP32 storage on extents 1 and 2 and a ragged tail: the single-pass
-    kernel's LDS reference planes wrap onto themselves; it must agree with the
-    two-pass variant (global reads) and follow the oracle to FP32 rounding."""
+    kernel's LDS phi planes and halo ring wrap onto themselves; it must agree
+    with the two-pass variant (global reads) and follow the oracle to FP32
+    rounding."""
     phi0 = lbinputs.spinodal_phi0(shape, seed=98, amp=0.5)
     out = {}
     for kernel in ("fused", "two_pass"):
