@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--spinodal-steps", type=int, default=1000,
+                    help="steps of the extra 128^3 FP64 spinodal throughput line (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -224,6 +226,22 @@ def main():
                                      "u_max": float(du.max()),
                                      "u_rms": float(np.sqrt((du ** 2).mean()))}
     del runs
+
+    # FP64 on the 128^3 spinodal-decomposition lattice (phi0 ~ U(-0.05, 0.05))
+    if not args.no_fp64 and args.spinodal_steps > 0:
+        sh = (128, 128, 128)
+        lb = LB(sh, precision="fp64", device="cuda:0", **params)
+        lb.init_phi(lbinputs.spinodal_phi0(sh))
+        log(f"fp64 spinodal {sh}: {args.spinodal_steps} steps")
+        ms = time_steps(lb, args.spinodal_steps, args.warmup)
+        t = ms / args.spinodal_steps * 1e-3
+        n128 = 128 ** 3
+        out["fp64_spinodal_128"] = {
+            "value": round(n128 / t / 1e6, 1), "unit": "MLUPS", "steps": args.spinodal_steps,
+            "ms_per_step": round(ms / args.spinodal_steps, 4),
+            "achieved_GBps": round(step_bytes_per_site(8)["kernel"] * n128 / t / 1e9, 1)}
+        del lb
+        torch.cuda.empty_cache()
 
     # the library's streaming copy over 2 GiB (read 1 GiB + write 1 GiB): the
     # practical HBM ceiling, measured in the same job

@@ -191,7 +191,8 @@ lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
  * adjoint buffers (FP64 in LB_FP64, FP32 in LB_FP32_DEV).  For a loss on the
  * final order parameter:
  *   lb_adjoint_seed(dL/dphi_T)  then, for t = T-1 .. 0,
- *   lb_adjoint_step(state_t)    (state_t as saved by lb_get_state at time t)
+ *   lb_adjoint_step(state_t)    (state_t as saved by lb_get_state at time t;
+ *                                or lb_adjoint_step_next with level t+1 too)
  * and lb_adjoint_phi0 gives dL/dphi0.  Requires adj[0], adj[1], adj_scratch. */
 
 /* lambda_T from dphi_dev = dL/dphi_T (FP64, N): dL/dg_i = dphi for every i,
@@ -203,6 +204,16 @@ lb_status lb_adjoint_seed(lb_ctx *ctx, const double *dphi_dev);
  * dtheta3_dev (FP64[3], device) is incremented by the step's contribution to
  * [dL/dA, dL/dB, dL/dkappa]; it may be NULL. */
 lb_status lb_adjoint_step(lb_ctx *ctx, const void *state_t_dev, double *dtheta3_dev);
+
+/* lb_adjoint_step with the level that one step from state_t produced
+ * (state_next_dev, as saved by lb_get_state or written by lb_step_from; may be
+ * NULL).  In LB_FP32_DEV that level's reference field holds phi of state_t,
+ * bit-identical to what the step would recompute, so the phi pass is skipped;
+ * LB_FP64 ignores it.  The result is identical to lb_adjoint_step's only if
+ * state_next_dev really is that level.  LB_EINVAL if it equals state_t_dev,
+ * LB_EALIGN if it is not 256-byte aligned. */
+lb_status lb_adjoint_step_next(lb_ctx *ctx, const void *state_t_dev, const void *state_next_dev,
+                               double *dtheta3_dev);
 
 /* dL/dphi0 (FP64, N) of the initial state built by lb_init_phi, from the
  * current lambda_0. */

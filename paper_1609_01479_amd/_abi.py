@@ -20,7 +20,7 @@ LB_KERNEL_FUSED, LB_KERNEL_TWO_PASS = 0, 1
 # Every symbol include/lb.h declares.
 EXPORTS = ("lb_abi_version", "lb_query_sizes", "lb_create", "lb_destroy", "lb_set_stream",
            "lb_init_phi", "lb_step", "lb_step_sums", "lb_step_from", "lb_moments", "lb_sums", "lb_get_state", "lb_set_state",
-           "lb_export_dist", "lb_import_dist", "lb_adjoint_seed", "lb_adjoint_step",
+           "lb_export_dist", "lb_import_dist", "lb_adjoint_seed", "lb_adjoint_step", "lb_adjoint_step_next",
            "lb_adjoint_phi0", "lb_copy_probe", "lb_status_string", "lb_last_error")
 
 
@@ -84,6 +84,7 @@ def lib():
         "lb_import_dist": ([vp, dp, dp], ctypes.c_int),
         "lb_adjoint_seed": ([vp, dp], ctypes.c_int),
         "lb_adjoint_step": ([vp, vp, dp], ctypes.c_int),
+        "lb_adjoint_step_next": ([vp, vp, vp, dp], ctypes.c_int),
         "lb_adjoint_phi0": ([vp, dp], ctypes.c_int),
         "lb_copy_probe": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "lb_status_string": ([ctypes.c_int], ctypes.c_char_p),

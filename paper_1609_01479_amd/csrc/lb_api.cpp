@@ -294,12 +294,22 @@ lb_status lb_adjoint_seed(lb_ctx* ctx, const double* dphi_dev)
 
 lb_status lb_adjoint_step(lb_ctx* ctx, const void* state_t_dev, double* dtheta3_dev)
 {
+    return lb_adjoint_step_next(ctx, state_t_dev, nullptr, dtheta3_dev);
+}
+
+lb_status lb_adjoint_step_next(lb_ctx* ctx, const void* state_t_dev, const void* state_next_dev,
+                               double* dtheta3_dev)
+{
     if (!ctx || !state_t_dev) return fail(LB_EINVAL, "ctx and state_t_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
     if (!aligned(state_t_dev)) return fail(LB_EALIGN, "state_t_dev is not 256-byte aligned");
+    if (state_next_dev && !aligned(state_next_dev))
+        return fail(LB_EALIGN, "state_next_dev is not 256-byte aligned");
+    if (state_next_dev == state_t_dev)
+        return fail(LB_EINVAL, "state_next_dev must be the level after state_t_dev");
     int nb = 0;
     double* part = static_cast<double*>(ctx->b.scratch);
-    hipError_t e = lbk::launch_adj_step(ctx->kp, ctx->fp32, state_t_dev,
+    hipError_t e = lbk::launch_adj_step(ctx->kp, ctx->fp32, state_t_dev, state_next_dev,
                                         static_cast<double*>(ctx->b.phi),
                                         ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
                                         ctx->b.adj_scratch, part, &nb, ctx->stream);

@@ -90,6 +90,16 @@ __device__ __forceinline__ int push_site(const KParams& p, const Geo& q, int i)
                    plus_c(CZ[i], q.z, q.zm, q.zp));
 }
 
+// Workgroup ids are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  This remaps them so that each XCD receives a contiguous run of ids
+// (when the grid is a multiple of 8): neighbouring sites, whose pulls share
+// cache lines, are then fetched into one L2.
+__device__ __forceinline__ int xcd_block()
+{
+    const int b = blockIdx.x, nb = gridDim.x;
+    return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
+
 // ---------------------------------------------------------------------------
 // Pull of the order-parameter populations.  d[i] = g_i(x) in FP64:
 //   FP64 mode: G_i(x - c_i);  FP32 mode: G_i(x - c_i) + r_i phi_c(x).

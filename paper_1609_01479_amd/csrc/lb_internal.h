@@ -58,9 +58,12 @@ hipError_t launch_import(const KParams& p, bool fp32, void* state, const double*
 // Reverse mode.
 hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, const double* dphi,
                            hipStream_t s);
-hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state, double* phi,
-                           const void* adj_next, void* adj_prev, void* adj_scratch,
-                           double* partials, int* nblocks_out, hipStream_t s);
+// state_next (may be null): the level one step after `state`; in FP32 mode
+// its reference field is phi of `state`, so the phi pass is skipped.
+hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
+                           const void* state_next, double* phi, const void* adj_next,
+                           void* adj_prev, void* adj_scratch, double* partials, int* nblocks_out,
+                           hipStream_t s);
 hipError_t launch_adj_phi0(const KParams& p, bool fp32, const void* adj, double* dphi0,
                            hipStream_t s);
 

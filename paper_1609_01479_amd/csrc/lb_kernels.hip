@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_phi(KParams p, const T* __restrict__
                                                 const double* __restrict__ phic,
                                                 double* __restrict__ phi)
 {
-    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const int s = xcd_block() * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
     phi[s] = phi_at<T, REF>(p, geo_of(p, s), G, phic);
 }
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_step_2s(KParams p, const T* __restri
                                                     const double* __restrict__ phi,
                                                     T* __restrict__ dF, T* __restrict__ dG)
 {
-    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const int s = xcd_block() * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
     const Geo q = geo_of(p, s);
     T f[NV], g[NV];
@@ -241,9 +241,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     using K = typename std::conditional<REF, T, double>::type;
     const unsigned S = p.stride;
 
-    int b = blockIdx.x;
-    const int nb = gridDim.x;
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int b = xcd_block();
     const int tile = b % tc.ntiles, seg = b / tc.ntiles;
     const int y0 = (tile / tc.ntz) * TY, z0 = (tile % tc.ntz) * TZ;
     const int x0 = seg * tc.sx;
@@ -518,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restri
                                                     double* __restrict__ partials)
 {
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int s = blockIdx.x * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
+    for (int s = xcd_block() * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
         const Geo q = geo_of(p, s);
         double fv[NV];
 #pragma unroll
@@ -551,23 +549,34 @@ __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restri
     block_partials<5>(acc, partials);
 }
 
-// out[k] (+)= sum over nblocks partials of component k; one block, fixed order.
+// out[k] (+)= sum over nblocks partials of component k (k < ncomp <= 5); one
+// block, fixed order: strided per-thread sums, a wavefront butterfly, then
+// the 4 waves pairwise.
 __global__ __launch_bounds__(kBlock) void k_sums_final(const double* __restrict__ partials,
                                                        int nblocks, int ncomp,
                                                        double* __restrict__ out, int accumulate)
 {
-    __shared__ double sm[kBlock];
-    for (int k = 0; k < ncomp; k++) {
-        double v = 0.0;
-        for (int j = threadIdx.x; j < nblocks; j += kBlock) v += partials[k * nblocks + j];
-        sm[threadIdx.x] = v;
-        __syncthreads();
-        for (int w = kBlock / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
-            lds_barrier();
-        }
-        if (threadIdx.x == 0) out[k] = accumulate ? out[k] + sm[0] : sm[0];
-        __syncthreads();
+    constexpr int KMAX = 5;
+    __shared__ double sm[KMAX][kBlock / 64];
+    double v[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; k++) {
+        v[k] = 0.0;
+        if (k < ncomp)
+            for (int j = threadIdx.x; j < nblocks; j += kBlock) v[k] += partials[k * nblocks + j];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < KMAX; k++) v[k] += __shfl_xor(v[k], off, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < KMAX; k++) sm[k][threadIdx.x >> 6] = v[k];
+    __syncthreads();
+    if (threadIdx.x < ncomp) {
+        const int k = threadIdx.x;
+        const double t = (sm[k][0] + sm[k][1]) + (sm[k][2] + sm[k][3]);
+        out[k] = accumulate ? out[k] + t : t;
     }
 }
 

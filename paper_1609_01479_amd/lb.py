@@ -195,8 +195,14 @@ class LB:
         self._call("lb_adjoint_seed", _ptr(t))
         t.record_stream(self.stream)
 
-    def adjoint_step(self, state_t: torch.Tensor, dtheta: torch.Tensor | None = None) -> None:
-        self._call("lb_adjoint_step", _ptr(state_t), _ptr(dtheta))
+    def adjoint_step(self, state_t: torch.Tensor, dtheta: torch.Tensor | None = None,
+                     next_state: torch.Tensor | None = None) -> None:
+        """One reverse step at state_t; next_state, the level one step later,
+        lets FP32 storage skip recomputing phi (lb_adjoint_step_next)."""
+        if next_state is None:
+            self._call("lb_adjoint_step", _ptr(state_t), _ptr(dtheta))
+        else:
+            self._call("lb_adjoint_step_next", _ptr(state_t), _ptr(next_state), _ptr(dtheta))
 
     def adjoint_phi0(self) -> torch.Tensor:
         out = self._out(*self.shape)

@@ -65,7 +65,13 @@ class _Rollout(torch.autograd.Function):
             for j in range(1, t1 - t0):
                 lb.step_from(seg[j - 1], seg[j])
             for t in reversed(range(t0, t1)):
-                lb.adjoint_step(seg[t - t0], dtheta)
+                # level t+1: the next buffer of this segment, else the next
+                # segment's checkpoint (none after the last step)
+                if t + 1 < t1:
+                    nxt = seg[t + 1 - t0]
+                else:
+                    nxt = ckpts[si + 1] if si + 1 < len(ckpts) else None
+                lb.adjoint_step(seg[t - t0], dtheta, next_state=nxt)
         dphi0 = lb.adjoint_phi0()
         ctx.lb = None
         ctx.ckpts = None

@@ -103,6 +103,31 @@ def test_create_validates_buffers_without_launching(abi):
     L.lb_destroy(None)
 
 
+def test_adjoint_step_next_validates_without_launching(abi):
+    """lb_adjoint_step_next rejects a missing adjoint, a successor equal to
+    state_t and a misaligned successor before any HIP call."""
+    L = abi.lib()
+    p = _params(abi)
+    ctx = ctypes.c_void_p()
+    b = abi.LbBuffers()
+    b.state[0], b.state[1], b.phi, b.scratch = 0x1000, 0x2000, 0x3000, 0x4000
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
+    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000),
+                                  None) == abi.LB_ESTATE
+    L.lb_destroy(ctx)
+    b.adj[0], b.adj[1], b.adj_scratch = 0x5000, 0x6000, 0x7000
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
+    assert L.lb_adjoint_step_next(None, ctypes.c_void_p(0x1000), None, None) == abi.LB_EINVAL
+    assert L.lb_adjoint_step_next(ctx, None, ctypes.c_void_p(0x2000), None) == abi.LB_EINVAL
+    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000),
+                                  None) == abi.LB_EINVAL
+    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2010),
+                                  None) == abi.LB_EALIGN
+    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1010), ctypes.c_void_p(0x2000),
+                                  None) == abi.LB_EALIGN
+    L.lb_destroy(ctx)
+
+
 def test_status_strings(abi):
     L = abi.lib()
     for code in range(6):

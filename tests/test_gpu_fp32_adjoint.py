@@ -126,3 +126,32 @@ def test_adjoint_fp32_close_to_fp64():
     assert e_phi <= 1e-4
     for a, b in zip(g32[2:], g64[2:]):
         assert abs(a - b) <= 1e-3 * abs(b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("shape", [(6, 5, 7), (5, 4, 128)])
+def test_adjoint_step_next_bit_exact(prec, shape):
+    """lb_adjoint_step_next (phi of level t taken from level t+1's reference
+    field in FP32 storage) gives bit-identical adjoint levels and parameter
+    gradients to lb_adjoint_step (phi recomputed), over 6 reverse steps.
+    (5, 4, 128) is made of one full tile, which the FP32 kernel marches with
+    its pipelined path."""
+    print(f"[adjoint next] {prec} {shape}", flush=True)
+    T = 6
+    phi0 = lbinputs.spinodal_phi0(shape, seed=5, amp=0.3)
+    dphi = torch.tensor(lbinputs.random_field(shape, 9), device="cuda:0")
+    lb = make_lb(shape, precision=prec, adjoint=True, tau_f=0.8, tau_g=1.3)
+    lb.init_phi(phi0)
+    states = [lb.get_state()]
+    for _ in range(T):
+        lb.step(1)
+        states.append(lb.get_state())
+    out = []
+    for use_next in (False, True):
+        dth = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+        lb.adjoint_seed(dphi)
+        for t in reversed(range(T)):
+            lb.adjoint_step(states[t], dth, next_state=states[t + 1] if use_next else None)
+        out.append((lb.adjoint_phi0().cpu().numpy(), dth.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
