@@ -52,11 +52,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(KParams p, T* __restrict__ 
 // from the saved state; writes lf, lg of the previous level, the stencil
 // cotangents, and block partials of d/d(A, B, kappa).
 template <typename T, bool DEV>
-__global__ __launch_bounds__(kBlock) void k_adj_local(KParams p, const T* __restrict__ F,
-                                                      const double* __restrict__ phi,
-                                                      const T* __restrict__ an,
-                                                      T* __restrict__ ap, T* __restrict__ sc,
-                                                      double* __restrict__ partials)
+__device__ __forceinline__ void adj_local_body(const KParams& p, const T* __restrict__ F,
+                                               const double* __restrict__ phi,
+                                               const T* __restrict__ an, T* __restrict__ ap,
+                                               T* __restrict__ sc, double* __restrict__ partials)
 {
     double dth[3] = {0.0, 0.0, 0.0};
     const unsigned S = p.stride;
@@ -150,6 +149,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_local(KParams p, const T* __rest
     block_partials<3>(dth, partials);
 }
 
+// FP32 storage: one load or store instruction moves 256 bytes per wavefront,
+// so the kernel needs many waves in flight; 4 per SIMD (at most 128 VGPRs)
+// measured 13% faster than the 3 its natural allocation allows.  FP64 keeps
+// its full register allocation (capping it spills).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adj_local_f32(
+    KParams p, const float* __restrict__ F, const double* __restrict__ phi,
+    const float* __restrict__ an, float* __restrict__ ap, float* __restrict__ sc,
+    double* __restrict__ partials)
+{
+    adj_local_body<float, true>(p, F, phi, an, ap, sc, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_local_f64(
+    KParams p, const double* __restrict__ F, const double* __restrict__ phi,
+    const double* __restrict__ an, double* __restrict__ ap, double* __restrict__ sc,
+    double* __restrict__ partials)
+{
+    adj_local_body<double, false>(p, F, phi, an, ap, sc, partials);
+}
+
 // lp(x) = a(x) - sum_a D_a b_a (x) + lap c (x)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_stencil(KParams p, const T* __restrict__ sc,
@@ -218,14 +237,14 @@ hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
     const int nb = reduction_grid(p);
     *nblocks_out = nb;
     if (fp32) {
-        k_adj_local<float, true><<<nb, kBlock, 0, s>>>(p, static_cast<const float*>(state), phi,
+        k_adj_local_f32<<<nb, kBlock, 0, s>>>(p, static_cast<const float*>(state), phi,
                                                        static_cast<const float*>(adj_next),
                                                        static_cast<float*>(adj_prev),
                                                        static_cast<float*>(adj_scratch), partials);
         k_adj_stencil<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const float*>(adj_scratch),
                                                             static_cast<float*>(adj_prev));
     } else {
-        k_adj_local<double, false><<<nb, kBlock, 0, s>>>(p, static_cast<const double*>(state), phi,
+        k_adj_local_f64<<<nb, kBlock, 0, s>>>(p, static_cast<const double*>(state), phi,
                                                          static_cast<const double*>(adj_next),
                                                          static_cast<double*>(adj_prev),
                                                          static_cast<double*>(adj_scratch), partials);
