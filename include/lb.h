@@ -83,8 +83,10 @@ typedef enum {
     LB_KERNEL_TWO_PASS = 1 /* a phi pass, then the stencil/collision pass  */
 } lb_kernel;
 
-/* Lattice and model.  nx, ny, nz >= 1 with nx*ny*nz < 2^31 (periodic in all
- * three directions); tau_f, tau_g > 1/2; rho0 > 0. */
+/* Lattice and model.  nx, ny, nz >= 1 (periodic in all three directions),
+ * N = nx*ny*nz below ~1.1e8 sites (39 * stride_elems < 2^32) and one x-plane
+ * of f below 4 GiB (ny*nz*19*elem_bytes < 2^32), else LB_ESHAPE;
+ * tau_f, tau_g > 1/2; rho0 > 0. */
 typedef struct {
     int32_t nx, ny, nz;
     double A, B, kappa; /* free energy A/2 phi^2 + B/4 phi^4 + kappa/2 |grad phi|^2 */
@@ -99,7 +101,7 @@ typedef struct {
 /* Sizes in bytes of the caller-owned device buffers (lb_query_sizes). */
 typedef struct {
     size_t elem_bytes;        /* 8 (LB_FP64) or 4 (LB_FP32_DEV)                         */
-    size_t stride_elems;      /* padded per-component stride of a distribution          */
+    size_t stride_elems;      /* padded elements per component of a distribution        */
     size_t state_bytes;       /* one time level: f, g (2*19*stride elements) and, in
                                  LB_FP32_DEV, phi_c (stride FP64 values)                */
     size_t phi_bytes;         /* FP64 order-parameter work field                        */

@@ -67,7 +67,7 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
             const int d = push_site(p, q, i);
             lf[i] = an[i * S + d];
             lg[i] = an[(NV + i) * S + d] + an[2 * NV * S + d];
-            f[i] = F[i * S + pull_site(p, q, i)];
+            f[i] = F[dist_pull(p, q, i)];
         }
         const Stencil st = stencil(phi[s], phi[site_of(p, q.xp, q.y, q.z)],
                                    phi[site_of(p, q.xm, q.y, q.z)],

@@ -35,11 +35,11 @@ constexpr size_t kAlign = 256;
 constexpr int kAdjComponents = 2 * LB_NVEL + 1;  // lambda_f, lambda_g, lambda_phi
 constexpr int kAdjScratchComponents = 5;         // a, b_x, b_y, b_z, c
 
-// Per-component stride: N rounded up to 256 elements, plus a 4352-element
-// (4096 + 256) skew so the component streams of a kernel do not start at the
-// same offset modulo large powers of two (HBM channel and bank interleave).
-// Measured on MI355X at 256^3: 2-4% faster steps than a 256-element skew or
-// none.
+// Elements per component in a time level: N rounded up to 256, plus 4352
+// (4096 + 256) of padding between the f region, the g region and phi_c, so
+// those streams do not start at the same offset modulo large powers of two
+// (HBM channel and bank interleave; measured on MI355X with one array per
+// component, 2-4% faster than 256 or none).
 size_t stride_for(long long n)
 {
     const size_t r = (size_t(n) + 255) / 256 * 256;
@@ -58,6 +58,12 @@ lb_status validate(const lb_params* p)
     // up to 39 components (an adjoint level)
     if ((long long)(stride_for(n)) * 39 >= (1LL << 32))
         return fail(LB_ESHAPE, "lattice of %lld sites is too large (limit ~1.1e8 sites)", n);
+    // one x-plane of the row-blocked f or g region is addressed with 32-bit
+    // byte offsets (FP64: ny*nz < ~2.8e7)
+    const long long elem = p->precision == LB_FP32_DEV ? 4 : 8;
+    if ((long long)p->ny * p->nz * LB_NVEL * elem >= (1LL << 32))
+        return fail(LB_ESHAPE, "x-plane of %lld sites is too large (ny*nz*19*%lld bytes >= 4 GiB)",
+                    (long long)p->ny * p->nz, elem);
     if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5))
         return fail(LB_EINVAL, "tau_f and tau_g must exceed 1/2 (got %g, %g)", p->tau_f, p->tau_g);
     if (!(p->rho0 > 0.0)) return fail(LB_EINVAL, "rho0 must be positive (got %g)", p->rho0);

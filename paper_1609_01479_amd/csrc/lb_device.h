@@ -19,6 +19,8 @@
 //   in the bulk phases, so FP32 rounding does not accumulate into the O(1)
 //   order parameter.
 // Post-propagation values at x are the pull  f_i(x) = f*_i(x - c_i).
+// Memory layout of F and G: didx() below; phi_c is one value per site in
+// site order (x*ny + y)*nz + z.
 #pragma once
 
 #include "lb_internal.h"
@@ -100,6 +102,27 @@ __device__ __forceinline__ int xcd_block()
     return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
 }
 
+// Distribution layout of a time level: F and G are each row-blocked -- for
+// every (x, y) row the 19 components' z-runs follow one another, element
+// (i, x, y, z) at ((x*ny + y)*19 + i)*nz + z.  A workgroup's accesses to one
+// plane then fall in a few long contiguous stretches (measured on MI355X:
+// 4-7% faster steps than one array per component).  Indices fit 32 bits
+// (19 N < 2^32 is checked at creation).
+__device__ __forceinline__ unsigned didx(const KParams& p, int i, int x, int y, int z)
+{
+    return (unsigned(x * p.ny + y) * unsigned(NV) + unsigned(i)) * unsigned(p.nz) + unsigned(z);
+}
+// component i at x - c_i, at x itself, at x + c_i
+__device__ __forceinline__ unsigned dist_pull(const KParams& p, const Geo& q, int i)
+{
+    return didx(p, i, minus_c(CX[i], q.x, q.xm, q.xp), minus_c(CY[i], q.y, q.ym, q.yp),
+                minus_c(CZ[i], q.z, q.zm, q.zp));
+}
+__device__ __forceinline__ unsigned dist_own(const KParams& p, const Geo& q, int i)
+{
+    return didx(p, i, q.x, q.y, q.z);
+}
+
 // ---------------------------------------------------------------------------
 // Pull of the order-parameter populations.  d[i] = g_i(x) in FP64:
 //   FP64 mode: G_i(x - c_i);  FP32 mode: G_i(x - c_i) + r_i phi_c(x).
@@ -115,7 +138,7 @@ __device__ __forceinline__ double pull_g(const KParams& p, const Geo& q, const T
     const double pc = REF ? phic[site_of(p, q.x, q.y, q.z)] : 0.0;
 #pragma unroll
     for (int i = 0; i < NV; i++) {
-        const double gv = double(G[i * p.stride + pull_site(p, q, i)]);
+        const double gv = double(G[dist_pull(p, q, i)]);
         if (d) d[i] = REF ? __builtin_fma(rweight(i), pc, gv) : gv;
         acc += gv;
     }

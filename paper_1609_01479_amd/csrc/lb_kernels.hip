@@ -74,12 +74,13 @@ __global__ __launch_bounds__(kBlock) void k_init(KParams p, T* __restrict__ F, T
     const Geo q = geo_of(p, s);
 #pragma unroll
     for (int i = 0; i < NV; i++) {
-        F[i * p.stride + s] = DEV ? T(0) : T(weight(i) * p.rho0);
+        const unsigned d = dist_own(p, q, i);
+        F[d] = DEV ? T(0) : T(weight(i) * p.rho0);
         if (REF) {
             const double pd = phi0[push_site(p, q, i)];
-            G[i * p.stride + s] = T((i == 0 ? pd : 0.0) - rweight(i) * pd);
+            G[d] = T((i == 0 ? pd : 0.0) - rweight(i) * pd);
         } else {
-            G[i * p.stride + s] = i == 0 ? T(phi0[s]) : T(0);
+            G[d] = i == 0 ? T(phi0[s]) : T(0);
         }
     }
     if (REF) phic[s] = phi0[s];
@@ -112,8 +113,8 @@ __global__ __launch_bounds__(kBlock) void k_step_2s(KParams p, const T* __restri
     T f[NV], g[NV];
 #pragma unroll
     for (int i = 0; i < NV; i++) {
-        f[i] = sF[i * p.stride + pull_site(p, q, i)];
-        g[i] = sG[i * p.stride + pull_site(p, q, i)];
+        f[i] = sF[dist_pull(p, q, i)];
+        g[i] = sG[dist_pull(p, q, i)];
     }
     const double c = phi[s];
     const Stencil st = stencil(c, phi[site_of(p, q.xp, q.y, q.z)], phi[site_of(p, q.xm, q.y, q.z)],
@@ -127,8 +128,8 @@ __global__ __launch_bounds__(kBlock) void k_step_2s(KParams p, const T* __restri
     collide<T, DEV, REF>(p, f, g, st);
 #pragma unroll
     for (int i = 0; i < NV; i++) {
-        dF[i * p.stride + s] = f[i];
-        dG[i * p.stride + s] = REF ? to_dest_ref(i, g[i], c, phi[push_site(p, q, i)]) : g[i];
+        dF[dist_own(p, q, i)] = f[i];
+        dG[dist_own(p, q, i)] = REF ? to_dest_ref(i, g[i], c, phi[push_site(p, q, i)]) : g[i];
     }
 }
 
@@ -167,38 +168,41 @@ __device__ __forceinline__ int wrapg(int v, int n)
     return v;
 }
 
-// Addressing: a thread's (y, z) never changes while it marches along x, so
-// the 9 (y - cy, z - cz) byte offsets of its pulls are computed once; a plane
-// and a component each contribute a uniform byte offset.  When a whole
-// 19-component array is smaller than 4 GiB (SMALL) one 32-bit byte offset
-// per load (component + plane + row) on a single base pointer suffices;
-// larger lattices keep a uniform base pointer per component instead.
+// Addressing (row-blocked layout, didx()): a thread's (y, z) never changes
+// while it marches along x, so the byte offsets of the 9 rows/columns
+// (y - cy, z - cz) within a plane are computed once (32-bit: one plane of F
+// or G is under 4 GiB, checked at creation); a component (nz elements) adds a
+// uniform in-plane offset and a plane (ny*19*nz elements) a uniform plane
+// offset -- 32-bit when the whole F or G region is under 4 GiB (SMALL), else
+// 64-bit, added to the base pointer.
+template <bool SMALL>
+using OffT = typename std::conditional<SMALL, unsigned, size_t>::type;
+
 template <bool SMALL, typename T>
-__device__ __forceinline__ T ldc(const T* __restrict__ base, unsigned stride, int i, unsigned off)
+__device__ __forceinline__ T ldc(const T* __restrict__ base, OffT<SMALL> pl, int i,
+                                 unsigned compb, unsigned row)
 {
-    if (SMALL) {
-        const unsigned o = unsigned(i) * stride * unsigned(sizeof(T)) + off;
-        return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + o);
-    }
-    const char* b = reinterpret_cast<const char*>(base + size_t(i) * stride);
-    return *reinterpret_cast<const T*>(b + off);
+    const char* b = reinterpret_cast<const char*>(base);
+    if (SMALL) return *reinterpret_cast<const T*>(b + (unsigned(pl) + unsigned(i) * compb + row));
+    // uniform 64-bit pointer to the component's run in the plane, then the row
+    const char* bi = b + (size_t(pl) + size_t(i) * compb);
+    return *reinterpret_cast<const T*>(bi + row);
 }
 // Stores are non-temporal: the new level is not read again in this launch,
 // so it should not displace the source lines that neighbouring tiles still
 // pull through L2.
 template <bool SMALL, typename T>
-__device__ __forceinline__ void stc(T* __restrict__ base, unsigned stride, int i, unsigned off, T v)
+__device__ __forceinline__ void stc(T* __restrict__ base, OffT<SMALL> pl, int i, unsigned compb,
+                                    unsigned row, T v)
 {
-    if (SMALL) {
-        const unsigned o = unsigned(i) * stride * unsigned(sizeof(T)) + off;
-        __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + o));
-        return;
-    }
-    char* b = reinterpret_cast<char*>(base + size_t(i) * stride);
-    __builtin_nontemporal_store(v, reinterpret_cast<T*>(b + off));
+    char* b = reinterpret_cast<char*>(base);
+    T* q = SMALL ? reinterpret_cast<T*>(b + (unsigned(pl) + unsigned(i) * compb + row))
+                 : reinterpret_cast<T*>((b + (size_t(pl) + size_t(i) * compb)) + row);
+    __builtin_nontemporal_store(v, q);
 }
 
-// byte offsets of the 9 rows/columns (y + dy, z + dz), dy, dz in {-1, 0, 1}
+// byte offsets of the 9 rows/columns (y + dy, z + dz), dy, dz in {-1, 0, 1},
+// within a plane of a row-blocked F or G region
 struct Yz9 {
     unsigned o[3][3];
 };
@@ -211,7 +215,9 @@ __device__ __forceinline__ Yz9 yz9(const KParams& p, int y, int z)
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
-        for (int c = 0; c < 3; c++) r.o[a][c] = unsigned(ys[a] * p.nz + zs[c]) * unsigned(sizeof(T));
+        for (int c = 0; c < 3; c++)
+            r.o[a][c] = (unsigned(ys[a]) * unsigned(NV) * unsigned(p.nz) + unsigned(zs[c])) *
+                        unsigned(sizeof(T));
     return r;
 }
 
@@ -239,7 +245,9 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     // value kept per direction between the phi pull and the collision: the
     // stored FP32 deviation (FP32 mode) or the FP64 population
     using K = typename std::conditional<REF, T, double>::type;
-    const unsigned S = p.stride;
+    using O = OffT<SMALL>;
+    const unsigned compb = unsigned(p.nz) * unsigned(sizeof(T));  // one component's z-run
+    const O planeb = O(p.ny) * O(NV) * O(p.nz) * O(sizeof(T));    // one plane of F or G
 
     const int b = xcd_block();
     const int tile = b % tc.ntiles, seg = b / tc.ntiles;
@@ -250,9 +258,11 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     const int lz = threadIdx.x % TZ, ly = threadIdx.x / TZ;
     const bool active = lz < tza && ly < tya;
     const int plane = p.ny * p.nz;
-    // lanes outside the lattice hold a valid site's offsets and do nothing
-    const Yz9 row = yz9<T>(p, active ? y0 + ly : 0, active ? z0 + lz : 0);
-    const unsigned rowsite = row.o[1][1] / unsigned(sizeof(T));
+    // lanes outside the lattice hold a valid site's offsets and do nothing;
+    // rowsite is the in-plane site index (for phi_c)
+    const int sy = active ? y0 + ly : 0, sz = active ? z0 + lz : 0;
+    const Yz9 row = yz9<T>(p, sy, sz);
+    const unsigned rowsite = unsigned(sy * p.nz + sz);
 
     // halo ring: rows y0-1 and y0+tya, columns z0-1 and z0+tza, and in FP32
     // mode the 4 corners; cell r at LDS position (rly, rlz)
@@ -271,7 +281,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     ring_cell(r, rly, rlz);
     const int ry = wrapg(y0 + rly - 1, p.ny), rz = wrapg(z0 + rlz - 1, p.nz);
     const Yz9 rrow = yz9<T>(p, ring ? ry : 0, ring ? rz : 0);
-    const unsigned rsite = rrow.o[1][1] / unsigned(sizeof(T));
+    const unsigned rsite = unsigned((ring ? ry : 0) * p.nz + (ring ? rz : 0));
 
     // plane indices run from x0-2 to x1+1 (nx may be 1): wrap without
     // division or branches (valid on [-2nx, 4nx))
@@ -283,23 +293,24 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
         X -= X >= p.nx ? p.nx : 0;
         return X;
     };
-    // byte base of plane X in a T array
-    auto pbase = [&](int X) { return unsigned(xw(X) * plane) * unsigned(sizeof(T)); };
+    // byte base of plane X in F or G; element base of plane X in phi_c
+    auto pbase = [&](int X) { return O(xw(X)) * planeb; };
+    auto pcbase = [&](int X) { return unsigned(xw(X) * plane); };
     // pull of plane X for a site with row offsets yz and in-plane index
     // `site`: kept values into kv[] and the site's phi_c into *pc (if
     // non-null); returns phi
     auto pull_phi = [&](int X, const Yz9& yz, unsigned site, K* kv, double* pc)
                         __attribute__((always_inline)) -> double {
-        const unsigned pb[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
+        const O pb[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            const K v = K(ldc<SMALL>(sG, S, i, pb[1 - CX[i]] + yz.o[1 - CY[i]][1 - CZ[i]]));
+            const K v = K(ldc<SMALL>(sG, pb[1 - CX[i]], i, compb, yz.o[1 - CY[i]][1 - CZ[i]]));
             if (kv) kv[i] = v;
             acc += double(v);
         }
         if (REF) {
-            const double c = sphic[pb[1] / unsigned(sizeof(T)) + site];
+            const double c = sphic[pcbase(X) + site];
             if (pc) *pc = c;
             return c + acc;
         }
@@ -346,16 +357,17 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
             acc[4] += jz;
         }
         collide<T, DEV, REF>(p, f, g, st);
-        const unsigned so = pbase(x) + row.o[1][1];
+        const O pso = pbase(x);
+        const unsigned so = row.o[1][1];
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            stc<SMALL>(dF, S, i, so, f[i]);
+            stc<SMALL>(dF, pso, i, compb, so, f[i]);
             const T gi = REF ? to_dest_ref(i, g[i], c,
                                            ph[psl[1 + CX[i]]][ly + 1 + CY[i]][lz + 1 + CZ[i]])
                              : g[i];
-            stc<SMALL>(dG, S, i, so, gi);
+            stc<SMALL>(dG, pso, i, compb, so, gi);
         }
-        if (REF) dphic[so / unsigned(sizeof(T))] = c;
+        if (REF) dphic[pcbase(x) + rowsite] = c;
     };
 
     // Software-pipelined march (full tiles): the loads of plane x+2's g
@@ -375,32 +387,33 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
         const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
         int qly, qlz;
         ring_cell(min(w * RPW + (lane < RPW ? lane : 0), nring - 1), qly, qlz);
-        const Yz9 qrow = yz9<T>(p, wrapg(y0 + qly - 1, p.ny), wrapg(z0 + qlz - 1, p.nz));
-        const unsigned qsite = qrow.o[1][1] / unsigned(sizeof(T));
+        const int qy = wrapg(y0 + qly - 1, p.ny), qz = wrapg(z0 + qlz - 1, p.nz);
+        const Yz9 qrow = yz9<T>(p, qy, qz);
+        const unsigned qsite = unsigned(qy * p.nz + qz);
 
         T fq[NV], fc[NV];
         K gq[NV], rq[NV], kn[NV], kcur[NV];
         double pq = 0.0, rpq = 0.0, pcn = 0.0, pccur = 0.0;
         // g and phi_c of plane X+1 (interior, ring); f(X)
         auto issue = [&](int X) __attribute__((always_inline)) {
-            const unsigned pf[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
-            const unsigned pg[3] = {pf[1], pf[2], pbase(X + 2)};
+            const O pf[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
+            const O pg[3] = {pf[1], pf[2], pbase(X + 2)};
             // issue order fixed (scheduling barriers): interior g, ring g,
             // f -- the order in which the next iteration consumes them
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < NV; i++)
-                gq[i] = K(ldc<SMALL>(sG, S, i, pg[1 - CX[i]] + row.o[1 - CY[i]][1 - CZ[i]]));
-            if (REF) pq = sphic[pg[1] / unsigned(sizeof(T)) + rowsite];
+                gq[i] = K(ldc<SMALL>(sG, pg[1 - CX[i]], i, compb, row.o[1 - CY[i]][1 - CZ[i]]));
+            if (REF) pq = sphic[pcbase(X + 1) + rowsite];
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < NV; i++)
-                rq[i] = K(ldc<SMALL>(sG, S, i, pg[1 - CX[i]] + qrow.o[1 - CY[i]][1 - CZ[i]]));
-            if (REF) rpq = sphic[pg[1] / unsigned(sizeof(T)) + qsite];
+                rq[i] = K(ldc<SMALL>(sG, pg[1 - CX[i]], i, compb, qrow.o[1 - CY[i]][1 - CZ[i]]));
+            if (REF) rpq = sphic[pcbase(X + 1) + qsite];
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < NV; i++)
-                fq[i] = ldc<SMALL>(sF, S, i, pf[1 - CX[i]] + row.o[1 - CY[i]][1 - CZ[i]]);
+                fq[i] = ldc<SMALL>(sF, pf[1 - CX[i]], i, compb, row.o[1 - CY[i]][1 - CZ[i]]);
             __builtin_amdgcn_sched_barrier(0);
         };
         ph[0][ly + 1][lz + 1] = pull_phi(x0 - 1, row, rowsite, nullptr, nullptr);
@@ -452,12 +465,12 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
         for (int x = x0; x < x1; x++) {
             const int kk = x - x0 + 2;  // phi slot counter of plane x+1
             const int sn = kk & 3, sc = (kk - 1) & 3, sp = (kk - 2) & 3;
-            const unsigned pbx[3] = {pbase(x - 1), pbase(x), pbase(x + 1)};
+            const O pbx[3] = {pbase(x - 1), pbase(x), pbase(x + 1)};
             T f[NV];
             if (active) {
 #pragma unroll
                 for (int i = 0; i < NV; i++)
-                    f[i] = ldc<SMALL>(sF, S, i, pbx[1 - CX[i]] + row.o[1 - CY[i]][1 - CZ[i]]);
+                    f[i] = ldc<SMALL>(sF, pbx[1 - CX[i]], i, compb, row.o[1 - CY[i]][1 - CZ[i]]);
                 ph[sn][ly + 1][lz + 1] = pull_phi(x + 1, row, rowsite, knext, &pcnext);
             }
             if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, rrow, rsite, nullptr, nullptr);
@@ -520,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restri
         const Geo q = geo_of(p, s);
         double fv[NV];
 #pragma unroll
-        for (int i = 0; i < NV; i++) fv[i] = double(F[i * p.stride + pull_site(p, q, i)]);
+        for (int i = 0; i < NV; i++) fv[i] = double(F[dist_pull(p, q, i)]);
         const double ph = phi_at<T, REF>(p, q, G, phic);
         double b = 0.0;
 #pragma unroll
@@ -593,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_export(KParams p, const T* __restric
 #pragma unroll
         for (int i = 0; i < NV; i++)
             f[(long long)i * p.nsites + s] =
-                double(F[i * p.stride + pull_site(p, q, i)]) + (DEV ? weight(i) * p.rho0 : 0.0);
+                double(F[dist_pull(p, q, i)]) + (DEV ? weight(i) * p.rho0 : 0.0);
     if (g) {
         double d[NV];
         pull_g<T, REF>(p, q, G, phic, d);
@@ -630,8 +643,8 @@ __global__ __launch_bounds__(kBlock) void k_import(KParams p, T* __restrict__ F,
     for (int i = 0; i < NV; i++) {
         const int d = push_site(p, q, i);
         const long long n = d + (long long)i * p.nsites;
-        F[i * p.stride + s] = T(f[n] - (DEV ? weight(i) * p.rho0 : 0.0));
-        G[i * p.stride + s] = T(REF ? g[n] - rweight(i) * phic[d] : g[n]);
+        F[dist_own(p, q, i)] = T(f[n] - (DEV ? weight(i) * p.rho0 : 0.0));
+        G[dist_own(p, q, i)] = T(REF ? g[n] - rweight(i) * phic[d] : g[n]);
     }
 }
 
@@ -661,7 +674,7 @@ int reduction_grid(const KParams& p)
         }                                 \
     } while (0)
 
-// a 19-component array addressed with 32-bit byte offsets
+// a 19-component F or G region addressed with 32-bit byte offsets
 bool small_arrays(const KParams& p, size_t elem)
 {
     return size_t(NV) * p.stride * elem < (size_t(1) << 32);

@@ -65,6 +65,7 @@ def test_query_sizes(abi):
 @pytest.mark.parametrize("kw,code", [
     (dict(nx=0), "LB_ESHAPE"), (dict(ny=-3), "LB_ESHAPE"),
     (dict(nx=2048, ny=2048, nz=1024), "LB_ESHAPE"),
+    (dict(nx=1, ny=8192, nz=4096), "LB_ESHAPE"),  # one FP64 x-plane of f >= 4 GiB
     (dict(tau_f=0.5), "LB_EINVAL"), (dict(tau_g=0.2), "LB_EINVAL"),
     (dict(tau_f=float("nan")), "LB_EINVAL"), (dict(rho0=0.0), "LB_EINVAL"),
     (dict(precision=7), "LB_EINVAL"), (dict(kernel=2), "LB_EINVAL"),
@@ -73,6 +74,13 @@ def test_bad_parameters_rejected(abi, kw, code):
     st, _ = _query(abi, **kw)
     assert st == getattr(abi, code)
     assert abi.lib().lb_last_error().decode()
+
+
+def test_fp32_plane_limit_is_twice_fp64(abi):
+    """The per-plane limit counts bytes: the plane that FP64 rejects fits in
+    FP32 storage."""
+    st, _ = _query(abi, nx=1, ny=8192, nz=4096, precision=abi.LB_FP32_DEV)
+    assert st == abi.LB_OK
 
 
 def test_create_validates_buffers_without_launching(abi):
