@@ -84,6 +84,19 @@ def test_sampled_parity_droplet_256(precision, tol):
     _sampled_parity((256, 256, 256), precision, _droplet(256), 5, dict(tau_f=0.8, tau_g=1.3), tol)
 
 
+@pytest.mark.parametrize("precision,shape,tol", [("fp64", (320, 320, 320), 1e-12),
+                                                 ("fp32_dev", (400, 384, 384), 2e-6)])
+def test_sampled_parity_large_regions(precision, shape, tol):
+    """Lattices whose f or g region exceeds 4 GiB: the single-pass kernel
+    addresses planes with 64-bit offsets (one pointer per component) instead
+    of 32-bit ones.  (400, 384, 384) in FP32 also runs the pipelined march on
+    full tiles."""
+    pr = lbinputs.SPINODAL_PARAMS
+    xi = lbinputs.interface_width(pr["A"], pr["kappa"])
+    phi0 = lbinputs.droplet_phi0(shape, min(shape) / 4, xi, noise=1e-3, seed=lbinputs.SEED_DROPLET)
+    _sampled_parity(shape, precision, phi0, 2, dict(tau_f=0.8, tau_g=1.3), tol, nsample=12)
+
+
 def test_sampled_parity_spinodal_128_fp64():
     shape = (128, 128, 128)
     _sampled_parity(shape, "fp64", lbinputs.spinodal_phi0(shape), 20, {}, 1e-12)
