@@ -62,8 +62,8 @@ def sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(prec: str, n: int):
-    if n != 256 or TRAFFIC_SHA256 is None or prec not in TRAFFIC_BYTES:
+def measured_traffic(prec: str, n: int, layout: str = "rows"):
+    if n != 256 or layout != "rows" or TRAFFIC_SHA256 is None or prec not in TRAFFIC_BYTES:
         return None
     if sources_sha256() != TRAFFIC_SHA256:
         return None
@@ -125,6 +125,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--layout", default="rows", choices=["rows", "soa", "aos", "aosoa"],
+                    help="distribution layout of the 256^3 legs (default: row-blocked)")
+    ap.add_argument("--aosoa-len", type=int, default=64, help="z-sites per block for --layout aosoa")
     ap.add_argument("--spinodal-steps", type=int, default=1000,
                     help="steps of the extra 128^3 FP64 spinodal throughput line (0: skip)")
     args = ap.parse_args()
@@ -152,8 +155,9 @@ def main():
 
     runs = {}
     precs = ["fp32_dev"] + ([] if args.no_fp64 else ["fp64"])
+    lay = dict(layout=args.layout, aosoa_len=args.aosoa_len if args.layout == "aosoa" else 0)
     for prec in precs:
-        lb = LB(shape, precision=prec, device="cuda:0", **params)
+        lb = LB(shape, precision=prec, device="cuda:0", **lay, **params)
         lb.init_phi(phi0)
         s0 = lb.sums().cpu().numpy()
         hist = torch.empty((args.steps, 5), dtype=torch.float64, device="cuda:0")
@@ -189,7 +193,7 @@ def main():
         achieved = per_step * nsites / t / 1e9
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": measured_traffic(prec, n),
+                "traffic": measured_traffic(prec, n, args.layout),
                 "effective_GBps": round(b["method_min"] * nsites / t / 1e9, 1),
                 "bytes_per_site": per_step, "algorithmic_bytes_per_launch": per_step * nsites,
                 "kernel": "k_step_fused_f32" if e == 4 else "k_step_fused_f64",
@@ -202,7 +206,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded tanh droplet + noise)",
         "config": {"workload": f"D3Q19 binary-fluid droplet {n}^3 periodic, FP32 deviation storage",
-                   "lattice": list(shape), "radius": radius, "xi": round(xi, 6),
+                   "lattice": list(shape), "layout": args.layout
+                   + (f":{args.aosoa_len}" if args.layout == "aosoa" else ""),
+                   "radius": radius, "xi": round(xi, 6),
                    "noise": 1e-3, "seed": lbinputs.SEED_DROPLET, **params},
         "roofline": roof(prim, "fp32_dev"),
     }

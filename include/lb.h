@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 1
+#define LB_ABI_VERSION 2
 #define LB_NVEL 19
 
 typedef enum {
@@ -83,6 +83,18 @@ typedef enum {
     LB_KERNEL_TWO_PASS = 1 /* a phi pass, then the stencil/collision pass  */
 } lb_kernel;
 
+/* Memory layout of the f and g regions of a time level (opaque to callers,
+ * who see dense arrays through lb_export_dist / lb_import_dist; every layout
+ * gives bit-identical results).  Element (i, x, y, z), row r = x*ny + y: */
+typedef enum {
+    LB_LAYOUT_ROWS = 0, /* row-blocked: (r*19 + i)*nz + z (default, fastest)  */
+    LB_LAYOUT_SOA = 1,  /* one array per component: i*stride + r*nz + z      */
+    LB_LAYOUT_AOS = 2,  /* a site's 19 components together: (r*nz + z)*19 + i */
+    LB_LAYOUT_AOSOA = 3 /* blocks of V = aosoa_len z-sites (a power of two
+                           dividing nz), 19 components each:
+                           (r*nz + (z/V)*V)*19 + i*V + z%V                    */
+} lb_layout;
+
 /* Lattice and model.  nx, ny, nz >= 1 (periodic in all three directions),
  * N = nx*ny*nz below ~1.1e8 sites (39 * stride_elems < 2^32) and one x-plane
  * of f below 4 GiB (ny*nz*19*elem_bytes < 2^32), else LB_ESHAPE;
@@ -96,6 +108,8 @@ typedef struct {
     int32_t precision;  /* lb_precision                                             */
     int32_t kernel;     /* lb_kernel (same results; a performance choice)           */
     int32_t segment_x;  /* planes per workgroup in the fused kernel; <= 0: automatic */
+    int32_t layout;     /* lb_layout of the distributions                           */
+    int32_t aosoa_len;  /* V for LB_LAYOUT_AOSOA (ignored otherwise)                */
 } lb_params;
 
 /* Sizes in bytes of the caller-owned device buffers (lb_query_sizes). */

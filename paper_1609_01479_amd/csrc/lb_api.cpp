@@ -71,6 +71,14 @@ lb_status validate(const lb_params* p)
         return fail(LB_EINVAL, "unknown precision %d", p->precision);
     if (p->kernel != LB_KERNEL_FUSED && p->kernel != LB_KERNEL_TWO_PASS)
         return fail(LB_EINVAL, "unknown kernel variant %d", p->kernel);
+    if (p->layout < LB_LAYOUT_ROWS || p->layout > LB_LAYOUT_AOSOA)
+        return fail(LB_EINVAL, "unknown layout %d", p->layout);
+    if (p->layout == LB_LAYOUT_AOSOA) {
+        const int v = p->aosoa_len;
+        if (v < 1 || (v & (v - 1)) != 0 || p->nz % v != 0)
+            return fail(LB_ESHAPE, "aosoa_len %d must be a power of two dividing nz = %d", v,
+                        p->nz);
+    }
     return LB_OK;
 }
 
@@ -171,6 +179,7 @@ lb_status lb_create(const lb_params* p, const lb_buffers* b, void* hip_stream, l
     k.nz = p->nz;
     k.nsites = p->nx * p->ny * p->nz;
     k.stride = unsigned(sz.stride_elems);
+    lbk::set_layout(k, p->layout, p->aosoa_len);
     k.A = p->A;
     k.B = p->B;
     k.kappa = p->kappa;

@@ -102,15 +102,19 @@ __device__ __forceinline__ int xcd_block()
     return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
 }
 
-// Distribution layout of a time level: F and G are each row-blocked -- for
-// every (x, y) row the 19 components' z-runs follow one another, element
-// (i, x, y, z) at ((x*ny + y)*19 + i)*nz + z.  A workgroup's accesses to one
-// plane then fall in a few long contiguous stretches (measured on MI355X:
-// 4-7% faster steps than one array per component).  Indices fit 32 bits
-// (19 N < 2^32 is checked at creation).
+// Distribution layout of a time level (KParams layout fields, set by
+// set_layout): element (i, x, y, z) of the F or G region at
+//   x*plane_e + y*ry + (z >> vs)*zb + (z & vm) + i*cs,
+// which covers the row-blocked default ((x*ny + y)*19 + i)*nz + z, one array
+// per component, a site's components together, and blocks of 2^vs z-sites.
+// Indices fit 32 bits (39*stride < 2^32 is checked at creation).
+__device__ __forceinline__ unsigned row_off(const KParams& p, int y, int z)
+{
+    return unsigned(y) * p.ry + (unsigned(z) >> p.vs) * p.zb + (unsigned(z) & p.vm);
+}
 __device__ __forceinline__ unsigned didx(const KParams& p, int i, int x, int y, int z)
 {
-    return (unsigned(x * p.ny + y) * unsigned(NV) + unsigned(i)) * unsigned(p.nz) + unsigned(z);
+    return unsigned(x) * p.plane_e + row_off(p, y, z) + unsigned(i) * p.cs;
 }
 // component i at x - c_i, at x itself, at x + c_i
 __device__ __forceinline__ unsigned dist_pull(const KParams& p, const Geo& q, int i)

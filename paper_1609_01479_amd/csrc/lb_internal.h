@@ -17,6 +17,9 @@ struct KParams {
     unsigned stride;       // elements per distribution component; every element
                            // offset in a kernel (component * stride + site, at
                            // most 39 components) fits in 32 bits
+    // layout of the f and g regions: element (i, x, y, z) at
+    //   x*plane_e + y*ry + (z >> vs)*zb + (z & vm) + i*cs
+    unsigned plane_e, ry, zb, vs, vm, cs;
     double A, B, kappa, gamma;
     double omega_f, omega_g;  // 1/tau
     double rho0;
@@ -31,10 +34,14 @@ struct TileCfg {
 // segment_x <= 0 picks the segment length automatically.
 TileCfg tile_config(const KParams& p, int segment_x, bool fp32);
 
+// Fills the layout fields of k (nx, ny, nz and stride set) for an lb_layout.
+void set_layout(KParams& k, int layout, int aosoa_len);
+
 // All launchers enqueue on `s` and return hipGetLastError().
 // `fp32` selects the FP32 deviation-storage instantiation; otherwise FP64.
-// A time level (`state`) is F[19][stride], G[19][stride] and, in FP32 mode,
-// phi_c[stride] (FP64).  Order-parameter fields (`phi`) are FP64.
+// A time level (`state`) is an F region and a G region of 19*stride elements
+// each (laid out per KParams) and, in FP32 mode, phi_c[stride] (FP64, site
+// order).  Order-parameter fields (`phi`) are FP64.
 hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* phi0, hipStream_t s);
 // variant 0: single-pass fused step; 1: phi pass + collision pass.
 // If sums_out is non-null, also writes the 5 FP64 conserved sums

@@ -168,13 +168,12 @@ __device__ __forceinline__ int wrapg(int v, int n)
     return v;
 }
 
-// Addressing (row-blocked layout, didx()): a thread's (y, z) never changes
-// while it marches along x, so the byte offsets of the 9 rows/columns
-// (y - cy, z - cz) within a plane are computed once (32-bit: one plane of F
-// or G is under 4 GiB, checked at creation); a component (nz elements) adds a
-// uniform in-plane offset and a plane (ny*19*nz elements) a uniform plane
-// offset -- 32-bit when the whole F or G region is under 4 GiB (SMALL), else
-// 64-bit, added to the base pointer.
+// Addressing (layout of didx()): a thread's (y, z) never changes while it
+// marches along x, so the byte offsets of the 9 rows/columns (y - cy, z - cz)
+// within a plane are computed once (32-bit: one plane of F or G is under
+// 4 GiB, checked at creation); a component adds a uniform in-plane offset
+// and a plane a uniform plane offset -- 32-bit when the whole F or G region
+// is under 4 GiB (SMALL), else 64-bit, added to the base pointer.
 template <bool SMALL>
 using OffT = typename std::conditional<SMALL, unsigned, size_t>::type;
 
@@ -202,7 +201,7 @@ __device__ __forceinline__ void stc(T* __restrict__ base, OffT<SMALL> pl, int i,
 }
 
 // byte offsets of the 9 rows/columns (y + dy, z + dz), dy, dz in {-1, 0, 1},
-// within a plane of a row-blocked F or G region
+// within a plane of an F or G region
 struct Yz9 {
     unsigned o[3][3];
 };
@@ -215,9 +214,7 @@ __device__ __forceinline__ Yz9 yz9(const KParams& p, int y, int z)
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
-        for (int c = 0; c < 3; c++)
-            r.o[a][c] = (unsigned(ys[a]) * unsigned(NV) * unsigned(p.nz) + unsigned(zs[c])) *
-                        unsigned(sizeof(T));
+        for (int c = 0; c < 3; c++) r.o[a][c] = row_off(p, ys[a], zs[c]) * unsigned(sizeof(T));
     return r;
 }
 
@@ -246,8 +243,8 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     // stored FP32 deviation (FP32 mode) or the FP64 population
     using K = typename std::conditional<REF, T, double>::type;
     using O = OffT<SMALL>;
-    const unsigned compb = unsigned(p.nz) * unsigned(sizeof(T));  // one component's z-run
-    const O planeb = O(p.ny) * O(NV) * O(p.nz) * O(sizeof(T));    // one plane of F or G
+    const unsigned compb = p.cs * unsigned(sizeof(T));   // one component step
+    const O planeb = O(p.plane_e) * O(sizeof(T));        // one plane of F or G
 
     const int b = xcd_block();
     const int tile = b % tc.ntiles, seg = b / tc.ntiles;
@@ -681,6 +678,41 @@ bool small_arrays(const KParams& p, size_t elem)
 }
 
 }  // namespace
+
+void set_layout(KParams& k, int layout, int aosoa_len)
+{
+    const unsigned ny = unsigned(k.ny), nz = unsigned(k.nz), nv = unsigned(NV);
+    k.vs = 31;  // z >> 31 == 0: no z-blocks
+    k.vm = 0xffffffffu;
+    k.zb = 0;
+    k.plane_e = ny * nz * nv;
+    k.ry = nz * nv;
+    switch (layout) {
+    case 1:  // one array per component
+        k.plane_e = ny * nz;
+        k.ry = nz;
+        k.cs = k.stride;
+        break;
+    case 2:  // a site's components together
+        k.vs = 0;
+        k.vm = 0;
+        k.zb = nv;
+        k.cs = 1;
+        break;
+    case 3: {  // blocks of V z-sites
+        unsigned v = unsigned(aosoa_len), sh = 0;
+        while ((1u << sh) < v) sh++;
+        k.vs = sh;
+        k.vm = v - 1;
+        k.zb = nv * v;
+        k.cs = v;
+        break;
+    }
+    default:  // row-blocked
+        k.cs = nz;
+        break;
+    }
+}
 
 TileCfg tile_config(const KParams& p, int segment_x, bool fp32)
 {

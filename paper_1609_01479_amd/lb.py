@@ -15,6 +15,10 @@ from . import _abi
 from ._abi import LB_FP32_DEV, LB_FP64, NVEL, check
 
 
+# distribution layouts (lb_layout); every layout gives bit-identical results
+LAYOUTS = {"rows": 0, "soa": 1, "aos": 2, "aosoa": 3}
+
+
 def _precision_code(precision) -> int:
     if precision in ("fp64", "f64", LB_FP64):
         return LB_FP64
@@ -35,11 +39,15 @@ class LB:
     adjoint: also allocate the reverse-mode buffers.
     kernel: "fused" (one pass per step) or "two_pass" (phi pass + collision pass).
     segment_x: x planes per workgroup of the fused kernel (0 = automatic).
+    layout: memory layout of the distributions, "rows" (row-blocked, default),
+        "soa", "aos" or "aosoa" with aosoa_len z-sites per block (a power of
+        two dividing nz); results are bit-identical across layouts.
     """
 
     def __init__(self, shape, *, A=-0.00625, B=0.00625, kappa=0.004, gamma=0.5, tau_f=1.0,
                  tau_g=1.0, rho0=1.0, precision="fp64", adjoint=False, device=None,
-                 stream: torch.cuda.Stream | None = None, kernel="fused", segment_x=0):
+                 stream: torch.cuda.Stream | None = None, kernel="fused", segment_x=0,
+                 layout="rows", aosoa_len=0):
         L = _abi.lib()
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
@@ -47,7 +55,8 @@ class LB:
         self.precision = _precision_code(precision)
         self.params = _abi.LbParams(nx, ny, nz, float(A), float(B), float(kappa), float(gamma),
                                     float(tau_f), float(tau_g), float(rho0), self.precision,
-                                    {"fused": 0, "two_pass": 1}[kernel], int(segment_x))
+                                    {"fused": 0, "two_pass": 1}[kernel], int(segment_x),
+                                    LAYOUTS[layout], int(aosoa_len))
         self.sizes = _abi.LbSizes()
         check(L.lb_query_sizes(ctypes.byref(self.params), ctypes.byref(self.sizes)),
               "lb_query_sizes")

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(abi):
     L = abi.lib()
     for name in _declared_functions():
         assert hasattr(L, name), name
-    assert L.lb_abi_version() == 1
+    assert L.lb_abi_version() == 2
 
 
 def _params(abi, **kw):
@@ -69,6 +69,9 @@ def test_query_sizes(abi):
     (dict(tau_f=0.5), "LB_EINVAL"), (dict(tau_g=0.2), "LB_EINVAL"),
     (dict(tau_f=float("nan")), "LB_EINVAL"), (dict(rho0=0.0), "LB_EINVAL"),
     (dict(precision=7), "LB_EINVAL"), (dict(kernel=2), "LB_EINVAL"),
+    (dict(layout=4), "LB_EINVAL"), (dict(layout=-1), "LB_EINVAL"),
+    (dict(layout=3, aosoa_len=3), "LB_ESHAPE"), (dict(layout=3, aosoa_len=0), "LB_ESHAPE"),
+    (dict(layout=3, aosoa_len=64, nz=96), "LB_ESHAPE"),
 ])
 def test_bad_parameters_rejected(abi, kw, code):
     st, _ = _query(abi, **kw)
