@@ -70,6 +70,17 @@ def measured_traffic(prec: str, n: int, layout: str = "rows"):
     return TRAFFIC_BYTES[prec]
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def time_steps(lb, steps: int, warmup: int, sums=None):
     """ms for `steps` steps on the library's stream (HIP events on that
     stream).  With `sums` (a (steps, 5) FP64 device tensor) every step also
@@ -167,9 +178,12 @@ def main():
         rho, u, phi = lb.moments()
         torch.cuda.synchronize()
         h = hist.cpu().numpy()
-        # the same steps without the per-step reduction, for reference
+        # the same steps without the per-step reduction, for reference, and
+        # five repeats of a tenth of them (min and median per step)
         ms_plain = time_steps(lb, max(args.steps // 4, 1), 0) * args.steps / max(args.steps // 4, 1)
-        runs[prec] = dict(ms=ms, ms_plain=ms_plain, elem=int(lb.sizes.elem_bytes), sums0=s0,
+        kr = max(args.steps // 10, 1)
+        reps = sorted(time_steps(lb, kr, 0) / kr for _ in range(5))
+        runs[prec] = dict(ms=ms, ms_plain=ms_plain, reps=reps, elem=int(lb.sizes.elem_bytes), sums0=s0,
                           sums1=s1, u=u.cpu().numpy(), phi=phi.cpu().numpy(),
                           max_drift=np.abs(h - h[0]).max(axis=0))
         log(f"{prec}: {ms:.1f} ms -> {nsites * args.steps / (ms * 1e-3) / 1e6:.1f} MLUPS "
@@ -213,6 +227,8 @@ def main():
         "roofline": roof(prim, "fp32_dev"),
     }
     out["ms_per_step_without_sums"] = round(prim["ms_plain"] / args.steps, 4)
+    out["ms_per_step_without_sums_5_repeats"] = {"min": round(prim["reps"][0], 4),
+                                                 "median": round(prim["reps"][2], 4)}
     out["conservation"] = {"fp32_max_abs_drift_over_run": {
         k: float(v) for k, v in zip(("rho", "phi", "jx", "jy", "jz"), prim["max_drift"])}}
     if "fp64" in runs:
@@ -221,6 +237,8 @@ def main():
         out["fp64"] = {"value": round(nsites / (ms64 * 1e-3) / 1e6, 1), "unit": "MLUPS",
                        "ms_per_step": round(ms64, 4),
                        "ms_per_step_without_sums": round(r64["ms_plain"] / args.steps, 4),
+                       "ms_per_step_without_sums_5_repeats": {"min": round(r64["reps"][0], 4),
+                                                              "median": round(r64["reps"][2], 4)},
                        "roofline": roof(r64, "fp64")}
         out["conservation"]["fp64_max_abs_drift_over_run"] = {
             k: float(v) for k, v in zip(("rho", "phi", "jx", "jy", "jz"), r64["max_drift"])}
@@ -286,14 +304,30 @@ def main():
         p = oracle.Params(*shape, **params)
         f, g = oracle.init(p, phi0)
         cores = len(os.sched_getaffinity(0))
-        log(f"oracle: 1 step at {shape} on {cores} threads")
+        cores = oracle.set_threads(cores)
+        cpu = host_cpu_model()
+        log(f"oracle: 1 step at {shape} on {cores} threads ({cpu})")
         t0 = time.perf_counter()
         oracle.run(p, f, g, 1)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(nsites / dt / 1e6, 3), "unit": "MLUPS",
                                "cores": cores, "kind": "oracle",
                                "sample": f"1 FP64 step of the same {n}^3 droplet lattice "
-                                         f"({dt:.1f} s)"}
+                                         f"({dt:.1f} s) on {cpu}"}
+        # single-thread figure on a 64^3 droplet of the same recipe
+        del f, g
+        s1 = (64, 64, 64)
+        p1 = oracle.Params(*s1, **params)
+        f1, g1 = oracle.init(p1, lbinputs.droplet_phi0(s1, 16.0, xi, noise=1e-3,
+                                                        seed=lbinputs.SEED_DROPLET))
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.run(p1, f1, g1, 1)
+        dt1 = time.perf_counter() - t0
+        oracle.set_threads(cores)
+        out["cpu_baseline_1thread"] = {"value": round(64 ** 3 / dt1 / 1e6, 3), "unit": "MLUPS",
+                                       "cores": 1, "kind": "oracle",
+                                       "sample": f"1 FP64 step of a 64^3 droplet ({dt1:.1f} s)"}
     print(json.dumps(out), flush=True)
 
 

@@ -89,6 +89,8 @@ def _load():
     lib.oracle_moments.argtypes = [P, D, D, D, D, D]
     lib.oracle_sum.argtypes = [D, ctypes.c_long]
     lib.oracle_sum.restype = ctypes.c_double
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -215,3 +217,9 @@ def sums(p: Params, f, g):
     rho, u, phi = moments(p, f, g)
     j = u * rho[None]
     return np.array([fsum(rho), fsum(phi), fsum(j[0]), fsum(j[1]), fsum(j[2])])
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's site loops (timing only; results do not
+    depend on it).  Returns the count now in effect."""
+    return int(_load().oracle_set_threads(int(n)))

@@ -40,6 +40,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int32_t nx, ny, nz;
@@ -315,6 +318,20 @@ void oracle_moments(const oracle_params *p, const double *f, const double *g,
         if (u) for (int a = 0; a < 3; a++) u[a * n + s] = j[a] / r;
         if (phi) phi[s] = ph;
     }
+}
+
+/* ---- thread count (timing only: every parallel loop is over independent
+ * sites, so results do not depend on it) ---------------------------------- */
+
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* ---- FP64 pairwise sum (fixed order) ---------------------------------- */
