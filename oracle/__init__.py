@@ -37,7 +37,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("A", ctypes.c_double), ("B", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("tau_f", ctypes.c_double),
-                ("tau_g", ctypes.c_double), ("rho0", ctypes.c_double)]
+                ("tau_g", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("coupling", ctypes.c_int32)]
 
 
 @dataclass
@@ -53,6 +54,7 @@ class Params:
     tau_f: float = 1.0
     tau_g: float = 1.0
     rho0: float = 1.0
+    coupling: int = 0  # 0: Pi in f^eq; 1: body force -div Pi (Guo forcing)
 
     @property
     def shape(self):
@@ -60,7 +62,7 @@ class Params:
 
     def c(self) -> _Params:
         return _Params(self.nx, self.ny, self.nz, self.A, self.B, self.kappa, self.gamma,
-                       self.tau_f, self.tau_g, self.rho0)
+                       self.tau_f, self.tau_g, self.rho0, self.coupling)
 
 
 def _load():
@@ -89,6 +91,10 @@ def _load():
     lib.oracle_moments.argtypes = [P, D, D, D, D, D]
     lib.oracle_sum.argtypes = [D, ctypes.c_long]
     lib.oracle_sum.restype = ctypes.c_double
+    lib.oracle_force.argtypes = [P, D, D]
+    lib.oracle_equilibrium_force_site.argtypes = [P, ctypes.c_double, D, ctypes.c_double,
+                                                  ctypes.c_double, D, D]
+    lib.oracle_collide_force.argtypes = [P, D, D, D, D, D, D, D]
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_threads.restype = ctypes.c_int
     _lib = lib
@@ -217,6 +223,36 @@ def sums(p: Params, f, g):
     rho, u, phi = moments(p, f, g)
     j = u * rho[None]
     return np.array([fsum(rho), fsum(phi), fsum(j[0]), fsum(j[1]), fsum(j[2])])
+
+
+def force(p: Params, pi):
+    """Body force of the force coupling, F = -div Pi (central differences),
+    from the chemical stress pi (6, nx, ny, nz): returns (3, nx, ny, nz)."""
+    pi = _f64(pi)
+    F = np.empty((3,) + p.shape)
+    _load().oracle_force(ctypes.byref(p.c()), _ptr(pi), _ptr(F))
+    return F
+
+
+def equilibrium_force_site(p: Params, rho, u, phi, mu):
+    """Force-coupling equilibria (f^eq, g^eq), each (19,), at one site from
+    rho, the velocity u (3,), phi and mu."""
+    feq = np.empty(NVEL)
+    geq = np.empty(NVEL)
+    uu = _f64(np.asarray(u, dtype=np.float64))
+    _load().oracle_equilibrium_force_site(ctypes.byref(p.c()), float(rho), _ptr(uu), float(phi),
+                                          float(mu), _ptr(feq), _ptr(geq))
+    return feq, geq
+
+
+def collide_force(p: Params, f, g, phi, mu, F):
+    """BGK collision with the forcing term at every site: (f*, g*)."""
+    f, g, phi, mu, F = (_f64(a) for a in (f, g, phi, mu, F))
+    fs = np.empty_like(f)
+    gs = np.empty_like(g)
+    _load().oracle_collide_force(ctypes.byref(p.c()), _ptr(f), _ptr(g), _ptr(phi), _ptr(mu),
+                                 _ptr(F), _ptr(fs), _ptr(gs))
+    return fs, gs
 
 
 def set_threads(n: int) -> int:

@@ -25,6 +25,19 @@
  *   f*_i  = f_i - (f_i - feq_i)/tau_f,   g*_i = g_i - (g_i - geq_i)/tau_g
  *   f_i(x + c_i, t+1) = f*_i(x, t)   (periodic; same for g)
  *
+ * Force coupling (coupling = 1; the paper's statement for its Ludwig model,
+ * Sec. 2.1.1: the divergence of the chemical stress acts as a body force):
+ *
+ *   F_a(x)      = - sum_b [Pi_ab(x+e_b) - Pi_ab(x-e_b)] / 2      (central div)
+ *   u           = (j + F/2) / rho
+ *   feq_i       = w_i rho [1 + 3 c_i.u + 9/2 Q_i : u u]   (no Pi)
+ *   geq_i       as above with this u
+ *   f*_i        = f_i - (f_i - feq_i)/tau_f
+ *                 + (1 - 1/(2 tau_f)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F
+ *
+ * (Guo, Zheng and Shi's forcing term: the collision adds exactly F to the
+ * momentum of every site.)
+ *
  * The paper does not print these formulas (it names the kernels only); they
  * are the standard free-energy binary-fluid LB model.  The readings taken
  * where the paper is silent (equilibrium form for all i including the rest
@@ -47,6 +60,7 @@
 typedef struct {
     int32_t nx, ny, nz;
     double A, B, kappa, gamma, tau_f, tau_g, rho0;
+    int32_t coupling; /* 0: Pi in f^eq's second moment; 1: force -div Pi */
 } oracle_params;
 
 #define NVEL 19
@@ -205,6 +219,80 @@ void oracle_equilibrium_site(const oracle_params *p, double rho, const double j[
     }
 }
 
+/* ---- force coupling: F = -div Pi (central differences) ---------------- */
+
+void oracle_force(const oracle_params *p, const double *pi /* [6][N] */, double *F /* [3][N] */)
+{
+    long n = nsites(p);
+    /* component of Pi_ab in the xx, xy, xz, yy, yz, zz storage */
+    static const int K[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    for (long s = 0; s < n; s++) {
+        int x, y, z;
+        site_coords(p, s, &x, &y, &z);
+        long nb[3][2] = {
+            {site_index(p, x + 1, y, z), site_index(p, x - 1, y, z)},
+            {site_index(p, x, y + 1, z), site_index(p, x, y - 1, z)},
+            {site_index(p, x, y, z + 1), site_index(p, x, y, z - 1)},
+        };
+        for (int a = 0; a < 3; a++) {
+            double div = 0.0;
+            for (int b = 0; b < 3; b++) {
+                const double *t = pi + (long)K[a][b] * n;
+                div += 0.5 * (t[nb[b][0]] - t[nb[b][1]]);
+            }
+            F[a * n + s] = -div;
+        }
+    }
+}
+
+/* Force-coupling equilibria at one site from rho, the velocity u, phi, mu. */
+void oracle_equilibrium_force_site(const oracle_params *p, double rho, const double u[3],
+                                   double phi, double mu, double *feq, double *geq)
+{
+    double mf[3][3], mg[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            mf[a][b] = rho * u[a] * u[b];
+            mg[a][b] = (a == b ? p->gamma * mu - phi / 3.0 : 0.0) + phi * u[a] * u[b];
+        }
+    for (int i = 0; i < NVEL; i++) {
+        double cu = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
+        feq[i] = weight(i) * (rho + 3.0 * rho * cu + 4.5 * q_contract(i, mf));
+        geq[i] = weight(i) * (phi + 3.0 * phi * cu + 4.5 * q_contract(i, mg));
+    }
+}
+
+/* BGK collision with the forcing term, every site. */
+void oracle_collide_force(const oracle_params *p, const double *f, const double *g,
+                          const double *phi, const double *mu, const double *F,
+                          double *fstar, double *gstar)
+{
+    long n = nsites(p);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < n; s++) {
+        double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < NVEL; i++) {
+            double fi = f[i * n + s];
+            rho += fi;
+            for (int a = 0; a < 3; a++) j[a] += fi * CV[i][a];
+        }
+        double fv[3] = {F[s], F[n + s], F[2 * n + s]};
+        double u[3];
+        for (int a = 0; a < 3; a++) u[a] = (j[a] + 0.5 * fv[a]) / rho;
+        double feq[NVEL], geq[NVEL];
+        oracle_equilibrium_force_site(p, rho, u, phi[s], mu[s], feq, geq);
+        double pref = 1.0 - 0.5 / p->tau_f;
+        for (int i = 0; i < NVEL; i++) {
+            double cu = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
+            double src = 0.0;
+            for (int a = 0; a < 3; a++) src += (3.0 * (CV[i][a] - u[a]) + 9.0 * cu * CV[i][a]) * fv[a];
+            double fi = f[i * n + s], gi = g[i * n + s];
+            fstar[i * n + s] = fi - (fi - feq[i]) / p->tau_f + pref * weight(i) * src;
+            gstar[i * n + s] = gi - (gi - geq[i]) / p->tau_g;
+        }
+    }
+}
+
 /* ---- BGK collision at every site -------------------------------------- */
 
 void oracle_collide(const oracle_params *p, const double *f, const double *g,
@@ -266,7 +354,18 @@ int oracle_step(const oracle_params *p, const double *f, const double *g,
     oracle_order_parameter(p, g, phi);
     oracle_gradients(p, phi, grad, lap);
     oracle_chemical(p, phi, grad, lap, mu, pi);
-    oracle_collide(p, f, g, phi, mu, pi, fs, gs);
+    if (p->coupling == 1) {
+        double *F = malloc(sizeof(double) * 3 * n);
+        if (!F) {
+            free(phi); free(grad); free(lap); free(mu); free(pi); free(fs); free(gs);
+            return 1;
+        }
+        oracle_force(p, pi, F);
+        oracle_collide_force(p, f, g, phi, mu, F, fs, gs);
+        free(F);
+    } else {
+        oracle_collide(p, f, g, phi, mu, pi, fs, gs);
+    }
     oracle_stream(p, fs, fnew);
     oracle_stream(p, gs, gnew);
     free(phi); free(grad); free(lap); free(mu); free(pi); free(fs); free(gs);
@@ -303,10 +402,30 @@ void oracle_init(const oracle_params *p, const double *phi0, double *f, double *
 
 /* ---- hydrodynamic moments of a post-stream state ---------------------- */
 
+/* rho, u, phi.  u = j/rho; in the force coupling u = (j + F/2)/rho, the
+ * velocity the collision uses, with F = -div Pi of the state's own phi. */
 void oracle_moments(const oracle_params *p, const double *f, const double *g,
                     double *rho, double *u /* [3][N] */, double *phi)
 {
     long n = nsites(p);
+    double *F = NULL;
+    if (p->coupling == 1 && u) {
+        double *ph = malloc(sizeof(double) * n), *grad = malloc(sizeof(double) * 3 * n);
+        double *lap = malloc(sizeof(double) * n), *mu = malloc(sizeof(double) * n);
+        double *pi = malloc(sizeof(double) * 6 * n);
+        F = malloc(sizeof(double) * 3 * n);
+        if (ph && grad && lap && mu && pi && F) {
+            oracle_order_parameter(p, g, ph);
+            oracle_gradients(p, ph, grad, lap);
+            oracle_chemical(p, ph, grad, lap, mu, pi);
+            oracle_force(p, pi, F);
+        } else {
+            free(F);
+            F = NULL;
+        }
+        free(ph); free(grad); free(lap); free(mu); free(pi);
+        if (!F) return; /* out of memory: outputs untouched */
+    }
     for (long s = 0; s < n; s++) {
         double r = 0.0, j[3] = {0.0, 0.0, 0.0}, ph = 0.0;
         for (int i = 0; i < NVEL; i++) {
@@ -314,24 +433,13 @@ void oracle_moments(const oracle_params *p, const double *f, const double *g,
             for (int a = 0; a < 3; a++) j[a] += f[i * n + s] * CV[i][a];
             ph += g[i * n + s];
         }
+        if (F)
+            for (int a = 0; a < 3; a++) j[a] += 0.5 * F[a * n + s];
         if (rho) rho[s] = r;
         if (u) for (int a = 0; a < 3; a++) u[a * n + s] = j[a] / r;
         if (phi) phi[s] = ph;
     }
-}
-
-/* ---- thread count (timing only: every parallel loop is over independent
- * sites, so results do not depend on it) ---------------------------------- */
-
-int oracle_set_threads(int n)
-{
-#ifdef _OPENMP
-    if (n > 0) omp_set_num_threads(n);
-    return omp_get_max_threads();
-#else
-    (void)n;
-    return 1;
-#endif
+    free(F);
 }
 
 /* ---- FP64 pairwise sum (fixed order) ---------------------------------- */
@@ -346,4 +454,18 @@ double oracle_sum(const double *x, long n)
     }
     long h = n / 2;
     return oracle_sum(x, h) + oracle_sum(x + h, n - h);
+}
+
+/* ---- thread count (timing only: every parallel loop is over independent
+ * sites, so results do not depend on it) ---------------------------------- */
+
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

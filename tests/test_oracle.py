@@ -356,11 +356,13 @@ def test_two_transcriptions_agree():
 
 # ------------------------------------------ hydrodynamic closed forms --
 
-def test_shear_wave_decays_with_bgk_viscosity():
-    """u_y = U sin(kx) decays as exp(-nu k^2 t) with nu = (tau_f - 1/2)/3."""
+@pytest.mark.parametrize("coupling", [0, 1])
+def test_shear_wave_decays_with_bgk_viscosity(coupling):
+    """u_y = U sin(kx) decays as exp(-nu k^2 t) with nu = (tau_f - 1/2)/3
+    (phi = 0: no stress and no force, in either coupling)."""
     n = 32
     shape = (n, 3, 3)
-    p = _params(shape, tau_f=0.8, tau_g=1.0)
+    p = _params(shape, tau_f=0.8, tau_g=1.0, coupling=coupling)
     k = 2 * math.pi / n
     U = 1e-5
     f = np.zeros((19,) + shape)
@@ -381,11 +383,13 @@ def test_shear_wave_decays_with_bgk_viscosity():
     assert abs(nu_meas / nu - 1) < 5e-3, nu_meas
 
 
-def test_order_parameter_relaxes_by_cahn_hilliard():
-    """Small phi = eps cos(kx), A > 0: decay rate M k^2 (A + kappa k^2), M = Gamma (tau_g - 1/2)."""
+@pytest.mark.parametrize("coupling", [0, 1])
+def test_order_parameter_relaxes_by_cahn_hilliard(coupling):
+    """Small phi = eps cos(kx), A > 0: decay rate M k^2 (A + kappa k^2), M = Gamma (tau_g - 1/2);
+    the flow the stress or force drives is second order in eps."""
     n = 32
     shape = (n, 3, 3)
-    p = _params(shape, A=0.1, B=0.0, kappa=0.004, tau_g=1.0, gamma=0.5)
+    p = _params(shape, A=0.1, B=0.0, kappa=0.004, tau_g=1.0, gamma=0.5, coupling=coupling)
     k = 2 * math.pi / n
     phi0 = 1e-4 * np.broadcast_to(np.cos(k * np.arange(n))[:, None, None], shape).copy()
     f, g = oracle.init(p, phi0)
@@ -400,6 +404,138 @@ def test_order_parameter_relaxes_by_cahn_hilliard():
     M = p.gamma * (p.tau_g - 0.5)
     expect = M * k * k * (p.A + p.kappa * k * k)
     assert abs(rate / expect - 1) < 0.02, (rate, expect)
+
+
+# ------------------------------------------------------ force coupling --
+
+def _smooth_field(n, k):
+    x, y, z = np.meshgrid(*[np.arange(n)] * 3, indexing="ij")
+    return (0.5 * np.sin(k * x) + 0.3 * np.cos(k * y + 0.4) + 0.2 * np.sin(k * z + 1.1)
+            + 0.25 * np.sin(k * (x + y)) + 0.15 * np.cos(k * (y - z)))
+
+
+def test_force_is_minus_phi_grad_mu_on_smooth_fields():
+    """F = -div Pi equals -phi grad mu in the continuum (Gibbs-Duhem): on a
+    smooth field the lattice versions agree to O(k^2); a sign, index or
+    component error leaves an O(1) gap.  A uniform field has F = 0 exactly,
+    and the central divergence sums to zero over the periodic lattice."""
+    n = 48
+    p = _params((n, n, n), A=-0.05, B=0.05, kappa=0.02, coupling=1)
+    k = 2 * math.pi / n
+    phi = _smooth_field(n, k)
+    grad, lap = oracle.gradients(p, phi)
+    mu, pi = oracle.chemical(p, phi, grad, lap)
+    F = oracle.force(p, pi)
+
+    def d(field, a):
+        return 0.5 * (np.roll(field, -1, a) - np.roll(field, 1, a))
+
+    scale = max(np.abs(phi * d(mu, a)).max() for a in range(3))
+    for a in range(3):
+        err = np.abs(F[a] + phi * d(mu, a)).max()
+        assert err < 0.02 * scale, (a, err, scale)
+    assert np.abs(F.sum(axis=(1, 2, 3))).max() < 1e-12 * np.abs(F).max() * F[0].size
+    pu = np.full((6, 5, 6, 7), 0.0)
+    pu[0] = pu[3] = pu[5] = 0.7
+    pu[1] = 0.2
+    assert np.array_equal(oracle.force(_params((5, 6, 7)), pu), np.zeros((3, 5, 6, 7)))
+
+
+def test_force_equilibrium_moments_exact():
+    """Force-coupling equilibria: sum f = rho, sum f c = rho u, sum f cc =
+    rho/3 I + rho u u (no stress); g as in the stress coupling."""
+    p = _params((3, 3, 3), coupling=1)
+    c, w = oracle.lattice()
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        rho, phi, mu = 1 + 0.1 * rng.random(), rng.uniform(-1, 1), rng.uniform(-0.1, 0.1)
+        u = rng.uniform(-0.05, 0.05, 3)
+        feq, geq = oracle.equilibrium_force_site(p, rho, u, phi, mu)
+        np.testing.assert_allclose(feq.sum(), rho, rtol=1e-15)
+        np.testing.assert_allclose(feq @ c, rho * u, rtol=0, atol=1e-16)
+        np.testing.assert_allclose(np.einsum("i,ia,ib->ab", feq, c, c),
+                                   rho / 3 * np.eye(3) + rho * np.outer(u, u), rtol=0, atol=1e-15)
+        np.testing.assert_allclose(geq.sum(), phi, rtol=1e-15, atol=1e-16)
+        np.testing.assert_allclose(geq @ c, phi * u, rtol=0, atol=1e-16)
+        np.testing.assert_allclose(np.einsum("i,ia,ib->ab", geq, c, c),
+                                   p.gamma * mu * np.eye(3) + phi * np.outer(u, u), rtol=0,
+                                   atol=1e-15)
+
+
+def test_force_collision_adds_exactly_the_force():
+    """Per site the forcing collision keeps mass and phi and adds exactly F to
+    the momentum (the half-force velocity and the (1 - 1/(2 tau)) source
+    together); g's first moment relaxes towards phi u with u = (j + F/2)/rho.
+    With F = 0 it is the stress-coupling collision with Pi = 0."""
+    shape = (4, 5, 3)
+    p = _params(shape, tau_f=0.8, tau_g=1.3, coupling=1)
+    c, w = oracle.lattice()
+    rng = np.random.default_rng(11)
+    f, g = _perturbed_state(p, 6)
+    phi = g.sum(0)
+    mu = rng.uniform(-0.01, 0.01, shape)
+    F = 1e-3 * rng.standard_normal((3,) + shape)
+    fs, gs = oracle.collide_force(p, f, g, phi, mu, F)
+    rho, j = f.sum(0), np.einsum("i...,ia->a...", f, c)
+    np.testing.assert_allclose(fs.sum(0), rho, rtol=1e-14)
+    np.testing.assert_allclose(np.einsum("i...,ia->a...", fs, c), j + F, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(gs.sum(0), phi, rtol=0, atol=1e-15)
+    u = (j + 0.5 * F) / rho
+    gj = np.einsum("i...,ia->a...", g, c)
+    np.testing.assert_allclose(np.einsum("i...,ia->a...", gs, c),
+                               (1 - 1 / p.tau_g) * gj + phi * u / p.tau_g, rtol=0, atol=1e-15)
+    f0, g0 = oracle.collide_force(p, f, g, phi, mu, np.zeros_like(F))
+    fr, gr = oracle.collide(p, f, g, phi, mu, np.zeros((6,) + shape))
+    np.testing.assert_allclose(f0, fr, rtol=1e-14, atol=1e-17)
+    np.testing.assert_allclose(g0, gr, rtol=1e-14, atol=1e-17)
+
+
+def test_force_coupling_conserves_and_keeps_uniform_state():
+    """sum rho, sum phi and total momentum conserved to round-off over 40
+    steps (the central divergence telescopes); a uniform equilibrium (F = 0)
+    is a fixed point."""
+    p = _params((6, 7, 8), tau_f=0.8, tau_g=1.3, coupling=1)
+    f, g = _perturbed_state(p, 4)
+    s0 = oracle.sums(p, f, g)
+    f2, g2 = oracle.run(p, f, g, 40)
+    np.testing.assert_allclose(oracle.sums(p, f2, g2), s0, rtol=0, atol=1e-12)
+    assert np.abs(f2 - f).max() > 1e-6  # the force acted
+    shape = (4, 5, 3)
+    pu = _params(shape, tau_f=0.8, tau_g=1.3, coupling=1)
+    phib = 0.3
+    mu = pu.A * phib + pu.B * phib ** 3
+    feq, geq = oracle.equilibrium_force_site(pu, 1.0, np.zeros(3), phib, mu)
+    f = np.broadcast_to(feq[:, None, None, None], (19,) + shape).copy()
+    g = np.broadcast_to(geq[:, None, None, None], (19,) + shape).copy()
+    f3, g3 = oracle.run(pu, f, g, 10)
+    np.testing.assert_allclose(f3, f, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(g3, g, rtol=1e-14, atol=1e-17)
+
+
+@pytest.mark.parametrize("coupling,tol", [(0, 2e-3), (1, 3e-2)])
+def test_flat_interfaces_reach_mechanical_equilibrium(coupling, tol):
+    """Two flat interfaces (width xi = 8) relax to rest, where the total
+    normal stress rho/3 + Pi_xx is uniform: rho - <rho> = -3 (Pi_xx - <Pi_xx>).
+    The stress coupling meets this to round-off once at rest; the force
+    coupling up to the difference between its central divergence and the
+    lattice's own pressure gradient (1% here, 16% at xi = 4).  A sign or
+    factor error in the force or the forcing term misses by 50-200%."""
+    n = 96
+    shape = (n, 1, 1)
+    A, B, kappa = -0.005, 0.005, 0.16
+    xi = math.sqrt(-2 * kappa / A)
+    x = np.arange(n)
+    phi0 = (np.tanh((x - n / 4) / xi) - np.tanh((x - 3 * n / 4) / xi) - 1.0).reshape(shape)
+    p = _params(shape, A=A, B=B, kappa=kappa, tau_f=1.0, tau_g=1.0, coupling=coupling)
+    f, g = oracle.run(p, *oracle.init(p, phi0), 8000)
+    rho, u, phi = oracle.moments(p, f, g)
+    assert np.abs(u).max() < 1e-6
+    grad, lap = oracle.gradients(p, phi)
+    _, pi = oracle.chemical(p, phi, grad, lap)
+    d = (rho - rho.mean()).ravel()
+    q = (-3 * (pi[0] - pi[0].mean())).ravel()
+    assert np.ptp(d) > 1e-5
+    assert np.abs(d - q).max() < tol * np.ptp(d), np.abs(d - q).max() / np.ptp(d)
 
 
 # ----------------------------------------------- reverse-mode gradients --
