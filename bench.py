@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--layout", default="rows", choices=["rows", "soa", "aos", "aosoa"],
                     help="distribution layout of the 256^3 legs (default: row-blocked)")
     ap.add_argument("--aosoa-len", type=int, default=64, help="z-sites per block for --layout aosoa")
+    ap.add_argument("--force-steps", type=int, default=200,
+                    help="steps of the 256^3 FP64 force-coupling line (0: skip)")
     ap.add_argument("--spinodal-steps", type=int, default=1000,
                     help="steps of the extra 128^3 FP64 spinodal throughput line (0: skip)")
     args = ap.parse_args()
@@ -251,6 +253,25 @@ def main():
                                      "u_max": float(du.max()),
                                      "u_rms": float(np.sqrt((du ** 2).mean()))}
     del runs
+
+    # FP64 force coupling (body force -div Pi) on the same 256^3 droplet: phi,
+    # Pi and collision passes move 880 B per site (160 + 56 + 664) against the
+    # method's 608
+    if args.force_steps > 0:
+        lb = LB(shape, precision="fp64", coupling="force", device="cuda:0", **lay, **params)
+        lb.init_phi(phi0)
+        log(f"fp64 force coupling {shape}: {args.force_steps} steps")
+        ms = time_steps(lb, args.force_steps, args.warmup)
+        t = ms / args.force_steps * 1e-3
+        out["fp64_force_coupling"] = {
+            "value": round(nsites / t / 1e6, 1), "unit": "MLUPS", "steps": args.force_steps,
+            "ms_per_step": round(ms / args.force_steps, 4),
+            "achieved_GBps": round(880 * nsites / t / 1e9, 1),
+            "frac": round(880 * nsites / t / 1e9 / HBM_PEAK_GBPS, 4),
+            "effective_GBps": round(608 * nsites / t / 1e9, 1),
+            "kernels": "k_phi + k_pi + k_step_force"}
+        del lb
+        torch.cuda.empty_cache()
 
     # FP64 on the 128^3 spinodal-decomposition lattice (phi0 ~ U(-0.05, 0.05))
     if not args.no_fp64 and args.spinodal_steps > 0:

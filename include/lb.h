@@ -83,6 +83,16 @@ typedef enum {
     LB_KERNEL_TWO_PASS = 1 /* a phi pass, then the stencil/collision pass  */
 } lb_kernel;
 
+/* How the chemical stress Pi drives the flow (both FP64 forms of the same
+ * hydrodynamics to leading order): */
+typedef enum {
+    LB_COUPLING_STRESS = 0, /* Pi in f^eq's second moment (default)         */
+    LB_COUPLING_FORCE = 1   /* body force F = -div Pi (central differences)
+                               with the half-force velocity u = (j + F/2)/rho
+                               and Guo's forcing term; LB_FP64 only, no
+                               adjoint; runs phi, Pi and collision passes   */
+} lb_coupling;
+
 /* Memory layout of the f and g regions of a time level (opaque to callers,
  * who see dense arrays through lb_export_dist / lb_import_dist; every layout
  * gives bit-identical results).  Element (i, x, y, z), row r = x*ny + y: */
@@ -110,6 +120,7 @@ typedef struct {
     int32_t segment_x;  /* planes per workgroup in the fused kernel; <= 0: automatic */
     int32_t layout;     /* lb_layout of the distributions                           */
     int32_t aosoa_len;  /* V for LB_LAYOUT_AOSOA (ignored otherwise)                */
+    int32_t coupling;   /* lb_coupling                                              */
 } lb_params;
 
 /* Sizes in bytes of the caller-owned device buffers (lb_query_sizes). */
@@ -118,7 +129,8 @@ typedef struct {
     size_t stride_elems;      /* padded elements per component of a distribution        */
     size_t state_bytes;       /* one time level: f, g (2*19*stride elements) and, in
                                  LB_FP32_DEV, phi_c (stride FP64 values)                */
-    size_t phi_bytes;         /* FP64 order-parameter work field                        */
+    size_t phi_bytes;         /* FP64 work fields: phi (N values of stride), and for
+                                 LB_COUPLING_FORCE also the 6 components of Pi         */
     size_t scratch_bytes;     /* reduction partials                                     */
     size_t adj_bytes;         /* one adjoint time level (lambda_f, lambda_g, lambda_phi) */
     size_t adj_scratch_bytes; /* adjoint stencil cotangents and parameter partials      */
@@ -179,7 +191,9 @@ lb_status lb_step_from(lb_ctx *ctx, const void *src_dev, void *dst_dev);
 
 /* Moments of the current (post-propagation) state, as dense FP64 device
  * arrays: rho_dev (N), u_dev (3N: x, y, z planes), phi_dev (N).  Any pointer
- * may be NULL to skip that output. */
+ * may be NULL to skip that output.  u = j/rho; with LB_COUPLING_FORCE
+ * u = (j + F/2)/rho, F = -div Pi of this state (the velocity the collision
+ * uses), and lb_sums' momentum sums are those of rho u likewise. */
 lb_status lb_moments(lb_ctx *ctx, double *rho_dev, double *u_dev, double *phi_dev);
 
 /* Global sums of the current state in FP64, written to out5_dev:

@@ -31,7 +31,7 @@ class LbParams(ctypes.Structure):
                 ("tau_g", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("segment_x", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("aosoa_len", ctypes.c_int32)]
+                ("aosoa_len", ctypes.c_int32), ("coupling", ctypes.c_int32)]
 
 
 class LbSizes(ctypes.Structure):

@@ -73,6 +73,10 @@ lb_status validate(const lb_params* p)
         return fail(LB_EINVAL, "unknown kernel variant %d", p->kernel);
     if (p->layout < LB_LAYOUT_ROWS || p->layout > LB_LAYOUT_AOSOA)
         return fail(LB_EINVAL, "unknown layout %d", p->layout);
+    if (p->coupling != LB_COUPLING_STRESS && p->coupling != LB_COUPLING_FORCE)
+        return fail(LB_EINVAL, "unknown coupling %d", p->coupling);
+    if (p->coupling == LB_COUPLING_FORCE && p->precision != LB_FP64)
+        return fail(LB_EINVAL, "the force coupling is available in LB_FP64 only");
     if (p->layout == LB_LAYOUT_AOSOA) {
         const int v = p->aosoa_len;
         if (v < 1 || (v & (v - 1)) != 0 || p->nz % v != 0)
@@ -128,7 +132,8 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     out->stride_elems = stride;
     // f and g, plus the FP64 reference order parameter in FP32 mode
     out->state_bytes = 2 * LB_NVEL * stride * e + (p->precision == LB_FP32_DEV ? stride * 8 : 0);
-    out->phi_bytes = stride * 8;
+    // FP64 work fields: phi, and for the force coupling also Pi (6 fields)
+    out->phi_bytes = (p->coupling == LB_COUPLING_FORCE ? 7 : 1) * stride * 8;
     // block partials of the reductions: 5 FP64 per block of the largest grid
     lbk::KParams k{};
     k.nx = p->nx;
@@ -187,6 +192,7 @@ lb_status lb_create(const lb_params* p, const lb_buffers* b, void* hip_stream, l
     k.omega_f = 1.0 / p->tau_f;
     k.omega_g = 1.0 / p->tau_g;
     k.rho0 = p->rho0;
+    k.force = p->coupling == LB_COUPLING_FORCE;
     c->tc = lbk::tile_config(k, p->segment_x, c->fp32);
     *out = c;
     return LB_OK;
@@ -249,7 +255,8 @@ lb_status lb_moments(lb_ctx* ctx, double* rho_dev, double* u_dev, double* phi_de
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
     int nb = 0;
     hipError_t e = lbk::launch_moments(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], rho_dev, u_dev,
-                                       phi_dev, static_cast<double*>(ctx->b.scratch), &nb, ctx->stream);
+                                       phi_dev, static_cast<double*>(ctx->b.phi),
+                                       static_cast<double*>(ctx->b.scratch), &nb, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_moments");
 }
 
@@ -259,7 +266,8 @@ lb_status lb_sums(lb_ctx* ctx, double* out5_dev)
     int nb = 0;
     double* part = static_cast<double*>(ctx->b.scratch);
     hipError_t e = lbk::launch_moments(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], nullptr, nullptr,
-                                       nullptr, part, &nb, ctx->stream);
+                                       nullptr, static_cast<double*>(ctx->b.phi), part, &nb,
+                                       ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "lb_sums (partials)");
     e = lbk::launch_sums_final(part, nb, 5, out5_dev, false, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_sums (final)");
@@ -302,6 +310,7 @@ lb_status lb_adjoint_seed(lb_ctx* ctx, const double* dphi_dev)
 {
     if (!ctx || !dphi_dev) return fail(LB_EINVAL, "ctx and dphi_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
+    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
     ctx->adj_cur = 0;
     hipError_t e = lbk::launch_adj_seed(ctx->kp, ctx->fp32, ctx->b.adj[0], dphi_dev, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_seed");
@@ -317,6 +326,7 @@ lb_status lb_adjoint_step_next(lb_ctx* ctx, const void* state_t_dev, const void*
 {
     if (!ctx || !state_t_dev) return fail(LB_EINVAL, "ctx and state_t_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
+    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
     if (!aligned(state_t_dev)) return fail(LB_EALIGN, "state_t_dev is not 256-byte aligned");
     if (state_next_dev && !aligned(state_next_dev))
         return fail(LB_EALIGN, "state_next_dev is not 256-byte aligned");
@@ -341,6 +351,7 @@ lb_status lb_adjoint_phi0(lb_ctx* ctx, double* dphi0_dev)
 {
     if (!ctx || !dphi0_dev) return fail(LB_EINVAL, "ctx and dphi0_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
+    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
     hipError_t e = lbk::launch_adj_phi0(ctx->kp, ctx->fp32, ctx->b.adj[ctx->adj_cur], dphi0_dev,
                                         ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_phi0");

@@ -322,6 +322,56 @@ __device__ __forceinline__ void collide(const KParams& p, T* f, T* g, const Sten
 }
 
 // ---------------------------------------------------------------------------
+// Force coupling (FP64): the chemical stress leaves f^eq and its central
+// divergence F = -div Pi acts as a body force, with the half-force velocity
+// u = (j + F/2)/rho and the forcing source (1 - omega/2) w [3(c - u) + 9(c.u) c].F
+// (Guo, Zheng and Shi), so one collision adds exactly F to the momentum.
+
+// mu and the chemical stress Pi (xx, xy, xz, yy, yz, zz) of one site.
+__device__ __forceinline__ void chem_stress(const KParams& p, const Stencil& st, double* mu,
+                                            double pi[6])
+{
+    const double phi = st.phi, phi2 = phi * phi, k = p.kappa;
+    *mu = p.A * phi + p.B * phi2 * phi - k * st.lap;
+    const double iso = 0.5 * p.A * phi2 + 0.75 * p.B * phi2 * phi2 - k * phi * st.lap
+                     - 0.5 * k * (st.gx * st.gx + st.gy * st.gy + st.gz * st.gz);
+    pi[0] = iso + k * st.gx * st.gx;
+    pi[1] = k * st.gx * st.gy;
+    pi[2] = k * st.gx * st.gz;
+    pi[3] = iso + k * st.gy * st.gy;
+    pi[4] = k * st.gy * st.gz;
+    pi[5] = iso + k * st.gz * st.gz;
+}
+
+// f^eq_i = w rho [1 + 3 c.u + 9/2 ((c.u)^2 - |u|^2/3)],
+// g^eq_i = w [phi + 3 phi c.u + 9/2 ((Gamma mu - phi/3)(|c|^2 - 1) + phi ((c.u)^2 - |u|^2/3))]
+__device__ __forceinline__ void collide_force(const KParams& p, double* f, double* g, double phi,
+                                              double mu, const double F[3])
+{
+    const Moments<double> m = moments_of<double, false>(p, f);
+    const double ri = 1.0 / m.rho;
+    const double ux = (m.jx + 0.5 * F[0]) * ri, uy = (m.jy + 0.5 * F[1]) * ri,
+                 uz = (m.jz + 0.5 * F[2]) * ri;
+    const double uu3 = (ux * ux + uy * uy + uz * uz) * (1.0 / 3.0);
+    const double sg = p.gamma * mu - phi * (1.0 / 3.0);
+    const double pref = 1.0 - 0.5 * p.omega_f;
+    const double uF = ux * F[0] + uy * F[1] + uz * F[2];
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        const double w = weight(i);
+        const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+        const double cF = CX[i] * F[0] + CY[i] * F[1] + CZ[i] * F[2];
+        const double q = cu * cu - uu3;
+        const double feq = w * m.rho * (1.0 + 3.0 * cu + 4.5 * q);
+        const double src = pref * w * (3.0 * (cF - uF) + 9.0 * cu * cF);
+        f[i] += p.omega_f * (feq - f[i]) + src;
+        const int c2 = CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i];
+        const double geq = w * (phi + 3.0 * phi * cu + 4.5 * (sg * (c2 - 1) + phi * q));
+        g[i] += p.omega_g * (geq - g[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Block reduction of K FP64 values (fixed order): wavefront butterfly, then
 // the block's NB/64 waves as a pairwise tree.  Thread 0 writes component k to
 // out[k*gridDim.x + blockIdx.x].  Needs blockDim.x == NB.

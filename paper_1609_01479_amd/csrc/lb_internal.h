@@ -23,6 +23,7 @@ struct KParams {
     double A, B, kappa, gamma;
     double omega_f, omega_g;  // 1/tau
     double rho0;
+    int force;  // force coupling (FP64 only): -div Pi as a body force
 };
 
 // Launch geometry of the single-pass step: (y, z) tiles times x segments.
@@ -43,7 +44,9 @@ void set_layout(KParams& k, int layout, int aosoa_len);
 // each (laid out per KParams) and, in FP32 mode, phi_c[stride] (FP64, site
 // order).  Order-parameter fields (`phi`) are FP64.
 hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* phi0, hipStream_t s);
-// variant 0: single-pass fused step; 1: phi pass + collision pass.
+// variant 0: single-pass fused step; 1: phi pass + collision pass.  The force
+// coupling always runs phi, Pi and collision passes, with phi_work holding
+// phi and Pi (7 fields of `stride`).
 // If sums_out is non-null, also writes the 5 FP64 conserved sums
 // [rho, phi, jx, jy, jz] of the source level to sums_out, through block
 // partials in `partials` (at least 5 * max(tc.ntiles * tc.nseg,
@@ -53,8 +56,11 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
                        double* sums_out, hipStream_t s);
 // phi(x) of the post-propagation state held in `state`.
 hipError_t launch_phi(const KParams& p, bool fp32, const void* state, double* phi, hipStream_t s);
+// work: FP64 fields the force coupling needs (phi, then the 6 components of
+// Pi, each `stride` long); unused otherwise.
 hipError_t launch_moments(const KParams& p, bool fp32, const void* state, double* rho, double* u,
-                          double* phi, double* partials, int* nblocks_out, hipStream_t s);
+                          double* phi, double* work, double* partials, int* nblocks_out,
+                          hipStream_t s);
 hipError_t launch_sums_final(const double* partials, int nblocks, int ncomp, double* out,
                              bool accumulate, hipStream_t s);
 hipError_t launch_export(const KParams& p, bool fp32, const void* state, double* f, double* g,

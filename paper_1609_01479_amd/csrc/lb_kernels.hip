@@ -160,6 +160,80 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// ---------------------------------------------------------------------------
+// Force coupling (FP64): after the phi pass, a pass for the chemical stress
+// Pi of every site, then the collision with F = -div Pi from Pi at the six
+// face neighbours (central differences).
+
+// Pi (xx, xy, xz, yy, yz, zz) of every site, each component `stride` long.
+__global__ __launch_bounds__(kBlock) void k_pi(KParams p, const double* __restrict__ phi,
+                                               double* __restrict__ pi)
+{
+    const int s = xcd_block() * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    const Geo q = geo_of(p, s);
+    const Stencil st = stencil(phi[s], phi[site_of(p, q.xp, q.y, q.z)], phi[site_of(p, q.xm, q.y, q.z)],
+                               phi[site_of(p, q.x, q.yp, q.z)], phi[site_of(p, q.x, q.ym, q.z)],
+                               phi[site_of(p, q.x, q.y, q.zp)], phi[site_of(p, q.x, q.y, q.zm)]);
+    double mu, t[6];
+    chem_stress(p, st, &mu, t);
+#pragma unroll
+    for (int k = 0; k < 6; k++) pi[k * p.stride + s] = t[k];
+}
+
+// F = -div Pi at site q (central differences of Pi at the face neighbours).
+__device__ __forceinline__ void force_at(const KParams& p, const Geo& q, const double* __restrict__ pi,
+                                         double F[3])
+{
+    // component of Pi_ab in the xx, xy, xz, yy, yz, zz storage
+    constexpr int K[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    const int np[3] = {site_of(p, q.xp, q.y, q.z), site_of(p, q.x, q.yp, q.z), site_of(p, q.x, q.y, q.zp)};
+    const int nm[3] = {site_of(p, q.xm, q.y, q.z), site_of(p, q.x, q.ym, q.z), site_of(p, q.x, q.y, q.zm)};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        double div = 0.0;
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            const double* t = pi + size_t(K[a][b]) * p.stride;
+            div += 0.5 * (t[np[b]] - t[nm[b]]);
+        }
+        F[a] = -div;
+    }
+}
+
+// The force-coupling collision and propagation, one site per thread; phi and
+// Pi of the source level (all sites) come from k_phi and k_pi.
+__global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const double* __restrict__ sF,
+                                                       const double* __restrict__ sG,
+                                                       const double* __restrict__ phi,
+                                                       const double* __restrict__ pi,
+                                                       double* __restrict__ dF,
+                                                       double* __restrict__ dG)
+{
+    const int s = xcd_block() * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    const Geo q = geo_of(p, s);
+    double f[NV], g[NV];
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        f[i] = sF[dist_pull(p, q, i)];
+        g[i] = sG[dist_pull(p, q, i)];
+    }
+    const double c = phi[s];
+    const double lap = (phi[site_of(p, q.xp, q.y, q.z)] + phi[site_of(p, q.xm, q.y, q.z)] - 2.0 * c)
+                     + (phi[site_of(p, q.x, q.yp, q.z)] + phi[site_of(p, q.x, q.ym, q.z)] - 2.0 * c)
+                     + (phi[site_of(p, q.x, q.y, q.zp)] + phi[site_of(p, q.x, q.y, q.zm)] - 2.0 * c);
+    const double mu = p.A * c + p.B * c * c * c - p.kappa * lap;
+    double F[3];
+    force_at(p, q, pi, F);
+    collide_force(p, f, g, c, mu, F);
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        dF[dist_own(p, q, i)] = f[i];
+        dG[dist_own(p, q, i)] = g[i];
+    }
+}
+
 // Wrap a coordinate v in [-2n, 3n) onto [0, n).
 __device__ __forceinline__ int wrapg(int v, int n)
 {
@@ -516,10 +590,13 @@ struct Fused<double> {
 
 // Dense FP64 moments of the post-propagation state and block partials of
 // [rho, phi, jx, jy, jz] (grid-stride, FP64 accumulation).
+// With pi (force coupling, FP64) the velocity is (j + F/2)/rho, F = -div Pi
+// of this state, and the momentum sums are those of j + F/2.
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restrict__ F,
                                                     const T* __restrict__ G,
                                                     const double* __restrict__ phic,
+                                                    const double* __restrict__ pi,
                                                     double* __restrict__ rho_out,
                                                     double* __restrict__ u_out,
                                                     double* __restrict__ phi_out,
@@ -542,6 +619,13 @@ __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restri
             jx += CX[i] * fv[i];
             jy += CY[i] * fv[i];
             jz += CZ[i] * fv[i];
+        }
+        if (pi) {
+            double fo[3];
+            force_at(p, q, pi, fo);
+            jx += 0.5 * fo[0];
+            jy += 0.5 * fo[1];
+            jz += 0.5 * fo[2];
         }
         if (rho_out) rho_out[s] = rho;
         if (u_out) {
@@ -753,6 +837,23 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
                        double* sums_out, hipStream_t s)
 {
     int nparts = 0;
+    if (p.force) {
+        // FP64 only (checked at creation): phi, Pi, then the forcing collision
+        Lvl<double> a = level<double>(const_cast<void*>(src), p, false);
+        Lvl<double> d = level<double>(dst, p, false);
+        double* pi = phi_work + p.stride;
+        if (sums_out) {
+            nparts = reduction_grid(p);
+            k_moments<double, false, false><<<nparts, kBlock, 0, s>>>(p, a.F, a.G, nullptr, nullptr,
+                                                                      nullptr, nullptr, nullptr,
+                                                                      partials);
+        }
+        k_phi<double, false><<<grid_for(p), kBlock, 0, s>>>(p, a.G, nullptr, phi_work);
+        k_pi<<<grid_for(p), kBlock, 0, s>>>(p, phi_work, pi);
+        k_step_force<<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, phi_work, pi, d.F, d.G);
+        if (sums_out) k_sums_final<<<1, kBlock, 0, s>>>(partials, nparts, 5, sums_out, 0);
+        return hipGetLastError();
+    }
 #define CALL                                                                                    \
     {                                                                                           \
         Lvl<T> a = level<T>(const_cast<void*>(src), p, REF);                                    \
@@ -766,7 +867,8 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
             if (sums_out) {                                                                     \
                 nparts = reduction_grid(p);                                                     \
                 k_moments<T, DEV, REF><<<nparts, kBlock, 0, s>>>(p, a.F, a.G, a.phic, nullptr,  \
-                                                                 nullptr, nullptr, partials);   \
+                                                                 nullptr, nullptr, nullptr,     \
+                                                                 partials);                     \
             }                                                                                   \
             double* phin = REF ? d.phic : phi_work;                                             \
             k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);                 \
@@ -793,14 +895,23 @@ hipError_t launch_phi(const KParams& p, bool fp32, const void* state, double* ph
 }
 
 hipError_t launch_moments(const KParams& p, bool fp32, const void* state, double* rho, double* u,
-                          double* phi, double* partials, int* nblocks_out, hipStream_t s)
+                          double* phi, double* work, double* partials, int* nblocks_out,
+                          hipStream_t s)
 {
     const int nb = reduction_grid(p);
     *nblocks_out = nb;
+    double* pi = nullptr;
+    if (p.force && (u || partials)) {
+        // F of this state: phi and Pi into the work fields first
+        Lvl<double> a = level<double>(const_cast<void*>(state), p, false);
+        pi = work + p.stride;
+        k_phi<double, false><<<grid_for(p), kBlock, 0, s>>>(p, a.G, nullptr, work);
+        k_pi<<<grid_for(p), kBlock, 0, s>>>(p, work, pi);
+    }
 #define CALL                                                                                  \
     {                                                                                         \
         Lvl<T> a = level<T>(const_cast<void*>(state), p, REF);                                \
-        k_moments<T, DEV, REF><<<nb, kBlock, 0, s>>>(p, a.F, a.G, a.phic, rho, u, phi,       \
+        k_moments<T, DEV, REF><<<nb, kBlock, 0, s>>>(p, a.F, a.G, a.phic, pi, rho, u, phi,   \
                                                      partials);                               \
     }
     LB_DISPATCH(fp32, CALL, CALL);

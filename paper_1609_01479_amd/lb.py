@@ -17,6 +17,8 @@ from ._abi import LB_FP32_DEV, LB_FP64, NVEL, check
 
 # distribution layouts (lb_layout); every layout gives bit-identical results
 LAYOUTS = {"rows": 0, "soa": 1, "aos": 2, "aosoa": 3}
+# how the chemical stress drives the flow (lb_coupling); "force" is FP64 only
+COUPLINGS = {"stress": 0, "force": 1}
 
 
 def _precision_code(precision) -> int:
@@ -42,12 +44,14 @@ class LB:
     layout: memory layout of the distributions, "rows" (row-blocked, default),
         "soa", "aos" or "aosoa" with aosoa_len z-sites per block (a power of
         two dividing nz); results are bit-identical across layouts.
+    coupling: "stress" (Pi in the f equilibrium, default) or "force" (body
+        force -div Pi with the half-force velocity; FP64, no adjoint).
     """
 
     def __init__(self, shape, *, A=-0.00625, B=0.00625, kappa=0.004, gamma=0.5, tau_f=1.0,
                  tau_g=1.0, rho0=1.0, precision="fp64", adjoint=False, device=None,
                  stream: torch.cuda.Stream | None = None, kernel="fused", segment_x=0,
-                 layout="rows", aosoa_len=0):
+                 layout="rows", aosoa_len=0, coupling="stress"):
         L = _abi.lib()
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
@@ -56,7 +60,7 @@ class LB:
         self.params = _abi.LbParams(nx, ny, nz, float(A), float(B), float(kappa), float(gamma),
                                     float(tau_f), float(tau_g), float(rho0), self.precision,
                                     {"fused": 0, "two_pass": 1}[kernel], int(segment_x),
-                                    LAYOUTS[layout], int(aosoa_len))
+                                    LAYOUTS[layout], int(aosoa_len), COUPLINGS[coupling])
         self.sizes = _abi.LbSizes()
         check(L.lb_query_sizes(ctypes.byref(self.params), ctypes.byref(self.sizes)),
               "lb_query_sizes")

@@ -72,11 +72,30 @@ def test_query_sizes(abi):
     (dict(layout=4), "LB_EINVAL"), (dict(layout=-1), "LB_EINVAL"),
     (dict(layout=3, aosoa_len=3), "LB_ESHAPE"), (dict(layout=3, aosoa_len=0), "LB_ESHAPE"),
     (dict(layout=3, aosoa_len=64, nz=96), "LB_ESHAPE"),
+    (dict(coupling=2), "LB_EINVAL"), (dict(coupling=1, precision=1), "LB_EINVAL"),
 ])
 def test_bad_parameters_rejected(abi, kw, code):
     st, _ = _query(abi, **kw)
     assert st == getattr(abi, code)
     assert abi.lib().lb_last_error().decode()
+
+
+def test_force_coupling_sizes_and_no_adjoint(abi):
+    """The force coupling needs 7 FP64 work fields (phi and Pi) and has no
+    adjoint: the reverse-mode calls return LB_ESTATE before any HIP call."""
+    st, s1 = _query(abi, coupling=1)
+    assert st == abi.LB_OK and s1.phi_bytes == 7 * s1.stride_elems * 8
+    L = abi.lib()
+    p = _params(abi, coupling=1)
+    ctx = ctypes.c_void_p()
+    b = abi.LbBuffers()
+    b.state[0], b.state[1], b.phi, b.scratch = 0x1000, 0x2000, 0x3000, 0x4000
+    b.adj[0], b.adj[1], b.adj_scratch = 0x5000, 0x6000, 0x7000
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
+    assert L.lb_adjoint_seed(ctx, ctypes.c_void_p(0x8000)) == abi.LB_ESTATE
+    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), None, None) == abi.LB_ESTATE
+    assert L.lb_adjoint_phi0(ctx, ctypes.c_void_p(0x8000)) == abi.LB_ESTATE
+    L.lb_destroy(ctx)
 
 
 def test_fp32_plane_limit_is_twice_fp64(abi):

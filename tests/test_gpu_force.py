@@ -1,0 +1,93 @@
+"""Parity of the force coupling (body force -div Pi with Guo forcing, FP64)
+between the HIP path (through the C ABI) and the CPU oracle.
+
+Bar: for every output field F (f, g, rho, u, phi; u = (j + F/2)/rho),
+max_x |F_gpu - F_oracle| / max_x |F_oracle| <= 1e-12 (u on scale 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import lbinputs
+import oracle
+from tests._gpu import field_errors, gpu_state, make_lb, oracle_params, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _run_both(shape, steps, phi0, **kw):
+    print(f"[force] shape={shape} steps={steps} params={kw}", flush=True)
+    lb = make_lb(shape, coupling="force", **kw)
+    lb.init_phi(phi0)
+    lb.step(steps)
+    got = gpu_state(lb)
+    p = oracle_params(shape, coupling=1, **kw)
+    ref = oracle_state(p, *oracle.run(p, *oracle.init(p, phi0), steps))
+    return got, ref, lb, p
+
+
+@pytest.mark.parametrize("steps", [0, 1, 10, 100])
+def test_force_spinodal_16cubed(steps):
+    shape = (16, 16, 16)
+    got, ref, *_ = _run_both(shape, steps, lbinputs.spinodal_phi0(shape))
+    errs = field_errors(got, ref)
+    assert max(errs.values()) <= TOL, errs
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (3, 5, 131), (17, 9, 70), (1, 7, 1), (2, 2, 2)])
+def test_force_noncubic_ragged_degenerate_tau_not_one(shape):
+    phi0 = lbinputs.spinodal_phi0(shape, seed=12, amp=0.4)
+    got, ref, *_ = _run_both(shape, 25, phi0, tau_f=0.8, tau_g=1.3)
+    errs = field_errors(got, ref)
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_force_droplet_interface():
+    """A sharp tanh droplet: the force is large at the interface."""
+    shape = (24, 20, 22)
+    pr = lbinputs.SPINODAL_PARAMS
+    xi = lbinputs.interface_width(pr["A"], pr["kappa"])
+    phi0 = lbinputs.droplet_phi0(shape, 6.0, xi, noise=1e-3, seed=3)
+    got, ref, lb, p = _run_both(shape, 50, phi0)
+    errs = field_errors(got, ref)
+    assert max(errs.values()) <= TOL, errs
+    # the sums: mass, phi and momentum of rho u = j + F/2
+    np.testing.assert_allclose(lb.sums().cpu().numpy(), oracle.sums(p, *oracle.run(
+        p, *oracle.init(p, phi0), 50)), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("layout,v", [("soa", 0), ("aosoa", 8)])
+def test_force_layouts_bit_identical(layout, v):
+    shape = (6, 7, 16)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=8, amp=0.3)
+    out = []
+    for lay, vv in (("rows", 0), (layout, v)):
+        lb = make_lb(shape, coupling="force", layout=lay, aosoa_len=vv, tau_f=0.9)
+        lb.init_phi(phi0)
+        lb.step(9)
+        out.append(gpu_state(lb))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+def test_force_step_sums_and_determinism():
+    """Per-step FP64 sums are conserved (mass, phi; momentum to round-off), and
+    two runs from one checkpoint agree bit for bit."""
+    shape = (12, 10, 14)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=2, amp=0.3)
+    lb = make_lb(shape, coupling="force", tau_f=0.8, tau_g=1.1)
+    lb.init_phi(phi0)
+    hist = lb.step_sums(30).cpu().numpy()
+    assert np.abs(hist[:, :2] - hist[0, :2]).max() <= 1e-11
+    assert np.abs(hist[:, 2:] - hist[0, 2:]).max() <= 1e-12
+    ck = lb.get_state()
+    lb.step(7)
+    a = gpu_state(lb)
+    lb.set_state(ck)
+    lb.step(7)
+    b = gpu_state(lb)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
