@@ -97,6 +97,22 @@ def test_sampled_parity_large_regions(precision, shape, tol):
     _sampled_parity(shape, precision, phi0, 2, dict(tau_f=0.8, tau_g=1.3), tol, nsample=12)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_dev", 2e-6)])
+def test_sampled_parity_maximum_size(precision, tol):
+    """479^3, the largest cube the library accepts (39 * stride just under
+    2^32 elements: every 32-bit element index near its limit), ragged in every
+    tile dimension; 480^3 is rejected."""
+    from paper_1609_01479_amd import LB
+    from paper_1609_01479_amd._abi import LbError
+    with pytest.raises(LbError):
+        LB((480, 480, 480), precision=precision, device="cuda:0")
+    shape = (479, 479, 479)
+    pr = lbinputs.SPINODAL_PARAMS
+    xi = lbinputs.interface_width(pr["A"], pr["kappa"])
+    phi0 = lbinputs.droplet_phi0(shape, 100.0, xi, noise=1e-3, seed=lbinputs.SEED_DROPLET)
+    _sampled_parity(shape, precision, phi0, 1, dict(tau_f=0.8, tau_g=1.3), tol, nsample=10)
+
+
 def test_sampled_parity_spinodal_128_fp64():
     shape = (128, 128, 128)
     _sampled_parity(shape, "fp64", lbinputs.spinodal_phi0(shape), 20, {}, 1e-12)
