@@ -28,6 +28,7 @@ struct KParams {
 
 // Launch geometry of the single-pass step: (y, z) tiles times x segments.
 struct TileCfg {
+    int tz;                // tile width along z (128 or 64; kFused/tz rows)
     int nty, ntz, ntiles;  // tiles along y, along z, total
     int sx, nseg;          // planes per x segment, number of segments
 };

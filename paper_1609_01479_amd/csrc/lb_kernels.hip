@@ -25,10 +25,11 @@ using namespace dev;
 
 namespace {
 
-// Tile of the single-pass kernel: TY rows of TZ contiguous z-sites, one
-// site per thread of a kFused-thread workgroup (measured on MI355X at 256^3:
-// 4 x 128 tiles of 512 threads beat 4 x 64 and 8 x 64; the longer z runs
-// give each component stream 512-byte (FP32) contiguous row pieces).
+// Tiles of the single-pass kernel: TY rows of TZ contiguous z-sites, one
+// site per thread of a kFused-thread workgroup: 4 x 128 (measured on MI355X at
+// 256^3 against 4 x 64 and 8 x 64: the longer z runs give each component
+// stream 512-byte (FP32) contiguous pieces), or 8 x 64 where that covers nz
+// with fewer idle lanes (e.g. nz = 192: 64 + 64 + 64 instead of 128 + 64).
 constexpr int kFused = 512;
 #ifndef LB_PIPE32
 #define LB_PIPE32 true
@@ -36,10 +37,9 @@ constexpr int kFused = 512;
 #ifndef LB_PIPE64
 #define LB_PIPE64 false
 #endif
-constexpr int TZ = 128;
-constexpr int TY = kFused / TZ;
 // one thread per halo-ring cell (2 rows, 2 columns, 4 corners)
-static_assert(2 * TZ + 2 * TY + 4 <= kFused, "halo ring larger than the workgroup");
+static_assert(2 * 128 + 2 * (kFused / 128) + 4 <= kFused, "halo ring larger than the workgroup");
+static_assert(2 * 64 + 2 * (kFused / 64) + 4 <= kFused, "halo ring larger than the workgroup");
 
 template <typename T>
 struct Lvl {
@@ -303,7 +303,7 @@ __device__ __forceinline__ Yz9 yz9(const KParams& p, int y, int z)
 // site); the store of direction i needs phi at the destination y + c_i, which
 // the LDS phi ring already holds (its halo then includes the tile's 4 corner
 // cells, for the directions with c_x = 0 and c_y, c_z != 0).
-template <typename T, bool DEV, bool REF, bool SMALL, bool PIPE>
+template <typename T, bool DEV, bool REF, bool SMALL, bool PIPE, int TZ>
 __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg& tc,
                                                 const T* __restrict__ sF,
                                                 const T* __restrict__ sG,
@@ -312,6 +312,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
                                                 double* __restrict__ dphic,
                                                 double* __restrict__ partials)
 {
+    constexpr int TY = kFused / TZ;
     __shared__ double ph[4][TY + 2][TZ + 2];
     // value kept per direction between the phi pull and the collision: the
     // stored FP32 deviation (FP32 mode) or the FP64 population
@@ -557,35 +558,46 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     if (partials) block_partials<5, kFused>(acc, partials);
 }
 
-template <bool SMALL>
+template <bool SMALL, int TZ>
 __global__ __launch_bounds__(kFused) void k_step_fused_f32(
     KParams p, TileCfg tc, const float* __restrict__ sF, const float* __restrict__ sG,
     const double* __restrict__ sphic, float* __restrict__ dF, float* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<float, true, true, SMALL, LB_PIPE32>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
+    step_fused_body<float, true, true, SMALL, LB_PIPE32, TZ>(p, tc, sF, sG, sphic, dF, dG, dphic,
+                                                             partials);
 }
 
-template <bool SMALL>
+template <bool SMALL, int TZ>
 __global__ __launch_bounds__(kFused) void k_step_fused_f64(
     KParams p, TileCfg tc, const double* __restrict__ sF, const double* __restrict__ sG,
     const double* __restrict__ sphic, double* __restrict__ dF, double* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<double, false, false, SMALL, LB_PIPE64>(p, tc, sF, sG, sphic, dF, dG, dphic, partials);
+    step_fused_body<double, false, false, SMALL, LB_PIPE64, TZ>(p, tc, sF, sG, sphic, dF, dG,
+                                                                dphic, partials);
 }
 
+// the single-pass kernel for an offset width and a tile width
 template <typename T>
 struct Fused;
 template <>
 struct Fused<float> {
-    static constexpr auto small = k_step_fused_f32<true>;
-    static constexpr auto large = k_step_fused_f32<false>;
+    using K = decltype(&k_step_fused_f32<true, 128>);
+    static K get(bool small, int tz)
+    {
+        if (tz == 64) return small ? k_step_fused_f32<true, 64> : k_step_fused_f32<false, 64>;
+        return small ? k_step_fused_f32<true, 128> : k_step_fused_f32<false, 128>;
+    }
 };
 template <>
 struct Fused<double> {
-    static constexpr auto small = k_step_fused_f64<true>;
-    static constexpr auto large = k_step_fused_f64<false>;
+    using K = decltype(&k_step_fused_f64<true, 128>);
+    static K get(bool small, int tz)
+    {
+        if (tz == 64) return small ? k_step_fused_f64<true, 64> : k_step_fused_f64<false, 64>;
+        return small ? k_step_fused_f64<true, 128> : k_step_fused_f64<false, 128>;
+    }
 };
 
 // Dense FP64 moments of the post-propagation state and block partials of
@@ -798,21 +810,38 @@ void set_layout(KParams& k, int layout, int aosoa_len)
     }
 }
 
+// Number of CUs of an MI355X: with 512-thread workgroups at 2 waves per SIMD,
+// one workgroup per CU runs at a time.
+constexpr int kCUs = 256;
+
 TileCfg tile_config(const KParams& p, int segment_x, bool fp32)
 {
     (void)fp32;  // same tiling for both storage modes
     TileCfg tc;
-    tc.nty = (p.ny + TY - 1) / TY;
-    tc.ntz = (p.nz + TZ - 1) / TZ;
+    // tile width: 128 unless 64 leaves fewer idle lanes along z
+    const long long w128 = 128LL * ((p.nz + 127) / 128), w64 = 64LL * ((p.nz + 63) / 64);
+    tc.tz = w64 < w128 ? 64 : 128;
+    const int ty = kFused / tc.tz;
+    tc.nty = (p.ny + ty - 1) / ty;
+    tc.ntz = (p.nz + tc.tz - 1) / tc.tz;
     tc.ntiles = tc.nty * tc.ntz;
     int sx = segment_x;
     if (sx <= 0) {
-        // measured on MI355X at 256^3: both kernels stream best with about
-        // one workgroup per CU (256), i.e. the longest segments and the
-        // fewest concurrent DRAM streams.  Segments of at least 8 planes.
-        const long long target = 256;
-        const long long want = (long long)p.nx * tc.ntiles / target;
-        sx = int(want < 8 ? 8 : want);
+        // Segments along x: a workgroup marches sx planes after 2 warm-up
+        // planes, and workgroups run in rounds of kCUs.  Pick the segment
+        // count minimising rounds * (sx + 2) (fewest workgroups on ties);
+        // this fits measured times at 128^3 to 256^3 within 10%.
+        long long best = -1;
+        for (int nseg = 1; nseg <= p.nx; nseg++) {
+            const int s = (p.nx + nseg - 1) / nseg;
+            const long long nb = (long long)tc.ntiles * ((p.nx + s - 1) / s);
+            const long long rounds = (nb + kCUs - 1) / kCUs;
+            const long long cost = rounds * (s + 2);
+            if (best < 0 || cost < best) {
+                best = cost;
+                sx = s;
+            }
+        }
     }
     if (sx > p.nx) sx = p.nx;
     tc.sx = sx;
@@ -860,7 +889,7 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
         Lvl<T> d = level<T>(dst, p, REF);                                                       \
         if (variant == 0) {                                                                     \
             nparts = tc.ntiles * tc.nseg;                                                       \
-            auto kern = small_arrays(p, sizeof(T)) ? Fused<T>::small : Fused<T>::large;        \
+            auto kern = Fused<T>::get(small_arrays(p, sizeof(T)), tc.tz);                      \
             kern<<<nparts, kFused, 0, s>>>(p, tc, a.F, a.G, a.phic, d.F, d.G, d.phic,           \
                                            sums_out ? partials : nullptr);                      \
         } else {                                                                                \
