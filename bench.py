@@ -140,7 +140,7 @@ def main():
                     help="distribution layout of the 256^3 legs (default: row-blocked)")
     ap.add_argument("--aosoa-len", type=int, default=64, help="z-sites per block for --layout aosoa")
     ap.add_argument("--force-steps", type=int, default=200,
-                    help="steps of the 256^3 FP64 force-coupling line (0: skip)")
+                    help="steps of the 256^3 force-coupling lines (0: skip)")
     ap.add_argument("--spinodal-steps", type=int, default=1000,
                     help="steps of the extra 128^3 FP64 spinodal throughput line (0: skip)")
     args = ap.parse_args()
@@ -254,24 +254,27 @@ def main():
                                      "u_rms": float(np.sqrt((du ** 2).mean()))}
     del runs
 
-    # FP64 force coupling (body force -div Pi) on the same 256^3 droplet: phi,
-    # Pi and collision passes move 880 B per site (160 + 56 + 664) against the
-    # method's 608
+    # force coupling (body force -div Pi) on the same 256^3 droplet: the phi,
+    # Pi and collision passes move 880 B per site in FP64 (160 + 56 + 664) and
+    # 516 in FP32 storage (92 + 56 + 368), against the method's 608 and 320
     if args.force_steps > 0:
-        lb = LB(shape, precision="fp64", coupling="force", device="cuda:0", **lay, **params)
-        lb.init_phi(phi0)
-        log(f"fp64 force coupling {shape}: {args.force_steps} steps")
-        ms = time_steps(lb, args.force_steps, args.warmup)
-        t = ms / args.force_steps * 1e-3
-        out["fp64_force_coupling"] = {
-            "value": round(nsites / t / 1e6, 1), "unit": "MLUPS", "steps": args.force_steps,
-            "ms_per_step": round(ms / args.force_steps, 4),
-            "achieved_GBps": round(880 * nsites / t / 1e9, 1),
-            "frac": round(880 * nsites / t / 1e9 / HBM_PEAK_GBPS, 4),
-            "effective_GBps": round(608 * nsites / t / 1e9, 1),
-            "kernels": "k_phi + k_pi + k_step_force"}
-        del lb
-        torch.cuda.empty_cache()
+        out["force_coupling"] = {}
+        for prec, moved, minimum in (("fp32_dev", 516, 320), ("fp64", 880, 608)):
+            lb = LB(shape, precision=prec, coupling="force", device="cuda:0", **lay, **params)
+            lb.init_phi(phi0)
+            log(f"{prec} force coupling {shape}: {args.force_steps} steps")
+            ms = time_steps(lb, args.force_steps, args.warmup)
+            t = ms / args.force_steps * 1e-3
+            out["force_coupling"][prec] = {
+                "value": round(nsites / t / 1e6, 1), "unit": "MLUPS", "steps": args.force_steps,
+                "ms_per_step": round(ms / args.force_steps, 4),
+                "achieved_GBps": round(moved * nsites / t / 1e9, 1),
+                "frac": round(moved * nsites / t / 1e9 / HBM_PEAK_GBPS, 4),
+                "bytes_per_site": moved,
+                "effective_GBps": round(minimum * nsites / t / 1e9, 1),
+                "kernels": "k_phi + k_pi + k_step_force"}
+            del lb
+            torch.cuda.empty_cache()
 
     # FP64 on the 128^3 spinodal-decomposition lattice (phi0 ~ U(-0.05, 0.05))
     if not args.no_fp64 and args.spinodal_steps > 0:

@@ -83,14 +83,14 @@ typedef enum {
     LB_KERNEL_TWO_PASS = 1 /* a phi pass, then the stencil/collision pass  */
 } lb_kernel;
 
-/* How the chemical stress Pi drives the flow (both FP64 forms of the same
+/* How the chemical stress Pi drives the flow (two forms of the same
  * hydrodynamics to leading order): */
 typedef enum {
     LB_COUPLING_STRESS = 0, /* Pi in f^eq's second moment (default)         */
     LB_COUPLING_FORCE = 1   /* body force F = -div Pi (central differences)
                                with the half-force velocity u = (j + F/2)/rho
-                               and Guo's forcing term; LB_FP64 only, no
-                               adjoint; runs phi, Pi and collision passes   */
+                               and Guo's forcing term; no adjoint; runs phi,
+                               Pi and collision passes                      */
 } lb_coupling;
 
 /* Memory layout of the f and g regions of a time level (opaque to callers,

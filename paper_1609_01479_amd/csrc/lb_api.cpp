@@ -75,8 +75,6 @@ lb_status validate(const lb_params* p)
         return fail(LB_EINVAL, "unknown layout %d", p->layout);
     if (p->coupling != LB_COUPLING_STRESS && p->coupling != LB_COUPLING_FORCE)
         return fail(LB_EINVAL, "unknown coupling %d", p->coupling);
-    if (p->coupling == LB_COUPLING_FORCE && p->precision != LB_FP64)
-        return fail(LB_EINVAL, "the force coupling is available in LB_FP64 only");
     if (p->layout == LB_LAYOUT_AOSOA) {
         const int v = p->aosoa_len;
         if (v < 1 || (v & (v - 1)) != 0 || p->nz % v != 0)

@@ -343,31 +343,39 @@ __device__ __forceinline__ void chem_stress(const KParams& p, const Stencil& st,
     pi[5] = iso + k * st.gz * st.gz;
 }
 
-// f^eq_i = w rho [1 + 3 c.u + 9/2 ((c.u)^2 - |u|^2/3)],
-// g^eq_i = w [phi + 3 phi c.u + 9/2 ((Gamma mu - phi/3)(|c|^2 - 1) + phi ((c.u)^2 - |u|^2/3))]
-__device__ __forceinline__ void collide_force(const KParams& p, double* f, double* g, double phi,
-                                              double mu, const double F[3])
+// In place on f[] and g[] in the stored convention (as collide()), in T:
+//   f^eq_i = w rho [1 + 3 c.u + 9/2 ((c.u)^2 - |u|^2/3)],
+//   g^eq_i = w [phi + 3 phi c.u + 9/2 ((Gamma mu - phi/3)(|c|^2 - 1) + phi ((c.u)^2 - |u|^2/3))],
+//   g^eq_i - r_i phi = w [3 phi c.u + 9/2 (Gamma mu (|c|^2 - 1) + phi ((c.u)^2 - |u|^2/3))],
+//   f*_i = f_i + omega_f (f^eq_i - f_i) + (1 - omega_f/2) w [3 (c - u).F + 9 (c.u)(c.F)].
+template <typename T, bool DEV, bool REF>
+__device__ __forceinline__ void collide_force(const KParams& p, T* f, T* g, double phi_d, double mu_d,
+                                              const double Fd[3])
 {
-    const Moments<double> m = moments_of<double, false>(p, f);
-    const double ri = 1.0 / m.rho;
-    const double ux = (m.jx + 0.5 * F[0]) * ri, uy = (m.jy + 0.5 * F[1]) * ri,
-                 uz = (m.jz + 0.5 * F[2]) * ri;
-    const double uu3 = (ux * ux + uy * uy + uz * uz) * (1.0 / 3.0);
-    const double sg = p.gamma * mu - phi * (1.0 / 3.0);
-    const double pref = 1.0 - 0.5 * p.omega_f;
-    const double uF = ux * F[0] + uy * F[1] + uz * F[2];
+    const Moments<T> m = moments_of<T, DEV>(p, f);
+    const T phi = T(phi_d), mu = T(mu_d);
+    const T F[3] = {T(Fd[0]), T(Fd[1]), T(Fd[2])};
+    const T ri = T(1) / m.rho;
+    const T ux = (m.jx + T(0.5) * F[0]) * ri, uy = (m.jy + T(0.5) * F[1]) * ri,
+            uz = (m.jz + T(0.5) * F[2]) * ri;
+    const T uu3 = (ux * ux + uy * uy + uz * uz) * T(1.0 / 3.0);
+    const T gm = T(p.gamma) * mu, sg = REF ? gm : gm - phi * T(1.0 / 3.0);
+    const T omf = T(p.omega_f), omg = T(p.omega_g);
+    const T pref = T(1) - T(0.5) * omf;
+    const T uF = ux * F[0] + uy * F[1] + uz * F[2];
 #pragma unroll
     for (int i = 0; i < NV; i++) {
-        const double w = weight(i);
-        const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-        const double cF = CX[i] * F[0] + CY[i] * F[1] + CZ[i] * F[2];
-        const double q = cu * cu - uu3;
-        const double feq = w * m.rho * (1.0 + 3.0 * cu + 4.5 * q);
-        const double src = pref * w * (3.0 * (cF - uF) + 9.0 * cu * cF);
-        f[i] += p.omega_f * (feq - f[i]) + src;
-        const int c2 = CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i];
-        const double geq = w * (phi + 3.0 * phi * cu + 4.5 * (sg * (c2 - 1) + phi * q));
-        g[i] += p.omega_g * (geq - g[i]);
+        const T w = T(weight(i));
+        const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
+        const T cF = T(CX[i]) * F[0] + T(CY[i]) * F[1] + T(CZ[i]) * F[2];
+        const T q = cu * cu - uu3;
+        // f^eq in the stored convention: w [b + rho (3 c.u + 9/2 q)], b = sum of the stored f
+        const T feq = w * (m.b + m.rho * (T(3) * cu + T(4.5) * q));
+        const T src = pref * w * (T(3) * (cF - uF) + T(9) * cu * cF);
+        f[i] += omf * (feq - f[i]) + src;
+        const T c2m1 = T(CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i] - 1);
+        const T geq = w * ((REF ? T(0) : phi) + T(3) * phi * cu + T(4.5) * (sg * c2m1 + phi * q));
+        g[i] += omg * (geq - g[i]);
     }
 }
 

@@ -23,7 +23,7 @@ struct KParams {
     double A, B, kappa, gamma;
     double omega_f, omega_g;  // 1/tau
     double rho0;
-    int force;  // force coupling (FP64 only): -div Pi as a body force
+    int force;  // force coupling: -div Pi as a body force
 };
 
 // Launch geometry of the single-pass step: (y, z) tiles times x segments.

@@ -202,18 +202,20 @@ __device__ __forceinline__ void force_at(const KParams& p, const Geo& q, const d
 }
 
 // The force-coupling collision and propagation, one site per thread; phi and
-// Pi of the source level (all sites) come from k_phi and k_pi.
-__global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const double* __restrict__ sF,
-                                                       const double* __restrict__ sG,
+// Pi of the source level (all sites) come from k_phi and k_pi.  In FP32 mode
+// phi is the destination level's phi_c field (as in k_step_2s).
+template <typename T, bool DEV, bool REF>
+__global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const T* __restrict__ sF,
+                                                       const T* __restrict__ sG,
+                                                       const double* __restrict__ sphic,
                                                        const double* __restrict__ phi,
                                                        const double* __restrict__ pi,
-                                                       double* __restrict__ dF,
-                                                       double* __restrict__ dG)
+                                                       T* __restrict__ dF, T* __restrict__ dG)
 {
     const int s = xcd_block() * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
     const Geo q = geo_of(p, s);
-    double f[NV], g[NV];
+    T f[NV], g[NV];
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         f[i] = sF[dist_pull(p, q, i)];
@@ -224,13 +226,18 @@ __global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const double* 
                      + (phi[site_of(p, q.x, q.yp, q.z)] + phi[site_of(p, q.x, q.ym, q.z)] - 2.0 * c)
                      + (phi[site_of(p, q.x, q.y, q.zp)] + phi[site_of(p, q.x, q.y, q.zm)] - 2.0 * c);
     const double mu = p.A * c + p.B * c * c * c - p.kappa * lap;
+    if (REF) {
+        const double dphi = c - sphic[s];
+#pragma unroll
+        for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, g[i], dphi);
+    }
     double F[3];
     force_at(p, q, pi, F);
-    collide_force(p, f, g, c, mu, F);
+    collide_force<T, DEV, REF>(p, f, g, c, mu, F);
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         dF[dist_own(p, q, i)] = f[i];
-        dG[dist_own(p, q, i)] = g[i];
+        dG[dist_own(p, q, i)] = REF ? to_dest_ref(i, g[i], c, phi[push_site(p, q, i)]) : g[i];
     }
 }
 
@@ -602,7 +609,7 @@ struct Fused<double> {
 
 // Dense FP64 moments of the post-propagation state and block partials of
 // [rho, phi, jx, jy, jz] (grid-stride, FP64 accumulation).
-// With pi (force coupling, FP64) the velocity is (j + F/2)/rho, F = -div Pi
+// With pi (force coupling) the velocity is (j + F/2)/rho, F = -div Pi
 // of this state, and the momentum sums are those of j + F/2.
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restrict__ F,
@@ -867,19 +874,26 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
 {
     int nparts = 0;
     if (p.force) {
-        // FP64 only (checked at creation): phi, Pi, then the forcing collision
-        Lvl<double> a = level<double>(const_cast<void*>(src), p, false);
-        Lvl<double> d = level<double>(dst, p, false);
-        double* pi = phi_work + p.stride;
-        if (sums_out) {
-            nparts = reduction_grid(p);
-            k_moments<double, false, false><<<nparts, kBlock, 0, s>>>(p, a.F, a.G, nullptr, nullptr,
-                                                                      nullptr, nullptr, nullptr,
-                                                                      partials);
-        }
-        k_phi<double, false><<<grid_for(p), kBlock, 0, s>>>(p, a.G, nullptr, phi_work);
-        k_pi<<<grid_for(p), kBlock, 0, s>>>(p, phi_work, pi);
-        k_step_force<<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, phi_work, pi, d.F, d.G);
+        // phi (the new level's phi_c in FP32 mode), Pi, then the forcing collision
+#define CALL                                                                                   \
+    {                                                                                          \
+        Lvl<T> a = level<T>(const_cast<void*>(src), p, REF);                                   \
+        Lvl<T> d = level<T>(dst, p, REF);                                                      \
+        double* phin = REF ? d.phic : phi_work;                                                \
+        double* pi = phi_work + p.stride;                                                      \
+        if (sums_out) {                                                                        \
+            nparts = reduction_grid(p);                                                        \
+            k_moments<T, DEV, REF><<<nparts, kBlock, 0, s>>>(p, a.F, a.G, a.phic, nullptr,     \
+                                                             nullptr, nullptr, nullptr,        \
+                                                             partials);                        \
+        }                                                                                      \
+        k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);                    \
+        k_pi<<<grid_for(p), kBlock, 0, s>>>(p, phin, pi);                                      \
+        k_step_force<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phin,    \
+                                                                 pi, d.F, d.G);                \
+    }
+        LB_DISPATCH(fp32, CALL, CALL);
+#undef CALL
         if (sums_out) k_sums_final<<<1, kBlock, 0, s>>>(partials, nparts, 5, sums_out, 0);
         return hipGetLastError();
     }
@@ -932,9 +946,14 @@ hipError_t launch_moments(const KParams& p, bool fp32, const void* state, double
     double* pi = nullptr;
     if (p.force && (u || partials)) {
         // F of this state: phi and Pi into the work fields first
-        Lvl<double> a = level<double>(const_cast<void*>(state), p, false);
         pi = work + p.stride;
-        k_phi<double, false><<<grid_for(p), kBlock, 0, s>>>(p, a.G, nullptr, work);
+#define CALL                                                                                  \
+    {                                                                                         \
+        Lvl<T> a = level<T>(const_cast<void*>(state), p, REF);                                \
+        k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, work);                   \
+    }
+        LB_DISPATCH(fp32, CALL, CALL);
+#undef CALL
         k_pi<<<grid_for(p), kBlock, 0, s>>>(p, work, pi);
     }
 #define CALL                                                                                  \

@@ -17,7 +17,7 @@ from ._abi import LB_FP32_DEV, LB_FP64, NVEL, check
 
 # distribution layouts (lb_layout); every layout gives bit-identical results
 LAYOUTS = {"rows": 0, "soa": 1, "aos": 2, "aosoa": 3}
-# how the chemical stress drives the flow (lb_coupling); "force" is FP64 only
+# how the chemical stress drives the flow (lb_coupling)
 COUPLINGS = {"stress": 0, "force": 1}
 
 
@@ -45,7 +45,7 @@ class LB:
         "soa", "aos" or "aosoa" with aosoa_len z-sites per block (a power of
         two dividing nz); results are bit-identical across layouts.
     coupling: "stress" (Pi in the f equilibrium, default) or "force" (body
-        force -div Pi with the half-force velocity; FP64, no adjoint).
+        force -div Pi with the half-force velocity; no adjoint).
     """
 
     def __init__(self, shape, *, A=-0.00625, B=0.00625, kappa=0.004, gamma=0.5, tau_f=1.0,

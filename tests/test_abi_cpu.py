@@ -72,7 +72,7 @@ def test_query_sizes(abi):
     (dict(layout=4), "LB_EINVAL"), (dict(layout=-1), "LB_EINVAL"),
     (dict(layout=3, aosoa_len=3), "LB_ESHAPE"), (dict(layout=3, aosoa_len=0), "LB_ESHAPE"),
     (dict(layout=3, aosoa_len=64, nz=96), "LB_ESHAPE"),
-    (dict(coupling=2), "LB_EINVAL"), (dict(coupling=1, precision=1), "LB_EINVAL"),
+    (dict(coupling=2), "LB_EINVAL"), (dict(coupling=-1), "LB_EINVAL"),
 ])
 def test_bad_parameters_rejected(abi, kw, code):
     st, _ = _query(abi, **kw)
