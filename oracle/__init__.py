@@ -38,7 +38,7 @@ class _Params(ctypes.Structure):
                 ("A", ctypes.c_double), ("B", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("tau_f", ctypes.c_double),
                 ("tau_g", ctypes.c_double), ("rho0", ctypes.c_double),
-                ("coupling", ctypes.c_int32)]
+                ("coupling", ctypes.c_int32), ("order_param", ctypes.c_int32)]
 
 
 @dataclass
@@ -55,6 +55,7 @@ class Params:
     tau_g: float = 1.0
     rho0: float = 1.0
     coupling: int = 0  # 0: Pi in f^eq; 1: body force -div Pi (Guo forcing)
+    order_param: int = 0  # 0: LB distribution g; 1: finite-difference field phi
 
     @property
     def shape(self):
@@ -62,7 +63,12 @@ class Params:
 
     def c(self) -> _Params:
         return _Params(self.nx, self.ny, self.nz, self.A, self.B, self.kappa, self.gamma,
-                       self.tau_f, self.tau_g, self.rho0, self.coupling)
+                       self.tau_f, self.tau_g, self.rho0, self.coupling, self.order_param)
+
+    @property
+    def mobility(self) -> float:
+        """M = Gamma (tau_g - 1/2), the Cahn-Hilliard mobility of both schemes."""
+        return self.gamma * (self.tau_g - 0.5)
 
 
 def _load():
@@ -95,6 +101,14 @@ def _load():
     lib.oracle_equilibrium_force_site.argtypes = [P, ctypes.c_double, D, ctypes.c_double,
                                                   ctypes.c_double, D, D]
     lib.oracle_collide_force.argtypes = [P, D, D, D, D, D, D, D]
+    lib.oracle_fd_init.argtypes = [P, D, D, D]
+    lib.oracle_fd_moments.argtypes = [P, D, D, D, D, D]
+    lib.oracle_fd_fluxes.argtypes = [P, D, D, D, D]
+    lib.oracle_fd_update.argtypes = [P, D, D, D]
+    lib.oracle_fd_step.argtypes = [P, D, D, D, D]
+    lib.oracle_fd_step.restype = ctypes.c_int
+    lib.oracle_fd_run.argtypes = [P, D, D, ctypes.c_int]
+    lib.oracle_fd_run.restype = ctypes.c_int
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_threads.restype = ctypes.c_int
     _lib = lib
@@ -253,6 +267,78 @@ def collide_force(p: Params, f, g, phi, mu, F):
     _load().oracle_collide_force(ctypes.byref(p.c()), _ptr(f), _ptr(g), _ptr(phi), _ptr(mu),
                                  _ptr(F), _ptr(fs), _ptr(gs))
     return fs, gs
+
+
+# -- finite-difference order parameter (order_param = 1) ----------------------
+# The state is (f, phi): f (19, nx, ny, nz) post-stream as above, phi a field.
+
+def _fd_check(rc: int, what: str):
+    if rc == 1:
+        raise MemoryError(f"{what}: allocation failed")
+    if rc == 2:
+        raise ValueError(f"{what}: the finite-difference scheme has the stress coupling only")
+
+
+def fd_init(p: Params, phi0):
+    """(f, phi) at t = 0: f_i = w_i rho0, phi = phi0."""
+    phi0 = _f64(phi0)
+    f = np.empty((NVEL,) + p.shape)
+    phi = np.empty(p.shape)
+    _load().oracle_fd_init(ctypes.byref(p.c()), _ptr(phi0), _ptr(f), _ptr(phi))
+    return f, phi
+
+
+def fd_moments(p: Params, f, phi):
+    """(rho, u (3, nx, ny, nz), phi) of a finite-difference state; u = j/rho."""
+    f, phi = _f64(f), _f64(phi)
+    rho = np.empty(p.shape)
+    u = np.empty((3,) + p.shape)
+    ph = np.empty(p.shape)
+    _load().oracle_fd_moments(ctypes.byref(p.c()), _ptr(f), _ptr(phi), _ptr(rho), _ptr(u), _ptr(ph))
+    return rho, u, ph
+
+
+def fd_fluxes(p: Params, phi, mu, u):
+    """Face fluxes J (3, nx, ny, nz): J[a] at x is the flux from x to x + e_a
+    (upwind advection with the face-averaged velocity, minus M times the
+    difference of mu)."""
+    phi, mu, u = _f64(phi), _f64(mu), _f64(u)
+    J = np.empty((3,) + p.shape)
+    _load().oracle_fd_fluxes(ctypes.byref(p.c()), _ptr(phi), _ptr(mu), _ptr(u), _ptr(J))
+    return J
+
+
+def fd_update(p: Params, phi, J):
+    """phi - div J (conservative finite-volume update)."""
+    phi, J = _f64(phi), _f64(J)
+    out = np.empty(p.shape)
+    _load().oracle_fd_update(ctypes.byref(p.c()), _ptr(phi), _ptr(J), _ptr(out))
+    return out
+
+
+def fd_step(p: Params, f, phi):
+    f, phi = _f64(f), _f64(phi)
+    fn = np.empty_like(f)
+    pn = np.empty_like(phi)
+    _fd_check(_load().oracle_fd_step(ctypes.byref(p.c()), _ptr(f), _ptr(phi), _ptr(fn), _ptr(pn)),
+              "oracle_fd_step")
+    return fn, pn
+
+
+def fd_run(p: Params, f, phi, nsteps: int):
+    """nsteps finite-difference timesteps from (f, phi); returns new arrays."""
+    f = _f64(f).copy()
+    phi = _f64(phi).copy()
+    _fd_check(_load().oracle_fd_run(ctypes.byref(p.c()), _ptr(f), _ptr(phi), int(nsteps)),
+              "oracle_fd_run")
+    return f, phi
+
+
+def fd_sums(p: Params, f, phi):
+    """(sum rho, sum phi, sum j_x, sum j_y, sum j_z) of a finite-difference state."""
+    rho, u, ph = fd_moments(p, f, phi)
+    j = u * rho[None]
+    return np.array([fsum(rho), fsum(ph), fsum(j[0]), fsum(j[1]), fsum(j[2])])
 
 
 def set_threads(n: int) -> int:

@@ -38,6 +38,22 @@
  * (Guo, Zheng and Shi's forcing term: the collision adds exactly F to the
  * momentum of every site.)
  *
+ * Finite-difference order parameter (order_param = 1): the binary-fluid
+ * counterpart of the paper's "Advection" and order-parameter update kernels
+ * (Sec. 2.1.1).  There is no g; the state is (f, phi) with phi a field, and
+ * phi follows a conservative Cahn-Hilliard update with advection, fluxes on
+ * the faces between neighbouring sites (face x + e_a/2 belongs to x):
+ *
+ *   u_f(x + e_a/2) = [u_a(x) + u_a(x + e_a)] / 2          (u = j/rho of f)
+ *   J_a(x + e_a/2) = u_f * (u_f > 0 ? phi(x) : phi(x + e_a))    (upwind)
+ *                    - M [mu(x + e_a) - mu(x)]                  (diffusion)
+ *   phi(x, t+1)    = phi(x) - sum_a [J_a(x + e_a/2) - J_a(x - e_a/2)]
+ *   M              = Gamma (tau_g - 1/2)
+ *
+ * (the mobility the g scheme above gives, so both schemes solve the same
+ * Cahn-Hilliard equation).  f collides with Pi in f^eq as in the first form,
+ * mu and Pi from phi(t), u from f(t) before collision.
+ *
  * The paper does not print these formulas (it names the kernels only); they
  * are the standard free-energy binary-fluid LB model.  The readings taken
  * where the paper is silent (equilibrium form for all i including the rest
@@ -61,6 +77,7 @@ typedef struct {
     int32_t nx, ny, nz;
     double A, B, kappa, gamma, tau_f, tau_g, rho0;
     int32_t coupling; /* 0: Pi in f^eq's second moment; 1: force -div Pi */
+    int32_t order_param; /* 0: LB distribution g; 1: finite-difference field */
 } oracle_params;
 
 #define NVEL 19
@@ -293,7 +310,7 @@ void oracle_collide_force(const oracle_params *p, const double *f, const double 
     }
 }
 
-/* ---- BGK collision at every site -------------------------------------- */
+/* ---- BGK collision at every site (g and gstar may be NULL: f only) ---- */
 
 void oracle_collide(const oracle_params *p, const double *f, const double *g,
                     const double *phi, const double *mu, const double *pi,
@@ -313,9 +330,9 @@ void oracle_collide(const oracle_params *p, const double *f, const double *g,
         double feq[NVEL], geq[NVEL];
         oracle_equilibrium_site(p, rho, j, phi[s], mu[s], t, feq, geq);
         for (int i = 0; i < NVEL; i++) {
-            double fi = f[i * n + s], gi = g[i * n + s];
+            double fi = f[i * n + s];
             fstar[i * n + s] = fi - (fi - feq[i]) / p->tau_f;
-            gstar[i * n + s] = gi - (gi - geq[i]) / p->tau_g;
+            if (g) gstar[i * n + s] = g[i * n + s] - (g[i * n + s] - geq[i]) / p->tau_g;
         }
     }
 }
@@ -440,6 +457,116 @@ void oracle_moments(const oracle_params *p, const double *f, const double *g,
         if (phi) phi[s] = ph;
     }
     free(F);
+}
+
+/* ---- finite-difference order parameter ------------------------------- */
+
+/* Initial state: f_i = w_i rho0 (rest), phi = phi0. */
+void oracle_fd_init(const oracle_params *p, const double *phi0, double *f, double *phi)
+{
+    long n = nsites(p);
+    for (int i = 0; i < NVEL; i++)
+        for (long s = 0; s < n; s++) f[i * n + s] = weight(i) * p->rho0;
+    memcpy(phi, phi0, sizeof(double) * n);
+}
+
+/* rho, u = j/rho of a post-stream f, and phi copied from the field. */
+void oracle_fd_moments(const oracle_params *p, const double *f, const double *phi,
+                       double *rho, double *u /* [3][N] */, double *phi_out)
+{
+    long n = nsites(p);
+    for (long s = 0; s < n; s++) {
+        double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < NVEL; i++) {
+            r += f[i * n + s];
+            for (int a = 0; a < 3; a++) j[a] += f[i * n + s] * CV[i][a];
+        }
+        if (rho) rho[s] = r;
+        if (u) for (int a = 0; a < 3; a++) u[a * n + s] = j[a] / r;
+        if (phi_out) phi_out[s] = phi[s];
+    }
+}
+
+/* Flux J_a through the face between x and x + e_a, stored at x: J[3][N]. */
+void oracle_fd_fluxes(const oracle_params *p, const double *phi, const double *mu,
+                      const double *u /* [3][N] */, double *J /* [3][N] */)
+{
+    long n = nsites(p);
+    double M = p->gamma * (p->tau_g - 0.5);
+    for (long s = 0; s < n; s++) {
+        int x, y, z;
+        site_coords(p, s, &x, &y, &z);
+        long nb[3] = {site_index(p, x + 1, y, z), site_index(p, x, y + 1, z),
+                      site_index(p, x, y, z + 1)};
+        for (int a = 0; a < 3; a++) {
+            double uf = 0.5 * (u[a * n + s] + u[a * n + nb[a]]);
+            double up = uf > 0.0 ? phi[s] : phi[nb[a]];
+            J[a * n + s] = uf * up - M * (mu[nb[a]] - mu[s]);
+        }
+    }
+}
+
+/* phi_new(x) = phi(x) - sum_a [J_a(x) - J_a(x - e_a)] (the flux divergence). */
+void oracle_fd_update(const oracle_params *p, const double *phi, const double *J,
+                      double *phi_new)
+{
+    long n = nsites(p);
+    for (long s = 0; s < n; s++) {
+        int x, y, z;
+        site_coords(p, s, &x, &y, &z);
+        long nm[3] = {site_index(p, x - 1, y, z), site_index(p, x, y - 1, z),
+                      site_index(p, x, y, z - 1)};
+        double div = 0.0;
+        for (int a = 0; a < 3; a++) div += J[a * n + s] - J[a * n + nm[a]];
+        phi_new[s] = phi[s] - div;
+    }
+}
+
+/* One timestep of the finite-difference scheme: (f, phi) -> (fnew, phinew).
+ * Returns 1 on allocation failure, 2 for the force coupling (not defined
+ * with this scheme). */
+int oracle_fd_step(const oracle_params *p, const double *f, const double *phi,
+                   double *fnew, double *phinew)
+{
+    if (p->coupling != 0) return 2;
+    long n = nsites(p);
+    double *grad = malloc(sizeof(double) * 3 * n);
+    double *lap = malloc(sizeof(double) * n);
+    double *mu = malloc(sizeof(double) * n);
+    double *pi = malloc(sizeof(double) * 6 * n);
+    double *u = malloc(sizeof(double) * 3 * n);
+    double *J = malloc(sizeof(double) * 3 * n);
+    double *fs = malloc(sizeof(double) * NVEL * n);
+    if (!grad || !lap || !mu || !pi || !u || !J || !fs) {
+        free(grad); free(lap); free(mu); free(pi); free(u); free(J); free(fs);
+        return 1;
+    }
+    oracle_fd_moments(p, f, phi, NULL, u, NULL);
+    oracle_gradients(p, phi, grad, lap);
+    oracle_chemical(p, phi, grad, lap, mu, pi);
+    oracle_collide(p, f, NULL, phi, mu, pi, fs, NULL);
+    oracle_stream(p, fs, fnew);
+    oracle_fd_fluxes(p, phi, mu, u, J);
+    oracle_fd_update(p, phi, J, phinew);
+    free(grad); free(lap); free(mu); free(pi); free(u); free(J); free(fs);
+    return 0;
+}
+
+/* nsteps timesteps in place on (f, phi). */
+int oracle_fd_run(const oracle_params *p, double *f, double *phi, int nsteps)
+{
+    long n = nsites(p);
+    double *f2 = malloc(sizeof(double) * NVEL * n);
+    double *p2 = malloc(sizeof(double) * n);
+    if (!f2 || !p2) { free(f2); free(p2); return 1; }
+    for (int t = 0; t < nsteps; t++) {
+        int rc = oracle_fd_step(p, f, phi, f2, p2);
+        if (rc) { free(f2); free(p2); return rc; }
+        memcpy(f, f2, sizeof(double) * NVEL * n);
+        memcpy(phi, p2, sizeof(double) * n);
+    }
+    free(f2); free(p2);
+    return 0;
 }
 
 /* ---- FP64 pairwise sum (fixed order) ---------------------------------- */

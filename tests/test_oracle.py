@@ -538,6 +538,173 @@ def test_flat_interfaces_reach_mechanical_equilibrium(coupling, tol):
     assert np.abs(d - q).max() < tol * np.ptp(d), np.abs(d - q).max() / np.ptp(d)
 
 
+# ---------------------------------- finite-difference order parameter --
+# The state is (f, phi); phi follows a conservative Cahn-Hilliard update with
+# upwind advection (face fluxes), M = Gamma (tau_g - 1/2).
+
+def _fd_params(shape, **kw):
+    kw.setdefault("order_param", 1)
+    return _params(shape, **kw)
+
+
+def _lap_eig(shape, q):
+    """Eigenvalue of the 7-point Laplacian for the integer wave vector q."""
+    return -sum(2 * (1 - math.cos(2 * math.pi * qa / n)) for qa, n in zip(q, shape))
+
+
+@pytest.mark.parametrize("q,tau_g,gamma", [((1, 2, 0), 1.3, 0.5), ((3, 1, 2), 0.8, 0.9)])
+def test_fd_diffusion_is_the_discrete_linear_multiplier(q, tau_g, gamma):
+    """From rest (u = 0) a small mode phi = eps cos(q.x + 0.3) changes per step
+    by the factor 1 + M lam (A - kappa lam), lam the Laplacian eigenvalue:
+    the flux difference of mu is the 7-point Laplacian of the linearised mu.
+    The flow the stress drives is O(eps^2) (zero mean phi), so five steps
+    follow the factor to the fifth power to O(eps^2) relative.  A flux sign,
+    the mobility's tau_g convention or a kappa sign error is O(1) off."""
+    shape = (8, 6, 10)
+    p = _fd_params(shape, tau_g=tau_g, gamma=gamma, tau_f=0.9)
+    x, y, z = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    arg = 2 * math.pi * (q[0] * x / shape[0] + q[1] * y / shape[1] + q[2] * z / shape[2]) + 0.3
+    eps = 1e-6
+    phi0 = eps * np.cos(arg)
+    lam = _lap_eig(shape, q)
+    M = gamma * (tau_g - 0.5)
+    m = 1 + M * lam * (p.A - p.kappa * lam)
+    f, phi = oracle.fd_init(p, phi0)
+    _, phi1 = oracle.fd_step(p, f, phi)
+    np.testing.assert_allclose(phi1, m * phi0, rtol=0, atol=1e-9 * eps)
+    _, phi5 = oracle.fd_run(p, f, phi, 5)
+    np.testing.assert_allclose(phi5, m ** 5 * phi0, rtol=0, atol=1e-9 * eps)
+    assert abs(m - 1) > 1e-3  # the mode moved
+
+
+def _first_order_state(rho, j):
+    """f_i = w_i (rho + 3 c_i . j): moments exactly rho and j."""
+    c, w = oracle.lattice()
+    return w[:, None, None, None] * (rho[None] + 3 * np.einsum("ia,a...->i...", c, j))
+
+
+def test_fd_upwind_advection_matches_fourier_multiplier():
+    """A = B = kappa = 0 and M = 0 (Gamma = 0): phi is advected by a uniform
+    velocity with mixed signs.  Upwind differencing along each axis is the
+    linear map with the Fourier multiplier
+    1 - sum_{u_a > 0} u_a (1 - e^{-i q_a}) - sum_{u_a < 0} u_a (e^{i q_a} - 1),
+    applied here with numpy's FFT.  Taking the downwind side, or the wrong
+    sign of a flux, breaks it."""
+    shape = (9, 8, 7)
+    p = _fd_params(shape, A=0.0, B=0.0, kappa=0.0, gamma=0.0)
+    u0 = np.array([0.031, -0.022, 0.013])
+    rho = np.full(shape, 1.0)
+    f = _first_order_state(rho, np.broadcast_to(u0[:, None, None, None], (3,) + shape))
+    phi = lbinputs.random_field(shape, seed=21)
+    _, u, _ = oracle.fd_moments(p, f, phi)
+    np.testing.assert_allclose(u, np.broadcast_to(u0[:, None, None, None], u.shape), atol=1e-16)
+    _, phi1 = oracle.fd_step(p, f, phi)
+    qs = np.meshgrid(*[2 * np.pi * np.fft.fftfreq(n) for n in shape], indexing="ij")
+    mult = np.ones(shape, dtype=complex)
+    for a in range(3):
+        ua = u0[a]
+        mult -= ua * (1 - np.exp(-1j * qs[a])) if ua > 0 else ua * (np.exp(1j * qs[a]) - 1)
+    expect = np.fft.ifftn(np.fft.fftn(phi) * mult).real
+    np.testing.assert_allclose(phi1, expect, rtol=0, atol=1e-13)
+
+
+def test_fd_face_velocity_gives_central_divergence():
+    """A uniform phi = c under a non-uniform velocity (M = 0): every face
+    carries c times its face velocity, so phi changes by -c times the sum of
+    the face-velocity differences, which for the mean of the two sites'
+    velocities is the central-difference divergence of u (numpy rolls here);
+    taking one site's velocity instead gives a one-sided difference."""
+    shape = (6, 5, 4)
+    p = _fd_params(shape, A=0.0, B=0.0, kappa=0.0, gamma=0.0)
+    rng = np.random.default_rng(5)
+    rho = 1.0 + 0.05 * rng.random(shape)
+    j = 0.02 * rng.standard_normal((3,) + shape)
+    f = _first_order_state(rho, j)
+    cval = 0.7
+    _, phi1 = oracle.fd_step(p, f, np.full(shape, cval))
+    u = j / rho[None]
+    div = sum(0.5 * (np.roll(u[a], -1, a) - np.roll(u[a], 1, a)) for a in range(3))
+    np.testing.assert_allclose(phi1, cval * (1 - div), rtol=0, atol=1e-15)
+
+
+def test_fd_conserves_and_keeps_uniform_state():
+    """sum rho, sum phi, total momentum conserved to round-off over 40 steps
+    (fluxes telescope; Pi in f^eq); a uniform phi at rest is unchanged
+    bit-for-bit (every flux is exactly zero)."""
+    shape = (6, 7, 8)
+    p = _fd_params(shape, tau_f=0.8, tau_g=1.3)
+    f, _ = _perturbed_state(_params(shape, tau_f=0.8, tau_g=1.3), 4)
+    phi = 0.1 + lbinputs.spinodal_phi0(shape, seed=8)
+    s0 = oracle.fd_sums(p, f, phi)
+    assert abs(s0[2]) + abs(s0[3]) + abs(s0[4]) > 1e-4
+    f2, phi2 = oracle.fd_run(p, f, phi, 40)
+    np.testing.assert_allclose(oracle.fd_sums(p, f2, phi2), s0, rtol=0, atol=1e-12)
+    assert np.abs(phi2 - phi).max() > 1e-3
+    fu, pu = oracle.fd_init(p, np.full(shape, 0.3))
+    fu2, pu2 = oracle.fd_run(p, fu, pu, 10)
+    assert np.array_equal(pu2, pu)
+    _, u, _ = oracle.fd_moments(p, fu2, pu2)
+    assert np.array_equal(u, np.zeros_like(u))
+
+
+def test_fd_relaxes_like_the_lb_scheme():
+    """Both order-parameter schemes solve the same Cahn-Hilliard equation:
+    the decay rate of a small mode (A > 0) matches the continuum
+    M k^2 (A + kappa k^2), M = Gamma (tau_g - 1/2), to 2% for each
+    (FD 0.3%, LB 1.1% here; a mobility off by tau_g's 1/2 is 70% off)."""
+    n = 32
+    shape = (n, 3, 3)
+    rates = []
+    k = 2 * math.pi / n
+    phi0 = 1e-4 * np.broadcast_to(np.cos(k * np.arange(n))[:, None, None], shape).copy()
+
+    def amp(phi):
+        return 2.0 / n * (phi[:, 0, 0] * np.cos(k * np.arange(n))).sum()
+
+    for op in (0, 1):
+        p = _params(shape, A=0.1, B=0.0, kappa=0.004, tau_g=1.2, gamma=0.5, order_param=op)
+        if op:
+            f, phi = oracle.fd_run(p, *oracle.fd_init(p, phi0), 30)
+            _, phi2 = oracle.fd_run(p, f, phi, 400)
+        else:
+            f, g = oracle.run(p, *oracle.init(p, phi0), 30)
+            phi = g.sum(0)
+            phi2 = oracle.run(p, f, g, 400)[1].sum(0)
+        rates.append(-math.log(amp(phi2) / amp(phi)) / 400)
+    expect = 0.5 * 0.7 * k * k * (0.1 + 0.004 * k * k)
+    for r in rates:
+        assert abs(r / expect - 1) < 0.02, (rates, expect)
+
+
+def test_fd_flat_interfaces_reach_equilibrium():
+    """Two flat interfaces relax to rest with uniform normal stress
+    rho/3 + Pi_xx, as in the LB scheme, and keep their tanh profile."""
+    n = 96
+    shape = (n, 1, 1)
+    A, B, kappa = -0.005, 0.005, 0.16
+    xi = math.sqrt(-2 * kappa / A)
+    x = np.arange(n)
+    phi0 = (np.tanh((x - n / 4) / xi) - np.tanh((x - 3 * n / 4) / xi) - 1.0).reshape(shape)
+    p = _fd_params(shape, A=A, B=B, kappa=kappa, tau_f=1.0, tau_g=1.0)
+    f, phi = oracle.fd_run(p, *oracle.fd_init(p, phi0), 8000)
+    rho, u, _ = oracle.fd_moments(p, f, phi)
+    assert np.abs(u).max() < 1e-6
+    grad, lap = oracle.gradients(p, phi)
+    _, pi = oracle.chemical(p, phi, grad, lap)
+    assert np.abs(phi - phi0).max() < 1e-2
+    d = (rho - rho.mean()).ravel()
+    q = (-3 * (pi[0] - pi[0].mean())).ravel()
+    assert np.ptp(d) > 1e-5
+    assert np.abs(d - q).max() < 2e-3 * np.ptp(d), np.abs(d - q).max() / np.ptp(d)
+
+
+def test_fd_rejects_force_coupling():
+    p = _fd_params((4, 4, 4), coupling=1)
+    f, phi = oracle.fd_init(p, np.zeros((4, 4, 4)))
+    with pytest.raises(ValueError):
+        oracle.fd_step(p, f, phi)
+
+
 # ----------------------------------------------- reverse-mode gradients --
 
 def test_reverse_mode_matches_central_differences():
