@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--aosoa-len", type=int, default=64, help="z-sites per block for --layout aosoa")
     ap.add_argument("--force-steps", type=int, default=200,
                     help="steps of the 256^3 force-coupling lines (0: skip)")
+    ap.add_argument("--fd-steps", type=int, default=200,
+                    help="steps of the 256^3 finite-difference order-parameter lines (0: skip)")
     ap.add_argument("--spinodal-steps", type=int, default=1000,
                     help="steps of the extra 128^3 FP64 spinodal throughput line (0: skip)")
     args = ap.parse_args()
@@ -275,6 +277,35 @@ def main():
                 "kernels": "k_phi + k_pi + k_step_force"}
             del lb
             torch.cuda.empty_cache()
+
+    # finite-difference order parameter (a phi field, no g) on the same 256^3
+    # droplet: the collision pass moves 344 B per site in FP64 (f read 152 and
+    # written 152, phi 8, mu and u written 32) and 192 in FP32 storage
+    # (76 + 76 + 8 + 32); the update pass 48 (phi, mu, u read, phi written).
+    # The scheme's minimum, f and phi read and written once, is 320 and 168.
+    if args.fd_steps > 0:
+        out["fd_order_parameter"] = {}
+        fd_phi = {}
+        for prec, moved, minimum in (("fp32_dev", 240, 168), ("fp64", 392, 320)):
+            lb = LB(shape, precision=prec, order_param="fd", device="cuda:0", **lay, **params)
+            lb.init_phi(phi0)
+            log(f"{prec} finite-difference order parameter {shape}: {args.fd_steps} steps")
+            ms = time_steps(lb, args.fd_steps, args.warmup)
+            t = ms / args.fd_steps * 1e-3
+            fd_phi[prec] = lb.phi().cpu().numpy()
+            out["fd_order_parameter"][prec] = {
+                "value": round(nsites / t / 1e6, 1), "unit": "MLUPS", "steps": args.fd_steps,
+                "ms_per_step": round(ms / args.fd_steps, 4),
+                "achieved_GBps": round(moved * nsites / t / 1e9, 1),
+                "frac": round(moved * nsites / t / 1e9 / HBM_PEAK_GBPS, 4),
+                "bytes_per_site": moved,
+                "effective_GBps": round(minimum * nsites / t / 1e9, 1),
+                "kernels": "k_fd_collide + k_fd_update"}
+            del lb
+            torch.cuda.empty_cache()
+        out["fd_order_parameter"]["phi_fp32_vs_fp64_max"] = float(
+            np.abs(fd_phi["fp32_dev"] - fd_phi["fp64"]).max())
+        del fd_phi
 
     # FP64 on the 128^3 spinodal-decomposition lattice (phi0 ~ U(-0.05, 0.05))
     if not args.no_fp64 and args.spinodal_steps > 0:

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 2
+#define LB_ABI_VERSION 3
 #define LB_NVEL 19
 
 typedef enum {
@@ -93,6 +93,24 @@ typedef enum {
                                Pi and collision passes                      */
 } lb_coupling;
 
+/* How the order parameter evolves: */
+typedef enum {
+    LB_OP_LB = 0, /* the distribution g above (default)                       */
+    LB_OP_FD = 1  /* a field phi(x) with a conservative finite-difference
+                     Cahn-Hilliard update and upwind advection -- the binary-
+                     fluid counterpart of the paper's "Advection" and order-
+                     parameter update kernels (Sec. 2.1.1); there is no g.
+                     With the flux through the face between x and x + e_a,
+                       u_f = (u_a(x) + u_a(x + e_a)) / 2   (u = j/rho of f(t))
+                       J_a = u_f * (u_f > 0 ? phi(x) : phi(x + e_a))
+                             - M (mu(x + e_a) - mu(x)),
+                     phi(x, t+1) = phi(x) - sum_a [J_a(x + e_a/2) - J_a(x - e_a/2)]
+                     with M = Gamma (tau_g - 1/2), the mobility of the g
+                     scheme; mu and Pi from phi(t); f collides as above with Pi
+                     in f^eq.  Requires LB_COUPLING_STRESS; no adjoint; phi is
+                     FP64 in both precisions.                                */
+} lb_order_param;
+
 /* Memory layout of the f and g regions of a time level (opaque to callers,
  * who see dense arrays through lb_export_dist / lb_import_dist; every layout
  * gives bit-identical results).  Element (i, x, y, z), row r = x*ny + y: */
@@ -121,6 +139,7 @@ typedef struct {
     int32_t layout;     /* lb_layout of the distributions                           */
     int32_t aosoa_len;  /* V for LB_LAYOUT_AOSOA (ignored otherwise)                */
     int32_t coupling;   /* lb_coupling                                              */
+    int32_t order_param; /* lb_order_param                                          */
 } lb_params;
 
 /* Sizes in bytes of the caller-owned device buffers (lb_query_sizes). */
@@ -128,9 +147,11 @@ typedef struct {
     size_t elem_bytes;        /* 8 (LB_FP64) or 4 (LB_FP32_DEV)                         */
     size_t stride_elems;      /* padded elements per component of a distribution        */
     size_t state_bytes;       /* one time level: f, g (2*19*stride elements) and, in
-                                 LB_FP32_DEV, phi_c (stride FP64 values)                */
-    size_t phi_bytes;         /* FP64 work fields: phi (N values of stride), and for
-                                 LB_COUPLING_FORCE also the 6 components of Pi         */
+                                 LB_FP32_DEV, phi_c (stride FP64 values); LB_OP_FD:
+                                 f (19*stride elements), then phi (stride FP64)        */
+    size_t phi_bytes;         /* FP64 work fields of stride values each: phi, and for
+                                 LB_COUPLING_FORCE also the 6 components of Pi;
+                                 LB_OP_FD: mu, u_x, u_y, u_z                           */
     size_t scratch_bytes;     /* reduction partials                                     */
     size_t adj_bytes;         /* one adjoint time level (lambda_f, lambda_g, lambda_phi) */
     size_t adj_scratch_bytes; /* adjoint stencil cotangents and parameter partials      */
@@ -169,7 +190,8 @@ lb_status lb_set_stream(lb_ctx *ctx, void *hip_stream);
 
 /* Initial state from phi0_dev (FP64, nx*ny*nz): rho = rho0 and u = 0
  * (f_i = w_i rho0), all of phi0 in the rest population (g_0 = phi0,
- * g_i = 0 for i > 0).  Resets the time-level index. */
+ * g_i = 0 for i > 0; LB_OP_FD: the field phi = phi0).  Resets the time-level
+ * index. */
 lb_status lb_init_phi(lb_ctx *ctx, const double *phi0_dev);
 
 /* Advance nsteps >= 0 timesteps (asynchronous). */
@@ -207,13 +229,15 @@ lb_status lb_get_state(lb_ctx *ctx, void *dst_dev);
 lb_status lb_set_state(lb_ctx *ctx, const void *src_dev);
 
 /* Current state as dense FP64 post-propagation distributions, each of shape
- * (19, nx, ny, nz); either pointer may be NULL. */
+ * (19, nx, ny, nz); either pointer may be NULL.  LB_OP_FD has no g: g_dev
+ * must be NULL (LB_EINVAL). */
 lb_status lb_export_dist(lb_ctx *ctx, double *f_dev, double *g_dev);
 
 /* Set the current state from dense FP64 post-propagation distributions
  * (19, nx, ny, nz).  In LB_FP32_DEV phi_c(x) becomes sum_i g_i(x) and the
  * values are rounded to FP32 after subtracting w_i rho0 from f_i and
- * r_i phi_c(x) from g_i(x). */
+ * r_i phi_c(x) from g_i(x).  LB_OP_FD: g_dev must be NULL and only f is set
+ * (the phi field keeps its values). */
 lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
 
 /* ---- reverse mode ------------------------------------------------------
@@ -223,7 +247,8 @@ lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
  *   lb_adjoint_seed(dL/dphi_T)  then, for t = T-1 .. 0,
  *   lb_adjoint_step(state_t)    (state_t as saved by lb_get_state at time t;
  *                                or lb_adjoint_step_next with level t+1 too)
- * and lb_adjoint_phi0 gives dL/dphi0.  Requires adj[0], adj[1], adj_scratch. */
+ * and lb_adjoint_phi0 gives dL/dphi0.  Requires adj[0], adj[1], adj_scratch,
+ * LB_COUPLING_STRESS and LB_OP_LB (LB_ESTATE otherwise). */
 
 /* lambda_T from dphi_dev = dL/dphi_T (FP64, N): dL/dg_i = dphi for every i,
  * dL/df_i = 0. */

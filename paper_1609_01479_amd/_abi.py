@@ -31,7 +31,8 @@ class LbParams(ctypes.Structure):
                 ("tau_g", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("segment_x", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("aosoa_len", ctypes.c_int32), ("coupling", ctypes.c_int32)]
+                ("aosoa_len", ctypes.c_int32), ("coupling", ctypes.c_int32),
+                ("order_param", ctypes.c_int32)]
 
 
 class LbSizes(ctypes.Structure):
@@ -95,7 +96,7 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = res
-    if L.lb_abi_version() != 2:
+    if L.lb_abi_version() != 3:
         raise RuntimeError("liblbmi.so ABI version mismatch")
     _lib = L
     return L

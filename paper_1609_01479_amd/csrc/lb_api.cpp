@@ -75,6 +75,10 @@ lb_status validate(const lb_params* p)
         return fail(LB_EINVAL, "unknown layout %d", p->layout);
     if (p->coupling != LB_COUPLING_STRESS && p->coupling != LB_COUPLING_FORCE)
         return fail(LB_EINVAL, "unknown coupling %d", p->coupling);
+    if (p->order_param != LB_OP_LB && p->order_param != LB_OP_FD)
+        return fail(LB_EINVAL, "unknown order_param %d", p->order_param);
+    if (p->order_param == LB_OP_FD && p->coupling != LB_COUPLING_STRESS)
+        return fail(LB_EINVAL, "LB_OP_FD requires LB_COUPLING_STRESS");
     if (p->layout == LB_LAYOUT_AOSOA) {
         const int v = p->aosoa_len;
         if (v < 1 || (v & (v - 1)) != 0 || p->nz % v != 0)
@@ -128,17 +132,26 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     const size_t stride = stride_for(n);
     out->elem_bytes = e;
     out->stride_elems = stride;
-    // f and g, plus the FP64 reference order parameter in FP32 mode
-    out->state_bytes = 2 * LB_NVEL * stride * e + (p->precision == LB_FP32_DEV ? stride * 8 : 0);
-    // FP64 work fields: phi, and for the force coupling also Pi (6 fields)
-    out->phi_bytes = (p->coupling == LB_COUPLING_FORCE ? 7 : 1) * stride * 8;
+    const bool fd = p->order_param == LB_OP_FD;
+    if (fd) {
+        // f, then the FP64 phi field; work fields mu, u_x, u_y, u_z
+        out->state_bytes = LB_NVEL * stride * e + stride * 8;
+        out->phi_bytes = 4 * stride * 8;
+    } else {
+        // f and g, plus the FP64 reference order parameter in FP32 mode
+        out->state_bytes = 2 * LB_NVEL * stride * e + (p->precision == LB_FP32_DEV ? stride * 8 : 0);
+        // FP64 work fields: phi, and for the force coupling also Pi (6 fields)
+        out->phi_bytes = (p->coupling == LB_COUPLING_FORCE ? 7 : 1) * stride * 8;
+    }
     // block partials of the reductions: 5 FP64 per block of the largest grid
     lbk::KParams k{};
     k.nx = p->nx;
     k.ny = p->ny;
     k.nz = p->nz;
     const lbk::TileCfg tc = lbk::tile_config(k, p->segment_x, p->precision == LB_FP32_DEV);
-    const size_t nparts = std::max<size_t>(size_t(tc.ntiles) * tc.nseg, lbk::kMaxPartialBlocks);
+    k.nsites = int(n);
+    size_t nparts = std::max<size_t>(size_t(tc.ntiles) * tc.nseg, lbk::kMaxPartialBlocks);
+    if (fd) nparts = std::max<size_t>(nparts, size_t(lbk::fd_step_partial_blocks(k)));
     out->scratch_bytes = nparts * 5 * 8;
     out->adj_bytes = size_t(kAdjComponents) * stride * e;
     out->adj_scratch_bytes = size_t(kAdjScratchComponents) * stride * e;
@@ -191,6 +204,8 @@ lb_status lb_create(const lb_params* p, const lb_buffers* b, void* hip_stream, l
     k.omega_g = 1.0 / p->tau_g;
     k.rho0 = p->rho0;
     k.force = p->coupling == LB_COUPLING_FORCE;
+    k.fd = p->order_param == LB_OP_FD;
+    k.mobility = p->gamma * (p->tau_g - 0.5);
     c->tc = lbk::tile_config(k, p->segment_x, c->fp32);
     *out = c;
     return LB_OK;
@@ -209,8 +224,21 @@ lb_status lb_init_phi(lb_ctx* ctx, const double* phi0_dev)
 {
     if (!ctx || !phi0_dev) return fail(LB_EINVAL, "ctx and phi0_dev are required");
     ctx->cur = 0;
-    hipError_t e = lbk::launch_init(ctx->kp, ctx->fp32, ctx->b.state[0], phi0_dev, ctx->stream);
+    hipError_t e = ctx->kp.fd
+                       ? lbk::launch_fd_init(ctx->kp, ctx->fp32, ctx->b.state[0], phi0_dev, ctx->stream)
+                       : lbk::launch_init(ctx->kp, ctx->fp32, ctx->b.state[0], phi0_dev, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_init_phi");
+}
+
+// One step from src to dst with the context's scheme.
+static hipError_t one_step(lb_ctx* ctx, const void* src, void* dst, double* sums_dev)
+{
+    double* work = static_cast<double*>(ctx->b.phi);
+    double* part = static_cast<double*>(ctx->b.scratch);
+    if (ctx->kp.fd)
+        return lbk::launch_fd_step(ctx->kp, ctx->fp32, src, dst, work, part, sums_dev, ctx->stream);
+    return lbk::launch_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel, src, dst, work, part,
+                            sums_dev, ctx->stream);
 }
 
 static lb_status step_n(lb_ctx* ctx, int32_t nsteps, double* sums_dev, const char* name)
@@ -218,11 +246,8 @@ static lb_status step_n(lb_ctx* ctx, int32_t nsteps, double* sums_dev, const cha
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
     if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0 (got %d)", nsteps);
     for (int32_t t = 0; t < nsteps; t++) {
-        hipError_t e = lbk::launch_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel,
-                                        ctx->b.state[ctx->cur], ctx->b.state[1 - ctx->cur],
-                                        static_cast<double*>(ctx->b.phi),
-                                        static_cast<double*>(ctx->b.scratch),
-                                        sums_dev ? sums_dev + 5 * size_t(t) : nullptr, ctx->stream);
+        hipError_t e = one_step(ctx, ctx->b.state[ctx->cur], ctx->b.state[1 - ctx->cur],
+                                sums_dev ? sums_dev + 5 * size_t(t) : nullptr);
         if (e != hipSuccess) return hip_fail(e, name);
         ctx->cur = 1 - ctx->cur;
     }
@@ -243,18 +268,26 @@ lb_status lb_step_from(lb_ctx* ctx, const void* src_dev, void* dst_dev)
     if (src_dev == dst_dev) return fail(LB_EINVAL, "src_dev and dst_dev must differ");
     if (!aligned(src_dev) || !aligned(dst_dev))
         return fail(LB_EALIGN, "src_dev and dst_dev must be 256-byte aligned");
-    hipError_t e = lbk::launch_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel, src_dev, dst_dev,
-                                    static_cast<double*>(ctx->b.phi), nullptr, nullptr, ctx->stream);
+    hipError_t e = one_step(ctx, src_dev, dst_dev, nullptr);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_step_from");
+}
+
+// Moments of the current level, and block partials of its sums in scratch.
+static hipError_t moments(lb_ctx* ctx, double* rho, double* u, double* phi, int* nb)
+{
+    double* part = static_cast<double*>(ctx->b.scratch);
+    if (ctx->kp.fd)
+        return lbk::launch_fd_moments(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], rho, u, phi, part,
+                                      nb, ctx->stream);
+    return lbk::launch_moments(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], rho, u, phi,
+                               static_cast<double*>(ctx->b.phi), part, nb, ctx->stream);
 }
 
 lb_status lb_moments(lb_ctx* ctx, double* rho_dev, double* u_dev, double* phi_dev)
 {
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
     int nb = 0;
-    hipError_t e = lbk::launch_moments(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], rho_dev, u_dev,
-                                       phi_dev, static_cast<double*>(ctx->b.phi),
-                                       static_cast<double*>(ctx->b.scratch), &nb, ctx->stream);
+    hipError_t e = moments(ctx, rho_dev, u_dev, phi_dev, &nb);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_moments");
 }
 
@@ -263,9 +296,7 @@ lb_status lb_sums(lb_ctx* ctx, double* out5_dev)
     if (!ctx || !out5_dev) return fail(LB_EINVAL, "ctx and out5_dev are required");
     int nb = 0;
     double* part = static_cast<double*>(ctx->b.scratch);
-    hipError_t e = lbk::launch_moments(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], nullptr, nullptr,
-                                       nullptr, static_cast<double*>(ctx->b.phi), part, &nb,
-                                       ctx->stream);
+    hipError_t e = moments(ctx, nullptr, nullptr, nullptr, &nb);
     if (e != hipSuccess) return hip_fail(e, "lb_sums (partials)");
     e = lbk::launch_sums_final(part, nb, 5, out5_dev, false, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_sums (final)");
@@ -290,17 +321,27 @@ lb_status lb_set_state(lb_ctx* ctx, const void* src_dev)
 lb_status lb_export_dist(lb_ctx* ctx, double* f_dev, double* g_dev)
 {
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    if (ctx->kp.fd && g_dev) return fail(LB_EINVAL, "LB_OP_FD has no g: g_dev must be NULL");
     if (!f_dev && !g_dev) return LB_OK;
-    hipError_t e = lbk::launch_export(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], f_dev, g_dev,
-                                      ctx->stream);
+    hipError_t e = ctx->kp.fd ? lbk::launch_fd_export(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur],
+                                                      f_dev, ctx->stream)
+                              : lbk::launch_export(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur],
+                                                   f_dev, g_dev, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_export_dist");
 }
 
 lb_status lb_import_dist(lb_ctx* ctx, const double* f_dev, const double* g_dev)
 {
-    if (!ctx || !f_dev || !g_dev) return fail(LB_EINVAL, "ctx, f_dev and g_dev are required");
-    hipError_t e = lbk::launch_import(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], f_dev, g_dev,
-                                      ctx->stream);
+    if (!ctx || !f_dev) return fail(LB_EINVAL, "ctx and f_dev are required");
+    hipError_t e;
+    if (ctx->kp.fd) {
+        if (g_dev) return fail(LB_EINVAL, "LB_OP_FD has no g: g_dev must be NULL");
+        e = lbk::launch_fd_import(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], f_dev, ctx->stream);
+    } else {
+        if (!g_dev) return fail(LB_EINVAL, "g_dev is required");
+        e = lbk::launch_import(ctx->kp, ctx->fp32, ctx->b.state[ctx->cur], f_dev, g_dev,
+                               ctx->stream);
+    }
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_import_dist");
 }
 
@@ -308,7 +349,8 @@ lb_status lb_adjoint_seed(lb_ctx* ctx, const double* dphi_dev)
 {
     if (!ctx || !dphi_dev) return fail(LB_EINVAL, "ctx and dphi_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
-    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
+    if (ctx->kp.force || ctx->kp.fd)
+        return fail(LB_ESTATE, "the adjoint covers the stress coupling and LB order parameter only");
     ctx->adj_cur = 0;
     hipError_t e = lbk::launch_adj_seed(ctx->kp, ctx->fp32, ctx->b.adj[0], dphi_dev, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_seed");
@@ -324,7 +366,8 @@ lb_status lb_adjoint_step_next(lb_ctx* ctx, const void* state_t_dev, const void*
 {
     if (!ctx || !state_t_dev) return fail(LB_EINVAL, "ctx and state_t_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
-    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
+    if (ctx->kp.force || ctx->kp.fd)
+        return fail(LB_ESTATE, "the adjoint covers the stress coupling and LB order parameter only");
     if (!aligned(state_t_dev)) return fail(LB_EALIGN, "state_t_dev is not 256-byte aligned");
     if (state_next_dev && !aligned(state_next_dev))
         return fail(LB_EALIGN, "state_next_dev is not 256-byte aligned");
@@ -349,7 +392,8 @@ lb_status lb_adjoint_phi0(lb_ctx* ctx, double* dphi0_dev)
 {
     if (!ctx || !dphi0_dev) return fail(LB_EINVAL, "ctx and dphi0_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
-    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
+    if (ctx->kp.force || ctx->kp.fd)
+        return fail(LB_ESTATE, "the adjoint covers the stress coupling and LB order parameter only");
     hipError_t e = lbk::launch_adj_phi0(ctx->kp, ctx->fp32, ctx->b.adj[ctx->adj_cur], dphi0_dev,
                                         ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_phi0");

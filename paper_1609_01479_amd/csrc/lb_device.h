@@ -221,14 +221,19 @@ __device__ __forceinline__ Moments<T> moments_of(const KParams& p, const T* f)
 //   g_eq = w [phi + 3 phi c.u + 9/2 (Gamma mu - phi/3)(|c|^2 - 1)
 //             + 9/2 phi ((c.u)^2 - |u|^2/3)]
 //   g_eq - r phi = w [3 phi c.u + 9/2 Gamma mu (|c|^2 - 1) + 9/2 phi ((c.u)^2 - |u|^2/3)]
-template <typename T, bool DEV, bool REF>
-__device__ __forceinline__ void collide(const KParams& p, T* f, T* g, const Stencil& st)
+// collide_f does f and returns u = j/rho; collide_g does g.
+template <typename T>
+struct Vel {
+    T x, y, z;
+};
+
+template <typename T, bool DEV>
+__device__ __forceinline__ Vel<T> collide_f(const KParams& p, T* f, const Stencil& st)
 {
-    const T A = T(p.A), B = T(p.B), kap = T(p.kappa), gam = T(p.gamma);
-    const T omf = T(p.omega_f), omg = T(p.omega_g);
+    const T A = T(p.A), B = T(p.B), kap = T(p.kappa);
+    const T omf = T(p.omega_f);
     const T phi = T(st.phi), gx = T(st.gx), gy = T(st.gy), gz = T(st.gz), lap = T(st.lap);
     const T phi2 = phi * phi;
-    const T mu = A * phi + B * phi2 * phi - kap * lap;
     const T iso = T(0.5) * A * phi2 + T(0.75) * B * phi2 * phi2 - kap * phi * lap
                 - T(0.5) * kap * (gx * gx + gy * gy + gz * gz);
 
@@ -277,6 +282,18 @@ __device__ __forceinline__ void collide(const KParams& p, T* f, T* g, const Sten
     }
 #pragma unroll
     for (int i = 0; i < NV; i++) f[i] += omf * (eq[i] - f[i]);
+    return Vel<T>{ux, uy, uz};
+}
+
+template <typename T, bool REF>
+__device__ __forceinline__ void collide_g(const KParams& p, T* g, T phi, T mu, Vel<T> u)
+{
+    const T gam = T(p.gamma), omg = T(p.omega_g);
+    const T ux = u.x, uy = u.y, uz = u.z;
+    const T h = T(4.5);
+    const T w0 = T(weight(0)), wf = T(weight(1)), we = T(weight(7));
+    const T wf3 = T(3.0 * weight(1)), we3 = T(3.0 * weight(7));
+    T eq[NV];
 
     const T uu3 = (ux * ux + uy * uy + uz * uz) * T(1.0 / 3.0);
     const T hp = h * phi;
@@ -319,6 +336,17 @@ __device__ __forceinline__ void collide(const KParams& p, T* f, T* g, const Sten
     }
 #pragma unroll
     for (int i = 0; i < NV; i++) g[i] += omg * (eq[i] - g[i]);
+}
+
+template <typename T, bool DEV, bool REF>
+__device__ __forceinline__ void collide(const KParams& p, T* f, T* g, const Stencil& st)
+{
+    const Vel<T> u = collide_f<T, DEV>(p, f, st);
+    const T A = T(p.A), B = T(p.B), kap = T(p.kappa);
+    const T phi = T(st.phi), lap = T(st.lap);
+    const T phi2 = phi * phi;
+    const T mu = A * phi + B * phi2 * phi - kap * lap;
+    collide_g<T, REF>(p, g, phi, mu, u);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,309 @@
+// Finite-difference order parameter (LB_OP_FD): the state is the LB
+// distribution f and a field phi, which follows a conservative Cahn-Hilliard
+// update with upwind advection -- the binary-fluid counterpart of the paper's
+// "Advection" (a stencil of fluxes) and order-parameter update (local)
+// kernels, Sec. 2.1.1.  Two kernels per step, one site per thread:
+//
+//   k_fd_collide: pull of f, 7-point stencil of phi, mu and Pi, collision of
+//     f with Pi in f^eq and its store; mu and u = j/rho into FP64 work
+//     fields; optionally the block partials of the source level's conserved
+//     sums.
+//   k_fd_update: the fluxes through the site's six faces from phi, mu and u
+//     of the site and its face neighbours,
+//       J_a(x + e_a/2) = u_f (u_f > 0 ? phi(x) : phi(x + e_a)) - M (mu(x + e_a) - mu(x)),
+//       u_f = (u_a(x) + u_a(x + e_a)) / 2,
+//     and phi(t+1) = phi - sum_a [J_a(x + e_a/2) - J_a(x - e_a/2)].
+//
+// Each face flux is evaluated by both sites that share it, with the same
+// instructions on the same operands, so the two values are identical and
+// sum phi changes only by the rounding of each site's own update.
+//
+// Time level: F (19*stride elements of T in the layout of didx(); FP32 mode
+// stores f - w rho0) followed by phi (stride FP64 values in site order).
+#include "lb_device.h"
+
+namespace lbk {
+
+using namespace dev;
+
+namespace {
+
+template <typename T>
+struct FdLvl {
+    T* F;
+    double* phi;
+};
+
+template <typename T>
+FdLvl<T> fd_level(void* state, const KParams& p)
+{
+    T* base = static_cast<T*>(state);
+    return FdLvl<T>{base, reinterpret_cast<double*>(base + size_t(NV) * p.stride)};
+}
+
+// rho = rho0, u = 0, phi = phi0.
+template <typename T, bool DEV>
+__global__ __launch_bounds__(kBlock) void k_fd_init(KParams p, T* __restrict__ F,
+                                                    double* __restrict__ phi,
+                                                    const double* __restrict__ phi0)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    const Geo q = geo_of(p, s);
+#pragma unroll
+    for (int i = 0; i < NV; i++) F[dist_own(p, q, i)] = DEV ? T(0) : T(weight(i) * p.rho0);
+    phi[s] = phi0[s];
+}
+
+// Work fields (each `stride` FP64 values): mu, u_x, u_y, u_z.
+template <typename T, bool DEV>
+__global__ __launch_bounds__(kBlock) void k_fd_collide(KParams p, const T* __restrict__ sF,
+                                                       const double* __restrict__ sphi,
+                                                       T* __restrict__ dF,
+                                                       double* __restrict__ work,
+                                                       double* __restrict__ partials)
+{
+    const int s = xcd_block() * kBlock + threadIdx.x;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (s < p.nsites) {
+        const Geo q = geo_of(p, s);
+        T f[NV];
+#pragma unroll
+        for (int i = 0; i < NV; i++) f[i] = sF[dist_pull(p, q, i)];
+        const double c = sphi[s];
+        const Stencil st = stencil(c, sphi[site_of(p, q.xp, q.y, q.z)], sphi[site_of(p, q.xm, q.y, q.z)],
+                                   sphi[site_of(p, q.x, q.yp, q.z)], sphi[site_of(p, q.x, q.ym, q.z)],
+                                   sphi[site_of(p, q.x, q.y, q.zp)], sphi[site_of(p, q.x, q.y, q.zm)]);
+        if (partials) {
+            // FP64 moments of the source level, in index order
+            double b = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+            for (int i = 0; i < NV; i++) {
+                const double v = double(f[i]);
+                b += v;
+                jx += CX[i] * v;
+                jy += CY[i] * v;
+                jz += CZ[i] * v;
+            }
+            acc[0] = DEV ? p.rho0 + b : b;
+            acc[1] = c;
+            acc[2] = jx;
+            acc[3] = jy;
+            acc[4] = jz;
+        }
+        const Vel<T> u = collide_f<T, DEV>(p, f, st);
+        // the new level is not read in this launch
+#pragma unroll
+        for (int i = 0; i < NV; i++) __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
+        work[s] = p.A * c + p.B * c * c * c - p.kappa * st.lap;
+        work[p.stride + s] = double(u.x);
+        work[2 * p.stride + s] = double(u.y);
+        work[3 * p.stride + s] = double(u.z);
+    }
+    if (partials) block_partials<5>(acc, partials);
+}
+
+// Flux through the face between L and L + e_a (R).  Explicit fma: both sites
+// of the face evaluate exactly these instructions.
+__device__ __forceinline__ double fd_flux(double phiL, double phiR, double uL, double uR,
+                                          double muL, double muR, double M)
+{
+    const double uf = 0.5 * (uL + uR);
+    const double up = uf > 0.0 ? phiL : phiR;
+    const double dif = M * (muR - muL);
+    return __builtin_fma(uf, up, -dif);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fd_update(KParams p, const double* __restrict__ sphi,
+                                                      const double* __restrict__ work,
+                                                      double* __restrict__ dphi)
+{
+    const int s = xcd_block() * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    const Geo q = geo_of(p, s);
+    const double* __restrict__ mu = work;
+    const int np[3] = {site_of(p, q.xp, q.y, q.z), site_of(p, q.x, q.yp, q.z), site_of(p, q.x, q.y, q.zp)};
+    const int nm[3] = {site_of(p, q.xm, q.y, q.z), site_of(p, q.x, q.ym, q.z), site_of(p, q.x, q.y, q.zm)};
+    const double c = sphi[s], mc = mu[s], M = p.mobility;
+    double div = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double* __restrict__ ua = work + size_t(a + 1) * p.stride;
+        const double uc = ua[s];
+        const double jp = fd_flux(c, sphi[np[a]], uc, ua[np[a]], mc, mu[np[a]], M);
+        const double jm = fd_flux(sphi[nm[a]], c, ua[nm[a]], uc, mu[nm[a]], mc, M);
+        div += jp - jm;
+    }
+    dphi[s] = c - div;
+}
+
+// Dense FP64 moments and block partials of [rho, phi, jx, jy, jz]
+// (grid-stride); u = j/rho.
+template <typename T, bool DEV>
+__global__ __launch_bounds__(kBlock) void k_fd_moments(KParams p, const T* __restrict__ F,
+                                                       const double* __restrict__ phi,
+                                                       double* __restrict__ rho_out,
+                                                       double* __restrict__ u_out,
+                                                       double* __restrict__ phi_out,
+                                                       double* __restrict__ partials)
+{
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int s = xcd_block() * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
+        const Geo q = geo_of(p, s);
+        double b = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            const double v = double(F[dist_pull(p, q, i)]);
+            b += v;
+            jx += CX[i] * v;
+            jy += CY[i] * v;
+            jz += CZ[i] * v;
+        }
+        const double rho = DEV ? p.rho0 + b : b;
+        const double ph = phi[s];
+        if (rho_out) rho_out[s] = rho;
+        if (u_out) {
+            u_out[s] = jx / rho;
+            u_out[p.nsites + s] = jy / rho;
+            u_out[2LL * p.nsites + s] = jz / rho;
+        }
+        if (phi_out) phi_out[s] = ph;
+        acc[0] += rho;
+        acc[1] += ph;
+        acc[2] += jx;
+        acc[3] += jy;
+        acc[4] += jz;
+    }
+    block_partials<5>(acc, partials);
+}
+
+template <typename T, bool DEV>
+__global__ __launch_bounds__(kBlock) void k_fd_export(KParams p, const T* __restrict__ F,
+                                                      double* __restrict__ f)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    const Geo q = geo_of(p, s);
+#pragma unroll
+    for (int i = 0; i < NV; i++)
+        f[(long long)i * p.nsites + s] = double(F[dist_pull(p, q, i)]) + (DEV ? weight(i) * p.rho0 : 0.0);
+}
+
+// The stored value of direction i at y is the post-propagation value at y + c_i.
+template <typename T, bool DEV>
+__global__ __launch_bounds__(kBlock) void k_fd_import(KParams p, T* __restrict__ F,
+                                                      const double* __restrict__ f)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    const Geo q = geo_of(p, s);
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        const long long n = push_site(p, q, i) + (long long)i * p.nsites;
+        F[dist_own(p, q, i)] = T(f[n] - (DEV ? weight(i) * p.rho0 : 0.0));
+    }
+}
+
+int fd_grid(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
+
+int fd_reduction_grid(const KParams& p)
+{
+    const int g = fd_grid(p);
+    return g < kMaxPartialBlocks ? g : kMaxPartialBlocks;
+}
+
+// FP64 mode <double, false>, FP32 mode <float, true>.
+#define LB_FD_DISPATCH(fp32, CALL)     \
+    do {                               \
+        if (fp32) {                    \
+            using T = float;           \
+            constexpr bool DEV = true; \
+            CALL;                      \
+        } else {                       \
+            using T = double;          \
+            constexpr bool DEV = false; \
+            CALL;                      \
+        }                              \
+    } while (0)
+
+}  // namespace
+
+int fd_step_partial_blocks(const KParams& p) { return fd_grid(p); }
+
+hipError_t launch_fd_init(const KParams& p, bool fp32, void* state, const double* phi0,
+                          hipStream_t s)
+{
+#define CALL                                                                          \
+    {                                                                                 \
+        FdLvl<T> l = fd_level<T>(state, p);                                           \
+        k_fd_init<T, DEV><<<fd_grid(p), kBlock, 0, s>>>(p, l.F, l.phi, phi0);         \
+    }
+    LB_FD_DISPATCH(fp32, CALL);
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_step(const KParams& p, bool fp32, const void* src, void* dst, double* work,
+                          double* partials, double* sums_out, hipStream_t s)
+{
+#define CALL                                                                                  \
+    {                                                                                         \
+        FdLvl<T> a = fd_level<T>(const_cast<void*>(src), p);                                  \
+        FdLvl<T> d = fd_level<T>(dst, p);                                                     \
+        k_fd_collide<T, DEV><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, d.F, work,          \
+                                                           sums_out ? partials : nullptr);    \
+        k_fd_update<<<fd_grid(p), kBlock, 0, s>>>(p, a.phi, work, d.phi);                     \
+    }
+    LB_FD_DISPATCH(fp32, CALL);
+#undef CALL
+    if (sums_out) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_sums_final(partials, fd_grid(p), 5, sums_out, false, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_moments(const KParams& p, bool fp32, const void* state, double* rho,
+                             double* u, double* phi, double* partials, int* nblocks_out,
+                             hipStream_t s)
+{
+    const int nb = fd_reduction_grid(p);
+    *nblocks_out = nb;
+#define CALL                                                                                \
+    {                                                                                       \
+        FdLvl<T> a = fd_level<T>(const_cast<void*>(state), p);                              \
+        k_fd_moments<T, DEV><<<nb, kBlock, 0, s>>>(p, a.F, a.phi, rho, u, phi, partials);   \
+    }
+    LB_FD_DISPATCH(fp32, CALL);
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_export(const KParams& p, bool fp32, const void* state, double* f,
+                            hipStream_t s)
+{
+#define CALL                                                                        \
+    {                                                                               \
+        FdLvl<T> a = fd_level<T>(const_cast<void*>(state), p);                      \
+        k_fd_export<T, DEV><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, f);               \
+    }
+    LB_FD_DISPATCH(fp32, CALL);
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_import(const KParams& p, bool fp32, void* state, const double* f,
+                            hipStream_t s)
+{
+#define CALL                                                                        \
+    {                                                                               \
+        FdLvl<T> a = fd_level<T>(state, p);                                         \
+        k_fd_import<T, DEV><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, f);               \
+    }
+    LB_FD_DISPATCH(fp32, CALL);
+#undef CALL
+    return hipGetLastError();
+}
+
+}  // namespace lbk

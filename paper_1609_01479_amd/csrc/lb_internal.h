@@ -24,6 +24,8 @@ struct KParams {
     double omega_f, omega_g;  // 1/tau
     double rho0;
     int force;  // force coupling: -div Pi as a body force
+    int fd;           // finite-difference order parameter (no g)
+    double mobility;  // M = Gamma (tau_g - 1/2) of the finite-difference update
 };
 
 // Launch geometry of the single-pass step: (y, z) tiles times x segments.
@@ -80,6 +82,23 @@ hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
                            hipStream_t s);
 hipError_t launch_adj_phi0(const KParams& p, bool fp32, const void* adj, double* dphi0,
                            hipStream_t s);
+
+// Finite-difference order parameter (lb_fd.hip).  A time level is F
+// (19*stride elements, laid out per KParams) then phi (stride FP64 values);
+// `work` holds mu, u_x, u_y, u_z (4 FP64 fields of `stride`).  With sums_out,
+// `partials` needs 5 * fd_step_partial_blocks(p) doubles.
+int fd_step_partial_blocks(const KParams& p);
+hipError_t launch_fd_init(const KParams& p, bool fp32, void* state, const double* phi0,
+                          hipStream_t s);
+hipError_t launch_fd_step(const KParams& p, bool fp32, const void* src, void* dst, double* work,
+                          double* partials, double* sums_out, hipStream_t s);
+hipError_t launch_fd_moments(const KParams& p, bool fp32, const void* state, double* rho,
+                             double* u, double* phi, double* partials, int* nblocks_out,
+                             hipStream_t s);
+hipError_t launch_fd_export(const KParams& p, bool fp32, const void* state, double* f,
+                            hipStream_t s);
+hipError_t launch_fd_import(const KParams& p, bool fp32, void* state, const double* f,
+                            hipStream_t s);
 
 // Upper bound on the block partials any reduction writes (per component).
 constexpr int kMaxPartialBlocks = 2048;

@@ -19,6 +19,9 @@ from ._abi import LB_FP32_DEV, LB_FP64, NVEL, check
 LAYOUTS = {"rows": 0, "soa": 1, "aos": 2, "aosoa": 3}
 # how the chemical stress drives the flow (lb_coupling)
 COUPLINGS = {"stress": 0, "force": 1}
+# how the order parameter evolves (lb_order_param): LB distribution g, or a
+# field with the finite-difference Cahn-Hilliard update and upwind advection
+ORDER_PARAMS = {"lb": 0, "fd": 1}
 
 
 def _precision_code(precision) -> int:
@@ -46,12 +49,15 @@ class LB:
         two dividing nz); results are bit-identical across layouts.
     coupling: "stress" (Pi in the f equilibrium, default) or "force" (body
         force -div Pi with the half-force velocity; no adjoint).
+    order_param: "lb" (distribution g, default) or "fd" (a phi field with the
+        finite-difference Cahn-Hilliard update and upwind advection, mobility
+        Gamma (tau_g - 1/2); stress coupling only, no adjoint, no g).
     """
 
     def __init__(self, shape, *, A=-0.00625, B=0.00625, kappa=0.004, gamma=0.5, tau_f=1.0,
                  tau_g=1.0, rho0=1.0, precision="fp64", adjoint=False, device=None,
                  stream: torch.cuda.Stream | None = None, kernel="fused", segment_x=0,
-                 layout="rows", aosoa_len=0, coupling="stress"):
+                 layout="rows", aosoa_len=0, coupling="stress", order_param="lb"):
         L = _abi.lib()
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
@@ -60,7 +66,9 @@ class LB:
         self.params = _abi.LbParams(nx, ny, nz, float(A), float(B), float(kappa), float(gamma),
                                     float(tau_f), float(tau_g), float(rho0), self.precision,
                                     {"fused": 0, "two_pass": 1}[kernel], int(segment_x),
-                                    LAYOUTS[layout], int(aosoa_len), COUPLINGS[coupling])
+                                    LAYOUTS[layout], int(aosoa_len), COUPLINGS[coupling],
+                                    ORDER_PARAMS[order_param])
+        self.fd = self.params.order_param == ORDER_PARAMS["fd"]
         self.sizes = _abi.LbSizes()
         check(L.lb_query_sizes(ctypes.byref(self.params), ctypes.byref(self.sizes)),
               "lb_query_sizes")
@@ -187,19 +195,23 @@ class LB:
         self._call("lb_set_state", _ptr(src))
 
     def export_dist(self):
-        """Dense post-propagation (f, g), each FP64 (19, nx, ny, nz)."""
+        """Dense post-propagation (f, g), each FP64 (19, nx, ny, nz); g is None
+        for the finite-difference order parameter."""
         f = self._out(NVEL, *self.shape)
-        g = self._out(NVEL, *self.shape)
+        g = None if self.fd else self._out(NVEL, *self.shape)
         self._call("lb_export_dist", _ptr(f), _ptr(g))
         return f, g
 
-    def import_dist(self, f, g) -> None:
+    def import_dist(self, f, g=None) -> None:
+        """Set the state from dense (f, g); with order_param "fd", g is None
+        and phi keeps its values."""
         tf = self._dev64(f, (NVEL,) + self.shape)
-        tg = self._dev64(g, (NVEL,) + self.shape)
+        tg = None if g is None else self._dev64(g, (NVEL,) + self.shape)
         self._sync_inputs()
         self._call("lb_import_dist", _ptr(tf), _ptr(tg))
         tf.record_stream(self.stream)
-        tg.record_stream(self.stream)
+        if tg is not None:
+            tg.record_stream(self.stream)
 
     # -- reverse mode -------------------------------------------------------
     def adjoint_seed(self, dphi) -> None:

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(abi):
     L = abi.lib()
     for name in _declared_functions():
         assert hasattr(L, name), name
-    assert L.lb_abi_version() == 2
+    assert L.lb_abi_version() == 3
 
 
 def _params(abi, **kw):
@@ -73,6 +73,8 @@ def test_query_sizes(abi):
     (dict(layout=3, aosoa_len=3), "LB_ESHAPE"), (dict(layout=3, aosoa_len=0), "LB_ESHAPE"),
     (dict(layout=3, aosoa_len=64, nz=96), "LB_ESHAPE"),
     (dict(coupling=2), "LB_EINVAL"), (dict(coupling=-1), "LB_EINVAL"),
+    (dict(order_param=2), "LB_EINVAL"), (dict(order_param=-1), "LB_EINVAL"),
+    (dict(order_param=1, coupling=1), "LB_EINVAL"),
 ])
 def test_bad_parameters_rejected(abi, kw, code):
     st, _ = _query(abi, **kw)
@@ -95,6 +97,35 @@ def test_force_coupling_sizes_and_no_adjoint(abi):
     assert L.lb_adjoint_seed(ctx, ctypes.c_void_p(0x8000)) == abi.LB_ESTATE
     assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), None, None) == abi.LB_ESTATE
     assert L.lb_adjoint_phi0(ctx, ctypes.c_void_p(0x8000)) == abi.LB_ESTATE
+    L.lb_destroy(ctx)
+
+
+@pytest.mark.parametrize("prec,e", [(0, 8), (1, 4)])
+def test_fd_order_parameter_sizes_and_calls_without_launching(abi, prec, e):
+    """The finite-difference order parameter: a level is f then the FP64 phi
+    field, 4 FP64 work fields (mu, u), partials for one block per 256 sites;
+    g-taking calls reject a g pointer and the reverse mode returns LB_ESTATE,
+    all before any HIP call."""
+    n = 40 * 40 * 40
+    st, s = _query(abi, nx=40, ny=40, nz=40, order_param=1, precision=prec)
+    assert st == abi.LB_OK
+    assert s.state_bytes == 19 * s.stride_elems * e + s.stride_elems * 8
+    assert s.phi_bytes == 4 * s.stride_elems * 8
+    assert s.scratch_bytes >= 5 * 8 * ((n + 255) // 256)
+    L = abi.lib()
+    p = _params(abi, order_param=1, precision=prec)
+    ctx = ctypes.c_void_p()
+    b = abi.LbBuffers()
+    b.state[0], b.state[1], b.phi, b.scratch = 0x1000, 0x2000, 0x3000, 0x4000
+    b.adj[0], b.adj[1], b.adj_scratch = 0x5000, 0x6000, 0x7000
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
+    v = ctypes.c_void_p(0x8000)
+    assert L.lb_export_dist(ctx, v, v) == abi.LB_EINVAL
+    assert L.lb_import_dist(ctx, v, v) == abi.LB_EINVAL
+    assert L.lb_import_dist(ctx, None, None) == abi.LB_EINVAL
+    assert L.lb_adjoint_seed(ctx, v) == abi.LB_ESTATE
+    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), None, None) == abi.LB_ESTATE
+    assert L.lb_adjoint_phi0(ctx, v) == abi.LB_ESTATE
     L.lb_destroy(ctx)
 
 

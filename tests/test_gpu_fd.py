@@ -1,0 +1,176 @@
+"""Parity of the finite-difference order parameter (a phi field with a
+conservative Cahn-Hilliard update and upwind advection; no g) between the HIP
+path (through the C ABI) and the CPU oracle.
+
+Bar (FP64): for every output field F (f, rho, u, phi),
+max_x |F_gpu - F_oracle| / max_x |F_oracle| <= 1e-12 (u on scale 1).  FP32
+storage of f: phi stays FP64, so it follows the FP64 oracle to 1e-6 over 20
+steps (rho 1e-6, u 1e-7), and the 40^3 droplet to 1e-5 over 300 steps.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import lbinputs
+import oracle
+from tests._gpu import field_errors, make_lb, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+NAMES = ("f", "rho", "u", "phi")
+
+
+def _gpu(lb):
+    f, g = lb.export_dist()
+    assert g is None
+    rho, u, phi = lb.moments()
+    torch.cuda.synchronize()
+    return tuple(t.cpu().numpy() for t in (f, rho, u, phi))
+
+
+def _ref(p, f, phi):
+    rho, u, ph = oracle.fd_moments(p, f, phi)
+    return f, rho, u, ph
+
+
+def _run_both(shape, steps, phi0, precision="fp64", **kw):
+    print(f"[fd] shape={shape} steps={steps} precision={precision} params={kw}", flush=True)
+    lb = make_lb(shape, precision=precision, order_param="fd", **kw)
+    lb.init_phi(phi0)
+    lb.step(steps)
+    got = _gpu(lb)
+    p = oracle_params(shape, order_param=1, **kw)
+    ref = _ref(p, *oracle.fd_run(p, *oracle.fd_init(p, phi0), steps))
+    return got, ref, lb, p
+
+
+@pytest.mark.parametrize("steps", [0, 1, 10, 100])
+def test_fd_spinodal_16cubed(steps):
+    shape = (16, 16, 16)
+    got, ref, *_ = _run_both(shape, steps, lbinputs.spinodal_phi0(shape))
+    errs = field_errors(got, ref, NAMES)
+    assert max(errs.values()) <= TOL, errs
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (3, 5, 131), (17, 9, 70), (1, 7, 1), (2, 2, 2)])
+def test_fd_noncubic_ragged_degenerate_tau_not_one(shape):
+    phi0 = lbinputs.spinodal_phi0(shape, seed=12, amp=0.4)
+    got, ref, *_ = _run_both(shape, 25, phi0, tau_f=0.8, tau_g=1.3)
+    errs = field_errors(got, ref, NAMES)
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_fd_droplet_interface_and_sums():
+    """A sharp tanh droplet (large mu and Pi at the interface), 50 steps; the
+    conserved sums of the final state."""
+    shape = (24, 20, 22)
+    pr = lbinputs.SPINODAL_PARAMS
+    xi = lbinputs.interface_width(pr["A"], pr["kappa"])
+    phi0 = lbinputs.droplet_phi0(shape, 6.0, xi, noise=1e-3, seed=3)
+    got, ref, lb, p = _run_both(shape, 50, phi0)
+    errs = field_errors(got, ref, NAMES)
+    assert max(errs.values()) <= TOL, errs
+    want = oracle.fd_sums(p, *oracle.fd_run(p, *oracle.fd_init(p, phi0), 50))
+    np.testing.assert_allclose(lb.sums().cpu().numpy(), want, rtol=1e-12, atol=1e-12)
+
+
+def test_fd_flow_advects_phi():
+    """A uniform flow imported as f = w (rho + 3 c.j): the upwind advection
+    moves phi exactly as the oracle's (mixed-sign velocity, M = 0 and no
+    free energy, so advection is all that acts on phi)."""
+    shape = (12, 10, 14)
+    kw = dict(A=0.0, B=0.0, kappa=0.0, gamma=0.0)
+    c, w = oracle.lattice()
+    j = np.array([0.031, -0.022, 0.013])
+    f0 = np.broadcast_to((w * (1.0 + 3 * (c @ j)))[:, None, None, None], (19,) + shape).copy()
+    phi0 = lbinputs.random_field(shape, seed=21)
+    lb = make_lb(shape, order_param="fd", **kw)
+    lb.init_phi(phi0)
+    lb.import_dist(f0)
+    lb.step(20)
+    got = _gpu(lb)
+    p = oracle_params(shape, order_param=1, **kw)
+    ref = _ref(p, *oracle.fd_run(p, f0, phi0, 20))
+    errs = field_errors(got, ref, NAMES)
+    assert max(errs.values()) <= TOL, errs
+    assert np.abs(got[3] - phi0).max() > 0.1  # phi moved
+
+
+@pytest.mark.parametrize("layout,v", [("soa", 0), ("aos", 0), ("aosoa", 8)])
+def test_fd_layouts_bit_identical(layout, v):
+    shape = (6, 7, 16)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=8, amp=0.3)
+    out = []
+    for lay, vv in (("rows", 0), (layout, v)):
+        lb = make_lb(shape, order_param="fd", layout=lay, aosoa_len=vv, tau_f=0.9)
+        lb.init_phi(phi0)
+        lb.step(9)
+        out.append(_gpu(lb))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+def test_fd_step_sums_step_from_and_determinism():
+    """Per-step FP64 sums are conserved (mass, phi; momentum to round-off) and
+    match the oracle's; lb_step_from gives the same level as lb_step; two runs
+    from one checkpoint agree bit for bit."""
+    shape = (12, 10, 14)
+    phi0 = 0.1 + lbinputs.spinodal_phi0(shape, seed=2, amp=0.3)
+    lb = make_lb(shape, order_param="fd", tau_f=0.8, tau_g=1.1)
+    lb.init_phi(phi0)
+    hist = lb.step_sums(30).cpu().numpy()
+    assert np.abs(hist[:, :2] - hist[0, :2]).max() <= 1e-11
+    assert np.abs(hist[:, 2:] - hist[0, 2:]).max() <= 1e-12
+    p = oracle_params(shape, order_param=1, tau_f=0.8, tau_g=1.1)
+    f, phi = oracle.fd_run(p, *oracle.fd_init(p, phi0), 29)
+    np.testing.assert_allclose(hist[29], oracle.fd_sums(p, f, phi), rtol=1e-12, atol=1e-12)
+    ck = lb.get_state()
+    lb.step(7)
+    a = _gpu(lb)
+    lb.set_state(ck)
+    lb.step(7)
+    b = _gpu(lb)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    lb.set_state(ck)
+    lb.step(1)
+    a = _gpu(lb)
+    nxt = lb.new_state()
+    lb.step_from(ck, nxt)
+    lb.set_state(nxt)
+    b = _gpu(lb)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (9, 6, 131)])
+def test_fd_fp32_storage(shape):
+    """FP32 deviation storage of f (phi FP64) follows the FP64 oracle to FP32
+    rounding over 20 steps (tau != 1)."""
+    phi0 = lbinputs.spinodal_phi0(shape, seed=14, amp=0.3)
+    got, ref, *_ = _run_both(shape, 20, phi0, precision="fp32_dev", tau_f=0.8, tau_g=1.3)
+    f, rho, u, phi = got
+    rf, rrho, ru, rphi = ref
+    assert np.abs(phi - rphi).max() <= 1e-6
+    assert np.abs(rho - rrho).max() <= 1e-6
+    assert np.abs(u - ru).max() <= 1e-7
+
+
+def test_fd_fp32_droplet_phi_error_vs_fp64():
+    """A droplet over 300 steps: max |phi32 - phi64| <= 1e-5."""
+    shape = (40, 40, 40)
+    pr = lbinputs.SPINODAL_PARAMS
+    xi = lbinputs.interface_width(pr["A"], pr["kappa"])
+    phi0 = lbinputs.droplet_phi0(shape, 10.0, xi, noise=1e-3, seed=4)
+    out = {}
+    for prec in ("fp64", "fp32_dev"):
+        lb = make_lb(shape, precision=prec, order_param="fd")
+        lb.init_phi(phi0)
+        lb.step(300)
+        out[prec] = lb.phi().cpu().numpy()
+    err = np.abs(out["fp32_dev"] - out["fp64"]).max()
+    print(f"[fd] fp32 vs fp64 phi error after 300 steps: {err:.3e}", flush=True)
+    assert err <= 1e-5
