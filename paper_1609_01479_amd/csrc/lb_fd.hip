@@ -2,14 +2,14 @@
 // distribution f and a field phi, which follows a conservative Cahn-Hilliard
 // update with upwind advection -- the binary-fluid counterpart of the paper's
 // "Advection" (a stencil of fluxes) and order-parameter update (local)
-// kernels, Sec. 2.1.1.  Two kernels per step, one site per thread:
+// kernels, Sec. 2.1.1.  Two kernels per step:
 //
-//   k_fd_collide: pull of f, 7-point stencil of phi, mu and Pi, collision of
-//     f with Pi in f^eq and its store; mu and u = j/rho into FP64 work
-//     fields; optionally the block partials of the source level's conserved
-//     sums.
-//   k_fd_update: the fluxes through the site's six faces from phi, mu and u
-//     of the site and its face neighbours,
+//   k_fd_collide (one site per thread): pull of f, 7-point stencil of phi,
+//     mu and Pi, collision of f with Pi in f^eq and its store; mu and
+//     u = j/rho into FP64 work fields; optionally the block partials of the
+//     source level's conserved sums.
+//   k_fd_update: marching along x, the fluxes through each site's six faces
+//     from phi, mu and u of the site and its face neighbours,
 //       J_a(x + e_a/2) = u_f (u_f > 0 ? phi(x) : phi(x + e_a)) - M (mu(x + e_a) - mu(x)),
 //       u_f = (u_a(x) + u_a(x + e_a)) / 2,
 //     and phi(t+1) = phi - sum_a [J_a(x + e_a/2) - J_a(x - e_a/2)].
@@ -114,27 +114,58 @@ __device__ __forceinline__ double fd_flux(double phiL, double phiR, double uL, d
     return __builtin_fma(uf, up, -dif);
 }
 
-__global__ __launch_bounds__(kBlock) void k_fd_update(KParams p, const double* __restrict__ sphi,
-                                                      const double* __restrict__ work,
-                                                      double* __restrict__ dphi)
+// Update pass, marching along x: a workgroup owns a kFdTY x kFdTZ tile of
+// (y, z) columns and a segment of x planes; each thread keeps phi, mu and u_x
+// of planes x-1, x, x+1 of its column in registers, so the x-neighbour
+// fields are read from HBM once (one site per thread would need three
+// planes of five fields, more than an XCD's L2, and read them twice).  The
+// y and z neighbours are in the same plane, read by the neighbouring threads
+// and tiles at about the same time (cache hits).  No LDS and no barriers:
+// threads outside the lattice return at once.
+constexpr int kFdTY = 4, kFdTZ = 64;
+static_assert(kFdTY * kFdTZ == kBlock, "update tile must match the block");
+
+// 8 waves per SIMD (at most 64 VGPRs): the ~2048 workgroups then run in one
+// round on 256 CUs instead of 1.33.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fd_update(
+    KParams p, int ntz, int ntiles, int sx, const double* __restrict__ sphi,
+    const double* __restrict__ work, double* __restrict__ dphi)
 {
-    const int s = xcd_block() * kBlock + threadIdx.x;
-    if (s >= p.nsites) return;
-    const Geo q = geo_of(p, s);
+    const int b = xcd_block();
+    const int seg = b / ntiles, tile = b - seg * ntiles;
+    const int y = (tile / ntz) * kFdTY + int(threadIdx.x) / kFdTZ;
+    const int z = (tile % ntz) * kFdTZ + int(threadIdx.x) % kFdTZ;
+    if (y >= p.ny || z >= p.nz) return;
+    const int x0 = seg * sx, x1 = min(p.nx, x0 + sx);
     const double* __restrict__ mu = work;
-    const int np[3] = {site_of(p, q.xp, q.y, q.z), site_of(p, q.x, q.yp, q.z), site_of(p, q.x, q.y, q.zp)};
-    const int nm[3] = {site_of(p, q.xm, q.y, q.z), site_of(p, q.x, q.ym, q.z), site_of(p, q.x, q.y, q.zm)};
-    const double c = sphi[s], mc = mu[s], M = p.mobility;
-    double div = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const double* __restrict__ ua = work + size_t(a + 1) * p.stride;
-        const double uc = ua[s];
-        const double jp = fd_flux(c, sphi[np[a]], uc, ua[np[a]], mc, mu[np[a]], M);
-        const double jm = fd_flux(sphi[nm[a]], c, ua[nm[a]], uc, mu[nm[a]], mc, M);
-        div += jp - jm;
+    const double* __restrict__ ux = work + p.stride;
+    const double* __restrict__ uy = work + 2 * size_t(p.stride);
+    const double* __restrict__ uz = work + 3 * size_t(p.stride);
+    const double M = p.mobility;
+    const int plane = p.ny * p.nz;
+    const int oc = y * p.nz + z;
+    const int oym = wrapm(y, p.ny) * p.nz + z, oyp = wrapp(y, p.ny) * p.nz + z;
+    const int ozm = y * p.nz + wrapm(z, p.nz), ozp = y * p.nz + wrapp(z, p.nz);
+    const int sm = wrapm(x0, p.nx) * plane + oc;
+    double pm = sphi[sm], mm = mu[sm], um = ux[sm];
+    const int s0 = x0 * plane + oc;
+    double pc = sphi[s0], mc = mu[s0], uc = ux[s0];
+    for (int x = x0; x < x1; x++) {
+        const int sc = x * plane;
+        const int sp = wrapp(x, p.nx) * plane + oc;
+        const double pp = sphi[sp], mp = mu[sp], up = ux[sp];
+        double div = 0.0;
+        div += fd_flux(pc, pp, uc, up, mc, mp, M) - fd_flux(pm, pc, um, uc, mm, mc, M);
+        const double uyc = uy[sc + oc];
+        div += fd_flux(pc, sphi[sc + oyp], uyc, uy[sc + oyp], mc, mu[sc + oyp], M)
+             - fd_flux(sphi[sc + oym], pc, uy[sc + oym], uyc, mu[sc + oym], mc, M);
+        const double uzc = uz[sc + oc];
+        div += fd_flux(pc, sphi[sc + ozp], uzc, uz[sc + ozp], mc, mu[sc + ozp], M)
+             - fd_flux(sphi[sc + ozm], pc, uz[sc + ozm], uzc, mu[sc + ozm], mc, M);
+        dphi[sc + oc] = pc - div;
+        pm = pc; mm = mc; um = uc;
+        pc = pp; mc = mp; uc = up;
     }
-    dphi[s] = c - div;
 }
 
 // Dense FP64 moments and block partials of [rho, phi, jx, jy, jz]
@@ -206,6 +237,24 @@ __global__ __launch_bounds__(kBlock) void k_fd_import(KParams p, T* __restrict__
 
 int fd_grid(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
 
+// Update-pass geometry: (y, z) tiles times x segments, about 2048
+// workgroups (8 waves per SIMD on 256 CUs) when the lattice allows.
+struct FdTiles {
+    int ntz, ntiles, sx, nseg;
+};
+
+FdTiles fd_tiles(const KParams& p)
+{
+    FdTiles t;
+    t.ntz = (p.nz + kFdTZ - 1) / kFdTZ;
+    t.ntiles = ((p.ny + kFdTY - 1) / kFdTY) * t.ntz;
+    int nseg = (2048 + t.ntiles - 1) / t.ntiles;
+    nseg = nseg < 1 ? 1 : (nseg > p.nx ? p.nx : nseg);
+    t.sx = (p.nx + nseg - 1) / nseg;
+    t.nseg = (p.nx + t.sx - 1) / t.sx;
+    return t;
+}
+
 int fd_reduction_grid(const KParams& p)
 {
     const int g = fd_grid(p);
@@ -246,13 +295,15 @@ hipError_t launch_fd_init(const KParams& p, bool fp32, void* state, const double
 hipError_t launch_fd_step(const KParams& p, bool fp32, const void* src, void* dst, double* work,
                           double* partials, double* sums_out, hipStream_t s)
 {
+    const FdTiles ft = fd_tiles(p);
 #define CALL                                                                                  \
     {                                                                                         \
         FdLvl<T> a = fd_level<T>(const_cast<void*>(src), p);                                  \
         FdLvl<T> d = fd_level<T>(dst, p);                                                     \
         k_fd_collide<T, DEV><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, d.F, work,          \
                                                            sums_out ? partials : nullptr);    \
-        k_fd_update<<<fd_grid(p), kBlock, 0, s>>>(p, a.phi, work, d.phi);                     \
+        k_fd_update<<<ft.ntiles * ft.nseg, kBlock, 0, s>>>(p, ft.ntz, ft.ntiles, ft.sx, a.phi,  \
+                                                           work, d.phi);                      \
     }
     LB_FD_DISPATCH(fp32, CALL);
 #undef CALL

@@ -174,3 +174,91 @@ def test_fd_fp32_droplet_phi_error_vs_fp64():
     err = np.abs(out["fp32_dev"] - out["fp64"]).max()
     print(f"[fd] fp32 vs fp64 phi error after 300 steps: {err:.3e}", flush=True)
     assert err <= 1e-5
+
+
+# ---- full sizes: sampled sites --------------------------------------------
+# One step at x depends only on the state within L-infinity distance 2 of x
+# (phi(t+1) uses mu and u at the face neighbours; mu needs phi's stencil
+# there and u the populations pulled from one site further), so the oracle
+# steps a 7^3 periodic window cut around each sampled site from the GPU's
+# state, and the window's centre is compared with the GPU's step at x.
+
+R = 3
+
+
+def _win(t, site, shape):
+    idx = [torch.tensor([(c + d) % n for d in range(-R, R + 1)], device=t.device)
+           for c, n in zip(site, shape)]
+    off = t.dim() - 3
+    w = t.index_select(off, idx[0]).index_select(off + 1, idx[1]).index_select(off + 2, idx[2])
+    return w.cpu().numpy()
+
+
+def _sampled_fd(shape, precision, phi0, steps_before, kw, tol, nsample=16):
+    print(f"[fd fullsize] {shape} {precision} after {steps_before} steps, {nsample} sites",
+          flush=True)
+    rng = np.random.default_rng(9)
+    nx, ny, nz = shape
+    sites = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (nx // 2, ny // 2, nz // 2), (1, ny - 1, 64 % nz)]
+    sites += [(int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz)))
+              for _ in range(nsample)]
+    lb = make_lb(shape, precision=precision, order_param="fd", **kw)
+    lb.init_phi(phi0)
+    lb.step(steps_before)
+    f, _ = lb.export_dist()
+    phi = lb.phi()
+    wins = [(_win(f, s, shape), _win(phi, s, shape)) for s in sites]
+    del f, phi
+    torch.cuda.empty_cache()
+    lb.step(1)
+    f1, _ = lb.export_dist()
+    phi1 = lb.phi()
+    got = [(f1[:, x, y, z].cpu().numpy(), float(phi1[x, y, z])) for x, y, z in sites]
+    del f1, phi1, lb
+    torch.cuda.empty_cache()
+    pw = oracle_params((2 * R + 1,) * 3, order_param=1, **kw)
+    ferr = perr = fscale = pscale = 0.0
+    for (fw, pw_phi), (fg, pg) in zip(wins, got):
+        fo, po = oracle.fd_step(pw, fw, pw_phi)
+        ferr = max(ferr, float(np.abs(fg - fo[:, R, R, R]).max()))
+        perr = max(perr, abs(pg - float(po[R, R, R])))
+        fscale = max(fscale, float(np.abs(fo[:, R, R, R]).max()))
+        pscale = max(pscale, abs(float(po[R, R, R])))
+    print(f"[fd fullsize] rel err f {ferr / fscale:.3e}  phi {perr / pscale:.3e}", flush=True)
+    assert ferr <= tol * fscale and perr <= tol * pscale
+
+
+def _droplet(shape):
+    pr = lbinputs.SPINODAL_PARAMS
+    xi = lbinputs.interface_width(pr["A"], pr["kappa"])
+    return lbinputs.droplet_phi0(shape, min(shape) / 4, xi, noise=1e-3, seed=lbinputs.SEED_DROPLET)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_dev", 2e-6)])
+def test_fd_sampled_parity_droplet_256(precision, tol):
+    """The benchmark lattice (256^3 droplet), both precisions, tau != 1."""
+    shape = (256, 256, 256)
+    _sampled_fd(shape, precision, _droplet(shape), 5, dict(tau_f=0.8, tau_g=1.3), tol)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_dev", 2e-6)])
+def test_fd_sampled_parity_maximum_size(precision, tol):
+    """479^3, the largest cube the library accepts, ragged everywhere."""
+    shape = (479, 479, 479)
+    _sampled_fd(shape, precision, _droplet(shape), 1, dict(tau_f=0.8, tau_g=1.3), tol, nsample=8)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
+def test_fd_conservation_droplet_256(precision):
+    """Mass, phi and momentum over 100 steps of the 256^3 droplet."""
+    shape = (256, 256, 256)
+    lb = make_lb(shape, precision=precision, order_param="fd")
+    lb.init_phi(_droplet(shape))
+    s0 = lb.sums().cpu().numpy()
+    lb.step(100)
+    s1 = lb.sums().cpu().numpy()
+    n = 256 ** 3
+    # phi is FP64 in both modes; mass and momentum as the LB scheme's storage
+    tol = 1e-9 * n if precision == "fp64" else 2e-7 * n
+    assert np.abs(s1 - s0).max() <= tol, (s1 - s0)
+    assert abs(s1[1] - s0[1]) <= 1e-9 * n
