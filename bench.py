@@ -279,14 +279,13 @@ def main():
             torch.cuda.empty_cache()
 
     # finite-difference order parameter (a phi field, no g) on the same 256^3
-    # droplet: the collision pass moves 344 B per site in FP64 (f read 152 and
-    # written 152, phi 8, mu and u written 32) and 192 in FP32 storage
-    # (76 + 76 + 8 + 32); the update pass 48 (phi, mu, u read, phi written).
-    # The scheme's minimum, f and phi read and written once, is 320 and 168.
+    # droplet, single-pass kernel: f read and written once (FP64 304, FP32
+    # storage 152 B per site) and phi read and written once (16): 320 and 168
+    # B per site, the scheme's minimum.
     if args.fd_steps > 0:
         out["fd_order_parameter"] = {}
         fd_phi = {}
-        for prec, moved, minimum in (("fp32_dev", 240, 168), ("fp64", 392, 320)):
+        for prec, moved in (("fp32_dev", 168), ("fp64", 320)):
             lb = LB(shape, precision=prec, order_param="fd", device="cuda:0", **lay, **params)
             lb.init_phi(phi0)
             log(f"{prec} finite-difference order parameter {shape}: {args.fd_steps} steps")
@@ -299,8 +298,7 @@ def main():
                 "achieved_GBps": round(moved * nsites / t / 1e9, 1),
                 "frac": round(moved * nsites / t / 1e9 / HBM_PEAK_GBPS, 4),
                 "bytes_per_site": moved,
-                "effective_GBps": round(minimum * nsites / t / 1e9, 1),
-                "kernels": "k_fd_collide + k_fd_update"}
+                "kernels": "k_fd_fused"}
             del lb
             torch.cuda.empty_cache()
         out["fd_order_parameter"]["phi_fp32_vs_fp64_max"] = float(

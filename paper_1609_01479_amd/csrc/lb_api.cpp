@@ -236,7 +236,8 @@ static hipError_t one_step(lb_ctx* ctx, const void* src, void* dst, double* sums
     double* work = static_cast<double*>(ctx->b.phi);
     double* part = static_cast<double*>(ctx->b.scratch);
     if (ctx->kp.fd)
-        return lbk::launch_fd_step(ctx->kp, ctx->fp32, src, dst, work, part, sums_dev, ctx->stream);
+        return lbk::launch_fd_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel, src, dst, work, part,
+                                   sums_dev, ctx->stream);
     return lbk::launch_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel, src, dst, work, part,
                             sums_dev, ctx->stream);
 }

@@ -407,6 +407,17 @@ __device__ __forceinline__ void collide_force(const KParams& p, T* f, T* g, doub
     }
 }
 
+// Workgroup barrier for LDS traffic only: every wave's LDS writes have
+// completed (lgkmcnt) before any wave passes.  Unlike __syncthreads() it
+// does not first wait for the wave's outstanding global loads and stores,
+// which the single-pass kernels keep in flight across the barrier (no
+// global data written in a launch is read back in it).  The clobber keeps
+// the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // ---------------------------------------------------------------------------
 // Block reduction of K FP64 values (fixed order): wavefront butterfly, then
 // the block's NB/64 waves as a pairwise tree.  Thread 0 writes component k to

@@ -20,6 +20,15 @@
 //
 // Time level: F (19*stride elements of T in the layout of didx(); FP32 mode
 // stores f - w rho0) followed by phi (stride FP64 values in site order).
+// No floating-point contraction in this translation unit (including the
+// shared device functions it inlines): the compiler fuses a multiply and an
+// add differently in different kernels, and the single-pass and two-kernel
+// paths must round every expression alike.  The kernels are memory-bound, so
+// the extra instructions cost nothing measurable.
+#pragma clang fp contract(off)
+
+#include <type_traits>
+
 #include "lb_device.h"
 
 namespace lbk {
@@ -53,6 +62,12 @@ __global__ __launch_bounds__(kBlock) void k_fd_init(KParams p, T* __restrict__ F
 #pragma unroll
     for (int i = 0; i < NV; i++) F[dist_own(p, q, i)] = DEV ? T(0) : T(weight(i) * p.rho0);
     phi[s] = phi0[s];
+}
+
+// mu = A phi + B phi^3 - kappa lap phi (FP64), one expression for every kernel.
+__device__ __forceinline__ double fd_mu(const KParams& p, double c, double lap)
+{
+    return p.A * c + p.B * c * c * c - p.kappa * lap;
 }
 
 // Work fields (each `stride` FP64 values): mu, u_x, u_y, u_z.
@@ -95,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_fd_collide(KParams p, const T* __res
         // the new level is not read in this launch
 #pragma unroll
         for (int i = 0; i < NV; i++) __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
-        work[s] = p.A * c + p.B * c * c * c - p.kappa * st.lap;
+        work[s] = fd_mu(p, c, st.lap);
         work[p.stride + s] = double(u.x);
         work[2 * p.stride + s] = double(u.y);
         work[3 * p.stride + s] = double(u.z);
@@ -167,6 +182,199 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         pc = pp; mc = mp; uc = up;
     }
 }
+
+// ---------------------------------------------------------------------------
+// Single-pass step (LB_KERNEL_FUSED): both passes in one kernel, the
+// collision one plane ahead of the flux update.  A workgroup of kFdFused
+// threads owns a TY x TZ tile of (y, z) columns (the single-pass LB
+// kernel's tiling) and marches over its x segment [x0, x1).  For plane P it
+//   (a) loads phi(P+1) on the tile plus two cells around it into a 4-plane
+//       LDS ring;
+//   (c) collides f at the tile's sites of plane P (stencil from the ring),
+//       keeps mu(P) and u(P) of the thread's own column in registers and
+//       writes mu, u_y, u_z to a 2-plane LDS ring; the first 2(TY + TZ)
+//       threads also form mu and the face-normal velocity on the tile's
+//       face ring (rows y0-1, y0+TY; columns z0-1, z0+TZ) from their own
+//       pulls, which hit in cache;
+//   (e) updates phi at plane P-1 from the fluxes through its six faces.
+// Planes x0-1 and x1 only supply mu and u_x of the own column (nothing is
+// stored for them).  Tile cells beyond a ragged lattice edge stand for the
+// periodic images of the sites there: they compute but store nothing.
+// Every value is formed with the same arithmetic as the two-kernel path, so
+// both paths give bit-identical levels.
+constexpr int kFdFused = 512;
+
+template <int TZ>
+struct FdTile {
+    static constexpr int TY = kFdFused / TZ;
+    static constexpr int BY = TY + 4, BZ = TZ + 4;  // phi box: two cells around the tile
+    static constexpr int RY = TY + 2, RZ = TZ + 2;  // tile and its face ring
+    static constexpr int NBOX = BY * BZ;
+    static constexpr int NRING = 2 * (TY + TZ);
+    static constexpr int BOXPT = (NBOX + kFdFused - 1) / kFdFused;
+};
+
+__device__ __forceinline__ int wrap_any(int v, int n)
+{
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+template <typename T, bool DEV, int TZ>
+__global__ __launch_bounds__(kFdFused) void k_fd_fused(KParams p, TileCfg tc,
+                                                       const T* __restrict__ sF,
+                                                       const double* __restrict__ sphi,
+                                                       T* __restrict__ dF,
+                                                       double* __restrict__ dphi,
+                                                       double* __restrict__ partials)
+{
+    using G = FdTile<TZ>;
+    constexpr int TY = G::TY, BZ = G::BZ, RZ = G::RZ;
+    __shared__ double s_phi[4][G::NBOX];
+    __shared__ double s_mu[2][G::RY * RZ];
+    __shared__ double s_uy[2][G::RY * RZ];
+    __shared__ double s_uz[2][G::RY * RZ];
+
+    const int t = threadIdx.x;
+    const int b = xcd_block();
+    const int seg = b / tc.ntiles, tile = b - seg * tc.ntiles;
+    const int y0 = (tile / tc.ntz) * TY, z0 = (tile % tc.ntz) * TZ;
+    const int x0 = seg * tc.sx, x1 = min(p.nx, x0 + tc.sx);
+    const int plane = p.ny * p.nz;
+
+    // own tile cell
+    const int ly = t / TZ, lz = t % TZ;
+    const int yg = wrap_any(y0 + ly, p.ny), zg = wrap_any(z0 + lz, p.nz);
+    const bool valid = y0 + ly < p.ny && z0 + lz < p.nz;
+    const int bo = (ly + 2) * BZ + (lz + 2);
+    const int ro = (ly + 1) * RZ + (lz + 1);
+    // phi box cells loaded by this thread (in-plane offsets; -1: none)
+    int boff[G::BOXPT];
+#pragma unroll
+    for (int k = 0; k < G::BOXPT; k++) {
+        const int c = t + k * kFdFused;
+        boff[k] = c < G::NBOX
+                      ? wrap_any(y0 + c / BZ - 2, p.ny) * p.nz + wrap_any(z0 + c % BZ - 2, p.nz)
+                      : -1;
+    }
+    // face-ring cell of this thread
+    const bool ring = t < G::NRING;
+    int rly, rlz;
+    if (t < TZ) { rly = -1; rlz = t; }
+    else if (t < 2 * TZ) { rly = TY; rlz = t - TZ; }
+    else if (t < 2 * TZ + TY) { rly = t - 2 * TZ; rlz = -1; }
+    else { rly = t - 2 * TZ - TY; rlz = TZ; }
+    const bool ring_y = rly < 0 || rly >= TY;  // a row of the ring: u_y; else a column: u_z
+    const int ryg = wrap_any(y0 + rly, p.ny), rzg = wrap_any(z0 + rlz, p.nz);
+    const int rbo = (rly + 2) * BZ + (rlz + 2);
+    const int rro = (rly + 1) * RZ + (rlz + 1);
+
+    const double M = p.mobility;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+    auto load_phi = [&](int xp) {
+        const int xo = wrap_any(xp, p.nx) * plane;
+        double* __restrict__ dst = s_phi[xp & 3];
+#pragma unroll
+        for (int k = 0; k < G::BOXPT; k++)
+            if (boff[k] >= 0) dst[t + k * kFdFused] = sphi[xo + boff[k]];
+    };
+    load_phi(x0 - 2);
+    load_phi(x0 - 1);
+
+    // own column: phi, mu, u_x at X-1 and X, u_y and u_z at X, X = P-1
+    double phA = 0.0, phB = 0.0, muA = 0.0, muB = 0.0, uxA = 0.0, uxB = 0.0, uyB = 0.0, uzB = 0.0;
+    for (int P = x0 - 1; P <= x1; P++) {
+        // (a) phi(P+1) into the ring
+        load_phi(P + 1);
+        lds_barrier();
+        const double* __restrict__ fm = s_phi[(P - 1) & 3];
+        const double* __restrict__ fc = s_phi[P & 3];
+        const double* __restrict__ fp = s_phi[(P + 1) & 3];
+        const bool interior = P >= x0 && P < x1;
+        const int xg = wrap_any(P, p.nx);
+        const int w = P & 1;
+
+        // (c) collision of the own cell of plane P
+        const double phc = fc[bo];
+        const Stencil st = stencil(phc, fp[bo], fm[bo], fc[bo + BZ], fc[bo - BZ], fc[bo + 1], fc[bo - 1]);
+        const Geo q = geo_xyz(p, xg, yg, zg);
+        T f[NV];
+#pragma unroll
+        for (int i = 0; i < NV; i++) f[i] = sF[dist_pull(p, q, i)];
+        if (partials && interior && valid) {
+            double bs = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+            for (int i = 0; i < NV; i++) {
+                const double v = double(f[i]);
+                bs += v;
+                jx += CX[i] * v;
+                jy += CY[i] * v;
+                jz += CZ[i] * v;
+            }
+            acc[0] += DEV ? p.rho0 + bs : bs;
+            acc[1] += phc;
+            acc[2] += jx;
+            acc[3] += jy;
+            acc[4] += jz;
+        }
+        const Vel<T> u = collide_f<T, DEV>(p, f, st);
+        if (interior && valid)
+#pragma unroll
+            for (int i = 0; i < NV; i++) __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
+        const double muP = fd_mu(p, phc, st.lap);
+        const double uxP = double(u.x), uyP = double(u.y), uzP = double(u.z);
+        s_mu[w][ro] = muP;
+        s_uy[w][ro] = uyP;
+        s_uz[w][ro] = uzP;
+        // the face ring of plane P
+        if (ring && interior) {
+            const Geo qr = geo_xyz(p, xg, ryg, rzg);
+            T fr[NV];
+#pragma unroll
+            for (int i = 0; i < NV; i++) fr[i] = sF[dist_pull(p, qr, i)];
+            const Moments<T> m = moments_of<T, DEV>(p, fr);
+            const T ri = T(1) / m.rho;
+            const double c = fc[rbo];
+            const Stencil sr = stencil(c, fp[rbo], fm[rbo], fc[rbo + BZ], fc[rbo - BZ], fc[rbo + 1], fc[rbo - 1]);
+            s_mu[w][rro] = fd_mu(p, c, sr.lap);
+            if (ring_y)
+                s_uy[w][rro] = double(m.jy * ri);
+            else
+                s_uz[w][rro] = double(m.jz * ri);
+        }
+        lds_barrier();
+
+        // (e) phi(t+1) at plane X = P-1
+        if (P - 1 >= x0 && valid) {
+            const int v = (P - 1) & 1;
+            const double* __restrict__ fx = s_phi[(P - 1) & 3];
+            const double pc = phB, mc = muB, uc = uxB;
+            double div = 0.0;
+            div += fd_flux(pc, phc, uc, uxP, mc, muP, M) - fd_flux(phA, pc, uxA, uc, muA, mc, M);
+            div += fd_flux(pc, fx[bo + BZ], uyB, s_uy[v][ro + RZ], mc, s_mu[v][ro + RZ], M)
+                 - fd_flux(fx[bo - BZ], pc, s_uy[v][ro - RZ], uyB, s_mu[v][ro - RZ], mc, M);
+            div += fd_flux(pc, fx[bo + 1], uzB, s_uz[v][ro + 1], mc, s_mu[v][ro + 1], M)
+                 - fd_flux(fx[bo - 1], pc, s_uz[v][ro - 1], uzB, s_mu[v][ro - 1], mc, M);
+            __builtin_nontemporal_store(pc - div, &dphi[(P - 1) * plane + yg * p.nz + zg]);
+        }
+        phA = phB; phB = phc;
+        muA = muB; muB = muP;
+        uxA = uxB; uxB = uxP;
+        uyB = uyP; uzB = uzP;
+    }
+    if (partials) block_partials<5, kFdFused>(acc, partials);
+}
+
+template <typename T>
+struct FdFused {
+    using K = decltype(&k_fd_fused<T, std::is_same<T, float>::value, 128>);
+    static K get(int tz)
+    {
+        constexpr bool DEV = std::is_same<T, float>::value;
+        return tz == 64 ? k_fd_fused<T, DEV, 64> : k_fd_fused<T, DEV, 128>;
+    }
+};
 
 // Dense FP64 moments and block partials of [rho, phi, jx, jy, jz]
 // (grid-stride); u = j/rho.
@@ -292,10 +500,25 @@ hipError_t launch_fd_init(const KParams& p, bool fp32, void* state, const double
     return hipGetLastError();
 }
 
-hipError_t launch_fd_step(const KParams& p, bool fp32, const void* src, void* dst, double* work,
-                          double* partials, double* sums_out, hipStream_t s)
+hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
+                          const void* src, void* dst, double* work, double* partials,
+                          double* sums_out, hipStream_t s)
 {
-    const FdTiles ft = fd_tiles(p);
+    int nparts;
+    if (variant == 0) {
+        nparts = tc.ntiles * tc.nseg;
+#define CALL                                                                                  \
+    {                                                                                         \
+        FdLvl<T> a = fd_level<T>(const_cast<void*>(src), p);                                  \
+        FdLvl<T> d = fd_level<T>(dst, p);                                                     \
+        FdFused<T>::get(tc.tz)<<<nparts, kFdFused, 0, s>>>(p, tc, a.F, a.phi, d.F, d.phi,     \
+                                                           sums_out ? partials : nullptr);    \
+    }
+        LB_FD_DISPATCH(fp32, CALL);
+#undef CALL
+    } else {
+        const FdTiles ft = fd_tiles(p);
+        nparts = fd_grid(p);
 #define CALL                                                                                  \
     {                                                                                         \
         FdLvl<T> a = fd_level<T>(const_cast<void*>(src), p);                                  \
@@ -305,12 +528,13 @@ hipError_t launch_fd_step(const KParams& p, bool fp32, const void* src, void* ds
         k_fd_update<<<ft.ntiles * ft.nseg, kBlock, 0, s>>>(p, ft.ntz, ft.ntiles, ft.sx, a.phi,  \
                                                            work, d.phi);                      \
     }
-    LB_FD_DISPATCH(fp32, CALL);
+        LB_FD_DISPATCH(fp32, CALL);
 #undef CALL
+    }
     if (sums_out) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return launch_sums_final(partials, fd_grid(p), 5, sums_out, false, s);
+        return launch_sums_final(partials, nparts, 5, sums_out, false, s);
     }
     return hipGetLastError();
 }

@@ -84,14 +84,17 @@ hipError_t launch_adj_phi0(const KParams& p, bool fp32, const void* adj, double*
                            hipStream_t s);
 
 // Finite-difference order parameter (lb_fd.hip).  A time level is F
-// (19*stride elements, laid out per KParams) then phi (stride FP64 values);
-// `work` holds mu, u_x, u_y, u_z (4 FP64 fields of `stride`).  With sums_out,
-// `partials` needs 5 * fd_step_partial_blocks(p) doubles.
+// (19*stride elements, laid out per KParams) then phi (stride FP64 values).
+// variant 0: single-pass step with the tiling of tc; 1: collision pass, then
+// update pass, with `work` holding mu, u_x, u_y, u_z (4 FP64 fields of
+// `stride`).  With sums_out, `partials` needs 5 * max(tc.ntiles * tc.nseg,
+// fd_step_partial_blocks(p)) doubles.
 int fd_step_partial_blocks(const KParams& p);
 hipError_t launch_fd_init(const KParams& p, bool fp32, void* state, const double* phi0,
                           hipStream_t s);
-hipError_t launch_fd_step(const KParams& p, bool fp32, const void* src, void* dst, double* work,
-                          double* partials, double* sums_out, hipStream_t s);
+hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
+                          const void* src, void* dst, double* work, double* partials,
+                          double* sums_out, hipStream_t s);
 hipError_t launch_fd_moments(const KParams& p, bool fp32, const void* state, double* rho,
                              double* u, double* phi, double* partials, int* nblocks_out,
                              hipStream_t s);

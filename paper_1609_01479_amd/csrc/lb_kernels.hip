@@ -149,17 +149,6 @@ __device__ __forceinline__ double vcopy(double v)
     return r;
 }
 
-// Workgroup barrier for LDS traffic only: every wave's LDS writes have
-// completed (lgkmcnt) before any wave passes.  Unlike __syncthreads() it
-// does not first wait for the wave's outstanding global loads and stores,
-// which the single-pass kernel keeps in flight across the barrier (no
-// global data written in a launch is read back in it).  The clobber keeps
-// the compiler from moving memory accesses across it.
-__device__ __forceinline__ void lds_barrier()
-{
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
 // ---------------------------------------------------------------------------
 // Force coupling (FP64): after the phi pass, a pass for the chemical stress
 // Pi of every site, then the collision with F = -div Pi from Pi at the six
