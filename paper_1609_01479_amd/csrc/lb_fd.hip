@@ -188,8 +188,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 // collision one plane ahead of the flux update.  A workgroup of kFdFused
 // threads owns a TY x TZ tile of (y, z) columns (the single-pass LB
 // kernel's tiling) and marches over its x segment [x0, x1).  For plane P it
-//   (a) loads phi(P+1) on the tile plus two cells around it into a 4-plane
-//       LDS ring;
+//   (a) stores phi(P+1) on the tile plus two cells around it into a 4-plane
+//       LDS ring (loaded into registers one plane earlier, so the loads are
+//       in flight across the previous plane's work) and loads phi(P+2);
 //   (c) collides f at the tile's sites of plane P (stencil from the ring),
 //       keeps mu(P) and u(P) of the thread's own column in registers and
 //       writes mu, u_y, u_z to a 2-plane LDS ring; the first 2(TY + TZ)
@@ -281,12 +282,26 @@ __global__ __launch_bounds__(kFdFused) void k_fd_fused(KParams p, TileCfg tc,
     };
     load_phi(x0 - 2);
     load_phi(x0 - 1);
+    double pre[G::BOXPT];
+    {
+        const int xo = wrap_any(x0, p.nx) * plane;
+#pragma unroll
+        for (int k = 0; k < G::BOXPT; k++) pre[k] = boff[k] >= 0 ? sphi[xo + boff[k]] : 0.0;
+    }
 
     // own column: phi, mu, u_x at X-1 and X, u_y and u_z at X, X = P-1
     double phA = 0.0, phB = 0.0, muA = 0.0, muB = 0.0, uxA = 0.0, uxB = 0.0, uyB = 0.0, uzB = 0.0;
     for (int P = x0 - 1; P <= x1; P++) {
         // (a) phi(P+1) into the ring
-        load_phi(P + 1);
+        {
+            double* __restrict__ dst = s_phi[(P + 1) & 3];
+#pragma unroll
+            for (int k = 0; k < G::BOXPT; k++)
+                if (boff[k] >= 0) dst[t + k * kFdFused] = pre[k];
+            const int xo = wrap_any(P + 2, p.nx) * plane;
+#pragma unroll
+            for (int k = 0; k < G::BOXPT; k++) pre[k] = boff[k] >= 0 ? sphi[xo + boff[k]] : 0.0;
+        }
         lds_barrier();
         const double* __restrict__ fm = s_phi[(P - 1) & 3];
         const double* __restrict__ fc = s_phi[P & 3];
