@@ -257,12 +257,12 @@ def main():
                                      "u_rms": float(np.sqrt((du ** 2).mean()))}
     del runs
 
-    # force coupling (body force -div Pi) on the same 256^3 droplet: the phi,
-    # Pi and collision passes move 880 B per site in FP64 (160 + 56 + 664) and
-    # 516 in FP32 storage (92 + 56 + 368), against the method's 608 and 320
+    # force coupling (body force -div Pi) on the same 256^3 droplet: the phi
+    # and collision passes move 776 B per site in FP64 (160 + 616) and 412 in
+    # FP32 storage (92 + 320), against the method's 608 and 320
     if args.force_steps > 0:
         out["force_coupling"] = {}
-        for prec, moved, minimum in (("fp32_dev", 516, 320), ("fp64", 880, 608)):
+        for prec, moved, minimum in (("fp32_dev", 412, 320), ("fp64", 776, 608)):
             lb = LB(shape, precision=prec, coupling="force", device="cuda:0", **lay, **params)
             lb.init_phi(phi0)
             log(f"{prec} force coupling {shape}: {args.force_steps} steps")
@@ -275,7 +275,7 @@ def main():
                 "frac": round(moved * nsites / t / 1e9 / HBM_PEAK_GBPS, 4),
                 "bytes_per_site": moved,
                 "effective_GBps": round(minimum * nsites / t / 1e9, 1),
-                "kernels": "k_phi + k_pi + k_step_force"}
+                "kernels": "k_phi + k_step_force"}
             del lb
             torch.cuda.empty_cache()
 

@@ -89,8 +89,8 @@ typedef enum {
     LB_COUPLING_STRESS = 0, /* Pi in f^eq's second moment (default)         */
     LB_COUPLING_FORCE = 1   /* body force F = -div Pi (central differences)
                                with the half-force velocity u = (j + F/2)/rho
-                               and Guo's forcing term; no adjoint; runs phi,
-                               Pi and collision passes                      */
+                               and Guo's forcing term; no adjoint; runs a phi
+                               pass and a collision pass                    */
 } lb_coupling;
 
 /* How the order parameter evolves: */
@@ -149,8 +149,7 @@ typedef struct {
     size_t state_bytes;       /* one time level: f, g (2*19*stride elements) and, in
                                  LB_FP32_DEV, phi_c (stride FP64 values); LB_OP_FD:
                                  f (19*stride elements), then phi (stride FP64)        */
-    size_t phi_bytes;         /* FP64 work fields of stride values each: phi, and for
-                                 LB_COUPLING_FORCE also the 6 components of Pi;
+    size_t phi_bytes;         /* FP64 work fields of stride values each: phi;
                                  LB_OP_FD: mu, u_x, u_y, u_z                           */
     size_t scratch_bytes;     /* reduction partials                                     */
     size_t adj_bytes;         /* one adjoint time level (lambda_f, lambda_g, lambda_phi) */

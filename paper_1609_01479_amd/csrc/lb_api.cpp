@@ -140,8 +140,8 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     } else {
         // f and g, plus the FP64 reference order parameter in FP32 mode
         out->state_bytes = 2 * LB_NVEL * stride * e + (p->precision == LB_FP32_DEV ? stride * 8 : 0);
-        // FP64 work fields: phi, and for the force coupling also Pi (6 fields)
-        out->phi_bytes = (p->coupling == LB_COUPLING_FORCE ? 7 : 1) * stride * 8;
+        // FP64 work field: phi
+        out->phi_bytes = stride * 8;
     }
     // block partials of the reductions: 5 FP64 per block of the largest grid
     lbk::KParams k{};

@@ -48,8 +48,9 @@ void set_layout(KParams& k, int layout, int aosoa_len);
 // order).  Order-parameter fields (`phi`) are FP64.
 hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* phi0, hipStream_t s);
 // variant 0: single-pass fused step; 1: phi pass + collision pass.  The force
-// coupling always runs phi, Pi and collision passes, with phi_work holding
-// phi and Pi (7 fields of `stride`).
+// coupling always runs a phi pass and a collision pass (Pi formed on the fly
+// at the face neighbours), with phi in phi_work (FP64 mode; FP32 mode writes
+// the new level's phi_c).
 // If sums_out is non-null, also writes the 5 FP64 conserved sums
 // [rho, phi, jx, jy, jz] of the source level to sums_out, through block
 // partials in `partials` (at least 5 * max(tc.ntiles * tc.nseg,
@@ -59,8 +60,8 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
                        double* sums_out, hipStream_t s);
 // phi(x) of the post-propagation state held in `state`.
 hipError_t launch_phi(const KParams& p, bool fp32, const void* state, double* phi, hipStream_t s);
-// work: FP64 fields the force coupling needs (phi, then the 6 components of
-// Pi, each `stride` long); unused otherwise.
+// work: the FP64 phi field the force coupling needs (`stride` long); unused
+// otherwise.
 hipError_t launch_moments(const KParams& p, bool fp32, const void* state, double* rho, double* u,
                           double* phi, double* work, double* partials, int* nblocks_out,
                           hipStream_t s);

@@ -150,55 +150,54 @@ __device__ __forceinline__ double vcopy(double v)
 }
 
 // ---------------------------------------------------------------------------
-// Force coupling (FP64): after the phi pass, a pass for the chemical stress
-// Pi of every site, then the collision with F = -div Pi from Pi at the six
-// face neighbours (central differences).
+// Force coupling: after the phi pass, the collision with F = -div Pi by
+// central differences of Pi at the six face neighbours.  Each neighbour's Pi
+// is formed from its own 7-point stencil of the phi field (phi within
+// distance 2 of the site; neighbouring threads read the same values, so they
+// come from cache) instead of being stored by a separate pass and read back.
 
-// Pi (xx, xy, xz, yy, yz, zz) of every site, each component `stride` long.
-__global__ __launch_bounds__(kBlock) void k_pi(KParams p, const double* __restrict__ phi,
-                                               double* __restrict__ pi)
+// Pi (xx, xy, xz, yy, yz, zz) at site n from the phi field.
+__device__ __forceinline__ void pi_of(const KParams& p, const Geo& n, const double* __restrict__ phi,
+                                      double t[6])
 {
-    const int s = xcd_block() * kBlock + threadIdx.x;
-    if (s >= p.nsites) return;
-    const Geo q = geo_of(p, s);
-    const Stencil st = stencil(phi[s], phi[site_of(p, q.xp, q.y, q.z)], phi[site_of(p, q.xm, q.y, q.z)],
-                               phi[site_of(p, q.x, q.yp, q.z)], phi[site_of(p, q.x, q.ym, q.z)],
-                               phi[site_of(p, q.x, q.y, q.zp)], phi[site_of(p, q.x, q.y, q.zm)]);
-    double mu, t[6];
+    const Stencil st = stencil(phi[site_of(p, n.x, n.y, n.z)], phi[site_of(p, n.xp, n.y, n.z)],
+                               phi[site_of(p, n.xm, n.y, n.z)], phi[site_of(p, n.x, n.yp, n.z)],
+                               phi[site_of(p, n.x, n.ym, n.z)], phi[site_of(p, n.x, n.y, n.zp)],
+                               phi[site_of(p, n.x, n.y, n.zm)]);
+    double mu;
     chem_stress(p, st, &mu, t);
-#pragma unroll
-    for (int k = 0; k < 6; k++) pi[k * p.stride + s] = t[k];
 }
 
-// F = -div Pi at site q (central differences of Pi at the face neighbours).
-__device__ __forceinline__ void force_at(const KParams& p, const Geo& q, const double* __restrict__ pi,
-                                         double F[3])
+// F_a = -sum_b [Pi_ab(x + e_b) - Pi_ab(x - e_b)] / 2 at site q (the terms of
+// each component summed in the order b = x, y, z).
+__device__ __forceinline__ void force_from_phi(const KParams& p, const Geo& q,
+                                               const double* __restrict__ phi, double F[3])
 {
     // component of Pi_ab in the xx, xy, xz, yy, yz, zz storage
     constexpr int K[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-    const int np[3] = {site_of(p, q.xp, q.y, q.z), site_of(p, q.x, q.yp, q.z), site_of(p, q.x, q.y, q.zp)};
-    const int nm[3] = {site_of(p, q.xm, q.y, q.z), site_of(p, q.x, q.ym, q.z), site_of(p, q.x, q.y, q.zm)};
+    double div[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        double div = 0.0;
+    for (int b = 0; b < 3; b++) {
+        const Geo np = geo_xyz(p, b == 0 ? q.xp : q.x, b == 1 ? q.yp : q.y, b == 2 ? q.zp : q.z);
+        const Geo nm = geo_xyz(p, b == 0 ? q.xm : q.x, b == 1 ? q.ym : q.y, b == 2 ? q.zm : q.z);
+        double tp[6], tm[6];
+        pi_of(p, np, phi, tp);
+        pi_of(p, nm, phi, tm);
 #pragma unroll
-        for (int b = 0; b < 3; b++) {
-            const double* t = pi + size_t(K[a][b]) * p.stride;
-            div += 0.5 * (t[np[b]] - t[nm[b]]);
-        }
-        F[a] = -div;
+        for (int a = 0; a < 3; a++) div[a] += 0.5 * (tp[K[a][b]] - tm[K[a][b]]);
     }
+#pragma unroll
+    for (int a = 0; a < 3; a++) F[a] = -div[a];
 }
 
-// The force-coupling collision and propagation, one site per thread; phi and
-// Pi of the source level (all sites) come from k_phi and k_pi.  In FP32 mode
-// phi is the destination level's phi_c field (as in k_step_2s).
+// The force-coupling collision and propagation, one site per thread; phi of
+// the source level (all sites) comes from k_phi.  In FP32 mode phi is the
+// destination level's phi_c field (as in k_step_2s).
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const T* __restrict__ sF,
                                                        const T* __restrict__ sG,
                                                        const double* __restrict__ sphic,
                                                        const double* __restrict__ phi,
-                                                       const double* __restrict__ pi,
                                                        T* __restrict__ dF, T* __restrict__ dG)
 {
     const int s = xcd_block() * kBlock + threadIdx.x;
@@ -221,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const T* __res
         for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, g[i], dphi);
     }
     double F[3];
-    force_at(p, q, pi, F);
+    force_from_phi(p, q, phi, F);
     collide_force<T, DEV, REF>(p, f, g, c, mu, F);
 #pragma unroll
     for (int i = 0; i < NV; i++) {
@@ -598,13 +597,14 @@ struct Fused<double> {
 
 // Dense FP64 moments of the post-propagation state and block partials of
 // [rho, phi, jx, jy, jz] (grid-stride, FP64 accumulation).
-// With pi (force coupling) the velocity is (j + F/2)/rho, F = -div Pi
-// of this state, and the momentum sums are those of j + F/2.
+// With fphi (force coupling: phi of this state, all sites) the velocity is
+// (j + F/2)/rho, F = -div Pi of this state, and the momentum sums are those
+// of j + F/2.
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restrict__ F,
                                                     const T* __restrict__ G,
                                                     const double* __restrict__ phic,
-                                                    const double* __restrict__ pi,
+                                                    const double* __restrict__ fphi,
                                                     double* __restrict__ rho_out,
                                                     double* __restrict__ u_out,
                                                     double* __restrict__ phi_out,
@@ -628,9 +628,9 @@ __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restri
             jy += CY[i] * fv[i];
             jz += CZ[i] * fv[i];
         }
-        if (pi) {
+        if (fphi) {
             double fo[3];
-            force_at(p, q, pi, fo);
+            force_from_phi(p, q, fphi, fo);
             jx += 0.5 * fo[0];
             jy += 0.5 * fo[1];
             jz += 0.5 * fo[2];
@@ -863,13 +863,12 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
 {
     int nparts = 0;
     if (p.force) {
-        // phi (the new level's phi_c in FP32 mode), Pi, then the forcing collision
+        // phi (the new level's phi_c in FP32 mode), then the forcing collision
 #define CALL                                                                                   \
     {                                                                                          \
         Lvl<T> a = level<T>(const_cast<void*>(src), p, REF);                                   \
         Lvl<T> d = level<T>(dst, p, REF);                                                      \
         double* phin = REF ? d.phic : phi_work;                                                \
-        double* pi = phi_work + p.stride;                                                      \
         if (sums_out) {                                                                        \
             nparts = reduction_grid(p);                                                        \
             k_moments<T, DEV, REF><<<nparts, kBlock, 0, s>>>(p, a.F, a.G, a.phic, nullptr,     \
@@ -877,9 +876,8 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
                                                              partials);                        \
         }                                                                                      \
         k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);                    \
-        k_pi<<<grid_for(p), kBlock, 0, s>>>(p, phin, pi);                                      \
         k_step_force<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phin,    \
-                                                                 pi, d.F, d.G);                \
+                                                                 d.F, d.G);                    \
     }
         LB_DISPATCH(fp32, CALL, CALL);
 #undef CALL
@@ -932,10 +930,10 @@ hipError_t launch_moments(const KParams& p, bool fp32, const void* state, double
 {
     const int nb = reduction_grid(p);
     *nblocks_out = nb;
-    double* pi = nullptr;
+    double* fphi = nullptr;
     if (p.force && (u || partials)) {
-        // F of this state: phi and Pi into the work fields first
-        pi = work + p.stride;
+        // F of this state: phi into the work field first
+        fphi = work;
 #define CALL                                                                                  \
     {                                                                                         \
         Lvl<T> a = level<T>(const_cast<void*>(state), p, REF);                                \
@@ -943,12 +941,11 @@ hipError_t launch_moments(const KParams& p, bool fp32, const void* state, double
     }
         LB_DISPATCH(fp32, CALL, CALL);
 #undef CALL
-        k_pi<<<grid_for(p), kBlock, 0, s>>>(p, work, pi);
     }
 #define CALL                                                                                  \
     {                                                                                         \
         Lvl<T> a = level<T>(const_cast<void*>(state), p, REF);                                \
-        k_moments<T, DEV, REF><<<nb, kBlock, 0, s>>>(p, a.F, a.G, a.phic, pi, rho, u, phi,   \
+        k_moments<T, DEV, REF><<<nb, kBlock, 0, s>>>(p, a.F, a.G, a.phic, fphi, rho, u, phi, \
                                                      partials);                               \
     }
     LB_DISPATCH(fp32, CALL, CALL);

@@ -83,10 +83,11 @@ def test_bad_parameters_rejected(abi, kw, code):
 
 
 def test_force_coupling_sizes_and_no_adjoint(abi):
-    """The force coupling needs 7 FP64 work fields (phi and Pi) and has no
-    adjoint: the reverse-mode calls return LB_ESTATE before any HIP call."""
+    """The force coupling needs one FP64 work field (phi; Pi is formed on the
+    fly) and has no adjoint: the reverse-mode calls return LB_ESTATE before
+    any HIP call."""
     st, s1 = _query(abi, coupling=1)
-    assert st == abi.LB_OK and s1.phi_bytes == 7 * s1.stride_elems * 8
+    assert st == abi.LB_OK and s1.phi_bytes == s1.stride_elems * 8
     L = abi.lib()
     p = _params(abi, coupling=1)
     ctx = ctypes.c_void_p()
