@@ -275,7 +275,7 @@ def main():
                 "frac": round(moved * nsites / t / 1e9 / HBM_PEAK_GBPS, 4),
                 "bytes_per_site": moved,
                 "effective_GBps": round(minimum * nsites / t / 1e9, 1),
-                "kernels": "k_phi + k_step_force"}
+                "kernels": "k_phi + k_force_fused"}
             del lb
             torch.cuda.empty_cache()
 

@@ -407,6 +407,46 @@ __device__ __forceinline__ void collide_force(const KParams& p, T* f, T* g, doub
     }
 }
 
+// Force coupling: F = -div Pi by central differences of Pi at the six face
+// neighbours.  Each neighbour's Pi is formed from its own 7-point stencil of
+// the phi field (phi within distance 2 of the site; neighbouring threads read
+// the same values, so they come from cache) instead of being stored by a
+// separate pass and read back.
+
+// Pi (xx, xy, xz, yy, yz, zz) at site n from the phi field.
+__device__ __forceinline__ void pi_of(const KParams& p, const Geo& n, const double* __restrict__ phi,
+                                      double t[6])
+{
+    const Stencil st = stencil(phi[site_of(p, n.x, n.y, n.z)], phi[site_of(p, n.xp, n.y, n.z)],
+                               phi[site_of(p, n.xm, n.y, n.z)], phi[site_of(p, n.x, n.yp, n.z)],
+                               phi[site_of(p, n.x, n.ym, n.z)], phi[site_of(p, n.x, n.y, n.zp)],
+                               phi[site_of(p, n.x, n.y, n.zm)]);
+    double mu;
+    chem_stress(p, st, &mu, t);
+}
+
+// F_a = -sum_b [Pi_ab(x + e_b) - Pi_ab(x - e_b)] / 2 at site q (the terms of
+// each component summed in the order b = x, y, z).
+__device__ __forceinline__ void force_from_phi(const KParams& p, const Geo& q,
+                                               const double* __restrict__ phi, double F[3])
+{
+    // component of Pi_ab in the xx, xy, xz, yy, yz, zz storage
+    constexpr int K[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    double div[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        const Geo np = geo_xyz(p, b == 0 ? q.xp : q.x, b == 1 ? q.yp : q.y, b == 2 ? q.zp : q.z);
+        const Geo nm = geo_xyz(p, b == 0 ? q.xm : q.x, b == 1 ? q.ym : q.y, b == 2 ? q.zm : q.z);
+        double tp[6], tm[6];
+        pi_of(p, np, phi, tp);
+        pi_of(p, nm, phi, tm);
+#pragma unroll
+        for (int a = 0; a < 3; a++) div[a] += 0.5 * (tp[K[a][b]] - tm[K[a][b]]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; a++) F[a] = -div[a];
+}
+
 // Workgroup barrier for LDS traffic only: every wave's LDS writes have
 // completed (lgkmcnt) before any wave passes.  Unlike __syncthreads() it
 // does not first wait for the wave's outstanding global loads and stores,

@@ -1,0 +1,296 @@
+// Force coupling (LB_COUPLING_FORCE), the collision pass after k_phi: F =
+// -div Pi by central differences of the chemical stress at the six face
+// neighbours (the paper's Ludwig model applies the stress's divergence as a
+// body force, Sec. 2.1.1), with the half-force velocity and Guo's forcing
+// term in collide_force().  Two forms with bit-identical results:
+//
+//   k_force_fused (LB_KERNEL_FUSED): the single-pass LB kernel's tiling --
+//     a TY x TZ tile of (y, z) columns marching along x -- with phi of the
+//     tile plus two cells around it in an LDS ring, Pi of plane P formed
+//     once per site for the tile and its face ring and kept in LDS (the
+//     components the y and z neighbours need) and in registers (the own
+//     column's x row, for x +- 1), and the collision of plane P-1;
+//   k_step_force (LB_KERNEL_TWO_PASS): one site per thread, Pi formed at
+//     each face neighbour from the phi field (force_from_phi).
+//
+// No floating-point contraction in this translation unit (including the
+// shared device functions it inlines): the compiler fuses multiply-adds
+// differently in different kernels, and the two forms must round alike.
+#pragma clang fp contract(off)
+
+#include "lb_device.h"
+
+namespace lbk {
+
+using namespace dev;
+
+namespace {
+
+// The force-coupling collision and propagation, one site per thread; phi of
+// the source level (all sites) comes from k_phi.  In FP32 mode phi is the
+// destination level's phi_c field (as in k_step_2s).
+template <typename T, bool DEV, bool REF>
+__global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const T* __restrict__ sF,
+                                                       const T* __restrict__ sG,
+                                                       const double* __restrict__ sphic,
+                                                       const double* __restrict__ phi,
+                                                       T* __restrict__ dF, T* __restrict__ dG)
+{
+    const int s = xcd_block() * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    const Geo q = geo_of(p, s);
+    T f[NV], g[NV];
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        f[i] = sF[dist_pull(p, q, i)];
+        g[i] = sG[dist_pull(p, q, i)];
+    }
+    const double c = phi[s];
+    const double lap = (phi[site_of(p, q.xp, q.y, q.z)] + phi[site_of(p, q.xm, q.y, q.z)] - 2.0 * c)
+                     + (phi[site_of(p, q.x, q.yp, q.z)] + phi[site_of(p, q.x, q.ym, q.z)] - 2.0 * c)
+                     + (phi[site_of(p, q.x, q.y, q.zp)] + phi[site_of(p, q.x, q.y, q.zm)] - 2.0 * c);
+    const double mu = p.A * c + p.B * c * c * c - p.kappa * lap;
+    if (REF) {
+        const double dphi = c - sphic[s];
+#pragma unroll
+        for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, g[i], dphi);
+    }
+    double F[3];
+    force_from_phi(p, q, phi, F);
+    collide_force<T, DEV, REF>(p, f, g, c, mu, F);
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        dF[dist_own(p, q, i)] = f[i];
+        dG[dist_own(p, q, i)] = REF ? to_dest_ref(i, g[i], c, phi[push_site(p, q, i)]) : g[i];
+    }
+}
+
+constexpr int kForceFused = 512;
+constexpr int kPhiSlots = 8;  // phi planes P-2 .. P+1 are read while P+2 is written
+
+template <int TZ>
+struct ForceTile {
+    static constexpr int TY = kForceFused / TZ;
+    static constexpr int BY = TY + 4, BZ = TZ + 4;  // phi box: two cells around the tile
+    static constexpr int RY = TY + 2, RZ = TZ + 2;  // tile and its face ring
+    static constexpr int NBOX = BY * BZ;
+    static constexpr int NRING = 2 * (TY + TZ);
+    static constexpr int BOXPT = (NBOX + kForceFused - 1) / kForceFused;
+};
+
+__device__ __forceinline__ int wrap_any(int v, int n)
+{
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// For plane P: (a) phi(P+1) into the LDS ring (loaded one plane earlier),
+// the loads of phi(P+2), and the pulls of the own site of plane P-1; (c) Pi
+// of plane P at the own site and, for the first 2 (TY + TZ) threads, at a
+// face-ring cell; (e) the forcing collision of plane P-1, whose F uses Pi of
+// planes P-2 and P (own column, registers) and of plane P-1 at the four
+// in-plane neighbours (LDS, written one plane earlier).  Planes x0-1 and x1
+// only supply the own column's Pi.  Tile cells beyond a ragged lattice edge
+// stand for the periodic images there: they form Pi but store nothing.
+template <typename T, bool DEV, bool REF, int TZ>
+__global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg tc,
+                                                             const T* __restrict__ sF,
+                                                             const T* __restrict__ sG,
+                                                             const double* __restrict__ sphic,
+                                                             const double* __restrict__ phi,
+                                                             T* __restrict__ dF, T* __restrict__ dG)
+{
+    using G = ForceTile<TZ>;
+    constexpr int TY = G::TY, BZ = G::BZ, RZ = G::RZ, NR = G::RY * G::RZ;
+    __shared__ double s_phi[kPhiSlots][G::NBOX];
+    __shared__ double s_piy[2][3][NR];  // Pi_xy, Pi_yy, Pi_yz: read by the y neighbours
+    __shared__ double s_piz[2][3][NR];  // Pi_xz, Pi_yz, Pi_zz: read by the z neighbours
+
+    const int t = threadIdx.x;
+    const int b = xcd_block();
+    const int seg = b / tc.ntiles, tile = b - seg * tc.ntiles;
+    const int y0 = (tile / tc.ntz) * TY, z0 = (tile % tc.ntz) * TZ;
+    const int x0 = seg * tc.sx, x1 = min(p.nx, x0 + tc.sx);
+    const int plane = p.ny * p.nz;
+
+    const int ly = t / TZ, lz = t % TZ;
+    const int yg = wrap_any(y0 + ly, p.ny), zg = wrap_any(z0 + lz, p.nz);
+    const bool valid = y0 + ly < p.ny && z0 + lz < p.nz;
+    const int bo = (ly + 2) * BZ + (lz + 2);
+    const int ro = (ly + 1) * RZ + (lz + 1);
+    int boff[G::BOXPT];
+#pragma unroll
+    for (int k = 0; k < G::BOXPT; k++) {
+        const int c = t + k * kForceFused;
+        boff[k] = c < G::NBOX
+                      ? wrap_any(y0 + c / BZ - 2, p.ny) * p.nz + wrap_any(z0 + c % BZ - 2, p.nz)
+                      : -1;
+    }
+    const bool ring = t < G::NRING;
+    int rly, rlz;
+    if (t < TZ) { rly = -1; rlz = t; }
+    else if (t < 2 * TZ) { rly = TY; rlz = t - TZ; }
+    else if (t < 2 * TZ + TY) { rly = t - 2 * TZ; rlz = -1; }
+    else { rly = t - 2 * TZ - TY; rlz = TZ; }
+    const bool ring_y = rly < 0 || rly >= TY;  // a row of the ring, else a column
+    const int rbo = (rly + 2) * BZ + (rlz + 2);
+    const int rro = (rly + 1) * RZ + (rlz + 1);
+
+    auto load_box = [&](int xp, double (&v)[G::BOXPT]) {
+        const int xo = wrap_any(xp, p.nx) * plane;
+#pragma unroll
+        for (int k = 0; k < G::BOXPT; k++) v[k] = boff[k] >= 0 ? phi[xo + boff[k]] : 0.0;
+    };
+    auto store_box = [&](int xp, const double (&v)[G::BOXPT]) {
+        double* __restrict__ dst = s_phi[xp & (kPhiSlots - 1)];
+#pragma unroll
+        for (int k = 0; k < G::BOXPT; k++)
+            if (boff[k] >= 0) dst[t + k * kForceFused] = v[k];
+    };
+    double pre[G::BOXPT];
+    load_box(x0 - 2, pre);
+    store_box(x0 - 2, pre);
+    load_box(x0 - 1, pre);
+    store_box(x0 - 1, pre);
+    load_box(x0, pre);
+
+    // own column's Pi x row (xx, xy, xz) at planes X-1 and X, X = P-1
+    double pxA[3] = {0.0, 0.0, 0.0}, pxB[3] = {0.0, 0.0, 0.0};
+    for (int P = x0 - 1; P <= x1; P++) {
+        const int X = P - 1;
+        const bool collide_x = X >= x0 && valid;
+        // (a)
+        store_box(P + 1, pre);
+        load_box(P + 2, pre);
+        T f[NV], g[NV];
+        double pc_src = 0.0;
+        const Geo q = geo_xyz(p, wrap_any(X, p.nx), yg, zg);
+        if (collide_x) {
+#pragma unroll
+            for (int i = 0; i < NV; i++) {
+                f[i] = sF[dist_pull(p, q, i)];
+                g[i] = sG[dist_pull(p, q, i)];
+            }
+            if (REF) pc_src = sphic[X * plane + yg * p.nz + zg];
+        }
+        lds_barrier();
+        const double* __restrict__ fm = s_phi[(P - 1) & (kPhiSlots - 1)];
+        const double* __restrict__ fc = s_phi[P & (kPhiSlots - 1)];
+        const double* __restrict__ fp = s_phi[(P + 1) & (kPhiSlots - 1)];
+        const int w = P & 1;
+
+        // (c) Pi of plane P
+        double pxP[3];
+        {
+            const Stencil st = stencil(fc[bo], fp[bo], fm[bo], fc[bo + BZ], fc[bo - BZ], fc[bo + 1],
+                                       fc[bo - 1]);
+            double mu, tt[6];
+            chem_stress(p, st, &mu, tt);
+            pxP[0] = tt[0];
+            pxP[1] = tt[1];
+            pxP[2] = tt[2];
+            s_piy[w][0][ro] = tt[1];
+            s_piy[w][1][ro] = tt[3];
+            s_piy[w][2][ro] = tt[4];
+            s_piz[w][0][ro] = tt[2];
+            s_piz[w][1][ro] = tt[4];
+            s_piz[w][2][ro] = tt[5];
+        }
+        if (ring && P >= x0 && P < x1) {
+            const Stencil st = stencil(fc[rbo], fp[rbo], fm[rbo], fc[rbo + BZ], fc[rbo - BZ],
+                                       fc[rbo + 1], fc[rbo - 1]);
+            double mu, tt[6];
+            chem_stress(p, st, &mu, tt);
+            if (ring_y) {
+                s_piy[w][0][rro] = tt[1];
+                s_piy[w][1][rro] = tt[3];
+                s_piy[w][2][rro] = tt[4];
+            } else {
+                s_piz[w][0][rro] = tt[2];
+                s_piz[w][1][rro] = tt[4];
+                s_piz[w][2][rro] = tt[5];
+            }
+        }
+
+        // (e) the collision of plane X = P-1
+        if (collide_x) {
+            const int v = X & 1;
+            const double* __restrict__ xm = s_phi[(X - 1) & (kPhiSlots - 1)];
+            const double* __restrict__ xc = s_phi[X & (kPhiSlots - 1)];
+            const double* __restrict__ xp = s_phi[(X + 1) & (kPhiSlots - 1)];
+            const double c = xc[bo];
+            const double lap = (xp[bo] + xm[bo] - 2.0 * c) + (xc[bo + BZ] + xc[bo - BZ] - 2.0 * c)
+                             + (xc[bo + 1] + xc[bo - 1] - 2.0 * c);
+            const double mu = p.A * c + p.B * c * c * c - p.kappa * lap;
+            if (REF) {
+                const double dphi = c - pc_src;
+#pragma unroll
+                for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, g[i], dphi);
+            }
+            // F_a = -sum_b [Pi_ab(x + e_b) - Pi_ab(x - e_b)] / 2, b = x, y, z in order
+            double div[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int a = 0; a < 3; a++) div[a] += 0.5 * (pxP[a] - pxA[a]);
+#pragma unroll
+            for (int a = 0; a < 3; a++) div[a] += 0.5 * (s_piy[v][a][ro + RZ] - s_piy[v][a][ro - RZ]);
+#pragma unroll
+            for (int a = 0; a < 3; a++) div[a] += 0.5 * (s_piz[v][a][ro + 1] - s_piz[v][a][ro - 1]);
+            double F[3];
+#pragma unroll
+            for (int a = 0; a < 3; a++) F[a] = -div[a];
+            collide_force<T, DEV, REF>(p, f, g, c, mu, F);
+#pragma unroll
+            for (int i = 0; i < NV; i++) {
+                __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
+                T gv = g[i];
+                if (REF) {
+                    const double* __restrict__ pl = CX[i] > 0 ? xp : (CX[i] < 0 ? xm : xc);
+                    gv = to_dest_ref(i, g[i], c, pl[bo + CY[i] * BZ + CZ[i]]);
+                }
+                __builtin_nontemporal_store(gv, &dG[dist_own(p, q, i)]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            pxA[a] = pxB[a];
+            pxB[a] = pxP[a];
+        }
+    }
+}
+
+template <typename T, bool DEV, bool REF>
+struct ForceFused {
+    using K = decltype(&k_force_fused<T, DEV, REF, 128>);
+    static K get(int tz) { return tz == 64 ? k_force_fused<T, DEV, REF, 64> : k_force_fused<T, DEV, REF, 128>; }
+};
+
+int force_grid(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
+
+}  // namespace
+
+hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, int variant,
+                                const void* src, void* dst, const double* phi, hipStream_t s)
+{
+    if (fp32) {
+        Lvl<float> a = level<float>(const_cast<void*>(src), p, true);
+        Lvl<float> d = level<float>(dst, p, true);
+        if (variant == 0)
+            ForceFused<float, true, true>::get(tc.tz)<<<tc.ntiles * tc.nseg, kForceFused, 0, s>>>(
+                p, tc, a.F, a.G, a.phic, phi, d.F, d.G);
+        else
+            k_step_force<float, true, true><<<force_grid(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phi,
+                                                                             d.F, d.G);
+    } else {
+        Lvl<double> a = level<double>(const_cast<void*>(src), p, false);
+        Lvl<double> d = level<double>(dst, p, false);
+        if (variant == 0)
+            ForceFused<double, false, false>::get(tc.tz)<<<tc.ntiles * tc.nseg, kForceFused, 0, s>>>(
+                p, tc, a.F, a.G, a.phic, phi, d.F, d.G);
+        else
+            k_step_force<double, false, false><<<force_grid(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic,
+                                                                                phi, d.F, d.G);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lbk

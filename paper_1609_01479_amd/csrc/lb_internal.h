@@ -35,6 +35,26 @@ struct TileCfg {
     int sx, nseg;          // planes per x segment, number of segments
 };
 
+// A time level's regions (LB order parameter): F and G of 19*stride
+// elements of T each and, in FP32 mode, phi_c (stride FP64 values).
+template <typename T>
+struct Lvl {
+    T* F;
+    T* G;
+    double* phic;  // FP32 mode only
+};
+
+template <typename T>
+inline Lvl<T> level(void* state, const KParams& p, bool ref)
+{
+    T* base = static_cast<T*>(state);
+    Lvl<T> l;
+    l.F = base;
+    l.G = base + size_t(NV) * p.stride;
+    l.phic = ref ? reinterpret_cast<double*>(base + size_t(2 * NV) * p.stride) : nullptr;
+    return l;
+}
+
 // segment_x <= 0 picks the segment length automatically.
 TileCfg tile_config(const KParams& p, int segment_x, bool fp32);
 
@@ -58,6 +78,12 @@ hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* p
 hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
                        const void* src, void* dst, double* phi_work, double* partials,
                        double* sums_out, hipStream_t s);
+// Force coupling, after the phi pass: the forcing collision from src to dst
+// with phi (all sites, FP64) of src in `phi`.  variant 0: single pass over
+// (y, z) tiles marching along x (tiling tc), Pi in LDS; 1: one site per
+// thread, Pi formed at each face neighbour.  Bit-identical results.
+hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, int variant,
+                                const void* src, void* dst, const double* phi, hipStream_t s);
 // phi(x) of the post-propagation state held in `state`.
 hipError_t launch_phi(const KParams& p, bool fp32, const void* state, double* phi, hipStream_t s);
 // work: the FP64 phi field the force coupling needs (`stride` long); unused

@@ -41,24 +41,6 @@ constexpr int kFused = 512;
 static_assert(2 * 128 + 2 * (kFused / 128) + 4 <= kFused, "halo ring larger than the workgroup");
 static_assert(2 * 64 + 2 * (kFused / 64) + 4 <= kFused, "halo ring larger than the workgroup");
 
-template <typename T>
-struct Lvl {
-    T* F;
-    T* G;
-    double* phic;  // FP32 mode only
-};
-
-template <typename T>
-Lvl<T> level(void* state, const KParams& p, bool ref)
-{
-    T* base = static_cast<T*>(state);
-    Lvl<T> l;
-    l.F = base;
-    l.G = base + size_t(NV) * p.stride;
-    l.phic = ref ? reinterpret_cast<double*>(base + size_t(2 * NV) * p.stride) : nullptr;
-    return l;
-}
-
 // ---------------------------------------------------------------------------
 
 // Post-propagation state rho = rho0, u = 0, g_0 = phi0, g_{i>0} = 0.  In FP32
@@ -147,86 +129,6 @@ __device__ __forceinline__ double vcopy(double v)
     double r;
     asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "v"(v) : "memory");
     return r;
-}
-
-// ---------------------------------------------------------------------------
-// Force coupling: after the phi pass, the collision with F = -div Pi by
-// central differences of Pi at the six face neighbours.  Each neighbour's Pi
-// is formed from its own 7-point stencil of the phi field (phi within
-// distance 2 of the site; neighbouring threads read the same values, so they
-// come from cache) instead of being stored by a separate pass and read back.
-
-// Pi (xx, xy, xz, yy, yz, zz) at site n from the phi field.
-__device__ __forceinline__ void pi_of(const KParams& p, const Geo& n, const double* __restrict__ phi,
-                                      double t[6])
-{
-    const Stencil st = stencil(phi[site_of(p, n.x, n.y, n.z)], phi[site_of(p, n.xp, n.y, n.z)],
-                               phi[site_of(p, n.xm, n.y, n.z)], phi[site_of(p, n.x, n.yp, n.z)],
-                               phi[site_of(p, n.x, n.ym, n.z)], phi[site_of(p, n.x, n.y, n.zp)],
-                               phi[site_of(p, n.x, n.y, n.zm)]);
-    double mu;
-    chem_stress(p, st, &mu, t);
-}
-
-// F_a = -sum_b [Pi_ab(x + e_b) - Pi_ab(x - e_b)] / 2 at site q (the terms of
-// each component summed in the order b = x, y, z).
-__device__ __forceinline__ void force_from_phi(const KParams& p, const Geo& q,
-                                               const double* __restrict__ phi, double F[3])
-{
-    // component of Pi_ab in the xx, xy, xz, yy, yz, zz storage
-    constexpr int K[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-    double div[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int b = 0; b < 3; b++) {
-        const Geo np = geo_xyz(p, b == 0 ? q.xp : q.x, b == 1 ? q.yp : q.y, b == 2 ? q.zp : q.z);
-        const Geo nm = geo_xyz(p, b == 0 ? q.xm : q.x, b == 1 ? q.ym : q.y, b == 2 ? q.zm : q.z);
-        double tp[6], tm[6];
-        pi_of(p, np, phi, tp);
-        pi_of(p, nm, phi, tm);
-#pragma unroll
-        for (int a = 0; a < 3; a++) div[a] += 0.5 * (tp[K[a][b]] - tm[K[a][b]]);
-    }
-#pragma unroll
-    for (int a = 0; a < 3; a++) F[a] = -div[a];
-}
-
-// The force-coupling collision and propagation, one site per thread; phi of
-// the source level (all sites) comes from k_phi.  In FP32 mode phi is the
-// destination level's phi_c field (as in k_step_2s).
-template <typename T, bool DEV, bool REF>
-__global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const T* __restrict__ sF,
-                                                       const T* __restrict__ sG,
-                                                       const double* __restrict__ sphic,
-                                                       const double* __restrict__ phi,
-                                                       T* __restrict__ dF, T* __restrict__ dG)
-{
-    const int s = xcd_block() * kBlock + threadIdx.x;
-    if (s >= p.nsites) return;
-    const Geo q = geo_of(p, s);
-    T f[NV], g[NV];
-#pragma unroll
-    for (int i = 0; i < NV; i++) {
-        f[i] = sF[dist_pull(p, q, i)];
-        g[i] = sG[dist_pull(p, q, i)];
-    }
-    const double c = phi[s];
-    const double lap = (phi[site_of(p, q.xp, q.y, q.z)] + phi[site_of(p, q.xm, q.y, q.z)] - 2.0 * c)
-                     + (phi[site_of(p, q.x, q.yp, q.z)] + phi[site_of(p, q.x, q.ym, q.z)] - 2.0 * c)
-                     + (phi[site_of(p, q.x, q.y, q.zp)] + phi[site_of(p, q.x, q.y, q.zm)] - 2.0 * c);
-    const double mu = p.A * c + p.B * c * c * c - p.kappa * lap;
-    if (REF) {
-        const double dphi = c - sphic[s];
-#pragma unroll
-        for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, g[i], dphi);
-    }
-    double F[3];
-    force_from_phi(p, q, phi, F);
-    collide_force<T, DEV, REF>(p, f, g, c, mu, F);
-#pragma unroll
-    for (int i = 0; i < NV; i++) {
-        dF[dist_own(p, q, i)] = f[i];
-        dG[dist_own(p, q, i)] = REF ? to_dest_ref(i, g[i], c, phi[push_site(p, q, i)]) : g[i];
-    }
 }
 
 // Wrap a coordinate v in [-2n, 3n) onto [0, n).
@@ -876,11 +778,14 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
                                                              partials);                        \
         }                                                                                      \
         k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);                    \
-        k_step_force<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phin,    \
-                                                                 d.F, d.G);                    \
     }
         LB_DISPATCH(fp32, CALL, CALL);
 #undef CALL
+        {
+            hipError_t e = launch_force_collide(p, tc, fp32, variant, src, dst,
+                                                fp32 ? level<float>(dst, p, true).phic : phi_work, s);
+            if (e != hipSuccess) return e;
+        }
         if (sums_out) k_sums_final<<<1, kBlock, 0, s>>>(partials, nparts, 5, sums_out, 0);
         return hipGetLastError();
     }

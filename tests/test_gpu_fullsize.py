@@ -42,9 +42,11 @@ def _window(t, site, shape):
     return w.cpu().numpy()
 
 
-def _sampled_parity(shape, precision, phi0, steps_before, kw, tol, nsample=24):
-    print(f"[fullsize] {shape} {precision} after {steps_before} steps, {nsample} sites", flush=True)
-    lb = make_lb(shape, precision=precision, **kw)
+def _sampled_parity(shape, precision, phi0, steps_before, kw, tol, nsample=24, lb_kw=None,
+                    oracle_kw=None):
+    print(f"[fullsize] {shape} {precision} after {steps_before} steps, {nsample} sites "
+          f"{lb_kw or ''}", flush=True)
+    lb = make_lb(shape, precision=precision, **kw, **(lb_kw or {}))
     lb.init_phi(phi0)
     lb.step(steps_before)
     f, g = lb.export_dist()
@@ -57,7 +59,7 @@ def _sampled_parity(shape, precision, phi0, steps_before, kw, tol, nsample=24):
     got = [(f1[:, x, y, z].cpu().numpy(), g1[:, x, y, z].cpu().numpy()) for x, y, z in sites]
     del f1, g1
     torch.cuda.empty_cache()
-    pw = oracle_params((2 * R + 1,) * 3, **kw)
+    pw = oracle_params((2 * R + 1,) * 3, **kw, **(oracle_kw or {}))
     fscale = gscale = 0.0
     ferr = gerr = 0.0
     for (fw, gw), (fg, gg) in zip(wins, got):
@@ -111,6 +113,15 @@ def test_sampled_parity_maximum_size(precision, tol):
     xi = lbinputs.interface_width(pr["A"], pr["kappa"])
     phi0 = lbinputs.droplet_phi0(shape, 100.0, xi, noise=1e-3, seed=lbinputs.SEED_DROPLET)
     _sampled_parity(shape, precision, phi0, 1, dict(tau_f=0.8, tau_g=1.3), tol, nsample=10)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_dev", 2e-6)])
+def test_sampled_parity_force_coupling_droplet_256(precision, tol):
+    """The force coupling at the benchmark lattice: one step at x depends on
+    phi within distance 2 (the force's Pi at the face neighbours), i.e. on g
+    within distance 3, which the 7^3 window still holds."""
+    _sampled_parity((256, 256, 256), precision, _droplet(256), 5, dict(tau_f=0.8, tau_g=1.3), tol,
+                    lb_kw=dict(coupling="force"), oracle_kw=dict(coupling=1))
 
 
 def test_sampled_parity_spinodal_128_fp64():
