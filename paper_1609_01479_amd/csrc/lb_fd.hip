@@ -190,7 +190,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 // kernel's tiling) and marches over its x segment [x0, x1).  For plane P it
 //   (a) stores phi(P+1) on the tile plus two cells around it into a 4-plane
 //       LDS ring (loaded into registers one plane earlier, so the loads are
-//       in flight across the previous plane's work) and loads phi(P+2);
+//       in flight across the previous plane's work), loads phi(P+2) and
+//       issues the pulls of the own site of plane P, which then overlap the
+//       barrier;
 //   (c) collides f at the tile's sites of plane P (stencil from the ring),
 //       keeps mu(P) and u(P) of the thread's own column in registers and
 //       writes mu, u_y, u_z to a 2-plane LDS ring; the first 2(TY + TZ)
@@ -302,6 +304,10 @@ __global__ __launch_bounds__(kFdFused) void k_fd_fused(KParams p, TileCfg tc,
 #pragma unroll
             for (int k = 0; k < G::BOXPT; k++) pre[k] = boff[k] >= 0 ? sphi[xo + boff[k]] : 0.0;
         }
+        const Geo q = geo_xyz(p, wrap_any(P, p.nx), yg, zg);
+        T f[NV];
+#pragma unroll
+        for (int i = 0; i < NV; i++) f[i] = sF[dist_pull(p, q, i)];
         lds_barrier();
         const double* __restrict__ fm = s_phi[(P - 1) & 3];
         const double* __restrict__ fc = s_phi[P & 3];
@@ -313,10 +319,6 @@ __global__ __launch_bounds__(kFdFused) void k_fd_fused(KParams p, TileCfg tc,
         // (c) collision of the own cell of plane P
         const double phc = fc[bo];
         const Stencil st = stencil(phc, fp[bo], fm[bo], fc[bo + BZ], fc[bo - BZ], fc[bo + 1], fc[bo - 1]);
-        const Geo q = geo_xyz(p, xg, yg, zg);
-        T f[NV];
-#pragma unroll
-        for (int i = 0; i < NV; i++) f[i] = sF[dist_pull(p, q, i)];
         if (partials && interior && valid) {
             double bs = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
