@@ -143,6 +143,8 @@ def main():
                     help="steps of the 256^3 force-coupling lines (0: skip)")
     ap.add_argument("--fd-steps", type=int, default=200,
                     help="steps of the 256^3 finite-difference order-parameter lines (0: skip)")
+    ap.add_argument("--shard-steps", type=int, default=500,
+                    help="steps of the one-GPU-share lines (32 x 256 x 256, 0: skip)")
     ap.add_argument("--spinodal-steps", type=int, default=1000,
                     help="steps of the extra 128^3 FP64 spinodal throughput line (0: skip)")
     args = ap.parse_args()
@@ -305,6 +307,28 @@ def main():
         out["fd_order_parameter"]["phi_fp32_vs_fp64_max"] = float(
             np.abs(fd_phi["fp32_dev"] - fd_phi["fp64"]).max())
         del fd_phi
+
+    # one GPU's share of the 256^3 droplet split into 8 x-slabs: the same
+    # single-pass kernel on a 32 x 256 x 256 lattice (periodic here; a shard
+    # would read its two boundary planes' halos from its neighbours)
+    if args.shard_steps > 0 and n == 256:
+        out["shard_32x256x256"] = {}
+        sh = (32, 256, 256)
+        nsh = 32 * 256 * 256
+        phish = np.ascontiguousarray(phi0[n // 2 - 16:n // 2 + 16])  # the slab through the centre
+        for prec, moved in (("fp32_dev", 320), ("fp64", 608)):
+            lb = LB(sh, precision=prec, device="cuda:0", **lay, **params)
+            lb.init_phi(phish)
+            log(f"{prec} shard {sh}: {args.shard_steps} steps")
+            ms = time_steps(lb, args.shard_steps, args.warmup)
+            t = ms / args.shard_steps * 1e-3
+            out["shard_32x256x256"][prec] = {
+                "value": round(nsh / t / 1e6, 1), "unit": "MLUPS", "steps": args.shard_steps,
+                "ms_per_step": round(ms / args.shard_steps, 4),
+                "achieved_GBps": round(moved * nsh / t / 1e9, 1),
+                "frac": round(moved * nsh / t / 1e9 / HBM_PEAK_GBPS, 4)}
+            del lb
+            torch.cuda.empty_cache()
 
     # FP64 on the 128^3 spinodal-decomposition lattice (phi0 ~ U(-0.05, 0.05))
     if not args.no_fp64 and args.spinodal_steps > 0:

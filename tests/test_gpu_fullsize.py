@@ -124,6 +124,18 @@ def test_sampled_parity_force_coupling_droplet_256(precision, tol):
                     lb_kw=dict(coupling="force"), oracle_kw=dict(coupling=1))
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_dev", 2e-6)])
+def test_sampled_parity_force_coupling_maximum_size(precision, tol):
+    """The force coupling at 479^3, the largest accepted cube, ragged in every
+    tile dimension of the marching collision pass."""
+    shape = (479, 479, 479)
+    pr = lbinputs.SPINODAL_PARAMS
+    xi = lbinputs.interface_width(pr["A"], pr["kappa"])
+    phi0 = lbinputs.droplet_phi0(shape, 100.0, xi, noise=1e-3, seed=lbinputs.SEED_DROPLET)
+    _sampled_parity(shape, precision, phi0, 1, dict(tau_f=0.8, tau_g=1.3), tol, nsample=8,
+                    lb_kw=dict(coupling="force"), oracle_kw=dict(coupling=1))
+
+
 def test_sampled_parity_spinodal_128_fp64():
     shape = (128, 128, 128)
     _sampled_parity(shape, "fp64", lbinputs.spinodal_phi0(shape), 20, {}, 1e-12)
