@@ -487,17 +487,19 @@ int fd_reduction_grid(const KParams& p)
 }
 
 // FP64 mode <double, false>, FP32 mode <float, true>.
-#define LB_FD_DISPATCH(fp32, CALL)     \
-    do {                               \
-        if (fp32) {                    \
-            using T = float;           \
-            constexpr bool DEV = true; \
-            CALL;                      \
-        } else {                       \
-            using T = double;          \
+#define LB_FD_DISPATCH(fp32, CALL)      \
+    do {                                \
+        if (fp32) {                     \
+            using T = float;            \
+            constexpr bool DEV = true;  \
+            (void)DEV;                  \
+            CALL;                       \
+        } else {                        \
+            using T = double;           \
             constexpr bool DEV = false; \
-            CALL;                      \
-        }                              \
+            (void)DEV;                  \
+            CALL;                       \
+        }                               \
     } while (0)
 
 }  // namespace
