@@ -273,10 +273,8 @@ def collide_force(p: Params, f, g, phi, mu, F):
 # The state is (f, phi): f (19, nx, ny, nz) post-stream as above, phi a field.
 
 def _fd_check(rc: int, what: str):
-    if rc == 1:
+    if rc:
         raise MemoryError(f"{what}: allocation failed")
-    if rc == 2:
-        raise ValueError(f"{what}: the finite-difference scheme has the stress coupling only")
 
 
 def fd_init(p: Params, phi0):
@@ -289,7 +287,8 @@ def fd_init(p: Params, phi0):
 
 
 def fd_moments(p: Params, f, phi):
-    """(rho, u (3, nx, ny, nz), phi) of a finite-difference state; u = j/rho."""
+    """(rho, u (3, nx, ny, nz), phi) of a finite-difference state; u = j/rho,
+    or (j + F/2)/rho with the force coupling."""
     f, phi = _f64(f), _f64(phi)
     rho = np.empty(p.shape)
     u = np.empty((3,) + p.shape)

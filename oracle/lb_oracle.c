@@ -51,8 +51,12 @@
  *   M              = Gamma (tau_g - 1/2)
  *
  * (the mobility the g scheme above gives, so both schemes solve the same
- * Cahn-Hilliard equation).  f collides with Pi in f^eq as in the first form,
- * mu and Pi from phi(t), u from f(t) before collision.
+ * Cahn-Hilliard equation).  mu and Pi from phi(t).  With coupling = 0, f
+ * collides with Pi in f^eq as in the first form and u = j/rho of f(t)
+ * before collision; with coupling = 1 (the paper's arrangement: the stress
+ * divergence acts on the fluid, the order parameter follows finite
+ * differences), f collides with the force F = -div Pi as above and the
+ * fluxes use the same velocity u = (j + F/2)/rho.
  *
  * The paper does not print these formulas (it names the kernels only); they
  * are the standard free-energy binary-fluid LB model.  The readings taken
@@ -279,7 +283,8 @@ void oracle_equilibrium_force_site(const oracle_params *p, double rho, const dou
     }
 }
 
-/* BGK collision with the forcing term, every site. */
+/* BGK collision with the forcing term, every site (g and gstar may be
+ * NULL: f only). */
 void oracle_collide_force(const oracle_params *p, const double *f, const double *g,
                           const double *phi, const double *mu, const double *F,
                           double *fstar, double *gstar)
@@ -303,9 +308,9 @@ void oracle_collide_force(const oracle_params *p, const double *f, const double 
             double cu = CV[i][0] * u[0] + CV[i][1] * u[1] + CV[i][2] * u[2];
             double src = 0.0;
             for (int a = 0; a < 3; a++) src += (3.0 * (CV[i][a] - u[a]) + 9.0 * cu * CV[i][a]) * fv[a];
-            double fi = f[i * n + s], gi = g[i * n + s];
+            double fi = f[i * n + s];
             fstar[i * n + s] = fi - (fi - feq[i]) / p->tau_f + pref * weight(i) * src;
-            gstar[i * n + s] = gi - (gi - geq[i]) / p->tau_g;
+            if (g) gstar[i * n + s] = g[i * n + s] - (g[i * n + s] - geq[i]) / p->tau_g;
         }
     }
 }
@@ -470,21 +475,45 @@ void oracle_fd_init(const oracle_params *p, const double *phi0, double *f, doubl
     memcpy(phi, phi0, sizeof(double) * n);
 }
 
-/* rho, u = j/rho of a post-stream f, and phi copied from the field. */
+/* Body force F = -div Pi of a phi field (its gradients, mu and Pi first). */
+static int force_of_field(const oracle_params *p, const double *phi, double *F)
+{
+    long n = nsites(p);
+    double *grad = malloc(sizeof(double) * 3 * n), *lap = malloc(sizeof(double) * n);
+    double *mu = malloc(sizeof(double) * n), *pi = malloc(sizeof(double) * 6 * n);
+    int ok = grad && lap && mu && pi;
+    if (ok) {
+        oracle_gradients(p, phi, grad, lap);
+        oracle_chemical(p, phi, grad, lap, mu, pi);
+        oracle_force(p, pi, F);
+    }
+    free(grad); free(lap); free(mu); free(pi);
+    return ok ? 0 : 1;
+}
+
+/* rho, u of a post-stream f, and phi copied from the field: u = j/rho, or
+ * with the force coupling u = (j + F/2)/rho, F = -div Pi of this phi. */
 void oracle_fd_moments(const oracle_params *p, const double *f, const double *phi,
                        double *rho, double *u /* [3][N] */, double *phi_out)
 {
     long n = nsites(p);
+    double *F = NULL;
+    if (p->coupling == 1 && u) {
+        F = malloc(sizeof(double) * 3 * n);
+        if (!F || force_of_field(p, phi, F)) { free(F); return; }  /* out of memory */
+    }
     for (long s = 0; s < n; s++) {
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < NVEL; i++) {
             r += f[i * n + s];
             for (int a = 0; a < 3; a++) j[a] += f[i * n + s] * CV[i][a];
         }
+        if (F) for (int a = 0; a < 3; a++) j[a] += 0.5 * F[a * n + s];
         if (rho) rho[s] = r;
         if (u) for (int a = 0; a < 3; a++) u[a * n + s] = j[a] / r;
         if (phi_out) phi_out[s] = phi[s];
     }
+    free(F);
 }
 
 /* Flux J_a through the face between x and x + e_a, stored at x: J[3][N]. */
@@ -523,12 +552,10 @@ void oracle_fd_update(const oracle_params *p, const double *phi, const double *J
 }
 
 /* One timestep of the finite-difference scheme: (f, phi) -> (fnew, phinew).
- * Returns 1 on allocation failure, 2 for the force coupling (not defined
- * with this scheme). */
+ * Returns 1 on allocation failure. */
 int oracle_fd_step(const oracle_params *p, const double *f, const double *phi,
                    double *fnew, double *phinew)
 {
-    if (p->coupling != 0) return 2;
     long n = nsites(p);
     double *grad = malloc(sizeof(double) * 3 * n);
     double *lap = malloc(sizeof(double) * n);
@@ -544,7 +571,18 @@ int oracle_fd_step(const oracle_params *p, const double *f, const double *phi,
     oracle_fd_moments(p, f, phi, NULL, u, NULL);
     oracle_gradients(p, phi, grad, lap);
     oracle_chemical(p, phi, grad, lap, mu, pi);
-    oracle_collide(p, f, NULL, phi, mu, pi, fs, NULL);
+    if (p->coupling == 1) {
+        double *F = malloc(sizeof(double) * 3 * n);
+        if (!F) {
+            free(grad); free(lap); free(mu); free(pi); free(u); free(J); free(fs);
+            return 1;
+        }
+        oracle_force(p, pi, F);
+        oracle_collide_force(p, f, NULL, phi, mu, F, fs, NULL);
+        free(F);
+    } else {
+        oracle_collide(p, f, NULL, phi, mu, pi, fs, NULL);
+    }
     oracle_stream(p, fs, fnew);
     oracle_fd_fluxes(p, phi, mu, u, J);
     oracle_fd_update(p, phi, J, phinew);

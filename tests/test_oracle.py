@@ -552,8 +552,9 @@ def _lap_eig(shape, q):
     return -sum(2 * (1 - math.cos(2 * math.pi * qa / n)) for qa, n in zip(q, shape))
 
 
+@pytest.mark.parametrize("coupling", [0, 1])
 @pytest.mark.parametrize("q,tau_g,gamma", [((1, 2, 0), 1.3, 0.5), ((3, 1, 2), 0.8, 0.9)])
-def test_fd_diffusion_is_the_discrete_linear_multiplier(q, tau_g, gamma):
+def test_fd_diffusion_is_the_discrete_linear_multiplier(q, tau_g, gamma, coupling):
     """From rest (u = 0) a small mode phi = eps cos(q.x + 0.3) changes per step
     by the factor 1 + M lam (A - kappa lam), lam the Laplacian eigenvalue:
     the flux difference of mu is the 7-point Laplacian of the linearised mu.
@@ -561,7 +562,7 @@ def test_fd_diffusion_is_the_discrete_linear_multiplier(q, tau_g, gamma):
     follow the factor to the fifth power to O(eps^2) relative.  A flux sign,
     the mobility's tau_g convention or a kappa sign error is O(1) off."""
     shape = (8, 6, 10)
-    p = _fd_params(shape, tau_g=tau_g, gamma=gamma, tau_f=0.9)
+    p = _fd_params(shape, tau_g=tau_g, gamma=gamma, tau_f=0.9, coupling=coupling)
     x, y, z = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
     arg = 2 * math.pi * (q[0] * x / shape[0] + q[1] * y / shape[1] + q[2] * z / shape[2]) + 0.3
     eps = 1e-6
@@ -648,8 +649,9 @@ def test_fd_conserves_and_keeps_uniform_state():
 
 
 def test_fd_relaxes_like_the_lb_scheme():
-    """Both order-parameter schemes solve the same Cahn-Hilliard equation:
-    the decay rate of a small mode (A > 0) matches the continuum
+    """Both order-parameter schemes (and the finite-difference one with the
+    force coupling) solve the same Cahn-Hilliard equation: the decay rate of
+    a small mode (A > 0) matches the continuum
     M k^2 (A + kappa k^2), M = Gamma (tau_g - 1/2), to 2% for each
     (FD 0.3%, LB 1.1% here; a mobility off by tau_g's 1/2 is 70% off)."""
     n = 32
@@ -661,8 +663,9 @@ def test_fd_relaxes_like_the_lb_scheme():
     def amp(phi):
         return 2.0 / n * (phi[:, 0, 0] * np.cos(k * np.arange(n))).sum()
 
-    for op in (0, 1):
-        p = _params(shape, A=0.1, B=0.0, kappa=0.004, tau_g=1.2, gamma=0.5, order_param=op)
+    for op, coupling in ((0, 0), (1, 0), (1, 1)):
+        p = _params(shape, A=0.1, B=0.0, kappa=0.004, tau_g=1.2, gamma=0.5, order_param=op,
+                    coupling=coupling)
         if op:
             f, phi = oracle.fd_run(p, *oracle.fd_init(p, phi0), 30)
             _, phi2 = oracle.fd_run(p, f, phi, 400)
@@ -698,11 +701,70 @@ def test_fd_flat_interfaces_reach_equilibrium():
     assert np.abs(d - q).max() < 2e-3 * np.ptp(d), np.abs(d - q).max() / np.ptp(d)
 
 
-def test_fd_rejects_force_coupling():
-    p = _fd_params((4, 4, 4), coupling=1)
-    f, phi = oracle.fd_init(p, np.zeros((4, 4, 4)))
-    with pytest.raises(ValueError):
-        oracle.fd_step(p, f, phi)
+# -- with the force coupling (the stress divergence on the fluid) -----------
+
+def test_fd_force_advects_with_the_half_force_velocity():
+    """From rest (j = 0) with M = 0, phi's first change is advection alone by
+    the velocity the forcing collision uses, u = F / (2 rho0): the same
+    update as the (separately pinned) flux functions with that u.  Taking
+    u = j / rho instead leaves phi unchanged."""
+    shape = (9, 8, 7)
+    p = _fd_params(shape, coupling=1, gamma=0.0, A=-0.05, B=0.05, kappa=0.3)
+    phi0 = 0.8 * lbinputs.random_field(shape, seed=31)
+    f, phi = oracle.fd_init(p, phi0)
+    _, phi1 = oracle.fd_step(p, f, phi)
+    grad, lap = oracle.gradients(p, phi0)
+    _, pi = oracle.chemical(p, phi0, grad, lap)
+    u = oracle.force(p, pi) / (2 * p.rho0)
+    _, um, _ = oracle.fd_moments(p, f, phi0)
+    np.testing.assert_allclose(um, u, rtol=1e-14, atol=1e-17)
+    expect = oracle.fd_update(p, phi0, oracle.fd_fluxes(p, phi0, np.zeros(shape), u))
+    np.testing.assert_allclose(phi1, expect, rtol=0, atol=1e-15)
+    assert np.abs(phi1 - phi0).max() > 1e-6
+
+
+def test_fd_force_conserves_and_keeps_uniform_state():
+    """sum rho, sum phi and total momentum conserved to round-off over 40
+    steps (the central divergence and the fluxes telescope); a uniform phi at
+    rest stays bit-for-bit with j = 0 exactly (F = 0 exactly), f at w rho0
+    to round-off."""
+    shape = (6, 7, 8)
+    p = _fd_params(shape, coupling=1, tau_f=0.8, tau_g=1.3)
+    f, _ = _perturbed_state(_params(shape, tau_f=0.8, tau_g=1.3), 4)
+    phi = 0.1 + lbinputs.spinodal_phi0(shape, seed=8, amp=0.4)
+    s0 = oracle.fd_sums(p, f, phi)
+    f2, phi2 = oracle.fd_run(p, f, phi, 40)
+    np.testing.assert_allclose(oracle.fd_sums(p, f2, phi2), s0, rtol=0, atol=1e-12)
+    assert np.abs(f2 - f).max() > 1e-6
+    fu, pu = oracle.fd_init(p, np.full(shape, 0.3))
+    fu2, pu2 = oracle.fd_run(p, fu, pu, 10)
+    assert np.array_equal(pu2, pu)
+    _, uu, _ = oracle.fd_moments(p, fu2, pu2)
+    assert np.array_equal(uu, np.zeros_like(uu))
+    np.testing.assert_allclose(fu2, fu, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("coupling,tol", [(0, 2e-3), (1, 3e-2)])
+def test_fd_flat_interfaces_mechanical_equilibrium_both_couplings(coupling, tol):
+    """With either coupling the finite-difference scheme's flat interfaces
+    come to rest with rho/3 + Pi_xx uniform, to the tolerance the LB scheme
+    meets with the same coupling."""
+    n = 96
+    shape = (n, 1, 1)
+    A, B, kappa = -0.005, 0.005, 0.16
+    xi = math.sqrt(-2 * kappa / A)
+    x = np.arange(n)
+    phi0 = (np.tanh((x - n / 4) / xi) - np.tanh((x - 3 * n / 4) / xi) - 1.0).reshape(shape)
+    p = _fd_params(shape, A=A, B=B, kappa=kappa, tau_f=1.0, tau_g=1.0, coupling=coupling)
+    f, phi = oracle.fd_run(p, *oracle.fd_init(p, phi0), 8000)
+    rho, u, _ = oracle.fd_moments(p, f, phi)
+    assert np.abs(u).max() < 1e-6
+    grad, lap = oracle.gradients(p, phi)
+    _, pi = oracle.chemical(p, phi, grad, lap)
+    d = (rho - rho.mean()).ravel()
+    q = (-3 * (pi[0] - pi[0].mean())).ravel()
+    assert np.ptp(d) > 1e-5
+    assert np.abs(d - q).max() < tol * np.ptp(d), np.abs(d - q).max() / np.ptp(d)
 
 
 # ----------------------------------------------- reverse-mode gradients --
