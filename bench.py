@@ -307,6 +307,26 @@ def main():
         out["fd_order_parameter"]["phi_fp32_vs_fp64_max"] = float(
             np.abs(fd_phi["fp32_dev"] - fd_phi["fp64"]).max())
         del fd_phi
+        # with the force coupling: the two-kernel path, collision pass 344 / 192
+        # B per site (FP64 / FP32 storage; Pi at the face neighbours from the
+        # phi field, in cache) and flux pass 48
+        out["fd_order_parameter"]["force_coupling"] = {}
+        for prec, moved in (("fp32_dev", 240), ("fp64", 392)):
+            lb = LB(shape, precision=prec, order_param="fd", coupling="force", device="cuda:0",
+                    **lay, **params)
+            lb.init_phi(phi0)
+            log(f"{prec} finite-difference order parameter + force coupling {shape}: "
+                f"{args.fd_steps} steps")
+            ms = time_steps(lb, args.fd_steps, args.warmup)
+            t = ms / args.fd_steps * 1e-3
+            out["fd_order_parameter"]["force_coupling"][prec] = {
+                "value": round(nsites / t / 1e6, 1), "unit": "MLUPS", "steps": args.fd_steps,
+                "ms_per_step": round(ms / args.fd_steps, 4),
+                "achieved_GBps": round(moved * nsites / t / 1e9, 1),
+                "frac": round(moved * nsites / t / 1e9 / HBM_PEAK_GBPS, 4),
+                "bytes_per_site": moved, "kernels": "k_fd_collide + k_fd_update"}
+            del lb
+            torch.cuda.empty_cache()
 
     # one GPU's share of the 256^3 droplet split into 8 x-slabs: the same
     # single-pass kernel on a 32 x 256 x 256 lattice (periodic here; a shard

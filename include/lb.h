@@ -106,9 +106,13 @@ typedef enum {
                              - M (mu(x + e_a) - mu(x)),
                      phi(x, t+1) = phi(x) - sum_a [J_a(x + e_a/2) - J_a(x - e_a/2)]
                      with M = Gamma (tau_g - 1/2), the mobility of the g
-                     scheme; mu and Pi from phi(t); f collides as above with Pi
-                     in f^eq.  Requires LB_COUPLING_STRESS; no adjoint; phi is
-                     FP64 in both precisions.                                */
+                     scheme; mu and Pi from phi(t).  With LB_COUPLING_STRESS f
+                     collides as above with Pi in f^eq; with
+                     LB_COUPLING_FORCE (the paper's arrangement) f collides
+                     with F = -div Pi and u = (j + F/2)/rho is also the
+                     fluxes' velocity (that combination always runs the
+                     two-kernel path).  No adjoint; phi is FP64 in both
+                     precisions.                                             */
 } lb_order_param;
 
 /* Memory layout of the f and g regions of a time level (opaque to callers,

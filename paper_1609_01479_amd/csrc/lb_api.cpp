@@ -77,8 +77,6 @@ lb_status validate(const lb_params* p)
         return fail(LB_EINVAL, "unknown coupling %d", p->coupling);
     if (p->order_param != LB_OP_LB && p->order_param != LB_OP_FD)
         return fail(LB_EINVAL, "unknown order_param %d", p->order_param);
-    if (p->order_param == LB_OP_FD && p->coupling != LB_COUPLING_STRESS)
-        return fail(LB_EINVAL, "LB_OP_FD requires LB_COUPLING_STRESS");
     if (p->layout == LB_LAYOUT_AOSOA) {
         const int v = p->aosoa_len;
         if (v < 1 || (v & (v - 1)) != 0 || p->nz % v != 0)

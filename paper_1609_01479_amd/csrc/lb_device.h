@@ -376,19 +376,17 @@ __device__ __forceinline__ void chem_stress(const KParams& p, const Stencil& st,
 //   g^eq_i = w [phi + 3 phi c.u + 9/2 ((Gamma mu - phi/3)(|c|^2 - 1) + phi ((c.u)^2 - |u|^2/3))],
 //   g^eq_i - r_i phi = w [3 phi c.u + 9/2 (Gamma mu (|c|^2 - 1) + phi ((c.u)^2 - |u|^2/3))],
 //   f*_i = f_i + omega_f (f^eq_i - f_i) + (1 - omega_f/2) w [3 (c - u).F + 9 (c.u)(c.F)].
-template <typename T, bool DEV, bool REF>
-__device__ __forceinline__ void collide_force(const KParams& p, T* f, T* g, double phi_d, double mu_d,
-                                              const double Fd[3])
+// The f half of collide_force (returns u = (j + F/2)/rho) and the g half.
+template <typename T, bool DEV>
+__device__ __forceinline__ Vel<T> collide_force_f(const KParams& p, T* f, const double Fd[3])
 {
     const Moments<T> m = moments_of<T, DEV>(p, f);
-    const T phi = T(phi_d), mu = T(mu_d);
     const T F[3] = {T(Fd[0]), T(Fd[1]), T(Fd[2])};
     const T ri = T(1) / m.rho;
     const T ux = (m.jx + T(0.5) * F[0]) * ri, uy = (m.jy + T(0.5) * F[1]) * ri,
             uz = (m.jz + T(0.5) * F[2]) * ri;
     const T uu3 = (ux * ux + uy * uy + uz * uz) * T(1.0 / 3.0);
-    const T gm = T(p.gamma) * mu, sg = REF ? gm : gm - phi * T(1.0 / 3.0);
-    const T omf = T(p.omega_f), omg = T(p.omega_g);
+    const T omf = T(p.omega_f);
     const T pref = T(1) - T(0.5) * omf;
     const T uF = ux * F[0] + uy * F[1] + uz * F[2];
 #pragma unroll
@@ -401,10 +399,36 @@ __device__ __forceinline__ void collide_force(const KParams& p, T* f, T* g, doub
         const T feq = w * (m.b + m.rho * (T(3) * cu + T(4.5) * q));
         const T src = pref * w * (T(3) * (cF - uF) + T(9) * cu * cF);
         f[i] += omf * (feq - f[i]) + src;
+    }
+    return Vel<T>{ux, uy, uz};
+}
+
+template <typename T, bool REF>
+__device__ __forceinline__ void collide_force_g(const KParams& p, T* g, double phi_d, double mu_d,
+                                                Vel<T> u)
+{
+    const T phi = T(phi_d), mu = T(mu_d);
+    const T ux = u.x, uy = u.y, uz = u.z;
+    const T uu3 = (ux * ux + uy * uy + uz * uz) * T(1.0 / 3.0);
+    const T gm = T(p.gamma) * mu, sg = REF ? gm : gm - phi * T(1.0 / 3.0);
+    const T omg = T(p.omega_g);
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        const T w = T(weight(i));
+        const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
+        const T q = cu * cu - uu3;
         const T c2m1 = T(CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i] - 1);
         const T geq = w * ((REF ? T(0) : phi) + T(3) * phi * cu + T(4.5) * (sg * c2m1 + phi * q));
         g[i] += omg * (geq - g[i]);
     }
+}
+
+template <typename T, bool DEV, bool REF>
+__device__ __forceinline__ void collide_force(const KParams& p, T* f, T* g, double phi_d, double mu_d,
+                                              const double Fd[3])
+{
+    const Vel<T> u = collide_force_f<T, DEV>(p, f, Fd);
+    collide_force_g<T, REF>(p, g, phi_d, mu_d, u);
 }
 
 // Force coupling: F = -div Pi by central differences of Pi at the six face

@@ -18,6 +18,12 @@
 // instructions on the same operands, so the two values are identical and
 // sum phi changes only by the rounding of each site's own update.
 //
+// With the force coupling (the paper's arrangement: the stress divergence
+// acts on the fluid) the collision pass forms F = -div Pi from the phi field
+// and collides f with it, and the fluxes use u = (j + F/2)/rho; that
+// combination always runs the two kernels (the single pass would need mu,
+// u and F on a ring one cell wider).
+//
 // Time level: F (19*stride elements of T in the layout of didx(); FP32 mode
 // stores f - w rho0) followed by phi (stride FP64 values in site order).
 // No floating-point contraction in this translation unit (including the
@@ -70,8 +76,10 @@ __device__ __forceinline__ double fd_mu(const KParams& p, double c, double lap)
     return p.A * c + p.B * c * c * c - p.kappa * lap;
 }
 
-// Work fields (each `stride` FP64 values): mu, u_x, u_y, u_z.
-template <typename T, bool DEV>
+// Work fields (each `stride` FP64 values): mu, u_x, u_y, u_z.  FORCE: the
+// force coupling, F = -div Pi from the phi field (force_from_phi), the
+// forcing collision of f, u = (j + F/2)/rho, and momentum sums of j + F/2.
+template <typename T, bool DEV, bool FORCE>
 __global__ __launch_bounds__(kBlock) void k_fd_collide(KParams p, const T* __restrict__ sF,
                                                        const double* __restrict__ sphi,
                                                        T* __restrict__ dF,
@@ -89,6 +97,8 @@ __global__ __launch_bounds__(kBlock) void k_fd_collide(KParams p, const T* __res
         const Stencil st = stencil(c, sphi[site_of(p, q.xp, q.y, q.z)], sphi[site_of(p, q.xm, q.y, q.z)],
                                    sphi[site_of(p, q.x, q.yp, q.z)], sphi[site_of(p, q.x, q.ym, q.z)],
                                    sphi[site_of(p, q.x, q.y, q.zp)], sphi[site_of(p, q.x, q.y, q.zm)]);
+        double F[3] = {0.0, 0.0, 0.0};
+        if (FORCE) force_from_phi(p, q, sphi, F);
         if (partials) {
             // FP64 moments of the source level, in index order
             double b = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
@@ -102,11 +112,11 @@ __global__ __launch_bounds__(kBlock) void k_fd_collide(KParams p, const T* __res
             }
             acc[0] = DEV ? p.rho0 + b : b;
             acc[1] = c;
-            acc[2] = jx;
-            acc[3] = jy;
-            acc[4] = jz;
+            acc[2] = FORCE ? jx + 0.5 * F[0] : jx;
+            acc[3] = FORCE ? jy + 0.5 * F[1] : jy;
+            acc[4] = FORCE ? jz + 0.5 * F[2] : jz;
         }
-        const Vel<T> u = collide_f<T, DEV>(p, f, st);
+        const Vel<T> u = FORCE ? collide_force_f<T, DEV>(p, f, F) : collide_f<T, DEV>(p, f, st);
         // the new level is not read in this launch
 #pragma unroll
         for (int i = 0; i < NV; i++) __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
@@ -394,8 +404,8 @@ struct FdFused {
 };
 
 // Dense FP64 moments and block partials of [rho, phi, jx, jy, jz]
-// (grid-stride); u = j/rho.
-template <typename T, bool DEV>
+// (grid-stride); u = j/rho, or with FORCE (j + F/2)/rho and sums of j + F/2.
+template <typename T, bool DEV, bool FORCE>
 __global__ __launch_bounds__(kBlock) void k_fd_moments(KParams p, const T* __restrict__ F,
                                                        const double* __restrict__ phi,
                                                        double* __restrict__ rho_out,
@@ -417,6 +427,13 @@ __global__ __launch_bounds__(kBlock) void k_fd_moments(KParams p, const T* __res
         }
         const double rho = DEV ? p.rho0 + b : b;
         const double ph = phi[s];
+        if (FORCE) {
+            double F[3];
+            force_from_phi(p, q, phi, F);
+            jx += 0.5 * F[0];
+            jy += 0.5 * F[1];
+            jz += 0.5 * F[2];
+        }
         if (rho_out) rho_out[s] = rho;
         if (u_out) {
             u_out[s] = jx / rho;
@@ -524,7 +541,7 @@ hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int va
                           double* sums_out, hipStream_t s)
 {
     int nparts;
-    if (variant == 0) {
+    if (variant == 0 && !p.force) {
         nparts = tc.ntiles * tc.nseg;
 #define CALL                                                                                  \
     {                                                                                         \
@@ -542,8 +559,14 @@ hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int va
     {                                                                                         \
         FdLvl<T> a = fd_level<T>(const_cast<void*>(src), p);                                  \
         FdLvl<T> d = fd_level<T>(dst, p);                                                     \
-        k_fd_collide<T, DEV><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, d.F, work,          \
-                                                           sums_out ? partials : nullptr);    \
+        if (p.force)                                                                          \
+            k_fd_collide<T, DEV, true><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, d.F, work, \
+                                                                     sums_out ? partials       \
+                                                                              : nullptr);      \
+        else                                                                                  \
+            k_fd_collide<T, DEV, false><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, d.F, work,\
+                                                                      sums_out ? partials      \
+                                                                               : nullptr);     \
         k_fd_update<<<ft.ntiles * ft.nseg, kBlock, 0, s>>>(p, ft.ntz, ft.ntiles, ft.sx, a.phi,  \
                                                            work, d.phi);                      \
     }
@@ -567,7 +590,12 @@ hipError_t launch_fd_moments(const KParams& p, bool fp32, const void* state, dou
 #define CALL                                                                                \
     {                                                                                       \
         FdLvl<T> a = fd_level<T>(const_cast<void*>(state), p);                              \
-        k_fd_moments<T, DEV><<<nb, kBlock, 0, s>>>(p, a.F, a.phi, rho, u, phi, partials);   \
+        if (p.force)                                                                        \
+            k_fd_moments<T, DEV, true><<<nb, kBlock, 0, s>>>(p, a.F, a.phi, rho, u, phi,    \
+                                                             partials);                     \
+        else                                                                                \
+            k_fd_moments<T, DEV, false><<<nb, kBlock, 0, s>>>(p, a.F, a.phi, rho, u, phi,   \
+                                                              partials);                    \
     }
     LB_FD_DISPATCH(fp32, CALL);
 #undef CALL

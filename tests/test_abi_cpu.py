@@ -74,7 +74,6 @@ def test_query_sizes(abi):
     (dict(layout=3, aosoa_len=64, nz=96), "LB_ESHAPE"),
     (dict(coupling=2), "LB_EINVAL"), (dict(coupling=-1), "LB_EINVAL"),
     (dict(order_param=2), "LB_EINVAL"), (dict(order_param=-1), "LB_EINVAL"),
-    (dict(order_param=1, coupling=1), "LB_EINVAL"),
 ])
 def test_bad_parameters_rejected(abi, kw, code):
     st, _ = _query(abi, **kw)

@@ -36,13 +36,14 @@ def _ref(p, f, phi):
     return f, rho, u, ph
 
 
-def _run_both(shape, steps, phi0, precision="fp64", **kw):
-    print(f"[fd] shape={shape} steps={steps} precision={precision} params={kw}", flush=True)
-    lb = make_lb(shape, precision=precision, order_param="fd", **kw)
+def _run_both(shape, steps, phi0, precision="fp64", coupling="stress", **kw):
+    print(f"[fd] shape={shape} steps={steps} precision={precision} coupling={coupling} "
+          f"params={kw}", flush=True)
+    lb = make_lb(shape, precision=precision, order_param="fd", coupling=coupling, **kw)
     lb.init_phi(phi0)
     lb.step(steps)
     got = _gpu(lb)
-    p = oracle_params(shape, order_param=1, **kw)
+    p = oracle_params(shape, order_param=1, coupling={"stress": 0, "force": 1}[coupling], **kw)
     ref = _ref(p, *oracle.fd_run(p, *oracle.fd_init(p, phi0), steps))
     return got, ref, lb, p
 
@@ -217,15 +218,15 @@ def _win(t, site, shape):
     return w.cpu().numpy()
 
 
-def _sampled_fd(shape, precision, phi0, steps_before, kw, tol, nsample=16):
-    print(f"[fd fullsize] {shape} {precision} after {steps_before} steps, {nsample} sites",
-          flush=True)
+def _sampled_fd(shape, precision, phi0, steps_before, kw, tol, nsample=16, coupling="stress"):
+    print(f"[fd fullsize] {shape} {precision} {coupling} after {steps_before} steps, "
+          f"{nsample} sites", flush=True)
     rng = np.random.default_rng(9)
     nx, ny, nz = shape
     sites = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (nx // 2, ny // 2, nz // 2), (1, ny - 1, 64 % nz)]
     sites += [(int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz)))
               for _ in range(nsample)]
-    lb = make_lb(shape, precision=precision, order_param="fd", **kw)
+    lb = make_lb(shape, precision=precision, order_param="fd", coupling=coupling, **kw)
     lb.init_phi(phi0)
     lb.step(steps_before)
     f, _ = lb.export_dist()
@@ -239,7 +240,8 @@ def _sampled_fd(shape, precision, phi0, steps_before, kw, tol, nsample=16):
     got = [(f1[:, x, y, z].cpu().numpy(), float(phi1[x, y, z])) for x, y, z in sites]
     del f1, phi1, lb
     torch.cuda.empty_cache()
-    pw = oracle_params((2 * R + 1,) * 3, order_param=1, **kw)
+    pw = oracle_params((2 * R + 1,) * 3, order_param=1,
+                       coupling={"stress": 0, "force": 1}[coupling], **kw)
     ferr = perr = fscale = pscale = 0.0
     for (fw, pw_phi), (fg, pg) in zip(wins, got):
         fo, po = oracle.fd_step(pw, fw, pw_phi)
@@ -285,3 +287,60 @@ def test_fd_conservation_droplet_256(precision):
     tol = 1e-9 * n if precision == "fp64" else 2e-7 * n
     assert np.abs(s1 - s0).max() <= tol, (s1 - s0)
     assert abs(s1[1] - s0[1]) <= 1e-9 * n
+
+
+# ---- with the force coupling (the paper's arrangement) ------------------------
+# One step at x depends on phi within distance 3 here (the fluxes use u at the
+# face neighbours, whose force needs Pi one site further), still inside the
+# 7^3 window.
+
+@pytest.mark.parametrize("steps", [0, 1, 10, 100])
+def test_fd_force_spinodal_16cubed(steps):
+    shape = (16, 16, 16)
+    got, ref, *_ = _run_both(shape, steps, lbinputs.spinodal_phi0(shape), coupling="force")
+    errs = field_errors(got, ref, NAMES)
+    assert max(errs.values()) <= TOL, errs
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (3, 5, 131), (1, 7, 1), (2, 2, 2)])
+def test_fd_force_ragged_degenerate_tau_not_one(shape):
+    phi0 = lbinputs.spinodal_phi0(shape, seed=12, amp=0.4)
+    got, ref, *_ = _run_both(shape, 25, phi0, coupling="force", tau_f=0.8, tau_g=1.3)
+    errs = field_errors(got, ref, NAMES)
+    assert max(errs.values()) <= TOL, errs
+
+
+def test_fd_force_droplet_and_step_sums():
+    """A sharp droplet (large force at the interface), 50 steps; per-step sums
+    (momentum of j + F/2) against the oracle's and conserved."""
+    shape = (24, 20, 22)
+    pr = lbinputs.SPINODAL_PARAMS
+    xi = lbinputs.interface_width(pr["A"], pr["kappa"])
+    phi0 = lbinputs.droplet_phi0(shape, 6.0, xi, noise=1e-3, seed=3)
+    got, ref, lb, p = _run_both(shape, 50, phi0, coupling="force")
+    errs = field_errors(got, ref, NAMES)
+    assert max(errs.values()) <= TOL, errs
+    hist = lb.step_sums(10).cpu().numpy()
+    want = oracle.fd_sums(p, *oracle.fd_run(p, *oracle.fd_init(p, phi0), 50))
+    np.testing.assert_allclose(hist[0], want, rtol=1e-12, atol=1e-12)
+    assert np.abs(hist[:, :2] - hist[0, :2]).max() <= 1e-11
+    assert np.abs(hist[:, 2:] - hist[0, 2:]).max() <= 1e-12
+
+
+def test_fd_force_fp32_storage():
+    shape = (16, 16, 16)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=14, amp=0.3)
+    got, ref, *_ = _run_both(shape, 20, phi0, precision="fp32_dev", coupling="force", tau_f=0.8,
+                             tau_g=1.3)
+    f, rho, u, phi = got
+    rf, rrho, ru, rphi = ref
+    assert np.abs(phi - rphi).max() <= 1e-6
+    assert np.abs(rho - rrho).max() <= 1e-6
+    assert np.abs(u - ru).max() <= 1e-7
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_dev", 2e-6)])
+def test_fd_force_sampled_parity_droplet_256(precision, tol):
+    shape = (256, 256, 256)
+    _sampled_fd(shape, precision, _droplet(shape), 5, dict(tau_f=0.8, tau_g=1.3), tol,
+                coupling="force")
