@@ -2,8 +2,8 @@
 //
 // The step of the paper's Ludwig timestep (Sec. 2.1.1) -- order-parameter
 // gradients, chemical stress, collision, propagation -- runs as ONE kernel,
-// k_step_fused_f32 / _f64: each workgroup owns a (y, z) tile of 4 x 64 sites
-// and marches along x over a segment of planes.  For plane x it needs phi at
+// k_step_fused_f32 / _f64: each workgroup owns a (y, z) tile of 4 x 128 (or
+// 8 x 64) sites and marches along x over a segment of planes.  For plane x it needs phi at
 // planes x-1, x, x+1 (7-point stencil); phi(x+1) is formed from the pulled g
 // of plane x+1, which the same threads keep in registers for plane x+1's own
 // collision one iteration later.  phi on the tile's (y, z) halo ring is
@@ -14,7 +14,9 @@
 //
 // k_phi + k_step_2s are the two-pass variant (phi kernel, then the
 // stencil/collision/propagation kernel), kept for comparison; both variants
-// produce bit-identical levels.
+// produce bit-identical levels.  The force coupling runs k_phi and then the
+// collision pass of lb_force.hip; the finite-difference order parameter has
+// its own kernels in lb_fd.hip.
 #include <type_traits>
 
 #include "lb_device.h"
