@@ -324,7 +324,7 @@ def main():
                 "ms_per_step": round(ms / args.fd_steps, 4),
                 "achieved_GBps": round(moved * nsites / t / 1e9, 1),
                 "frac": round(moved * nsites / t / 1e9 / HBM_PEAK_GBPS, 4),
-                "bytes_per_site": moved, "kernels": "k_fd_collide + k_fd_update"}
+                "bytes_per_site": moved, "kernels": "k_fd_force_collide + k_fd_update"}
             del lb
             torch.cuda.empty_cache()
 

@@ -21,8 +21,10 @@
 // With the force coupling (the paper's arrangement: the stress divergence
 // acts on the fluid) the collision pass forms F = -div Pi from the phi field
 // and collides f with it, and the fluxes use u = (j + F/2)/rho; that
-// combination always runs the two kernels (the single pass would need mu,
-// u and F on a ring one cell wider).
+// combination always runs a collision pass and the flux pass (a single pass
+// would need mu, u and F on a ring one cell wider): k_fd_force_collide
+// marching with Pi in LDS (LB_KERNEL_FUSED), or k_fd_collide one site per
+// thread (LB_KERNEL_TWO_PASS), bit-identical.
 //
 // Time level: F (19*stride elements of T in the layout of didx(); FP32 mode
 // stores f - w rho0) followed by phi (stride FP64 values in site order).
@@ -403,6 +405,194 @@ struct FdFused {
     }
 };
 
+// The collision pass of the force coupling, marching (LB_KERNEL_FUSED): the
+// tiling and plane loop of k_fd_fused with phi of the tile plus two cells
+// around it in an 8-plane LDS ring (from the phi field, loaded one plane
+// ahead), Pi of plane P formed once per site for the tile and its face ring
+// (LDS: the components the y and z neighbours need; registers: the own
+// column's x row) and the forcing collision of plane P-1, which writes f*,
+// mu and u = (j + F/2)/rho for k_fd_update.  Bit-identical to
+// k_fd_collide<T, DEV, true>, which forms Pi at each face neighbour.
+constexpr int kFdPhiSlots = 8;  // planes P-2 .. P+1 are read while P+2 is written
+
+template <typename T, bool DEV, int TZ>
+__global__ __launch_bounds__(kFdFused) void k_fd_force_collide(KParams p, TileCfg tc,
+                                                               const T* __restrict__ sF,
+                                                               const double* __restrict__ sphi,
+                                                               T* __restrict__ dF,
+                                                               double* __restrict__ work,
+                                                               double* __restrict__ partials)
+{
+    using G = FdTile<TZ>;
+    constexpr int TY = G::TY, BZ = G::BZ, RZ = G::RZ, NR = G::RY * G::RZ;
+    constexpr int SM = kFdPhiSlots - 1;
+    __shared__ double s_phi[kFdPhiSlots][G::NBOX];
+    __shared__ double s_piy[2][3][NR];  // Pi_xy, Pi_yy, Pi_yz: read by the y neighbours
+    __shared__ double s_piz[2][3][NR];  // Pi_xz, Pi_yz, Pi_zz: read by the z neighbours
+
+    const int t = threadIdx.x;
+    const int b = xcd_block();
+    const int seg = b / tc.ntiles, tile = b - seg * tc.ntiles;
+    const int y0 = (tile / tc.ntz) * TY, z0 = (tile % tc.ntz) * TZ;
+    const int x0 = seg * tc.sx, x1 = min(p.nx, x0 + tc.sx);
+    const int plane = p.ny * p.nz;
+
+    const int ly = t / TZ, lz = t % TZ;
+    const int yg = wrap_any(y0 + ly, p.ny), zg = wrap_any(z0 + lz, p.nz);
+    const bool valid = y0 + ly < p.ny && z0 + lz < p.nz;
+    const int bo = (ly + 2) * BZ + (lz + 2);
+    const int ro = (ly + 1) * RZ + (lz + 1);
+    int boff[G::BOXPT];
+#pragma unroll
+    for (int k = 0; k < G::BOXPT; k++) {
+        const int c = t + k * kFdFused;
+        boff[k] = c < G::NBOX
+                      ? wrap_any(y0 + c / BZ - 2, p.ny) * p.nz + wrap_any(z0 + c % BZ - 2, p.nz)
+                      : -1;
+    }
+    const bool ring = t < G::NRING;
+    int rly, rlz;
+    if (t < TZ) { rly = -1; rlz = t; }
+    else if (t < 2 * TZ) { rly = TY; rlz = t - TZ; }
+    else if (t < 2 * TZ + TY) { rly = t - 2 * TZ; rlz = -1; }
+    else { rly = t - 2 * TZ - TY; rlz = TZ; }
+    const bool ring_y = rly < 0 || rly >= TY;
+    const int rbo = (rly + 2) * BZ + (rlz + 2);
+    const int rro = (rly + 1) * RZ + (rlz + 1);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+    auto load_box = [&](int xp, double (&v)[G::BOXPT]) {
+        const int xo = wrap_any(xp, p.nx) * plane;
+#pragma unroll
+        for (int k = 0; k < G::BOXPT; k++) v[k] = boff[k] >= 0 ? sphi[xo + boff[k]] : 0.0;
+    };
+    auto store_box = [&](int xp, const double (&v)[G::BOXPT]) {
+        double* __restrict__ dst = s_phi[xp & SM];
+#pragma unroll
+        for (int k = 0; k < G::BOXPT; k++)
+            if (boff[k] >= 0) dst[t + k * kFdFused] = v[k];
+    };
+    double pre[G::BOXPT];
+    load_box(x0 - 2, pre);
+    store_box(x0 - 2, pre);
+    load_box(x0 - 1, pre);
+    store_box(x0 - 1, pre);
+    load_box(x0, pre);
+
+    double pxA[3] = {0.0, 0.0, 0.0}, pxB[3] = {0.0, 0.0, 0.0};
+    for (int P = x0 - 1; P <= x1; P++) {
+        const int X = P - 1;
+        const bool collide_x = X >= x0 && valid;
+        store_box(P + 1, pre);
+        load_box(P + 2, pre);
+        T f[NV];
+        const Geo q = geo_xyz(p, wrap_any(X, p.nx), yg, zg);
+        if (collide_x)
+#pragma unroll
+            for (int i = 0; i < NV; i++) f[i] = sF[dist_pull(p, q, i)];
+        lds_barrier();
+        const double* __restrict__ fm = s_phi[(P - 1) & SM];
+        const double* __restrict__ fc = s_phi[P & SM];
+        const double* __restrict__ fp = s_phi[(P + 1) & SM];
+        const int w = P & 1;
+
+        // Pi of plane P
+        double pxP[3];
+        {
+            const Stencil st = stencil(fc[bo], fp[bo], fm[bo], fc[bo + BZ], fc[bo - BZ], fc[bo + 1],
+                                       fc[bo - 1]);
+            double mu, tt[6];
+            chem_stress(p, st, &mu, tt);
+            pxP[0] = tt[0];
+            pxP[1] = tt[1];
+            pxP[2] = tt[2];
+            s_piy[w][0][ro] = tt[1];
+            s_piy[w][1][ro] = tt[3];
+            s_piy[w][2][ro] = tt[4];
+            s_piz[w][0][ro] = tt[2];
+            s_piz[w][1][ro] = tt[4];
+            s_piz[w][2][ro] = tt[5];
+        }
+        if (ring && P >= x0 && P < x1) {
+            const Stencil st = stencil(fc[rbo], fp[rbo], fm[rbo], fc[rbo + BZ], fc[rbo - BZ],
+                                       fc[rbo + 1], fc[rbo - 1]);
+            double mu, tt[6];
+            chem_stress(p, st, &mu, tt);
+            if (ring_y) {
+                s_piy[w][0][rro] = tt[1];
+                s_piy[w][1][rro] = tt[3];
+                s_piy[w][2][rro] = tt[4];
+            } else {
+                s_piz[w][0][rro] = tt[2];
+                s_piz[w][1][rro] = tt[4];
+                s_piz[w][2][rro] = tt[5];
+            }
+        }
+
+        // the forcing collision of plane X = P-1
+        if (collide_x) {
+            const int v = X & 1;
+            const double* __restrict__ xm = s_phi[(X - 1) & SM];
+            const double* __restrict__ xc = s_phi[X & SM];
+            const double* __restrict__ xp = s_phi[(X + 1) & SM];
+            const double c = xc[bo];
+            const Stencil st = stencil(c, xp[bo], xm[bo], xc[bo + BZ], xc[bo - BZ], xc[bo + 1],
+                                       xc[bo - 1]);
+            // F_a = -sum_b [Pi_ab(x + e_b) - Pi_ab(x - e_b)] / 2, b = x, y, z in order
+            double div[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int a = 0; a < 3; a++) div[a] += 0.5 * (pxP[a] - pxA[a]);
+#pragma unroll
+            for (int a = 0; a < 3; a++) div[a] += 0.5 * (s_piy[v][a][ro + RZ] - s_piy[v][a][ro - RZ]);
+#pragma unroll
+            for (int a = 0; a < 3; a++) div[a] += 0.5 * (s_piz[v][a][ro + 1] - s_piz[v][a][ro - 1]);
+            double F[3];
+#pragma unroll
+            for (int a = 0; a < 3; a++) F[a] = -div[a];
+            if (partials) {
+                double bs = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+                for (int i = 0; i < NV; i++) {
+                    const double vv = double(f[i]);
+                    bs += vv;
+                    jx += CX[i] * vv;
+                    jy += CY[i] * vv;
+                    jz += CZ[i] * vv;
+                }
+                acc[0] += DEV ? p.rho0 + bs : bs;
+                acc[1] += c;
+                acc[2] += jx + 0.5 * F[0];
+                acc[3] += jy + 0.5 * F[1];
+                acc[4] += jz + 0.5 * F[2];
+            }
+            const Vel<T> u = collide_force_f<T, DEV>(p, f, F);
+#pragma unroll
+            for (int i = 0; i < NV; i++) __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
+            const int s = X * plane + yg * p.nz + zg;
+            work[s] = fd_mu(p, c, st.lap);
+            work[p.stride + s] = double(u.x);
+            work[2 * p.stride + s] = double(u.y);
+            work[3 * p.stride + s] = double(u.z);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            pxA[a] = pxB[a];
+            pxB[a] = pxP[a];
+        }
+    }
+    if (partials) block_partials<5, kFdFused>(acc, partials);
+}
+
+template <typename T>
+struct FdForce {
+    using K = decltype(&k_fd_force_collide<T, std::is_same<T, float>::value, 128>);
+    static K get(int tz)
+    {
+        constexpr bool DEV = std::is_same<T, float>::value;
+        return tz == 64 ? k_fd_force_collide<T, DEV, 64> : k_fd_force_collide<T, DEV, 128>;
+    }
+};
+
 // Dense FP64 moments and block partials of [rho, phi, jx, jy, jz]
 // (grid-stride); u = j/rho, or with FORCE (j + F/2)/rho and sums of j + F/2.
 template <typename T, bool DEV, bool FORCE>
@@ -541,7 +731,22 @@ hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int va
                           double* sums_out, hipStream_t s)
 {
     int nparts;
-    if (variant == 0 && !p.force) {
+    if (variant == 0 && p.force) {
+        // marching collision pass with the force, then the flux pass
+        const FdTiles ft = fd_tiles(p);
+        nparts = tc.ntiles * tc.nseg;
+#define CALL                                                                                  \
+    {                                                                                         \
+        FdLvl<T> a = fd_level<T>(const_cast<void*>(src), p);                                  \
+        FdLvl<T> d = fd_level<T>(dst, p);                                                     \
+        FdForce<T>::get(tc.tz)<<<nparts, kFdFused, 0, s>>>(p, tc, a.F, a.phi, d.F, work,      \
+                                                           sums_out ? partials : nullptr);    \
+        k_fd_update<<<ft.ntiles * ft.nseg, kBlock, 0, s>>>(p, ft.ntz, ft.ntiles, ft.sx, a.phi,  \
+                                                           work, d.phi);                      \
+    }
+        LB_FD_DISPATCH(fp32, CALL);
+#undef CALL
+    } else if (variant == 0) {
         nparts = tc.ntiles * tc.nseg;
 #define CALL                                                                                  \
     {                                                                                         \

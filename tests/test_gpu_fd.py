@@ -100,22 +100,24 @@ def test_fd_flow_advects_phi():
     assert np.abs(got[3] - phi0).max() > 0.1  # phi moved
 
 
+@pytest.mark.parametrize("coupling", ["stress", "force"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
 @pytest.mark.parametrize("shape,seg", [((16, 16, 16), 0), ((16, 16, 16), 5), ((5, 6, 7), 2),
                                        ((3, 5, 131), 0), ((17, 9, 70), 4), ((1, 7, 1), 0),
                                        ((2, 2, 2), 1), ((6, 13, 200), 3), ((9, 6, 131), 9),
                                        ((24, 20, 192), 0)])
-def test_fd_single_pass_matches_two_pass(precision, shape, seg):
-    """The single-pass kernel (collision one plane ahead of the flux update,
-    face ring in LDS) and the two-kernel path give bit-identical levels:
-    ragged tiles in y and z, 4 x 128 and 8 x 64 tiles, one-plane and long
-    x segments, extents 1 and 2."""
-    print(f"[fd fused] {shape} segment_x={seg} {precision}", flush=True)
+def test_fd_single_pass_matches_two_pass(precision, shape, seg, coupling):
+    """The marching kernels (stress: collision one plane ahead of the flux
+    update, face ring in LDS; force: the collision pass with Pi in LDS) and
+    the one-site-per-thread kernels give bit-identical levels: ragged tiles
+    in y and z, 4 x 128 and 8 x 64 tiles, one-plane and long x segments,
+    extents 1 and 2."""
+    print(f"[fd fused] {shape} segment_x={seg} {precision} {coupling}", flush=True)
     phi0 = lbinputs.spinodal_phi0(shape, seed=17, amp=0.4)
     out = []
     for kern in ("fused", "two_pass"):
         lb = make_lb(shape, precision=precision, order_param="fd", kernel=kern, segment_x=seg,
-                     tau_f=0.8, tau_g=1.3)
+                     coupling=coupling, tau_f=0.8, tau_g=1.3)
         lb.init_phi(phi0)
         lb.step(7)
         out.append(_gpu(lb))
