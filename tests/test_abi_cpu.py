@@ -189,6 +189,50 @@ def test_adjoint_step_next_validates_without_launching(abi):
     L.lb_destroy(ctx)
 
 
+def test_struct_layouts_and_enums_match_the_header(abi, tmp_path):
+    """The ctypes structures and constants of the binding agree with
+    include/lb.h as a C compiler lays them out (sizeof, every field's
+    offset, every enum value the binding and lb.py use)."""
+    import subprocess
+
+    from paper_1609_01479_amd import lb as lbpy
+    structs = {"lb_params": abi.LbParams, "lb_sizes": abi.LbSizes, "lb_buffers": abi.LbBuffers}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lb.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    enums = {"LB_OK": abi.LB_OK, "LB_EINVAL": abi.LB_EINVAL, "LB_ESHAPE": abi.LB_ESHAPE,
+             "LB_EALIGN": abi.LB_EALIGN, "LB_EHIP": abi.LB_EHIP, "LB_ESTATE": abi.LB_ESTATE,
+             "LB_FP64": abi.LB_FP64, "LB_FP32_DEV": abi.LB_FP32_DEV,
+             "LB_KERNEL_FUSED": abi.LB_KERNEL_FUSED, "LB_KERNEL_TWO_PASS": abi.LB_KERNEL_TWO_PASS,
+             "LB_NVEL": abi.NVEL, "LB_ABI_VERSION": abi.lib().lb_abi_version(),
+             "LB_LAYOUT_ROWS": lbpy.LAYOUTS["rows"], "LB_LAYOUT_SOA": lbpy.LAYOUTS["soa"],
+             "LB_LAYOUT_AOS": lbpy.LAYOUTS["aos"], "LB_LAYOUT_AOSOA": lbpy.LAYOUTS["aosoa"],
+             "LB_COUPLING_STRESS": lbpy.COUPLINGS["stress"],
+             "LB_COUPLING_FORCE": lbpy.COUPLINGS["force"],
+             "LB_OP_LB": lbpy.ORDER_PARAMS["lb"], "LB_OP_FD": lbpy.ORDER_PARAMS["fd"]}
+    for name in enums:
+        lines.append(f'printf("enum {name} %d\\n", (int){name});')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in filter(None, out):
+        parts = line.split()
+        got[tuple(parts[:-1])] = int(parts[-1])
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+    for name, val in enums.items():
+        assert got[("enum", name)] == val, name
+
+
 def test_status_strings(abi):
     L = abi.lib()
     for code in range(6):
