@@ -125,13 +125,15 @@ def test_fd_single_pass_matches_two_pass(precision, shape, seg, coupling):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("coupling", ["stress", "force"])
 @pytest.mark.parametrize("layout,v", [("soa", 0), ("aos", 0), ("aosoa", 8)])
-def test_fd_layouts_bit_identical(layout, v):
+def test_fd_layouts_bit_identical(layout, v, coupling):
     shape = (6, 7, 16)
     phi0 = lbinputs.spinodal_phi0(shape, seed=8, amp=0.3)
     out = []
     for lay, vv in (("rows", 0), (layout, v)):
-        lb = make_lb(shape, order_param="fd", layout=lay, aosoa_len=vv, tau_f=0.9)
+        lb = make_lb(shape, order_param="fd", layout=lay, aosoa_len=vv, tau_f=0.9,
+                     coupling=coupling)
         lb.init_phi(phi0)
         lb.step(9)
         out.append(_gpu(lb))
@@ -345,4 +347,13 @@ def test_fd_force_fp32_storage():
 def test_fd_force_sampled_parity_droplet_256(precision, tol):
     shape = (256, 256, 256)
     _sampled_fd(shape, precision, _droplet(shape), 5, dict(tau_f=0.8, tau_g=1.3), tol,
+                coupling="force")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_dev", 2e-6)])
+def test_fd_force_sampled_parity_maximum_size(precision, tol):
+    """479^3, the largest accepted cube, ragged in every tile dimension of the
+    marching collision pass and of the flux pass."""
+    shape = (479, 479, 479)
+    _sampled_fd(shape, precision, _droplet(shape), 1, dict(tau_f=0.8, tau_g=1.3), tol, nsample=8,
                 coupling="force")
