@@ -375,6 +375,12 @@ def main():
     if "fp64" in out:
         out["fp64"]["roofline"]["frac_of_copy_probe"] = round(
             out["fp64"]["roofline"]["achieved"] / probe, 4)
+    # the same copy at the footprint of the FP32 step (read one time level,
+    # write another: 2 x 320/2 B per site)
+    probe_fp = copy_probe_gbps(160 * nsites, reps=10)
+    out["copy_probe_same_footprint_GBps"] = round(probe_fp, 1)
+    out["roofline"]["frac_of_copy_probe_same_footprint"] = round(
+        out["roofline"]["achieved"] / probe_fp, 4)
 
     if not args.no_adjoint:
         adj = {}
