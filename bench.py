@@ -264,6 +264,7 @@ def main():
     # FP32 storage (92 + 320), against the method's 608 and 320
     if args.force_steps > 0:
         out["force_coupling"] = {}
+        force_phi = {}
         for prec, moved, minimum in (("fp32_dev", 412, 320), ("fp64", 776, 608)):
             lb = LB(shape, precision=prec, coupling="force", device="cuda:0", **lay, **params)
             lb.init_phi(phi0)
@@ -278,8 +279,12 @@ def main():
                 "bytes_per_site": moved,
                 "effective_GBps": round(minimum * nsites / t / 1e9, 1),
                 "kernels": "k_phi + k_force_fused"}
+            force_phi[prec] = lb.phi().cpu().numpy()
             del lb
             torch.cuda.empty_cache()
+        out["force_coupling"]["phi_fp32_vs_fp64_max"] = float(
+            np.abs(force_phi["fp32_dev"] - force_phi["fp64"]).max())
+        del force_phi
 
     # finite-difference order parameter (a phi field, no g) on the same 256^3
     # droplet, single-pass kernel: f read and written once (FP64 304, FP32
