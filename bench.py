@@ -389,7 +389,10 @@ def main():
 
     if not args.no_adjoint:
         adj = {}
+        # the sqrt(T) checkpoint intervals of the two configurations, and the
+        # 64^3 one with every state kept (200 x 81 MB: no recomputation)
         for name, nn, T, k, prec in (("64^3_fp64_T200", 64, 200, 15, "fp64"),
+                                     ("64^3_fp64_T200_every_state", 64, 200, 1, "fp64"),
                                      ("128^3_fp32_T1000", 128, 1000, 32, "fp32_dev")):
             sh = (nn, nn, nn)
             ph0 = lbinputs.spinodal_phi0(sh)
