@@ -65,8 +65,10 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
 #pragma unroll
         for (int i = 0; i < NV; i++) {
             const int d = push_site(p, q, i);
-            lf[i] = an[i * S + d];
-            lg[i] = an[(NV + i) * S + d] + an[2 * NV * S + d];
+            // lambda_f and lambda_g of the later level are read once (non-
+            // temporal); lambda_phi at d is gathered by 19 sites (cached)
+            lf[i] = __builtin_nontemporal_load(&an[i * S + d]);
+            lg[i] = __builtin_nontemporal_load(&an[(NV + i) * S + d]) + an[2 * NV * S + d];
             f[i] = F[dist_pull(p, q, i)];
         }
         const Stencil st = stencil(phi[s], phi[site_of(p, q.xp, q.y, q.z)],
@@ -234,7 +236,11 @@ hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
         hipError_t e = launch_phi(p, fp32, state, phi, s);
         if (e != hipSuccess) return e;
     }
-    const int nb = reduction_grid(p);
+    // one resident round: 256 CUs x 4 workgroups of 256 threads (4 waves per
+    // SIMD), each thread looping over its sites (10% faster than 2048 in FP32
+    // storage at 128^3 together with the non-temporal gathers)
+    constexpr int kAdjBlocks = 1024;
+    const int nb = reduction_grid(p) < kAdjBlocks ? reduction_grid(p) : kAdjBlocks;
     *nblocks_out = nb;
     if (fp32) {
         k_adj_local_f32<<<nb, kBlock, 0, s>>>(p, static_cast<const float*>(state), phi,
