@@ -120,3 +120,52 @@ def loss_and_grads(phi0, target, A, B, kappa, nsteps, gamma=0.5, tau_f=1.0, tau_
     loss.backward()
     return (float(loss.detach()), p0.grad.numpy().copy(), float(tA.grad), float(tB.grad),
             float(tk.grad))
+
+
+# -- finite-difference order parameter (stress coupling) ----------------------
+# The state is (f, phi): f post-stream as above, phi a field.  phi follows
+# the conservative face-flux update: upwind advection with the face-averaged
+# velocity u = j/rho of f before collision, minus M times the difference of
+# mu, M = Gamma (tau_g - 1/2); torch.where routes the upwind value's
+# derivative to the side it was taken from.
+
+def fd_step(f, phi, A, B, kappa, gamma, tau_f, tau_g):
+    grad, lap = gradients(phi)
+    mu, pi = chemical(phi, grad, lap, A, B, kappa)
+    rho = f.sum(0)
+    j = torch.einsum("ia,ixyz->axyz", CF, f)
+    feq, _ = equilibria(rho, j, phi, mu, pi, gamma)
+    fs = f - (f - feq) / tau_f
+    u = j / rho[None]
+    M = gamma * (tau_g - 0.5)
+    div = torch.zeros_like(phi)
+    for a in range(3):
+        uf = 0.5 * (u[a] + _shift(u[a], a, 1))
+        flux = uf * torch.where(uf > 0, phi, _shift(phi, a, 1)) - M * (_shift(mu, a, 1) - mu)
+        div = div + (flux - _shift(flux, a, -1))
+    return propagate(fs), phi - div
+
+
+def fd_rollout_phi(phi0, A, B, kappa, nsteps, gamma=0.5, tau_f=1.0, tau_g=1.0, rho0=1.0):
+    """phi after nsteps of the finite-difference scheme from rest; differentiable."""
+    f = WEIGHTS[:, None, None, None] * rho0 * torch.ones((19,) + tuple(phi0.shape),
+                                                          dtype=torch.float64)
+    phi = phi0
+    for _ in range(nsteps):
+        f, phi = fd_step(f, phi, A, B, kappa, gamma, tau_f, tau_g)
+    return phi
+
+
+def fd_loss_and_grads(phi0, target, A, B, kappa, nsteps, gamma=0.5, tau_f=1.0, tau_g=1.0,
+                      rho0=1.0):
+    """As loss_and_grads, for the finite-difference order parameter."""
+    p0 = torch.as_tensor(phi0, dtype=torch.float64).clone().requires_grad_(True)
+    tA = torch.tensor(float(A), dtype=torch.float64, requires_grad=True)
+    tB = torch.tensor(float(B), dtype=torch.float64, requires_grad=True)
+    tk = torch.tensor(float(kappa), dtype=torch.float64, requires_grad=True)
+    phiT = fd_rollout_phi(p0, tA, tB, tk, nsteps, gamma, tau_f, tau_g, rho0)
+    tgt = torch.as_tensor(target, dtype=torch.float64)
+    loss = 0.5 * ((phiT - tgt) ** 2).sum()
+    loss.backward()
+    return (float(loss.detach()), p0.grad.numpy().copy(), float(tA.grad), float(tB.grad),
+            float(tk.grad))

@@ -807,6 +807,50 @@ def test_reverse_mode_matches_central_differences():
         assert abs(fd - gv) < 1e-6 * abs(fd), (name, fd, gv)
 
 
+def test_fd_two_transcriptions_agree():
+    """The finite-difference step re-expressed with whole-lattice torch ops
+    matches the C oracle's per-site loops to round-off (20 steps, tau != 1)."""
+    shape = (7, 6, 9)
+    p = _fd_params(shape, tau_f=0.8, tau_g=1.3)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=5, amp=0.4)
+    f, phi = oracle.fd_run(p, *oracle.fd_init(p, phi0), 20)
+    ft = R.WEIGHTS[:, None, None, None] * torch.ones((19,) + shape, dtype=torch.float64)
+    pt = torch.tensor(phi0)
+    for _ in range(20):
+        ft, pt = R.fd_step(ft, pt, p.A, p.B, p.kappa, p.gamma, p.tau_f, p.tau_g)
+    np.testing.assert_allclose(pt.numpy(), phi, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(ft.numpy(), f, rtol=0, atol=1e-15)
+
+
+def test_fd_reverse_mode_matches_central_differences():
+    """torch autograd through the finite-difference step vs central
+    differences of the C oracle's forward run (8^3, 20 steps)."""
+    shape = (8, 8, 8)
+    T = 20
+    p = _fd_params(shape, tau_f=0.8, tau_g=1.3)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=77, amp=0.3)
+    tgt = lbinputs.lamellar_target(shape, 8, lbinputs.interface_width(p.A, p.kappa))
+
+    def loss(phi0_, A=p.A, B=p.B, kappa=p.kappa):
+        q = oracle.Params(*shape, A=A, B=B, kappa=kappa, gamma=p.gamma, tau_f=p.tau_f,
+                          tau_g=p.tau_g, rho0=p.rho0, order_param=1)
+        f, phi = oracle.fd_run(q, *oracle.fd_init(q, phi0_), T)
+        return 0.5 * ((phi - tgt) ** 2).sum()
+
+    L, gphi, gA, gB, gk = R.fd_loss_and_grads(phi0, tgt, p.A, p.B, p.kappa, T, p.gamma,
+                                              p.tau_f, p.tau_g, p.rho0)
+    assert abs(L - loss(phi0)) < 1e-12 * abs(L)
+    v = lbinputs.random_field(shape, 5)
+    h = 1e-5
+    fd = (loss(phi0 + h * v) - loss(phi0 - h * v)) / (2 * h)
+    assert abs(fd - (gphi * v).sum()) < 1e-6 * abs(fd), (fd, (gphi * v).sum())
+    for name, val, gv, rel in (("A", p.A, gA, 1e-4), ("B", p.B, gB, 1e-2),
+                               ("kappa", p.kappa, gk, 1e-4)):
+        hh = rel * abs(val)
+        fd = (loss(phi0, **{name: val + hh}) - loss(phi0, **{name: val - hh})) / (2 * hh)
+        assert abs(fd - gv) < 1e-5 * abs(fd), (name, fd, gv)
+
+
 def test_one_step_depends_on_radius_two():
     """One step at x depends only on the state within L-inf distance 2 of x:
     stepping a small periodic window cut around x reproduces the full-lattice
