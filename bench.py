@@ -49,8 +49,8 @@ def step_bytes_per_site(elem_bytes: int) -> dict:
 # They hold only for the kernel sources they were taken on (the hash below);
 # after any change to those sources the traffic is reported as null.
 TRAFFIC_SOURCES = ("lb_kernels.hip", "lb_device.h", "lb_internal.h")
-TRAFFIC_SHA256 = "fe2d696d96cb36ede3c4de2f15023cb7807881155aedd7ac6455bf7feeeec474"
-TRAFFIC_BYTES = {"fp32_dev": 5483748494, "fp64": 10423956188}
+TRAFFIC_SHA256 = "695dea963a0628130304342f867a4b977e52020254249832cba221debccdc8ee"
+TRAFFIC_BYTES = {"fp32_dev": 5482819002, "fp64": 10425546136}
 
 
 def sources_sha256() -> str:
@@ -102,13 +102,13 @@ def time_steps(lb, steps: int, warmup: int, sums=None):
     return e0.elapsed_time(e1)
 
 
-def adjoint_ratio(shape, T, interval, precision, phi0, tgt, params):
+def adjoint_ratio(shape, T, interval, precision, phi0, tgt, params, order_param="lb"):
     """(forward ms for T plain steps, backward ms incl. recompute, grads)."""
     import torch
     from paper_1609_01479_amd import LB
     from paper_1609_01479_amd.rollout import rollout
     dev = torch.device("cuda:0")
-    lb = LB(shape, precision=precision, device=dev, **params)
+    lb = LB(shape, precision=precision, device=dev, order_param=order_param, **params)
     lb.init_phi(phi0)
     fwd_ms = time_steps(lb, T, 0)
     del lb
@@ -116,7 +116,8 @@ def adjoint_ratio(shape, T, interval, precision, phi0, tgt, params):
     th = [torch.tensor(params[k], dtype=torch.float64, device=dev, requires_grad=True)
           for k in ("A", "B", "kappa")]
     rest = {k: params[k] for k in ("gamma", "tau_f", "tau_g", "rho0")}
-    phiT = rollout(p0, *th, T, interval=interval, precision=precision, **rest)
+    phiT = rollout(p0, *th, T, interval=interval, precision=precision, order_param=order_param,
+                   **rest)
     loss = 0.5 * ((phiT - torch.tensor(tgt, device=dev)) ** 2).sum()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -389,20 +390,24 @@ def main():
 
     if not args.no_adjoint:
         adj = {}
-        # the sqrt(T) checkpoint intervals of the two configurations, and the
-        # 64^3 one with every state kept (200 x 81 MB: no recomputation)
-        for name, nn, T, k, prec in (("64^3_fp64_T200", 64, 200, 15, "fp64"),
-                                     ("64^3_fp64_T200_every_state", 64, 200, 1, "fp64"),
-                                     ("128^3_fp32_T1000", 128, 1000, 32, "fp32_dev")):
+        # the sqrt(T) checkpoint intervals of the two configurations, the
+        # 64^3 one with every state kept (200 x 81 MB: no recomputation), and
+        # the finite-difference scheme's two configurations
+        for name, nn, T, k, prec, op in (
+                ("64^3_fp64_T200", 64, 200, 15, "fp64", "lb"),
+                ("64^3_fp64_T200_every_state", 64, 200, 1, "fp64", "lb"),
+                ("128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "lb"),
+                ("fd_64^3_fp64_T200", 64, 200, 15, "fp64", "fd"),
+                ("fd_128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "fd")):
             sh = (nn, nn, nn)
             ph0 = lbinputs.spinodal_phi0(sh)
             tgt = lbinputs.lamellar_target(sh, 32, xi)
             log(f"adjoint {name}")
-            fwd, bwd, g = adjoint_ratio(sh, T, k, prec, ph0, tgt, params)
+            fwd, bwd, g = adjoint_ratio(sh, T, k, prec, ph0, tgt, params, op)
             entry = {"forward_ms": round(fwd, 2), "backward_ms": round(bwd, 2),
                      "adjoint_over_forward": round(bwd / fwd, 3), "interval": k}
             if prec == "fp32_dev":
-                _, _, g64 = adjoint_ratio(sh, T, k, "fp64", ph0, tgt, params)
+                _, _, g64 = adjoint_ratio(sh, T, k, "fp64", ph0, tgt, params, op)
                 entry["grad_rel_err_vs_fp64"] = {
                     "phi0_l2": float(np.linalg.norm(g[0] - g64[0]) / np.linalg.norm(g64[0])),
                     "A": g[1][0] / g64[1][0] - 1, "B": g[1][1] / g64[1][1] - 1,

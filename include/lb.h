@@ -111,8 +111,8 @@ typedef enum {
                      LB_COUPLING_FORCE (the paper's arrangement) f collides
                      with F = -div Pi and u = (j + F/2)/rho is also the
                      fluxes' velocity (that combination always runs the
-                     two-kernel path).  No adjoint; phi is FP64 in both
-                     precisions.                                             */
+                     two-kernel path).  The adjoint covers the stress
+                     coupling; phi is FP64 in both precisions.              */
 } lb_order_param;
 
 /* Memory layout of the f and g regions of a time level (opaque to callers,
@@ -250,11 +250,15 @@ lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
  *   lb_adjoint_seed(dL/dphi_T)  then, for t = T-1 .. 0,
  *   lb_adjoint_step(state_t)    (state_t as saved by lb_get_state at time t;
  *                                or lb_adjoint_step_next with level t+1 too)
- * and lb_adjoint_phi0 gives dL/dphi0.  Requires adj[0], adj[1], adj_scratch,
- * LB_COUPLING_STRESS and LB_OP_LB (LB_ESTATE otherwise). */
+ * and lb_adjoint_phi0 gives dL/dphi0.  Requires adj[0], adj[1], adj_scratch
+ * and LB_COUPLING_STRESS (LB_ESTATE otherwise); covers both order-parameter
+ * schemes.  With LB_OP_FD the level holds dL/df_i and dL/dphi (the g
+ * components of adj_bytes are unused), and the upwind choice of each face is
+ * held fixed: at a face velocity of exactly zero the derivative taken is
+ * that of the phi(x + e_a) branch, the one the forward step takes. */
 
-/* lambda_T from dphi_dev = dL/dphi_T (FP64, N): dL/dg_i = dphi for every i,
- * dL/df_i = 0. */
+/* lambda_T from dphi_dev = dL/dphi_T (FP64, N): dL/df_i = 0; LB_OP_LB:
+ * dL/dg_i = dphi for every i; LB_OP_FD: dL/dphi = dphi. */
 lb_status lb_adjoint_seed(lb_ctx *ctx, const double *dphi_dev);
 
 /* One reverse step: lambda_t = J(state_t)^T lambda_{t+1}, where J is the
@@ -267,7 +271,7 @@ lb_status lb_adjoint_step(lb_ctx *ctx, const void *state_t_dev, double *dtheta3_
  * (state_next_dev, as saved by lb_get_state or written by lb_step_from; may be
  * NULL).  In LB_FP32_DEV that level's reference field holds phi of state_t,
  * bit-identical to what the step would recompute, so the phi pass is skipped;
- * LB_FP64 ignores it.  The result is identical to lb_adjoint_step's only if
+ * LB_FP64 and LB_OP_FD (whose level holds phi) ignore it.  The result is identical to lb_adjoint_step's only if
  * state_next_dev really is that level.  LB_EINVAL if it equals state_t_dev,
  * LB_EALIGN if it is not 256-byte aligned. */
 lb_status lb_adjoint_step_next(lb_ctx *ctx, const void *state_t_dev, const void *state_next_dev,

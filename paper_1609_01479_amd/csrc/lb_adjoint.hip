@@ -200,7 +200,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_phi0(KParams p, const T* __restr
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
-    out[s] = double(adj[NV * p.stride + s]) + double(adj[2 * NV * p.stride + s]);
+    // LB scheme: dL/dphi0 = dL/dg_0 = lg_0 + lp (the rest state holds phi0
+    // in g_0); FD scheme: the phi field itself
+    const double lp = double(adj[2 * NV * p.stride + s]);
+    out[s] = p.fd ? lp : double(adj[NV * p.stride + s]) + lp;
 }
 
 int grid_for(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
@@ -258,6 +261,18 @@ hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
         k_adj_stencil<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const double*>(adj_scratch),
                                                              static_cast<double*>(adj_prev));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_stencil(const KParams& p, bool fp32, const void* adj_scratch,
+                              void* adj_prev, hipStream_t s)
+{
+    if (fp32)
+        k_adj_stencil<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const float*>(adj_scratch),
+                                                            static_cast<float*>(adj_prev));
+    else
+        k_adj_stencil<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const double*>(adj_scratch),
+                                                             static_cast<double*>(adj_prev));
     return hipGetLastError();
 }
 

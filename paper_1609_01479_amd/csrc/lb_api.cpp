@@ -348,8 +348,7 @@ lb_status lb_adjoint_seed(lb_ctx* ctx, const double* dphi_dev)
 {
     if (!ctx || !dphi_dev) return fail(LB_EINVAL, "ctx and dphi_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
-    if (ctx->kp.force || ctx->kp.fd)
-        return fail(LB_ESTATE, "the adjoint covers the stress coupling and LB order parameter only");
+    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
     ctx->adj_cur = 0;
     hipError_t e = lbk::launch_adj_seed(ctx->kp, ctx->fp32, ctx->b.adj[0], dphi_dev, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_seed");
@@ -365,8 +364,7 @@ lb_status lb_adjoint_step_next(lb_ctx* ctx, const void* state_t_dev, const void*
 {
     if (!ctx || !state_t_dev) return fail(LB_EINVAL, "ctx and state_t_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
-    if (ctx->kp.force || ctx->kp.fd)
-        return fail(LB_ESTATE, "the adjoint covers the stress coupling and LB order parameter only");
+    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
     if (!aligned(state_t_dev)) return fail(LB_EALIGN, "state_t_dev is not 256-byte aligned");
     if (state_next_dev && !aligned(state_next_dev))
         return fail(LB_EALIGN, "state_next_dev is not 256-byte aligned");
@@ -374,10 +372,16 @@ lb_status lb_adjoint_step_next(lb_ctx* ctx, const void* state_t_dev, const void*
         return fail(LB_EINVAL, "state_next_dev must be the level after state_t_dev");
     int nb = 0;
     double* part = static_cast<double*>(ctx->b.scratch);
-    hipError_t e = lbk::launch_adj_step(ctx->kp, ctx->fp32, state_t_dev, state_next_dev,
-                                        static_cast<double*>(ctx->b.phi),
-                                        ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
-                                        ctx->b.adj_scratch, part, &nb, ctx->stream);
+    // FD scheme: phi is part of the level, so state_next is not needed
+    hipError_t e =
+        ctx->kp.fd ? lbk::launch_fd_adj_step(ctx->kp, ctx->fp32, state_t_dev,
+                                             static_cast<double*>(ctx->b.phi),
+                                             ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
+                                             ctx->b.adj_scratch, part, &nb, ctx->stream)
+                   : lbk::launch_adj_step(ctx->kp, ctx->fp32, state_t_dev, state_next_dev,
+                                          static_cast<double*>(ctx->b.phi),
+                                          ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
+                                          ctx->b.adj_scratch, part, &nb, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "lb_adjoint_step");
     ctx->adj_cur = 1 - ctx->adj_cur;
     if (dtheta3_dev) {
@@ -391,8 +395,7 @@ lb_status lb_adjoint_phi0(lb_ctx* ctx, double* dphi0_dev)
 {
     if (!ctx || !dphi0_dev) return fail(LB_EINVAL, "ctx and dphi0_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
-    if (ctx->kp.force || ctx->kp.fd)
-        return fail(LB_ESTATE, "the adjoint covers the stress coupling and LB order parameter only");
+    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
     hipError_t e = lbk::launch_adj_phi0(ctx->kp, ctx->fp32, ctx->b.adj[ctx->adj_cur], dphi0_dev,
                                         ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_phi0");

@@ -667,6 +667,155 @@ __global__ __launch_bounds__(kBlock) void k_fd_import(KParams p, T* __restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// Reverse mode of one step (stress coupling).  The adjoint level keeps the
+// layout of the LB scheme's: lf[19] = dL/df_i(x) of the pulled populations,
+// lp = dL/dphi(x) (component 2*19); the g components are not used.
+//
+// k_fd_adj_prep stores rho and u = j/rho of level t (fields rho, u_x, u_y,
+// u_z of the storage type: u is formed in that type, with the forward's own
+// expressions, so the upwind choices below are the forward's).
+template <typename T, bool DEV>
+__global__ __launch_bounds__(kBlock) void k_fd_adj_prep(KParams p, const T* __restrict__ F,
+                                                        T* __restrict__ work)
+{
+    const int s = xcd_block() * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    const Geo q = geo_of(p, s);
+    T f[NV];
+#pragma unroll
+    for (int i = 0; i < NV; i++) f[i] = F[dist_pull(p, q, i)];
+    const Moments<T> m = moments_of<T, DEV>(p, f);
+    const T ri = T(1) / m.rho;
+    work[s] = m.rho;
+    work[p.stride + s] = m.jx * ri;
+    work[2 * p.stride + s] = m.jy * ri;
+    work[3 * p.stride + s] = m.jz * ri;
+}
+
+// Transposed step at x.  With lambda' the later level:
+//   flux update: dL/dJ_a(x + e_a/2) = lp'(x + e_a) - lp'(x) =: lJ_a(x), so
+//     lambda_mu(x) = M sum_a [lJ_a(x) - lJ_a(x - e_a)],
+//     lambda_u_a(x) = [lJ_a(x) phi_up(x + e_a/2) + lJ_a(x - e_a) phi_up(x - e_a/2)] / 2,
+//     and phi at the upwind site of each face takes u_f lJ;
+//   u = j/rho: lambda_f,i += (c_i - u) . lambda_u / rho;
+//   mu = A phi + B phi^3 - kappa lap: lambda_mu feeds the direct phi
+//     cotangent (A + 3B phi^2), the Laplacian's (-kappa) and d/d(A, B, kappa);
+//   the f collision: the LB scheme's transposed Jacobian without its g part
+//     (lambda* gathered from x + c_i, weighted moments S0, S1, S2).
+// Writes lf of the earlier level, the stencil cotangents a, b_x, b_y, b_z, c
+// (lp = a - sum_a D_a b_a + lap c follows in k_adj_stencil) and block
+// partials of d/d(A, B, kappa).  One resident round of workgroups, each
+// thread looping over its sites.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fd_adj_local(KParams p, const double* __restrict__ phi,
+                                                         const T* __restrict__ work,
+                                                         const T* __restrict__ an,
+                                                         T* __restrict__ ap, T* __restrict__ sc,
+                                                         double* __restrict__ partials)
+{
+    double dth[3] = {0.0, 0.0, 0.0};
+    const unsigned S = p.stride;
+    const T* __restrict__ lpn = an + size_t(2 * NV) * S;
+    const T* __restrict__ rhof = work;
+    const T* __restrict__ uf[3] = {work + S, work + 2 * size_t(S), work + 3 * size_t(S)};
+    const T A = T(p.A), B = T(p.B), kap = T(p.kappa), M = T(p.mobility);
+    const T omf = T(p.omega_f), cf = T(1) - omf;
+    const T h = T(4.5), third = T(1.0 / 3.0);
+    for (int s = xcd_block() * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
+        const Geo q = geo_of(p, s);
+        T lf[NV];
+#pragma unroll
+        for (int i = 0; i < NV; i++)
+            lf[i] = __builtin_nontemporal_load(&an[i * S + push_site(p, q, i)]);
+        const int nb[3][2] = {{site_of(p, q.xp, q.y, q.z), site_of(p, q.xm, q.y, q.z)},
+                              {site_of(p, q.x, q.yp, q.z), site_of(p, q.x, q.ym, q.z)},
+                              {site_of(p, q.x, q.y, q.zp), site_of(p, q.x, q.y, q.zm)}};
+        const double pc = phi[s];
+        double pn[3][2];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            pn[a][0] = phi[nb[a][0]];
+            pn[a][1] = phi[nb[a][1]];
+        }
+        const Stencil st = stencil(pc, pn[0][0], pn[0][1], pn[1][0], pn[1][1], pn[2][0], pn[2][1]);
+
+        // flux update, transposed (upwind choices in FP64, as the forward)
+        const T lc = lpn[s];
+        T lmu = T(0), adv = T(0), lu[3], u[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const double uc = double(uf[a][s]);
+            const double ufp = 0.5 * (uc + double(uf[a][nb[a][0]]));  // face x + e_a/2
+            const double ufm = 0.5 * (double(uf[a][nb[a][1]]) + uc);  // face x - e_a/2
+            const T ljp = lpn[nb[a][0]] - lc, ljm = lc - lpn[nb[a][1]];
+            const T upp = T(ufp > 0.0 ? pc : pn[a][0]);
+            const T upm = T(ufm > 0.0 ? pn[a][1] : pc);
+            lmu += ljp - ljm;
+            lu[a] = T(0.5) * (ljp * upp + ljm * upm);
+            if (ufp > 0.0) adv += T(ufp) * ljp;
+            if (!(ufm > 0.0)) adv += T(ufm) * ljm;
+            u[a] = T(uc);
+        }
+        lmu *= M;
+
+        // collision of f, transposed
+        T s0 = 0, s1x = 0, s1y = 0, s1z = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            const T wl = T(weight(i)) * omf * lf[i];
+            s0 += wl;
+            if (CX[i]) { s1x += CX[i] * wl; sxx += wl; }
+            if (CY[i]) { s1y += CY[i] * wl; syy += wl; }
+            if (CZ[i]) { s1z += CZ[i] * wl; szz += wl; }
+            if (CX[i] * CY[i]) sxy += CX[i] * CY[i] * wl;
+            if (CX[i] * CZ[i]) sxz += CX[i] * CZ[i] * wl;
+            if (CY[i] * CZ[i]) syz += CY[i] * CZ[i] * wl;
+        }
+        sxx -= third * s0; syy -= third * s0; szz -= third * s0;
+        const T ux = u[0], uy = u[1], uz = u[2];
+        const T ri = T(1) / rhof[s];
+        const T trs = sxx + syy + szz;
+        const T s2ux = sxx * ux + sxy * uy + sxz * uz;
+        const T s2uy = sxy * ux + syy * uy + syz * uz;
+        const T s2uz = sxz * ux + syz * uy + szz * uz;
+        const T s2uu = s2ux * ux + s2uy * uy + s2uz * uz;
+        const T gx = T(st.gx), gy = T(st.gy), gz = T(st.gz), lap = T(st.lap), phc = T(pc);
+        const T s2gx = sxx * gx + sxy * gy + sxz * gz;
+        const T s2gy = sxy * gx + syy * gy + syz * gz;
+        const T s2gz = sxz * gx + syz * gy + szz * gz;
+        const T gsg = s2gx * gx + s2gy * gy + s2gz * gz;
+
+        const T arho = s0 - h * s2uu - (lu[0] * ux + lu[1] * uy + lu[2] * uz) * ri;
+        const T ajx = T(3) * s1x + T(9) * s2ux + lu[0] * ri;
+        const T ajy = T(3) * s1y + T(9) * s2uy + lu[1] * ri;
+        const T ajz = T(3) * s1z + T(9) * s2uz + lu[2] * ri;
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            T v = cf * lf[i] + arho;
+            if (CX[i]) v += CX[i] * ajx;
+            if (CY[i]) v += CY[i] * ajy;
+            if (CZ[i]) v += CZ[i] * ajz;
+            __builtin_nontemporal_store(v, &ap[i * S + s]);
+        }
+        const T phi2 = phc * phc;
+        const T a_dir = lc + (A + T(3) * B * phi2) * lmu + adv
+                      + h * trs * (A * phc + T(3) * B * phi2 * phc - kap * lap);
+        const T hk = h * kap;
+        __builtin_nontemporal_store(a_dir, &sc[0 * S + s]);
+        __builtin_nontemporal_store(hk * (T(2) * s2gx - trs * gx), &sc[1 * S + s]);
+        __builtin_nontemporal_store(hk * (T(2) * s2gy - trs * gy), &sc[2 * S + s]);
+        __builtin_nontemporal_store(hk * (T(2) * s2gz - trs * gz), &sc[3 * S + s]);
+        __builtin_nontemporal_store(-kap * lmu - hk * phc * trs, &sc[4 * S + s]);
+        const double g2 = st.gx * st.gx + st.gy * st.gy + st.gz * st.gz;
+        const double dtrs = double(trs), dlm = double(lmu), dph = pc;
+        dth[0] += dph * dlm + 4.5 * dtrs * 0.5 * dph * dph;
+        dth[1] += dph * dph * dph * dlm + 4.5 * dtrs * 0.75 * dph * dph * dph * dph;
+        dth[2] += -st.lap * dlm + 4.5 * (dtrs * (-dph * st.lap - 0.5 * g2) + double(gsg));
+    }
+    block_partials<3>(dth, partials);
+}
+
 int fd_grid(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
 
 // Update-pass geometry: (y, z) tiles times x segments, about 2048
@@ -784,6 +933,32 @@ hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int va
         return launch_sums_final(partials, nparts, 5, sums_out, false, s);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_fd_adj_step(const KParams& p, bool fp32, const void* state, double* work,
+                              const void* adj_next, void* adj_prev, void* adj_scratch,
+                              double* partials, int* nblocks_out, hipStream_t s)
+{
+    // rho and u go to `work` in the storage type (FP32 mode: half its
+    // space); one resident round of workgroups (4 per CU), as the LB
+    // scheme's local adjoint kernel
+    constexpr int kAdjBlocks = 1024;
+    const int nb = fd_reduction_grid(p) < kAdjBlocks ? fd_reduction_grid(p) : kAdjBlocks;
+    *nblocks_out = nb;
+#define CALL                                                                                  \
+    {                                                                                         \
+        FdLvl<T> a = fd_level<T>(const_cast<void*>(state), p);                                \
+        T* w = reinterpret_cast<T*>(work);                                                    \
+        k_fd_adj_prep<T, DEV><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, w);                       \
+        k_fd_adj_local<T><<<nb, kBlock, 0, s>>>(p, a.phi, w, static_cast<const T*>(adj_next),  \
+                                                static_cast<T*>(adj_prev),                    \
+                                                static_cast<T*>(adj_scratch), partials);      \
+    }
+    LB_FD_DISPATCH(fp32, CALL);
+#undef CALL
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_adj_stencil(p, fp32, adj_scratch, adj_prev, s);
 }
 
 hipError_t launch_fd_moments(const KParams& p, bool fp32, const void* state, double* rho,

@@ -51,7 +51,7 @@ class LB:
         force -div Pi with the half-force velocity; no adjoint).
     order_param: "lb" (distribution g, default) or "fd" (a phi field with the
         finite-difference Cahn-Hilliard update and upwind advection, mobility
-        Gamma (tau_g - 1/2); either coupling; no adjoint, no g).
+        Gamma (tau_g - 1/2); either coupling, the adjoint with "stress"; no g).
     """
 
     def __init__(self, shape, *, A=-0.00625, B=0.00625, kappa=0.004, gamma=0.5, tau_f=1.0,

@@ -104,8 +104,8 @@ def test_force_coupling_sizes_and_no_adjoint(abi):
 def test_fd_order_parameter_sizes_and_calls_without_launching(abi, prec, e):
     """The finite-difference order parameter: a level is f then the FP64 phi
     field, 4 FP64 work fields (mu, u), partials for one block per 256 sites;
-    g-taking calls reject a g pointer and the reverse mode returns LB_ESTATE,
-    all before any HIP call."""
+    g-taking calls reject a g pointer, and the reverse mode of the force
+    coupling returns LB_ESTATE, all before any HIP call."""
     n = 40 * 40 * 40
     st, s = _query(abi, nx=40, ny=40, nz=40, order_param=1, precision=prec)
     assert st == abi.LB_OK
@@ -123,6 +123,9 @@ def test_fd_order_parameter_sizes_and_calls_without_launching(abi, prec, e):
     assert L.lb_export_dist(ctx, v, v) == abi.LB_EINVAL
     assert L.lb_import_dist(ctx, v, v) == abi.LB_EINVAL
     assert L.lb_import_dist(ctx, None, None) == abi.LB_EINVAL
+    L.lb_destroy(ctx)
+    p = _params(abi, order_param=1, precision=prec, coupling=1)
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
     assert L.lb_adjoint_seed(ctx, v) == abi.LB_ESTATE
     assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), None, None) == abi.LB_ESTATE
     assert L.lb_adjoint_phi0(ctx, v) == abi.LB_ESTATE
