@@ -171,13 +171,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_local_f64(
     adj_local_body<double, false>(p, F, phi, an, ap, sc, partials);
 }
 
-// lp(x) = a(x) - sum_a D_a b_a (x) + lap c (x)
+// lp(x) = a(x) - sum_a D_a b_a (x) + lap c (x).  With dtheta, workgroup 0
+// also adds the step's d/d(A, B, kappa) from the local kernel's nparts block
+// partials (instead of a launch of its own).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj_stencil(KParams p, const T* __restrict__ sc,
-                                                        T* __restrict__ ap)
+__device__ __forceinline__ void adj_stencil_site(const KParams& p, int s, const T* __restrict__ sc,
+                                                 T* __restrict__ ap)
 {
-    const int s = xcd_block() * kBlock + threadIdx.x;
-    if (s >= p.nsites) return;
     const Geo q = geo_of(p, s);
     const unsigned S = p.stride;
     const int xp = site_of(p, q.xp, q.y, q.z), xm = site_of(p, q.xm, q.y, q.z);
@@ -192,6 +192,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_stencil(KParams p, const T* __re
     const T divb = T(0.5) * (bx[xp] - bx[xm]) + T(0.5) * (by[yp] - by[ym]) + T(0.5) * (bz[zp] - bz[zm]);
     const T lapc = (c[xp] + c[xm] - T(2) * cc) + (c[yp] + c[ym] - T(2) * cc) + (c[zp] + c[zm] - T(2) * cc);
     ap[2 * NV * S + s] = a[s] - divb + lapc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_stencil(KParams p, const T* __restrict__ sc,
+                                                        T* __restrict__ ap,
+                                                        const double* __restrict__ partials,
+                                                        int nparts, double* __restrict__ dtheta)
+{
+    const int s = xcd_block() * kBlock + threadIdx.x;
+    if (s < p.nsites) adj_stencil_site<T>(p, s, sc, ap);
+    if (dtheta && blockIdx.x == 0) reduce_partials_block(partials, nparts, 3, dtheta, true);
 }
 
 template <typename T>
@@ -227,7 +238,7 @@ hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, const double*
 
 hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
                            const void* state_next, double* phi, const void* adj_next,
-                           void* adj_prev, void* adj_scratch, double* partials, int* nblocks_out,
+                           void* adj_prev, void* adj_scratch, double* partials, double* dtheta,
                            hipStream_t s)
 {
     if (fp32 && state_next) {
@@ -241,38 +252,38 @@ hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
     }
     // one resident round: 256 CUs x 4 workgroups of 256 threads (4 waves per
     // SIMD), each thread looping over its sites; the parameter reduction
-    // then reads half the partials of 2048 workgroups (rollout kernel
-    // trace at 128^3: k_sums_final 9.9 -> 5.5 us, k_adj_local unchanged)
+    // (workgroup 0 of the stencil kernel) then reads half the partials of
+    // 2048 workgroups (measured as a launch of its own at 128^3: 9.9 -> 5.5
+    // us, k_adj_local unchanged)
     constexpr int kAdjBlocks = 1024;
     const int nb = reduction_grid(p) < kAdjBlocks ? reduction_grid(p) : kAdjBlocks;
-    *nblocks_out = nb;
-    if (fp32) {
+    if (fp32)
         k_adj_local_f32<<<nb, kBlock, 0, s>>>(p, static_cast<const float*>(state), phi,
                                                        static_cast<const float*>(adj_next),
                                                        static_cast<float*>(adj_prev),
                                                        static_cast<float*>(adj_scratch), partials);
-        k_adj_stencil<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const float*>(adj_scratch),
-                                                            static_cast<float*>(adj_prev));
-    } else {
+    else
         k_adj_local_f64<<<nb, kBlock, 0, s>>>(p, static_cast<const double*>(state), phi,
                                                          static_cast<const double*>(adj_next),
                                                          static_cast<double*>(adj_prev),
                                                          static_cast<double*>(adj_scratch), partials);
-        k_adj_stencil<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const double*>(adj_scratch),
-                                                             static_cast<double*>(adj_prev));
-    }
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_adj_stencil(p, fp32, adj_scratch, adj_prev, partials, nb, dtheta, s);
 }
 
 hipError_t launch_adj_stencil(const KParams& p, bool fp32, const void* adj_scratch,
-                              void* adj_prev, hipStream_t s)
+                              void* adj_prev, const double* partials, int nparts, double* dtheta,
+                              hipStream_t s)
 {
     if (fp32)
         k_adj_stencil<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const float*>(adj_scratch),
-                                                            static_cast<float*>(adj_prev));
+                                                            static_cast<float*>(adj_prev), partials,
+                                                            nparts, dtheta);
     else
         k_adj_stencil<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const double*>(adj_scratch),
-                                                             static_cast<double*>(adj_prev));
+                                                             static_cast<double*>(adj_prev), partials,
+                                                             nparts, dtheta);
     return hipGetLastError();
 }
 

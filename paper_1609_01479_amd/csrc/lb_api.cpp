@@ -370,24 +370,19 @@ lb_status lb_adjoint_step_next(lb_ctx* ctx, const void* state_t_dev, const void*
         return fail(LB_EALIGN, "state_next_dev is not 256-byte aligned");
     if (state_next_dev == state_t_dev)
         return fail(LB_EINVAL, "state_next_dev must be the level after state_t_dev");
-    int nb = 0;
     double* part = static_cast<double*>(ctx->b.scratch);
     // FD scheme: phi is part of the level, so state_next is not needed
     hipError_t e =
         ctx->kp.fd ? lbk::launch_fd_adj_step(ctx->kp, ctx->fp32, state_t_dev,
                                              static_cast<double*>(ctx->b.phi),
                                              ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
-                                             ctx->b.adj_scratch, part, &nb, ctx->stream)
+                                             ctx->b.adj_scratch, part, dtheta3_dev, ctx->stream)
                    : lbk::launch_adj_step(ctx->kp, ctx->fp32, state_t_dev, state_next_dev,
                                           static_cast<double*>(ctx->b.phi),
                                           ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
-                                          ctx->b.adj_scratch, part, &nb, ctx->stream);
+                                          ctx->b.adj_scratch, part, dtheta3_dev, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "lb_adjoint_step");
     ctx->adj_cur = 1 - ctx->adj_cur;
-    if (dtheta3_dev) {
-        e = lbk::launch_sums_final(part, nb, 3, dtheta3_dev, true, ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "lb_adjoint_step (parameter sums)");
-    }
     return LB_OK;
 }
 

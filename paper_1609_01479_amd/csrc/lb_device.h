@@ -486,6 +486,40 @@ __device__ __forceinline__ void lds_barrier()
 // Block reduction of K FP64 values (fixed order): wavefront butterfly, then
 // the block's NB/64 waves as a pairwise tree.  Thread 0 writes component k to
 // out[k*gridDim.x + blockIdx.x].  Needs blockDim.x == NB.
+// Final reduction of `nblocks` block partials of `ncomp` (at most 5)
+// components, laid out as block_partials writes them, by one workgroup of
+// kBlock threads in a fixed order (strided per-thread sums, a wavefront
+// butterfly, then the four waves pairwise): out[k] = sum, or out[k] += sum.
+// Every thread of the workgroup must call it.
+__device__ __forceinline__ void reduce_partials_block(const double* __restrict__ partials,
+                                                      int nblocks, int ncomp,
+                                                      double* __restrict__ out, bool accumulate)
+{
+    static_assert(kBlock == 256, "four waves");
+    constexpr int KMAX = 5;
+    __shared__ double sm[KMAX][kBlock / 64];
+    double v[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; k++) {
+        v[k] = 0.0;
+        if (k < ncomp)
+            for (int j = threadIdx.x; j < nblocks; j += kBlock) v[k] += partials[k * nblocks + j];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < KMAX; k++) v[k] += __shfl_xor(v[k], off, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < KMAX; k++) sm[k][threadIdx.x >> 6] = v[k];
+    __syncthreads();
+    if (threadIdx.x < ncomp) {
+        const int k = threadIdx.x;
+        const double t = (sm[k][0] + sm[k][1]) + (sm[k][2] + sm[k][3]);
+        out[k] = accumulate ? out[k] + t : t;
+    }
+}
+
 template <int K, int NB = kBlock>
 __device__ __forceinline__ void block_partials(double (&v)[K], double* out)
 {

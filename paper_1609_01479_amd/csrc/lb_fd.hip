@@ -937,14 +937,13 @@ hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int va
 
 hipError_t launch_fd_adj_step(const KParams& p, bool fp32, const void* state, double* work,
                               const void* adj_next, void* adj_prev, void* adj_scratch,
-                              double* partials, int* nblocks_out, hipStream_t s)
+                              double* partials, double* dtheta, hipStream_t s)
 {
     // rho and u go to `work` in the storage type (FP32 mode: half its
     // space); one resident round of workgroups (4 per CU), as the LB
     // scheme's local adjoint kernel
     constexpr int kAdjBlocks = 1024;
     const int nb = fd_reduction_grid(p) < kAdjBlocks ? fd_reduction_grid(p) : kAdjBlocks;
-    *nblocks_out = nb;
 #define CALL                                                                                  \
     {                                                                                         \
         FdLvl<T> a = fd_level<T>(const_cast<void*>(state), p);                                \
@@ -958,7 +957,7 @@ hipError_t launch_fd_adj_step(const KParams& p, bool fp32, const void* state, do
 #undef CALL
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_adj_stencil(p, fp32, adj_scratch, adj_prev, s);
+    return launch_adj_stencil(p, fp32, adj_scratch, adj_prev, partials, nb, dtheta, s);
 }
 
 hipError_t launch_fd_moments(const KParams& p, bool fp32, const void* state, double* rho,

@@ -103,14 +103,18 @@ hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, const double*
                            hipStream_t s);
 // state_next (may be null): the level one step after `state`; in FP32 mode
 // its reference field is phi of `state`, so the phi pass is skipped.
+// dtheta (may be null): FP64[3] incremented by the step's d/d(A, B, kappa),
+// reduced from block partials in `partials` (3 * 1024 doubles).
 hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
                            const void* state_next, double* phi, const void* adj_next,
-                           void* adj_prev, void* adj_scratch, double* partials, int* nblocks_out,
+                           void* adj_prev, void* adj_scratch, double* partials, double* dtheta,
                            hipStream_t s);
 // lp of adj_prev from the stencil cotangents in adj_scratch (a, b_x, b_y,
-// b_z, c): lp = a - sum_a D_a b_a + lap c.
+// b_z, c): lp = a - sum_a D_a b_a + lap c; with dtheta, also
+// dtheta[k] += the sum of the nparts block partials of component k < 3.
 hipError_t launch_adj_stencil(const KParams& p, bool fp32, const void* adj_scratch,
-                              void* adj_prev, hipStream_t s);
+                              void* adj_prev, const double* partials, int nparts, double* dtheta,
+                              hipStream_t s);
 // dL/dphi0 from the level in `adj` (LB scheme: lg_0 + lp; FD scheme: lp).
 hipError_t launch_adj_phi0(const KParams& p, bool fp32, const void* adj, double* dphi0,
                            hipStream_t s);
@@ -129,12 +133,11 @@ hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int va
                           double* sums_out, hipStream_t s);
 // Reverse mode of one FD step (stress coupling): adj_prev = J(state)^T adj_next
 // in the adjoint-level layout (lf[19], unused g components, lp), with
-// `work` (4 FP64 fields) taking rho and u of `state`, adj_scratch the five
-// stencil cotangents, and `partials` 3 * *nblocks_out block partials of
-// d/d(A, B, kappa).
+// `work` (4 FP64 fields of space) taking rho and u of `state`, adj_scratch
+// the five stencil cotangents, and dtheta as for launch_adj_step.
 hipError_t launch_fd_adj_step(const KParams& p, bool fp32, const void* state, double* work,
                               const void* adj_next, void* adj_prev, void* adj_scratch,
-                              double* partials, int* nblocks_out, hipStream_t s);
+                              double* partials, double* dtheta, hipStream_t s);
 hipError_t launch_fd_moments(const KParams& p, bool fp32, const void* state, double* rho,
                              double* u, double* phi, double* partials, int* nblocks_out,
                              hipStream_t s);

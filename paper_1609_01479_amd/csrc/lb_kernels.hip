@@ -555,35 +555,13 @@ __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restri
     block_partials<5>(acc, partials);
 }
 
-// out[k] (+)= sum over nblocks partials of component k (k < ncomp <= 5); one
-// block, fixed order: strided per-thread sums, a wavefront butterfly, then
-// the 4 waves pairwise.
+// out[k] (+)= sum over nblocks partials of component k (k < ncomp <= 5), one
+// workgroup.
 __global__ __launch_bounds__(kBlock) void k_sums_final(const double* __restrict__ partials,
                                                        int nblocks, int ncomp,
                                                        double* __restrict__ out, int accumulate)
 {
-    constexpr int KMAX = 5;
-    __shared__ double sm[KMAX][kBlock / 64];
-    double v[KMAX];
-#pragma unroll
-    for (int k = 0; k < KMAX; k++) {
-        v[k] = 0.0;
-        if (k < ncomp)
-            for (int j = threadIdx.x; j < nblocks; j += kBlock) v[k] += partials[k * nblocks + j];
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int k = 0; k < KMAX; k++) v[k] += __shfl_xor(v[k], off, 64);
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int k = 0; k < KMAX; k++) sm[k][threadIdx.x >> 6] = v[k];
-    __syncthreads();
-    if (threadIdx.x < ncomp) {
-        const int k = threadIdx.x;
-        const double t = (sm[k][0] + sm[k][1]) + (sm[k][2] + sm[k][3]);
-        out[k] = accumulate ? out[k] + t : t;
-    }
+    reduce_partials_block(partials, nblocks, ncomp, out, accumulate != 0);
 }
 
 template <typename T, bool DEV, bool REF>
