@@ -89,6 +89,43 @@ def step(f, g, A, B, kappa, gamma, tau_f, tau_g):
     return propagate(fs), propagate(gs)
 
 
+# -- force coupling: F = -div Pi by central differences, Guo forcing ---------
+# f^eq keeps only the ideal part (Pi leaves the equilibrium), both equilibria
+# take u = (j + F/2)/rho, and the source (1 - 1/(2 tau_f)) w_i
+# [3(c_i - u) + 9 (c_i.u) c_i].F adds F to each site's momentum.
+
+def body_force(pi):
+    """F_a = -sum_b D_b Pi_ab, shape (3, nx, ny, nz)."""
+    return torch.stack([-sum(0.5 * (_shift(pi[a, b], b, 1) - _shift(pi[a, b], b, -1))
+                             for b in range(3)) for a in range(3)])
+
+
+def _collide_f_force(f, rho, j, F, phi, mu, gamma, tau_f):
+    """(f*, g^eq, u) of the forcing collision; g^eq uses the same u."""
+    jh = j + 0.5 * F
+    feq, geq = equilibria(rho, jh, phi, mu, torch.zeros((3, 3) + tuple(rho.shape),
+                                                        dtype=rho.dtype), gamma)
+    u = jh / rho[None]
+    cu = torch.einsum("ia,axyz->ixyz", CF, u)
+    cF = torch.einsum("ia,axyz->ixyz", CF, F)
+    uF = (u * F).sum(0)
+    src = (1.0 - 0.5 / tau_f) * WEIGHTS[:, None, None, None] * (3.0 * (cF - uF[None])
+                                                               + 9.0 * cu * cF)
+    return f - (f - feq) / tau_f + src, geq, u
+
+
+def step_force(f, g, A, B, kappa, gamma, tau_f, tau_g):
+    phi = g.sum(0)
+    grad, lap = gradients(phi)
+    mu, pi = chemical(phi, grad, lap, A, B, kappa)
+    F = body_force(pi)
+    rho = f.sum(0)
+    j = torch.einsum("ia,ixyz->axyz", CF, f)
+    fs, geq, _ = _collide_f_force(f, rho, j, F, phi, mu, gamma, tau_f)
+    gs = g - (g - geq) / tau_g
+    return propagate(fs), propagate(gs)
+
+
 def initial_state(phi0, rho0):
     shape = phi0.shape
     f = WEIGHTS[:, None, None, None] * rho0 * torch.ones((19,) + tuple(shape), dtype=torch.float64)
@@ -96,16 +133,18 @@ def initial_state(phi0, rho0):
     return f, g
 
 
-def rollout_phi(phi0, A, B, kappa, nsteps, gamma=0.5, tau_f=1.0, tau_g=1.0, rho0=1.0):
+def rollout_phi(phi0, A, B, kappa, nsteps, gamma=0.5, tau_f=1.0, tau_g=1.0, rho0=1.0,
+                coupling="stress"):
     """phi after nsteps from the standard initial state; differentiable."""
     f, g = initial_state(phi0, rho0)
+    stepper = step_force if coupling == "force" else step
     for _ in range(nsteps):
-        f, g = step(f, g, A, B, kappa, gamma, tau_f, tau_g)
+        f, g = stepper(f, g, A, B, kappa, gamma, tau_f, tau_g)
     return g.sum(0)
 
 
 def loss_and_grads(phi0, target, A, B, kappa, nsteps, gamma=0.5, tau_f=1.0, tau_g=1.0,
-                   rho0=1.0):
+                   rho0=1.0, coupling="stress"):
     """L = 1/2 sum_x (phi_T - phi*)^2 and its gradients (dphi0, dA, dB, dkappa).
 
     phi0, target: float64 numpy or tensors of shape (nx, ny, nz).
@@ -114,7 +153,7 @@ def loss_and_grads(phi0, target, A, B, kappa, nsteps, gamma=0.5, tau_f=1.0, tau_
     tA = torch.tensor(float(A), dtype=torch.float64, requires_grad=True)
     tB = torch.tensor(float(B), dtype=torch.float64, requires_grad=True)
     tk = torch.tensor(float(kappa), dtype=torch.float64, requires_grad=True)
-    phiT = rollout_phi(p0, tA, tB, tk, nsteps, gamma, tau_f, tau_g, rho0)
+    phiT = rollout_phi(p0, tA, tB, tk, nsteps, gamma, tau_f, tau_g, rho0, coupling)
     tgt = torch.as_tensor(target, dtype=torch.float64)
     loss = 0.5 * ((phiT - tgt) ** 2).sum()
     loss.backward()
@@ -129,14 +168,17 @@ def loss_and_grads(phi0, target, A, B, kappa, nsteps, gamma=0.5, tau_f=1.0, tau_
 # mu, M = Gamma (tau_g - 1/2); torch.where routes the upwind value's
 # derivative to the side it was taken from.
 
-def fd_step(f, phi, A, B, kappa, gamma, tau_f, tau_g):
+def fd_step(f, phi, A, B, kappa, gamma, tau_f, tau_g, coupling="stress"):
     grad, lap = gradients(phi)
     mu, pi = chemical(phi, grad, lap, A, B, kappa)
     rho = f.sum(0)
     j = torch.einsum("ia,ixyz->axyz", CF, f)
-    feq, _ = equilibria(rho, j, phi, mu, pi, gamma)
-    fs = f - (f - feq) / tau_f
-    u = j / rho[None]
+    if coupling == "force":
+        fs, _, u = _collide_f_force(f, rho, j, body_force(pi), phi, mu, gamma, tau_f)
+    else:
+        feq, _ = equilibria(rho, j, phi, mu, pi, gamma)
+        fs = f - (f - feq) / tau_f
+        u = j / rho[None]
     M = gamma * (tau_g - 0.5)
     div = torch.zeros_like(phi)
     for a in range(3):
@@ -146,24 +188,25 @@ def fd_step(f, phi, A, B, kappa, gamma, tau_f, tau_g):
     return propagate(fs), phi - div
 
 
-def fd_rollout_phi(phi0, A, B, kappa, nsteps, gamma=0.5, tau_f=1.0, tau_g=1.0, rho0=1.0):
+def fd_rollout_phi(phi0, A, B, kappa, nsteps, gamma=0.5, tau_f=1.0, tau_g=1.0, rho0=1.0,
+                   coupling="stress"):
     """phi after nsteps of the finite-difference scheme from rest; differentiable."""
     f = WEIGHTS[:, None, None, None] * rho0 * torch.ones((19,) + tuple(phi0.shape),
                                                           dtype=torch.float64)
     phi = phi0
     for _ in range(nsteps):
-        f, phi = fd_step(f, phi, A, B, kappa, gamma, tau_f, tau_g)
+        f, phi = fd_step(f, phi, A, B, kappa, gamma, tau_f, tau_g, coupling)
     return phi
 
 
 def fd_loss_and_grads(phi0, target, A, B, kappa, nsteps, gamma=0.5, tau_f=1.0, tau_g=1.0,
-                      rho0=1.0):
+                      rho0=1.0, coupling="stress"):
     """As loss_and_grads, for the finite-difference order parameter."""
     p0 = torch.as_tensor(phi0, dtype=torch.float64).clone().requires_grad_(True)
     tA = torch.tensor(float(A), dtype=torch.float64, requires_grad=True)
     tB = torch.tensor(float(B), dtype=torch.float64, requires_grad=True)
     tk = torch.tensor(float(kappa), dtype=torch.float64, requires_grad=True)
-    phiT = fd_rollout_phi(p0, tA, tB, tk, nsteps, gamma, tau_f, tau_g, rho0)
+    phiT = fd_rollout_phi(p0, tA, tB, tk, nsteps, gamma, tau_f, tau_g, rho0, coupling)
     tgt = torch.as_tensor(target, dtype=torch.float64)
     loss = 0.5 * ((phiT - tgt) ** 2).sum()
     loss.backward()
