@@ -102,13 +102,15 @@ def time_steps(lb, steps: int, warmup: int, sums=None):
     return e0.elapsed_time(e1)
 
 
-def adjoint_ratio(shape, T, interval, precision, phi0, tgt, params, order_param="lb"):
+def adjoint_ratio(shape, T, interval, precision, phi0, tgt, params, order_param="lb",
+                  coupling="stress"):
     """(forward ms for T plain steps, backward ms incl. recompute, grads)."""
     import torch
     from paper_1609_01479_amd import LB
     from paper_1609_01479_amd.rollout import rollout
     dev = torch.device("cuda:0")
-    lb = LB(shape, precision=precision, device=dev, order_param=order_param, **params)
+    lb = LB(shape, precision=precision, device=dev, order_param=order_param, coupling=coupling,
+            **params)
     lb.init_phi(phi0)
     fwd_ms = time_steps(lb, T, 0)
     del lb
@@ -117,7 +119,7 @@ def adjoint_ratio(shape, T, interval, precision, phi0, tgt, params, order_param=
           for k in ("A", "B", "kappa")]
     rest = {k: params[k] for k in ("gamma", "tau_f", "tau_g", "rho0")}
     phiT = rollout(p0, *th, T, interval=interval, precision=precision, order_param=order_param,
-                   **rest)
+                   coupling=coupling, **rest)
     loss = 0.5 * ((phiT - torch.tensor(tgt, device=dev)) ** 2).sum()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -392,22 +394,26 @@ def main():
         adj = {}
         # the sqrt(T) checkpoint intervals of the two configurations, the
         # 64^3 one with every state kept (200 x 81 MB: no recomputation), and
-        # the finite-difference scheme's two configurations
-        for name, nn, T, k, prec, op in (
-                ("64^3_fp64_T200", 64, 200, 15, "fp64", "lb"),
-                ("64^3_fp64_T200_every_state", 64, 200, 1, "fp64", "lb"),
-                ("128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "lb"),
-                ("fd_64^3_fp64_T200", 64, 200, 15, "fp64", "fd"),
-                ("fd_128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "fd")):
+        # the same two configurations for the finite-difference scheme and
+        # for the force coupling (the larger one for both together)
+        for name, nn, T, k, prec, op, cp in (
+                ("64^3_fp64_T200", 64, 200, 15, "fp64", "lb", "stress"),
+                ("64^3_fp64_T200_every_state", 64, 200, 1, "fp64", "lb", "stress"),
+                ("128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "lb", "stress"),
+                ("fd_64^3_fp64_T200", 64, 200, 15, "fp64", "fd", "stress"),
+                ("fd_128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "fd", "stress"),
+                ("force_64^3_fp64_T200", 64, 200, 15, "fp64", "lb", "force"),
+                ("force_128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "lb", "force"),
+                ("fd_force_128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "fd", "force")):
             sh = (nn, nn, nn)
             ph0 = lbinputs.spinodal_phi0(sh)
             tgt = lbinputs.lamellar_target(sh, 32, xi)
             log(f"adjoint {name}")
-            fwd, bwd, g = adjoint_ratio(sh, T, k, prec, ph0, tgt, params, op)
+            fwd, bwd, g = adjoint_ratio(sh, T, k, prec, ph0, tgt, params, op, cp)
             entry = {"forward_ms": round(fwd, 2), "backward_ms": round(bwd, 2),
                      "adjoint_over_forward": round(bwd / fwd, 3), "interval": k}
             if prec == "fp32_dev":
-                _, _, g64 = adjoint_ratio(sh, T, k, "fp64", ph0, tgt, params, op)
+                _, _, g64 = adjoint_ratio(sh, T, k, "fp64", ph0, tgt, params, op, cp)
                 entry["grad_rel_err_vs_fp64"] = {
                     "phi0_l2": float(np.linalg.norm(g[0] - g64[0]) / np.linalg.norm(g64[0])),
                     "A": g[1][0] / g64[1][0] - 1, "B": g[1][1] / g64[1][1] - 1,

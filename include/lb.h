@@ -89,8 +89,8 @@ typedef enum {
     LB_COUPLING_STRESS = 0, /* Pi in f^eq's second moment (default)         */
     LB_COUPLING_FORCE = 1   /* body force F = -div Pi (central differences)
                                with the half-force velocity u = (j + F/2)/rho
-                               and Guo's forcing term; no adjoint; runs a phi
-                               pass and a collision pass                    */
+                               and Guo's forcing term; runs a phi pass and
+                               a collision pass                             */
 } lb_coupling;
 
 /* How the order parameter evolves: */
@@ -111,8 +111,8 @@ typedef enum {
                      LB_COUPLING_FORCE (the paper's arrangement) f collides
                      with F = -div Pi and u = (j + F/2)/rho is also the
                      fluxes' velocity (that combination always runs the
-                     two-kernel path).  The adjoint covers the stress
-                     coupling; phi is FP64 in both precisions.              */
+                     two-kernel path).  phi is FP64 in both
+                     precisions.                                             */
 } lb_order_param;
 
 /* Memory layout of the f and g regions of a time level (opaque to callers,
@@ -157,7 +157,8 @@ typedef struct {
                                  LB_OP_FD: mu, u_x, u_y, u_z                           */
     size_t scratch_bytes;     /* reduction partials                                     */
     size_t adj_bytes;         /* one adjoint time level (lambda_f, lambda_g, lambda_phi) */
-    size_t adj_scratch_bytes; /* adjoint stencil cotangents and parameter partials      */
+    size_t adj_scratch_bytes; /* adjoint stencil cotangents (5 fields; 8 with the force
+                                 coupling, which adds dL/dF)                         */
 } lb_sizes;
 
 /* Caller-owned device memory.  state[0..1] are the two time levels the step
@@ -250,12 +251,13 @@ lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
  *   lb_adjoint_seed(dL/dphi_T)  then, for t = T-1 .. 0,
  *   lb_adjoint_step(state_t)    (state_t as saved by lb_get_state at time t;
  *                                or lb_adjoint_step_next with level t+1 too)
- * and lb_adjoint_phi0 gives dL/dphi0.  Requires adj[0], adj[1], adj_scratch
- * and LB_COUPLING_STRESS (LB_ESTATE otherwise); covers both order-parameter
- * schemes.  With LB_OP_FD the level holds dL/df_i and dL/dphi (the g
- * components of adj_bytes are unused), and the upwind choice of each face is
- * held fixed: at a face velocity of exactly zero the derivative taken is
- * that of the phi(x + e_a) branch, the one the forward step takes. */
+ * and lb_adjoint_phi0 gives dL/dphi0.  Requires adj[0], adj[1] and
+ * adj_scratch (LB_ESTATE otherwise); covers both couplings and both
+ * order-parameter schemes.  With LB_OP_FD the level holds dL/df_i and
+ * dL/dphi (the g components of adj_bytes are unused), and the upwind choice
+ * of each face is held fixed: at a face velocity of exactly zero the
+ * derivative taken is that of the phi(x + e_a) branch, the one the forward
+ * step takes. */
 
 /* lambda_T from dphi_dev = dL/dphi_T (FP64, N): dL/df_i = 0; LB_OP_LB:
  * dL/dg_i = dphi for every i; LB_OP_FD: dL/dphi = dphi. */

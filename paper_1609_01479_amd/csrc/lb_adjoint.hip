@@ -171,9 +171,203 @@ __global__ __launch_bounds__(kBlock) void k_adj_local_f64(
     adj_local_body<double, false>(p, F, phi, an, ap, sc, partials);
 }
 
+// Force coupling (u = (j + F/2)/rho in both equilibria, f^eq = w rho (1 +
+// 3 c.u + 9/2 (c.u)^2 - 3/2 u^2), Guo's source S = (1 - omega_f/2) w
+// [3(c - u) + 9 (c.u) c].F, F = -div Pi).  With M0, M1, M2 the moments
+// sum w L, sum w L c, sum w L c c of L = lambda*_f (full M2), and the g
+// part's T moments as above:
+//   dPhi/du   = omega_f rho (3 M1 + 9 M2 u - 3 u M0) + (1 - omega_f/2)
+//               (9 M2 F - 3 F M0) + 3 phi T1 + 9 phi T2 u
+//   dPhi/drho = omega_f (M0 + 3 M1.u + 9/2 u.M2.u - 3/2 u^2 M0) - dPhi/du . u / rho
+//   dPhi/dj   = dPhi/du / rho
+//   dPhi/dF   = (1 - omega_f/2) (3 M1 - 3 u M0 + 9 M2 u) + dPhi/du / (2 rho)
+// and the g part's phi, mu terms as in the stress coupling without S2.
+// dPhi/dF (three fields after the five stencil cotangents) reaches phi
+// through Pi at the face neighbours: k_adj_force_pi.
+template <typename T, bool DEV>
+__device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* __restrict__ F,
+                                                     const double* __restrict__ phi,
+                                                     const T* __restrict__ an, T* __restrict__ ap,
+                                                     T* __restrict__ sc,
+                                                     double* __restrict__ partials)
+{
+    double dth[3] = {0.0, 0.0, 0.0};
+    const unsigned S = p.stride;
+    const T A = T(p.A), B = T(p.B), kap = T(p.kappa), gam = T(p.gamma);
+    const T omf = T(p.omega_f), omg = T(p.omega_g), pref = T(1) - T(0.5) * omf;
+    const T h = T(4.5), third = T(1.0 / 3.0);
+    for (int s = xcd_block() * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
+        const Geo q = geo_of(p, s);
+        T lf[NV], lg[NV], f[NV];
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            const int d = push_site(p, q, i);
+            lf[i] = __builtin_nontemporal_load(&an[i * S + d]);
+            lg[i] = __builtin_nontemporal_load(&an[(NV + i) * S + d]) + an[2 * NV * S + d];
+            f[i] = F[dist_pull(p, q, i)];
+        }
+        const Stencil st = stencil(phi[s], phi[site_of(p, q.xp, q.y, q.z)],
+                                   phi[site_of(p, q.xm, q.y, q.z)],
+                                   phi[site_of(p, q.x, q.yp, q.z)],
+                                   phi[site_of(p, q.x, q.ym, q.z)],
+                                   phi[site_of(p, q.x, q.y, q.zp)],
+                                   phi[site_of(p, q.x, q.y, q.zm)]);
+        double Fd[3];
+        force_from_phi(p, q, phi, Fd);
+        const Moments<T> m = moments_of<T, DEV>(p, f);
+        const T rho = m.rho, ri = T(1) / rho;
+        const T Fx = T(Fd[0]), Fy = T(Fd[1]), Fz = T(Fd[2]);
+        const T ux = (m.jx + T(0.5) * Fx) * ri, uy = (m.jy + T(0.5) * Fy) * ri,
+                uz = (m.jz + T(0.5) * Fz) * ri;
+        const T phi_c = T(st.phi);
+
+        T m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
+        T t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            const T wl = T(weight(i)) * lf[i];
+            const T wg = T(weight(i)) * omg * lg[i];
+            m0 += wl;
+            t0 += wg;
+            if (CX[i]) { m1x += CX[i] * wl; t1x += CX[i] * wg; mxx += wl; txx += wg; }
+            if (CY[i]) { m1y += CY[i] * wl; t1y += CY[i] * wg; myy += wl; tyy += wg; }
+            if (CZ[i]) { m1z += CZ[i] * wl; t1z += CZ[i] * wg; mzz += wl; tzz += wg; }
+            if (CX[i] * CY[i]) { mxy += CX[i] * CY[i] * wl; txy += CX[i] * CY[i] * wg; }
+            if (CX[i] * CZ[i]) { mxz += CX[i] * CZ[i] * wl; txz += CX[i] * CZ[i] * wg; }
+            if (CY[i] * CZ[i]) { myz += CY[i] * CZ[i] * wl; tyz += CY[i] * CZ[i] * wg; }
+        }
+        txx -= third * t0; tyy -= third * t0; tzz -= third * t0;
+        const T trt = txx + tyy + tzz;
+        const T t2ux = txx * ux + txy * uy + txz * uz;
+        const T t2uy = txy * ux + tyy * uy + tyz * uz;
+        const T t2uz = txz * ux + tyz * uy + tzz * uz;
+        const T t2uu = t2ux * ux + t2uy * uy + t2uz * uz;
+        const T t1u = t1x * ux + t1y * uy + t1z * uz;
+        const T m2ux = mxx * ux + mxy * uy + mxz * uz;
+        const T m2uy = mxy * ux + myy * uy + myz * uz;
+        const T m2uz = mxz * ux + myz * uy + mzz * uz;
+        const T m2Fx = mxx * Fx + mxy * Fy + mxz * Fz;
+        const T m2Fy = mxy * Fx + myy * Fy + myz * Fz;
+        const T m2Fz = mxz * Fx + myz * Fy + mzz * Fz;
+        const T uu = ux * ux + uy * uy + uz * uz;
+        const T orho = omf * rho;
+        const T lux = orho * (T(3) * m1x + T(9) * m2ux - T(3) * ux * m0)
+                    + pref * (T(9) * m2Fx - T(3) * Fx * m0) + phi_c * (T(3) * t1x + T(9) * t2ux);
+        const T luy = orho * (T(3) * m1y + T(9) * m2uy - T(3) * uy * m0)
+                    + pref * (T(9) * m2Fy - T(3) * Fy * m0) + phi_c * (T(3) * t1y + T(9) * t2uy);
+        const T luz = orho * (T(3) * m1z + T(9) * m2uz - T(3) * uz * m0)
+                    + pref * (T(9) * m2Fz - T(3) * Fz * m0) + phi_c * (T(3) * t1z + T(9) * t2uz);
+        const T arho = omf * (m0 + T(3) * (m1x * ux + m1y * uy + m1z * uz)
+                              + h * (m2ux * ux + m2uy * uy + m2uz * uz) - T(1.5) * uu * m0)
+                     - (lux * ux + luy * uy + luz * uz) * ri;
+        const T ajx = lux * ri, ajy = luy * ri, ajz = luz * ri;
+        const T hr = T(0.5) * ri;
+        const T lFx = pref * (T(3) * m1x - T(3) * ux * m0 + T(9) * m2ux) + hr * lux;
+        const T lFy = pref * (T(3) * m1y - T(3) * uy * m0 + T(9) * m2uy) + hr * luy;
+        const T lFz = pref * (T(3) * m1z - T(3) * uz * m0 + T(9) * m2uz) + hr * luz;
+        const T cf = T(1) - omf, cg = T(1) - omg;
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            T v = cf * lf[i] + arho;
+            if (CX[i]) v += CX[i] * ajx;
+            if (CY[i]) v += CY[i] * ajy;
+            if (CZ[i]) v += CZ[i] * ajz;
+            __builtin_nontemporal_store(v, &ap[i * S + s]);
+            __builtin_nontemporal_store(cg * lg[i], &ap[(NV + i) * S + s]);
+        }
+        const T phi2 = phi_c * phi_c;
+        const T a_dir = t0 + T(3) * t1u + h * (gam * (A + T(3) * B * phi2) - third) * trt + h * t2uu;
+        sc[0 * S + s] = a_dir;
+        sc[1 * S + s] = T(0);
+        sc[2 * S + s] = T(0);
+        sc[3 * S + s] = T(0);
+        sc[4 * S + s] = -h * kap * gam * trt;
+        sc[5 * S + s] = lFx;
+        sc[6 * S + s] = lFy;
+        sc[7 * S + s] = lFz;
+        const double dtrt = double(trt), dph = st.phi;
+        dth[0] += 4.5 * p.gamma * dph * dtrt;
+        dth[1] += 4.5 * p.gamma * dph * dph * dph * dtrt;
+        dth[2] += -4.5 * p.gamma * st.lap * dtrt;
+    }
+    block_partials<3>(dth, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_local_force_f32(
+    KParams p, const float* __restrict__ F, const double* __restrict__ phi,
+    const float* __restrict__ an, float* __restrict__ ap, float* __restrict__ sc,
+    double* __restrict__ partials)
+{
+    adj_local_force_body<float, true>(p, F, phi, an, ap, sc, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_local_force_f64(
+    KParams p, const double* __restrict__ F, const double* __restrict__ phi,
+    const double* __restrict__ an, double* __restrict__ ap, double* __restrict__ sc,
+    double* __restrict__ partials)
+{
+    adj_local_force_body<double, false>(p, F, phi, an, ap, sc, partials);
+}
+
+// F_a(x) = -sum_b [Pi_ab(x + e_b) - Pi_ab(x - e_b)]/2 transposed: Pi(y) takes
+// L = (K + K^T)/2, K_ab(y) = [lambda_F,a(y + e_b) - lambda_F,a(y - e_b)]/2,
+// and Pi_ab = iso delta_ab + kappa d_a phi d_b phi (iso = A/2 phi^2 +
+// 3B/4 phi^4 - kappa phi lap - kappa/2 |grad|^2) passes it on to the
+// stencil cotangents at y:
+//   a += trL (A phi + 3B phi^3 - kappa lap),  b += kappa (2 L grad - trL grad),
+//   c += -kappa phi trL,
+// and d/d(A, B, kappa) += trL (phi^2/2, 3 phi^4/4, -phi lap - |grad|^2/2)
+// + (0, 0, grad.L.grad).  Each site updates only its own cotangents.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_force_pi(KParams p, const double* __restrict__ phi,
+                                                         T* __restrict__ sc,
+                                                         double* __restrict__ partials)
+{
+    double dth[3] = {0.0, 0.0, 0.0};
+    const unsigned S = p.stride;
+    const T* __restrict__ lF[3] = {sc + 5 * size_t(S), sc + 6 * size_t(S), sc + 7 * size_t(S)};
+    const T A = T(p.A), B = T(p.B), kap = T(p.kappa);
+    for (int s = xcd_block() * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
+        const Geo q = geo_of(p, s);
+        const int nb[3][2] = {{site_of(p, q.xp, q.y, q.z), site_of(p, q.xm, q.y, q.z)},
+                              {site_of(p, q.x, q.yp, q.z), site_of(p, q.x, q.ym, q.z)},
+                              {site_of(p, q.x, q.y, q.zp), site_of(p, q.x, q.y, q.zm)}};
+        T K[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) K[a][b] = T(0.5) * (lF[a][nb[b][0]] - lF[a][nb[b][1]]);
+        const T Lxx = K[0][0], Lyy = K[1][1], Lzz = K[2][2];
+        const T Lxy = T(0.5) * (K[0][1] + K[1][0]);
+        const T Lxz = T(0.5) * (K[0][2] + K[2][0]);
+        const T Lyz = T(0.5) * (K[1][2] + K[2][1]);
+        const Stencil st = stencil(phi[s], phi[nb[0][0]], phi[nb[0][1]], phi[nb[1][0]],
+                                   phi[nb[1][1]], phi[nb[2][0]], phi[nb[2][1]]);
+        const T ph = T(st.phi), gx = T(st.gx), gy = T(st.gy), gz = T(st.gz), lap = T(st.lap);
+        const T trL = Lxx + Lyy + Lzz;
+        const T Lgx = Lxx * gx + Lxy * gy + Lxz * gz;
+        const T Lgy = Lxy * gx + Lyy * gy + Lyz * gz;
+        const T Lgz = Lxz * gx + Lyz * gy + Lzz * gz;
+        const T ph2 = ph * ph;
+        sc[0 * S + s] += trL * (A * ph + T(3) * B * ph2 * ph - kap * lap);
+        sc[1 * S + s] += kap * (T(2) * Lgx - trL * gx);
+        sc[2 * S + s] += kap * (T(2) * Lgy - trL * gy);
+        sc[3 * S + s] += kap * (T(2) * Lgz - trL * gz);
+        sc[4 * S + s] += -kap * ph * trL;
+        const double dtr = double(trL), dph = st.phi;
+        const double g2 = st.gx * st.gx + st.gy * st.gy + st.gz * st.gz;
+        const double gLg = double(Lgx) * st.gx + double(Lgy) * st.gy + double(Lgz) * st.gz;
+        dth[0] += dtr * 0.5 * dph * dph;
+        dth[1] += dtr * 0.75 * dph * dph * dph * dph;
+        dth[2] += dtr * (-dph * st.lap - 0.5 * g2) + gLg;
+    }
+    block_partials<3>(dth, partials);
+}
+
 // lp(x) = a(x) - sum_a D_a b_a (x) + lap c (x).  With dtheta, workgroup 0
 // also adds the step's d/d(A, B, kappa) from the local kernel's nparts block
-// partials (instead of a launch of its own).
+// partials, and from k_adj_force_pi's in partials2 if given (instead of a
+// launch of its own).
 template <typename T>
 __device__ __forceinline__ void adj_stencil_site(const KParams& p, int s, const T* __restrict__ sc,
                                                  T* __restrict__ ap)
@@ -198,11 +392,18 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_stencil(KParams p, const T* __restrict__ sc,
                                                         T* __restrict__ ap,
                                                         const double* __restrict__ partials,
+                                                        const double* __restrict__ partials2,
                                                         int nparts, double* __restrict__ dtheta)
 {
     const int s = xcd_block() * kBlock + threadIdx.x;
     if (s < p.nsites) adj_stencil_site<T>(p, s, sc, ap);
-    if (dtheta && blockIdx.x == 0) reduce_partials_block(partials, nparts, 3, dtheta, true);
+    if (dtheta && blockIdx.x == 0) {
+        reduce_partials_block(partials, nparts, 3, dtheta, true);
+        if (partials2) {
+            __syncthreads();
+            reduce_partials_block(partials2, nparts, 3, dtheta, true);
+        }
+    }
 }
 
 template <typename T>
@@ -257,33 +458,60 @@ hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
     // us, k_adj_local unchanged)
     constexpr int kAdjBlocks = 1024;
     const int nb = reduction_grid(p) < kAdjBlocks ? reduction_grid(p) : kAdjBlocks;
-    if (fp32)
-        k_adj_local_f32<<<nb, kBlock, 0, s>>>(p, static_cast<const float*>(state), phi,
-                                                       static_cast<const float*>(adj_next),
-                                                       static_cast<float*>(adj_prev),
-                                                       static_cast<float*>(adj_scratch), partials);
-    else
-        k_adj_local_f64<<<nb, kBlock, 0, s>>>(p, static_cast<const double*>(state), phi,
-                                                         static_cast<const double*>(adj_next),
-                                                         static_cast<double*>(adj_prev),
-                                                         static_cast<double*>(adj_scratch), partials);
+    // force coupling: the second pass's partials follow the first's
+    double* partials2 = p.force ? partials + 3 * kAdjBlocks : nullptr;
+    if (fp32) {
+        const float* F = static_cast<const float*>(state);
+        const float* an = static_cast<const float*>(adj_next);
+        float* ap = static_cast<float*>(adj_prev);
+        float* sc = static_cast<float*>(adj_scratch);
+        if (p.force) {
+            k_adj_local_force_f32<<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
+            k_adj_force_pi<float><<<nb, kBlock, 0, s>>>(p, phi, sc, partials2);
+        } else {
+            k_adj_local_f32<<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
+        }
+    } else {
+        const double* F = static_cast<const double*>(state);
+        const double* an = static_cast<const double*>(adj_next);
+        double* ap = static_cast<double*>(adj_prev);
+        double* sc = static_cast<double*>(adj_scratch);
+        if (p.force) {
+            k_adj_local_force_f64<<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
+            k_adj_force_pi<double><<<nb, kBlock, 0, s>>>(p, phi, sc, partials2);
+        } else {
+            k_adj_local_f64<<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
+        }
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_adj_stencil(p, fp32, adj_scratch, adj_prev, partials, nb, dtheta, s);
+    return launch_adj_stencil(p, fp32, adj_scratch, adj_prev, partials, partials2, nb, dtheta, s);
+}
+
+hipError_t launch_adj_force_pi(const KParams& p, bool fp32, const double* phi, void* adj_scratch,
+                               double* partials2, int nblocks, hipStream_t s)
+{
+    if (fp32)
+        k_adj_force_pi<float><<<nblocks, kBlock, 0, s>>>(p, phi, static_cast<float*>(adj_scratch),
+                                                         partials2);
+    else
+        k_adj_force_pi<double><<<nblocks, kBlock, 0, s>>>(p, phi, static_cast<double*>(adj_scratch),
+                                                          partials2);
+    return hipGetLastError();
 }
 
 hipError_t launch_adj_stencil(const KParams& p, bool fp32, const void* adj_scratch,
-                              void* adj_prev, const double* partials, int nparts, double* dtheta,
-                              hipStream_t s)
+                              void* adj_prev, const double* partials, const double* partials2,
+                              int nparts, double* dtheta, hipStream_t s)
 {
     if (fp32)
         k_adj_stencil<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const float*>(adj_scratch),
                                                             static_cast<float*>(adj_prev), partials,
-                                                            nparts, dtheta);
+                                                            partials2, nparts, dtheta);
     else
         k_adj_stencil<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const double*>(adj_scratch),
                                                              static_cast<double*>(adj_prev), partials,
-                                                             nparts, dtheta);
+                                                             partials2, nparts, dtheta);
     return hipGetLastError();
 }
 

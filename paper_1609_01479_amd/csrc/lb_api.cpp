@@ -34,6 +34,7 @@ lb_status hip_fail(hipError_t e, const char* what)
 constexpr size_t kAlign = 256;
 constexpr int kAdjComponents = 2 * LB_NVEL + 1;  // lambda_f, lambda_g, lambda_phi
 constexpr int kAdjScratchComponents = 5;         // a, b_x, b_y, b_z, c
+constexpr int kAdjScratchForce = 8;              // ... and dL/dF (force coupling)
 
 // Elements per component in a time level: N rounded up to 256, plus 4352
 // (4096 + 256) of padding between the f region, the g region and phi_c, so
@@ -152,7 +153,9 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     if (fd) nparts = std::max<size_t>(nparts, size_t(lbk::fd_step_partial_blocks(k)));
     out->scratch_bytes = nparts * 5 * 8;
     out->adj_bytes = size_t(kAdjComponents) * stride * e;
-    out->adj_scratch_bytes = size_t(kAdjScratchComponents) * stride * e;
+    out->adj_scratch_bytes =
+        size_t(p->coupling == LB_COUPLING_FORCE ? kAdjScratchForce : kAdjScratchComponents) *
+        stride * e;
     return LB_OK;
 }
 
@@ -348,7 +351,6 @@ lb_status lb_adjoint_seed(lb_ctx* ctx, const double* dphi_dev)
 {
     if (!ctx || !dphi_dev) return fail(LB_EINVAL, "ctx and dphi_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
-    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
     ctx->adj_cur = 0;
     hipError_t e = lbk::launch_adj_seed(ctx->kp, ctx->fp32, ctx->b.adj[0], dphi_dev, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_seed");
@@ -364,7 +366,6 @@ lb_status lb_adjoint_step_next(lb_ctx* ctx, const void* state_t_dev, const void*
 {
     if (!ctx || !state_t_dev) return fail(LB_EINVAL, "ctx and state_t_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
-    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
     if (!aligned(state_t_dev)) return fail(LB_EALIGN, "state_t_dev is not 256-byte aligned");
     if (state_next_dev && !aligned(state_next_dev))
         return fail(LB_EALIGN, "state_next_dev is not 256-byte aligned");
@@ -390,7 +391,6 @@ lb_status lb_adjoint_phi0(lb_ctx* ctx, double* dphi0_dev)
 {
     if (!ctx || !dphi0_dev) return fail(LB_EINVAL, "ctx and dphi0_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
-    if (ctx->kp.force) return fail(LB_ESTATE, "the adjoint covers the stress coupling only");
     hipError_t e = lbk::launch_adj_phi0(ctx->kp, ctx->fp32, ctx->b.adj[ctx->adj_cur], dphi0_dev,
                                         ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_phi0");

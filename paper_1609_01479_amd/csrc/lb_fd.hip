@@ -672,11 +672,13 @@ __global__ __launch_bounds__(kBlock) void k_fd_import(KParams p, T* __restrict__
 // layout of the LB scheme's: lf[19] = dL/df_i(x) of the pulled populations,
 // lp = dL/dphi(x) (component 2*19); the g components are not used.
 //
-// k_fd_adj_prep stores rho and u = j/rho of level t (fields rho, u_x, u_y,
-// u_z of the storage type: u is formed in that type, with the forward's own
-// expressions, so the upwind choices below are the forward's).
-template <typename T, bool DEV>
+// k_fd_adj_prep stores rho and u of level t (fields rho, u_x, u_y, u_z of
+// the storage type: u is formed in that type, with the forward's own
+// expressions, so the upwind choices below are the forward's): u = j/rho,
+// or with the force coupling u = (j + F/2)/rho, F = -div Pi of phi.
+template <typename T, bool DEV, bool FORCE>
 __global__ __launch_bounds__(kBlock) void k_fd_adj_prep(KParams p, const T* __restrict__ F,
+                                                        const double* __restrict__ phi,
                                                         T* __restrict__ work)
 {
     const int s = xcd_block() * kBlock + threadIdx.x;
@@ -687,10 +689,19 @@ __global__ __launch_bounds__(kBlock) void k_fd_adj_prep(KParams p, const T* __re
     for (int i = 0; i < NV; i++) f[i] = F[dist_pull(p, q, i)];
     const Moments<T> m = moments_of<T, DEV>(p, f);
     const T ri = T(1) / m.rho;
+    T jx = m.jx, jy = m.jy, jz = m.jz;
+    if (FORCE) {
+        double Fd[3];
+        force_from_phi(p, q, phi, Fd);
+        const T Ft[3] = {T(Fd[0]), T(Fd[1]), T(Fd[2])};
+        jx = m.jx + T(0.5) * Ft[0];
+        jy = m.jy + T(0.5) * Ft[1];
+        jz = m.jz + T(0.5) * Ft[2];
+    }
     work[s] = m.rho;
-    work[p.stride + s] = m.jx * ri;
-    work[2 * p.stride + s] = m.jy * ri;
-    work[3 * p.stride + s] = m.jz * ri;
+    work[p.stride + s] = jx * ri;
+    work[2 * p.stride + s] = jy * ri;
+    work[3 * p.stride + s] = jz * ri;
 }
 
 // Transposed step at x.  With lambda' the later level:
@@ -707,7 +718,11 @@ __global__ __launch_bounds__(kBlock) void k_fd_adj_prep(KParams p, const T* __re
 // (lp = a - sum_a D_a b_a + lap c follows in k_adj_stencil) and block
 // partials of d/d(A, B, kappa).  One resident round of workgroups, each
 // thread looping over its sites.
-template <typename T>
+// FORCE: u = (j + F/2)/rho and the forcing collision of f (Pi is not in
+// f^eq): the flux's lambda_u joins the collision's, the total goes to j,
+// rho and F as in the LB scheme's force adjoint (lb_adjoint.hip), and dL/dF
+// is written after the five cotangents for k_adj_force_pi.
+template <typename T, bool FORCE>
 __global__ __launch_bounds__(kBlock) void k_fd_adj_local(KParams p, const double* __restrict__ phi,
                                                          const T* __restrict__ work,
                                                          const T* __restrict__ an,
@@ -758,6 +773,69 @@ __global__ __launch_bounds__(kBlock) void k_fd_adj_local(KParams p, const double
             u[a] = T(uc);
         }
         lmu *= M;
+
+        if (FORCE) {
+            // forcing collision of f, transposed (full second moment M2)
+            double Fd[3];
+            force_from_phi(p, q, phi, Fd);
+            const T Fx = T(Fd[0]), Fy = T(Fd[1]), Fz = T(Fd[2]);
+            const T ux = u[0], uy = u[1], uz = u[2];
+            const T rho = rhof[s], ri = T(1) / rho;
+            T m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0,
+              myz = 0;
+#pragma unroll
+            for (int i = 0; i < NV; i++) {
+                const T wl = T(weight(i)) * lf[i];
+                m0 += wl;
+                if (CX[i]) { m1x += CX[i] * wl; mxx += wl; }
+                if (CY[i]) { m1y += CY[i] * wl; myy += wl; }
+                if (CZ[i]) { m1z += CZ[i] * wl; mzz += wl; }
+                if (CX[i] * CY[i]) mxy += CX[i] * CY[i] * wl;
+                if (CX[i] * CZ[i]) mxz += CX[i] * CZ[i] * wl;
+                if (CY[i] * CZ[i]) myz += CY[i] * CZ[i] * wl;
+            }
+            const T m2ux = mxx * ux + mxy * uy + mxz * uz;
+            const T m2uy = mxy * ux + myy * uy + myz * uz;
+            const T m2uz = mxz * ux + myz * uy + mzz * uz;
+            const T m2Fx = mxx * Fx + mxy * Fy + mxz * Fz;
+            const T m2Fy = mxy * Fx + myy * Fy + myz * Fz;
+            const T m2Fz = mxz * Fx + myz * Fy + mzz * Fz;
+            const T uu = ux * ux + uy * uy + uz * uz;
+            const T pref = T(1) - T(0.5) * omf, orho = omf * rho;
+            const T lux = lu[0] + orho * (T(3) * m1x + T(9) * m2ux - T(3) * ux * m0)
+                        + pref * (T(9) * m2Fx - T(3) * Fx * m0);
+            const T luy = lu[1] + orho * (T(3) * m1y + T(9) * m2uy - T(3) * uy * m0)
+                        + pref * (T(9) * m2Fy - T(3) * Fy * m0);
+            const T luz = lu[2] + orho * (T(3) * m1z + T(9) * m2uz - T(3) * uz * m0)
+                        + pref * (T(9) * m2Fz - T(3) * Fz * m0);
+            const T arho = omf * (m0 + T(3) * (m1x * ux + m1y * uy + m1z * uz)
+                                  + h * (m2ux * ux + m2uy * uy + m2uz * uz) - T(1.5) * uu * m0)
+                         - (lux * ux + luy * uy + luz * uz) * ri;
+            const T ajx = lux * ri, ajy = luy * ri, ajz = luz * ri;
+            const T hr = T(0.5) * ri;
+#pragma unroll
+            for (int i = 0; i < NV; i++) {
+                T v = cf * lf[i] + arho;
+                if (CX[i]) v += CX[i] * ajx;
+                if (CY[i]) v += CY[i] * ajy;
+                if (CZ[i]) v += CZ[i] * ajz;
+                __builtin_nontemporal_store(v, &ap[i * S + s]);
+            }
+            const T phc = T(pc);
+            sc[0 * S + s] = lc + (A + T(3) * B * phc * phc) * lmu + adv;
+            sc[1 * S + s] = T(0);
+            sc[2 * S + s] = T(0);
+            sc[3 * S + s] = T(0);
+            sc[4 * S + s] = -kap * lmu;
+            sc[5 * S + s] = pref * (T(3) * m1x - T(3) * ux * m0 + T(9) * m2ux) + hr * lux;
+            sc[6 * S + s] = pref * (T(3) * m1y - T(3) * uy * m0 + T(9) * m2uy) + hr * luy;
+            sc[7 * S + s] = pref * (T(3) * m1z - T(3) * uz * m0 + T(9) * m2uz) + hr * luz;
+            const double dlm = double(lmu), dph = pc;
+            dth[0] += dph * dlm;
+            dth[1] += dph * dph * dph * dlm;
+            dth[2] += -st.lap * dlm;
+            continue;
+        }
 
         // collision of f, transposed
         T s0 = 0, s1x = 0, s1y = 0, s1z = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
@@ -944,20 +1022,35 @@ hipError_t launch_fd_adj_step(const KParams& p, bool fp32, const void* state, do
     // scheme's local adjoint kernel
     constexpr int kAdjBlocks = 1024;
     const int nb = fd_reduction_grid(p) < kAdjBlocks ? fd_reduction_grid(p) : kAdjBlocks;
+    // force coupling: dL/dF through Pi (launch_adj_force_pi), whose
+    // partials follow the local kernel's
+    double* partials2 = p.force ? partials + 3 * kAdjBlocks : nullptr;
+    void* st = const_cast<void*>(state);
+    const double* phi = fp32 ? fd_level<float>(st, p).phi : fd_level<double>(st, p).phi;
 #define CALL                                                                                  \
     {                                                                                         \
         FdLvl<T> a = fd_level<T>(const_cast<void*>(state), p);                                \
         T* w = reinterpret_cast<T*>(work);                                                    \
-        k_fd_adj_prep<T, DEV><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, w);                       \
-        k_fd_adj_local<T><<<nb, kBlock, 0, s>>>(p, a.phi, w, static_cast<const T*>(adj_next),  \
-                                                static_cast<T*>(adj_prev),                    \
-                                                static_cast<T*>(adj_scratch), partials);      \
+        const T* an = static_cast<const T*>(adj_next);                                        \
+        T* ap = static_cast<T*>(adj_prev);                                                    \
+        T* sc = static_cast<T*>(adj_scratch);                                                 \
+        if (p.force) {                                                                        \
+            k_fd_adj_prep<T, DEV, true><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, w);      \
+            k_fd_adj_local<T, true><<<nb, kBlock, 0, s>>>(p, a.phi, w, an, ap, sc, partials); \
+        } else {                                                                              \
+            k_fd_adj_prep<T, DEV, false><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, w);     \
+            k_fd_adj_local<T, false><<<nb, kBlock, 0, s>>>(p, a.phi, w, an, ap, sc, partials);\
+        }                                                                                     \
     }
     LB_FD_DISPATCH(fp32, CALL);
 #undef CALL
-    const hipError_t e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_adj_stencil(p, fp32, adj_scratch, adj_prev, partials, nb, dtheta, s);
+    if (p.force) {
+        e = launch_adj_force_pi(p, fp32, phi, adj_scratch, partials2, nb, s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_adj_stencil(p, fp32, adj_scratch, adj_prev, partials, partials2, nb, dtheta, s);
 }
 
 hipError_t launch_fd_moments(const KParams& p, bool fp32, const void* state, double* rho,

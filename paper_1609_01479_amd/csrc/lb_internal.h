@@ -104,17 +104,26 @@ hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, const double*
 // state_next (may be null): the level one step after `state`; in FP32 mode
 // its reference field is phi of `state`, so the phi pass is skipped.
 // dtheta (may be null): FP64[3] incremented by the step's d/d(A, B, kappa),
-// reduced from block partials in `partials` (3 * 1024 doubles).
+// reduced from block partials in `partials` (3 * 1024 doubles; 6 * 1024
+// with the force coupling).  The force coupling needs 8 components of
+// adj_scratch (the stencil cotangents, then dL/dF).
 hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
                            const void* state_next, double* phi, const void* adj_next,
                            void* adj_prev, void* adj_scratch, double* partials, double* dtheta,
                            hipStream_t s);
 // lp of adj_prev from the stencil cotangents in adj_scratch (a, b_x, b_y,
 // b_z, c): lp = a - sum_a D_a b_a + lap c; with dtheta, also
-// dtheta[k] += the sum of the nparts block partials of component k < 3.
+// dtheta[k] += the sum of the nparts block partials of component k < 3 in
+// `partials` and, if not null, in `partials2`.
 hipError_t launch_adj_stencil(const KParams& p, bool fp32, const void* adj_scratch,
-                              void* adj_prev, const double* partials, int nparts, double* dtheta,
-                              hipStream_t s);
+                              void* adj_prev, const double* partials, const double* partials2,
+                              int nparts, double* dtheta, hipStream_t s);
+// Force coupling: dL/dF (adj_scratch components 5..7) through Pi at the face
+// neighbours into the stencil cotangents (components 0..4) of the FP64 phi
+// field `phi`; nblocks workgroups, their partials of d/d(A, B, kappa) in
+// partials2 (3 * nblocks).
+hipError_t launch_adj_force_pi(const KParams& p, bool fp32, const double* phi, void* adj_scratch,
+                               double* partials2, int nblocks, hipStream_t s);
 // dL/dphi0 from the level in `adj` (LB scheme: lg_0 + lp; FD scheme: lp).
 hipError_t launch_adj_phi0(const KParams& p, bool fp32, const void* adj, double* dphi0,
                            hipStream_t s);

@@ -48,10 +48,10 @@ class LB:
         "soa", "aos" or "aosoa" with aosoa_len z-sites per block (a power of
         two dividing nz); results are bit-identical across layouts.
     coupling: "stress" (Pi in the f equilibrium, default) or "force" (body
-        force -div Pi with the half-force velocity; no adjoint).
+        force -div Pi with the half-force velocity).
     order_param: "lb" (distribution g, default) or "fd" (a phi field with the
         finite-difference Cahn-Hilliard update and upwind advection, mobility
-        Gamma (tau_g - 1/2); either coupling, the adjoint with "stress"; no g).
+        Gamma (tau_g - 1/2); either coupling; no g).
     """
 
     def __init__(self, shape, *, A=-0.00625, B=0.00625, kappa=0.004, gamma=0.5, tau_f=1.0,

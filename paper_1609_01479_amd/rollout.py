@@ -35,7 +35,7 @@ class _Rollout(torch.autograd.Function):
                 gamma=cfg.get("gamma", 0.5), tau_f=cfg.get("tau_f", 1.0),
                 tau_g=cfg.get("tau_g", 1.0), rho0=cfg.get("rho0", 1.0),
                 precision=cfg.get("precision", "fp64"), adjoint=True, device=phi0.device,
-                order_param=cfg.get("order_param", "lb"))
+                order_param=cfg.get("order_param", "lb"), coupling=cfg.get("coupling", "stress"))
         lb.init_phi(phi0.detach())
         ckpts = []
         t = 0
@@ -81,14 +81,14 @@ class _Rollout(torch.autograd.Function):
 
 def rollout(phi0: torch.Tensor, A, B, kappa, nsteps: int, *, interval: int | None = None,
             gamma=0.5, tau_f=1.0, tau_g=1.0, rho0=1.0, precision="fp64",
-            order_param="lb") -> torch.Tensor:
+            order_param="lb", coupling="stress") -> torch.Tensor:
     """phi after `nsteps` steps from the state (rho0, u = 0, phi0); differentiable
     in phi0 (FP64 device tensor (nx, ny, nz)) and in A, B, kappa (tensors or
     floats).  order_param: "lb" (distribution g) or "fd" (finite-difference
-    phi field)."""
+    phi field); coupling: "stress" (Pi in f^eq) or "force" (F = -div Pi)."""
     dev = phi0.device
     as_t = lambda v: v if torch.is_tensor(v) else torch.tensor(float(v), dtype=torch.float64,  # noqa: E731
                                                                device=dev)
     cfg = dict(nsteps=nsteps, interval=interval, gamma=gamma, tau_f=tau_f, tau_g=tau_g,
-               rho0=rho0, precision=precision, order_param=order_param)
+               rho0=rho0, precision=precision, order_param=order_param, coupling=coupling)
     return _Rollout.apply(phi0, as_t(A), as_t(B), as_t(kappa), cfg)

@@ -81,31 +81,25 @@ def test_bad_parameters_rejected(abi, kw, code):
     assert abi.lib().lb_last_error().decode()
 
 
-def test_force_coupling_sizes_and_no_adjoint(abi):
+def test_force_coupling_sizes(abi):
     """The force coupling needs one FP64 work field (phi; Pi is formed on the
-    fly) and has no adjoint: the reverse-mode calls return LB_ESTATE before
-    any HIP call."""
-    st, s1 = _query(abi, coupling=1)
-    assert st == abi.LB_OK and s1.phi_bytes == s1.stride_elems * 8
-    L = abi.lib()
-    p = _params(abi, coupling=1)
-    ctx = ctypes.c_void_p()
-    b = abi.LbBuffers()
-    b.state[0], b.state[1], b.phi, b.scratch = 0x1000, 0x2000, 0x3000, 0x4000
-    b.adj[0], b.adj[1], b.adj_scratch = 0x5000, 0x6000, 0x7000
-    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
-    assert L.lb_adjoint_seed(ctx, ctypes.c_void_p(0x8000)) == abi.LB_ESTATE
-    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), None, None) == abi.LB_ESTATE
-    assert L.lb_adjoint_phi0(ctx, ctypes.c_void_p(0x8000)) == abi.LB_ESTATE
-    L.lb_destroy(ctx)
+    fly) and, for its adjoint, three more scratch components (dL/dF) than
+    the stress coupling's five, in either order-parameter scheme."""
+    for op in (0, 1):
+        for prec, e in ((0, 8), (1, 4)):
+            st, s0 = _query(abi, coupling=0, order_param=op, precision=prec)
+            st1, s1 = _query(abi, coupling=1, order_param=op, precision=prec)
+            assert st == st1 == abi.LB_OK
+            assert s0.adj_scratch_bytes == 5 * s0.stride_elems * e
+            assert s1.adj_scratch_bytes == 8 * s1.stride_elems * e
+            assert s1.phi_bytes == (s1.stride_elems * 8 if op == 0 else 4 * s1.stride_elems * 8)
 
 
 @pytest.mark.parametrize("prec,e", [(0, 8), (1, 4)])
 def test_fd_order_parameter_sizes_and_calls_without_launching(abi, prec, e):
     """The finite-difference order parameter: a level is f then the FP64 phi
     field, 4 FP64 work fields (mu, u), partials for one block per 256 sites;
-    g-taking calls reject a g pointer, and the reverse mode of the force
-    coupling returns LB_ESTATE, all before any HIP call."""
+    g-taking calls reject a g pointer, all before any HIP call."""
     n = 40 * 40 * 40
     st, s = _query(abi, nx=40, ny=40, nz=40, order_param=1, precision=prec)
     assert st == abi.LB_OK
@@ -123,12 +117,6 @@ def test_fd_order_parameter_sizes_and_calls_without_launching(abi, prec, e):
     assert L.lb_export_dist(ctx, v, v) == abi.LB_EINVAL
     assert L.lb_import_dist(ctx, v, v) == abi.LB_EINVAL
     assert L.lb_import_dist(ctx, None, None) == abi.LB_EINVAL
-    L.lb_destroy(ctx)
-    p = _params(abi, order_param=1, precision=prec, coupling=1)
-    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
-    assert L.lb_adjoint_seed(ctx, v) == abi.LB_ESTATE
-    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), None, None) == abi.LB_ESTATE
-    assert L.lb_adjoint_phi0(ctx, v) == abi.LB_ESTATE
     L.lb_destroy(ctx)
 
 

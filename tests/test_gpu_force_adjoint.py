@@ -1,0 +1,188 @@
+"""Reverse mode of the force coupling (F = -div Pi, Guo forcing) with the LB
+order parameter on the GPU, against autograd through the oracle's torch
+transcription of that step (pinned to the C oracle and to central
+differences in the CPU suite).  The finite-difference scheme's force
+adjoint is covered in test_gpu_fd_adjoint.py."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import lbinputs
+import oracle
+import oracle.reverse as R
+from tests._gpu import make_lb, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _rollout_grads(shape, T, phi0, tgt, interval=None, precision="fp64", **kw):
+    from paper_1609_01479_amd.rollout import rollout
+    pr = dict(lbinputs.SPINODAL_PARAMS, **kw)
+    dev = torch.device("cuda:0")
+    p0 = torch.tensor(phi0, dtype=torch.float64, device=dev, requires_grad=True)
+    th = [torch.tensor(pr[k], dtype=torch.float64, device=dev, requires_grad=True)
+          for k in ("A", "B", "kappa")]
+    phiT = rollout(p0, *th, T, interval=interval, gamma=pr["gamma"], tau_f=pr["tau_f"],
+                   tau_g=pr["tau_g"], rho0=pr["rho0"], precision=precision, coupling="force")
+    loss = 0.5 * ((phiT - torch.tensor(tgt, device=dev)) ** 2).sum()
+    loss.backward()
+    return (float(loss.detach()), p0.grad.cpu().numpy()) + tuple(float(t.grad) for t in th)
+
+
+def _check(got, ref, tol_phi=1e-10, tol_theta=1e-9):
+    L, gphi, *gth = got
+    rL, rphi, *rth = ref
+    assert abs(L - rL) <= 1e-12 * abs(rL), (L, rL)
+    assert rel_err(gphi, rphi) <= tol_phi, rel_err(gphi, rphi)
+    for name, a, b in zip(("A", "B", "kappa"), gth, rth):
+        assert abs(a - b) <= tol_theta * abs(b), (name, a, b)
+
+
+@pytest.mark.parametrize("interval", [None, 1, 7])
+def test_force_adjoint_matches_oracle_reverse_mode_8cubed(interval):
+    """8^3 x 20 steps from rest, tau != 1, through the checkpointed rollout."""
+    shape, T = (8, 8, 8), 20
+    kw = dict(tau_f=0.8, tau_g=1.3)
+    pr = dict(lbinputs.SPINODAL_PARAMS, **kw)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=77)
+    tgt = lbinputs.lamellar_target(shape, 8, lbinputs.interface_width(pr["A"], pr["kappa"]))
+    print(f"[force adjoint] 8^3 x {T} interval={interval}", flush=True)
+    got = _rollout_grads(shape, T, phi0, tgt, interval=interval, **kw)
+    ref = R.loss_and_grads(phi0, tgt, pr["A"], pr["B"], pr["kappa"], T, pr["gamma"],
+                           pr["tau_f"], pr["tau_g"], pr["rho0"], "force")
+    _check(got, ref)
+
+
+def test_force_adjoint_noncubic_default_taus():
+    shape, T = (6, 5, 7), 12
+    pr = dict(lbinputs.SPINODAL_PARAMS)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=3, amp=0.4)
+    tgt = lbinputs.random_field(shape, 10)
+    print(f"[force adjoint] {shape} x {T}", flush=True)
+    got = _rollout_grads(shape, T, phi0, tgt, interval=4)
+    ref = R.loss_and_grads(phi0, tgt, pr["A"], pr["B"], pr["kappa"], T, pr["gamma"],
+                           pr["tau_f"], pr["tau_g"], pr["rho0"], "force")
+    _check(got, ref)
+
+
+def _flowing_state(shape, seed):
+    """f: second-order equilibrium of a sign-changing shear flow; g: phi's
+    rest equilibrium; both perturbed by 1% seeded noise."""
+    c, w = oracle.lattice()
+    nx, ny, nz = shape
+    x, y, z = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    u = np.stack([0.03 * np.sin(2 * np.pi * (y + 0.5) / ny),
+                  0.02 * np.cos(2 * np.pi * (z + 0.25) / nz),
+                  0.015 * np.sin(2 * np.pi * (x + 0.3) / nx)])
+    cu = np.einsum("ia,axyz->ixyz", c, u)
+    uu = (u * u).sum(0)
+    f0 = w[:, None, None, None] * (1.0 + 3 * cu + 4.5 * cu * cu - 1.5 * uu[None])
+    f0 = f0 * (1.0 + 0.01 * lbinputs.random_field((19,) + tuple(shape), seed))
+    phi = lbinputs.spinodal_phi0(shape, seed=seed + 1, amp=0.5)
+    g0 = w[:, None, None, None] * phi[None] * (1.0 + 3 * cu)
+    g0 = g0 + 0.01 * w[:, None, None, None] * lbinputs.random_field((19,) + tuple(shape),
+                                                                       seed + 2)
+    return f0, g0
+
+
+def _reference_from_state(f0, g0, tgt, T, pr):
+    f = torch.tensor(f0, dtype=torch.float64, requires_grad=True)
+    g = torch.tensor(g0, dtype=torch.float64, requires_grad=True)
+    th = [torch.tensor(float(pr[k]), dtype=torch.float64, requires_grad=True)
+          for k in ("A", "B", "kappa")]
+    fs, gs = f, g
+    for _ in range(T):
+        fs, gs = R.step_force(fs, gs, *th, pr["gamma"], pr["tau_f"], pr["tau_g"])
+    loss = 0.5 * ((gs.sum(0) - torch.tensor(tgt, dtype=torch.float64)) ** 2).sum()
+    loss.backward()
+    return (float(loss.detach()), f.grad.numpy(), g.grad.numpy(),
+            tuple(float(t.grad) for t in th))
+
+
+def _gpu_from_state(f0, g0, tgt, T, precision="fp64", **kw):
+    shape = f0.shape[1:]
+    lb = make_lb(shape, precision=precision, adjoint=True, coupling="force", **kw)
+    lb.import_dist(f0, g0)
+    states = []
+    for _ in range(T):
+        states.append(lb.get_state())
+        lb.step(1)
+    phiT = lb.phi()
+    dphi = phiT - torch.tensor(tgt, device=phiT.device)
+    L = 0.5 * float((dphi ** 2).sum())
+    lb.adjoint_seed(dphi)
+    dth = torch.zeros(3, dtype=torch.float64, device=phiT.device)
+    for t in reversed(range(T)):
+        lb.adjoint_step(states[t], dth)
+    # the level after T reverse steps is buffer T % 2: lambda_f, the
+    # g-specific parts lg_i, then lp (dL/dg_i = lg_i + lp), each of
+    # `stride` elements with sites in (x, y, z) order
+    n = lb.nsites
+    S = lb.sizes.stride_elems
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    lev = lb.adj_buf[T % 2].view(dt)[:39 * S].view(39, S)[:, :n].double().cpu().numpy()
+    lev = lev.reshape((39,) + tuple(shape))
+    return L, lev[:19], lev[19:38] + lev[38][None], tuple(float(v) for v in dth.cpu())
+
+
+@pytest.mark.parametrize("shape", [(6, 5, 7), (2, 3, 1), (1, 4, 9)])
+def test_force_adjoint_flowing_state_df0_dg0(shape):
+    """From an imported flowing, non-equilibrium state, tau != 1: dL/df0 and
+    dL/dg0 (the adjoint level) and dL/d(A, B, kappa)."""
+    T = 10
+    kw = dict(tau_f=0.9, tau_g=1.2)
+    pr = dict(lbinputs.SPINODAL_PARAMS, **kw)
+    f0, g0 = _flowing_state(shape, 51)
+    tgt = lbinputs.random_field(shape, 52)
+    print(f"[force adjoint flow] {shape} x {T}", flush=True)
+    L, lf, lg, th = _gpu_from_state(f0, g0, tgt, T, **kw)
+    rL, rf, rg, rth = _reference_from_state(f0, g0, tgt, T, pr)
+    assert abs(L - rL) <= 1e-12 * abs(rL), (L, rL)
+    assert rel_err(lf, rf) <= 1e-10, rel_err(lf, rf)
+    assert rel_err(lg, rg) <= 1e-10, rel_err(lg, rg)
+    for name, a, b in zip(("A", "B", "kappa"), th, rth):
+        assert abs(a - b) <= 1e-9 * abs(b), (name, a, b)
+
+
+def test_force_adjoint_fp32_close_to_fp64():
+    shape, T = (16, 16, 16), 40
+    pr = dict(lbinputs.SPINODAL_PARAMS)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=12)
+    tgt = lbinputs.lamellar_target(shape, 8, lbinputs.interface_width(pr["A"], pr["kappa"]))
+    g64 = _rollout_grads(shape, T, phi0, tgt, precision="fp64")
+    g32 = _rollout_grads(shape, T, phi0, tgt, precision="fp32_dev")
+    e_phi = np.linalg.norm(g32[1] - g64[1]) / np.linalg.norm(g64[1])
+    print(f"[force adjoint fp32] rel L2 err dphi0 = {e_phi:.3e}; "
+          f"A {g32[2]/g64[2]-1:.2e} B {g32[3]/g64[3]-1:.2e} kappa {g32[4]/g64[4]-1:.2e}",
+          flush=True)
+    assert e_phi <= 1e-4
+    for a, b in zip(g32[2:], g64[2:]):
+        assert abs(a - b) <= 1e-3 * abs(b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("layout,v", [("rows", 0), ("soa", 0), ("aosoa", 32)])
+def test_force_adjoint_step_next_and_layouts_bit_identical(prec, layout, v):
+    """lb_adjoint_step_next (FP32: phi of level t from level t+1's reference
+    field) and every layout give gradients bit-identical to lb_adjoint_step
+    on the row-blocked default, over 5 reverse steps."""
+    shape, T = (6, 5, 64), 5
+    phi0 = lbinputs.spinodal_phi0(shape, seed=23, amp=0.3)
+    dphi = torch.tensor(lbinputs.random_field(shape, 4), device="cuda:0")
+    out = []
+    for lay, vv, use_next in (("rows", 0, False), (layout, v, True)):
+        lb = make_lb(shape, precision=prec, adjoint=True, coupling="force", layout=lay,
+                     aosoa_len=vv)
+        lb.init_phi(phi0)
+        states = [lb.get_state()]
+        for _ in range(T):
+            lb.step(1)
+            states.append(lb.get_state())
+        dth = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+        lb.adjoint_seed(dphi)
+        for t in reversed(range(T)):
+            lb.adjoint_step(states[t], dth, next_state=states[t + 1] if use_next else None)
+        out.append((lb.adjoint_phi0().cpu().numpy(), dth.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
