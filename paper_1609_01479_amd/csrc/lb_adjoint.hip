@@ -29,6 +29,7 @@
 //   lp = dL/dphi(x), so that dL/dg_i(x) = lg_i(x) + lp(x).
 // adj_scratch holds a (direct dPhi/dphi), b_x, b_y, b_z, c per site.
 #include "lb_device.h"
+#include "lb_sweep.h"
 
 namespace lbk {
 
@@ -59,7 +60,8 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
 {
     double dth[3] = {0.0, 0.0, 0.0};
     const unsigned S = p.stride;
-    for (int s = xcd_block() * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
+    for (XcdSweep w = xcd_sweep(p.nsites, kBlock); w.s < w.end; w.s += w.stride) {
+        const int s = w.s;
         const Geo q = geo_of(p, s);
         T lf[NV], lg[NV], f[NV];
 #pragma unroll
@@ -196,7 +198,8 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
     const T A = T(p.A), B = T(p.B), kap = T(p.kappa), gam = T(p.gamma);
     const T omf = T(p.omega_f), omg = T(p.omega_g), pref = T(1) - T(0.5) * omf;
     const T h = T(4.5), third = T(1.0 / 3.0);
-    for (int s = xcd_block() * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
+    for (XcdSweep w = xcd_sweep(p.nsites, kBlock); w.s < w.end; w.s += w.stride) {
+        const int s = w.s;
         const Geo q = geo_of(p, s);
         T lf[NV], lg[NV], f[NV];
 #pragma unroll
@@ -327,7 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_force_pi(KParams p, const double
     const unsigned S = p.stride;
     const T* __restrict__ lF[3] = {sc + 5 * size_t(S), sc + 6 * size_t(S), sc + 7 * size_t(S)};
     const T A = T(p.A), B = T(p.B), kap = T(p.kappa);
-    for (int s = xcd_block() * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
+    for (XcdSweep w = xcd_sweep(p.nsites, kBlock); w.s < w.end; w.s += w.stride) {
+        const int s = w.s;
         const Geo q = geo_of(p, s);
         const int nb[3][2] = {{site_of(p, q.xp, q.y, q.z), site_of(p, q.xm, q.y, q.z)},
                               {site_of(p, q.x, q.yp, q.z), site_of(p, q.x, q.ym, q.z)},

@@ -38,6 +38,7 @@
 #include <type_traits>
 
 #include "lb_device.h"
+#include "lb_sweep.h"
 
 namespace lbk {
 
@@ -737,7 +738,8 @@ __global__ __launch_bounds__(kBlock) void k_fd_adj_local(KParams p, const double
     const T A = T(p.A), B = T(p.B), kap = T(p.kappa), M = T(p.mobility);
     const T omf = T(p.omega_f), cf = T(1) - omf;
     const T h = T(4.5), third = T(1.0 / 3.0);
-    for (int s = xcd_block() * kBlock + threadIdx.x; s < p.nsites; s += gridDim.x * kBlock) {
+    for (XcdSweep w = xcd_sweep(p.nsites, kBlock); w.s < w.end; w.s += w.stride) {
+        const int s = w.s;
         const Geo q = geo_of(p, s);
         T lf[NV];
 #pragma unroll
