@@ -315,11 +315,12 @@ def main():
         out["fd_order_parameter"]["phi_fp32_vs_fp64_max"] = float(
             np.abs(fd_phi["fp32_dev"] - fd_phi["fp64"]).max())
         del fd_phi
-        # with the force coupling: the two-kernel path, collision pass 344 / 192
+        # with the force coupling: the two-kernel path, collision pass 344 / 176
         # B per site (FP64 / FP32 storage; Pi at the face neighbours from the
-        # phi field, in cache) and flux pass 48
+        # phi field, in cache; mu and u in the storage type) and flux pass
+        # 48 / 32
         out["fd_order_parameter"]["force_coupling"] = {}
-        for prec, moved in (("fp32_dev", 240), ("fp64", 392)):
+        for prec, moved in (("fp32_dev", 208), ("fp64", 392)):
             lb = LB(shape, precision=prec, order_param="fd", coupling="force", device="cuda:0",
                     **lay, **params)
             lb.init_phi(phi0)

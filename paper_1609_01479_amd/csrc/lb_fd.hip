@@ -6,8 +6,9 @@
 //
 //   k_fd_collide (one site per thread): pull of f, 7-point stencil of phi,
 //     mu and Pi, collision of f with Pi in f^eq and its store; mu and
-//     u = j/rho into FP64 work fields; optionally the block partials of the
-//     source level's conserved sums.
+//     u = j/rho into work fields (FP64; FP32 with the force coupling in
+//     FP32 storage); optionally the block partials of the source level's
+//     conserved sums.
 //   k_fd_update: marching along x, the fluxes through each site's six faces
 //     from phi, mu and u of the site and its face neighbours,
 //       J_a(x + e_a/2) = u_f (u_f > 0 ? phi(x) : phi(x + e_a)) - M (mu(x + e_a) - mu(x)),
@@ -79,6 +80,13 @@ __device__ __forceinline__ double fd_mu(const KParams& p, double c, double lap)
     return p.A * c + p.B * c * c * c - p.kappa * lap;
 }
 
+// Element type of the collision pass's work fields (mu, u_x, u_y, u_z): FP64,
+// except with the force coupling in FP32 storage, where u is an FP32 value
+// already and mu is rounded to FP32 (the stress coupling's two passes stay
+// bit-identical to its single-pass kernel, which keeps mu in FP64).
+template <typename T, bool FORCE>
+using FdWork = typename std::conditional<FORCE && std::is_same<T, float>::value, float, double>::type;
+
 // Work fields (each `stride` FP64 values): mu, u_x, u_y, u_z.  FORCE: the
 // force coupling, F = -div Pi from the phi field (force_from_phi), the
 // forcing collision of f, u = (j + F/2)/rho, and momentum sums of j + F/2.
@@ -86,9 +94,10 @@ template <typename T, bool DEV, bool FORCE>
 __global__ __launch_bounds__(kBlock) void k_fd_collide(KParams p, const T* __restrict__ sF,
                                                        const double* __restrict__ sphi,
                                                        T* __restrict__ dF,
-                                                       double* __restrict__ work,
+                                                       FdWork<T, FORCE>* __restrict__ work,
                                                        double* __restrict__ partials)
 {
+    using W = FdWork<T, FORCE>;
     const int s = xcd_block() * kBlock + threadIdx.x;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (s < p.nsites) {
@@ -123,10 +132,10 @@ __global__ __launch_bounds__(kBlock) void k_fd_collide(KParams p, const T* __res
         // the new level is not read in this launch
 #pragma unroll
         for (int i = 0; i < NV; i++) __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
-        work[s] = fd_mu(p, c, st.lap);
-        work[p.stride + s] = double(u.x);
-        work[2 * p.stride + s] = double(u.y);
-        work[3 * p.stride + s] = double(u.z);
+        work[s] = W(fd_mu(p, c, st.lap));
+        work[p.stride + s] = W(u.x);
+        work[2 * p.stride + s] = W(u.y);
+        work[3 * p.stride + s] = W(u.z);
     }
     if (partials) block_partials<5>(acc, partials);
 }
@@ -154,10 +163,11 @@ constexpr int kFdTY = 4, kFdTZ = 64;
 static_assert(kFdTY * kFdTZ == kBlock, "update tile must match the block");
 
 // 8 waves per SIMD (at most 64 VGPRs): the ~2048 workgroups then run in one
-// round on 256 CUs instead of 1.33.
+// round on 256 CUs instead of 1.33.  W: the work fields' element type.
+template <typename W>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fd_update(
     KParams p, int ntz, int ntiles, int sx, const double* __restrict__ sphi,
-    const double* __restrict__ work, double* __restrict__ dphi)
+    const W* __restrict__ work, double* __restrict__ dphi)
 {
     const int b = xcd_block();
     const int seg = b / ntiles, tile = b - seg * ntiles;
@@ -165,10 +175,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     const int z = (tile % ntz) * kFdTZ + int(threadIdx.x) % kFdTZ;
     if (y >= p.ny || z >= p.nz) return;
     const int x0 = seg * sx, x1 = min(p.nx, x0 + sx);
-    const double* __restrict__ mu = work;
-    const double* __restrict__ ux = work + p.stride;
-    const double* __restrict__ uy = work + 2 * size_t(p.stride);
-    const double* __restrict__ uz = work + 3 * size_t(p.stride);
+    // (FP32 work fields widen exactly to FP64 on load)
+    const W* __restrict__ mu = work;
+    const W* __restrict__ ux = work + p.stride;
+    const W* __restrict__ uy = work + 2 * size_t(p.stride);
+    const W* __restrict__ uz = work + 3 * size_t(p.stride);
     const double M = p.mobility;
     const int plane = p.ny * p.nz;
     const int oc = y * p.nz + z;
@@ -421,7 +432,7 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_collide(KParams p, TileCf
                                                                const T* __restrict__ sF,
                                                                const double* __restrict__ sphi,
                                                                T* __restrict__ dF,
-                                                               double* __restrict__ work,
+                                                               FdWork<T, true>* __restrict__ work,
                                                                double* __restrict__ partials)
 {
     using G = FdTile<TZ>;
@@ -570,10 +581,11 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_collide(KParams p, TileCf
 #pragma unroll
             for (int i = 0; i < NV; i++) __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
             const int s = X * plane + yg * p.nz + zg;
-            work[s] = fd_mu(p, c, st.lap);
-            work[p.stride + s] = double(u.x);
-            work[2 * p.stride + s] = double(u.y);
-            work[3 * p.stride + s] = double(u.z);
+            using W = FdWork<T, true>;
+            work[s] = W(fd_mu(p, c, st.lap));
+            work[p.stride + s] = W(u.x);
+            work[2 * p.stride + s] = W(u.y);
+            work[3 * p.stride + s] = W(u.z);
         }
 #pragma unroll
         for (int a = 0; a < 3; a++) {
@@ -968,10 +980,12 @@ hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int va
     {                                                                                         \
         FdLvl<T> a = fd_level<T>(const_cast<void*>(src), p);                                  \
         FdLvl<T> d = fd_level<T>(dst, p);                                                     \
-        FdForce<T>::get(tc.tz)<<<nparts, kFdFused, 0, s>>>(p, tc, a.F, a.phi, d.F, work,      \
+        using W = FdWork<T, true>;                                                            \
+        W* w = reinterpret_cast<W*>(work);                                                    \
+        FdForce<T>::get(tc.tz)<<<nparts, kFdFused, 0, s>>>(p, tc, a.F, a.phi, d.F, w,         \
                                                            sums_out ? partials : nullptr);    \
-        k_fd_update<<<ft.ntiles * ft.nseg, kBlock, 0, s>>>(p, ft.ntz, ft.ntiles, ft.sx, a.phi,  \
-                                                           work, d.phi);                      \
+        k_fd_update<W><<<ft.ntiles * ft.nseg, kBlock, 0, s>>>(p, ft.ntz, ft.ntiles, ft.sx,    \
+                                                              a.phi, w, d.phi);               \
     }
         LB_FD_DISPATCH(fp32, CALL);
 #undef CALL
@@ -993,16 +1007,22 @@ hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int va
     {                                                                                         \
         FdLvl<T> a = fd_level<T>(const_cast<void*>(src), p);                                  \
         FdLvl<T> d = fd_level<T>(dst, p);                                                     \
-        if (p.force)                                                                          \
-            k_fd_collide<T, DEV, true><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, d.F, work, \
+        if (p.force) {                                                                        \
+            using W = FdWork<T, true>;                                                        \
+            W* w = reinterpret_cast<W*>(work);                                                \
+            k_fd_collide<T, DEV, true><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, d.F, w,    \
                                                                      sums_out ? partials       \
                                                                               : nullptr);      \
-        else                                                                                  \
+            k_fd_update<W><<<ft.ntiles * ft.nseg, kBlock, 0, s>>>(p, ft.ntz, ft.ntiles, ft.sx, \
+                                                                  a.phi, w, d.phi);           \
+        } else {                                                                              \
             k_fd_collide<T, DEV, false><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, d.F, work,\
                                                                       sums_out ? partials      \
                                                                                : nullptr);     \
-        k_fd_update<<<ft.ntiles * ft.nseg, kBlock, 0, s>>>(p, ft.ntz, ft.ntiles, ft.sx, a.phi,  \
-                                                           work, d.phi);                      \
+            k_fd_update<double><<<ft.ntiles * ft.nseg, kBlock, 0, s>>>(p, ft.ntz, ft.ntiles,   \
+                                                                       ft.sx, a.phi, work,     \
+                                                                       d.phi);                 \
+        }                                                                                     \
     }
         LB_FD_DISPATCH(fp32, CALL);
 #undef CALL

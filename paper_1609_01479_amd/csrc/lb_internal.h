@@ -131,8 +131,9 @@ hipError_t launch_adj_phi0(const KParams& p, bool fp32, const void* adj, double*
 // Finite-difference order parameter (lb_fd.hip).  A time level is F
 // (19*stride elements, laid out per KParams) then phi (stride FP64 values).
 // variant 0: single-pass step with the tiling of tc; 1: collision pass, then
-// update pass, with `work` holding mu, u_x, u_y, u_z (4 FP64 fields of
-// `stride`).  With sums_out, `partials` needs 5 * max(tc.ntiles * tc.nseg,
+// update pass, with `work` holding mu, u_x, u_y, u_z (4 fields of `stride`:
+// FP64, or FP32 with the force coupling in FP32 storage; 4 FP64 fields of
+// space).  With sums_out, `partials` needs 5 * max(tc.ntiles * tc.nseg,
 // fd_step_partial_blocks(p)) doubles.
 int fd_step_partial_blocks(const KParams& p);
 hipError_t launch_fd_init(const KParams& p, bool fp32, void* state, const double* phi0,
