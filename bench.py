@@ -114,13 +114,21 @@ def adjoint_ratio(shape, T, interval, precision, phi0, tgt, params, order_param=
     lb.init_phi(phi0)
     fwd_ms = time_steps(lb, T, 0)
     del lb
-    p0 = torch.tensor(phi0, dtype=torch.float64, device=dev, requires_grad=True)
-    th = [torch.tensor(params[k], dtype=torch.float64, device=dev, requires_grad=True)
-          for k in ("A", "B", "kappa")]
     rest = {k: params[k] for k in ("gamma", "tau_f", "tau_g", "rho0")}
-    phiT = rollout(p0, *th, T, interval=interval, precision=precision, order_param=order_param,
-                   coupling=coupling, **rest)
-    loss = 0.5 * ((phiT - torch.tensor(tgt, device=dev)) ** 2).sum()
+    tgt_t = torch.tensor(tgt, device=dev)
+
+    def forward():
+        p0 = torch.tensor(phi0, dtype=torch.float64, device=dev, requires_grad=True)
+        th = [torch.tensor(params[k], dtype=torch.float64, device=dev, requires_grad=True)
+              for k in ("A", "B", "kappa")]
+        phiT = rollout(p0, *th, T, interval=interval, precision=precision,
+                       order_param=order_param, coupling=coupling, **rest)
+        return p0, th, 0.5 * ((phiT - tgt_t) ** 2).sum()
+
+    # one untimed rollout first (kernel loading, allocator), as every timed
+    # region here has its warm-up
+    forward()[2].backward()
+    p0, th, loss = forward()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     loss.backward()
