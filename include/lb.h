@@ -246,8 +246,14 @@ lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
 
 /* ---- reverse mode ------------------------------------------------------
  * The adjoint carries lambda_t = dL/d(state at time t) in the context's
- * adjoint buffers (FP64 in LB_FP64, FP32 in LB_FP32_DEV).  For a loss on the
- * final order parameter:
+ * adjoint buffers (FP64 in LB_FP64, FP32 in LB_FP32_DEV).  A level is 39
+ * components of stride_elems elements each, sites in dense (x, y, z) order:
+ * components 0..18 hold dL/df_i of the post-propagation populations (FP32
+ * storage: of the deviations, the same values), 19..37 the parts lg_i
+ * specific to each g_i and 38 lp, with dL/dg_i = lg_i + lp (LB_OP_LB), or
+ * lp = dL/dphi (LB_OP_FD).  After lb_adjoint_seed the level is adj[0]; each
+ * reverse step moves it to the other buffer.  For a loss on the final order
+ * parameter:
  *   lb_adjoint_seed(dL/dphi_T)  then, for t = T-1 .. 0,
  *   lb_adjoint_step(state_t)    (state_t as saved by lb_get_state at time t;
  *                                or lb_adjoint_step_next with level t+1 too)

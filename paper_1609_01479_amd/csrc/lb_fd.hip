@@ -688,11 +688,14 @@ __global__ __launch_bounds__(kBlock) void k_fd_import(KParams p, T* __restrict__
 // k_fd_adj_prep stores rho and u of level t (fields rho, u_x, u_y, u_z of
 // the storage type: u is formed in that type, with the forward's own
 // expressions, so the upwind choices below are the forward's): u = j/rho,
-// or with the force coupling u = (j + F/2)/rho, F = -div Pi of phi.
+// or with the force coupling u = (j + F/2)/rho, F = -div Pi of phi; then F
+// itself (in the storage type, as the forward uses it) goes to the three
+// scratch fields that the local kernel reads at the same site and then
+// overwrites with dL/dF.
 template <typename T, bool DEV, bool FORCE>
 __global__ __launch_bounds__(kBlock) void k_fd_adj_prep(KParams p, const T* __restrict__ F,
                                                         const double* __restrict__ phi,
-                                                        T* __restrict__ work)
+                                                        T* __restrict__ work, T* __restrict__ sc)
 {
     const int s = xcd_block() * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
@@ -710,6 +713,9 @@ __global__ __launch_bounds__(kBlock) void k_fd_adj_prep(KParams p, const T* __re
         jx = m.jx + T(0.5) * Ft[0];
         jy = m.jy + T(0.5) * Ft[1];
         jz = m.jz + T(0.5) * Ft[2];
+        sc[5 * size_t(p.stride) + s] = Ft[0];
+        sc[6 * size_t(p.stride) + s] = Ft[1];
+        sc[7 * size_t(p.stride) + s] = Ft[2];
     }
     work[s] = m.rho;
     work[p.stride + s] = jx * ri;
@@ -789,10 +795,9 @@ __global__ __launch_bounds__(kBlock) void k_fd_adj_local(KParams p, const double
         lmu *= M;
 
         if (FORCE) {
-            // forcing collision of f, transposed (full second moment M2)
-            double Fd[3];
-            force_from_phi(p, q, phi, Fd);
-            const T Fx = T(Fd[0]), Fy = T(Fd[1]), Fz = T(Fd[2]);
+            // forcing collision of f, transposed (full second moment M2);
+            // F of this site from the pre-pass, in the slots dL/dF replaces
+            const T Fx = sc[5 * S + s], Fy = sc[6 * S + s], Fz = sc[7 * S + s];
             const T ux = u[0], uy = u[1], uz = u[2];
             const T rho = rhof[s], ri = T(1) / rho;
             T m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0,
@@ -1057,10 +1062,10 @@ hipError_t launch_fd_adj_step(const KParams& p, bool fp32, const void* state, do
         T* ap = static_cast<T*>(adj_prev);                                                    \
         T* sc = static_cast<T*>(adj_scratch);                                                 \
         if (p.force) {                                                                        \
-            k_fd_adj_prep<T, DEV, true><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, w);      \
+            k_fd_adj_prep<T, DEV, true><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, w, sc);  \
             k_fd_adj_local<T, true><<<nb, kBlock, 0, s>>>(p, a.phi, w, an, ap, sc, partials); \
         } else {                                                                              \
-            k_fd_adj_prep<T, DEV, false><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, w);     \
+            k_fd_adj_prep<T, DEV, false><<<fd_grid(p), kBlock, 0, s>>>(p, a.F, a.phi, w, sc); \
             k_fd_adj_local<T, false><<<nb, kBlock, 0, s>>>(p, a.phi, w, an, ap, sc, partials);\
         }                                                                                     \
     }

@@ -121,14 +121,9 @@ def _gpu_from_state(f0, phi0, tgt, T, precision="fp64", coupling="stress", **kw)
     for t in reversed(range(T)):
         lb.adjoint_step(states[t], dth)
     gphi = lb.adjoint_phi0().cpu().numpy()
-    # the level after T reverse steps is buffer T % 2; lambda_f occupies its
-    # first 19 components of `stride` elements, sites in (x, y, z) order
-    n = lb.nsites
-    S = lb.sizes.stride_elems
-    dt = torch.float64 if precision == "fp64" else torch.float32
-    lev = lb.adj_buf[T % 2].view(dt)[:19 * S].view(19, S)[:, :n]
-    lf = lev.double().cpu().numpy().reshape((19,) + tuple(shape))
-    return (L, gphi) + tuple(float(v) for v in dth.cpu()), lf
+    lf, lg = lb.adjoint_dist()
+    assert lg is None
+    return (L, gphi) + tuple(float(v) for v in dth.cpu()), lf.cpu().numpy()
 
 
 @pytest.mark.parametrize("coupling", COUPLINGS)

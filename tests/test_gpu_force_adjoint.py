@@ -116,15 +116,8 @@ def _gpu_from_state(f0, g0, tgt, T, precision="fp64", **kw):
     dth = torch.zeros(3, dtype=torch.float64, device=phiT.device)
     for t in reversed(range(T)):
         lb.adjoint_step(states[t], dth)
-    # the level after T reverse steps is buffer T % 2: lambda_f, the
-    # g-specific parts lg_i, then lp (dL/dg_i = lg_i + lp), each of
-    # `stride` elements with sites in (x, y, z) order
-    n = lb.nsites
-    S = lb.sizes.stride_elems
-    dt = torch.float64 if precision == "fp64" else torch.float32
-    lev = lb.adj_buf[T % 2].view(dt)[:39 * S].view(39, S)[:, :n].double().cpu().numpy()
-    lev = lev.reshape((39,) + tuple(shape))
-    return L, lev[:19], lev[19:38] + lev[38][None], tuple(float(v) for v in dth.cpu())
+    lf, lg = lb.adjoint_dist()
+    return L, lf.cpu().numpy(), lg.cpu().numpy(), tuple(float(v) for v in dth.cpu())
 
 
 @pytest.mark.parametrize("shape", [(6, 5, 7), (2, 3, 1), (1, 4, 9)])
