@@ -186,7 +186,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_local_f64(
 // and the g part's phi, mu terms as in the stress coupling without S2.
 // dPhi/dF (three fields after the five stencil cotangents) reaches phi
 // through Pi at the face neighbours: k_adj_force_pi.
-template <typename T, bool DEV>
+// F_IN: F comes from k_adj_force_f in the dL/dF slots of sc (read at the own
+// site before they are overwritten), instead of being formed here.
+template <typename T, bool DEV, bool F_IN>
 __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* __restrict__ F,
                                                      const double* __restrict__ phi,
                                                      const T* __restrict__ an, T* __restrict__ ap,
@@ -215,11 +217,20 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
                                    phi[site_of(p, q.x, q.ym, q.z)],
                                    phi[site_of(p, q.x, q.y, q.zp)],
                                    phi[site_of(p, q.x, q.y, q.zm)]);
-        double Fd[3];
-        force_from_phi(p, q, phi, Fd);
+        T Fx, Fy, Fz;
+        if (F_IN) {
+            Fx = sc[5 * S + s];
+            Fy = sc[6 * S + s];
+            Fz = sc[7 * S + s];
+        } else {
+            double Fd[3];
+            force_from_phi(p, q, phi, Fd);
+            Fx = T(Fd[0]);
+            Fy = T(Fd[1]);
+            Fz = T(Fd[2]);
+        }
         const Moments<T> m = moments_of<T, DEV>(p, f);
         const T rho = m.rho, ri = T(1) / rho;
-        const T Fx = T(Fd[0]), Fy = T(Fd[1]), Fz = T(Fd[2]);
         const T ux = (m.jx + T(0.5) * Fx) * ri, uy = (m.jy + T(0.5) * Fy) * ri,
                 uz = (m.jz + T(0.5) * Fz) * ri;
         const T phi_c = T(st.phi);
@@ -301,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_local_force_f32(
     const float* __restrict__ an, float* __restrict__ ap, float* __restrict__ sc,
     double* __restrict__ partials)
 {
-    adj_local_force_body<float, true>(p, F, phi, an, ap, sc, partials);
+    adj_local_force_body<float, true, false>(p, F, phi, an, ap, sc, partials);
 }
 
 __global__ __launch_bounds__(kBlock) void k_adj_local_force_f64(
@@ -309,7 +320,25 @@ __global__ __launch_bounds__(kBlock) void k_adj_local_force_f64(
     const double* __restrict__ an, double* __restrict__ ap, double* __restrict__ sc,
     double* __restrict__ partials)
 {
-    adj_local_force_body<double, false>(p, F, phi, an, ap, sc, partials);
+    adj_local_force_body<double, false, true>(p, F, phi, an, ap, sc, partials);
+}
+
+// F = -div Pi of the phi field (T-rounded, as the forward uses it) into the
+// dL/dF slots of sc, one site per thread.  FP64 runs it before its local
+// kernel: formed there, F's six neighbour stencils made that kernel (which
+// holds 256 VGPRs) half again as slow; in FP32 forming it inline costs
+// nothing measurable, and this pass would.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_force_f(KParams p, const double* __restrict__ phi,
+                                                        T* __restrict__ sc)
+{
+    const int s = xcd_block() * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    double Fd[3];
+    force_from_phi(p, geo_of(p, s), phi, Fd);
+    sc[5 * size_t(p.stride) + s] = T(Fd[0]);
+    sc[6 * size_t(p.stride) + s] = T(Fd[1]);
+    sc[7 * size_t(p.stride) + s] = T(Fd[2]);
 }
 
 // F_a(x) = -sum_b [Pi_ab(x + e_b) - Pi_ab(x - e_b)]/2 transposed: Pi(y) takes
@@ -481,6 +510,7 @@ hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
         double* ap = static_cast<double*>(adj_prev);
         double* sc = static_cast<double*>(adj_scratch);
         if (p.force) {
+            k_adj_force_f<double><<<grid_for(p), kBlock, 0, s>>>(p, phi, sc);
             k_adj_local_force_f64<<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
             k_adj_force_pi<double><<<nb, kBlock, 0, s>>>(p, phi, sc, partials2);
         } else {
