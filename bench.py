@@ -420,7 +420,8 @@ def main():
             log(f"adjoint {name}")
             fwd, bwd, g = adjoint_ratio(sh, T, k, prec, ph0, tgt, params, op, cp)
             entry = {"forward_ms": round(fwd, 2), "backward_ms": round(bwd, 2),
-                     "adjoint_over_forward": round(bwd / fwd, 3), "interval": k}
+                     "adjoint_over_forward": round(bwd / fwd, 3), "interval": k,
+                     "order_param": op, "coupling": cp, "warmup_rollouts": 1}
             if prec == "fp32_dev":
                 _, _, g64 = adjoint_ratio(sh, T, k, "fp64", ph0, tgt, params, op, cp)
                 entry["grad_rel_err_vs_fp64"] = {
