@@ -190,3 +190,52 @@ def test_adjoint_directional_derivative_64cubed():
     fdk = (loss(phi0, pr["kappa"] + hk) - loss(phi0, pr["kappa"] - hk)) / (2 * hk)
     print(f"[adjoint 64^3] dL/dkappa: adjoint {float(th[2].grad):.12e} fd {fdk:.12e}", flush=True)
     assert abs(float(th[2].grad) - fdk) <= 1e-6 * abs(fdk)
+
+
+@pytest.mark.parametrize("coupling", ["stress", "force"])
+def test_adjoint_directional_derivative_256cubed(coupling):
+    """The adjoint at the benchmark's 256^3 droplet, where the persistent
+    kernels sweep each XCD's eighth of the lattice in 64 rounds: a 3-step
+    FP64 rollout (checkpoint every 2 steps), <dL/dphi0, v> and dL/dA against
+    central differences of the GPU forward (the LB step is smooth, so the
+    difference is exact to O(h^2))."""
+    from paper_1609_01479_amd.rollout import rollout
+    shape = (256, 256, 256)
+    T = 3
+    pr = dict(lbinputs.SPINODAL_PARAMS)
+    xi = lbinputs.interface_width(pr["A"], pr["kappa"])
+    phi0 = lbinputs.droplet_phi0(shape, 64.0, xi)
+    dev = torch.device("cuda:0")
+    tgt = torch.tensor(lbinputs.lamellar_target(shape, 32, xi), device=dev)
+    rest = {k: pr[k] for k in ("gamma", "tau_f", "tau_g", "rho0")}
+    print(f"[adjoint 256^3] {coupling} x {T}", flush=True)
+
+    def loss(p0, A):
+        lb = make_lb(shape, A=A, coupling=coupling)
+        lb.init_phi(p0)
+        lb.step(T)
+        out = float(0.5 * ((lb.phi() - tgt) ** 2).sum())
+        del lb
+        torch.cuda.empty_cache()
+        return out
+
+    p0 = torch.tensor(phi0, dtype=torch.float64, device=dev, requires_grad=True)
+    th = [torch.tensor(pr[k], dtype=torch.float64, device=dev, requires_grad=True)
+          for k in ("A", "B", "kappa")]
+    phiT = rollout(p0, *th, T, interval=2, coupling=coupling, **rest)
+    L = 0.5 * ((phiT - tgt) ** 2).sum()
+    L.backward()
+    gphi = p0.grad.cpu().numpy()
+    gA = float(th[0].grad)
+    del phiT, L, p0
+    torch.cuda.empty_cache()
+    v = lbinputs.random_field(shape, 3)
+    h = 1e-4
+    fd = (loss(phi0 + h * v, pr["A"]) - loss(phi0 - h * v, pr["A"])) / (2 * h)
+    ad = float((gphi * v).sum())
+    print(f"[adjoint 256^3] {coupling} <grad, v>: adjoint {ad:.12e} fd {fd:.12e}", flush=True)
+    assert abs(ad - fd) <= 1e-6 * abs(fd)
+    hA = 1e-4 * abs(pr["A"])
+    fdA = (loss(phi0, pr["A"] + hA) - loss(phi0, pr["A"] - hA)) / (2 * hA)
+    print(f"[adjoint 256^3] {coupling} dL/dA: adjoint {gA:.12e} fd {fdA:.12e}", flush=True)
+    assert abs(gA - fdA) <= 1e-6 * abs(fdA)
