@@ -397,10 +397,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_force_pi(KParams p, const double
     block_partials<3>(dth, partials);
 }
 
-// lp(x) = a(x) - sum_a D_a b_a (x) + lap c (x).  With dtheta, workgroup 0
-// also adds the step's d/d(A, B, kappa) from the local kernel's nparts block
-// partials, and from k_adj_force_pi's in partials2 if given (instead of a
-// launch of its own).
+// lp(x) = a(x) - sum_a D_a b_a (x) + lap c (x).  With dtheta, workgroups
+// 0-2 also add the step's d/d(A, B, kappa) from the local kernel's nparts
+// block partials, and from k_adj_force_pi's in partials2 if given (instead
+// of a launch of its own).
 template <typename T>
 __device__ __forceinline__ void adj_stencil_site(const KParams& p, int s, const T* __restrict__ sc,
                                                  T* __restrict__ ap)
@@ -430,12 +430,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_stencil(KParams p, const T* __re
 {
     const int s = xcd_block() * kBlock + threadIdx.x;
     if (s < p.nsites) adj_stencil_site<T>(p, s, sc, ap);
-    if (dtheta && blockIdx.x == 0) {
-        reduce_partials_block(partials, nparts, 3, dtheta, true);
-        if (partials2) {
-            __syncthreads();
-            reduce_partials_block(partials2, nparts, 3, dtheta, true);
-        }
+    if (!dtheta) return;
+    // workgroup k < 3 adds component k (one workgroup does all three on a
+    // grid smaller than that), so no workgroup carries the whole reduction
+    const int k0 = gridDim.x >= 3 ? int(blockIdx.x) : 0;
+    const int nk = gridDim.x >= 3 ? 1 : 3;
+    if (int(blockIdx.x) != k0 || k0 >= 3) return;
+    reduce_partials_block(partials + size_t(k0) * nparts, nparts, nk, dtheta + k0, true);
+    if (partials2) {
+        __syncthreads();
+        reduce_partials_block(partials2 + size_t(k0) * nparts, nparts, nk, dtheta + k0, true);
     }
 }
 
@@ -486,7 +490,7 @@ hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
     }
     // one resident round: 256 CUs x 4 workgroups of 256 threads (4 waves per
     // SIMD), each thread looping over its sites; the parameter reduction
-    // (workgroup 0 of the stencil kernel) then reads half the partials of
+    // (in the stencil kernel's first workgroups) then reads half the partials of
     // 2048 workgroups (measured as a launch of its own at 128^3: 9.9 -> 5.5
     // us, k_adj_local unchanged)
     constexpr int kAdjBlocks = 1024;
