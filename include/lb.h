@@ -215,6 +215,14 @@ lb_status lb_step_sums(lb_ctx *ctx, int32_t nsteps, double *sums_dev);
  * must differ. */
 lb_status lb_step_from(lb_ctx *ctx, const void *src_dev, void *dst_dev);
 
+/* lb_step_from that also stores phi of src_dev in phi_dev (device, N FP64
+ * values in dense (x, y, z) order, 256-byte aligned), as the step forms it
+ * (bit-identical to the phi lb_adjoint_step would form), for
+ * lb_adjoint_step_phi.  LB_FP64 with LB_OP_LB only (LB_EINVAL otherwise: FP32
+ * storage keeps phi of the previous level in each level, see
+ * lb_adjoint_step_next; LB_OP_FD holds phi in the level). */
+lb_status lb_step_from_phi(lb_ctx *ctx, const void *src_dev, void *dst_dev, double *phi_dev);
+
 /* Moments of the current (post-propagation) state, as dense FP64 device
  * arrays: rho_dev (N), u_dev (3N: x, y, z planes), phi_dev (N).  Any pointer
  * may be NULL to skip that output.  u = j/rho; with LB_COUPLING_FORCE
@@ -284,6 +292,13 @@ lb_status lb_adjoint_step(lb_ctx *ctx, const void *state_t_dev, double *dtheta3_
  * LB_EALIGN if it is not 256-byte aligned. */
 lb_status lb_adjoint_step_next(lb_ctx *ctx, const void *state_t_dev, const void *state_next_dev,
                                double *dtheta3_dev);
+
+/* lb_adjoint_step with phi of state_t_dev given (phi_t_dev, as stored by
+ * lb_step_from_phi from state_t_dev), so that no phi pass runs; the result
+ * is identical to lb_adjoint_step's only if phi_t_dev really is that field.
+ * LB_FP64 with LB_OP_LB only (LB_EINVAL otherwise). */
+lb_status lb_adjoint_step_phi(lb_ctx *ctx, const void *state_t_dev, const double *phi_t_dev,
+                              double *dtheta3_dev);
 
 /* dL/dphi0 (FP64, N) of the initial state built by lb_init_phi, from the
  * current lambda_0. */

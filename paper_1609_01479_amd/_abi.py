@@ -19,9 +19,9 @@ LB_KERNEL_FUSED, LB_KERNEL_TWO_PASS = 0, 1
 
 # Every symbol include/lb.h declares.
 EXPORTS = ("lb_abi_version", "lb_query_sizes", "lb_create", "lb_destroy", "lb_set_stream",
-           "lb_init_phi", "lb_step", "lb_step_sums", "lb_step_from", "lb_moments", "lb_sums", "lb_get_state", "lb_set_state",
+           "lb_init_phi", "lb_step", "lb_step_sums", "lb_step_from", "lb_step_from_phi", "lb_moments", "lb_sums", "lb_get_state", "lb_set_state",
            "lb_export_dist", "lb_import_dist", "lb_adjoint_seed", "lb_adjoint_step", "lb_adjoint_step_next",
-           "lb_adjoint_phi0", "lb_copy_probe", "lb_status_string", "lb_last_error")
+           "lb_adjoint_step_phi", "lb_adjoint_phi0", "lb_copy_probe", "lb_status_string", "lb_last_error")
 
 
 class LbParams(ctypes.Structure):
@@ -77,6 +77,7 @@ def lib():
         "lb_init_phi": ([vp, dp], ctypes.c_int),
         "lb_step": ([vp, i32], ctypes.c_int),
         "lb_step_from": ([vp, vp, vp], ctypes.c_int),
+        "lb_step_from_phi": ([vp, vp, vp, dp], ctypes.c_int),
         "lb_step_sums": ([vp, i32, dp], ctypes.c_int),
         "lb_moments": ([vp, dp, dp, dp], ctypes.c_int),
         "lb_sums": ([vp, dp], ctypes.c_int),
@@ -87,6 +88,7 @@ def lib():
         "lb_adjoint_seed": ([vp, dp], ctypes.c_int),
         "lb_adjoint_step": ([vp, vp, dp], ctypes.c_int),
         "lb_adjoint_step_next": ([vp, vp, vp, dp], ctypes.c_int),
+        "lb_adjoint_step_phi": ([vp, vp, dp, dp], ctypes.c_int),
         "lb_adjoint_phi0": ([vp, dp], ctypes.c_int),
         "lb_copy_probe": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "lb_status_string": ([ctypes.c_int], ctypes.c_char_p),

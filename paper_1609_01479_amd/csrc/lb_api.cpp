@@ -232,7 +232,8 @@ lb_status lb_init_phi(lb_ctx* ctx, const double* phi0_dev)
 }
 
 // One step from src to dst with the context's scheme.
-static hipError_t one_step(lb_ctx* ctx, const void* src, void* dst, double* sums_dev)
+static hipError_t one_step(lb_ctx* ctx, const void* src, void* dst, double* sums_dev,
+                           double* phi_src_out = nullptr)
 {
     double* work = static_cast<double*>(ctx->b.phi);
     double* part = static_cast<double*>(ctx->b.scratch);
@@ -240,7 +241,7 @@ static hipError_t one_step(lb_ctx* ctx, const void* src, void* dst, double* sums
         return lbk::launch_fd_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel, src, dst, work, part,
                                    sums_dev, ctx->stream);
     return lbk::launch_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel, src, dst, work, part,
-                            sums_dev, ctx->stream);
+                            sums_dev, phi_src_out, ctx->stream);
 }
 
 static lb_status step_n(lb_ctx* ctx, int32_t nsteps, double* sums_dev, const char* name)
@@ -272,6 +273,21 @@ lb_status lb_step_from(lb_ctx* ctx, const void* src_dev, void* dst_dev)
         return fail(LB_EALIGN, "src_dev and dst_dev must be 256-byte aligned");
     hipError_t e = one_step(ctx, src_dev, dst_dev, nullptr);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_step_from");
+}
+
+lb_status lb_step_from_phi(lb_ctx* ctx, const void* src_dev, void* dst_dev, double* phi_dev)
+{
+    if (!ctx || !phi_dev) return fail(LB_EINVAL, "ctx and phi_dev are required");
+    if (ctx->fp32 || ctx->kp.fd)
+        return fail(LB_EINVAL, "lb_step_from_phi is for LB_FP64 with LB_OP_LB (FP32 storage "
+                               "keeps phi in the next level; LB_OP_FD in the level itself)");
+    if (!aligned(phi_dev)) return fail(LB_EALIGN, "phi_dev is not 256-byte aligned");
+    if (!src_dev || !dst_dev) return fail(LB_EINVAL, "src_dev and dst_dev are required");
+    if (src_dev == dst_dev) return fail(LB_EINVAL, "src_dev and dst_dev must differ");
+    if (!aligned(src_dev) || !aligned(dst_dev))
+        return fail(LB_EALIGN, "src_dev and dst_dev must be 256-byte aligned");
+    hipError_t e = one_step(ctx, src_dev, dst_dev, nullptr, phi_dev);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_step_from_phi");
 }
 
 // Moments of the current level, and block partials of its sums in scratch.
@@ -361,8 +377,27 @@ lb_status lb_adjoint_step(lb_ctx* ctx, const void* state_t_dev, double* dtheta3_
     return lb_adjoint_step_next(ctx, state_t_dev, nullptr, dtheta3_dev);
 }
 
+static lb_status adjoint_step(lb_ctx* ctx, const void* state_t_dev, const void* state_next_dev,
+                              const double* phi_t_dev, double* dtheta3_dev);
+
 lb_status lb_adjoint_step_next(lb_ctx* ctx, const void* state_t_dev, const void* state_next_dev,
                                double* dtheta3_dev)
+{
+    return adjoint_step(ctx, state_t_dev, state_next_dev, nullptr, dtheta3_dev);
+}
+
+lb_status lb_adjoint_step_phi(lb_ctx* ctx, const void* state_t_dev, const double* phi_t_dev,
+                              double* dtheta3_dev)
+{
+    if (!ctx || !phi_t_dev) return fail(LB_EINVAL, "ctx and phi_t_dev are required");
+    if (ctx->fp32 || ctx->kp.fd)
+        return fail(LB_EINVAL, "lb_adjoint_step_phi is for LB_FP64 with LB_OP_LB");
+    if (!aligned(phi_t_dev)) return fail(LB_EALIGN, "phi_t_dev is not 256-byte aligned");
+    return adjoint_step(ctx, state_t_dev, nullptr, phi_t_dev, dtheta3_dev);
+}
+
+static lb_status adjoint_step(lb_ctx* ctx, const void* state_t_dev, const void* state_next_dev,
+                              const double* phi_t_dev, double* dtheta3_dev)
 {
     if (!ctx || !state_t_dev) return fail(LB_EINVAL, "ctx and state_t_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
@@ -379,7 +414,7 @@ lb_status lb_adjoint_step_next(lb_ctx* ctx, const void* state_t_dev, const void*
                                              ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
                                              ctx->b.adj_scratch, part, dtheta3_dev, ctx->stream)
                    : lbk::launch_adj_step(ctx->kp, ctx->fp32, state_t_dev, state_next_dev,
-                                          static_cast<double*>(ctx->b.phi),
+                                          phi_t_dev, static_cast<double*>(ctx->b.phi),
                                           ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
                                           ctx->b.adj_scratch, part, dtheta3_dev, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "lb_adjoint_step");

@@ -75,9 +75,11 @@ hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* p
 // [rho, phi, jx, jy, jz] of the source level to sums_out, through block
 // partials in `partials` (at least 5 * max(tc.ntiles * tc.nseg,
 // kMaxPartialBlocks) doubles).
+// phi_src_out (FP64 mode, may be null): also store phi of src there (N
+// FP64 values in site order, bit-identical to launch_phi's).
 hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
                        const void* src, void* dst, double* phi_work, double* partials,
-                       double* sums_out, hipStream_t s);
+                       double* sums_out, double* phi_src_out, hipStream_t s);
 // Force coupling, after the phi pass: the forcing collision from src to dst
 // with phi (all sites, FP64) of src in `phi`.  variant 0: single pass over
 // (y, z) tiles marching along x (tiling tc), Pi in LDS; 1: one site per
@@ -107,10 +109,12 @@ hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, const double*
 // reduced from block partials in `partials` (3 * 1024 doubles; 6 * 1024
 // with the force coupling).  The force coupling needs 8 components of
 // adj_scratch (the stencil cotangents, then dL/dF).
+// phi_given (may be null): phi of `state` (N FP64 values in site order), so
+// that no phi pass is needed.
 hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
-                           const void* state_next, double* phi, const void* adj_next,
-                           void* adj_prev, void* adj_scratch, double* partials, double* dtheta,
-                           hipStream_t s);
+                           const void* state_next, const double* phi_given, double* phi,
+                           const void* adj_next, void* adj_prev, void* adj_scratch,
+                           double* partials, double* dtheta, hipStream_t s);
 // lp of adj_prev from the stencil cotangents in adj_scratch (a, b_x, b_y,
 // b_z, c): lp = a - sum_a D_a b_a + lap c; with dtheta, also
 // dtheta[k] += the sum of the nparts block partials of component k < 3 in

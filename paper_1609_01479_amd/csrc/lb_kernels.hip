@@ -338,7 +338,9 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
                              : g[i];
             stc<SMALL>(dG, pso, i, compb, so, gi);
         }
-        if (REF) dphic[pcbase(x) + rowsite] = c;
+        // FP32: the new level's reference field; FP64: phi of the source
+        // level, if asked for (dphic non-null)
+        if (REF || dphic) dphic[pcbase(x) + rowsite] = c;
     };
 
     // Software-pipelined march (full tiles): the loads of plane x+2's g
@@ -741,8 +743,11 @@ hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* p
 
 hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
                        const void* src, void* dst, double* phi_work, double* partials,
-                       double* sums_out, hipStream_t s)
+                       double* sums_out, double* phi_src_out, hipStream_t s)
 {
+    // FP64 mode: phi of src goes to phi_src_out if given (the work field
+    // otherwise, where a pass needs one)
+    double* phi64 = phi_src_out ? phi_src_out : phi_work;
     int nparts = 0;
     if (p.force) {
         // phi (the new level's phi_c in FP32 mode), then the forcing collision
@@ -750,7 +755,7 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
     {                                                                                          \
         Lvl<T> a = level<T>(const_cast<void*>(src), p, REF);                                   \
         Lvl<T> d = level<T>(dst, p, REF);                                                      \
-        double* phin = REF ? d.phic : phi_work;                                                \
+        double* phin = REF ? d.phic : phi64;                                                   \
         if (sums_out) {                                                                        \
             nparts = reduction_grid(p);                                                        \
             k_moments<T, DEV, REF><<<nparts, kBlock, 0, s>>>(p, a.F, a.G, a.phic, nullptr,     \
@@ -763,7 +768,7 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
 #undef CALL
         {
             hipError_t e = launch_force_collide(p, tc, fp32, variant, src, dst,
-                                                fp32 ? level<float>(dst, p, true).phic : phi_work, s);
+                                                fp32 ? level<float>(dst, p, true).phic : phi64, s);
             if (e != hipSuccess) return e;
         }
         if (sums_out) k_sums_final<<<1, kBlock, 0, s>>>(partials, nparts, 5, sums_out, 0);
@@ -776,7 +781,8 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
         if (variant == 0) {                                                                     \
             nparts = tc.ntiles * tc.nseg;                                                       \
             auto kern = Fused<T>::get(small_arrays(p, sizeof(T)), tc.tz);                      \
-            kern<<<nparts, kFused, 0, s>>>(p, tc, a.F, a.G, a.phic, d.F, d.G, d.phic,           \
+            kern<<<nparts, kFused, 0, s>>>(p, tc, a.F, a.G, a.phic, d.F, d.G,                   \
+                                           REF ? d.phic : phi_src_out,                          \
                                            sums_out ? partials : nullptr);                      \
         } else {                                                                                \
             if (sums_out) {                                                                     \
@@ -785,7 +791,7 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
                                                                  nullptr, nullptr, nullptr,     \
                                                                  partials);                     \
             }                                                                                   \
-            double* phin = REF ? d.phic : phi_work;                                             \
+            double* phin = REF ? d.phic : phi64;                                                \
             k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);                 \
             k_step_2s<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phin,    \
                                                                   d.F, d.G);                    \

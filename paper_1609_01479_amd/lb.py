@@ -157,12 +157,24 @@ class LB:
         with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
             return torch.empty(int(self.sizes.state_bytes), dtype=torch.uint8, device=self.device)
 
-    def step_from(self, src: torch.Tensor, dst: torch.Tensor) -> None:
-        """One step from the time level in `src` into `dst` (caller buffers)."""
+    def step_from(self, src: torch.Tensor, dst: torch.Tensor,
+                  phi_out: torch.Tensor | None = None) -> None:
+        """One step from the time level in `src` into `dst` (caller buffers);
+        phi_out (FP64 storage, LB order parameter): an FP64 device tensor of
+        the lattice's shape that receives phi of `src`, for adjoint_step."""
         for t in (src, dst):
             if t.numel() * t.element_size() != self.sizes.state_bytes:
                 raise ValueError("state buffer has the wrong size")
-        self._call("lb_step_from", _ptr(src), _ptr(dst))
+        if phi_out is None:
+            self._call("lb_step_from", _ptr(src), _ptr(dst))
+        else:
+            self._check_phi(phi_out)
+            self._call("lb_step_from_phi", _ptr(src), _ptr(dst), _ptr(phi_out))
+
+    def _check_phi(self, t: torch.Tensor) -> None:
+        if (t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != self.nsites
+                or t.device != self.device):
+            raise ValueError("phi must be a contiguous FP64 device tensor of the lattice's size")
 
     def moments(self):
         """(rho (nx,ny,nz), u (3,nx,ny,nz), phi (nx,ny,nz)) as FP64 device tensors."""
@@ -223,10 +235,16 @@ class LB:
         self._adj_cur = 0
 
     def adjoint_step(self, state_t: torch.Tensor, dtheta: torch.Tensor | None = None,
-                     next_state: torch.Tensor | None = None) -> None:
+                     next_state: torch.Tensor | None = None,
+                     phi: torch.Tensor | None = None) -> None:
         """One reverse step at state_t; next_state, the level one step later,
-        lets FP32 storage skip recomputing phi (lb_adjoint_step_next)."""
-        if next_state is None:
+        lets FP32 storage skip recomputing phi (lb_adjoint_step_next); phi,
+        phi of state_t from step_from(..., phi_out=), does the same in FP64
+        (lb_adjoint_step_phi)."""
+        if phi is not None:
+            self._check_phi(phi)
+            self._call("lb_adjoint_step_phi", _ptr(state_t), _ptr(phi), _ptr(dtheta))
+        elif next_state is None:
             self._call("lb_adjoint_step", _ptr(state_t), _ptr(dtheta))
         else:
             self._call("lb_adjoint_step_next", _ptr(state_t), _ptr(next_state), _ptr(dtheta))

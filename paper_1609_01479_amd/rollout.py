@@ -59,20 +59,30 @@ class _Rollout(torch.autograd.Function):
         # segment buffers: the checkpoint itself is the segment's first state;
         # the others are recomputed in place by one step each (no copies)
         seg = [None] + [lb.new_state() for _ in range(min(k, T) - 1)]
+        # FP64 storage of the LB order parameter: the recomputing steps also
+        # store phi of each level they start from, so the reverse steps of
+        # those levels skip their phi pass (FP32 storage finds it in the
+        # next level; the finite-difference level holds phi)
+        phis = None
+        if lb.sizes.elem_bytes == 8 and not lb.fd:
+            phis = [torch.empty(lb.shape, dtype=torch.float64, device=lb.device)
+                    for _ in range(min(k, T) - 1)]
         for si in reversed(range(len(ckpts))):
             t0 = si * k
             t1 = min(T, t0 + k)
             seg[0] = ckpts[si]
             for j in range(1, t1 - t0):
-                lb.step_from(seg[j - 1], seg[j])
+                lb.step_from(seg[j - 1], seg[j], phi_out=phis[j - 1] if phis else None)
             for t in reversed(range(t0, t1)):
                 # level t+1: the next buffer of this segment, else the next
                 # segment's checkpoint (none after the last step)
                 if t + 1 < t1:
                     nxt = seg[t + 1 - t0]
+                    phi = phis[t - t0] if phis else None
                 else:
                     nxt = ckpts[si + 1] if si + 1 < len(ckpts) else None
-                lb.adjoint_step(seg[t - t0], dtheta, next_state=nxt)
+                    phi = None
+                lb.adjoint_step(seg[t - t0], dtheta, next_state=nxt, phi=phi)
         dphi0 = lb.adjoint_phi0()
         ctx.lb = None
         ctx.ckpts = None

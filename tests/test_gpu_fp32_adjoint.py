@@ -155,3 +155,52 @@ def test_adjoint_step_next_bit_exact(prec, shape):
         out.append((lb.adjoint_phi0().cpu().numpy(), dth.cpu().numpy()))
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("coupling", ["stress", "force"])
+@pytest.mark.parametrize("kernel", ["fused", "two_pass"])
+@pytest.mark.parametrize("shape", [(6, 5, 7), (5, 4, 128)])
+def test_adjoint_step_phi_bit_exact(coupling, kernel, shape):
+    """FP64: phi stored by lb_step_from_phi is the level's phi bit for bit,
+    and lb_adjoint_step_phi with it gives the adjoint levels and parameter
+    gradients of lb_adjoint_step bit for bit, over 5 reverse steps."""
+    from paper_1609_01479_amd._abi import LbError
+    print(f"[adjoint phi] {coupling} {kernel} {shape}", flush=True)
+    T = 5
+    phi0 = lbinputs.spinodal_phi0(shape, seed=29, amp=0.3)
+    dphi = torch.tensor(lbinputs.random_field(shape, 6), device="cuda:0")
+    out = []
+    for use_phi in (False, True):
+        lb = make_lb(shape, adjoint=True, coupling=coupling, kernel=kernel)
+        lb.init_phi(phi0)
+        states = [lb.get_state()]
+        phis = []
+        for _ in range(T):
+            nxt = lb.new_state()
+            ph = torch.empty(shape, dtype=torch.float64, device="cuda:0")
+            lb.step_from(states[-1], nxt, phi_out=ph)
+            states.append(nxt)
+            phis.append(ph)
+        # the stored phi is the library's phi of that level
+        lb.set_state(states[2])
+        assert torch.equal(lb.phi(), phis[2])
+        dth = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+        lb.adjoint_seed(dphi)
+        for t in reversed(range(T)):
+            lb.adjoint_step(states[t], dth, phi=phis[t] if use_phi else None)
+        lf, lg = lb.adjoint_dist()
+        out.append((lb.adjoint_phi0().cpu().numpy(), dth.cpu().numpy(), lf.cpu().numpy(),
+                    lg.cpu().numpy()))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+    # FP32 storage and the finite-difference scheme reject the calls
+    for kw in (dict(precision="fp32_dev"), dict(order_param="fd")):
+        lb = make_lb(shape, adjoint=True, **kw)
+        lb.init_phi(phi0)
+        s0, s1 = lb.get_state(), lb.new_state()
+        ph = torch.empty(shape, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(LbError):
+            lb.step_from(s0, s1, phi_out=ph)
+        lb.adjoint_seed(dphi)
+        with pytest.raises(LbError):
+            lb.adjoint_step(s0, None, phi=ph)
