@@ -33,9 +33,10 @@ def log(msg):
 
 # Algorithmic HBM bytes per lattice-site update of one step (one launch of the
 # single-pass kernel processes every site once).  The method must read and
-# write the 19 f and 19 g populations once (76 words of the storage type); in
-# FP32 mode the stored time level also carries the FP64 reference order
-# parameter (read once, written once: 16 B).
+# write the 19 f and 19 g populations once: 76 words of the storage type,
+# 304 B (FP32 storage) or 608 B (FP64) -- the roofline's basis.  In FP32 mode
+# the stored time level also carries the FP64 reference order parameter
+# (read once, written once: 16 B), which the kernel moves on top of that.
 def step_bytes_per_site(elem_bytes: int) -> dict:
     extra = 16 if elem_bytes == 4 else 0
     return {"method_min": 76 * elem_bytes, "kernel": 76 * elem_bytes + extra}
@@ -147,6 +148,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2,
+                    help="oracle steps of the 256^3 CPU baseline sample")
     ap.add_argument("--layout", default="rows", choices=["rows", "soa", "aos", "aosoa"],
                     help="distribution layout of the 256^3 legs (default: row-blocked)")
     ap.add_argument("--aosoa-len", type=int, default=64, help="z-sites per block for --layout aosoa")
@@ -156,6 +159,8 @@ def main():
                     help="steps of the 256^3 finite-difference order-parameter lines (0: skip)")
     ap.add_argument("--shard-steps", type=int, default=500,
                     help="steps of the one-GPU-share lines (32 x 256 x 256, 0: skip)")
+    ap.add_argument("--error-steps", type=int, default=2000,
+                    help="steps of the FP32-vs-FP64 error leg on the 256^3 droplet (0: skip)")
     ap.add_argument("--spinodal-steps", type=int, default=1000,
                     help="steps of the extra 128^3 FP64 spinodal throughput line (0: skip)")
     args = ap.parse_args()
@@ -180,7 +185,6 @@ def main():
     log(f"droplet {shape} radius {radius} xi {xi:.5f}")
     phi0 = lbinputs.droplet_phi0(shape, radius, xi, noise=1e-3, seed=lbinputs.SEED_DROPLET)
     nsites = n ** 3
-    total = args.warmup + args.steps
 
     runs = {}
     precs = ["fp32_dev"] + ([] if args.no_fp64 else ["fp64"])
@@ -188,25 +192,23 @@ def main():
     for prec in precs:
         lb = LB(shape, precision=prec, device="cuda:0", **lay, **params)
         lb.init_phi(phi0)
-        s0 = lb.sums().cpu().numpy()
         hist = torch.empty((args.steps, 5), dtype=torch.float64, device="cuda:0")
         log(f"{prec}: warmup {args.warmup}, timing {args.steps} steps (with per-step sums)")
         ms = time_steps(lb, args.steps, args.warmup, sums=hist)
-        s1 = lb.sums().cpu().numpy()
-        rho, u, phi = lb.moments()
         torch.cuda.synchronize()
         h = hist.cpu().numpy()
-        # the same steps without the per-step reduction, for reference, and
-        # five repeats of a tenth of them (min and median per step)
-        ms_plain = time_steps(lb, max(args.steps // 4, 1), 0) * args.steps / max(args.steps // 4, 1)
+        # the same number of steps without the per-step reduction: one launch
+        # of the single-pass kernel per step, timed with HIP events on the
+        # library's stream -- the kernel's average launch duration; and five
+        # repeats of a tenth of them (min and median per step)
+        ms_plain = time_steps(lb, args.steps, 0)
         kr = max(args.steps // 10, 1)
         reps = sorted(time_steps(lb, kr, 0) / kr for _ in range(5))
-        runs[prec] = dict(ms=ms, ms_plain=ms_plain, reps=reps, elem=int(lb.sizes.elem_bytes), sums0=s0,
-                          sums1=s1, u=u.cpu().numpy(), phi=phi.cpu().numpy(),
+        runs[prec] = dict(ms=ms, ms_plain=ms_plain, reps=reps, elem=int(lb.sizes.elem_bytes),
                           max_drift=np.abs(h - h[0]).max(axis=0))
         log(f"{prec}: {ms:.1f} ms -> {nsites * args.steps / (ms * 1e-3) / 1e6:.1f} MLUPS "
             f"(plain steps {ms_plain:.1f} ms)")
-        del lb, rho, u, phi
+        del lb, hist
         torch.cuda.empty_cache()
 
     prim = runs["fp32_dev"]
@@ -216,20 +218,22 @@ def main():
     def roof(run, prec):
         e = run["elem"]
         b = step_bytes_per_site(e)
-        per_step = b["kernel"]
-        # one k_step_fused launch per step; its duration is taken as the timed
-        # region's time per step, which also holds the step's one-block
-        # reduction of the conserved sums (an upper bound on the kernel's own
-        # duration, so `achieved` is a lower bound)
-        t = run["ms"] / args.steps * 1e-3
-        achieved = per_step * nsites / t / 1e9
+        # achieved = the method's algorithmic bytes per launch (304 or 608 B
+        # per site times the N sites one launch updates) / the kernel's
+        # average launch duration (plain steps: one launch each)
+        t = run["ms_plain"] / args.steps * 1e-3
+        achieved = b["method_min"] * nsites / t / 1e9
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": measured_traffic(prec, n, args.layout),
-                "effective_GBps": round(b["method_min"] * nsites / t / 1e9, 1),
-                "bytes_per_site": per_step, "algorithmic_bytes_per_launch": per_step * nsites,
+                "bytes_per_site": b["method_min"],
+                "algorithmic_bytes_per_launch": b["method_min"] * nsites,
                 "kernel": "k_step_fused_f32" if e == 4 else "k_step_fused_f64",
-                "kernel_ms_without_sums": round(run["ms_plain"] / args.steps, 4)}
+                "kernel_ms": round(t * 1e3, 4),
+                "kernel_time_source": f"HIP events around {args.steps} plain steps "
+                                      "(one launch each) on the library's stream",
+                "kernel_bytes_per_site": b["kernel"],
+                "achieved_kernel_bytes_GBps": round(b["kernel"] * nsites / t / 1e9, 1)}
 
     out = {
         "metric": "MLUPS & % peak HBM GB/s, D3Q19 binary 256^3: FP32 vs FP64; adjoint/forward cost",
@@ -261,13 +265,40 @@ def main():
         out["conservation"]["fp64_max_abs_drift_over_run"] = {
             k: float(v) for k, v in zip(("rho", "phi", "jx", "jy", "jz"), r64["max_drift"])}
         out["fp32_over_fp64_speedup"] = round(ms64 / ms_step, 3)
-        dphi = np.abs(prim["phi"] - r64["phi"])
-        du = np.abs(prim["u"] - r64["u"])
-        out["fp32_vs_fp64_error"] = {"after_steps": total,
+
+    # FP32 deviation storage against FP64 on the same droplet over a fixed
+    # number of steps (2000 by default, whatever --steps is): max and RMS of
+    # |phi32 - phi64| at a few points of the run, and of |u32 - u64| at its end
+    if not args.no_fp64 and args.error_steps > 0:
+        log(f"FP32 vs FP64: {args.error_steps} steps of both")
+        l32 = LB(shape, precision="fp32_dev", device="cuda:0", **lay, **params)
+        l64 = LB(shape, precision="fp64", device="cuda:0", **lay, **params)
+        l32.init_phi(phi0)
+        l64.init_phi(phi0)
+        marks = sorted({m for m in (args.error_steps // 4, args.error_steps // 2, args.error_steps)
+                        if m > 0})
+        done, phi_hist = 0, {}
+        for m in marks:
+            l32.step(m - done)
+            l64.step(m - done)
+            done = m
+            d = (l32.phi() - l64.phi()).abs()
+            phi_hist[str(m)] = {"max": float(d.max()), "rms": float(d.square().mean().sqrt())}
+            del d
+        _, u32, p32 = l32.moments()
+        _, u64, p64 = l64.moments()
+        dphi = (p32 - p64).abs()
+        du = (u32 - u64).abs()
+        out["fp32_vs_fp64_error"] = {"after_steps": done,
                                      "phi_max": float(dphi.max()),
-                                     "phi_rms": float(np.sqrt((dphi ** 2).mean())),
+                                     "phi_rms": float(dphi.square().mean().sqrt()),
                                      "u_max": float(du.max()),
-                                     "u_rms": float(np.sqrt((du ** 2).mean()))}
+                                     "u_rms": float(du.square().mean().sqrt()),
+                                     "u64_max": float(u64.abs().max()),
+                                     "phi_by_step": phi_hist,
+                                     "target_phi_max": 1e-5}
+        del l32, l64, u32, u64, p32, p64, dphi, du
+        torch.cuda.empty_cache()
     del runs
 
     # force coupling (body force -div Pi) on the same 256^3 droplet: the phi
@@ -353,7 +384,7 @@ def main():
         sh = (32, 256, 256)
         nsh = 32 * 256 * 256
         phish = np.ascontiguousarray(phi0[n // 2 - 16:n // 2 + 16])  # the slab through the centre
-        for prec, moved in (("fp32_dev", 320), ("fp64", 608)):
+        for prec, moved in (("fp32_dev", 304), ("fp64", 608)):
             lb = LB(sh, precision=prec, device="cuda:0", **lay, **params)
             lb.init_phi(phish)
             log(f"{prec} shard {sh}: {args.shard_steps} steps")
@@ -379,7 +410,8 @@ def main():
         out["fp64_spinodal_128"] = {
             "value": round(n128 / t / 1e6, 1), "unit": "MLUPS", "steps": args.spinodal_steps,
             "ms_per_step": round(ms / args.spinodal_steps, 4),
-            "achieved_GBps": round(step_bytes_per_site(8)["kernel"] * n128 / t / 1e9, 1)}
+            "achieved_GBps": round(step_bytes_per_site(8)["method_min"] * n128 / t / 1e9, 1),
+            "frac": round(step_bytes_per_site(8)["method_min"] * n128 / t / 1e9 / HBM_PEAK_GBPS, 4)}
         del lb
         torch.cuda.empty_cache()
 
@@ -388,16 +420,18 @@ def main():
     from paper_1609_01479_amd.lb import copy_probe_gbps
     probe = copy_probe_gbps(1024 ** 3)
     out["copy_probe_GBps"] = round(probe, 1)
-    out["roofline"]["frac_of_copy_probe"] = round(out["roofline"]["achieved"] / probe, 4)
+    # the kernels' own bytes (FP32: with phi_c) over the copy's rate
+    out["roofline"]["kernel_frac_of_copy_probe"] = round(
+        out["roofline"]["achieved_kernel_bytes_GBps"] / probe, 4)
     if "fp64" in out:
-        out["fp64"]["roofline"]["frac_of_copy_probe"] = round(
-            out["fp64"]["roofline"]["achieved"] / probe, 4)
+        out["fp64"]["roofline"]["kernel_frac_of_copy_probe"] = round(
+            out["fp64"]["roofline"]["achieved_kernel_bytes_GBps"] / probe, 4)
     # the same copy at the footprint of the FP32 step (read one time level,
     # write another: 2 x 320/2 B per site)
     probe_fp = copy_probe_gbps(160 * nsites, reps=10)
     out["copy_probe_same_footprint_GBps"] = round(probe_fp, 1)
-    out["roofline"]["frac_of_copy_probe_same_footprint"] = round(
-        out["roofline"]["achieved"] / probe_fp, 4)
+    out["roofline"]["kernel_frac_of_copy_probe_same_footprint"] = round(
+        out["roofline"]["achieved_kernel_bytes_GBps"] / probe_fp, 4)
 
     if not args.no_adjoint:
         adj = {}
@@ -433,22 +467,42 @@ def main():
         out["adjoint"] = adj
 
     if not args.no_cpu_baseline:
+        # The FP64 oracle as it stands (plain per-site C loops; OpenMP over
+        # sites in its gradient and collision loops; the order-parameter sum,
+        # chemical potential and stress, and streaming serial) on the host cores: a bounded sample of the
+        # headline workload (cpu_steps steps of the same 256^3 droplet), the
+        # 128^3 spinodal input of the FP64 throughput line (5 steps), and one
+        # thread on a 64^3 droplet.  A baseline, not the target.
         import oracle
-        p = oracle.Params(*shape, **params)
-        f, g = oracle.init(p, phi0)
         cores = len(os.sched_getaffinity(0))
         cores = oracle.set_threads(cores)
         cpu = host_cpu_model()
-        log(f"oracle: 1 step at {shape} on {cores} threads ({cpu})")
+        p = oracle.Params(*shape, **params)
+        f, g = oracle.init(p, phi0)
+        log(f"oracle: {args.cpu_steps} steps at {shape} on {cores} threads ({cpu})")
         t0 = time.perf_counter()
-        oracle.run(p, f, g, 1)
+        oracle.run(p, f, g, args.cpu_steps)
         dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(nsites / dt / 1e6, 3), "unit": "MLUPS",
-                               "cores": cores, "kind": "oracle",
-                               "sample": f"1 FP64 step of the same {n}^3 droplet lattice "
-                                         f"({dt:.1f} s) on {cpu}"}
-        # single-thread figure on a 64^3 droplet of the same recipe
+        out["cpu_baseline"] = {"value": round(nsites * args.cpu_steps / dt / 1e6, 3),
+                               "unit": "MLUPS", "cores": cores, "kind": "oracle",
+                               "sample": f"{args.cpu_steps} FP64 steps of the same {n}^3 droplet "
+                                         f"lattice ({dt:.1f} s) on {cpu}; the oracle's OpenMP "
+                                         f"covers its gradient and collision loops, its "
+                                         f"order-parameter sum, chemical stress and "
+                                         f"streaming run serially"}
         del f, g
+        s2 = (128, 128, 128)
+        p2 = oracle.Params(*s2, **params)
+        f2, g2 = oracle.init(p2, lbinputs.spinodal_phi0(s2))
+        t0 = time.perf_counter()
+        oracle.run(p2, f2, g2, 5)
+        dt2 = time.perf_counter() - t0
+        out["cpu_baseline_spinodal_128"] = {"value": round(128 ** 3 * 5 / dt2 / 1e6, 3),
+                                            "unit": "MLUPS", "cores": cores, "kind": "oracle",
+                                            "sample": f"5 FP64 steps of the 128^3 spinodal "
+                                                      f"lattice ({dt2:.1f} s)"}
+        del f2, g2
+        # single-thread figure on a 64^3 droplet of the same recipe
         s1 = (64, 64, 64)
         p1 = oracle.Params(*s1, **params)
         f1, g1 = oracle.init(p1, lbinputs.droplet_phi0(s1, 16.0, xi, noise=1e-3,

@@ -44,6 +44,10 @@
  *    time.  The library never allocates or frees device memory and keeps only
  *    borrowed pointers, which must outlive the context.
  *  - lb_last_error() returns a thread-local text for the last failure.
+ *  - "Passage:" in each declaration names the part of the paper the call
+ *    implements.  The reverse mode, the checkpoint calls and the FP32
+ *    deviation storage are extensions of this project: the paper has no
+ *    adjoint and no reduced-precision storage.
  */
 #ifndef LB_H
 #define LB_H
@@ -55,7 +59,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 3
+#define LB_ABI_VERSION 4
 #define LB_NVEL 19
 
 typedef enum {
@@ -174,45 +178,61 @@ typedef struct {
 
 typedef struct lb_ctx lb_ctx;
 
-/* Library ABI version (LB_ABI_VERSION). */
+/* Library ABI version (LB_ABI_VERSION).  Passage: none (this library's own
+ * versioning). */
 int32_t lb_abi_version(void);
 
 /* Buffer sizes for the given parameters.  Host only; launches nothing.
- * Returns LB_ESHAPE / LB_EINVAL for parameters lb_create would reject. */
+ * Returns LB_ESHAPE / LB_EINVAL for parameters lb_create would reject.
+ * Passage: Sec. 3.2.3, Fig. 2 (targetMalloc): the caller allocates the
+ * target's memory; this call says how much. */
 lb_status lb_query_sizes(const lb_params *p, lb_sizes *out);
 
 /* Create a context on the current HIP device, bound to hip_stream (a
  * hipStream_t; NULL = the null stream).  Copies *p and *b.  The state is
- * undefined until lb_init_phi, lb_set_state or lb_import_dist. */
+ * undefined until lb_init_phi, lb_set_state or lb_import_dist.
+ * Passage: Sec. 3.2.3, Fig. 2 (copyConstToTarget for the model constants;
+ * target pointers handed to the target functions): the context holds the
+ * constants and the caller's target pointers. */
 lb_status lb_create(const lb_params *p, const lb_buffers *b, void *hip_stream, lb_ctx **out);
 
-/* Free the host-side context (never the caller's device memory). NULL is a no-op. */
+/* Free the host-side context (never the caller's device memory). NULL is a no-op.
+ * Passage: Sec. 3.2.3, Fig. 2 (targetFree) -- the caller frees the device
+ * memory it allocated; this frees only what lb_create allocated on the host. */
 void lb_destroy(lb_ctx *ctx);
 
-/* Rebind the context to another stream. */
+/* Rebind the context to another stream.  Passage: Sec. 3.2.3 (a
+ * __targetLaunch__ is asynchronous until targetSynchronize): every call is
+ * ordered on this stream and the caller synchronises. */
 lb_status lb_set_stream(lb_ctx *ctx, void *hip_stream);
 
 /* Initial state from phi0_dev (FP64, nx*ny*nz): rho = rho0 and u = 0
  * (f_i = w_i rho0), all of phi0 in the rest population (g_0 = phi0,
  * g_i = 0 for i > 0; LB_OP_FD: the field phi = phi0).  Resets the time-level
- * index. */
+ * index.  Passage: Sec. 3.2.3, Fig. 2 (copyToTarget) for the hand-over of
+ * phi0; the state built from it is this library's reading (the paper gives
+ * no initial condition for this model). */
 lb_status lb_init_phi(lb_ctx *ctx, const double *phi0_dev);
 
-/* Advance nsteps >= 0 timesteps (asynchronous). */
+/* Advance nsteps >= 0 timesteps (asynchronous).  Passage: Sec. 2.1.1 (the
+ * Ludwig timestep: order parameter gradients, chemical stress, collision,
+ * propagation), each step one or two launches (Fig. 2, __targetLaunch__). */
 lb_status lb_step(lb_ctx *ctx, int32_t nsteps);
 
 /* lb_step that also reduces, inside each step, the FP64 conserved sums of
  * the state the step starts from: sums_dev (device, 5*nsteps FP64) receives
  * [sum rho, sum phi, sum j_x, sum j_y, sum j_z] for each step t at
  * sums_dev[5t..5t+4] (the targetDoubleSum of the paper's host model,
- * Sec. 3.2.3; deterministic, as lb_sums). */
+ * Sec. 3.2.3; deterministic, as lb_sums).  Passage: Sec. 2.1.1 for the
+ * step, Sec. 3.2.3 (targetDoubleSum) for the sums. */
 lb_status lb_step_sums(lb_ctx *ctx, int32_t nsteps, double *sums_dev);
 
 /* One timestep from the caller's time level src_dev to dst_dev (both
  * state_bytes, as written by lb_get_state or a previous lb_step_from),
  * without touching the context's current level.  Used by the reverse mode to
  * recompute the states of a checkpoint segment in place.  src_dev and dst_dev
- * must differ. */
+ * must differ.  Passage: Sec. 2.1.1 (the step); taking the levels from the
+ * caller is a project extension for the reverse mode's recomputation. */
 lb_status lb_step_from(lb_ctx *ctx, const void *src_dev, void *dst_dev);
 
 /* lb_step_from that also stores phi of src_dev in phi_dev (device, N FP64
@@ -220,36 +240,46 @@ lb_status lb_step_from(lb_ctx *ctx, const void *src_dev, void *dst_dev);
  * (bit-identical to the phi lb_adjoint_step would form), for
  * lb_adjoint_step_phi.  LB_FP64 with LB_OP_LB only (LB_EINVAL otherwise: FP32
  * storage keeps phi of the previous level in each level, see
- * lb_adjoint_step_next; LB_OP_FD holds phi in the level). */
+ * lb_adjoint_step_next; LB_OP_FD holds phi in the level).  Passage: none
+ * beyond lb_step_from's (a project extension for the reverse mode). */
 lb_status lb_step_from_phi(lb_ctx *ctx, const void *src_dev, void *dst_dev, double *phi_dev);
 
 /* Moments of the current (post-propagation) state, as dense FP64 device
  * arrays: rho_dev (N), u_dev (3N: x, y, z planes), phi_dev (N).  Any pointer
  * may be NULL to skip that output.  u = j/rho; with LB_COUPLING_FORCE
  * u = (j + F/2)/rho, F = -div Pi of this state (the velocity the collision
- * uses), and lb_sums' momentum sums are those of rho u likewise. */
+ * uses), and lb_sums' momentum sums are those of rho u likewise.
+ * Passage: Sec. 3.2.3, Fig. 2 (copyFromTarget) of the moments of Sec. 2.1.1's
+ * fields (order parameter, fluid density and velocity). */
 lb_status lb_moments(lb_ctx *ctx, double *rho_dev, double *u_dev, double *phi_dev);
 
 /* Global sums of the current state in FP64, written to out5_dev:
  * [sum rho, sum phi, sum j_x, sum j_y, sum j_z].  Deterministic: fixed
- * per-block order, then one fixed-order pass over the block partials. */
+ * per-block order, then one fixed-order pass over the block partials.
+ * Passage: Sec. 3.2.3 (targetDoubleSum, the summation of a per-site array). */
 lb_status lb_sums(lb_ctx *ctx, double *out5_dev);
 
 /* Copy the current time level (state_bytes, opaque internal layout) to /
- * from a caller buffer: lossless checkpoint and restore. */
+ * from a caller buffer: lossless checkpoint and restore.  Passage: none (a
+ * project extension: the checkpoints of the reverse mode's rollout); the
+ * copies themselves are target-to-target transfers in the sense of
+ * Sec. 3.2.3. */
 lb_status lb_get_state(lb_ctx *ctx, void *dst_dev);
 lb_status lb_set_state(lb_ctx *ctx, const void *src_dev);
 
 /* Current state as dense FP64 post-propagation distributions, each of shape
  * (19, nx, ny, nz); either pointer may be NULL.  LB_OP_FD has no g: g_dev
- * must be NULL (LB_EINVAL). */
+ * must be NULL (LB_EINVAL).  Passage: Sec. 3.2.3, Fig. 2 (copyFromTarget);
+ * the stored layout is internal (Sec. 3.1's choice of layout is made inside
+ * the library), the exported one dense. */
 lb_status lb_export_dist(lb_ctx *ctx, double *f_dev, double *g_dev);
 
 /* Set the current state from dense FP64 post-propagation distributions
  * (19, nx, ny, nz).  In LB_FP32_DEV phi_c(x) becomes sum_i g_i(x) and the
  * values are rounded to FP32 after subtracting w_i rho0 from f_i and
  * r_i phi_c(x) from g_i(x).  LB_OP_FD: g_dev must be NULL and only f is set
- * (the phi field keeps its values). */
+ * (the phi field keeps its values).  Passage: Sec. 3.2.3, Fig. 2
+ * (copyToTarget), dense in, internal layout (Sec. 3.1) stored. */
 lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
 
 /* ---- reverse mode ------------------------------------------------------
@@ -271,7 +301,14 @@ lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
  * dL/dphi (the g components of adj_bytes are unused), and the upwind choice
  * of each face is held fixed: at a face velocity of exactly zero the
  * derivative taken is that of the phi(x + e_a) branch, the one the forward
- * step takes. */
+ * step takes.
+ *
+ * Passage for every call of this block: none -- the reverse mode is a
+ * project extension (the paper differentiates nothing).  lambda lives in the
+ * two context-held levels adj[0], adj[1] rather than in caller arguments of
+ * each step: a level's layout (39 padded components) is internal, like a
+ * time level's, so callers seed it (lb_adjoint_seed), step it, and read it
+ * through dense copies (lb_adjoint_export, lb_adjoint_phi0). */
 
 /* lambda_T from dphi_dev = dL/dphi_T (FP64, N): dL/df_i = 0; LB_OP_LB:
  * dL/dg_i = dphi for every i; LB_OP_FD: dL/dphi = dphi. */
@@ -304,6 +341,16 @@ lb_status lb_adjoint_step_phi(lb_ctx *ctx, const void *state_t_dev, const double
  * current lambda_0. */
 lb_status lb_adjoint_phi0(lb_ctx *ctx, double *dphi0_dev);
 
+/* The current adjoint level as dense FP64 device arrays of shape
+ * (19, nx, ny, nz): df_dev[i] = dL/df_i and (LB_OP_LB) dg_dev[i] = dL/dg_i =
+ * lg_i + lp, both with respect to the post-propagation populations of the
+ * state the level belongs to (FP32 storage: of the stored deviations, the
+ * same values).  Either pointer may be NULL; with LB_OP_FD dg_dev must be
+ * NULL (LB_EINVAL: there is no g; dL/dphi is lb_adjoint_phi0's output).
+ * Caller-owned, 256-byte aligned (LB_EALIGN), 19*N FP64 values each;
+ * LB_ESTATE without adjoint buffers. */
+lb_status lb_adjoint_export(lb_ctx *ctx, double *df_dev, double *dg_dev);
+
 /* ---- measurement ------------------------------------------------------ */
 
 /* Streaming copy of `bytes` (a multiple of 16) from src_dev to dst_dev on
@@ -312,7 +359,8 @@ lb_status lb_adjoint_phi0(lb_ctx *ctx, double *dphi0_dev);
  * be 256-byte aligned and must not overlap. */
 lb_status lb_copy_probe(const void *src_dev, void *dst_dev, size_t bytes, void *hip_stream);
 
-/* Text for a status code, and the thread-local detail of the last failure. */
+/* Text for a status code, and the thread-local detail of the last failure.
+ * Passage: none (this library's error reporting). */
 const char *lb_status_string(lb_status s);
 const char *lb_last_error(void);
 

@@ -16,12 +16,14 @@ NVEL = 19
 LB_OK, LB_EINVAL, LB_ESHAPE, LB_EALIGN, LB_EHIP, LB_ESTATE = range(6)
 LB_FP64, LB_FP32_DEV = 0, 1
 LB_KERNEL_FUSED, LB_KERNEL_TWO_PASS = 0, 1
+ABI_VERSION = 4
 
 # Every symbol include/lb.h declares.
 EXPORTS = ("lb_abi_version", "lb_query_sizes", "lb_create", "lb_destroy", "lb_set_stream",
            "lb_init_phi", "lb_step", "lb_step_sums", "lb_step_from", "lb_step_from_phi", "lb_moments", "lb_sums", "lb_get_state", "lb_set_state",
            "lb_export_dist", "lb_import_dist", "lb_adjoint_seed", "lb_adjoint_step", "lb_adjoint_step_next",
-           "lb_adjoint_step_phi", "lb_adjoint_phi0", "lb_copy_probe", "lb_status_string", "lb_last_error")
+           "lb_adjoint_step_phi", "lb_adjoint_phi0", "lb_adjoint_export", "lb_copy_probe",
+           "lb_status_string", "lb_last_error")
 
 
 class LbParams(ctypes.Structure):
@@ -90,6 +92,7 @@ def lib():
         "lb_adjoint_step_next": ([vp, vp, vp, dp], ctypes.c_int),
         "lb_adjoint_step_phi": ([vp, vp, dp, dp], ctypes.c_int),
         "lb_adjoint_phi0": ([vp, dp], ctypes.c_int),
+        "lb_adjoint_export": ([vp, dp, dp], ctypes.c_int),
         "lb_copy_probe": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "lb_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "lb_last_error": ([], ctypes.c_char_p),
@@ -98,7 +101,7 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = res
-    if L.lb_abi_version() != 3:
+    if L.lb_abi_version() != ABI_VERSION:
         raise RuntimeError("liblbmi.so ABI version mismatch")
     _lib = L
     return L

@@ -455,6 +455,28 @@ __global__ __launch_bounds__(kBlock) void k_adj_phi0(KParams p, const T* __restr
     out[s] = p.fd ? lp : double(adj[NV * p.stride + s]) + lp;
 }
 
+// Dense FP64 copy of an adjoint level: df[i][s] = lf_i(s) and, LB scheme,
+// dg[i][s] = lg_i(s) + lp(s) = dL/dg_i(s), each (19, nx, ny, nz); the FD
+// scheme has no g (dg is null there).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_export(KParams p, const T* __restrict__ adj,
+                                                       double* __restrict__ df,
+                                                       double* __restrict__ dg)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= p.nsites) return;
+    const long long n = p.nsites;
+    if (df)
+#pragma unroll
+        for (int i = 0; i < NV; i++) df[i * n + s] = double(adj[size_t(i) * p.stride + s]);
+    if (dg) {
+        const double lp = double(adj[size_t(2 * NV) * p.stride + s]);
+#pragma unroll
+        for (int i = 0; i < NV; i++)
+            dg[i * n + s] = double(adj[size_t(NV + i) * p.stride + s]) + lp;
+    }
+}
+
 int grid_for(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
 
 int reduction_grid(const KParams& p)
@@ -562,6 +584,17 @@ hipError_t launch_adj_phi0(const KParams& p, bool fp32, const void* adj, double*
         k_adj_phi0<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const float*>(adj), dphi0);
     else
         k_adj_phi0<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const double*>(adj), dphi0);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_export(const KParams& p, bool fp32, const void* adj, double* df, double* dg,
+                             hipStream_t s)
+{
+    if (fp32)
+        k_adj_export<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const float*>(adj), df, dg);
+    else
+        k_adj_export<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<const double*>(adj), df,
+                                                            dg);
     return hipGetLastError();
 }
 

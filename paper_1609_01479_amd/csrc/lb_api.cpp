@@ -431,4 +431,17 @@ lb_status lb_adjoint_phi0(lb_ctx* ctx, double* dphi0_dev)
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_phi0");
 }
 
+lb_status lb_adjoint_export(lb_ctx* ctx, double* df_dev, double* dg_dev)
+{
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
+    if (ctx->kp.fd && dg_dev) return fail(LB_EINVAL, "LB_OP_FD has no g: dg_dev must be NULL");
+    if ((df_dev && !aligned(df_dev)) || (dg_dev && !aligned(dg_dev)))
+        return fail(LB_EALIGN, "df_dev and dg_dev must be 256-byte aligned");
+    if (!df_dev && !dg_dev) return LB_OK;
+    hipError_t e = lbk::launch_adj_export(ctx->kp, ctx->fp32, ctx->b.adj[ctx->adj_cur], df_dev,
+                                          dg_dev, ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_export");
+}
+
 }  // extern "C"

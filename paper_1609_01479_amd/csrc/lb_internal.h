@@ -131,6 +131,10 @@ hipError_t launch_adj_force_pi(const KParams& p, bool fp32, const double* phi, v
 // dL/dphi0 from the level in `adj` (LB scheme: lg_0 + lp; FD scheme: lp).
 hipError_t launch_adj_phi0(const KParams& p, bool fp32, const void* adj, double* dphi0,
                            hipStream_t s);
+// Dense FP64 (19, nx, ny, nz) copies of the level in `adj`: df = lf and
+// (LB scheme; null for FD) dg = lg + lp.  Either pointer may be null.
+hipError_t launch_adj_export(const KParams& p, bool fp32, const void* adj, double* df, double* dg,
+                             hipStream_t s);
 
 // Finite-difference order parameter (lb_fd.hip).  A time level is F
 // (19*stride elements, laid out per KParams) then phi (stride FP64 values).

@@ -69,7 +69,6 @@ class LB:
                                     LAYOUTS[layout], int(aosoa_len), COUPLINGS[coupling],
                                     ORDER_PARAMS[order_param])
         self.fd = self.params.order_param == ORDER_PARAMS["fd"]
-        self._adj_cur = 0  # adjoint buffer holding the current level
         self.sizes = _abi.LbSizes()
         check(L.lb_query_sizes(ctypes.byref(self.params), ctypes.byref(self.sizes)),
               "lb_query_sizes")
@@ -232,7 +231,6 @@ class LB:
         self._sync_inputs()
         self._call("lb_adjoint_seed", _ptr(t))
         t.record_stream(self.stream)
-        self._adj_cur = 0
 
     def adjoint_step(self, state_t: torch.Tensor, dtheta: torch.Tensor | None = None,
                      next_state: torch.Tensor | None = None,
@@ -248,22 +246,16 @@ class LB:
             self._call("lb_adjoint_step", _ptr(state_t), _ptr(dtheta))
         else:
             self._call("lb_adjoint_step_next", _ptr(state_t), _ptr(next_state), _ptr(dtheta))
-        self._adj_cur = 1 - self._adj_cur
 
     def adjoint_dist(self):
         """(dL/df, dL/dg) of the current adjoint level as FP64 (19, nx, ny, nz)
-        tensors (copies; dL/dg is None for the finite-difference order
-        parameter, whose dL/dphi is adjoint_phi0())."""
+        tensors (lb_adjoint_export; dL/dg is None for the finite-difference
+        order parameter, whose dL/dphi is adjoint_phi0())."""
         if self.adj_buf[0] is None:
             raise RuntimeError("created without adjoint buffers")
-        S = int(self.sizes.stride_elems)
-        n = self.nsites
-        dt = torch.float64 if self.sizes.elem_bytes == 8 else torch.float32
-        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
-            lev = self.adj_buf[self._adj_cur].view(dt)[:39 * S].view(39, S)[:, :n].double()
-            lf = lev[:NVEL].reshape((NVEL,) + self.shape)
-            lg = None if self.fd else (lev[NVEL:2 * NVEL] + lev[2 * NVEL][None]).reshape(
-                (NVEL,) + self.shape)
+        lf = self._out(NVEL, *self.shape)
+        lg = None if self.fd else self._out(NVEL, *self.shape)
+        self._call("lb_adjoint_export", _ptr(lf), _ptr(lg))
         return lf, lg
 
     def adjoint_phi0(self) -> torch.Tensor:

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(abi):
     L = abi.lib()
     for name in _declared_functions():
         assert hasattr(L, name), name
-    assert L.lb_abi_version() == 3
+    assert L.lb_abi_version() == abi.ABI_VERSION == 4
 
 
 def _params(abi, **kw):
@@ -117,6 +117,8 @@ def test_fd_order_parameter_sizes_and_calls_without_launching(abi, prec, e):
     assert L.lb_export_dist(ctx, v, v) == abi.LB_EINVAL
     assert L.lb_import_dist(ctx, v, v) == abi.LB_EINVAL
     assert L.lb_import_dist(ctx, None, None) == abi.LB_EINVAL
+    # no g: the adjoint export takes dL/df only
+    assert L.lb_adjoint_export(ctx, v, v) == abi.LB_EINVAL
     L.lb_destroy(ctx)
 
 
@@ -151,6 +153,14 @@ def test_create_validates_buffers_without_launching(abi):
     assert L.lb_step_from(ctx, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2010)) == abi.LB_EALIGN
     assert L.lb_step_from(ctx, None, ctypes.c_void_p(0x2000)) == abi.LB_EINVAL
     assert L.lb_adjoint_seed(ctx, ctypes.c_void_p(0x1000)) == abi.LB_ESTATE
+    assert L.lb_adjoint_export(ctx, ctypes.c_void_p(0x1000), None) == abi.LB_ESTATE
+    assert L.lb_adjoint_export(None, ctypes.c_void_p(0x1000), None) == abi.LB_EINVAL
+    L.lb_destroy(ctx)
+    b.adj[0], b.adj[1], b.adj_scratch = 0x5000, 0x6000, 0x7000
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
+    assert L.lb_adjoint_export(ctx, ctypes.c_void_p(0x1010), None) == abi.LB_EALIGN
+    assert L.lb_adjoint_export(ctx, None, ctypes.c_void_p(0x1010)) == abi.LB_EALIGN
+    assert L.lb_adjoint_export(ctx, None, None) == abi.LB_OK  # nothing to copy
     L.lb_destroy(ctx)
     L.lb_destroy(None)
 
