@@ -266,6 +266,25 @@ def main():
             k: float(v) for k, v in zip(("rho", "phi", "jx", "jy", "jz"), r64["max_drift"])}
         out["fp32_over_fp64_speedup"] = round(ms64 / ms_step, 3)
 
+    # the single-pass kernel's memory-only twin (LB_KERNEL_STREAM: the same
+    # loads, phi sums and stores with the collision left out) on the same
+    # lattice: the memory-bound floor of this kernel's access pattern
+    out["stream_twin"] = {}
+    for prec in precs:
+        lb = LB(shape, precision=prec, kernel="stream", device="cuda:0", **lay, **params)
+        lb.init_phi(phi0)
+        log(f"{prec}: memory-only twin, {args.steps} steps")
+        ms_twin = time_steps(lb, args.steps, args.warmup)
+        e = int(lb.sizes.elem_bytes)
+        t = ms_twin / args.steps * 1e-3
+        kb = step_bytes_per_site(e)["kernel"]
+        key = "fp32_dev" if e == 4 else "fp64"
+        out["stream_twin"][key] = {
+            "ms_per_step": round(t * 1e3, 4), "GBps_kernel_bytes": round(kb * nsites / t / 1e9, 1),
+            "step_over_twin": round(runs[key]["ms_plain"] / ms_twin, 4)}
+        del lb
+        torch.cuda.empty_cache()
+
     # FP32 deviation storage against FP64 on the same droplet over a fixed
     # number of steps (2000 by default, whatever --steps is): max and RMS of
     # |phi32 - phi64| at a few points of the run, and of |u32 - u64| at its end

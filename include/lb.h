@@ -84,7 +84,15 @@ typedef enum {
 typedef enum {
     LB_KERNEL_FUSED = 0,   /* one pass per step: phi, gradients, stress,
                               collision and propagation in one kernel      */
-    LB_KERNEL_TWO_PASS = 1 /* a phi pass, then the stencil/collision pass  */
+    LB_KERNEL_TWO_PASS = 1, /* a phi pass, then the stencil/collision pass */
+    LB_KERNEL_STREAM = 2    /* measurement twin of LB_KERNEL_FUSED: the same
+                               kernel, loads, phi sums and stores with the
+                               collision left out, i.e. free streaming
+                               f_i(x + c_i, t+1) = f_i(x, t) (not a model of
+                               the fluid; the memory-bound floor of the
+                               fused step; LB_OP_LB with LB_COUPLING_STRESS
+                               only, LB_EINVAL otherwise; the reverse-mode
+                               calls return LB_ESTATE)                      */
 } lb_kernel;
 
 /* How the chemical stress Pi drives the flow (two forms of the same

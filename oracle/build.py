@@ -7,6 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lb_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+CHECK_SRC = os.path.join(HERE, "sanitize_check.c")
+CHECK_EXE = os.path.join(HERE, "sanitize_check")
 
 
 def build(verbose: bool = False) -> str:
@@ -17,6 +19,19 @@ def build(verbose: bool = False) -> str:
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
+
+
+def build_sanitize_check(verbose: bool = False) -> str:
+    """The oracle and a driver of all its entry points, built with
+    AddressSanitizer and UndefinedBehaviorSanitizer (host code only; any
+    report aborts the run with a nonzero exit)."""
+    cmd = ["gcc", "-O1", "-g", "-fopenmp", "-std=c11", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-o", CHECK_EXE, CHECK_SRC, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return CHECK_EXE
 
 
 if __name__ == "__main__":

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "liblbmi.so")
 NVEL = 19
 LB_OK, LB_EINVAL, LB_ESHAPE, LB_EALIGN, LB_EHIP, LB_ESTATE = range(6)
 LB_FP64, LB_FP32_DEV = 0, 1
-LB_KERNEL_FUSED, LB_KERNEL_TWO_PASS = 0, 1
+LB_KERNEL_FUSED, LB_KERNEL_TWO_PASS, LB_KERNEL_STREAM = 0, 1, 2
 ABI_VERSION = 4
 
 # Every symbol include/lb.h declares.

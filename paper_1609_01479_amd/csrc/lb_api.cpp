@@ -70,8 +70,12 @@ lb_status validate(const lb_params* p)
     if (!(p->rho0 > 0.0)) return fail(LB_EINVAL, "rho0 must be positive (got %g)", p->rho0);
     if (p->precision != LB_FP64 && p->precision != LB_FP32_DEV)
         return fail(LB_EINVAL, "unknown precision %d", p->precision);
-    if (p->kernel != LB_KERNEL_FUSED && p->kernel != LB_KERNEL_TWO_PASS)
+    if (p->kernel != LB_KERNEL_FUSED && p->kernel != LB_KERNEL_TWO_PASS &&
+        p->kernel != LB_KERNEL_STREAM)
         return fail(LB_EINVAL, "unknown kernel variant %d", p->kernel);
+    if (p->kernel == LB_KERNEL_STREAM &&
+        (p->coupling != LB_COUPLING_STRESS || p->order_param != LB_OP_LB))
+        return fail(LB_EINVAL, "LB_KERNEL_STREAM is the twin of the LB_OP_LB stress-coupled step");
     if (p->layout < LB_LAYOUT_ROWS || p->layout > LB_LAYOUT_AOSOA)
         return fail(LB_EINVAL, "unknown layout %d", p->layout);
     if (p->coupling != LB_COUPLING_STRESS && p->coupling != LB_COUPLING_FORCE)
@@ -367,6 +371,8 @@ lb_status lb_adjoint_seed(lb_ctx* ctx, const double* dphi_dev)
 {
     if (!ctx || !dphi_dev) return fail(LB_EINVAL, "ctx and dphi_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
+    if (ctx->p.kernel == LB_KERNEL_STREAM)
+        return fail(LB_ESTATE, "LB_KERNEL_STREAM (free streaming) has no reverse mode");
     ctx->adj_cur = 0;
     hipError_t e = lbk::launch_adj_seed(ctx->kp, ctx->fp32, ctx->b.adj[0], dphi_dev, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_seed");
@@ -401,6 +407,8 @@ static lb_status adjoint_step(lb_ctx* ctx, const void* state_t_dev, const void* 
 {
     if (!ctx || !state_t_dev) return fail(LB_EINVAL, "ctx and state_t_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
+    if (ctx->p.kernel == LB_KERNEL_STREAM)
+        return fail(LB_ESTATE, "LB_KERNEL_STREAM (free streaming) has no reverse mode");
     if (!aligned(state_t_dev)) return fail(LB_EALIGN, "state_t_dev is not 256-byte aligned");
     if (state_next_dev && !aligned(state_next_dev))
         return fail(LB_EALIGN, "state_next_dev is not 256-byte aligned");

@@ -33,12 +33,6 @@ namespace {
 // stream 512-byte (FP32) contiguous pieces), or 8 x 64 where that covers nz
 // with fewer idle lanes (e.g. nz = 192: 64 + 64 + 64 instead of 128 + 64).
 constexpr int kFused = 512;
-#ifndef LB_PIPE32
-#define LB_PIPE32 true
-#endif
-#ifndef LB_PIPE64
-#define LB_PIPE64 false
-#endif
 // one thread per halo-ring cell (2 rows, 2 columns, 4 corners)
 static_assert(2 * 128 + 2 * (kFused / 128) + 4 <= kFused, "halo ring larger than the workgroup");
 static_assert(2 * 64 + 2 * (kFused / 64) + 4 <= kFused, "halo ring larger than the workgroup");
@@ -202,7 +196,10 @@ __device__ __forceinline__ Yz9 yz9(const KParams& p, int y, int z)
 // site); the store of direction i needs phi at the destination y + c_i, which
 // the LDS phi ring already holds (its halo then includes the tile's 4 corner
 // cells, for the directions with c_x = 0 and c_y, c_z != 0).
-template <typename T, bool DEV, bool REF, bool SMALL, bool PIPE, int TZ>
+// COLL = false is the kernel's memory-only twin (LB_KERNEL_STREAM): every
+// load, LDS ring, phi sum and store of the step, with the collision left out,
+// so the populations stream freely, f_i(x + c_i, t+1) = f_i(x, t).
+template <typename T, bool DEV, bool REF, bool SMALL, bool PIPE, int TZ, bool COLL>
 __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg& tc,
                                                 const T* __restrict__ sF,
                                                 const T* __restrict__ sG,
@@ -327,7 +324,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
             acc[3] += jy;
             acc[4] += jz;
         }
-        collide<T, DEV, REF>(p, f, g, st);
+        if (COLL) collide<T, DEV, REF>(p, f, g, st);
         const O pso = pbase(x);
         const unsigned so = row.o[1][1];
 #pragma unroll
@@ -459,45 +456,56 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     if (partials) block_partials<5, kFused>(acc, partials);
 }
 
-template <bool SMALL, int TZ>
+template <bool SMALL, int TZ, bool COLL>
 __global__ __launch_bounds__(kFused) void k_step_fused_f32(
     KParams p, TileCfg tc, const float* __restrict__ sF, const float* __restrict__ sG,
     const double* __restrict__ sphic, float* __restrict__ dF, float* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<float, true, true, SMALL, LB_PIPE32, TZ>(p, tc, sF, sG, sphic, dF, dG, dphic,
-                                                             partials);
+    step_fused_body<float, true, true, SMALL, true, TZ, COLL>(p, tc, sF, sG, sphic, dF, dG, dphic,
+                                                              partials);
 }
 
-template <bool SMALL, int TZ>
+template <bool SMALL, int TZ, bool COLL>
 __global__ __launch_bounds__(kFused) void k_step_fused_f64(
     KParams p, TileCfg tc, const double* __restrict__ sF, const double* __restrict__ sG,
     const double* __restrict__ sphic, double* __restrict__ dF, double* __restrict__ dG,
     double* __restrict__ dphic, double* __restrict__ partials)
 {
-    step_fused_body<double, false, false, SMALL, LB_PIPE64, TZ>(p, tc, sF, sG, sphic, dF, dG,
-                                                                dphic, partials);
+    step_fused_body<double, false, false, SMALL, false, TZ, COLL>(p, tc, sF, sG, sphic, dF, dG,
+                                                                  dphic, partials);
 }
 
-// the single-pass kernel for an offset width and a tile width
+// the single-pass kernel (or, coll = false, its free-streaming twin) for an
+// offset width and a tile width
 template <typename T>
 struct Fused;
 template <>
 struct Fused<float> {
-    using K = decltype(&k_step_fused_f32<true, 128>);
-    static K get(bool small, int tz)
+    using K = decltype(&k_step_fused_f32<true, 128, true>);
+    template <bool COLL>
+    static K pick(bool small, int tz)
     {
-        if (tz == 64) return small ? k_step_fused_f32<true, 64> : k_step_fused_f32<false, 64>;
-        return small ? k_step_fused_f32<true, 128> : k_step_fused_f32<false, 128>;
+        if (tz == 64) return small ? k_step_fused_f32<true, 64, COLL> : k_step_fused_f32<false, 64, COLL>;
+        return small ? k_step_fused_f32<true, 128, COLL> : k_step_fused_f32<false, 128, COLL>;
+    }
+    static K get(bool small, int tz, bool coll)
+    {
+        return coll ? pick<true>(small, tz) : pick<false>(small, tz);
     }
 };
 template <>
 struct Fused<double> {
-    using K = decltype(&k_step_fused_f64<true, 128>);
-    static K get(bool small, int tz)
+    using K = decltype(&k_step_fused_f64<true, 128, true>);
+    template <bool COLL>
+    static K pick(bool small, int tz)
     {
-        if (tz == 64) return small ? k_step_fused_f64<true, 64> : k_step_fused_f64<false, 64>;
-        return small ? k_step_fused_f64<true, 128> : k_step_fused_f64<false, 128>;
+        if (tz == 64) return small ? k_step_fused_f64<true, 64, COLL> : k_step_fused_f64<false, 64, COLL>;
+        return small ? k_step_fused_f64<true, 128, COLL> : k_step_fused_f64<false, 128, COLL>;
+    }
+    static K get(bool small, int tz, bool coll)
+    {
+        return coll ? pick<true>(small, tz) : pick<false>(small, tz);
     }
 };
 
@@ -778,9 +786,9 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
     {                                                                                           \
         Lvl<T> a = level<T>(const_cast<void*>(src), p, REF);                                    \
         Lvl<T> d = level<T>(dst, p, REF);                                                       \
-        if (variant == 0) {                                                                     \
+        if (variant != 1) {                                                                     \
             nparts = tc.ntiles * tc.nseg;                                                       \
-            auto kern = Fused<T>::get(small_arrays(p, sizeof(T)), tc.tz);                      \
+            auto kern = Fused<T>::get(small_arrays(p, sizeof(T)), tc.tz, variant == 0);        \
             kern<<<nparts, kFused, 0, s>>>(p, tc, a.F, a.G, a.phic, d.F, d.G,                   \
                                            REF ? d.phic : phi_src_out,                          \
                                            sums_out ? partials : nullptr);                      \

@@ -19,6 +19,9 @@ from ._abi import LB_FP32_DEV, LB_FP64, NVEL, check
 LAYOUTS = {"rows": 0, "soa": 1, "aos": 2, "aosoa": 3}
 # how the chemical stress drives the flow (lb_coupling)
 COUPLINGS = {"stress": 0, "force": 1}
+# step kernels (lb_kernel): one pass, a phi pass plus a collision pass (the
+# same results), or the one-pass kernel's memory-only twin (free streaming)
+KERNELS = {"fused": 0, "two_pass": 1, "stream": 2}
 # how the order parameter evolves (lb_order_param): LB distribution g, or a
 # field with the finite-difference Cahn-Hilliard update and upwind advection
 ORDER_PARAMS = {"lb": 0, "fd": 1}
@@ -42,7 +45,9 @@ class LB:
     shape: (nx, ny, nz) periodic extents.  Model parameters as in lb.h.
     precision: "fp64" or "fp32_dev" (FP32 deviation storage).
     adjoint: also allocate the reverse-mode buffers.
-    kernel: "fused" (one pass per step) or "two_pass" (phi pass + collision pass).
+    kernel: "fused" (one pass per step) or "two_pass" (phi pass + collision pass);
+        "stream" is the fused kernel's memory-only twin (free streaming, no
+        collision), for measurement.
     segment_x: x planes per workgroup of the fused kernel (0 = automatic).
     layout: memory layout of the distributions, "rows" (row-blocked, default),
         "soa", "aos" or "aosoa" with aosoa_len z-sites per block (a power of
@@ -65,7 +70,7 @@ class LB:
         self.precision = _precision_code(precision)
         self.params = _abi.LbParams(nx, ny, nz, float(A), float(B), float(kappa), float(gamma),
                                     float(tau_f), float(tau_g), float(rho0), self.precision,
-                                    {"fused": 0, "two_pass": 1}[kernel], int(segment_x),
+                                    KERNELS[kernel], int(segment_x),
                                     LAYOUTS[layout], int(aosoa_len), COUPLINGS[coupling],
                                     ORDER_PARAMS[order_param])
         self.fd = self.params.order_param == ORDER_PARAMS["fd"]

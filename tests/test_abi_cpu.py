@@ -68,7 +68,9 @@ def test_query_sizes(abi):
     (dict(nx=1, ny=8192, nz=4096), "LB_ESHAPE"),  # one FP64 x-plane of f >= 4 GiB
     (dict(tau_f=0.5), "LB_EINVAL"), (dict(tau_g=0.2), "LB_EINVAL"),
     (dict(tau_f=float("nan")), "LB_EINVAL"), (dict(rho0=0.0), "LB_EINVAL"),
-    (dict(precision=7), "LB_EINVAL"), (dict(kernel=2), "LB_EINVAL"),
+    (dict(precision=7), "LB_EINVAL"), (dict(kernel=3), "LB_EINVAL"),
+    (dict(kernel=-1), "LB_EINVAL"),
+    (dict(kernel=2, coupling=1), "LB_EINVAL"), (dict(kernel=2, order_param=1), "LB_EINVAL"),
     (dict(layout=4), "LB_EINVAL"), (dict(layout=-1), "LB_EINVAL"),
     (dict(layout=3, aosoa_len=3), "LB_ESHAPE"), (dict(layout=3, aosoa_len=0), "LB_ESHAPE"),
     (dict(layout=3, aosoa_len=64, nz=96), "LB_ESHAPE"),
@@ -207,6 +209,7 @@ def test_struct_layouts_and_enums_match_the_header(abi, tmp_path):
              "LB_EALIGN": abi.LB_EALIGN, "LB_EHIP": abi.LB_EHIP, "LB_ESTATE": abi.LB_ESTATE,
              "LB_FP64": abi.LB_FP64, "LB_FP32_DEV": abi.LB_FP32_DEV,
              "LB_KERNEL_FUSED": abi.LB_KERNEL_FUSED, "LB_KERNEL_TWO_PASS": abi.LB_KERNEL_TWO_PASS,
+             "LB_KERNEL_STREAM": abi.LB_KERNEL_STREAM,
              "LB_NVEL": abi.NVEL, "LB_ABI_VERSION": abi.lib().lb_abi_version(),
              "LB_LAYOUT_ROWS": lbpy.LAYOUTS["rows"], "LB_LAYOUT_SOA": lbpy.LAYOUTS["soa"],
              "LB_LAYOUT_AOS": lbpy.LAYOUTS["aos"], "LB_LAYOUT_AOSOA": lbpy.LAYOUTS["aosoa"],
