@@ -139,6 +139,47 @@ def adjoint_ratio(shape, T, interval, precision, phi0, tgt, params, order_param=
     return fwd_ms, bwd_ms, grads
 
 
+def mixed_rollout_grads(shape, T, k, fwd_prec, adj_prec, phi0, tgt, params):
+    """dL/dphi0 and dL/d(A, B, kappa) of the LB-scheme rollout (stress
+    coupling, loss 1/2 sum (phi_T - tgt)^2) with the trajectory stepped in
+    fwd_prec storage and the adjoint steps taken in adj_prec storage: every
+    (recomputed) state of the trajectory is exported as dense FP64
+    distributions and imported into the adjoint's context, whose reverse step
+    then linearises the step there.  Separates the error of an FP32 forward
+    trajectory from that of FP32 adjoint arithmetic and storage."""
+    import torch
+    from paper_1609_01479_amd import LB
+    dev = torch.device("cuda:0")
+    fw = LB(shape, precision=fwd_prec, device=dev, **params)
+    ad = LB(shape, precision=adj_prec, adjoint=True, device=dev, **params)
+    fw.init_phi(phi0)
+    ckpts, t = [], 0
+    while t < T:
+        ckpts.append(fw.get_state())
+        n = min(k, T - t)
+        fw.step(n)
+        t += n
+    phiT = fw.phi()
+    ad.adjoint_seed(phiT - torch.tensor(tgt, device=dev))
+    dtheta = torch.zeros(3, dtype=torch.float64, device=dev)
+    seg = [None] + [fw.new_state() for _ in range(min(k, T) - 1)]
+    buf = ad.new_state()
+    for si in reversed(range(len(ckpts))):
+        t0, t1 = si * k, min(T, si * k + k)
+        seg[0] = ckpts[si]
+        for j in range(1, t1 - t0):
+            fw.step_from(seg[j - 1], seg[j])
+        for t in reversed(range(t0, t1)):
+            fw.set_state(seg[t - t0])
+            f, g = fw.export_dist()
+            ad.import_dist(f, g)
+            ad.get_state(buf)
+            ad.adjoint_step(buf, dtheta)
+    dphi0 = ad.adjoint_phi0()
+    torch.cuda.synchronize()
+    return dphi0.cpu().numpy(), [float(v) for v in dtheta.cpu()]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +200,9 @@ def main():
                     help="steps of the 256^3 finite-difference order-parameter lines (0: skip)")
     ap.add_argument("--shard-steps", type=int, default=500,
                     help="steps of the one-GPU-share lines (32 x 256 x 256, 0: skip)")
+    ap.add_argument("--grad-attribution", action="store_true",
+                    help="attribute the FP32 adjoint's gradient error (128^3, T=1000, k=32) "
+                         "to the trajectory or the adjoint precision")
     ap.add_argument("--error-steps", type=int, default=2000,
                     help="steps of the FP32-vs-FP64 error leg on the 256^3 droplet (0: skip)")
     ap.add_argument("--spinodal-steps", type=int, default=1000,
@@ -395,26 +439,54 @@ def main():
             del lb
             torch.cuda.empty_cache()
 
-    # one GPU's share of the 256^3 droplet split into 8 x-slabs: the same
-    # single-pass kernel on a 32 x 256 x 256 lattice (periodic here; a shard
-    # would read its two boundary planes' halos from its neighbours)
+    # one GPU's share of the 256^3 droplet split into 8 x-slabs: a shard of
+    # 32 x 256 x 256 (halo_x) whose step reads halo planes instead of the
+    # periodic wrap; here it receives its own faces (pack + unpack on the
+    # same GPU stand in for the exchange with its neighbours).  Timed: the
+    # step with its face copies, and the face copies alone.
     if args.shard_steps > 0 and n == 256:
         out["shard_32x256x256"] = {}
         sh = (32, 256, 256)
         nsh = 32 * 256 * 256
-        phish = np.ascontiguousarray(phi0[n // 2 - 16:n // 2 + 16])  # the slab through the centre
+        lo, hi = n // 2 - 16, n // 2 + 16  # the slab through the centre
+        phish = np.ascontiguousarray(phi0[lo - 1:hi + 1])
         for prec, moved in (("fp32_dev", 304), ("fp64", 608)):
-            lb = LB(sh, precision=prec, device="cuda:0", **lay, **params)
+            lb = LB(sh, precision=prec, device="cuda:0", halo_x=True, **lay, **params)
             lb.init_phi(phish)
-            log(f"{prec} shard {sh}: {args.shard_steps} steps")
-            ms = time_steps(lb, args.shard_steps, args.warmup)
+            faces = (lb.new_face(), lb.new_face())
+
+            def exchange():
+                lb.pack_faces(*faces)
+                lb.unpack_faces(faces[1], faces[0])
+
+            def timed(k, step):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                lb.synchronize()
+                e0.record(lb.stream)
+                for _ in range(k):
+                    exchange()
+                    if step:
+                        lb.step(1)
+                e1.record(lb.stream)
+                e1.synchronize()
+                return e0.elapsed_time(e1)
+
+            log(f"{prec} shard {sh}: {args.shard_steps} steps with face exchange")
+            timed(args.warmup, True)
+            ms = timed(args.shard_steps, True)
+            ms_faces = timed(args.shard_steps, False)
             t = ms / args.shard_steps * 1e-3
+            ts = (ms - ms_faces) / args.shard_steps * 1e-3
             out["shard_32x256x256"][prec] = {
                 "value": round(nsh / t / 1e6, 1), "unit": "MLUPS", "steps": args.shard_steps,
                 "ms_per_step": round(ms / args.shard_steps, 4),
-                "achieved_GBps": round(moved * nsh / t / 1e9, 1),
-                "frac": round(moved * nsh / t / 1e9 / HBM_PEAK_GBPS, 4)}
-            del lb
+                "faces_ms_per_step": round(ms_faces / args.shard_steps, 4),
+                "face_bytes": int(lb.sizes.face_bytes),
+                "step_ms_without_faces": round(ts * 1e3, 4),
+                "achieved_GBps": round(moved * nsh / ts / 1e9, 1),
+                "frac": round(moved * nsh / ts / 1e9 / HBM_PEAK_GBPS, 4)}
+            del lb, faces
             torch.cuda.empty_cache()
 
     # FP64 on the 128^3 spinodal-decomposition lattice (phi0 ~ U(-0.05, 0.05))
@@ -484,6 +556,26 @@ def main():
             adj[name] = entry
             torch.cuda.empty_cache()
         out["adjoint"] = adj
+
+    if args.grad_attribution:
+        # every (trajectory, adjoint) precision pair of the 128^3, T = 1000,
+        # k = 32 configuration against the all-FP64 pair
+        sh = (128, 128, 128)
+        ph0 = lbinputs.spinodal_phi0(sh)
+        tgt = lbinputs.lamellar_target(sh, 32, xi)
+        res = {}
+        for fp_, ap_ in (("fp64", "fp64"), ("fp32_dev", "fp32_dev"), ("fp32_dev", "fp64"),
+                         ("fp64", "fp32_dev")):
+            log(f"gradient attribution: trajectory {fp_}, adjoint {ap_}")
+            res[(fp_, ap_)] = mixed_rollout_grads(sh, 1000, 32, fp_, ap_, ph0, tgt, params)
+            torch.cuda.empty_cache()
+        g64 = res[("fp64", "fp64")]
+        out["grad_attribution"] = {
+            f"trajectory_{a}_adjoint_{b}": {
+                "phi0_l2": float(np.linalg.norm(g[0] - g64[0]) / np.linalg.norm(g64[0])),
+                "A": g[1][0] / g64[1][0] - 1, "B": g[1][1] / g64[1][1] - 1,
+                "kappa": g[1][2] / g64[1][2] - 1}
+            for (a, b), g in res.items() if (a, b) != ("fp64", "fp64")}
 
     if not args.no_cpu_baseline:
         # The FP64 oracle as it stands (plain per-site C loops; OpenMP over

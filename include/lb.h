@@ -142,7 +142,18 @@ typedef enum {
 /* Lattice and model.  nx, ny, nz >= 1 (periodic in all three directions),
  * N = nx*ny*nz below ~1.1e8 sites (39 * stride_elems < 2^32) and one x-plane
  * of f below 4 GiB (ny*nz*19*elem_bytes < 2^32), else LB_ESHAPE;
- * tau_f, tau_g > 1/2; rho0 > 0. */
+ * tau_f, tau_g > 1/2; rho0 > 0.
+ *
+ * halo_x = 1 makes the lattice one x-slab shard of a larger one (the paper's
+ * domain decomposition, Sec. 2.1.1 and Sec. 5): x is not periodic, and each
+ * time level also holds halo planes that the step reads instead of a wrap,
+ * filled from the neighbouring shards through lb_pack_faces /
+ * lb_unpack_faces before every step (see there).  Shards need nx >= 2,
+ * LB_OP_LB, LB_COUPLING_STRESS and LB_KERNEL_FUSED or LB_KERNEL_STREAM
+ * (LB_EINVAL otherwise); lb_step advances one step per call (nsteps <= 1);
+ * lb_import_dist, lb_step_from_phi and the reverse mode return LB_ESTATE;
+ * lb_init_phi's phi0 holds nx + 2 planes (see there).  Measured and tested
+ * on one GPU; the exchange between GPUs is the caller's. */
 typedef struct {
     int32_t nx, ny, nz;
     double A, B, kappa; /* free energy A/2 phi^2 + B/4 phi^4 + kappa/2 |grad phi|^2 */
@@ -156,6 +167,7 @@ typedef struct {
     int32_t aosoa_len;  /* V for LB_LAYOUT_AOSOA (ignored otherwise)                */
     int32_t coupling;   /* lb_coupling                                              */
     int32_t order_param; /* lb_order_param                                          */
+    int32_t halo_x;     /* 0: periodic in x; 1: an x-slab shard (halo planes)        */
 } lb_params;
 
 /* Sizes in bytes of the caller-owned device buffers (lb_query_sizes). */
@@ -171,6 +183,7 @@ typedef struct {
     size_t adj_bytes;         /* one adjoint time level (lambda_f, lambda_g, lambda_phi) */
     size_t adj_scratch_bytes; /* adjoint stencil cotangents (5 fields; 8 with the force
                                  coupling, which adds dL/dF)                         */
+    size_t face_bytes;        /* one face buffer of an x-slab shard (0 when periodic)    */
 } lb_sizes;
 
 /* Caller-owned device memory.  state[0..1] are the two time levels the step
@@ -217,7 +230,9 @@ lb_status lb_set_stream(lb_ctx *ctx, void *hip_stream);
 /* Initial state from phi0_dev (FP64, nx*ny*nz): rho = rho0 and u = 0
  * (f_i = w_i rho0), all of phi0 in the rest population (g_0 = phi0,
  * g_i = 0 for i > 0; LB_OP_FD: the field phi = phi0).  Resets the time-level
- * index.  Passage: Sec. 3.2.3, Fig. 2 (copyToTarget) for the hand-over of
+ * index.  An x-slab shard takes phi0 of nx + 2 planes: plane -1 (the lower
+ * neighbour's last), the shard's nx planes, plane nx (the upper neighbour's
+ * first).  Passage: Sec. 3.2.3, Fig. 2 (copyToTarget) for the hand-over of
  * phi0; the state built from it is this library's reading (the paper gives
  * no initial condition for this model). */
 lb_status lb_init_phi(lb_ctx *ctx, const double *phi0_dev);
@@ -358,6 +373,29 @@ lb_status lb_adjoint_phi0(lb_ctx *ctx, double *dphi0_dev);
  * Caller-owned, 256-byte aligned (LB_EALIGN), 19*N FP64 values each;
  * LB_ESTATE without adjoint buffers. */
 lb_status lb_adjoint_export(lb_ctx *ctx, double *df_dev, double *dg_dev);
+
+/* ---- x-slab shards (halo_x = 1) ---------------------------------------
+ * Passage: Sec. 2.1.1 (each sub-domain of the decomposed lattice is
+ * surrounded by a halo region filled from its neighbours) and Sec. 5 (the
+ * decomposed runs).  Before every step of a shard:
+ *   lb_pack_faces(ctx, send_lo, send_hi);         this shard's two faces
+ *   (send_lo to the lower neighbour, send_hi to the upper one; receive the
+ *    lower neighbour's send_hi as recv_lo, the upper one's send_lo as recv_hi)
+ *   lb_unpack_faces(ctx, recv_lo, recv_hi);       into the halo planes
+ *   lb_step(ctx, 1);
+ * (once more before lb_moments, lb_sums or lb_export_dist, which read the
+ * halo planes of the current level too).  A face carries, for the
+ * populations moving across it, f and g of the boundary plane, the g that
+ * form phi at the neighbour's boundary plane (its stencil neighbour) and,
+ * in LB_FP32_DEV, that plane's phi_c: 24 * ny * nz values of the storage
+ * type (+ ny * nz FP64), face_bytes bytes; the layout is internal and the
+ * buffers are opaque.  A shard that receives its own faces (recv_lo =
+ * send_hi, recv_hi = send_lo) steps exactly like the periodic lattice of
+ * the same extents, bit for bit.  Buffers are device memory of face_bytes,
+ * 256-byte aligned (LB_EALIGN); either pointer may be NULL to skip that
+ * face; LB_ESTATE on a periodic context. */
+lb_status lb_pack_faces(lb_ctx *ctx, void *send_lo_dev, void *send_hi_dev);
+lb_status lb_unpack_faces(lb_ctx *ctx, const void *recv_lo_dev, const void *recv_hi_dev);
 
 /* ---- measurement ------------------------------------------------------ */
 

@@ -22,7 +22,8 @@ ABI_VERSION = 4
 EXPORTS = ("lb_abi_version", "lb_query_sizes", "lb_create", "lb_destroy", "lb_set_stream",
            "lb_init_phi", "lb_step", "lb_step_sums", "lb_step_from", "lb_step_from_phi", "lb_moments", "lb_sums", "lb_get_state", "lb_set_state",
            "lb_export_dist", "lb_import_dist", "lb_adjoint_seed", "lb_adjoint_step", "lb_adjoint_step_next",
-           "lb_adjoint_step_phi", "lb_adjoint_phi0", "lb_adjoint_export", "lb_copy_probe",
+           "lb_adjoint_step_phi", "lb_adjoint_phi0", "lb_adjoint_export", "lb_pack_faces",
+           "lb_unpack_faces", "lb_copy_probe",
            "lb_status_string", "lb_last_error")
 
 
@@ -34,14 +35,14 @@ class LbParams(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("segment_x", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("aosoa_len", ctypes.c_int32), ("coupling", ctypes.c_int32),
-                ("order_param", ctypes.c_int32)]
+                ("order_param", ctypes.c_int32), ("halo_x", ctypes.c_int32)]
 
 
 class LbSizes(ctypes.Structure):
     _fields_ = [("elem_bytes", ctypes.c_size_t), ("stride_elems", ctypes.c_size_t),
                 ("state_bytes", ctypes.c_size_t), ("phi_bytes", ctypes.c_size_t),
                 ("scratch_bytes", ctypes.c_size_t), ("adj_bytes", ctypes.c_size_t),
-                ("adj_scratch_bytes", ctypes.c_size_t)]
+                ("adj_scratch_bytes", ctypes.c_size_t), ("face_bytes", ctypes.c_size_t)]
 
 
 class LbBuffers(ctypes.Structure):
@@ -93,6 +94,8 @@ def lib():
         "lb_adjoint_step_phi": ([vp, vp, dp, dp], ctypes.c_int),
         "lb_adjoint_phi0": ([vp, dp], ctypes.c_int),
         "lb_adjoint_export": ([vp, dp, dp], ctypes.c_int),
+        "lb_pack_faces": ([vp, vp, vp], ctypes.c_int),
+        "lb_unpack_faces": ([vp, vp, vp], ctypes.c_int),
         "lb_copy_probe": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "lb_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "lb_last_error": ([], ctypes.c_char_p),

@@ -9,7 +9,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbmi.so")
-SOURCES = ["lb_kernels.hip", "lb_fd.hip", "lb_force.hip", "lb_adjoint.hip", "lb_probe.hip", "lb_api.cpp"]
+SOURCES = ["lb_kernels.hip", "lb_fd.hip", "lb_force.hip", "lb_adjoint.hip", "lb_halo.hip",
+           "lb_probe.hip", "lb_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed-FP32 instructions are switched off for all device code.

@@ -49,12 +49,20 @@ size_t stride_for(long long n)
 
 bool aligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) % kAlign) == 0; }
 
+// Sites a component of a time level holds: the lattice's, plus (x-slab
+// shard) two halo planes on each side.
+long long level_sites(const lb_params* p)
+{
+    return (long long)(p->nx + (p->halo_x ? 4 : 0)) * p->ny * p->nz;
+}
+
 lb_status validate(const lb_params* p)
 {
     if (!p) return fail(LB_EINVAL, "params is NULL");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LB_ESHAPE, "extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
-    const long long n = (long long)p->nx * p->ny * p->nz;
+    if (p->halo_x != 0 && p->halo_x != 1) return fail(LB_EINVAL, "halo_x must be 0 or 1");
+    const long long n = level_sites(p);
     // element offsets in the kernels are 32-bit: component * stride + site with
     // up to 39 components (an adjoint level)
     if ((long long)(stride_for(n)) * 39 >= (1LL << 32))
@@ -82,6 +90,13 @@ lb_status validate(const lb_params* p)
         return fail(LB_EINVAL, "unknown coupling %d", p->coupling);
     if (p->order_param != LB_OP_LB && p->order_param != LB_OP_FD)
         return fail(LB_EINVAL, "unknown order_param %d", p->order_param);
+    if (p->halo_x) {
+        if (p->nx < 2) return fail(LB_ESHAPE, "an x-slab shard needs nx >= 2 (got %d)", p->nx);
+        if (p->order_param != LB_OP_LB || p->coupling != LB_COUPLING_STRESS ||
+            (p->kernel != LB_KERNEL_FUSED && p->kernel != LB_KERNEL_STREAM))
+            return fail(LB_EINVAL, "x-slab shards (halo_x) run the single-pass LB_OP_LB step "
+                                   "with LB_COUPLING_STRESS only");
+    }
     if (p->layout == LB_LAYOUT_AOSOA) {
         const int v = p->aosoa_len;
         if (v < 1 || (v & (v - 1)) != 0 || p->nz % v != 0)
@@ -132,7 +147,7 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     if (!out) return fail(LB_EINVAL, "out is NULL");
     const long long n = (long long)p->nx * p->ny * p->nz;
     const size_t e = p->precision == LB_FP64 ? 8 : 4;
-    const size_t stride = stride_for(n);
+    const size_t stride = stride_for(level_sites(p));
     out->elem_bytes = e;
     out->stride_elems = stride;
     const bool fd = p->order_param == LB_OP_FD;
@@ -157,6 +172,7 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     if (fd) nparts = std::max<size_t>(nparts, size_t(lbk::fd_step_partial_blocks(k)));
     out->scratch_bytes = nparts * 5 * 8;
     out->adj_bytes = size_t(kAdjComponents) * stride * e;
+    out->face_bytes = p->halo_x ? lbk::face_bytes(k, p->precision == LB_FP32_DEV) : 0;
     out->adj_scratch_bytes =
         size_t(p->coupling == LB_COUPLING_FORCE ? kAdjScratchForce : kAdjScratchComponents) *
         stride * e;
@@ -211,6 +227,7 @@ lb_status lb_create(const lb_params* p, const lb_buffers* b, void* hip_stream, l
     k.force = p->coupling == LB_COUPLING_FORCE;
     k.fd = p->order_param == LB_OP_FD;
     k.mobility = p->gamma * (p->tau_g - 0.5);
+    k.xh = p->halo_x ? 2 : 0;
     c->tc = lbk::tile_config(k, p->segment_x, c->fp32);
     *out = c;
     return LB_OK;
@@ -252,6 +269,9 @@ static lb_status step_n(lb_ctx* ctx, int32_t nsteps, double* sums_dev, const cha
 {
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
     if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0 (got %d)", nsteps);
+    if (ctx->kp.xh && nsteps > 1)
+        return fail(LB_EINVAL, "an x-slab shard advances one step per call (its halo planes "
+                               "are exchanged between steps); got nsteps = %d", nsteps);
     for (int32_t t = 0; t < nsteps; t++) {
         hipError_t e = one_step(ctx, ctx->b.state[ctx->cur], ctx->b.state[1 - ctx->cur],
                                 sums_dev ? sums_dev + 5 * size_t(t) : nullptr);
@@ -282,6 +302,7 @@ lb_status lb_step_from(lb_ctx* ctx, const void* src_dev, void* dst_dev)
 lb_status lb_step_from_phi(lb_ctx* ctx, const void* src_dev, void* dst_dev, double* phi_dev)
 {
     if (!ctx || !phi_dev) return fail(LB_EINVAL, "ctx and phi_dev are required");
+    if (ctx->kp.xh) return fail(LB_ESTATE, "lb_step_from_phi is not available on a shard");
     if (ctx->fp32 || ctx->kp.fd)
         return fail(LB_EINVAL, "lb_step_from_phi is for LB_FP64 with LB_OP_LB (FP32 storage "
                                "keeps phi in the next level; LB_OP_FD in the level itself)");
@@ -355,6 +376,9 @@ lb_status lb_export_dist(lb_ctx* ctx, double* f_dev, double* g_dev)
 lb_status lb_import_dist(lb_ctx* ctx, const double* f_dev, const double* g_dev)
 {
     if (!ctx || !f_dev) return fail(LB_EINVAL, "ctx and f_dev are required");
+    if (ctx->kp.xh)
+        return fail(LB_ESTATE, "a shard cannot import post-propagation values: the populations "
+                               "leaving it are its neighbours'");
     hipError_t e;
     if (ctx->kp.fd) {
         if (g_dev) return fail(LB_EINVAL, "LB_OP_FD has no g: g_dev must be NULL");
@@ -373,6 +397,7 @@ lb_status lb_adjoint_seed(lb_ctx* ctx, const double* dphi_dev)
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
     if (ctx->p.kernel == LB_KERNEL_STREAM)
         return fail(LB_ESTATE, "LB_KERNEL_STREAM (free streaming) has no reverse mode");
+    if (ctx->kp.xh) return fail(LB_ESTATE, "x-slab shards have no reverse mode");
     ctx->adj_cur = 0;
     hipError_t e = lbk::launch_adj_seed(ctx->kp, ctx->fp32, ctx->b.adj[0], dphi_dev, ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_seed");
@@ -409,6 +434,7 @@ static lb_status adjoint_step(lb_ctx* ctx, const void* state_t_dev, const void* 
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
     if (ctx->p.kernel == LB_KERNEL_STREAM)
         return fail(LB_ESTATE, "LB_KERNEL_STREAM (free streaming) has no reverse mode");
+    if (ctx->kp.xh) return fail(LB_ESTATE, "x-slab shards have no reverse mode");
     if (!aligned(state_t_dev)) return fail(LB_EALIGN, "state_t_dev is not 256-byte aligned");
     if (state_next_dev && !aligned(state_next_dev))
         return fail(LB_EALIGN, "state_next_dev is not 256-byte aligned");
@@ -437,6 +463,39 @@ lb_status lb_adjoint_phi0(lb_ctx* ctx, double* dphi0_dev)
     hipError_t e = lbk::launch_adj_phi0(ctx->kp, ctx->fp32, ctx->b.adj[ctx->adj_cur], dphi0_dev,
                                         ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_phi0");
+}
+
+static lb_status faces(lb_ctx* ctx, void* lo, void* hi, bool pack, const char* name)
+{
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    if (!ctx->kp.xh) return fail(LB_ESTATE, "%s: the context is not an x-slab shard", name);
+    if ((lo && !aligned(lo)) || (hi && !aligned(hi)))
+        return fail(LB_EALIGN, "%s: face buffers must be 256-byte aligned", name);
+    if (lo && lo == hi) return fail(LB_EINVAL, "%s: the two face buffers alias", name);
+    const int nx = ctx->p.nx;
+    void* st = ctx->b.state[ctx->cur];
+    hipError_t e = hipSuccess;
+    // packed: the face sent down (planes 0 and 1, c_x = -1) and the one sent
+    // up (planes nx-1 and nx-2, c_x = +1); unpacked: the lower neighbour's
+    // upward face into planes -1 and -2, the upper one's downward face into
+    // planes nx and nx+1
+    if (lo) e = lbk::launch_face(ctx->kp, ctx->fp32, st, lo, pack ? -1 : +1, pack ? 0 : -1, pack,
+                                 ctx->stream);
+    if (e == hipSuccess && hi)
+        e = lbk::launch_face(ctx->kp, ctx->fp32, st, hi, pack ? +1 : -1, pack ? nx - 1 : nx, pack,
+                             ctx->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, name);
+}
+
+lb_status lb_pack_faces(lb_ctx* ctx, void* send_lo_dev, void* send_hi_dev)
+{
+    return faces(ctx, send_lo_dev, send_hi_dev, true, "lb_pack_faces");
+}
+
+lb_status lb_unpack_faces(lb_ctx* ctx, const void* recv_lo_dev, const void* recv_hi_dev)
+{
+    return faces(ctx, const_cast<void*>(recv_lo_dev), const_cast<void*>(recv_hi_dev), false,
+                 "lb_unpack_faces");
 }
 
 lb_status lb_adjoint_export(lb_ctx* ctx, double* df_dev, double* dg_dev)

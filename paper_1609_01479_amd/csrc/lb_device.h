@@ -55,11 +55,13 @@ struct Geo {
 __device__ __forceinline__ int wrapm(int v, int n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ int wrapp(int v, int n) { return v == n - 1 ? 0 : v + 1; }
 
+// In an x-slab shard (p.xh > 0) x is not periodic: x - 1 and x + 1 of the
+// boundary planes are the halo planes -1 and nx.
 __device__ __forceinline__ Geo geo_xyz(const KParams& p, int x, int y, int z)
 {
     Geo q;
     q.x = x; q.y = y; q.z = z;
-    q.xm = wrapm(x, p.nx); q.xp = wrapp(x, p.nx);
+    q.xm = p.xh ? x - 1 : wrapm(x, p.nx); q.xp = p.xh ? x + 1 : wrapp(x, p.nx);
     q.ym = wrapm(y, p.ny); q.yp = wrapp(y, p.ny);
     q.zm = wrapm(z, p.nz); q.zp = wrapp(z, p.nz);
     return q;
@@ -75,6 +77,13 @@ __device__ __forceinline__ Geo geo_of(const KParams& p, int s)
 __device__ __forceinline__ int site_of(const KParams& p, int x, int y, int z)
 {
     return (x * p.ny + y) * p.nz + z;
+}
+
+// Index of site (x, y, z) in a level's phi_c field: site order, after one
+// halo plane in an x-slab shard (x from -1 to nx there).
+__device__ __forceinline__ int phic_site(const KParams& p, int x, int y, int z)
+{
+    return site_of(p, x + (p.xh >> 1), y, z);
 }
 
 __device__ __forceinline__ int minus_c(int c, int v, int vm, int vp) { return c > 0 ? vm : (c < 0 ? vp : v); }
@@ -107,14 +116,16 @@ __device__ __forceinline__ int xcd_block()
 //   x*plane_e + y*ry + (z >> vs)*zb + (z & vm) + i*cs,
 // which covers the row-blocked default ((x*ny + y)*19 + i)*nz + z, one array
 // per component, a site's components together, and blocks of 2^vs z-sites.
-// Indices fit 32 bits (39*stride < 2^32 is checked at creation).
+// Indices fit 32 bits (39*stride < 2^32 is checked at creation).  In an
+// x-slab shard the regions start with p.xh halo planes, so plane x (from -2
+// to nx + 1) is at (x + p.xh)*plane_e.
 __device__ __forceinline__ unsigned row_off(const KParams& p, int y, int z)
 {
     return unsigned(y) * p.ry + (unsigned(z) >> p.vs) * p.zb + (unsigned(z) & p.vm);
 }
 __device__ __forceinline__ unsigned didx(const KParams& p, int i, int x, int y, int z)
 {
-    return unsigned(x) * p.plane_e + row_off(p, y, z) + unsigned(i) * p.cs;
+    return unsigned(x + p.xh) * p.plane_e + row_off(p, y, z) + unsigned(i) * p.cs;
 }
 // component i at x - c_i, at x itself, at x + c_i
 __device__ __forceinline__ unsigned dist_pull(const KParams& p, const Geo& q, int i)
@@ -139,7 +150,7 @@ __device__ __forceinline__ double pull_g(const KParams& p, const Geo& q, const T
                                          const double* __restrict__ phic, double* d)
 {
     double acc = 0.0;
-    const double pc = REF ? phic[site_of(p, q.x, q.y, q.z)] : 0.0;
+    const double pc = REF ? phic[phic_site(p, q.x, q.y, q.z)] : 0.0;
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         const double gv = double(G[dist_pull(p, q, i)]);

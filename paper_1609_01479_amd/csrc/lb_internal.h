@@ -23,6 +23,8 @@ struct KParams {
     double A, B, kappa, gamma;
     double omega_f, omega_g;  // 1/tau
     double rho0;
+    int xh;     // x-slab shard: planes of halo on each side of the F and G
+                // regions (2; the phi_c field has 1), x not periodic; 0: periodic
     int force;  // force coupling: -div Pi as a body force
     int fd;           // finite-difference order parameter (no g)
     double mobility;  // M = Gamma (tau_g - 1/2) of the finite-difference update
@@ -163,6 +165,15 @@ hipError_t launch_fd_export(const KParams& p, bool fp32, const void* state, doub
                             hipStream_t s);
 hipError_t launch_fd_import(const KParams& p, bool fp32, void* state, const double* f,
                             hipStream_t s);
+
+// x-slab shards (lb_halo.hip): bytes of one face buffer, and the copy of a
+// face between `buf` and the level `state` -- pack: boundary plane xb and
+// the plane behind it (xb - s) into buf; unpack: buf into the halo planes
+// xb and xb - s.  s = +1: the face sent up (c_x = +1 populations), s = -1:
+// the face sent down.
+size_t face_bytes(const KParams& p, bool fp32);
+hipError_t launch_face(const KParams& p, bool fp32, void* state, void* buf, int s, int xb,
+                       bool pack, hipStream_t st);
 
 // Upper bound on the block partials any reduction writes (per component).
 constexpr int kMaxPartialBlocks = 2048;

@@ -41,7 +41,8 @@ static_assert(2 * 64 + 2 * (kFused / 64) + 4 <= kFused, "halo ring larger than t
 
 // Post-propagation state rho = rho0, u = 0, g_0 = phi0, g_{i>0} = 0.  In FP32
 // mode phi_c = phi0, and the stored deviation of direction i at y is
-// g_i(y + c_i) - r_i phi0(y + c_i).
+// g_i(y + c_i) - r_i phi0(y + c_i).  In an x-slab shard phi0 also holds the
+// planes -1 and nx (the neighbours'), first and last.
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_init(KParams p, T* __restrict__ F, T* __restrict__ G,
                                                  double* __restrict__ phic,
@@ -50,18 +51,19 @@ __global__ __launch_bounds__(kBlock) void k_init(KParams p, T* __restrict__ F, T
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
     const Geo q = geo_of(p, s);
+    const double* ph = phi0 + (p.xh ? p.ny * p.nz : 0);
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         const unsigned d = dist_own(p, q, i);
         F[d] = DEV ? T(0) : T(weight(i) * p.rho0);
         if (REF) {
-            const double pd = phi0[push_site(p, q, i)];
+            const double pd = ph[push_site(p, q, i)];
             G[d] = T((i == 0 ? pd : 0.0) - rweight(i) * pd);
         } else {
-            G[d] = i == 0 ? T(phi0[s]) : T(0);
+            G[d] = i == 0 ? T(ph[s]) : T(0);
         }
     }
-    if (REF) phic[s] = phi0[s];
+    if (REF) phic[phic_site(p, q.x, q.y, q.z)] = ph[s];
 }
 
 // phi(x) = sum_i g_i(x) of the post-propagation state (FP64).
@@ -251,8 +253,12 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     const Yz9 rrow = yz9<T>(p, ring ? ry : 0, ring ? rz : 0);
     const unsigned rsite = unsigned((ring ? ry : 0) * p.nz + (ring ? rz : 0));
 
-    // plane indices run from x0-2 to x1+1 (nx may be 1): wrap without
-    // division or branches (valid on [-2nx, 4nx))
+    // plane indices run from x0-2 to x1+2 (nx may be 1): wrap without
+    // division or branches (valid on [-2nx, 4nx)).  An x-slab shard has no
+    // wrap: its regions hold planes -2 .. nx+1 of F and G (the halo planes
+    // of the neighbours' populations) and -1 .. nx of phi_c; indices beyond
+    // those occur only in the prefetch past a segment's end, whose values
+    // go unused, and are clamped onto the last halo plane.
     auto xw = [&](int X) {
         X += X < 0 ? p.nx : 0;
         X += X < 0 ? p.nx : 0;
@@ -261,9 +267,11 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
         X -= X >= p.nx ? p.nx : 0;
         return X;
     };
+    auto xf = [&](int X) { return p.xh ? min(max(X, -2), p.nx + 1) + 2 : xw(X); };
+    auto xc = [&](int X) { return p.xh ? min(max(X, -1), p.nx) + 1 : xw(X); };
     // byte base of plane X in F or G; element base of plane X in phi_c
-    auto pbase = [&](int X) { return O(xw(X)) * planeb; };
-    auto pcbase = [&](int X) { return unsigned(xw(X) * plane); };
+    auto pbase = [&](int X) { return O(xf(X)) * planeb; };
+    auto pcbase = [&](int X) { return unsigned(xc(X) * plane); };
     // pull of plane X for a site with row offsets yz and in-plane index
     // `site`: kept values into kv[] and the site's phi_c into *pc (if
     // non-null); returns phi

@@ -62,7 +62,8 @@ class LB:
     def __init__(self, shape, *, A=-0.00625, B=0.00625, kappa=0.004, gamma=0.5, tau_f=1.0,
                  tau_g=1.0, rho0=1.0, precision="fp64", adjoint=False, device=None,
                  stream: torch.cuda.Stream | None = None, kernel="fused", segment_x=0,
-                 layout="rows", aosoa_len=0, coupling="stress", order_param="lb"):
+                 layout="rows", aosoa_len=0, coupling="stress", order_param="lb",
+                 halo_x=False):
         L = _abi.lib()
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
@@ -72,7 +73,8 @@ class LB:
                                     float(tau_f), float(tau_g), float(rho0), self.precision,
                                     KERNELS[kernel], int(segment_x),
                                     LAYOUTS[layout], int(aosoa_len), COUPLINGS[coupling],
-                                    ORDER_PARAMS[order_param])
+                                    ORDER_PARAMS[order_param], 1 if halo_x else 0)
+        self.halo_x = bool(halo_x)
         self.fd = self.params.order_param == ORDER_PARAMS["fd"]
         self.sizes = _abi.LbSizes()
         check(L.lb_query_sizes(ctypes.byref(self.params), ctypes.byref(self.sizes)),
@@ -138,7 +140,10 @@ class LB:
 
     # -- forward ------------------------------------------------------------
     def init_phi(self, phi0) -> None:
-        t = self._dev64(phi0, self.shape)
+        """phi0 of shape (nx, ny, nz); an x-slab shard (halo_x) takes
+        (nx + 2, ny, nz): the neighbours' planes -1 and nx around its own."""
+        nx, ny, nz = self.shape
+        t = self._dev64(phi0, (nx + 2, ny, nz) if self.halo_x else self.shape)
         self._sync_inputs()
         self._call("lb_init_phi", _ptr(t))
         t.record_stream(self.stream)
@@ -267,6 +272,21 @@ class LB:
         out = self._out(*self.shape)
         self._call("lb_adjoint_phi0", _ptr(out))
         return out
+
+    # -- x-slab shards (halo_x) -------------------------------------------
+    def new_face(self) -> torch.Tensor:
+        """An uninitialised device buffer for one face (face_bytes)."""
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            return torch.empty(int(self.sizes.face_bytes), dtype=torch.uint8, device=self.device)
+
+    def pack_faces(self, send_lo: torch.Tensor | None, send_hi: torch.Tensor | None) -> None:
+        """The shard's faces for its lower and upper neighbours (lb_pack_faces)."""
+        self._call("lb_pack_faces", _ptr(send_lo), _ptr(send_hi))
+
+    def unpack_faces(self, recv_lo: torch.Tensor | None, recv_hi: torch.Tensor | None) -> None:
+        """The neighbours' faces into the halo planes (lb_unpack_faces)."""
+        self._sync_inputs()
+        self._call("lb_unpack_faces", _ptr(recv_lo), _ptr(recv_hi))
 
     def synchronize(self):
         self.stream.synchronize()

@@ -7,7 +7,9 @@ recomputation: the forward keeps the state every k steps (k = ceil(sqrt(T))
 by default); the backward takes each checkpoint in reverse order,
 recomputes the k - 1 later states of its segment with lb_step_from (each
 written once, straight into its segment buffer), and walks the adjoint back
-through them.  Memory: ceil(T/k) + k - 1 states instead of T.
+through them.  Memory: ceil(T/k) + k - 1 states instead of T, plus, for the
+LB order parameter in FP64 storage, k - 1 FP64 phi fields (8 bytes per site
+each) that hand phi of each recomputed level to its reverse step.
 
 All state copies are lossless (lb_get_state / lb_set_state), and the forward
 step is deterministic, so the recomputed states are bit-identical to the

@@ -241,3 +241,47 @@ def test_status_strings(abi):
     L = abi.lib()
     for code in range(6):
         assert L.lb_status_string(code)
+
+
+def test_shard_sizes_and_validation(abi):
+    """An x-slab shard (halo_x): levels hold two halo planes on each side, a
+    face buffer is 24 component planes (+ the FP64 phi_c plane in FP32
+    storage); shards reject what they do not support, before any HIP call."""
+    for prec, e in ((0, 8), (1, 4)):
+        st, s = _query(abi, nx=6, ny=10, nz=12, precision=prec, halo_x=1)
+        assert st == abi.LB_OK
+        assert s.stride_elems >= (6 + 4) * 10 * 12
+        a = 10 * 12
+        assert s.face_bytes == (24 * a * e + (a * 8 if e == 4 else 0) + 255) // 256 * 256
+        st, s0 = _query(abi, nx=6, ny=10, nz=12, precision=prec)
+        assert st == abi.LB_OK and s0.face_bytes == 0
+    for kw, code in ((dict(nx=1), "LB_ESHAPE"), (dict(coupling=1), "LB_EINVAL"),
+                     (dict(order_param=1), "LB_EINVAL"), (dict(kernel=1), "LB_EINVAL"),
+                     (dict(halo_x=2), "LB_EINVAL")):
+        base = dict(halo_x=1)
+        base.update(kw)
+        st, _ = _query(abi, **base)
+        assert st == getattr(abi, code), kw
+    st, _ = _query(abi, halo_x=1, kernel=2)
+    assert st == abi.LB_OK
+    L = abi.lib()
+    ctx = ctypes.c_void_p()
+    b = abi.LbBuffers()
+    b.state[0], b.state[1], b.phi, b.scratch = 0x1000, 0x2000, 0x3000, 0x4000
+    b.adj[0], b.adj[1], b.adj_scratch = 0x5000, 0x6000, 0x7000
+    p = _params(abi, halo_x=1)
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
+    v, w = ctypes.c_void_p(0x8000), ctypes.c_void_p(0x9000)
+    assert L.lb_step(ctx, 2) == abi.LB_EINVAL
+    assert L.lb_import_dist(ctx, v, w) == abi.LB_ESTATE
+    assert L.lb_adjoint_seed(ctx, v) == abi.LB_ESTATE
+    assert L.lb_adjoint_step(ctx, v, None) == abi.LB_ESTATE
+    assert L.lb_pack_faces(ctx, ctypes.c_void_p(0x8010), None) == abi.LB_EALIGN
+    assert L.lb_unpack_faces(ctx, v, v) == abi.LB_EINVAL
+    assert L.lb_pack_faces(ctx, None, None) == abi.LB_OK
+    L.lb_destroy(ctx)
+    p = _params(abi)
+    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
+    assert L.lb_pack_faces(ctx, v, w) == abi.LB_ESTATE
+    assert L.lb_unpack_faces(ctx, v, w) == abi.LB_ESTATE
+    L.lb_destroy(ctx)

@@ -54,7 +54,11 @@ def test_stream_twin_conserves_and_rejects_the_adjoint():
     s0 = lb.sums().cpu().numpy()
     hist = lb.step_sums(4).cpu().numpy()
     s1 = lb.sums().cpu().numpy()
-    assert np.abs(hist - s0).max() <= 1e-9 and np.abs(s1 - s0).max() <= 1e-9
+    # mass and momentum: the f deviations move unchanged; sum phi: each
+    # step re-rounds the FP32 g deviations to their new reference (about
+    # 2e-8 per step here, against sum phi = 0.42)
+    for k, tol in ((0, 1e-9), (1, 1e-6), (2, 1e-9), (3, 1e-9), (4, 1e-9)):
+        assert np.abs(hist[:, k] - s0[k]).max() <= tol and abs(s1[k] - s0[k]) <= tol, k
     from paper_1609_01479_amd._abi import LB_ESTATE, LbError
     with pytest.raises(LbError) as e:
         lb.adjoint_seed(np.zeros(shape))
