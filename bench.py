@@ -180,6 +180,50 @@ def mixed_rollout_grads(shape, T, k, fwd_prec, adj_prec, phi0, tgt, params):
     return dphi0.cpu().numpy(), [float(v) for v in dtheta.cpu()]
 
 
+def footprint_sweep(args):
+    """Achieved bandwidth against the bytes a launch touches: the library's
+    streaming copy (read B, write B) and the single-pass step and its
+    memory-only twin (read one time level, write the other) on droplet
+    lattices of growing size.  GB/s count the kernels' own bytes (FP32
+    storage: 320 B per site with phi_c; FP64: 608)."""
+    import torch
+
+    import lbinputs
+    from paper_1609_01479_amd import LB
+    from paper_1609_01479_amd.lb import copy_probe_gbps
+    params = dict(lbinputs.SPINODAL_PARAMS)
+    xi = lbinputs.interface_width(params["A"], params["kappa"])
+    steps = max(args.steps, 20)
+    out = {"metric": "bandwidth against footprint", "copy": [], "lattice": []}
+    for gb in (0.25, 0.5, 1.0, 2.0, 2.68, 4.0, 8.0):
+        nbytes = int(gb * 1e9)
+        log(f"copy probe {gb} GB")
+        out["copy"].append({"read_GB": gb, "footprint_GB": 2 * gb,
+                            "GBps": round(copy_probe_gbps(nbytes, reps=10), 1)})
+        torch.cuda.empty_cache()
+    for n in (128, 192, 256, 320):
+        shape = (n, n, n)
+        nsites = n ** 3
+        phi0 = lbinputs.droplet_phi0(shape, n / 4.0, xi, noise=1e-3, seed=lbinputs.SEED_DROPLET)
+        for prec in ("fp32_dev", "fp64"):
+            row = {"n": n, "precision": prec}
+            for kern in ("fused", "stream"):
+                lb = LB(shape, precision=prec, kernel=kern, device="cuda:0", **params)
+                lb.init_phi(phi0)
+                e = int(lb.sizes.elem_bytes)
+                kb = step_bytes_per_site(e)["kernel"]
+                row["footprint_GB"] = round(kb * nsites / 1e9, 3)
+                log(f"{prec} {kern} {shape}: {steps} steps")
+                ms = time_steps(lb, steps, args.warmup) / steps
+                row[kern + "_ms"] = round(ms, 4)
+                row[kern + "_GBps"] = round(kb * nsites / (ms * 1e-3) / 1e9, 1)
+                del lb
+                torch.cuda.empty_cache()
+            row["step_over_twin"] = round(row["fused_ms"] / row["stream_ms"], 4)
+            out["lattice"].append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +251,10 @@ def main():
                     help="steps of the FP32-vs-FP64 error leg on the 256^3 droplet (0: skip)")
     ap.add_argument("--spinodal-steps", type=int, default=1000,
                     help="steps of the extra 128^3 FP64 spinodal throughput line (0: skip)")
+    ap.add_argument("--footprint-sweep", action="store_true",
+                    help="only the bandwidth-against-footprint sweep: the copy probe over "
+                         "0.25-8 GB and the single-pass step and its memory-only twin on "
+                         "droplet lattices of 128^3 to 320^3 (both storage precisions)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -220,6 +268,10 @@ def main():
 
     import lbinputs
     from paper_1609_01479_amd import LB
+
+    if args.footprint_sweep:
+        print(json.dumps(footprint_sweep(args)), flush=True)
+        return
 
     n = args.size
     shape = (n, n, n)
