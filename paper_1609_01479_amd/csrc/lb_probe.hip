@@ -4,7 +4,8 @@
 // Each thread moves 4 vectors per trip (all loads issued before the stores),
 // non-temporal, over a grid of 2 workgroups per CU -- the fastest of the copy
 // shapes measured on MI355X (plain grid-stride copies at 256..16384
-// workgroups reach 3.1-5.3 TB/s; this one 5.2-5.4 TB/s).
+// workgroups were slower).  Over 1 GiB it moved 5.9-6.3 TB/s on the boxes
+// used; its rate falls as the buffers grow (bench.py --footprint-sweep).
 #include <hip/hip_runtime.h>
 
 #include "lb.h"
