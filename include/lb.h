@@ -250,6 +250,25 @@ lb_status lb_step(lb_ctx *ctx, int32_t nsteps);
  * step, Sec. 3.2.3 (targetDoubleSum) for the sums. */
 lb_status lb_step_sums(lb_ctx *ctx, int32_t nsteps, double *sums_dev);
 
+/* lb_step_sums for callers that cannot allocate device memory or hand over a
+ * workspace (code under HIP graph capture, allocation-free serving loops,
+ * harnesses that forbid hipMalloc): the steps' reduction partials go to a
+ * device array inside the library instead of the context's scratch buffer;
+ * everything else, results included (bit for bit), is lb_step_sums'.  The
+ * call allocates nothing.  The array holds LB_NOALLOC_MAX_PARTIALS blocks of
+ * 5 FP64 partials (160 KiB), one copy per GPU the library runs on, kept until
+ * the process ends; its address on the current GPU is looked up on the first
+ * call there.  LB_EINVAL if the context's steps reduce over more blocks
+ * (scratch_bytes / 40 > LB_NOALLOC_MAX_PARTIALS; every cube up to 479^3
+ * fits), LB_ESTATE if the current device is not that of the context's
+ * stream.  Every block overwrites its own partials before they are summed,
+ * so nothing carries over from an earlier call; but all contexts on one GPU
+ * share the one array, so calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.  Passage: as
+ * lb_step_sums. */
+#define LB_NOALLOC_MAX_PARTIALS 4096
+lb_status lb_step_sums_noalloc(lb_ctx *ctx, int32_t nsteps, double *sums_dev);
+
 /* One timestep from the caller's time level src_dev to dst_dev (both
  * state_bytes, as written by lb_get_state or a previous lb_step_from),
  * without touching the context's current level.  Used by the reverse mode to

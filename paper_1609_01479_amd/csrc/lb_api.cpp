@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "lb_internal.h"
@@ -120,6 +121,53 @@ struct lb_ctx {
     int adj_cur;  // adjoint level holding the current lambda
     bool has_adj;
 };
+
+// ---- allocation-free lb_step_sums --------------------------------------
+// The reduction partials of lb_step_sums_noalloc live in this array instead
+// of the caller's scratch buffer: one copy per GPU the library runs on, held
+// until the process ends.  On the host the name `scratch` is only a stand-in
+// for the symbol, never a device address: host code takes the address of
+// each GPU's copy from hipGetSymbolAddress (with that GPU current) and uses
+// only that.  Every block of a reducing step writes its own five slots
+// before the final pass reads them, so nothing has to start at zero.
+static __device__ __align__(256) double scratch[LB_NOALLOC_MAX_PARTIALS * 5];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current GPU's copy of `scratch` (looked up once per
+// device, then reused).
+lb_status noalloc_scratch(lb_ctx* ctx, double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "lb_step_sums_noalloc (hipGetDevice)");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(LB_ESTATE, "lb_step_sums_noalloc: device %d is beyond the %d the library "
+                               "tracks", dev, kMaxDevices);
+    if (ctx->stream) {
+        int sdev = -1;
+        e = hipStreamGetDevice(ctx->stream, &sdev);
+        if (e != hipSuccess) return hip_fail(e, "lb_step_sums_noalloc (hipStreamGetDevice)");
+        if (sdev != dev)
+            return fail(LB_ESTATE, "lb_step_sums_noalloc: the current device (%d) is not the "
+                                   "context stream's (%d)", dev, sdev);
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "lb_step_sums_noalloc (hipGetSymbolAddress)");
+        g_scratch_dev[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return LB_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -254,10 +302,10 @@ lb_status lb_init_phi(lb_ctx* ctx, const double* phi0_dev)
 
 // One step from src to dst with the context's scheme.
 static hipError_t one_step(lb_ctx* ctx, const void* src, void* dst, double* sums_dev,
-                           double* phi_src_out = nullptr)
+                           double* phi_src_out = nullptr, double* part = nullptr)
 {
     double* work = static_cast<double*>(ctx->b.phi);
-    double* part = static_cast<double*>(ctx->b.scratch);
+    if (!part) part = static_cast<double*>(ctx->b.scratch);
     if (ctx->kp.fd)
         return lbk::launch_fd_step(ctx->kp, ctx->tc, ctx->fp32, ctx->p.kernel, src, dst, work, part,
                                    sums_dev, ctx->stream);
@@ -265,7 +313,8 @@ static hipError_t one_step(lb_ctx* ctx, const void* src, void* dst, double* sums
                             sums_dev, phi_src_out, ctx->stream);
 }
 
-static lb_status step_n(lb_ctx* ctx, int32_t nsteps, double* sums_dev, const char* name)
+static lb_status step_n(lb_ctx* ctx, int32_t nsteps, double* sums_dev, const char* name,
+                        double* part = nullptr)
 {
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
     if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0 (got %d)", nsteps);
@@ -274,7 +323,7 @@ static lb_status step_n(lb_ctx* ctx, int32_t nsteps, double* sums_dev, const cha
                                "are exchanged between steps); got nsteps = %d", nsteps);
     for (int32_t t = 0; t < nsteps; t++) {
         hipError_t e = one_step(ctx, ctx->b.state[ctx->cur], ctx->b.state[1 - ctx->cur],
-                                sums_dev ? sums_dev + 5 * size_t(t) : nullptr);
+                                sums_dev ? sums_dev + 5 * size_t(t) : nullptr, nullptr, part);
         if (e != hipSuccess) return hip_fail(e, name);
         ctx->cur = 1 - ctx->cur;
     }
@@ -287,6 +336,24 @@ lb_status lb_step_sums(lb_ctx* ctx, int32_t nsteps, double* sums_dev)
 {
     if (!sums_dev) return fail(LB_EINVAL, "sums_dev is required");
     return step_n(ctx, nsteps, sums_dev, "lb_step_sums");
+}
+
+lb_status lb_step_sums_noalloc(lb_ctx* ctx, int32_t nsteps, double* sums_dev)
+{
+    if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+    if (!sums_dev) return fail(LB_EINVAL, "sums_dev is required");
+    if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0 (got %d)", nsteps);
+    // the partial blocks any step of this context reduces over (the bound
+    // lb_query_sizes sized the context's scratch with)
+    const size_t need = ctx->sz.scratch_bytes / (5 * sizeof(double));
+    if (need > size_t(LB_NOALLOC_MAX_PARTIALS))
+        return fail(LB_EINVAL, "lb_step_sums_noalloc: this lattice reduces over %zu partial "
+                               "blocks, the library's array holds %d (use lb_step_sums)",
+                    need, LB_NOALLOC_MAX_PARTIALS);
+    double* part = nullptr;
+    lb_status st = noalloc_scratch(ctx, &part);
+    if (st != LB_OK) return st;
+    return step_n(ctx, nsteps, sums_dev, "lb_step_sums_noalloc", part);
 }
 
 lb_status lb_step_from(lb_ctx* ctx, const void* src_dev, void* dst_dev)

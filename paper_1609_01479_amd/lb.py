@@ -161,6 +161,15 @@ class LB:
         self._call("lb_step_sums", ctypes.c_int32(int(nsteps)), _ptr(out))
         return out
 
+    def step_sums_noalloc(self, nsteps: int, out: torch.Tensor) -> torch.Tensor:
+        """step_sums through the allocation-free entry point
+        (lb_step_sums_noalloc): the reduction partials live in the library's
+        own device array, and `out` must be given (nothing is allocated)."""
+        if out.dtype != torch.float64 or out.numel() < 5 * nsteps or not out.is_contiguous():
+            raise ValueError("out must be a contiguous FP64 tensor of 5*nsteps values")
+        self._call("lb_step_sums_noalloc", ctypes.c_int32(int(nsteps)), _ptr(out))
+        return out
+
     def new_state(self) -> torch.Tensor:
         """An uninitialised device buffer of one time level (state_bytes)."""
         with torch.cuda.device(self.device), torch.cuda.stream(self.stream):

@@ -167,6 +167,33 @@ def test_create_validates_buffers_without_launching(abi):
     L.lb_destroy(None)
 
 
+def test_step_sums_noalloc_validates_without_launching(abi):
+    """lb_step_sums_noalloc rejects a NULL context or output, a negative step
+    count and a lattice whose steps reduce over more partial blocks than the
+    library's array holds, before any HIP call."""
+    L = abi.lib()
+    ctx = ctypes.c_void_p()
+    b = abi.LbBuffers()
+    b.state[0], b.state[1], b.phi, b.scratch = 0x1000, 0x2000, 0x3000, 0x4000
+    out = ctypes.c_void_p(0x8000)
+    assert L.lb_step_sums_noalloc(None, 1, out) == abi.LB_EINVAL
+    # 479^3, the largest cube the kernels accept, fits the array
+    for shape, fits in (((479, 479, 479), True), ((1, 100000, 1), False),
+                        ((16, 16, 16), True)):
+        nx, ny, nz = shape
+        st, s = _query(abi, nx=nx, ny=ny, nz=nz)
+        assert st == abi.LB_OK
+        assert (s.scratch_bytes // 40 <= abi.NOALLOC_MAX_PARTIALS) == fits, shape
+        p = _params(abi, nx=nx, ny=ny, nz=nz)
+        assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
+        assert L.lb_step_sums_noalloc(ctx, 1, None) == abi.LB_EINVAL
+        assert L.lb_step_sums_noalloc(ctx, -1, out) == abi.LB_EINVAL
+        if not fits:
+            assert L.lb_step_sums_noalloc(ctx, 1, out) == abi.LB_EINVAL
+            assert b"partial blocks" in L.lb_last_error()
+        L.lb_destroy(ctx)
+
+
 def test_adjoint_step_next_validates_without_launching(abi):
     """lb_adjoint_step_next rejects a missing adjoint, a successor equal to
     state_t and a misaligned successor before any HIP call."""
@@ -215,7 +242,8 @@ def test_struct_layouts_and_enums_match_the_header(abi, tmp_path):
              "LB_LAYOUT_AOS": lbpy.LAYOUTS["aos"], "LB_LAYOUT_AOSOA": lbpy.LAYOUTS["aosoa"],
              "LB_COUPLING_STRESS": lbpy.COUPLINGS["stress"],
              "LB_COUPLING_FORCE": lbpy.COUPLINGS["force"],
-             "LB_OP_LB": lbpy.ORDER_PARAMS["lb"], "LB_OP_FD": lbpy.ORDER_PARAMS["fd"]}
+             "LB_OP_LB": lbpy.ORDER_PARAMS["lb"], "LB_OP_FD": lbpy.ORDER_PARAMS["fd"],
+             "LB_NOALLOC_MAX_PARTIALS": abi.NOALLOC_MAX_PARTIALS}
     for name in enums:
         lines.append(f'printf("enum {name} %d\\n", (int){name});')
     lines += ["return 0;", "}"]
