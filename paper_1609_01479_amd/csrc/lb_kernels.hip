@@ -432,7 +432,15 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
             pccur = pcn;
         }
     } else {
+        // Plain march (FP64, and FP32 ragged tiles), with the f pull of
+        // plane x+1 issued before plane x's collision so that those loads
+        // are in flight across its arithmetic and stores.  The registers for
+        // them come from parking the kept g values of plane x+1 in LDS (each
+        // thread its own slots) between their pull and their collision one
+        // iteration later; measured in FP64 at 256^3: 4% faster, now within
+        // 1% of the memory-only twin.
         K kcur[NV], knext[NV];
+        __shared__ K kst[NV][kFused];
         double pccur = 0.0, pcnext = 0.0;
         // warm-up: phi at planes x0-1 (slot 0) and x0 (slot 1), keeping
         // plane x0's populations
@@ -440,23 +448,32 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
         if (ring) ph[0][rly][rlz] = pull_phi(x0 - 1, rrow, rsite, nullptr, nullptr);
         if (active) ph[1][ly + 1][lz + 1] = pull_phi(x0, row, rowsite, kcur, &pccur);
         if (ring) ph[1][rly][rlz] = pull_phi(x0, rrow, rsite, nullptr, nullptr);
+        T fn[NV];
+        auto pull_f = [&](int X) __attribute__((always_inline)) {
+            const O pbx[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
+#pragma unroll
+            for (int i = 0; i < NV; i++)
+                fn[i] = ldc<SMALL>(sF, pbx[1 - CX[i]], i, compb, row.o[1 - CY[i]][1 - CZ[i]]);
+        };
+        if (active) pull_f(x0);
         for (int x = x0; x < x1; x++) {
             const int kk = x - x0 + 2;  // phi slot counter of plane x+1
             const int sn = kk & 3, sc = (kk - 1) & 3, sp = (kk - 2) & 3;
-            const O pbx[3] = {pbase(x - 1), pbase(x), pbase(x + 1)};
             T f[NV];
             if (active) {
-#pragma unroll
-                for (int i = 0; i < NV; i++)
-                    f[i] = ldc<SMALL>(sF, pbx[1 - CX[i]], i, compb, row.o[1 - CY[i]][1 - CZ[i]]);
                 ph[sn][ly + 1][lz + 1] = pull_phi(x + 1, row, rowsite, knext, &pcnext);
+#pragma unroll
+                for (int i = 0; i < NV; i++) kst[i][threadIdx.x] = knext[i];
             }
             if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, rrow, rsite, nullptr, nullptr);
             lds_barrier();
             if (active) {
+#pragma unroll
+                for (int i = 0; i < NV; i++) f[i] = vcopy(fn[i]);
+                if (x + 1 < x1) pull_f(x + 1);
                 update(x, f, kcur, pccur, sp, sc, sn);
 #pragma unroll
-                for (int i = 0; i < NV; i++) kcur[i] = knext[i];
+                for (int i = 0; i < NV; i++) kcur[i] = kst[i][threadIdx.x];
                 pccur = pcnext;
             }
         }
