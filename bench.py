@@ -470,12 +470,11 @@ def main():
         out["fd_order_parameter"]["phi_fp32_vs_fp64_max"] = float(
             np.abs(fd_phi["fp32_dev"] - fd_phi["fp64"]).max())
         del fd_phi
-        # with the force coupling: the two-kernel path, collision pass 344 / 176
-        # B per site (FP64 / FP32 storage; Pi at the face neighbours from the
-        # phi field, in cache; mu and u in the storage type) and flux pass
-        # 48 / 32
+        # with the force coupling: one marching kernel as well, f and phi
+        # read and written once (the scheme's minimum, 320 / 168 B per site;
+        # Pi, the force and the face ring's mu and u formed on chip)
         out["fd_order_parameter"]["force_coupling"] = {}
-        for prec, moved in (("fp32_dev", 208), ("fp64", 392)):
+        for prec, moved in (("fp32_dev", 168), ("fp64", 320)):
             lb = LB(shape, precision=prec, order_param="fd", coupling="force", device="cuda:0",
                     **lay, **params)
             lb.init_phi(phi0)
@@ -488,7 +487,7 @@ def main():
                 "ms_per_step": round(ms / args.fd_steps, 4),
                 "achieved_GBps": round(moved * nsites / t / 1e9, 1),
                 "frac": round(moved * nsites / t / 1e9 / HBM_PEAK_GBPS, 4),
-                "bytes_per_site": moved, "kernels": "k_fd_force_collide + k_fd_update"}
+                "bytes_per_site": moved, "kernels": "k_fd_force_fused"}
             del lb
             torch.cuda.empty_cache()
 

@@ -122,8 +122,10 @@ typedef enum {
                      collides as above with Pi in f^eq; with
                      LB_COUPLING_FORCE (the paper's arrangement) f collides
                      with F = -div Pi and u = (j + F/2)/rho is also the
-                     fluxes' velocity (that combination always runs the
-                     two-kernel path).  phi is FP64 in both
+                     fluxes' velocity.  Either coupling runs as one
+                     marching kernel (LB_KERNEL_FUSED) or as a collision
+                     pass and a flux pass (LB_KERNEL_TWO_PASS), with
+                     bit-identical results.  phi is FP64 in both
                      precisions.                                             */
 } lb_order_param;
 
@@ -259,9 +261,10 @@ lb_status lb_step_sums(lb_ctx *ctx, int32_t nsteps, double *sums_dev);
  * 5 FP64 partials (160 KiB), one copy per GPU the library runs on, kept until
  * the process ends; its address on the current GPU is looked up on the first
  * call there.  LB_EINVAL if the context's steps reduce over more blocks
- * (scratch_bytes / 40 > LB_NOALLOC_MAX_PARTIALS; every cube up to 479^3
- * fits), LB_ESTATE if the current device is not that of the context's
- * stream.  Every block overwrites its own partials before they are summed,
+ * than that (every cube up to 479^3 fits, except with LB_OP_FD and
+ * LB_KERNEL_TWO_PASS, whose collision pass reduces over one block per 256
+ * sites: up to about 1.05e6 sites), LB_ESTATE if the current device is not
+ * that of the context's stream.  Every block overwrites its own partials before they are summed,
  * so nothing carries over from an earlier call; but all contexts on one GPU
  * share the one array, so calls that overlap on one GPU (other streams,
  * other threads) race and must be serialised by the caller.  Passage: as

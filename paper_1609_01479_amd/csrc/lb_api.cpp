@@ -217,7 +217,7 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     const lbk::TileCfg tc = lbk::tile_config(k, p->segment_x, p->precision == LB_FP32_DEV);
     k.nsites = int(n);
     size_t nparts = std::max<size_t>(size_t(tc.ntiles) * tc.nseg, lbk::kMaxPartialBlocks);
-    if (fd) nparts = std::max<size_t>(nparts, size_t(lbk::fd_step_partial_blocks(k)));
+    if (fd) nparts = std::max<size_t>(nparts, size_t(lbk::fd_step_partial_blocks(k, p->segment_x)));
     out->scratch_bytes = nparts * 5 * 8;
     out->adj_bytes = size_t(kAdjComponents) * stride * e;
     out->face_bytes = p->halo_x ? lbk::face_bytes(k, p->precision == LB_FP32_DEV) : 0;
@@ -343,9 +343,9 @@ lb_status lb_step_sums_noalloc(lb_ctx* ctx, int32_t nsteps, double* sums_dev)
     if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
     if (!sums_dev) return fail(LB_EINVAL, "sums_dev is required");
     if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0 (got %d)", nsteps);
-    // the partial blocks any step of this context reduces over (the bound
-    // lb_query_sizes sized the context's scratch with)
-    const size_t need = ctx->sz.scratch_bytes / (5 * sizeof(double));
+    // the partial blocks this context's steps reduce over
+    const size_t need = size_t(ctx->kp.fd ? lbk::fd_sums_blocks(ctx->kp, ctx->tc, ctx->p.kernel)
+                                          : lbk::step_sums_blocks(ctx->kp, ctx->tc, ctx->p.kernel));
     if (need > size_t(LB_NOALLOC_MAX_PARTIALS))
         return fail(LB_EINVAL, "lb_step_sums_noalloc: this lattice reduces over %zu partial "
                                "blocks, the library's array holds %d (use lb_step_sums)",

@@ -20,12 +20,11 @@
 // sum phi changes only by the rounding of each site's own update.
 //
 // With the force coupling (the paper's arrangement: the stress divergence
-// acts on the fluid) the collision pass forms F = -div Pi from the phi field
-// and collides f with it, and the fluxes use u = (j + F/2)/rho; that
-// combination always runs a collision pass and the flux pass (a single pass
-// would need mu, u and F on a ring one cell wider): k_fd_force_collide
-// marching with Pi in LDS (LB_KERNEL_FUSED), or k_fd_collide one site per
-// thread (LB_KERNEL_TWO_PASS), bit-identical.
+// acts on the fluid) the collision forms F = -div Pi from the phi field and
+// collides f with it, and the fluxes use u = (j + F/2)/rho: one marching
+// kernel, k_fd_force_fused, with Pi staged in LDS and mu, u and F also formed
+// on the tile's face ring (LB_KERNEL_FUSED), or k_fd_collide one site per
+// thread and then k_fd_update (LB_KERNEL_TWO_PASS), bit-identical.
 //
 // Time level: F (19*stride elements of T in the layout of didx(); FP32 mode
 // stores f - w rho0) followed by phi (stride FP64 values in site order).
@@ -417,30 +416,69 @@ struct FdFused {
     }
 };
 
-// The collision pass of the force coupling, marching (LB_KERNEL_FUSED): the
-// tiling and plane loop of k_fd_fused with phi of the tile plus two cells
-// around it in an 8-plane LDS ring (from the phi field, loaded one plane
-// ahead), Pi of plane P formed once per site for the tile and its face ring
-// (LDS: the components the y and z neighbours need; registers: the own
-// column's x row) and the forcing collision of plane P-1, which writes f*,
-// mu and u = (j + F/2)/rho for k_fd_update.  Bit-identical to
-// k_fd_collide<T, DEV, true>, which forms Pi at each face neighbour.
-constexpr int kFdPhiSlots = 8;  // planes P-2 .. P+1 are read while P+2 is written
+// Single-pass step with the force coupling (LB_KERNEL_FUSED; the paper's
+// arrangement: the divergence of the chemical stress acts on the fluid, the
+// order parameter follows the finite-difference update).  A workgroup owns an
+// 8 x 64 tile of (y, z) columns (the perimeter, and with it the halo work,
+// is smaller than a 4 x 128 tile's) and marches over its x segment.  At
+// iteration P it
+//   (a) stores phi(P+1) of the tile plus three cells around it into a
+//       4-plane LDS ring (loaded one iteration earlier) and issues the pulls
+//       of f at the own cell of plane V = P-1;
+//   (b) forms Pi of plane P on the tile plus two cells around it (the cells
+//       that the forces of (c) need), keeping the x row Pi_xa of the own
+//       cell and of the thread's face-ring cell in registers (planes P-2 ..
+//       P) and the in-plane components in a 2-plane LDS ring;
+//   (c) forms F = -div Pi at the own cell of plane V and collides f there
+//       (stores it for V in the segment), and mu, u and phi of V for the
+//       fluxes: the own column in registers, the tile and its face ring
+//       (whose u needs the normal component of F and the ring cell's own
+//       pulls, which hit in cache) in a 2-plane LDS ring;
+//   (e) updates phi at plane U = P-2 from the fluxes through its six faces
+//       (fields of plane U written an iteration earlier).  Two LDS-only
+//       barriers per plane would suffice for the data (the collision's
+//       x - 1 neighbour phi is carried in registers, so no one reads the ring
+//       slot that the next iteration refills); a third after (c) keeps the
+//       waves in step and measured 6% (FP32) and 1% (FP64) faster.
+// Planes x0-1 and x1 only supply mu and u_x of the own column.  Every value
+// is formed with the instructions of the two-kernel path (k_fd_collide with
+// the force, then k_fd_update), with mu and u rounded to the work fields'
+// type, so both paths give bit-identical levels.
+struct FfTile {
+    static constexpr int TY = 8, TZ = 64;
+    static constexpr int BY = TY + 6, BZ = TZ + 6;   // phi box: three cells around the tile
+    static constexpr int NBOX = BY * BZ;
+    static constexpr int BOXPT = (NBOX + kFdFused - 1) / kFdFused;
+    static constexpr int PY = TY + 4, PZ = TZ + 4;   // Pi box: two cells around the tile
+    static constexpr int NPI = PY * PZ;
+    static constexpr int RY = TY + 2, RZ = TZ + 2;   // tile and its face ring
+    static constexpr int NR = RY * RZ;
+    static constexpr int NRING = 2 * (TY + TZ);      // face-ring cells
+    // Pi cells beyond the tile and its face ring that a face-ring force
+    // needs: the rows y0-2, y0+TY+1 and columns z0-2, z0+TZ+1 next to the
+    // ring, and the ring's four corners
+    static constexpr int NPIX = 2 * (TY + TZ) + 4;
+};
+static_assert(FfTile::TY * FfTile::TZ == kFdFused, "one site per thread");
+static_assert(FfTile::NPIX <= kFdFused && FfTile::NRING <= kFdFused, "halo cells per thread");
 
-template <typename T, bool DEV, int TZ>
-__global__ __launch_bounds__(kFdFused) void k_fd_force_collide(KParams p, TileCfg tc,
-                                                               const T* __restrict__ sF,
-                                                               const double* __restrict__ sphi,
-                                                               T* __restrict__ dF,
-                                                               FdWork<T, true>* __restrict__ work,
-                                                               double* __restrict__ partials)
+template <typename T, bool DEV>
+__global__ __launch_bounds__(kFdFused) void k_fd_force_fused(KParams p, TileCfg tc,
+                                                             const T* __restrict__ sF,
+                                                             const double* __restrict__ sphi,
+                                                             T* __restrict__ dF,
+                                                             double* __restrict__ dphi,
+                                                             double* __restrict__ partials)
 {
-    using G = FdTile<TZ>;
-    constexpr int TY = G::TY, BZ = G::BZ, RZ = G::RZ, NR = G::RY * G::RZ;
-    constexpr int SM = kFdPhiSlots - 1;
-    __shared__ double s_phi[kFdPhiSlots][G::NBOX];
-    __shared__ double s_piy[2][3][NR];  // Pi_xy, Pi_yy, Pi_yz: read by the y neighbours
-    __shared__ double s_piz[2][3][NR];  // Pi_xz, Pi_yz, Pi_zz: read by the z neighbours
+    using G = FfTile;
+    using W = FdWork<T, true>;
+    constexpr int TY = G::TY, TZ = G::TZ, BZ = G::BZ, PZ = G::PZ, RZ = G::RZ;
+    __shared__ double s_phi[4][G::NBOX];
+    __shared__ double s_pi[2][5][G::NPI];  // Pi_xy, Pi_xz, Pi_yy, Pi_yz, Pi_zz
+    __shared__ double s_ph[2][G::NR];
+    __shared__ W s_mu[2][G::NR];
+    __shared__ W s_uy[2][G::NR];
+    __shared__ W s_uz[2][G::NR];
 
     const int t = threadIdx.x;
     const int b = xcd_block();
@@ -449,19 +487,24 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_collide(KParams p, TileCf
     const int x0 = seg * tc.sx, x1 = min(p.nx, x0 + tc.sx);
     const int plane = p.ny * p.nz;
 
+    // own tile cell
     const int ly = t / TZ, lz = t % TZ;
     const int yg = wrap_any(y0 + ly, p.ny), zg = wrap_any(z0 + lz, p.nz);
     const bool valid = y0 + ly < p.ny && z0 + lz < p.nz;
-    const int bo = (ly + 2) * BZ + (lz + 2);
+    const int bo = (ly + 3) * BZ + (lz + 3);
+    const int po = (ly + 2) * PZ + (lz + 2);
     const int ro = (ly + 1) * RZ + (lz + 1);
+    // phi box cells loaded by this thread (in-plane offsets; -1: none)
     int boff[G::BOXPT];
 #pragma unroll
     for (int k = 0; k < G::BOXPT; k++) {
         const int c = t + k * kFdFused;
         boff[k] = c < G::NBOX
-                      ? wrap_any(y0 + c / BZ - 2, p.ny) * p.nz + wrap_any(z0 + c % BZ - 2, p.nz)
+                      ? wrap_any(y0 + c / BZ - 3, p.ny) * p.nz + wrap_any(z0 + c % BZ - 3, p.nz)
                       : -1;
     }
+    // face-ring cell of this thread (rows y0-1, y0+TY: u_y; columns z0-1,
+    // z0+TZ: u_z)
     const bool ring = t < G::NRING;
     int rly, rlz;
     if (t < TZ) { rly = -1; rlz = t; }
@@ -469,8 +512,22 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_collide(KParams p, TileCf
     else if (t < 2 * TZ + TY) { rly = t - 2 * TZ; rlz = -1; }
     else { rly = t - 2 * TZ - TY; rlz = TZ; }
     const bool ring_y = rly < 0 || rly >= TY;
-    const int rbo = (rly + 2) * BZ + (rlz + 2);
+    const int ryg = wrap_any(y0 + rly, p.ny), rzg = wrap_any(z0 + rlz, p.nz);
+    const int rbo = (rly + 3) * BZ + (rlz + 3);
+    const int rpo = (rly + 2) * PZ + (rlz + 2);
     const int rro = (rly + 1) * RZ + (rlz + 1);
+    // extra Pi cell of this thread, in Pi-box coordinates
+    const bool extra = t < G::NPIX;
+    int epy, epz;
+    if (t < TZ) { epy = 0; epz = t + 2; }
+    else if (t < 2 * TZ) { epy = G::PY - 1; epz = t - TZ + 2; }
+    else if (t < 2 * TZ + TY) { epy = t - 2 * TZ + 2; epz = 0; }
+    else if (t < 2 * (TY + TZ)) { epy = t - 2 * TZ - TY + 2; epz = PZ - 1; }
+    else { const int c = t - 2 * (TY + TZ); epy = (c & 1) ? TY + 2 : 1; epz = (c & 2) ? TZ + 2 : 1; }
+    const int ebo = (epy + 1) * BZ + (epz + 1);
+    const int epo = epy * PZ + epz;
+
+    const double M = p.mobility;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
     auto load_box = [&](int xp, double (&v)[G::BOXPT]) {
@@ -479,89 +536,108 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_collide(KParams p, TileCf
         for (int k = 0; k < G::BOXPT; k++) v[k] = boff[k] >= 0 ? sphi[xo + boff[k]] : 0.0;
     };
     auto store_box = [&](int xp, const double (&v)[G::BOXPT]) {
-        double* __restrict__ dst = s_phi[xp & SM];
+        double* __restrict__ dst = s_phi[xp & 3];
 #pragma unroll
         for (int k = 0; k < G::BOXPT; k++)
             if (boff[k] >= 0) dst[t + k * kFdFused] = v[k];
     };
+    // Pi at phi-box cell c of plane P (slots P-1, P, P+1)
+    auto pi_at = [&](const double* __restrict__ fm, const double* __restrict__ fc,
+                     const double* __restrict__ fp, int c, double (&tt)[6]) {
+        const Stencil st = stencil(fc[c], fp[c], fm[c], fc[c + BZ], fc[c - BZ], fc[c + 1], fc[c - 1]);
+        double mu;
+        chem_stress(p, st, &mu, tt);
+    };
+    auto store_pi = [&](int w, int c, const double (&tt)[6]) {
+        s_pi[w][0][c] = tt[1];
+        s_pi[w][1][c] = tt[2];
+        s_pi[w][2][c] = tt[3];
+        s_pi[w][3][c] = tt[4];
+        s_pi[w][4][c] = tt[5];
+    };
+
     double pre[G::BOXPT];
+    load_box(x0 - 3, pre);
+    store_box(x0 - 3, pre);
     load_box(x0 - 2, pre);
     store_box(x0 - 2, pre);
     load_box(x0 - 1, pre);
-    store_box(x0 - 1, pre);
-    load_box(x0, pre);
 
+    // own column: Pi_xa at planes P-2 (A), P-1 (B), P; phi, mu, u at the
+    // planes U-1 (A), U (B) of the flux update; the ring cell's Pi_xn
     double pxA[3] = {0.0, 0.0, 0.0}, pxB[3] = {0.0, 0.0, 0.0};
-    for (int P = x0 - 1; P <= x1; P++) {
-        const int X = P - 1;
-        const bool collide_x = X >= x0 && valid;
+    double rpA = 0.0, rpB = 0.0;
+    double phA = 0.0, muA = 0.0, uxA = 0.0;
+    double phB = 0.0, muB = 0.0, uxB = 0.0, uyB = 0.0, uzB = 0.0;
+    // phi of plane P-2 at the own cell and at the ring cell (the collision's
+    // x - 1 neighbour), so that no one reads that LDS slot after the
+    // iteration's second barrier: the next iteration refills it
+    double phm = 0.0, rphm = 0.0;
+    for (int P = x0 - 2; P <= x1 + 1; P++) {
+        const int V = P - 1;  // plane collided
+        const bool coll = V >= x0 - 1 && V <= x1;
+        const bool inner = V >= x0 && V < x1;
+        // (a) phi(P+1) into the ring, phi(P+2) into registers, pulls of V
         store_box(P + 1, pre);
-        load_box(P + 2, pre);
+        if (P + 2 <= x1 + 2) load_box(P + 2, pre);
+        const Geo q = geo_xyz(p, wrap_any(V, p.nx), yg, zg);
         T f[NV];
-        const Geo q = geo_xyz(p, wrap_any(X, p.nx), yg, zg);
-        if (collide_x)
+        if (coll)
 #pragma unroll
             for (int i = 0; i < NV; i++) f[i] = sF[dist_pull(p, q, i)];
         lds_barrier();
-        const double* __restrict__ fm = s_phi[(P - 1) & SM];
-        const double* __restrict__ fc = s_phi[P & SM];
-        const double* __restrict__ fp = s_phi[(P + 1) & SM];
-        const int w = P & 1;
 
-        // Pi of plane P
-        double pxP[3];
+        // (b) Pi of plane P
+        const double* __restrict__ fm = s_phi[(P - 1) & 3];
+        const double* __restrict__ fc = s_phi[P & 3];
+        const double* __restrict__ fp = s_phi[(P + 1) & 3];
+        const int wp = P & 1;
+        double pxP[3], rpP = 0.0;
         {
-            const Stencil st = stencil(fc[bo], fp[bo], fm[bo], fc[bo + BZ], fc[bo - BZ], fc[bo + 1],
-                                       fc[bo - 1]);
-            double mu, tt[6];
-            chem_stress(p, st, &mu, tt);
+            double tt[6];
+            pi_at(fm, fc, fp, bo, tt);
             pxP[0] = tt[0];
             pxP[1] = tt[1];
             pxP[2] = tt[2];
-            s_piy[w][0][ro] = tt[1];
-            s_piy[w][1][ro] = tt[3];
-            s_piy[w][2][ro] = tt[4];
-            s_piz[w][0][ro] = tt[2];
-            s_piz[w][1][ro] = tt[4];
-            s_piz[w][2][ro] = tt[5];
+            store_pi(wp, po, tt);
         }
-        if (ring && P >= x0 && P < x1) {
-            const Stencil st = stencil(fc[rbo], fp[rbo], fm[rbo], fc[rbo + BZ], fc[rbo - BZ],
-                                       fc[rbo + 1], fc[rbo - 1]);
-            double mu, tt[6];
-            chem_stress(p, st, &mu, tt);
-            if (ring_y) {
-                s_piy[w][0][rro] = tt[1];
-                s_piy[w][1][rro] = tt[3];
-                s_piy[w][2][rro] = tt[4];
-            } else {
-                s_piz[w][0][rro] = tt[2];
-                s_piz[w][1][rro] = tt[4];
-                s_piz[w][2][rro] = tt[5];
-            }
+        if (ring) {
+            double tt[6];
+            pi_at(fm, fc, fp, rbo, tt);
+            rpP = ring_y ? tt[1] : tt[2];  // Pi_xy (row) or Pi_xz (column)
+            store_pi(wp, rpo, tt);
         }
+        if (extra) {
+            double tt[6];
+            pi_at(fm, fc, fp, ebo, tt);
+            store_pi(wp, epo, tt);
+        }
+        lds_barrier();
 
-        // the forcing collision of plane X = P-1
-        if (collide_x) {
-            const int v = X & 1;
-            const double* __restrict__ xm = s_phi[(X - 1) & SM];
-            const double* __restrict__ xc = s_phi[X & SM];
-            const double* __restrict__ xp = s_phi[(X + 1) & SM];
-            const double c = xc[bo];
-            const Stencil st = stencil(c, xp[bo], xm[bo], xc[bo + BZ], xc[bo - BZ], xc[bo + 1],
-                                       xc[bo - 1]);
+        // (c) force, collision and flux fields of plane V
+        const int wv = V & 1;
+        double phC = 0.0, muC = 0.0, uxC = 0.0, uyC = 0.0, uzC = 0.0;
+        if (coll) {
             // F_a = -sum_b [Pi_ab(x + e_b) - Pi_ab(x - e_b)] / 2, b = x, y, z in order
+            const double* __restrict__ pv = &s_pi[wv][0][0];
+            constexpr int KY[3] = {0, 2, 3};  // Pi_xy, Pi_yy, Pi_yz
+            constexpr int KZ[3] = {1, 3, 4};  // Pi_xz, Pi_yz, Pi_zz
             double div[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int a = 0; a < 3; a++) div[a] += 0.5 * (pxP[a] - pxA[a]);
 #pragma unroll
-            for (int a = 0; a < 3; a++) div[a] += 0.5 * (s_piy[v][a][ro + RZ] - s_piy[v][a][ro - RZ]);
+            for (int a = 0; a < 3; a++)
+                div[a] += 0.5 * (pv[KY[a] * G::NPI + po + PZ] - pv[KY[a] * G::NPI + po - PZ]);
 #pragma unroll
-            for (int a = 0; a < 3; a++) div[a] += 0.5 * (s_piz[v][a][ro + 1] - s_piz[v][a][ro - 1]);
+            for (int a = 0; a < 3; a++)
+                div[a] += 0.5 * (pv[KZ[a] * G::NPI + po + 1] - pv[KZ[a] * G::NPI + po - 1]);
             double F[3];
 #pragma unroll
             for (int a = 0; a < 3; a++) F[a] = -div[a];
-            if (partials) {
+            const double c = fm[bo];
+            const Stencil st = stencil(c, fc[bo], phm, fm[bo + BZ], fm[bo - BZ], fm[bo + 1],
+                                       fm[bo - 1]);
+            if (partials && inner && valid) {
                 double bs = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
                 for (int i = 0; i < NV; i++) {
@@ -578,33 +654,82 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_collide(KParams p, TileCf
                 acc[4] += jz + 0.5 * F[2];
             }
             const Vel<T> u = collide_force_f<T, DEV>(p, f, F);
+            if (inner && valid)
 #pragma unroll
-            for (int i = 0; i < NV; i++) __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
-            const int s = X * plane + yg * p.nz + zg;
-            using W = FdWork<T, true>;
-            work[s] = W(fd_mu(p, c, st.lap));
-            work[p.stride + s] = W(u.x);
-            work[2 * p.stride + s] = W(u.y);
-            work[3 * p.stride + s] = W(u.z);
+                for (int i = 0; i < NV; i++) __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
+            const W muw = W(fd_mu(p, c, st.lap)), uyw = W(u.y), uzw = W(u.z);
+            phC = c;
+            muC = double(muw);
+            uxC = double(W(u.x));
+            uyC = double(uyw);
+            uzC = double(uzw);
+            s_ph[wv][ro] = c;
+            s_mu[wv][ro] = muw;
+            s_uy[wv][ro] = uyw;
+            s_uz[wv][ro] = uzw;
+        }
+        if (ring && inner) {
+            // mu and the face-normal velocity u_n = (j_n + F_n/2)/rho of the
+            // ring cell of plane V, F_n = -div Pi's n component
+            const Geo qr = geo_xyz(p, wrap_any(V, p.nx), ryg, rzg);
+            T fr[NV];
+#pragma unroll
+            for (int i = 0; i < NV; i++) fr[i] = sF[dist_pull(p, qr, i)];
+            const double* __restrict__ pv = &s_pi[wv][0][0];
+            const int ky = ring_y ? 2 : 3, kz = ring_y ? 3 : 4;  // Pi_ny, Pi_nz
+            double div = 0.0;
+            div += 0.5 * (rpP - rpA);
+            div += 0.5 * (pv[ky * G::NPI + rpo + PZ] - pv[ky * G::NPI + rpo - PZ]);
+            div += 0.5 * (pv[kz * G::NPI + rpo + 1] - pv[kz * G::NPI + rpo - 1]);
+            const double Fn = -div;
+            const Moments<T> m = moments_of<T, DEV>(p, fr);
+            const T ri = T(1) / m.rho;
+            const T un = ((ring_y ? m.jy : m.jz) + T(0.5) * T(Fn)) * ri;
+            const double c = fm[rbo];
+            const Stencil sr = stencil(c, fc[rbo], rphm, fm[rbo + BZ], fm[rbo - BZ], fm[rbo + 1],
+                                       fm[rbo - 1]);
+            s_ph[wv][rro] = c;
+            s_mu[wv][rro] = W(fd_mu(p, c, sr.lap));
+            if (ring_y)
+                s_uy[wv][rro] = W(un);
+            else
+                s_uz[wv][rro] = W(un);
+        }
+        // phi(V) of the own and ring cells: phi(V-1) of the next iteration
+        phm = fm[bo];
+        if (ring) rphm = fm[rbo];
+        lds_barrier();  // not needed for the data (see above): keeps the waves in step
+
+        // (e) phi(t+1) at plane U = P-2 (the fields of plane U were written
+        // in the previous iteration)
+        const int U = P - 2;
+        if (U >= x0 && U < x1 && valid) {
+            const int v = U & 1;
+            const double pc = phB, mc = muB, uc = uxB;
+            double dv = 0.0;
+            dv += fd_flux(pc, phC, uc, uxC, mc, muC, M) - fd_flux(phA, pc, uxA, uc, muA, mc, M);
+            dv += fd_flux(pc, s_ph[v][ro + RZ], uyB, double(s_uy[v][ro + RZ]), mc,
+                          double(s_mu[v][ro + RZ]), M)
+                - fd_flux(s_ph[v][ro - RZ], pc, double(s_uy[v][ro - RZ]), uyB,
+                          double(s_mu[v][ro - RZ]), mc, M);
+            dv += fd_flux(pc, s_ph[v][ro + 1], uzB, double(s_uz[v][ro + 1]), mc,
+                          double(s_mu[v][ro + 1]), M)
+                - fd_flux(s_ph[v][ro - 1], pc, double(s_uz[v][ro - 1]), uzB,
+                          double(s_mu[v][ro - 1]), mc, M);
+            __builtin_nontemporal_store(pc - dv, &dphi[U * plane + yg * p.nz + zg]);
         }
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             pxA[a] = pxB[a];
             pxB[a] = pxP[a];
         }
+        rpA = rpB;
+        rpB = rpP;
+        phA = phB; muA = muB; uxA = uxB;
+        phB = phC; muB = muC; uxB = uxC; uyB = uyC; uzB = uzC;
     }
     if (partials) block_partials<5, kFdFused>(acc, partials);
 }
-
-template <typename T>
-struct FdForce {
-    using K = decltype(&k_fd_force_collide<T, std::is_same<T, float>::value, 128>);
-    static K get(int tz)
-    {
-        constexpr bool DEV = std::is_same<T, float>::value;
-        return tz == 64 ? k_fd_force_collide<T, DEV, 64> : k_fd_force_collide<T, DEV, 128>;
-    }
-};
 
 // Dense FP64 moments and block partials of [rho, phi, jx, jy, jz]
 // (grid-stride); u = j/rho, or with FORCE (j + F/2)/rho and sums of j + F/2.
@@ -933,6 +1058,39 @@ FdTiles fd_tiles(const KParams& p)
     return t;
 }
 
+// Geometry of k_fd_force_fused: 8 x 64 tiles times x segments; a workgroup
+// holds a CU, so they run in rounds of 256, and a segment of s planes costs
+// s + 4 iterations (the pipeline's fill and drain): the segment count
+// minimises rounds * (s + 4) unless the caller fixed the segment length.
+constexpr int kFfCUs = 256;
+
+TileCfg ff_tiles(const KParams& p, int seg_req)
+{
+    TileCfg tc;
+    tc.tz = FfTile::TZ;
+    tc.nty = (p.ny + FfTile::TY - 1) / FfTile::TY;
+    tc.ntz = (p.nz + FfTile::TZ - 1) / FfTile::TZ;
+    tc.ntiles = tc.nty * tc.ntz;
+    tc.seg_req = seg_req;
+    int sx = seg_req;
+    if (sx <= 0) {
+        long long best = -1;
+        for (int nseg = 1; nseg <= p.nx; nseg++) {
+            const int sl = (p.nx + nseg - 1) / nseg;
+            const long long nb = (long long)tc.ntiles * ((p.nx + sl - 1) / sl);
+            const long long cost = ((nb + kFfCUs - 1) / kFfCUs) * (sl + 4);
+            if (best < 0 || cost < best) {
+                best = cost;
+                sx = sl;
+            }
+        }
+    }
+    if (sx > p.nx) sx = p.nx;
+    tc.sx = sx;
+    tc.nseg = (p.nx + sx - 1) / sx;
+    return tc;
+}
+
 int fd_reduction_grid(const KParams& p)
 {
     const int g = fd_grid(p);
@@ -957,7 +1115,22 @@ int fd_reduction_grid(const KParams& p)
 
 }  // namespace
 
-int fd_step_partial_blocks(const KParams& p) { return fd_grid(p); }
+int fd_step_partial_blocks(const KParams& p, int segment_x)
+{
+    const TileCfg ft = ff_tiles(p, segment_x);
+    const int g = fd_grid(p);
+    return ft.ntiles * ft.nseg > g ? ft.ntiles * ft.nseg : g;
+}
+
+int fd_sums_blocks(const KParams& p, const TileCfg& tc, int variant)
+{
+    if (variant != 0) return fd_grid(p);
+    if (p.force) {
+        const TileCfg ft = ff_tiles(p, tc.seg_req);
+        return ft.ntiles * ft.nseg;
+    }
+    return tc.ntiles * tc.nseg;
+}
 
 hipError_t launch_fd_init(const KParams& p, bool fp32, void* state, const double* phi0,
                           hipStream_t s)
@@ -978,19 +1151,15 @@ hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int va
 {
     int nparts;
     if (variant == 0 && p.force) {
-        // marching collision pass with the force, then the flux pass
-        const FdTiles ft = fd_tiles(p);
-        nparts = tc.ntiles * tc.nseg;
+        // one marching pass: force, collision and flux update
+        const TileCfg ft = ff_tiles(p, tc.seg_req);
+        nparts = ft.ntiles * ft.nseg;
 #define CALL                                                                                  \
     {                                                                                         \
         FdLvl<T> a = fd_level<T>(const_cast<void*>(src), p);                                  \
         FdLvl<T> d = fd_level<T>(dst, p);                                                     \
-        using W = FdWork<T, true>;                                                            \
-        W* w = reinterpret_cast<W*>(work);                                                    \
-        FdForce<T>::get(tc.tz)<<<nparts, kFdFused, 0, s>>>(p, tc, a.F, a.phi, d.F, w,         \
-                                                           sums_out ? partials : nullptr);    \
-        k_fd_update<W><<<ft.ntiles * ft.nseg, kBlock, 0, s>>>(p, ft.ntz, ft.ntiles, ft.sx,    \
-                                                              a.phi, w, d.phi);               \
+        k_fd_force_fused<T, DEV><<<nparts, kFdFused, 0, s>>>(p, ft, a.F, a.phi, d.F, d.phi,    \
+                                                             sums_out ? partials : nullptr);  \
     }
         LB_FD_DISPATCH(fp32, CALL);
 #undef CALL

@@ -35,6 +35,7 @@ struct TileCfg {
     int tz;                // tile width along z (128 or 64; kFused/tz rows)
     int nty, ntz, ntiles;  // tiles along y, along z, total
     int sx, nseg;          // planes per x segment, number of segments
+    int seg_req;           // segment length asked for (<= 0: automatic)
 };
 
 // A time level's regions (LB order parameter): F and G of 19*stride
@@ -79,6 +80,8 @@ hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* p
 // kMaxPartialBlocks) doubles).
 // phi_src_out (FP64 mode, may be null): also store phi of src there (N
 // FP64 values in site order, bit-identical to launch_phi's).
+// The number of partial blocks the LB-scheme step of `variant` reduces over.
+int step_sums_blocks(const KParams& p, const TileCfg& tc, int variant);
 hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
                        const void* src, void* dst, double* phi_work, double* partials,
                        double* sums_out, double* phi_src_out, hipStream_t s);
@@ -144,8 +147,10 @@ hipError_t launch_adj_export(const KParams& p, bool fp32, const void* adj, doubl
 // update pass, with `work` holding mu, u_x, u_y, u_z (4 fields of `stride`:
 // FP64, or FP32 with the force coupling in FP32 storage; 4 FP64 fields of
 // space).  With sums_out, `partials` needs 5 * max(tc.ntiles * tc.nseg,
-// fd_step_partial_blocks(p)) doubles.
-int fd_step_partial_blocks(const KParams& p);
+// fd_step_partial_blocks(p, segment_x)) doubles; fd_sums_blocks gives the
+// exact number of partial blocks the step of `variant` reduces over.
+int fd_step_partial_blocks(const KParams& p, int segment_x);
+int fd_sums_blocks(const KParams& p, const TileCfg& tc, int variant);
 hipError_t launch_fd_init(const KParams& p, bool fp32, void* state, const double* phi0,
                           hipStream_t s);
 hipError_t launch_fd_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,

@@ -759,7 +759,14 @@ TileCfg tile_config(const KParams& p, int segment_x, bool fp32)
     if (sx > p.nx) sx = p.nx;
     tc.sx = sx;
     tc.nseg = (p.nx + sx - 1) / sx;
+    tc.seg_req = segment_x;
     return tc;
+}
+
+int step_sums_blocks(const KParams& p, const TileCfg& tc, int variant)
+{
+    if (p.force || variant == 1) return reduction_grid(p);
+    return tc.ntiles * tc.nseg;
 }
 
 hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* phi0, hipStream_t s)

@@ -108,10 +108,11 @@ def test_fd_flow_advects_phi():
                                        ((24, 20, 192), 0)])
 def test_fd_single_pass_matches_two_pass(precision, shape, seg, coupling):
     """The marching kernels (stress: collision one plane ahead of the flux
-    update, face ring in LDS; force: the collision pass with Pi in LDS) and
-    the one-site-per-thread kernels give bit-identical levels: ragged tiles
-    in y and z, 4 x 128 and 8 x 64 tiles, one-plane and long x segments,
-    extents 1 and 2."""
+    update, face ring in LDS; force: Pi staged in LDS, the force, mu and u
+    also on the face ring, collision two planes ahead of the flux update)
+    and the one-site-per-thread kernels give bit-identical levels: ragged
+    tiles in y and z, 4 x 128 and 8 x 64 tiles, one-plane and long x
+    segments, extents 1 and 2."""
     print(f"[fd fused] {shape} segment_x={seg} {precision} {coupling}", flush=True)
     phi0 = lbinputs.spinodal_phi0(shape, seed=17, amp=0.4)
     out = []
