@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(KParams p, T* __restrict__ 
 // transposed local collision Jacobian at x with the forward locals recomputed
 // from the saved state; writes lf, lg of the previous level, the stencil
 // cotangents, and block partials of d/d(A, B, kappa).
-template <typename T, bool DEV>
+template <typename T, typename AR, bool DEV>
 __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __restrict__ F,
                                                const double* __restrict__ phi,
                                                const T* __restrict__ an, T* __restrict__ ap,
@@ -63,14 +63,15 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
     for (XcdSweep w = xcd_sweep(p.nsites, kBlock); w.s < w.end; w.s += w.stride) {
         const int s = w.s;
         const Geo q = geo_of(p, s);
-        T lf[NV], lg[NV], f[NV];
+        AR lf[NV], lg[NV];
+        T f[NV];
 #pragma unroll
         for (int i = 0; i < NV; i++) {
             const int d = push_site(p, q, i);
             // lambda_f and lambda_g of the later level are read once (non-
             // temporal); lambda_phi at d is gathered by 19 sites (cached)
-            lf[i] = __builtin_nontemporal_load(&an[i * S + d]);
-            lg[i] = __builtin_nontemporal_load(&an[(NV + i) * S + d]) + an[2 * NV * S + d];
+            lf[i] = AR(__builtin_nontemporal_load(&an[i * S + d]));
+            lg[i] = AR(__builtin_nontemporal_load(&an[(NV + i) * S + d])) + AR(an[2 * NV * S + d]);
             f[i] = F[dist_pull(p, q, i)];
         }
         const Stencil st = stencil(phi[s], phi[site_of(p, q.xp, q.y, q.z)],
@@ -79,19 +80,21 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
                                    phi[site_of(p, q.x, q.ym, q.z)],
                                    phi[site_of(p, q.x, q.y, q.zp)],
                                    phi[site_of(p, q.x, q.y, q.zm)]);
-        const T A = T(p.A), B = T(p.B), kap = T(p.kappa), gam = T(p.gamma);
-        const T omf = T(p.omega_f), omg = T(p.omega_g);
-        const Moments<T> m = moments_of<T, DEV>(p, f);
-        const T ri = T(1) / m.rho;
-        const T ux = m.jx * ri, uy = m.jy * ri, uz = m.jz * ri;
-        const T phi_c = T(st.phi), gx = T(st.gx), gy = T(st.gy), gz = T(st.gz), lap = T(st.lap);
+        const AR A = AR(p.A), B = AR(p.B), kap = AR(p.kappa), gam = AR(p.gamma);
+        const AR omf = AR(p.omega_f), omg = AR(p.omega_g);
+        // the forward step's own rho and u (in the storage type's arithmetic)
+        const Moments<T> mt = moments_of<T, DEV>(p, f);
+        const T rit = T(1) / mt.rho;
+        const AR ri = AR(rit);
+        const AR ux = AR(mt.jx * rit), uy = AR(mt.jy * rit), uz = AR(mt.jz * rit);
+        const AR phi_c = AR(st.phi), gx = AR(st.gx), gy = AR(st.gy), gz = AR(st.gz), lap = AR(st.lap);
 
-        T s0 = 0, s1x = 0, s1y = 0, s1z = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
-        T t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
+        AR s0 = 0, s1x = 0, s1y = 0, s1z = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
+        AR t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            const T wl = T(weight(i)) * omf * lf[i];
-            const T wg = T(weight(i)) * omg * lg[i];
+            const AR wl = AR(weight(i)) * omf * lf[i];
+            const AR wg = AR(weight(i)) * omg * lg[i];
             s0 += wl;
             t0 += wg;
             if (CX[i]) { s1x += CX[i] * wl; t1x += CX[i] * wg; sxx += wl; txx += wg; }
@@ -101,49 +104,49 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
             if (CX[i] * CZ[i]) { sxz += CX[i] * CZ[i] * wl; txz += CX[i] * CZ[i] * wg; }
             if (CY[i] * CZ[i]) { syz += CY[i] * CZ[i] * wl; tyz += CY[i] * CZ[i] * wg; }
         }
-        const T third = T(1.0 / 3.0);
+        const AR third = AR(1.0 / 3.0);
         sxx -= third * s0; syy -= third * s0; szz -= third * s0;
         txx -= third * t0; tyy -= third * t0; tzz -= third * t0;
-        const T trs = sxx + syy + szz, trt = txx + tyy + tzz;
-        const T s2ux = sxx * ux + sxy * uy + sxz * uz;
-        const T s2uy = sxy * ux + syy * uy + syz * uz;
-        const T s2uz = sxz * ux + syz * uy + szz * uz;
-        const T t2ux = txx * ux + txy * uy + txz * uz;
-        const T t2uy = txy * ux + tyy * uy + tyz * uz;
-        const T t2uz = txz * ux + tyz * uy + tzz * uz;
-        const T s2uu = s2ux * ux + s2uy * uy + s2uz * uz;
-        const T t2uu = t2ux * ux + t2uy * uy + t2uz * uz;
-        const T t1u = t1x * ux + t1y * uy + t1z * uz;
-        const T s2gx = sxx * gx + sxy * gy + sxz * gz;
-        const T s2gy = sxy * gx + syy * gy + syz * gz;
-        const T s2gz = sxz * gx + syz * gy + szz * gz;
-        const T gsg = s2gx * gx + s2gy * gy + s2gz * gz;
-        const T h = T(4.5);
-        const T pr = phi_c * ri;
+        const AR trs = sxx + syy + szz, trt = txx + tyy + tzz;
+        const AR s2ux = sxx * ux + sxy * uy + sxz * uz;
+        const AR s2uy = sxy * ux + syy * uy + syz * uz;
+        const AR s2uz = sxz * ux + syz * uy + szz * uz;
+        const AR t2ux = txx * ux + txy * uy + txz * uz;
+        const AR t2uy = txy * ux + tyy * uy + tyz * uz;
+        const AR t2uz = txz * ux + tyz * uy + tzz * uz;
+        const AR s2uu = s2ux * ux + s2uy * uy + s2uz * uz;
+        const AR t2uu = t2ux * ux + t2uy * uy + t2uz * uz;
+        const AR t1u = t1x * ux + t1y * uy + t1z * uz;
+        const AR s2gx = sxx * gx + sxy * gy + sxz * gz;
+        const AR s2gy = sxy * gx + syy * gy + syz * gz;
+        const AR s2gz = sxz * gx + syz * gy + szz * gz;
+        const AR gsg = s2gx * gx + s2gy * gy + s2gz * gz;
+        const AR h = AR(4.5);
+        const AR pr = phi_c * ri;
 
-        const T arho = s0 - h * s2uu - T(3) * pr * t1u - T(9) * pr * t2uu;
-        const T ajx = T(3) * s1x + T(9) * s2ux + T(3) * pr * t1x + T(9) * pr * t2ux;
-        const T ajy = T(3) * s1y + T(9) * s2uy + T(3) * pr * t1y + T(9) * pr * t2uy;
-        const T ajz = T(3) * s1z + T(9) * s2uz + T(3) * pr * t1z + T(9) * pr * t2uz;
-        const T cf = T(1) - omf, cg = T(1) - omg;
+        const AR arho = s0 - h * s2uu - AR(3) * pr * t1u - AR(9) * pr * t2uu;
+        const AR ajx = AR(3) * s1x + AR(9) * s2ux + AR(3) * pr * t1x + AR(9) * pr * t2ux;
+        const AR ajy = AR(3) * s1y + AR(9) * s2uy + AR(3) * pr * t1y + AR(9) * pr * t2uy;
+        const AR ajz = AR(3) * s1z + AR(9) * s2uz + AR(3) * pr * t1z + AR(9) * pr * t2uz;
+        const AR cf = AR(1) - omf, cg = AR(1) - omg;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            T v = cf * lf[i] + arho;
+            AR v = cf * lf[i] + arho;
             if (CX[i]) v += CX[i] * ajx;
             if (CY[i]) v += CY[i] * ajy;
             if (CZ[i]) v += CZ[i] * ajz;
-            __builtin_nontemporal_store(v, &ap[i * S + s]);
-            __builtin_nontemporal_store(cg * lg[i], &ap[(NV + i) * S + s]);
+            __builtin_nontemporal_store(T(v), &ap[i * S + s]);
+            __builtin_nontemporal_store(T(cg * lg[i]), &ap[(NV + i) * S + s]);
         }
-        const T phi2 = phi_c * phi_c;
-        const T a_dir = h * trs * (A * phi_c + T(3) * B * phi2 * phi_c - kap * lap) + t0
-                      + T(3) * t1u + h * (gam * (A + T(3) * B * phi2) - third) * trt + h * t2uu;
-        const T hk = h * kap;
-        __builtin_nontemporal_store(a_dir, &sc[0 * S + s]);
-        __builtin_nontemporal_store(hk * (T(2) * s2gx - trs * gx), &sc[1 * S + s]);
-        __builtin_nontemporal_store(hk * (T(2) * s2gy - trs * gy), &sc[2 * S + s]);
-        __builtin_nontemporal_store(hk * (T(2) * s2gz - trs * gz), &sc[3 * S + s]);
-        __builtin_nontemporal_store(-hk * (phi_c * trs + gam * trt), &sc[4 * S + s]);
+        const AR phi2 = phi_c * phi_c;
+        const AR a_dir = h * trs * (A * phi_c + AR(3) * B * phi2 * phi_c - kap * lap) + t0
+                      + AR(3) * t1u + h * (gam * (A + AR(3) * B * phi2) - third) * trt + h * t2uu;
+        const AR hk = h * kap;
+        __builtin_nontemporal_store(T(a_dir), &sc[0 * S + s]);
+        __builtin_nontemporal_store(T(hk * (AR(2) * s2gx - trs * gx)), &sc[1 * S + s]);
+        __builtin_nontemporal_store(T(hk * (AR(2) * s2gy - trs * gy)), &sc[2 * S + s]);
+        __builtin_nontemporal_store(T(hk * (AR(2) * s2gz - trs * gz)), &sc[3 * S + s]);
+        __builtin_nontemporal_store(T(-hk * (phi_c * trs + gam * trt)), &sc[4 * S + s]);
         const double g2 = st.gx * st.gx + st.gy * st.gy + st.gz * st.gz;
         const double dtrs = double(trs), dtrt = double(trt), dph = st.phi;
         dth[0] += 4.5 * (dtrs * 0.5 * dph * dph + p.gamma * dph * dtrt);
@@ -153,16 +156,18 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
     block_partials<3>(dth, partials);
 }
 
-// FP32 storage: one load or store instruction moves 256 bytes per wavefront,
-// so the kernel needs many waves in flight; 4 per SIMD (at most 128 VGPRs)
-// measured 13% faster than the 3 its natural allocation allows.  FP64 keeps
-// its full register allocation (capping it spills).
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adj_local_f32(
+// FP32 storage with FP64 arithmetic: the transposed collision sums 19
+// weighted cotangents into moments that nearly cancel, and in FP32 those
+// roundings, repeated over a long rollout, dominated the gradient's error
+// (1e-4 relative over 1000 steps at 128^3; 5e-6 in FP64, at no cost in
+// time).  The forward's own rho and u are formed in FP32, as the step forms
+// them, and then widened.
+__global__ __launch_bounds__(kBlock) void k_adj_local_f32(
     KParams p, const float* __restrict__ F, const double* __restrict__ phi,
     const float* __restrict__ an, float* __restrict__ ap, float* __restrict__ sc,
     double* __restrict__ partials)
 {
-    adj_local_body<float, true>(p, F, phi, an, ap, sc, partials);
+    adj_local_body<float, double, true>(p, F, phi, an, ap, sc, partials);
 }
 
 __global__ __launch_bounds__(kBlock) void k_adj_local_f64(
@@ -170,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_local_f64(
     const double* __restrict__ an, double* __restrict__ ap, double* __restrict__ sc,
     double* __restrict__ partials)
 {
-    adj_local_body<double, false>(p, F, phi, an, ap, sc, partials);
+    adj_local_body<double, double, false>(p, F, phi, an, ap, sc, partials);
 }
 
 // Force coupling (u = (j + F/2)/rho in both equilibria, f^eq = w rho (1 +
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_local_f64(
 // through Pi at the face neighbours: k_adj_force_pi.
 // F_IN: F comes from k_adj_force_f in the dL/dF slots of sc (read at the own
 // site before they are overwritten), instead of being formed here.
-template <typename T, bool DEV, bool F_IN>
+template <typename T, typename AR, bool DEV, bool F_IN>
 __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* __restrict__ F,
                                                      const double* __restrict__ phi,
                                                      const T* __restrict__ an, T* __restrict__ ap,
@@ -197,18 +202,19 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
 {
     double dth[3] = {0.0, 0.0, 0.0};
     const unsigned S = p.stride;
-    const T A = T(p.A), B = T(p.B), kap = T(p.kappa), gam = T(p.gamma);
-    const T omf = T(p.omega_f), omg = T(p.omega_g), pref = T(1) - T(0.5) * omf;
-    const T h = T(4.5), third = T(1.0 / 3.0);
+    const AR A = AR(p.A), B = AR(p.B), kap = AR(p.kappa), gam = AR(p.gamma);
+    const AR omf = AR(p.omega_f), omg = AR(p.omega_g), pref = AR(1) - AR(0.5) * omf;
+    const AR h = AR(4.5), third = AR(1.0 / 3.0);
     for (XcdSweep w = xcd_sweep(p.nsites, kBlock); w.s < w.end; w.s += w.stride) {
         const int s = w.s;
         const Geo q = geo_of(p, s);
-        T lf[NV], lg[NV], f[NV];
+        AR lf[NV], lg[NV];
+        T f[NV];
 #pragma unroll
         for (int i = 0; i < NV; i++) {
             const int d = push_site(p, q, i);
-            lf[i] = __builtin_nontemporal_load(&an[i * S + d]);
-            lg[i] = __builtin_nontemporal_load(&an[(NV + i) * S + d]) + an[2 * NV * S + d];
+            lf[i] = AR(__builtin_nontemporal_load(&an[i * S + d]));
+            lg[i] = AR(__builtin_nontemporal_load(&an[(NV + i) * S + d])) + AR(an[2 * NV * S + d]);
             f[i] = F[dist_pull(p, q, i)];
         }
         const Stencil st = stencil(phi[s], phi[site_of(p, q.xp, q.y, q.z)],
@@ -217,30 +223,33 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
                                    phi[site_of(p, q.x, q.ym, q.z)],
                                    phi[site_of(p, q.x, q.y, q.zp)],
                                    phi[site_of(p, q.x, q.y, q.zm)]);
-        T Fx, Fy, Fz;
+        // the forward step's own F, rho and u (the storage type's arithmetic)
+        T Ft[3];
         if (F_IN) {
-            Fx = sc[5 * S + s];
-            Fy = sc[6 * S + s];
-            Fz = sc[7 * S + s];
+            Ft[0] = sc[5 * S + s];
+            Ft[1] = sc[6 * S + s];
+            Ft[2] = sc[7 * S + s];
         } else {
             double Fd[3];
             force_from_phi(p, q, phi, Fd);
-            Fx = T(Fd[0]);
-            Fy = T(Fd[1]);
-            Fz = T(Fd[2]);
+            Ft[0] = T(Fd[0]);
+            Ft[1] = T(Fd[1]);
+            Ft[2] = T(Fd[2]);
         }
-        const Moments<T> m = moments_of<T, DEV>(p, f);
-        const T rho = m.rho, ri = T(1) / rho;
-        const T ux = (m.jx + T(0.5) * Fx) * ri, uy = (m.jy + T(0.5) * Fy) * ri,
-                uz = (m.jz + T(0.5) * Fz) * ri;
-        const T phi_c = T(st.phi);
+        const Moments<T> mt = moments_of<T, DEV>(p, f);
+        const T rit = T(1) / mt.rho;
+        const AR Fx = AR(Ft[0]), Fy = AR(Ft[1]), Fz = AR(Ft[2]);
+        const AR rho = AR(mt.rho), ri = AR(rit);
+        const AR ux = AR((mt.jx + T(0.5) * Ft[0]) * rit), uy = AR((mt.jy + T(0.5) * Ft[1]) * rit),
+                 uz = AR((mt.jz + T(0.5) * Ft[2]) * rit);
+        const AR phi_c = AR(st.phi);
 
-        T m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
-        T t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
+        AR m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
+        AR t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            const T wl = T(weight(i)) * lf[i];
-            const T wg = T(weight(i)) * omg * lg[i];
+            const AR wl = AR(weight(i)) * lf[i];
+            const AR wg = AR(weight(i)) * omg * lg[i];
             m0 += wl;
             t0 += wg;
             if (CX[i]) { m1x += CX[i] * wl; t1x += CX[i] * wg; mxx += wl; txx += wg; }
@@ -251,54 +260,54 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
             if (CY[i] * CZ[i]) { myz += CY[i] * CZ[i] * wl; tyz += CY[i] * CZ[i] * wg; }
         }
         txx -= third * t0; tyy -= third * t0; tzz -= third * t0;
-        const T trt = txx + tyy + tzz;
-        const T t2ux = txx * ux + txy * uy + txz * uz;
-        const T t2uy = txy * ux + tyy * uy + tyz * uz;
-        const T t2uz = txz * ux + tyz * uy + tzz * uz;
-        const T t2uu = t2ux * ux + t2uy * uy + t2uz * uz;
-        const T t1u = t1x * ux + t1y * uy + t1z * uz;
-        const T m2ux = mxx * ux + mxy * uy + mxz * uz;
-        const T m2uy = mxy * ux + myy * uy + myz * uz;
-        const T m2uz = mxz * ux + myz * uy + mzz * uz;
-        const T m2Fx = mxx * Fx + mxy * Fy + mxz * Fz;
-        const T m2Fy = mxy * Fx + myy * Fy + myz * Fz;
-        const T m2Fz = mxz * Fx + myz * Fy + mzz * Fz;
-        const T uu = ux * ux + uy * uy + uz * uz;
-        const T orho = omf * rho;
-        const T lux = orho * (T(3) * m1x + T(9) * m2ux - T(3) * ux * m0)
-                    + pref * (T(9) * m2Fx - T(3) * Fx * m0) + phi_c * (T(3) * t1x + T(9) * t2ux);
-        const T luy = orho * (T(3) * m1y + T(9) * m2uy - T(3) * uy * m0)
-                    + pref * (T(9) * m2Fy - T(3) * Fy * m0) + phi_c * (T(3) * t1y + T(9) * t2uy);
-        const T luz = orho * (T(3) * m1z + T(9) * m2uz - T(3) * uz * m0)
-                    + pref * (T(9) * m2Fz - T(3) * Fz * m0) + phi_c * (T(3) * t1z + T(9) * t2uz);
-        const T arho = omf * (m0 + T(3) * (m1x * ux + m1y * uy + m1z * uz)
-                              + h * (m2ux * ux + m2uy * uy + m2uz * uz) - T(1.5) * uu * m0)
+        const AR trt = txx + tyy + tzz;
+        const AR t2ux = txx * ux + txy * uy + txz * uz;
+        const AR t2uy = txy * ux + tyy * uy + tyz * uz;
+        const AR t2uz = txz * ux + tyz * uy + tzz * uz;
+        const AR t2uu = t2ux * ux + t2uy * uy + t2uz * uz;
+        const AR t1u = t1x * ux + t1y * uy + t1z * uz;
+        const AR m2ux = mxx * ux + mxy * uy + mxz * uz;
+        const AR m2uy = mxy * ux + myy * uy + myz * uz;
+        const AR m2uz = mxz * ux + myz * uy + mzz * uz;
+        const AR m2Fx = mxx * Fx + mxy * Fy + mxz * Fz;
+        const AR m2Fy = mxy * Fx + myy * Fy + myz * Fz;
+        const AR m2Fz = mxz * Fx + myz * Fy + mzz * Fz;
+        const AR uu = ux * ux + uy * uy + uz * uz;
+        const AR orho = omf * rho;
+        const AR lux = orho * (AR(3) * m1x + AR(9) * m2ux - AR(3) * ux * m0)
+                    + pref * (AR(9) * m2Fx - AR(3) * Fx * m0) + phi_c * (AR(3) * t1x + AR(9) * t2ux);
+        const AR luy = orho * (AR(3) * m1y + AR(9) * m2uy - AR(3) * uy * m0)
+                    + pref * (AR(9) * m2Fy - AR(3) * Fy * m0) + phi_c * (AR(3) * t1y + AR(9) * t2uy);
+        const AR luz = orho * (AR(3) * m1z + AR(9) * m2uz - AR(3) * uz * m0)
+                    + pref * (AR(9) * m2Fz - AR(3) * Fz * m0) + phi_c * (AR(3) * t1z + AR(9) * t2uz);
+        const AR arho = omf * (m0 + AR(3) * (m1x * ux + m1y * uy + m1z * uz)
+                              + h * (m2ux * ux + m2uy * uy + m2uz * uz) - AR(1.5) * uu * m0)
                      - (lux * ux + luy * uy + luz * uz) * ri;
-        const T ajx = lux * ri, ajy = luy * ri, ajz = luz * ri;
-        const T hr = T(0.5) * ri;
-        const T lFx = pref * (T(3) * m1x - T(3) * ux * m0 + T(9) * m2ux) + hr * lux;
-        const T lFy = pref * (T(3) * m1y - T(3) * uy * m0 + T(9) * m2uy) + hr * luy;
-        const T lFz = pref * (T(3) * m1z - T(3) * uz * m0 + T(9) * m2uz) + hr * luz;
-        const T cf = T(1) - omf, cg = T(1) - omg;
+        const AR ajx = lux * ri, ajy = luy * ri, ajz = luz * ri;
+        const AR hr = AR(0.5) * ri;
+        const AR lFx = pref * (AR(3) * m1x - AR(3) * ux * m0 + AR(9) * m2ux) + hr * lux;
+        const AR lFy = pref * (AR(3) * m1y - AR(3) * uy * m0 + AR(9) * m2uy) + hr * luy;
+        const AR lFz = pref * (AR(3) * m1z - AR(3) * uz * m0 + AR(9) * m2uz) + hr * luz;
+        const AR cf = AR(1) - omf, cg = AR(1) - omg;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            T v = cf * lf[i] + arho;
+            AR v = cf * lf[i] + arho;
             if (CX[i]) v += CX[i] * ajx;
             if (CY[i]) v += CY[i] * ajy;
             if (CZ[i]) v += CZ[i] * ajz;
-            __builtin_nontemporal_store(v, &ap[i * S + s]);
-            __builtin_nontemporal_store(cg * lg[i], &ap[(NV + i) * S + s]);
+            __builtin_nontemporal_store(T(v), &ap[i * S + s]);
+            __builtin_nontemporal_store(T(cg * lg[i]), &ap[(NV + i) * S + s]);
         }
-        const T phi2 = phi_c * phi_c;
-        const T a_dir = t0 + T(3) * t1u + h * (gam * (A + T(3) * B * phi2) - third) * trt + h * t2uu;
-        sc[0 * S + s] = a_dir;
+        const AR phi2 = phi_c * phi_c;
+        const AR a_dir = t0 + AR(3) * t1u + h * (gam * (A + AR(3) * B * phi2) - third) * trt + h * t2uu;
+        sc[0 * S + s] = T(a_dir);
         sc[1 * S + s] = T(0);
         sc[2 * S + s] = T(0);
         sc[3 * S + s] = T(0);
-        sc[4 * S + s] = -h * kap * gam * trt;
-        sc[5 * S + s] = lFx;
-        sc[6 * S + s] = lFy;
-        sc[7 * S + s] = lFz;
+        sc[4 * S + s] = T(-h * kap * gam * trt);
+        sc[5 * S + s] = T(lFx);
+        sc[6 * S + s] = T(lFy);
+        sc[7 * S + s] = T(lFz);
         const double dtrt = double(trt), dph = st.phi;
         dth[0] += 4.5 * p.gamma * dph * dtrt;
         dth[1] += 4.5 * p.gamma * dph * dph * dph * dtrt;
@@ -312,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_local_force_f32(
     const float* __restrict__ an, float* __restrict__ ap, float* __restrict__ sc,
     double* __restrict__ partials)
 {
-    adj_local_force_body<float, true, false>(p, F, phi, an, ap, sc, partials);
+    adj_local_force_body<float, double, true, false>(p, F, phi, an, ap, sc, partials);
 }
 
 __global__ __launch_bounds__(kBlock) void k_adj_local_force_f64(
@@ -320,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_local_force_f64(
     const double* __restrict__ an, double* __restrict__ ap, double* __restrict__ sc,
     double* __restrict__ partials)
 {
-    adj_local_force_body<double, false, true>(p, F, phi, an, ap, sc, partials);
+    adj_local_force_body<double, double, false, true>(p, F, phi, an, ap, sc, partials);
 }
 
 // F = -div Pi of the phi field (T-rounded, as the forward uses it) into the
