@@ -45,14 +45,14 @@ def step_bytes_per_site(elem_bytes: int) -> dict:
 # HBM bytes per launch of the single-pass step kernel on the 256^3 droplet,
 # from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) over
 # `bench.py --steps 5 --warmup 1 --no-adjoint --no-cpu-baseline
-# --spinodal-steps 0 --force-steps 0 --fd-steps 0 --shard-steps 0
+# --spinodal-steps 0 --force-steps 5 --fd-steps 5 --shard-steps 0
 # --error-steps 0`, each scaled by the same counter's reading for the
 # library's copy kernel of known size (FETCH x 2.000, WRITE x 1.000).
 # They hold only for the kernel sources they were taken on (the hash below);
 # after any change to those sources the traffic is reported as null.
 TRAFFIC_SOURCES = ("lb_kernels.hip", "lb_device.h", "lb_internal.h")
-TRAFFIC_SHA256 = "573817fb65aa77072d2602f4430c5cbee41a2d7bea2fac9514be42acbb51e5d8"
-TRAFFIC_BYTES = {"fp32_dev": 5474000757, "fp64": 10365988142}
+TRAFFIC_SHA256 = "d040c9151368380ca54f53aadf67279d9d131c4570cbb1f06a921ec61260f3cc"
+TRAFFIC_BYTES = {"fp32_dev": 5480100502, "fp64": 10362665441}
 
 
 def sources_sha256() -> str:
@@ -208,18 +208,29 @@ def footprint_sweep(args):
         phi0 = lbinputs.droplet_phi0(shape, n / 4.0, xi, noise=1e-3, seed=lbinputs.SEED_DROPLET)
         for prec in ("fp32_dev", "fp64"):
             row = {"n": n, "precision": prec}
-            for kern in ("fused", "stream"):
-                lb = LB(shape, precision=prec, kernel=kern, device="cuda:0", **params)
-                lb.init_phi(phi0)
-                e = int(lb.sizes.elem_bytes)
-                kb = step_bytes_per_site(e)["kernel"]
-                row["footprint_GB"] = round(kb * nsites / 1e9, 3)
-                log(f"{prec} {kern} {shape}: {steps} steps")
-                ms = time_steps(lb, steps, args.warmup) / steps
+            # the step and its twin on the same buffers, timed alternately
+            # (3 rounds, medians; even step counts keep both on one level)
+            lb = LB(shape, precision=prec, device="cuda:0", **params)
+            lb.init_phi(phi0)
+            twin = lb.sibling("stream")
+            e = int(lb.sizes.elem_bytes)
+            kb = step_bytes_per_site(e)["kernel"]
+            row["footprint_GB"] = round(kb * nsites / 1e9, 3)
+            k = steps + steps % 2
+            log(f"{prec} {shape}: step and twin, 3 x {k} steps each")
+            time_steps(lb, 0, 2 * (args.warmup // 2 + 1))
+            time_steps(twin, 0, 2 * (args.warmup // 2 + 1))
+            tm = {"fused": [], "stream": []}
+            for _ in range(3):
+                tm["fused"].append(time_steps(lb, k, 0) / k)
+                tm["stream"].append(time_steps(twin, k, 0) / k)
+            for kern, v in tm.items():
+                ms = sorted(v)[1]
                 row[kern + "_ms"] = round(ms, 4)
                 row[kern + "_GBps"] = round(kb * nsites / (ms * 1e-3) / 1e9, 1)
-                del lb
-                torch.cuda.empty_cache()
+            twin.close()
+            del lb, twin
+            torch.cuda.empty_cache()
             row["step_over_twin"] = round(row["fused_ms"] / row["stream_ms"], 4)
             out["lattice"].append(row)
     return out
@@ -368,18 +379,33 @@ def main():
     # lattice: the memory-bound floor of this kernel's access pattern
     out["stream_twin"] = {}
     for prec in precs:
-        lb = LB(shape, precision=prec, kernel="stream", device="cuda:0", **lay, **params)
+        # the twin as a second context on the step's own buffers, the two
+        # timed alternately (5 rounds; even step counts keep both contexts on
+        # the same time level): same memory, same moment, so the ratio does
+        # not carry placement or drift between separate allocations
+        lb = LB(shape, precision=prec, device="cuda:0", **lay, **params)
         lb.init_phi(phi0)
-        log(f"{prec}: memory-only twin, {args.steps} steps")
-        ms_twin = time_steps(lb, args.steps, args.warmup)
+        twin = lb.sibling("stream")
+        k = max(args.steps, 20)
+        k += k % 2
+        log(f"{prec}: step and memory-only twin on the same buffers, 5 x {k} steps each")
+        time_steps(lb, 0, 2 * (args.warmup // 2 + 1))
+        time_steps(twin, 0, 2 * (args.warmup // 2 + 1))
+        ts, tt = [], []
+        for _ in range(5):
+            ts.append(time_steps(lb, k, 0) / k)
+            tt.append(time_steps(twin, k, 0) / k)
+        ts.sort()
+        tt.sort()
         e = int(lb.sizes.elem_bytes)
-        t = ms_twin / args.steps * 1e-3
         kb = step_bytes_per_site(e)["kernel"]
         key = "fp32_dev" if e == 4 else "fp64"
         out["stream_twin"][key] = {
-            "ms_per_step": round(t * 1e3, 4), "GBps_kernel_bytes": round(kb * nsites / t / 1e9, 1),
-            "step_over_twin": round(runs[key]["ms_plain"] / ms_twin, 4)}
-        del lb
+            "step_ms_median": round(ts[2], 4), "twin_ms_median": round(tt[2], 4),
+            "twin_GBps_kernel_bytes": round(kb * nsites / (tt[2] * 1e-3) / 1e9, 1),
+            "step_over_twin": round(ts[2] / tt[2], 4), "rounds": 5, "steps_per_round": k}
+        twin.close()
+        del lb, twin
         torch.cuda.empty_cache()
 
     # FP32 deviation storage against FP64 on the same droplet over a fixed

@@ -105,6 +105,38 @@ class LB:
                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx)),
                   "lb_create")
 
+    def sibling(self, kernel: str) -> "LB":
+        """A second context on this lattice's own device buffers and stream
+        that steps with another kernel variant ("fused", "two_pass" or
+        "stream"), e.g. to time a kernel and its memory-only twin on the same
+        memory.  It starts at time level 0 of the shared buffers; the caller
+        keeps the two contexts from stepping over each other's levels."""
+        L = _abi.lib()
+        sib = object.__new__(LB)
+        sib.__dict__.update({k: v for k, v in self.__dict__.items() if k != "_ctx"})
+        sib.params = _abi.LbParams.from_buffer_copy(self.params)
+        sib.params.kernel = KERNELS[kernel]
+        sib.sizes = _abi.LbSizes()
+        check(L.lb_query_sizes(ctypes.byref(sib.params), ctypes.byref(sib.sizes)), "lb_query_sizes")
+        for f in ("state_bytes", "phi_bytes", "scratch_bytes"):
+            if getattr(sib.sizes, f) > getattr(self.sizes, f):
+                raise ValueError(f"kernel {kernel!r} needs more {f} than this lattice holds")
+        bufs = _abi.LbBuffers()
+        bufs.state[0] = self.state_buf[0].data_ptr()
+        bufs.state[1] = self.state_buf[1].data_ptr()
+        bufs.phi = self.phi_buf.data_ptr()
+        bufs.scratch = self.scratch.data_ptr()
+        if self.adj_buf[0] is not None:
+            bufs.adj[0] = self.adj_buf[0].data_ptr()
+            bufs.adj[1] = self.adj_buf[1].data_ptr()
+            bufs.adj_scratch = self.adj_scratch.data_ptr()
+        sib._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(L.lb_create(ctypes.byref(sib.params), ctypes.byref(bufs),
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(sib._ctx)),
+                  "lb_create")
+        return sib
+
     # -- lifetime -----------------------------------------------------------
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

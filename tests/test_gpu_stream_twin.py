@@ -64,3 +64,27 @@ def test_stream_twin_conserves_and_rejects_the_adjoint():
         lb.adjoint_seed(np.zeros(shape))
     assert e.value.status == LB_ESTATE
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
+def test_sibling_context_steps_on_the_shared_buffers(precision):
+    """LB.sibling (how the bench times the step and its twin on the same
+    memory): a second context on the lattice's own buffers starts from the
+    level the first one wrote and steps with its own kernel variant -- here
+    the two-pass variant, bit-identical to a separate single-pass lattice."""
+    shape = (9, 10, 70)
+    phi0 = lbinputs.spinodal_phi0(shape)
+    lb = make_lb(shape, precision=precision)
+    lb.init_phi(phi0)
+    sib = lb.sibling("two_pass")
+    sib.step(3)
+    ref = make_lb(shape, precision=precision)
+    ref.init_phi(phi0)
+    ref.step(3)
+    for a, b in zip(sib.moments(), ref.moments()):
+        assert torch.equal(a, b)
+    twin = lb.sibling("stream")
+    assert twin.params.kernel == 2 and lb.params.kernel == 0
+    sib.close()
+    twin.close()
+    torch.cuda.synchronize()

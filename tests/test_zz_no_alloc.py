@@ -16,13 +16,16 @@ pytestmark = pytest.mark.gpu
 
 # (name, LB keywords): every path lb_step_sums takes -- the single-pass step
 # in both storage precisions, the two-pass variant, the force coupling and
-# the finite-difference order parameter
+# the finite-difference order parameter (single pass with either coupling,
+# and its two-pass variant, which reduces over one block per 256 sites)
 CASES = [
     ("fused_fp64", dict(precision="fp64")),
     ("fused_fp32", dict(precision="fp32_dev")),
     ("two_pass_fp64", dict(precision="fp64", kernel="two_pass")),
     ("force_fp32", dict(precision="fp32_dev", coupling="force")),
     ("fd_fp64", dict(precision="fp64", order_param="fd")),
+    ("fd_force_fp32", dict(precision="fp32_dev", order_param="fd", coupling="force")),
+    ("fd_two_pass_fp64", dict(precision="fp64", order_param="fd", kernel="two_pass")),
 ]
 
 
