@@ -48,6 +48,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(KParams p, T* __restrict__ 
     adj[2 * NV * p.stride + s] = T(dphi[s]);
 }
 
+// A copy of v that the compiler cannot see through.  The FP32-storage
+// kernels widen each lambda_f twice (for its moments and for its output)
+// rather than keep the widened value live in two registers through the whole
+// site; without the copy the two widenings merge into one.
+template <typename T, typename AR>
+__device__ __forceinline__ T opaque_copy(T v)
+{
+    if constexpr (!std::is_same<T, AR>::value) asm("" : "+v"(v));
+    return v;
+}
+
 // Transposed propagation (gather lambda*_i(x) = lambda_i(x + c_i)), then the
 // transposed local collision Jacobian at x with the forward locals recomputed
 // from the saved state; writes lf, lg of the previous level, the stencil
@@ -63,15 +74,15 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
     for (XcdSweep w = xcd_sweep(p.nsites, kBlock); w.s < w.end; w.s += w.stride) {
         const int s = w.s;
         const Geo q = geo_of(p, s);
-        AR lf[NV], lg[NV];
-        T f[NV];
+        T lfr[NV], lgr[NV], lpr[NV], f[NV];
 #pragma unroll
         for (int i = 0; i < NV; i++) {
             const int d = push_site(p, q, i);
             // lambda_f and lambda_g of the later level are read once (non-
             // temporal); lambda_phi at d is gathered by 19 sites (cached)
-            lf[i] = AR(__builtin_nontemporal_load(&an[i * S + d]));
-            lg[i] = AR(__builtin_nontemporal_load(&an[(NV + i) * S + d])) + AR(an[2 * NV * S + d]);
+            lfr[i] = __builtin_nontemporal_load(&an[i * S + d]);
+            lgr[i] = __builtin_nontemporal_load(&an[(NV + i) * S + d]);
+            lpr[i] = an[2 * NV * S + d];
             f[i] = F[dist_pull(p, q, i)];
         }
         const Stencil st = stencil(phi[s], phi[site_of(p, q.xp, q.y, q.z)],
@@ -82,6 +93,23 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
                                    phi[site_of(p, q.x, q.y, q.zm)]);
         const AR A = AR(p.A), B = AR(p.B), kap = AR(p.kappa), gam = AR(p.gamma);
         const AR omf = AR(p.omega_f), omg = AR(p.omega_g);
+        const AR cf = AR(1) - omf, cg = AR(1) - omg;
+        // g part first: its moments, and the previous level's lg, which no
+        // later term needs
+        AR t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            const AR lg = AR(lgr[i]) + AR(lpr[i]);
+            const AR wg = AR(weight(i)) * omg * lg;
+            t0 += wg;
+            if (CX[i]) { t1x += CX[i] * wg; txx += wg; }
+            if (CY[i]) { t1y += CY[i] * wg; tyy += wg; }
+            if (CZ[i]) { t1z += CZ[i] * wg; tzz += wg; }
+            if (CX[i] * CY[i]) txy += CX[i] * CY[i] * wg;
+            if (CX[i] * CZ[i]) txz += CX[i] * CZ[i] * wg;
+            if (CY[i] * CZ[i]) tyz += CY[i] * CZ[i] * wg;
+            __builtin_nontemporal_store(T(cg * lg), &ap[(NV + i) * S + s]);
+        }
         // the forward step's own rho and u (in the storage type's arithmetic)
         const Moments<T> mt = moments_of<T, DEV>(p, f);
         const T rit = T(1) / mt.rho;
@@ -90,19 +118,18 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
         const AR phi_c = AR(st.phi), gx = AR(st.gx), gy = AR(st.gy), gz = AR(st.gz), lap = AR(st.lap);
 
         AR s0 = 0, s1x = 0, s1y = 0, s1z = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
-        AR t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
+        T lfc[NV];
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            const AR wl = AR(weight(i)) * omf * lf[i];
-            const AR wg = AR(weight(i)) * omg * lg[i];
+            const AR wl = AR(weight(i)) * omf * AR(lfr[i]);
             s0 += wl;
-            t0 += wg;
-            if (CX[i]) { s1x += CX[i] * wl; t1x += CX[i] * wg; sxx += wl; txx += wg; }
-            if (CY[i]) { s1y += CY[i] * wl; t1y += CY[i] * wg; syy += wl; tyy += wg; }
-            if (CZ[i]) { s1z += CZ[i] * wl; t1z += CZ[i] * wg; szz += wl; tzz += wg; }
-            if (CX[i] * CY[i]) { sxy += CX[i] * CY[i] * wl; txy += CX[i] * CY[i] * wg; }
-            if (CX[i] * CZ[i]) { sxz += CX[i] * CZ[i] * wl; txz += CX[i] * CZ[i] * wg; }
-            if (CY[i] * CZ[i]) { syz += CY[i] * CZ[i] * wl; tyz += CY[i] * CZ[i] * wg; }
+            if (CX[i]) { s1x += CX[i] * wl; sxx += wl; }
+            if (CY[i]) { s1y += CY[i] * wl; syy += wl; }
+            if (CZ[i]) { s1z += CZ[i] * wl; szz += wl; }
+            if (CX[i] * CY[i]) sxy += CX[i] * CY[i] * wl;
+            if (CX[i] * CZ[i]) sxz += CX[i] * CZ[i] * wl;
+            if (CY[i] * CZ[i]) syz += CY[i] * CZ[i] * wl;
+            lfc[i] = opaque_copy<T, AR>(lfr[i]);
         }
         const AR third = AR(1.0 / 3.0);
         sxx -= third * s0; syy -= third * s0; szz -= third * s0;
@@ -128,15 +155,13 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
         const AR ajx = AR(3) * s1x + AR(9) * s2ux + AR(3) * pr * t1x + AR(9) * pr * t2ux;
         const AR ajy = AR(3) * s1y + AR(9) * s2uy + AR(3) * pr * t1y + AR(9) * pr * t2uy;
         const AR ajz = AR(3) * s1z + AR(9) * s2uz + AR(3) * pr * t1z + AR(9) * pr * t2uz;
-        const AR cf = AR(1) - omf, cg = AR(1) - omg;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            AR v = cf * lf[i] + arho;
+            AR v = cf * AR(lfc[i]) + arho;
             if (CX[i]) v += CX[i] * ajx;
             if (CY[i]) v += CY[i] * ajy;
             if (CZ[i]) v += CZ[i] * ajz;
             __builtin_nontemporal_store(T(v), &ap[i * S + s]);
-            __builtin_nontemporal_store(T(cg * lg[i]), &ap[(NV + i) * S + s]);
         }
         const AR phi2 = phi_c * phi_c;
         const AR a_dir = h * trs * (A * phi_c + AR(3) * B * phi2 * phi_c - kap * lap) + t0
@@ -161,8 +186,14 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
 // roundings, repeated over a long rollout, dominated the gradient's error
 // (1e-4 relative over 1000 steps at 128^3; 5e-6 in FP64, at no cost in
 // time).  The forward's own rho and u are formed in FP32, as the step forms
-// them, and then widened.
-__global__ __launch_bounds__(kBlock) void k_adj_local_f32(
+// them, and then widened.  Register budgets: the g part goes first (its
+// moments and its output need nothing of the f part) and lambda_f stays in
+// FP32 until used, which fits 3 waves per SIMD (161 VGPRs, no spills; the
+// plain order took 292 registers, one wave per SIMD, and capping that at 2
+// waves made the compiler serialise the loads: 2.2x slower).  The FP32
+// kernel runs 3-5% faster this way; the FP64 ones gain nothing but are kept
+// at the budget that needs no AGPRs.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_adj_local_f32(
     KParams p, const float* __restrict__ F, const double* __restrict__ phi,
     const float* __restrict__ an, float* __restrict__ ap, float* __restrict__ sc,
     double* __restrict__ partials)
@@ -170,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_local_f32(
     adj_local_body<float, double, true>(p, F, phi, an, ap, sc, partials);
 }
 
-__global__ __launch_bounds__(kBlock) void k_adj_local_f64(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_adj_local_f64(
     KParams p, const double* __restrict__ F, const double* __restrict__ phi,
     const double* __restrict__ an, double* __restrict__ ap, double* __restrict__ sc,
     double* __restrict__ partials)
@@ -208,13 +239,13 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
     for (XcdSweep w = xcd_sweep(p.nsites, kBlock); w.s < w.end; w.s += w.stride) {
         const int s = w.s;
         const Geo q = geo_of(p, s);
-        AR lf[NV], lg[NV];
-        T f[NV];
+        T lfr[NV], lgr[NV], lpr[NV], f[NV];
 #pragma unroll
         for (int i = 0; i < NV; i++) {
             const int d = push_site(p, q, i);
-            lf[i] = AR(__builtin_nontemporal_load(&an[i * S + d]));
-            lg[i] = AR(__builtin_nontemporal_load(&an[(NV + i) * S + d])) + AR(an[2 * NV * S + d]);
+            lfr[i] = __builtin_nontemporal_load(&an[i * S + d]);
+            lgr[i] = __builtin_nontemporal_load(&an[(NV + i) * S + d]);
+            lpr[i] = an[2 * NV * S + d];
             f[i] = F[dist_pull(p, q, i)];
         }
         const Stencil st = stencil(phi[s], phi[site_of(p, q.xp, q.y, q.z)],
@@ -244,20 +275,34 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
                  uz = AR((mt.jz + T(0.5) * Ft[2]) * rit);
         const AR phi_c = AR(st.phi);
 
-        AR m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
+        const AR cf = AR(1) - omf, cg = AR(1) - omg;
         AR t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            const AR wl = AR(weight(i)) * lf[i];
-            const AR wg = AR(weight(i)) * omg * lg[i];
-            m0 += wl;
+            const AR lg = AR(lgr[i]) + AR(lpr[i]);
+            const AR wg = AR(weight(i)) * omg * lg;
             t0 += wg;
-            if (CX[i]) { m1x += CX[i] * wl; t1x += CX[i] * wg; mxx += wl; txx += wg; }
-            if (CY[i]) { m1y += CY[i] * wl; t1y += CY[i] * wg; myy += wl; tyy += wg; }
-            if (CZ[i]) { m1z += CZ[i] * wl; t1z += CZ[i] * wg; mzz += wl; tzz += wg; }
-            if (CX[i] * CY[i]) { mxy += CX[i] * CY[i] * wl; txy += CX[i] * CY[i] * wg; }
-            if (CX[i] * CZ[i]) { mxz += CX[i] * CZ[i] * wl; txz += CX[i] * CZ[i] * wg; }
-            if (CY[i] * CZ[i]) { myz += CY[i] * CZ[i] * wl; tyz += CY[i] * CZ[i] * wg; }
+            if (CX[i]) { t1x += CX[i] * wg; txx += wg; }
+            if (CY[i]) { t1y += CY[i] * wg; tyy += wg; }
+            if (CZ[i]) { t1z += CZ[i] * wg; tzz += wg; }
+            if (CX[i] * CY[i]) txy += CX[i] * CY[i] * wg;
+            if (CX[i] * CZ[i]) txz += CX[i] * CZ[i] * wg;
+            if (CY[i] * CZ[i]) tyz += CY[i] * CZ[i] * wg;
+            __builtin_nontemporal_store(T(cg * lg), &ap[(NV + i) * S + s]);
+        }
+        AR m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
+        T lfc[NV];
+#pragma unroll
+        for (int i = 0; i < NV; i++) {
+            const AR wl = AR(weight(i)) * AR(lfr[i]);
+            m0 += wl;
+            if (CX[i]) { m1x += CX[i] * wl; mxx += wl; }
+            if (CY[i]) { m1y += CY[i] * wl; myy += wl; }
+            if (CZ[i]) { m1z += CZ[i] * wl; mzz += wl; }
+            if (CX[i] * CY[i]) mxy += CX[i] * CY[i] * wl;
+            if (CX[i] * CZ[i]) mxz += CX[i] * CZ[i] * wl;
+            if (CY[i] * CZ[i]) myz += CY[i] * CZ[i] * wl;
+            lfc[i] = opaque_copy<T, AR>(lfr[i]);
         }
         txx -= third * t0; tyy -= third * t0; tzz -= third * t0;
         const AR trt = txx + tyy + tzz;
@@ -288,15 +333,13 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
         const AR lFx = pref * (AR(3) * m1x - AR(3) * ux * m0 + AR(9) * m2ux) + hr * lux;
         const AR lFy = pref * (AR(3) * m1y - AR(3) * uy * m0 + AR(9) * m2uy) + hr * luy;
         const AR lFz = pref * (AR(3) * m1z - AR(3) * uz * m0 + AR(9) * m2uz) + hr * luz;
-        const AR cf = AR(1) - omf, cg = AR(1) - omg;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            AR v = cf * lf[i] + arho;
+            AR v = cf * AR(lfc[i]) + arho;
             if (CX[i]) v += CX[i] * ajx;
             if (CY[i]) v += CY[i] * ajy;
             if (CZ[i]) v += CZ[i] * ajz;
             __builtin_nontemporal_store(T(v), &ap[i * S + s]);
-            __builtin_nontemporal_store(T(cg * lg[i]), &ap[(NV + i) * S + s]);
         }
         const AR phi2 = phi_c * phi_c;
         const AR a_dir = t0 + AR(3) * t1u + h * (gam * (A + AR(3) * B * phi2) - third) * trt + h * t2uu;
@@ -316,7 +359,7 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
     block_partials<3>(dth, partials);
 }
 
-__global__ __launch_bounds__(kBlock) void k_adj_local_force_f32(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_adj_local_force_f32(
     KParams p, const float* __restrict__ F, const double* __restrict__ phi,
     const float* __restrict__ an, float* __restrict__ ap, float* __restrict__ sc,
     double* __restrict__ partials)
@@ -522,9 +565,10 @@ hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
         hipError_t e = launch_phi(p, fp32, state, phi, s);
         if (e != hipSuccess) return e;
     }
-    // one resident round: 256 CUs x 4 workgroups of 256 threads (4 waves per
-    // SIMD), each thread looping over its sites; the parameter reduction
-    // (in the stencil kernel's first workgroups) then reads half the partials of
+    // 1024 workgroups of 256 threads, each thread looping over its sites (a
+    // few resident rounds at the local kernels' 1-3 waves per SIMD; a grid
+    // of exactly one round measured no faster); the parameter reduction (in
+    // the stencil kernel's first workgroups) then reads half the partials of
     // 2048 workgroups (measured as a launch of its own at 128^3: 9.9 -> 5.5
     // us, k_adj_local unchanged)
     constexpr int kAdjBlocks = 1024;

@@ -28,12 +28,15 @@
 //
 // Time level: F (19*stride elements of T in the layout of didx(); FP32 mode
 // stores f - w rho0) followed by phi (stride FP64 values in site order).
-// No floating-point contraction in this translation unit (including the
-// shared device functions it inlines): the compiler fuses a multiply and an
-// add differently in different kernels, and the single-pass and two-kernel
-// paths must round every expression alike.  The kernels are memory-bound, so
-// the extra instructions cost nothing measurable.
-#pragma clang fp contract(off)
+// Floating-point contraction within one source expression only (including
+// the shared device functions this translation unit inlines): a multiply and
+// an add written in one expression become one fused multiply-add in every
+// kernel alike, so the single-pass and two-kernel paths round every
+// expression the same way.  The compiler's default also fuses across
+// statements, and did so differently in different kernels; with no
+// contraction at all the force-coupled single pass ran 5% (FP32 storage) and
+// 2.5% (FP64) slower.
+#pragma clang fp contract(on)
 
 #include <type_traits>
 
