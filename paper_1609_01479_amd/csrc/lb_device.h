@@ -388,6 +388,10 @@ __device__ __forceinline__ void chem_stress(const KParams& p, const Stencil& st,
 //   g^eq_i - r_i phi = w [3 phi c.u + 9/2 (Gamma mu (|c|^2 - 1) + phi ((c.u)^2 - |u|^2/3))],
 //   f*_i = f_i + omega_f (f^eq_i - f_i) + (1 - omega_f/2) w [3 (c - u).F + 9 (c.u)(c.F)].
 // The f half of collide_force (returns u = (j + F/2)/rho) and the g half.
+// collide_force_f forms omega f^eq_i + S_i from its Hermite moments, as
+// collide_f forms f^eq_i: one value per direction pair from the even part and
+// one from the odd, then f*_i = (1 - omega_f) f_i + that (about half the
+// arithmetic of evaluating the two sums direction by direction).
 template <typename T, bool DEV>
 __device__ __forceinline__ Vel<T> collide_force_f(const KParams& p, T* f, const double Fd[3])
 {
@@ -396,21 +400,52 @@ __device__ __forceinline__ Vel<T> collide_force_f(const KParams& p, T* f, const 
     const T ri = T(1) / m.rho;
     const T ux = (m.jx + T(0.5) * F[0]) * ri, uy = (m.jy + T(0.5) * F[1]) * ri,
             uz = (m.jz + T(0.5) * F[2]) * ri;
-    const T uu3 = (ux * ux + uy * uy + uz * uz) * T(1.0 / 3.0);
     const T omf = T(p.omega_f);
     const T pref = T(1) - T(0.5) * omf;
-    const T uF = ux * F[0] + uy * F[1] + uz * F[2];
-#pragma unroll
-    for (int i = 0; i < NV; i++) {
-        const T w = T(weight(i));
-        const T cu = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
-        const T cF = T(CX[i]) * F[0] + T(CY[i]) * F[1] + T(CZ[i]) * F[2];
-        const T q = cu * cu - uu3;
-        // f^eq in the stored convention: w [b + rho (3 c.u + 9/2 q)], b = sum of the stored f
-        const T feq = w * (m.b + m.rho * (T(3) * cu + T(4.5) * q));
-        const T src = pref * w * (T(3) * (cF - uF) + T(9) * cu * cF);
-        f[i] += omf * (feq - f[i]) + src;
+    // omega f^eq_i + S_i = w_i [omega b + 3 c.a + 9/2 (c c - I/3):M] with
+    //   a = omega rho u + pref F,  M = omega rho u u + pref (u F + F u)
+    const T orho = omf * m.rho;
+    const T ob = omf * m.b;
+    const T ax = orho * ux + pref * F[0], ay = orho * uy + pref * F[1], az = orho * uz + pref * F[2];
+    const T pux = pref * ux, puy = pref * uy, puz = pref * uz;
+    const T mxx = orho * ux * ux + T(2) * pux * F[0];
+    const T myy = orho * uy * uy + T(2) * puy * F[1];
+    const T mzz = orho * uz * uz + T(2) * puz * F[2];
+    const T mxy = orho * ux * uy + (pux * F[1] + puy * F[0]);
+    const T mxz = orho * ux * uz + (pux * F[2] + puz * F[0]);
+    const T myz = orho * uy * uz + (puy * F[2] + puz * F[1]);
+    const T tm = (mxx + myy + mzz) * T(1.0 / 3.0);
+    const T h = T(4.5);
+    const T w0 = T(weight(0)), wf = T(weight(1)), we = T(weight(7));
+    const T wf3 = T(3.0 * weight(1)), we3 = T(3.0 * weight(7));
+    T x[NV];
+    x[0] = w0 * (ob - h * tm);
+    {
+        const T sx = wf * (ob + h * (mxx - tm)), vx = wf3 * ax;
+        const T sy = wf * (ob + h * (myy - tm)), vy = wf3 * ay;
+        const T sz = wf * (ob + h * (mzz - tm)), vz = wf3 * az;
+        x[1] = sx + vx; x[2] = sx - vx;
+        x[3] = sy + vy; x[4] = sy - vy;
+        x[5] = sz + vz; x[6] = sz - vz;
     }
+    {
+        const T dxy = mxx + myy - tm, dxz = mxx + mzz - tm, dyz = myy + mzz - tm;
+        const T s7 = we * (ob + h * (dxy + T(2) * mxy)), v7 = we3 * (ax + ay);
+        const T s9 = we * (ob + h * (dxy - T(2) * mxy)), v9 = we3 * (ax - ay);
+        const T s11 = we * (ob + h * (dxz + T(2) * mxz)), v11 = we3 * (ax + az);
+        const T s13 = we * (ob + h * (dxz - T(2) * mxz)), v13 = we3 * (ax - az);
+        const T s15 = we * (ob + h * (dyz + T(2) * myz)), v15 = we3 * (ay + az);
+        const T s17 = we * (ob + h * (dyz - T(2) * myz)), v17 = we3 * (ay - az);
+        x[7] = s7 + v7;     x[8] = s7 - v7;
+        x[9] = s9 + v9;     x[10] = s9 - v9;
+        x[11] = s11 + v11;  x[12] = s11 - v11;
+        x[13] = s13 + v13;  x[14] = s13 - v13;
+        x[15] = s15 + v15;  x[16] = s15 - v15;
+        x[17] = s17 + v17;  x[18] = s17 - v17;
+    }
+    const T cf = T(1) - omf;
+#pragma unroll
+    for (int i = 0; i < NV; i++) f[i] = cf * f[i] + x[i];
     return Vel<T>{ux, uy, uz};
 }
 

@@ -77,9 +77,13 @@ __global__ __launch_bounds__(kBlock) void k_fd_init(KParams p, T* __restrict__ F
 }
 
 // mu = A phi + B phi^3 - kappa lap phi (FP64), one expression for every kernel.
+// The expression of chem_stress's mu, so that the force-coupled single pass
+// can take mu from its Pi evaluation and stay bit-identical to the two-kernel
+// path.
 __device__ __forceinline__ double fd_mu(const KParams& p, double c, double lap)
 {
-    return p.A * c + p.B * c * c * c - p.kappa * lap;
+    const double c2 = c * c;
+    return p.A * c + p.B * c2 * c - p.kappa * lap;
 }
 
 // Element type of the collision pass's work fields (mu, u_x, u_y, u_z): FP64,
@@ -550,6 +554,7 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_fused(KParams p, TileCfg 
         const Stencil st = stencil(fc[c], fp[c], fm[c], fc[c + BZ], fc[c - BZ], fc[c + 1], fc[c - 1]);
         double mu;
         chem_stress(p, st, &mu, tt);
+        return mu;
     };
     auto store_pi = [&](int w, int c, const double (&tt)[6]) {
         s_pi[w][0][c] = tt[1];
@@ -572,10 +577,11 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_fused(KParams p, TileCfg 
     double rpA = 0.0, rpB = 0.0;
     double phA = 0.0, muA = 0.0, uxA = 0.0;
     double phB = 0.0, muB = 0.0, uxB = 0.0, uyB = 0.0, uzB = 0.0;
-    // phi of plane P-2 at the own cell and at the ring cell (the collision's
-    // x - 1 neighbour), so that no one reads that LDS slot after the
-    // iteration's second barrier: the next iteration refills it
-    double phm = 0.0, rphm = 0.0;
+    // mu of plane P-1 at the own cell and at the ring cell, from the Pi
+    // evaluation of the previous iteration (the stencil is the same)
+    double mum = 0.0, rmum = 0.0;
+    // flux through the x face below plane U, from the previous iteration
+    double fxm = 0.0;
     for (int P = x0 - 2; P <= x1 + 1; P++) {
         const int V = P - 1;  // plane collided
         const bool coll = V >= x0 - 1 && V <= x1;
@@ -595,10 +601,10 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_fused(KParams p, TileCfg 
         const double* __restrict__ fc = s_phi[P & 3];
         const double* __restrict__ fp = s_phi[(P + 1) & 3];
         const int wp = P & 1;
-        double pxP[3], rpP = 0.0;
+        double pxP[3], rpP = 0.0, muP, rmuP = 0.0;
         {
             double tt[6];
-            pi_at(fm, fc, fp, bo, tt);
+            muP = pi_at(fm, fc, fp, bo, tt);
             pxP[0] = tt[0];
             pxP[1] = tt[1];
             pxP[2] = tt[2];
@@ -606,7 +612,7 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_fused(KParams p, TileCfg 
         }
         if (ring) {
             double tt[6];
-            pi_at(fm, fc, fp, rbo, tt);
+            rmuP = pi_at(fm, fc, fp, rbo, tt);
             rpP = ring_y ? tt[1] : tt[2];  // Pi_xy (row) or Pi_xz (column)
             store_pi(wp, rpo, tt);
         }
@@ -638,8 +644,6 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_fused(KParams p, TileCfg 
 #pragma unroll
             for (int a = 0; a < 3; a++) F[a] = -div[a];
             const double c = fm[bo];
-            const Stencil st = stencil(c, fc[bo], phm, fm[bo + BZ], fm[bo - BZ], fm[bo + 1],
-                                       fm[bo - 1]);
             if (partials && inner && valid) {
                 double bs = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
@@ -660,7 +664,7 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_fused(KParams p, TileCfg 
             if (inner && valid)
 #pragma unroll
                 for (int i = 0; i < NV; i++) __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
-            const W muw = W(fd_mu(p, c, st.lap)), uyw = W(u.y), uzw = W(u.z);
+            const W muw = W(mum), uyw = W(u.y), uzw = W(u.z);
             phC = c;
             muC = double(muw);
             uxC = double(W(u.x));
@@ -688,19 +692,15 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_fused(KParams p, TileCfg 
             const Moments<T> m = moments_of<T, DEV>(p, fr);
             const T ri = T(1) / m.rho;
             const T un = ((ring_y ? m.jy : m.jz) + T(0.5) * T(Fn)) * ri;
-            const double c = fm[rbo];
-            const Stencil sr = stencil(c, fc[rbo], rphm, fm[rbo + BZ], fm[rbo - BZ], fm[rbo + 1],
-                                       fm[rbo - 1]);
-            s_ph[wv][rro] = c;
-            s_mu[wv][rro] = W(fd_mu(p, c, sr.lap));
+            s_ph[wv][rro] = fm[rbo];
+            s_mu[wv][rro] = W(rmum);
             if (ring_y)
                 s_uy[wv][rro] = W(un);
             else
                 s_uz[wv][rro] = W(un);
         }
-        // phi(V) of the own and ring cells: phi(V-1) of the next iteration
-        phm = fm[bo];
-        if (ring) rphm = fm[rbo];
+        mum = muP;
+        rmum = rmuP;
         lds_barrier();  // not needed for the data (see above): keeps the waves in step
 
         // (e) phi(t+1) at plane U = P-2 (the fields of plane U were written
@@ -709,8 +709,12 @@ __global__ __launch_bounds__(kFdFused) void k_fd_force_fused(KParams p, TileCfg 
         if (U >= x0 && U < x1 && valid) {
             const int v = U & 1;
             const double pc = phB, mc = muB, uc = uxB;
+            // the x face below U is the face above U - 1 of the same column
+            const double fxp = fd_flux(pc, phC, uc, uxC, mc, muC, M);
+            if (U == x0) fxm = fd_flux(phA, pc, uxA, uc, muA, mc, M);
             double dv = 0.0;
-            dv += fd_flux(pc, phC, uc, uxC, mc, muC, M) - fd_flux(phA, pc, uxA, uc, muA, mc, M);
+            dv += fxp - fxm;
+            fxm = fxp;
             dv += fd_flux(pc, s_ph[v][ro + RZ], uyB, double(s_uy[v][ro + RZ]), mc,
                           double(s_mu[v][ro + RZ]), M)
                 - fd_flux(s_ph[v][ro - RZ], pc, double(s_uy[v][ro - RZ]), uyB,
