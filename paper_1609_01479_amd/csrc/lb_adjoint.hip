@@ -28,6 +28,12 @@
 //   lf[19] = dL/df_i(x), lg[19] = the part of dL/dg_i(x) specific to i,
 //   lp = dL/dphi(x), so that dL/dg_i(x) = lg_i(x) + lp(x).
 // adj_scratch holds a (direct dPhi/dphi), b_x, b_y, b_z, c per site.
+//
+// With omega_g = 1 (tau_g = 1) the post-collision g is g^eq alone, so the
+// previous level's lg = (1 - omega_g) lambda*_g is identically zero: the seed
+// zeroes lg in both levels and the local kernels (G1) neither read nor write
+// it, which takes 152 of the 412 bytes per site off the FP32 step (304 of
+// 816 in FP64).
 #include "lb_device.h"
 #include "lb_sweep.h"
 
@@ -37,8 +43,10 @@ using namespace dev;
 
 namespace {
 
+// other (may be null): the other level, whose lg is zeroed too
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_seed(KParams p, T* __restrict__ adj,
+                                                     T* __restrict__ other,
                                                      const double* __restrict__ dphi)
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
@@ -46,6 +54,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(KParams p, T* __restrict__ 
 #pragma unroll
     for (int i = 0; i < 2 * NV; i++) adj[i * p.stride + s] = T(0);
     adj[2 * NV * p.stride + s] = T(dphi[s]);
+    if (other)
+#pragma unroll
+        for (int i = NV; i < 2 * NV; i++) other[i * p.stride + s] = T(0);
 }
 
 // A copy of v that the compiler cannot see through.  The FP32-storage
@@ -63,7 +74,7 @@ __device__ __forceinline__ T opaque_copy(T v)
 // transposed local collision Jacobian at x with the forward locals recomputed
 // from the saved state; writes lf, lg of the previous level, the stencil
 // cotangents, and block partials of d/d(A, B, kappa).
-template <typename T, typename AR, bool DEV>
+template <typename T, typename AR, bool DEV, bool G1>
 __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __restrict__ F,
                                                const double* __restrict__ phi,
                                                const T* __restrict__ an, T* __restrict__ ap,
@@ -81,7 +92,7 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
             // lambda_f and lambda_g of the later level are read once (non-
             // temporal); lambda_phi at d is gathered by 19 sites (cached)
             lfr[i] = __builtin_nontemporal_load(&an[i * S + d]);
-            lgr[i] = __builtin_nontemporal_load(&an[(NV + i) * S + d]);
+            lgr[i] = G1 ? T(0) : __builtin_nontemporal_load(&an[(NV + i) * S + d]);
             lpr[i] = an[2 * NV * S + d];
             f[i] = F[dist_pull(p, q, i)];
         }
@@ -99,7 +110,7 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
         AR t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            const AR lg = AR(lgr[i]) + AR(lpr[i]);
+            const AR lg = G1 ? AR(lpr[i]) : AR(lgr[i]) + AR(lpr[i]);
             const AR wg = AR(weight(i)) * omg * lg;
             t0 += wg;
             if (CX[i]) { t1x += CX[i] * wg; txx += wg; }
@@ -108,7 +119,7 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
             if (CX[i] * CY[i]) txy += CX[i] * CY[i] * wg;
             if (CX[i] * CZ[i]) txz += CX[i] * CZ[i] * wg;
             if (CY[i] * CZ[i]) tyz += CY[i] * CZ[i] * wg;
-            __builtin_nontemporal_store(T(cg * lg), &ap[(NV + i) * S + s]);
+            if (!G1) __builtin_nontemporal_store(T(cg * lg), &ap[(NV + i) * S + s]);
         }
         // the forward step's own rho and u (in the storage type's arithmetic)
         const Moments<T> mt = moments_of<T, DEV>(p, f);
@@ -193,20 +204,22 @@ __device__ __forceinline__ void adj_local_body(const KParams& p, const T* __rest
 // waves made the compiler serialise the loads: 2.2x slower).  The FP32
 // kernel runs 3-5% faster this way; the FP64 ones gain nothing but are kept
 // at the budget that needs no AGPRs.
+template <bool G1>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_adj_local_f32(
     KParams p, const float* __restrict__ F, const double* __restrict__ phi,
     const float* __restrict__ an, float* __restrict__ ap, float* __restrict__ sc,
     double* __restrict__ partials)
 {
-    adj_local_body<float, double, true>(p, F, phi, an, ap, sc, partials);
+    adj_local_body<float, double, true, G1>(p, F, phi, an, ap, sc, partials);
 }
 
+template <bool G1>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_adj_local_f64(
     KParams p, const double* __restrict__ F, const double* __restrict__ phi,
     const double* __restrict__ an, double* __restrict__ ap, double* __restrict__ sc,
     double* __restrict__ partials)
 {
-    adj_local_body<double, double, false>(p, F, phi, an, ap, sc, partials);
+    adj_local_body<double, double, false, G1>(p, F, phi, an, ap, sc, partials);
 }
 
 // Force coupling (u = (j + F/2)/rho in both equilibria, f^eq = w rho (1 +
@@ -224,7 +237,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 // through Pi at the face neighbours: k_adj_force_pi.
 // F_IN: F comes from k_adj_force_f in the dL/dF slots of sc (read at the own
 // site before they are overwritten), instead of being formed here.
-template <typename T, typename AR, bool DEV, bool F_IN>
+template <typename T, typename AR, bool DEV, bool F_IN, bool G1>
 __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* __restrict__ F,
                                                      const double* __restrict__ phi,
                                                      const T* __restrict__ an, T* __restrict__ ap,
@@ -244,7 +257,7 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
         for (int i = 0; i < NV; i++) {
             const int d = push_site(p, q, i);
             lfr[i] = __builtin_nontemporal_load(&an[i * S + d]);
-            lgr[i] = __builtin_nontemporal_load(&an[(NV + i) * S + d]);
+            lgr[i] = G1 ? T(0) : __builtin_nontemporal_load(&an[(NV + i) * S + d]);
             lpr[i] = an[2 * NV * S + d];
             f[i] = F[dist_pull(p, q, i)];
         }
@@ -279,7 +292,7 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
         AR t0 = 0, t1x = 0, t1y = 0, t1z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            const AR lg = AR(lgr[i]) + AR(lpr[i]);
+            const AR lg = G1 ? AR(lpr[i]) : AR(lgr[i]) + AR(lpr[i]);
             const AR wg = AR(weight(i)) * omg * lg;
             t0 += wg;
             if (CX[i]) { t1x += CX[i] * wg; txx += wg; }
@@ -288,7 +301,7 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
             if (CX[i] * CY[i]) txy += CX[i] * CY[i] * wg;
             if (CX[i] * CZ[i]) txz += CX[i] * CZ[i] * wg;
             if (CY[i] * CZ[i]) tyz += CY[i] * CZ[i] * wg;
-            __builtin_nontemporal_store(T(cg * lg), &ap[(NV + i) * S + s]);
+            if (!G1) __builtin_nontemporal_store(T(cg * lg), &ap[(NV + i) * S + s]);
         }
         AR m0 = 0, m1x = 0, m1y = 0, m1z = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
         T lfc[NV];
@@ -359,20 +372,22 @@ __device__ __forceinline__ void adj_local_force_body(const KParams& p, const T* 
     block_partials<3>(dth, partials);
 }
 
+template <bool G1>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_adj_local_force_f32(
     KParams p, const float* __restrict__ F, const double* __restrict__ phi,
     const float* __restrict__ an, float* __restrict__ ap, float* __restrict__ sc,
     double* __restrict__ partials)
 {
-    adj_local_force_body<float, double, true, false>(p, F, phi, an, ap, sc, partials);
+    adj_local_force_body<float, double, true, false, G1>(p, F, phi, an, ap, sc, partials);
 }
 
+template <bool G1>
 __global__ __launch_bounds__(kBlock) void k_adj_local_force_f64(
     KParams p, const double* __restrict__ F, const double* __restrict__ phi,
     const double* __restrict__ an, double* __restrict__ ap, double* __restrict__ sc,
     double* __restrict__ partials)
 {
-    adj_local_force_body<double, double, false, true>(p, F, phi, an, ap, sc, partials);
+    adj_local_force_body<double, double, false, true, G1>(p, F, phi, an, ap, sc, partials);
 }
 
 // F = -div Pi of the phi field (T-rounded, as the forward uses it) into the
@@ -531,6 +546,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_export(KParams p, const T* __res
 
 int grid_for(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
 
+// tau_g = 1: the levels' lg is identically zero (see the top of this file)
+bool g_free(const KParams& p) { return p.omega_g == 1.0; }
+
 int reduction_grid(const KParams& p)
 {
     const int g = grid_for(p);
@@ -539,12 +557,16 @@ int reduction_grid(const KParams& p)
 
 }  // namespace
 
-hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, const double* dphi, hipStream_t s)
+hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, void* other, const double* dphi,
+                           hipStream_t s)
 {
+    if (!g_free(p)) other = nullptr;
     if (fp32)
-        k_adj_seed<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<float*>(adj), dphi);
+        k_adj_seed<float><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<float*>(adj),
+                                                         static_cast<float*>(other), dphi);
     else
-        k_adj_seed<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<double*>(adj), dphi);
+        k_adj_seed<double><<<grid_for(p), kBlock, 0, s>>>(p, static_cast<double*>(adj),
+                                                          static_cast<double*>(other), dphi);
     return hipGetLastError();
 }
 
@@ -581,10 +603,15 @@ hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
         float* ap = static_cast<float*>(adj_prev);
         float* sc = static_cast<float*>(adj_scratch);
         if (p.force) {
-            k_adj_local_force_f32<<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
+            if (g_free(p))
+                k_adj_local_force_f32<true><<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
+            else
+                k_adj_local_force_f32<false><<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
             k_adj_force_pi<float><<<nb, kBlock, 0, s>>>(p, phi, sc, partials2);
+        } else if (g_free(p)) {
+            k_adj_local_f32<true><<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
         } else {
-            k_adj_local_f32<<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
+            k_adj_local_f32<false><<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
         }
     } else {
         const double* F = static_cast<const double*>(state);
@@ -593,10 +620,15 @@ hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
         double* sc = static_cast<double*>(adj_scratch);
         if (p.force) {
             k_adj_force_f<double><<<grid_for(p), kBlock, 0, s>>>(p, phi, sc);
-            k_adj_local_force_f64<<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
+            if (g_free(p))
+                k_adj_local_force_f64<true><<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
+            else
+                k_adj_local_force_f64<false><<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
             k_adj_force_pi<double><<<nb, kBlock, 0, s>>>(p, phi, sc, partials2);
+        } else if (g_free(p)) {
+            k_adj_local_f64<true><<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
         } else {
-            k_adj_local_f64<<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
+            k_adj_local_f64<false><<<nb, kBlock, 0, s>>>(p, F, phi, an, ap, sc, partials);
         }
     }
     const hipError_t e = hipGetLastError();

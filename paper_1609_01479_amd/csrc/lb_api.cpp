@@ -466,7 +466,8 @@ lb_status lb_adjoint_seed(lb_ctx* ctx, const double* dphi_dev)
         return fail(LB_ESTATE, "LB_KERNEL_STREAM (free streaming) has no reverse mode");
     if (ctx->kp.xh) return fail(LB_ESTATE, "x-slab shards have no reverse mode");
     ctx->adj_cur = 0;
-    hipError_t e = lbk::launch_adj_seed(ctx->kp, ctx->fp32, ctx->b.adj[0], dphi_dev, ctx->stream);
+    hipError_t e = lbk::launch_adj_seed(ctx->kp, ctx->fp32, ctx->b.adj[0], ctx->b.adj[1], dphi_dev,
+                                        ctx->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_seed");
 }
 

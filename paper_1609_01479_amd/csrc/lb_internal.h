@@ -106,7 +106,9 @@ hipError_t launch_import(const KParams& p, bool fp32, void* state, const double*
                          const double* g, hipStream_t s);
 
 // Reverse mode.
-hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, const double* dphi,
+// adj: the level seeded (lf = lg = 0, lp = dphi); other: the second level,
+// whose lg is zeroed too when tau_g = 1 (the steps then never touch lg).
+hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, void* other, const double* dphi,
                            hipStream_t s);
 // state_next (may be null): the level one step after `state`; in FP32 mode
 // its reference field is phi of `state`, so the phi pass is skipped.

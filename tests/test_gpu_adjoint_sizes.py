@@ -18,15 +18,17 @@ SHAPE = (72, 64, 64)
 
 
 @pytest.mark.parametrize("coupling", ["stress", "force"])
-@pytest.mark.parametrize("order_param", ["lb", "fd"])
-def test_adjoint_two_rounds_matches_oracle(order_param, coupling):
+@pytest.mark.parametrize("order_param,tau_g", [("lb", 1.3), ("lb", 1.0), ("fd", 1.3)])
+def test_adjoint_two_rounds_matches_oracle(order_param, tau_g, coupling):
+    """tau_g = 1 takes the local kernels' path without lambda_g's specific
+    components."""
     from paper_1609_01479_amd.rollout import rollout
     T = 3
-    kw = dict(tau_f=0.8, tau_g=1.3)
+    kw = dict(tau_f=0.8, tau_g=tau_g)
     pr = dict(lbinputs.SPINODAL_PARAMS, **kw)
     phi0 = lbinputs.spinodal_phi0(SHAPE, seed=31, amp=0.3)
     tgt = lbinputs.lamellar_target(SHAPE, 8, lbinputs.interface_width(pr["A"], pr["kappa"]))
-    print(f"[adjoint sizes] {SHAPE} x {T} {order_param} {coupling}", flush=True)
+    print(f"[adjoint sizes] {SHAPE} x {T} {order_param} {coupling} tau_g={tau_g}", flush=True)
     dev = torch.device("cuda:0")
     p0 = torch.tensor(phi0, dtype=torch.float64, device=dev, requires_grad=True)
     th = [torch.tensor(pr[k], dtype=torch.float64, device=dev, requires_grad=True)

@@ -87,23 +87,24 @@ def _flowing_state(shape, seed):
     return f0, g0
 
 
-def _reference_from_state(f0, g0, tgt, T, pr):
+def _reference_from_state(f0, g0, tgt, T, pr, coupling="force"):
+    step = R.step_force if coupling == "force" else R.step
     f = torch.tensor(f0, dtype=torch.float64, requires_grad=True)
     g = torch.tensor(g0, dtype=torch.float64, requires_grad=True)
     th = [torch.tensor(float(pr[k]), dtype=torch.float64, requires_grad=True)
           for k in ("A", "B", "kappa")]
     fs, gs = f, g
     for _ in range(T):
-        fs, gs = R.step_force(fs, gs, *th, pr["gamma"], pr["tau_f"], pr["tau_g"])
+        fs, gs = step(fs, gs, *th, pr["gamma"], pr["tau_f"], pr["tau_g"])
     loss = 0.5 * ((gs.sum(0) - torch.tensor(tgt, dtype=torch.float64)) ** 2).sum()
     loss.backward()
     return (float(loss.detach()), f.grad.numpy(), g.grad.numpy(),
             tuple(float(t.grad) for t in th))
 
 
-def _gpu_from_state(f0, g0, tgt, T, precision="fp64", **kw):
+def _gpu_from_state(f0, g0, tgt, T, precision="fp64", coupling="force", **kw):
     shape = f0.shape[1:]
-    lb = make_lb(shape, precision=precision, adjoint=True, coupling="force", **kw)
+    lb = make_lb(shape, precision=precision, adjoint=True, coupling=coupling, **kw)
     lb.import_dist(f0, g0)
     states = []
     for _ in range(T):
@@ -137,6 +138,33 @@ def test_force_adjoint_flowing_state_df0_dg0(shape):
     assert rel_err(lg, rg) <= 1e-10, rel_err(lg, rg)
     for name, a, b in zip(("A", "B", "kappa"), th, rth):
         assert abs(a - b) <= 1e-9 * abs(b), (name, a, b)
+
+
+@pytest.mark.parametrize("coupling", ["stress", "force"])
+@pytest.mark.parametrize("T", [10, 11])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
+def test_adjoint_tau_g_one_flowing_state(precision, T, coupling):
+    """tau_g = 1, where the levels' lambda_g-specific components are
+    identically zero and the local kernels skip them: dL/df0, dL/dg0 (every
+    dL/dg_i equal to dL/dphi, as the oracle's autograd finds) and dL/d(A, B,
+    kappa) from an imported flowing state.  An even and an odd number of
+    steps end on either of the two adjoint levels.  FP32 storage is held to
+    its rounding."""
+    shape = (6, 5, 7)
+    kw = dict(tau_f=0.9, tau_g=1.0)
+    pr = dict(lbinputs.SPINODAL_PARAMS, **kw)
+    f0, g0 = _flowing_state(shape, 61)
+    tgt = lbinputs.random_field(shape, 62)
+    print(f"[adjoint tau_g=1] {precision} {coupling} {shape} x {T}", flush=True)
+    L, lf, lg, th = _gpu_from_state(f0, g0, tgt, T, precision=precision, coupling=coupling, **kw)
+    rL, rf, rg, rth = _reference_from_state(f0, g0, tgt, T, pr, coupling)
+    assert np.abs(rg - rg[:1]).max() <= 1e-12 * np.abs(rg).max()
+    tol, tloss, tth = (1e-10, 1e-12, 1e-9) if precision == "fp64" else (1e-4, 1e-6, 1e-3)
+    assert abs(L - rL) <= tloss * abs(rL), (L, rL)
+    assert rel_err(lf, rf) <= tol, rel_err(lf, rf)
+    assert rel_err(lg, rg) <= tol, rel_err(lg, rg)
+    for name, a, b in zip(("A", "B", "kappa"), th, rth):
+        assert abs(a - b) <= tth * abs(b), (name, a, b)
 
 
 def test_force_adjoint_fp32_close_to_fp64():
