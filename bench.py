@@ -244,6 +244,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-legs", default="",
+                    help="comma-separated names of the adjoint legs to run (default: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="oracle steps of the 256^3 CPU baseline sample")
@@ -617,6 +619,8 @@ def main():
                 ("force_64^3_fp64_T200", 64, 200, 15, "fp64", "lb", "force"),
                 ("force_128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "lb", "force"),
                 ("fd_force_128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "fd", "force")):
+            if args.adjoint_legs and name not in args.adjoint_legs.split(","):
+                continue
             sh = (nn, nn, nn)
             ph0 = lbinputs.spinodal_phi0(sh)
             tgt = lbinputs.lamellar_target(sh, 32, xi)
