@@ -449,7 +449,9 @@ __device__ __forceinline__ Vel<T> collide_force_f(const KParams& p, T* f, const 
     return Vel<T>{ux, uy, uz};
 }
 
-template <typename T, bool REF>
+// G1 (omega_g = 1): g* = g^eq, with no term in the pre-collision g, which
+// the caller then need not load.
+template <typename T, bool REF, bool G1>
 __device__ __forceinline__ void collide_force_g(const KParams& p, T* g, double phi_d, double mu_d,
                                                 Vel<T> u)
 {
@@ -465,16 +467,19 @@ __device__ __forceinline__ void collide_force_g(const KParams& p, T* g, double p
         const T q = cu * cu - uu3;
         const T c2m1 = T(CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i] - 1);
         const T geq = w * ((REF ? T(0) : phi) + T(3) * phi * cu + T(4.5) * (sg * c2m1 + phi * q));
-        g[i] += omg * (geq - g[i]);
+        if (G1)
+            g[i] = geq;
+        else
+            g[i] += omg * (geq - g[i]);
     }
 }
 
-template <typename T, bool DEV, bool REF>
+template <typename T, bool DEV, bool REF, bool G1>
 __device__ __forceinline__ void collide_force(const KParams& p, T* f, T* g, double phi_d, double mu_d,
                                               const double Fd[3])
 {
     const Vel<T> u = collide_force_f<T, DEV>(p, f, Fd);
-    collide_force_g<T, REF>(p, g, phi_d, mu_d, u);
+    collide_force_g<T, REF, G1>(p, g, phi_d, mu_d, u);
 }
 
 // Force coupling: F = -div Pi by central differences of Pi at the six face

@@ -29,7 +29,7 @@ namespace {
 // The force-coupling collision and propagation, one site per thread; phi of
 // the source level (all sites) comes from k_phi.  In FP32 mode phi is the
 // destination level's phi_c field (as in k_step_2s).
-template <typename T, bool DEV, bool REF>
+template <typename T, bool DEV, bool REF, bool G1>
 __global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const T* __restrict__ sF,
                                                        const T* __restrict__ sG,
                                                        const double* __restrict__ sphic,
@@ -43,21 +43,21 @@ __global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const T* __res
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         f[i] = sF[dist_pull(p, q, i)];
-        g[i] = sG[dist_pull(p, q, i)];
+        g[i] = G1 ? T(0) : sG[dist_pull(p, q, i)];
     }
     const double c = phi[s];
     const double lap = (phi[site_of(p, q.xp, q.y, q.z)] + phi[site_of(p, q.xm, q.y, q.z)] - 2.0 * c)
                      + (phi[site_of(p, q.x, q.yp, q.z)] + phi[site_of(p, q.x, q.ym, q.z)] - 2.0 * c)
                      + (phi[site_of(p, q.x, q.y, q.zp)] + phi[site_of(p, q.x, q.y, q.zm)] - 2.0 * c);
     const double mu = p.A * c + p.B * c * c * c - p.kappa * lap;
-    if (REF) {
+    if (REF && !G1) {
         const double dphi = c - sphic[s];
 #pragma unroll
         for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, g[i], dphi);
     }
     double F[3];
     force_from_phi(p, q, phi, F);
-    collide_force<T, DEV, REF>(p, f, g, c, mu, F);
+    collide_force<T, DEV, REF, G1>(p, f, g, c, mu, F);
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         dF[dist_own(p, q, i)] = f[i];
@@ -92,12 +92,19 @@ __device__ __forceinline__ int wrap_any(int v, int n)
 // in-plane neighbours (LDS, written one plane earlier).  Planes x0-1 and x1
 // only supply the own column's Pi.  Tile cells beyond a ragged lattice edge
 // stand for the periodic images there: they form Pi but store nothing.
-template <typename T, bool DEV, bool REF, int TZ>
+//
+// PULL: phi of the box comes from the g populations themselves (pulled and
+// summed as k_phi sums them, so the values are bit-identical), one plane
+// ahead, instead of from a phi field; the own cell's phi is written to
+// `phi` (the next level's phi_c in FP32 mode; the caller's phi field in FP64
+// mode, or nowhere if it is null).  One kernel then reads and writes each
+// population once per step.
+template <typename T, bool DEV, bool REF, int TZ, bool PULL, bool G1>
 __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg tc,
                                                              const T* __restrict__ sF,
                                                              const T* __restrict__ sG,
                                                              const double* __restrict__ sphic,
-                                                             const double* __restrict__ phi,
+                                                             double* __restrict__ phi,
                                                              T* __restrict__ dF, T* __restrict__ dG)
 {
     using G = ForceTile<TZ>;
@@ -118,13 +125,13 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
     const bool valid = y0 + ly < p.ny && z0 + lz < p.nz;
     const int bo = (ly + 2) * BZ + (lz + 2);
     const int ro = (ly + 1) * RZ + (lz + 1);
-    int boff[G::BOXPT];
+    int boff[G::BOXPT], bcy[G::BOXPT], bcz[G::BOXPT];
 #pragma unroll
     for (int k = 0; k < G::BOXPT; k++) {
         const int c = t + k * kForceFused;
-        boff[k] = c < G::NBOX
-                      ? wrap_any(y0 + c / BZ - 2, p.ny) * p.nz + wrap_any(z0 + c % BZ - 2, p.nz)
-                      : -1;
+        bcy[k] = c < G::NBOX ? wrap_any(y0 + c / BZ - 2, p.ny) : -1;
+        bcz[k] = c < G::NBOX ? wrap_any(z0 + c % BZ - 2, p.nz) : -1;
+        boff[k] = c < G::NBOX ? bcy[k] * p.nz + bcz[k] : -1;
     }
     const bool ring = t < G::NRING;
     int rly, rlz;
@@ -136,18 +143,56 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
     const int rbo = (rly + 2) * BZ + (rlz + 2);
     const int rro = (rly + 1) * RZ + (rlz + 1);
 
-    auto load_box = [&](int xp, double (&v)[G::BOXPT]) {
-        const int xo = wrap_any(xp, p.nx) * plane;
-#pragma unroll
-        for (int k = 0; k < G::BOXPT; k++) v[k] = boff[k] >= 0 ? phi[xo + boff[k]] : 0.0;
+    // the box of plane xp in flight: phi values, or (PULL with FP32 storage)
+    // the pulled g and phi_c of each box cell, summed when stored (FP64
+    // storage sums its pulls at once: carrying them would take 76 more VGPRs)
+    constexpr bool CARRY = PULL && std::is_same<T, float>::value;
+    struct BoxLoads {
+        double v[G::BOXPT];
+        T g[CARRY ? G::BOXPT : 1][NV];
     };
-    auto store_box = [&](int xp, const double (&v)[G::BOXPT]) {
+    // phi_at's sum: the pulled values in index order, then phi_c
+    auto sum_g = [&](const T (&g)[NV], double pc) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < NV; i++) acc += double(g[i]);
+        return REF ? pc + acc : acc;
+    };
+    auto load_box = [&](int xp, BoxLoads& b) {
+        const int xw = wrap_any(xp, p.nx);
+#pragma unroll
+        for (int k = 0; k < G::BOXPT; k++) {
+            if (boff[k] < 0) continue;
+            if constexpr (PULL) {
+                const Geo q = geo_xyz(p, xw, bcy[k], bcz[k]);
+                T g[NV];
+#pragma unroll
+                for (int i = 0; i < NV; i++) g[i] = sG[dist_pull(p, q, i)];
+                const double pc = REF ? sphic[xw * plane + boff[k]] : 0.0;
+                if constexpr (CARRY) {
+#pragma unroll
+                    for (int i = 0; i < NV; i++) b.g[k][i] = g[i];
+                    b.v[k] = pc;
+                } else {
+                    b.v[k] = sum_g(g, pc);
+                }
+            } else {
+                b.v[k] = phi[xw * plane + boff[k]];
+            }
+        }
+    };
+    auto store_box = [&](int xp, const BoxLoads& b) {
         double* __restrict__ dst = s_phi[xp & (kPhiSlots - 1)];
 #pragma unroll
-        for (int k = 0; k < G::BOXPT; k++)
-            if (boff[k] >= 0) dst[t + k * kForceFused] = v[k];
+        for (int k = 0; k < G::BOXPT; k++) {
+            if (boff[k] < 0) continue;
+            if constexpr (CARRY)
+                dst[t + k * kForceFused] = sum_g(b.g[k], b.v[k]);
+            else
+                dst[t + k * kForceFused] = b.v[k];
+        }
     };
-    double pre[G::BOXPT];
+    BoxLoads pre;
     load_box(x0 - 2, pre);
     store_box(x0 - 2, pre);
     load_box(x0 - 1, pre);
@@ -161,7 +206,6 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
         const bool collide_x = X >= x0 && valid;
         // (a)
         store_box(P + 1, pre);
-        load_box(P + 2, pre);
         T f[NV], g[NV];
         double pc_src = 0.0;
         const Geo q = geo_xyz(p, wrap_any(X, p.nx), yg, zg);
@@ -169,10 +213,11 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
 #pragma unroll
             for (int i = 0; i < NV; i++) {
                 f[i] = sF[dist_pull(p, q, i)];
-                g[i] = sG[dist_pull(p, q, i)];
+                g[i] = G1 ? T(0) : sG[dist_pull(p, q, i)];
             }
-            if (REF) pc_src = sphic[X * plane + yg * p.nz + zg];
+            if (REF && !G1) pc_src = sphic[X * plane + yg * p.nz + zg];
         }
+        load_box(P + 2, pre);
         lds_barrier();
         const double* __restrict__ fm = s_phi[(P - 1) & (kPhiSlots - 1)];
         const double* __restrict__ fc = s_phi[P & (kPhiSlots - 1)];
@@ -222,7 +267,7 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
             const double lap = (xp[bo] + xm[bo] - 2.0 * c) + (xc[bo + BZ] + xc[bo - BZ] - 2.0 * c)
                              + (xc[bo + 1] + xc[bo - 1] - 2.0 * c);
             const double mu = p.A * c + p.B * c * c * c - p.kappa * lap;
-            if (REF) {
+            if (REF && !G1) {
                 const double dphi = c - pc_src;
 #pragma unroll
                 for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, g[i], dphi);
@@ -238,7 +283,8 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
             double F[3];
 #pragma unroll
             for (int a = 0; a < 3; a++) F[a] = -div[a];
-            collide_force<T, DEV, REF>(p, f, g, c, mu, F);
+            collide_force<T, DEV, REF, G1>(p, f, g, c, mu, F);
+            if (PULL && phi) phi[X * plane + yg * p.nz + zg] = c;
 #pragma unroll
             for (int i = 0; i < NV; i++) {
                 __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
@@ -258,37 +304,73 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
     }
 }
 
-template <typename T, bool DEV, bool REF>
-struct ForceFused {
-    using K = decltype(&k_force_fused<T, DEV, REF, 128>);
-    static K get(int tz) { return tz == 64 ? k_force_fused<T, DEV, REF, 64> : k_force_fused<T, DEV, REF, 128>; }
-};
-
 int force_grid(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
+
+// Tiling of the single pass (PULL): 8 x 64 tiles, whose box of phi (two
+// cells around the tile, 12 x 68) is 1.6 cells per thread, against 2.1 for
+// 4 x 128 tiles, whose pulled g would not fit the registers; x segments as
+// tile_config chooses them (fewest rounds of 256 workgroups times the
+// segment length plus its two warm-up planes).
+TileCfg force_tiles(const KParams& p, int seg_req)
+{
+    TileCfg tc;
+    tc.tz = 64;
+    tc.nty = (p.ny + kForceFused / 64 - 1) / (kForceFused / 64);
+    tc.ntz = (p.nz + 63) / 64;
+    tc.ntiles = tc.nty * tc.ntz;
+    tc.seg_req = seg_req;
+    int sx = seg_req;
+    if (sx <= 0) {
+        long long best = -1;
+        for (int nseg = 1; nseg <= p.nx; nseg++) {
+            const int sl = (p.nx + nseg - 1) / nseg;
+            const long long nb = (long long)tc.ntiles * ((p.nx + sl - 1) / sl);
+            const long long cost = ((nb + 255) / 256) * (sl + 2);
+            if (best < 0 || cost < best) {
+                best = cost;
+                sx = sl;
+            }
+        }
+    }
+    if (sx > p.nx) sx = p.nx;
+    tc.sx = sx;
+    tc.nseg = (p.nx + sx - 1) / sx;
+    return tc;
+}
 
 }  // namespace
 
 hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, int variant,
-                                const void* src, void* dst, const double* phi, hipStream_t s)
+                                const void* src, void* dst, double* phi, hipStream_t s)
 {
+    const TileCfg ft = force_tiles(p, tc.seg_req);
+    const int nft = ft.ntiles * ft.nseg;
+    // omega_g = 1: g* = g^eq, so the collision loads no g (the single pass
+    // still pulls g for phi)
+    const bool g1 = p.omega_g == 1.0;
     if (fp32) {
         Lvl<float> a = level<float>(const_cast<void*>(src), p, true);
         Lvl<float> d = level<float>(dst, p, true);
-        if (variant == 0)
-            ForceFused<float, true, true>::get(tc.tz)<<<tc.ntiles * tc.nseg, kForceFused, 0, s>>>(
-                p, tc, a.F, a.G, a.phic, phi, d.F, d.G);
-        else
-            k_step_force<float, true, true><<<force_grid(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phi,
-                                                                             d.F, d.G);
+        if (variant == 0) {
+            auto k = g1 ? k_force_fused<float, true, true, 64, true, true>
+                        : k_force_fused<float, true, true, 64, true, false>;
+            k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, a.phic, d.phic, d.F, d.G);
+        } else {
+            auto k = g1 ? k_step_force<float, true, true, true> : k_step_force<float, true, true, false>;
+            k<<<force_grid(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phi, d.F, d.G);
+        }
     } else {
         Lvl<double> a = level<double>(const_cast<void*>(src), p, false);
         Lvl<double> d = level<double>(dst, p, false);
-        if (variant == 0)
-            ForceFused<double, false, false>::get(tc.tz)<<<tc.ntiles * tc.nseg, kForceFused, 0, s>>>(
-                p, tc, a.F, a.G, a.phic, phi, d.F, d.G);
-        else
-            k_step_force<double, false, false><<<force_grid(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic,
-                                                                                phi, d.F, d.G);
+        if (variant == 0) {
+            auto k = g1 ? k_force_fused<double, false, false, 64, true, true>
+                        : k_force_fused<double, false, false, 64, true, false>;
+            k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, a.phic, phi, d.F, d.G);
+        } else {
+            auto k = g1 ? k_step_force<double, false, false, true>
+                        : k_step_force<double, false, false, false>;
+            k<<<force_grid(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phi, d.F, d.G);
+        }
     }
     return hipGetLastError();
 }

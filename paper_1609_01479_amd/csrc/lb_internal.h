@@ -85,12 +85,14 @@ int step_sums_blocks(const KParams& p, const TileCfg& tc, int variant);
 hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
                        const void* src, void* dst, double* phi_work, double* partials,
                        double* sums_out, double* phi_src_out, hipStream_t s);
-// Force coupling, after the phi pass: the forcing collision from src to dst
-// with phi (all sites, FP64) of src in `phi`.  variant 0: single pass over
-// (y, z) tiles marching along x (tiling tc), Pi in LDS; 1: one site per
-// thread, Pi formed at each face neighbour.  Bit-identical results.
+// Force coupling: the forcing collision from src to dst.  variant 0: the
+// whole step in one pass over (y, z) tiles marching along x (tiling tc),
+// phi summed from the pulled g, Pi in LDS; phi of src goes to dst's phi_c
+// field (FP32 mode) or to `phi` if not null (FP64 mode).  variant 1: after
+// the phi pass, which left phi (all sites, FP64) of src in `phi`, one site
+// per thread, Pi formed at each face neighbour.  Bit-identical results.
 hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, int variant,
-                                const void* src, void* dst, const double* phi, hipStream_t s);
+                                const void* src, void* dst, double* phi, hipStream_t s);
 // phi(x) of the post-propagation state held in `state`.
 hipError_t launch_phi(const KParams& p, bool fp32, const void* state, double* phi, hipStream_t s);
 // work: the FP64 phi field the force coupling needs (`stride` long); unused

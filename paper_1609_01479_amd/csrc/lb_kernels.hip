@@ -14,8 +14,9 @@
 //
 // k_phi + k_step_2s are the two-pass variant (phi kernel, then the
 // stencil/collision/propagation kernel), kept for comparison; both variants
-// produce bit-identical levels.  The force coupling runs k_phi and then the
-// collision pass of lb_force.hip; the finite-difference order parameter has
+// produce bit-identical levels.  The force coupling runs the marching kernel
+// of lb_force.hip (or k_phi and its one-site-per-thread collision pass);
+// the finite-difference order parameter has
 // its own kernels in lb_fd.hip.
 #include <type_traits>
 
@@ -790,7 +791,8 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
     double* phi64 = phi_src_out ? phi_src_out : phi_work;
     int nparts = 0;
     if (p.force) {
-        // phi (the new level's phi_c in FP32 mode), then the forcing collision
+        // the two-pass variant first forms phi (the new level's phi_c in FP32
+        // mode); the single pass sums it from its own pulls
 #define CALL                                                                                   \
     {                                                                                          \
         Lvl<T> a = level<T>(const_cast<void*>(src), p, REF);                                   \
@@ -802,13 +804,14 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
                                                              nullptr, nullptr, nullptr,        \
                                                              partials);                        \
         }                                                                                      \
-        k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);                    \
+        if (variant == 1) k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);  \
     }
         LB_DISPATCH(fp32, CALL, CALL);
 #undef CALL
         {
-            hipError_t e = launch_force_collide(p, tc, fp32, variant, src, dst,
-                                                fp32 ? level<float>(dst, p, true).phic : phi64, s);
+            hipError_t e = launch_force_collide(
+                p, tc, fp32, variant, src, dst,
+                fp32 ? level<float>(dst, p, true).phic : (variant == 1 ? phi64 : phi_src_out), s);
             if (e != hipSuccess) return e;
         }
         if (sums_out) k_sums_final<<<1, kBlock, 0, s>>>(partials, nparts, 5, sums_out, 0);

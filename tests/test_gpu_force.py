@@ -61,21 +61,23 @@ def test_force_droplet_interface():
         p, *oracle.init(p, phi0), 50)), rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("tau_g", [1.3, 1.0])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_dev"])
 @pytest.mark.parametrize("shape,seg", [((16, 16, 16), 0), ((16, 16, 16), 5), ((5, 6, 7), 2),
                                        ((3, 5, 131), 0), ((17, 9, 70), 4), ((1, 7, 1), 0),
                                        ((2, 2, 2), 1), ((6, 13, 200), 3), ((24, 20, 192), 0)])
-def test_force_single_pass_matches_per_site(precision, shape, seg):
-    """The marching collision pass (Pi of each site once, in LDS) and the
-    per-site one (Pi at each face neighbour) give bit-identical levels:
-    ragged tiles, both tile shapes, one-plane and long segments, extents 1
-    and 2."""
-    print(f"[force fused] {shape} segment_x={seg} {precision}", flush=True)
+def test_force_single_pass_matches_per_site(precision, shape, seg, tau_g):
+    """The single pass (phi summed from its own pulls, Pi of each site once,
+    in LDS) and the phi pass + per-site collision (Pi at each face
+    neighbour) give bit-identical levels: ragged tiles, one-plane and long
+    segments, extents 1 and 2; tau_g = 1 takes the collision that loads no
+    g."""
+    print(f"[force fused] {shape} segment_x={seg} {precision} tau_g={tau_g}", flush=True)
     phi0 = lbinputs.spinodal_phi0(shape, seed=19, amp=0.4)
     out = []
     for kern in ("fused", "two_pass"):
         lb = make_lb(shape, precision=precision, coupling="force", kernel=kern, segment_x=seg,
-                     tau_f=0.8, tau_g=1.3)
+                     tau_f=0.8, tau_g=tau_g)
         lb.init_phi(phi0)
         lb.step(7)
         out.append(gpu_state(lb))
