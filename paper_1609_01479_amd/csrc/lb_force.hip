@@ -1,17 +1,18 @@
-// Force coupling (LB_COUPLING_FORCE), the collision pass after k_phi: F =
-// -div Pi by central differences of the chemical stress at the six face
-// neighbours (the paper's Ludwig model applies the stress's divergence as a
-// body force, Sec. 2.1.1), with the half-force velocity and Guo's forcing
-// term in collide_force().  Two forms with bit-identical results:
+// Force coupling (LB_COUPLING_FORCE): F = -div Pi by central differences of
+// the chemical stress at the six face neighbours (the paper's Ludwig model
+// applies the stress's divergence as a body force, Sec. 2.1.1), with the
+// half-force velocity and Guo's forcing term in collide_force().  Two forms
+// with bit-identical results:
 //
-//   k_force_fused (LB_KERNEL_FUSED): the single-pass LB kernel's tiling --
-//     a TY x TZ tile of (y, z) columns marching along x -- with phi of the
-//     tile plus two cells around it in an LDS ring, Pi of plane P formed
-//     once per site for the tile and its face ring and kept in LDS (the
+//   k_force_fused (LB_KERNEL_FUSED): the whole step in one pass, on the
+//     single-pass LB kernel's tiling -- a TY x TZ tile of (y, z) columns
+//     marching along x -- with phi of the tile plus two cells around it
+//     summed from the pulled g into an LDS ring, Pi of plane P formed once
+//     per site for the tile and its face ring and kept in LDS (the
 //     components the y and z neighbours need) and in registers (the own
 //     column's x row, for x +- 1), and the collision of plane P-1;
-//   k_step_force (LB_KERNEL_TWO_PASS): one site per thread, Pi formed at
-//     each face neighbour from the phi field (force_from_phi).
+//   k_step_force (LB_KERNEL_TWO_PASS), after k_phi: one site per thread, Pi
+//     formed at each face neighbour from the phi field (force_from_phi).
 //
 // No floating-point contraction in this translation unit (including the
 // shared device functions it inlines): the compiler fuses multiply-adds
@@ -84,22 +85,21 @@ __device__ __forceinline__ int wrap_any(int v, int n)
     return r < 0 ? r + n : r;
 }
 
-// For plane P: (a) phi(P+1) into the LDS ring (loaded one plane earlier),
-// the loads of phi(P+2), and the pulls of the own site of plane P-1; (c) Pi
+// For plane P: (a) phi(P+1) into the LDS ring (its g pulled one plane
+// earlier), the pulls of the own site of plane P-1 and of the box of plane
+// P+2; (c) Pi
 // of plane P at the own site and, for the first 2 (TY + TZ) threads, at a
 // face-ring cell; (e) the forcing collision of plane P-1, whose F uses Pi of
 // planes P-2 and P (own column, registers) and of plane P-1 at the four
 // in-plane neighbours (LDS, written one plane earlier).  Planes x0-1 and x1
 // only supply the own column's Pi.  Tile cells beyond a ragged lattice edge
 // stand for the periodic images there: they form Pi but store nothing.
-//
-// PULL: phi of the box comes from the g populations themselves (pulled and
-// summed as k_phi sums them, so the values are bit-identical), one plane
-// ahead, instead of from a phi field; the own cell's phi is written to
-// `phi` (the next level's phi_c in FP32 mode; the caller's phi field in FP64
-// mode, or nowhere if it is null).  One kernel then reads and writes each
-// population once per step.
-template <typename T, bool DEV, bool REF, int TZ, bool PULL, bool G1>
+// phi of the box is pulled and summed as k_phi sums it (so the values are
+// bit-identical); the own cell's phi goes to `phi` (the next level's phi_c
+// in FP32 mode; the caller's phi field in FP64 mode, or nowhere if it is
+// null).  Each population is read and written once per step.  G1 (omega_g
+// = 1): the collision takes g* = g^eq and loads no g.
+template <typename T, bool DEV, bool REF, int TZ, bool G1>
 __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg tc,
                                                              const T* __restrict__ sF,
                                                              const T* __restrict__ sG,
@@ -125,10 +125,15 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
     const bool valid = y0 + ly < p.ny && z0 + lz < p.nz;
     const int bo = (ly + 2) * BZ + (lz + 2);
     const int ro = (ly + 1) * RZ + (lz + 1);
-    int boff[G::BOXPT], bcy[G::BOXPT], bcz[G::BOXPT];
+    // box cells of this thread: the partly filled last slot goes to the last
+    // threads, so that its extra work lands on the waves without face-ring
+    // cells (the first 2 (TY + TZ) threads); 3% faster in FP64
+    int boff[G::BOXPT], bcy[G::BOXPT], bcz[G::BOXPT], bcell[G::BOXPT];
 #pragma unroll
     for (int k = 0; k < G::BOXPT; k++) {
-        const int c = t + k * kForceFused;
+        const int nk = G::NBOX - k * kForceFused < kForceFused ? G::NBOX - k * kForceFused : kForceFused;
+        const int c = t >= kForceFused - nk ? k * kForceFused + t - (kForceFused - nk) : G::NBOX;
+        bcell[k] = c;
         bcy[k] = c < G::NBOX ? wrap_any(y0 + c / BZ - 2, p.ny) : -1;
         bcz[k] = c < G::NBOX ? wrap_any(z0 + c % BZ - 2, p.nz) : -1;
         boff[k] = c < G::NBOX ? bcy[k] * p.nz + bcz[k] : -1;
@@ -143,10 +148,10 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
     const int rbo = (rly + 2) * BZ + (rlz + 2);
     const int rro = (rly + 1) * RZ + (rlz + 1);
 
-    // the box of plane xp in flight: phi values, or (PULL with FP32 storage)
-    // the pulled g and phi_c of each box cell, summed when stored (FP64
-    // storage sums its pulls at once: carrying them would take 76 more VGPRs)
-    constexpr bool CARRY = PULL && std::is_same<T, float>::value;
+    // the box of plane xp in flight: with FP32 storage the pulled g and phi_c
+    // of each box cell, summed when stored; FP64 storage sums its pulls at
+    // once (carrying them would take 76 more VGPRs)
+    constexpr bool CARRY = std::is_same<T, float>::value;
     struct BoxLoads {
         double v[G::BOXPT];
         T g[CARRY ? G::BOXPT : 1][NV];
@@ -163,21 +168,17 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
 #pragma unroll
         for (int k = 0; k < G::BOXPT; k++) {
             if (boff[k] < 0) continue;
-            if constexpr (PULL) {
-                const Geo q = geo_xyz(p, xw, bcy[k], bcz[k]);
-                T g[NV];
+            const Geo q = geo_xyz(p, xw, bcy[k], bcz[k]);
+            T g[NV];
 #pragma unroll
-                for (int i = 0; i < NV; i++) g[i] = sG[dist_pull(p, q, i)];
-                const double pc = REF ? sphic[xw * plane + boff[k]] : 0.0;
-                if constexpr (CARRY) {
+            for (int i = 0; i < NV; i++) g[i] = sG[dist_pull(p, q, i)];
+            const double pc = REF ? sphic[xw * plane + boff[k]] : 0.0;
+            if constexpr (CARRY) {
 #pragma unroll
-                    for (int i = 0; i < NV; i++) b.g[k][i] = g[i];
-                    b.v[k] = pc;
-                } else {
-                    b.v[k] = sum_g(g, pc);
-                }
+                for (int i = 0; i < NV; i++) b.g[k][i] = g[i];
+                b.v[k] = pc;
             } else {
-                b.v[k] = phi[xw * plane + boff[k]];
+                b.v[k] = sum_g(g, pc);
             }
         }
     };
@@ -187,9 +188,9 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
         for (int k = 0; k < G::BOXPT; k++) {
             if (boff[k] < 0) continue;
             if constexpr (CARRY)
-                dst[t + k * kForceFused] = sum_g(b.g[k], b.v[k]);
+                dst[bcell[k]] = sum_g(b.g[k], b.v[k]);
             else
-                dst[t + k * kForceFused] = b.v[k];
+                dst[bcell[k]] = b.v[k];
         }
     };
     BoxLoads pre;
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
 #pragma unroll
             for (int a = 0; a < 3; a++) F[a] = -div[a];
             collide_force<T, DEV, REF, G1>(p, f, g, c, mu, F);
-            if (PULL && phi) phi[X * plane + yg * p.nz + zg] = c;
+            if (phi) phi[X * plane + yg * p.nz + zg] = c;
 #pragma unroll
             for (int i = 0; i < NV; i++) {
                 __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
@@ -306,11 +307,11 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
 
 int force_grid(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
 
-// Tiling of the single pass (PULL): 8 x 64 tiles, whose box of phi (two
-// cells around the tile, 12 x 68) is 1.6 cells per thread, against 2.1 for
-// 4 x 128 tiles, whose pulled g would not fit the registers; x segments as
-// tile_config chooses them (fewest rounds of 256 workgroups times the
-// segment length plus its two warm-up planes).
+// Tiling of the single pass: 8 x 64 tiles, whose box of phi (two cells
+// around the tile, 12 x 68) is 1.6 cells per thread, against 2.1 for
+// 4 x 128 tiles (whose carried pulls spill unless tau_g = 1, and then ran
+// only 0.4% faster); x segments as tile_config chooses them (fewest rounds
+// of 256 workgroups times the segment length plus its two warm-up planes).
 TileCfg force_tiles(const KParams& p, int seg_req)
 {
     TileCfg tc;
@@ -352,8 +353,8 @@ hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, 
         Lvl<float> a = level<float>(const_cast<void*>(src), p, true);
         Lvl<float> d = level<float>(dst, p, true);
         if (variant == 0) {
-            auto k = g1 ? k_force_fused<float, true, true, 64, true, true>
-                        : k_force_fused<float, true, true, 64, true, false>;
+            auto k = g1 ? k_force_fused<float, true, true, 64, true>
+                        : k_force_fused<float, true, true, 64, false>;
             k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, a.phic, d.phic, d.F, d.G);
         } else {
             auto k = g1 ? k_step_force<float, true, true, true> : k_step_force<float, true, true, false>;
@@ -363,8 +364,8 @@ hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, 
         Lvl<double> a = level<double>(const_cast<void*>(src), p, false);
         Lvl<double> d = level<double>(dst, p, false);
         if (variant == 0) {
-            auto k = g1 ? k_force_fused<double, false, false, 64, true, true>
-                        : k_force_fused<double, false, false, 64, true, false>;
+            auto k = g1 ? k_force_fused<double, false, false, 64, true>
+                        : k_force_fused<double, false, false, 64, false>;
             k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, a.phic, phi, d.F, d.G);
         } else {
             auto k = g1 ? k_step_force<double, false, false, true>
