@@ -101,8 +101,9 @@ typedef enum {
     LB_COUPLING_STRESS = 0, /* Pi in f^eq's second moment (default)         */
     LB_COUPLING_FORCE = 1   /* body force F = -div Pi (central differences)
                                with the half-force velocity u = (j + F/2)/rho
-                               and Guo's forcing term; runs a phi pass and
-                               a collision pass                             */
+                               and Guo's forcing term; one marching kernel
+                               per step (LB_KERNEL_FUSED), or a phi pass and
+                               a collision pass (LB_KERNEL_TWO_PASS)        */
 } lb_coupling;
 
 /* How the order parameter evolves: */
@@ -356,7 +357,10 @@ lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
  * through dense copies (lb_adjoint_export, lb_adjoint_phi0). */
 
 /* lambda_T from dphi_dev = dL/dphi_T (FP64, N): dL/df_i = 0; LB_OP_LB:
- * dL/dg_i = dphi for every i; LB_OP_FD: dL/dphi = dphi. */
+ * dL/dg_i = dphi for every i; LB_OP_FD: dL/dphi = dphi.  With tau_g = 1 the
+ * g-specific part of every later level is zero (g* = g^eq): the seed zeroes
+ * it in both adjoint buffers and the reverse steps neither read nor write
+ * it. */
 lb_status lb_adjoint_seed(lb_ctx *ctx, const double *dphi_dev);
 
 /* One reverse step: lambda_t = J(state_t)^T lambda_{t+1}, where J is the
