@@ -218,6 +218,8 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     k.nsites = int(n);
     size_t nparts = std::max<size_t>(size_t(tc.ntiles) * tc.nseg, lbk::kMaxPartialBlocks);
     if (fd) nparts = std::max<size_t>(nparts, size_t(lbk::fd_step_partial_blocks(k, p->segment_x)));
+    else if (p->coupling == LB_COUPLING_FORCE)
+        nparts = std::max<size_t>(nparts, size_t(lbk::force_sums_blocks(k, p->segment_x)));
     out->scratch_bytes = nparts * 5 * 8;
     out->adj_bytes = size_t(kAdjComponents) * stride * e;
     out->face_bytes = p->halo_x ? lbk::face_bytes(k, p->precision == LB_FP32_DEV) : 0;

@@ -98,14 +98,18 @@ __device__ __forceinline__ int wrap_any(int v, int n)
 // bit-identical); the own cell's phi goes to `phi` (the next level's phi_c
 // in FP32 mode; the caller's phi field in FP64 mode, or nowhere if it is
 // null).  Each population is read and written once per step.  G1 (omega_g
-// = 1): the collision takes g* = g^eq and loads no g.
-template <typename T, bool DEV, bool REF, int TZ, bool G1>
+// = 1): the collision takes g* = g^eq and loads no g.  SUMS: block partials
+// of [rho, phi, j + F/2] of the state stepped from go to `partials`, as
+// k_moments sums them with the force (a separate instantiation: the sums'
+// registers would otherwise make the plain step spill).
+template <typename T, bool DEV, bool REF, int TZ, bool G1, bool SUMS>
 __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg tc,
                                                              const T* __restrict__ sF,
                                                              const T* __restrict__ sG,
                                                              const double* __restrict__ sphic,
                                                              double* __restrict__ phi,
-                                                             T* __restrict__ dF, T* __restrict__ dG)
+                                                             T* __restrict__ dF, T* __restrict__ dG,
+                                                             double* __restrict__ partials)
 {
     using G = ForceTile<TZ>;
     constexpr int TY = G::TY, BZ = G::BZ, RZ = G::RZ, NR = G::RY * G::RZ;
@@ -202,6 +206,7 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
 
     // own column's Pi x row (xx, xy, xz) at planes X-1 and X, X = P-1
     double pxA[3] = {0.0, 0.0, 0.0}, pxB[3] = {0.0, 0.0, 0.0};
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int P = x0 - 1; P <= x1; P++) {
         const int X = P - 1;
         const bool collide_x = X >= x0 && valid;
@@ -284,6 +289,22 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
             double F[3];
 #pragma unroll
             for (int a = 0; a < 3; a++) F[a] = -div[a];
+            if (SUMS) {
+                double b = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+                for (int i = 0; i < NV; i++) b += double(f[i]);
+#pragma unroll
+                for (int i = 0; i < NV; i++) {
+                    jx += CX[i] * double(f[i]);
+                    jy += CY[i] * double(f[i]);
+                    jz += CZ[i] * double(f[i]);
+                }
+                acc[0] += DEV ? p.rho0 + b : b;
+                acc[1] += c;
+                acc[2] += jx + 0.5 * F[0];
+                acc[3] += jy + 0.5 * F[1];
+                acc[4] += jz + 0.5 * F[2];
+            }
             collide_force<T, DEV, REF, G1>(p, f, g, c, mu, F);
             if (phi) phi[X * plane + yg * p.nz + zg] = c;
 #pragma unroll
@@ -303,6 +324,7 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
             pxB[a] = pxP[a];
         }
     }
+    if (SUMS) block_partials<5, kForceFused>(acc, partials);
 }
 
 int force_grid(const KParams& p) { return (p.nsites + kBlock - 1) / kBlock; }
@@ -341,8 +363,15 @@ TileCfg force_tiles(const KParams& p, int seg_req)
 
 }  // namespace
 
+int force_sums_blocks(const KParams& p, int seg_req)
+{
+    const TileCfg ft = force_tiles(p, seg_req);
+    return ft.ntiles * ft.nseg;
+}
+
 hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, int variant,
-                                const void* src, void* dst, double* phi, hipStream_t s)
+                                const void* src, void* dst, double* phi, double* partials,
+                                hipStream_t s)
 {
     const TileCfg ft = force_tiles(p, tc.seg_req);
     const int nft = ft.ntiles * ft.nseg;
@@ -353,9 +382,11 @@ hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, 
         Lvl<float> a = level<float>(const_cast<void*>(src), p, true);
         Lvl<float> d = level<float>(dst, p, true);
         if (variant == 0) {
-            auto k = g1 ? k_force_fused<float, true, true, 64, true>
-                        : k_force_fused<float, true, true, 64, false>;
-            k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, a.phic, d.phic, d.F, d.G);
+            auto k = g1 ? (partials ? k_force_fused<float, true, true, 64, true, true>
+                                    : k_force_fused<float, true, true, 64, true, false>)
+                        : (partials ? k_force_fused<float, true, true, 64, false, true>
+                                    : k_force_fused<float, true, true, 64, false, false>);
+            k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, a.phic, d.phic, d.F, d.G, partials);
         } else {
             auto k = g1 ? k_step_force<float, true, true, true> : k_step_force<float, true, true, false>;
             k<<<force_grid(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phi, d.F, d.G);
@@ -364,9 +395,11 @@ hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, 
         Lvl<double> a = level<double>(const_cast<void*>(src), p, false);
         Lvl<double> d = level<double>(dst, p, false);
         if (variant == 0) {
-            auto k = g1 ? k_force_fused<double, false, false, 64, true>
-                        : k_force_fused<double, false, false, 64, false>;
-            k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, a.phic, phi, d.F, d.G);
+            auto k = g1 ? (partials ? k_force_fused<double, false, false, 64, true, true>
+                                    : k_force_fused<double, false, false, 64, true, false>)
+                        : (partials ? k_force_fused<double, false, false, 64, false, true>
+                                    : k_force_fused<double, false, false, 64, false, false>);
+            k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, a.phic, phi, d.F, d.G, partials);
         } else {
             auto k = g1 ? k_step_force<double, false, false, true>
                         : k_step_force<double, false, false, false>;

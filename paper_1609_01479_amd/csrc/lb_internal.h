@@ -86,13 +86,18 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
                        const void* src, void* dst, double* phi_work, double* partials,
                        double* sums_out, double* phi_src_out, hipStream_t s);
 // Force coupling: the forcing collision from src to dst.  variant 0: the
-// whole step in one pass over (y, z) tiles marching along x (tiling tc),
-// phi summed from the pulled g, Pi in LDS; phi of src goes to dst's phi_c
-// field (FP32 mode) or to `phi` if not null (FP64 mode).  variant 1: after
-// the phi pass, which left phi (all sites, FP64) of src in `phi`, one site
-// per thread, Pi formed at each face neighbour.  Bit-identical results.
+// whole step in one pass over (y, z) tiles marching along x (its own 8 x 64
+// tiling, segments as tc.seg_req asks), phi summed from the pulled g, Pi in
+// LDS; phi of src goes to dst's phi_c field (FP32 mode) or to `phi` if not
+// null (FP64 mode); with `partials`, the pass also leaves block partials of
+// [rho, phi, j + F/2] of src there (force_sums_blocks(p, tc.seg_req) blocks
+// of 5).  variant 1: after the phi pass, which left phi (all sites, FP64) of
+// src in `phi`, one site per thread, Pi formed at each face neighbour
+// (`partials` unused).  Bit-identical levels.
 hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, int variant,
-                                const void* src, void* dst, double* phi, hipStream_t s);
+                                const void* src, void* dst, double* phi, double* partials,
+                                hipStream_t s);
+int force_sums_blocks(const KParams& p, int seg_req);
 // phi(x) of the post-propagation state held in `state`.
 hipError_t launch_phi(const KParams& p, bool fp32, const void* state, double* phi, hipStream_t s);
 // work: the FP64 phi field the force coupling needs (`stride` long); unused

@@ -766,7 +766,8 @@ TileCfg tile_config(const KParams& p, int segment_x, bool fp32)
 
 int step_sums_blocks(const KParams& p, const TileCfg& tc, int variant)
 {
-    if (p.force || variant == 1) return reduction_grid(p);
+    if (variant == 1) return reduction_grid(p);
+    if (p.force) return force_sums_blocks(p, tc.seg_req);
     return tc.ntiles * tc.nseg;
 }
 
@@ -792,26 +793,32 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
     int nparts = 0;
     if (p.force) {
         // the two-pass variant first forms phi (the new level's phi_c in FP32
-        // mode); the single pass sums it from its own pulls
+        // mode), and with sums the moments pass (momentum sums of j + F/2
+        // from that phi); the single pass sums phi from its own pulls and
+        // leaves the block partials itself
 #define CALL                                                                                   \
     {                                                                                          \
         Lvl<T> a = level<T>(const_cast<void*>(src), p, REF);                                   \
         Lvl<T> d = level<T>(dst, p, REF);                                                      \
         double* phin = REF ? d.phic : phi64;                                                   \
-        if (sums_out) {                                                                        \
-            nparts = reduction_grid(p);                                                        \
-            k_moments<T, DEV, REF><<<nparts, kBlock, 0, s>>>(p, a.F, a.G, a.phic, nullptr,     \
-                                                             nullptr, nullptr, nullptr,        \
-                                                             partials);                        \
+        if (variant == 1) {                                                                    \
+            k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);                \
+            if (sums_out) {                                                                    \
+                nparts = reduction_grid(p);                                                    \
+                k_moments<T, DEV, REF><<<nparts, kBlock, 0, s>>>(p, a.F, a.G, a.phic, phin,    \
+                                                                 nullptr, nullptr, nullptr,    \
+                                                                 partials);                    \
+            }                                                                                  \
         }                                                                                      \
-        if (variant == 1) k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);  \
     }
         LB_DISPATCH(fp32, CALL, CALL);
 #undef CALL
+        if (variant != 1 && sums_out) nparts = force_sums_blocks(p, tc.seg_req);
         {
             hipError_t e = launch_force_collide(
                 p, tc, fp32, variant, src, dst,
-                fp32 ? level<float>(dst, p, true).phic : (variant == 1 ? phi64 : phi_src_out), s);
+                fp32 ? level<float>(dst, p, true).phic : (variant == 1 ? phi64 : phi_src_out),
+                sums_out ? partials : nullptr, s);
             if (e != hipSuccess) return e;
         }
         if (sums_out) k_sums_final<<<1, kBlock, 0, s>>>(partials, nparts, 5, sums_out, 0);

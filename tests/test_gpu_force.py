@@ -99,6 +99,31 @@ def test_force_layouts_bit_identical(layout, v):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("tau_g", [1.3, 1.0])
+@pytest.mark.parametrize("prec,kernel", [("fp64", "fused"), ("fp64", "two_pass"),
+                                         ("fp32_dev", "fused"), ("fp32_dev", "two_pass")])
+def test_force_step_sums_history(prec, kernel, tau_g):
+    """lb_step_sums with the force coupling: row t holds lb_sums of the state
+    step t starts from (momentum sums of j + F/2, F of that state), whether
+    the single pass reduces them itself or the two-pass variant runs its
+    moments pass; the step itself is bit-identical to lb_step."""
+    shape = (11, 9, 70)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=23, amp=0.3)
+    kw = dict(tau_f=0.8, tau_g=tau_g)
+    print(f"[force step sums] {prec} {kernel} tau_g={tau_g}", flush=True)
+    a = make_lb(shape, precision=prec, kernel=kernel, coupling="force", **kw)
+    a.init_phi(phi0)
+    b = make_lb(shape, precision=prec, kernel=kernel, coupling="force", **kw)
+    b.init_phi(phi0)
+    hist = a.step_sums(6).cpu().numpy()
+    for t in range(6):
+        ref = b.sums().cpu().numpy()
+        np.testing.assert_allclose(hist[t], ref, rtol=1e-13, atol=1e-13)
+        b.step(1)
+    for x, y in zip(gpu_state(a), gpu_state(b)):
+        assert np.array_equal(x, y)
+
+
 def test_force_step_sums_and_determinism():
     """Per-step FP64 sums are conserved (mass, phi; momentum to round-off), and
     two runs from one checkpoint agree bit for bit."""
