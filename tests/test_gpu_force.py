@@ -144,16 +144,18 @@ def test_force_step_sums_and_determinism():
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("tau_g", [1.3, 1.0])
 @pytest.mark.parametrize("shape", [(16, 16, 16), (9, 6, 131)])
-def test_force_fp32_storage(shape):
+def test_force_fp32_storage(shape, tau_g):
     """FP32 deviation storage of the force coupling follows the FP64 oracle to
-    FP32 rounding over 20 steps (tau != 1)."""
+    FP32 rounding over 20 steps (tau_f != 1; tau_g = 1 takes the collision
+    that loads no g)."""
     phi0 = lbinputs.spinodal_phi0(shape, seed=14, amp=0.3)
-    lb = make_lb(shape, precision="fp32_dev", coupling="force", tau_f=0.8, tau_g=1.3)
+    lb = make_lb(shape, precision="fp32_dev", coupling="force", tau_f=0.8, tau_g=tau_g)
     lb.init_phi(phi0)
     lb.step(20)
     f, g, rho, u, phi = gpu_state(lb)
-    p = oracle_params(shape, coupling=1, tau_f=0.8, tau_g=1.3)
+    p = oracle_params(shape, coupling=1, tau_f=0.8, tau_g=tau_g)
     rf, rg, rrho, ru, rphi = oracle_state(p, *oracle.run(p, *oracle.init(p, phi0), 20))
     assert np.abs(phi - rphi).max() <= 1e-6
     assert np.abs(rho - rrho).max() <= 1e-6
