@@ -87,17 +87,16 @@ __device__ __forceinline__ int wrap_any(int v, int n)
 
 // For plane P: (a) phi(P+1) into the LDS ring (its g pulled one plane
 // earlier), the pulls of the own site of plane P-1 and of the box of plane
-// P+2; (c) Pi
-// of plane P at the own site and, for the first 2 (TY + TZ) threads, at a
-// face-ring cell; (e) the forcing collision of plane P-1, whose F uses Pi of
-// planes P-2 and P (own column, registers) and of plane P-1 at the four
-// in-plane neighbours (LDS, written one plane earlier).  Planes x0-1 and x1
-// only supply the own column's Pi.  Tile cells beyond a ragged lattice edge
-// stand for the periodic images there: they form Pi but store nothing.
-// phi of the box is pulled and summed as k_phi sums it (so the values are
-// bit-identical); the own cell's phi goes to `phi` (the next level's phi_c
-// in FP32 mode; the caller's phi field in FP64 mode, or nowhere if it is
-// null).  Each population is read and written once per step.  G1 (omega_g
+// P+2; (c) Pi of plane P at the own site and, for the first 2 (TY + TZ)
+// threads, at a face-ring cell; (e) the forcing collision of plane P-1,
+// whose F uses Pi of planes P-2 and P (own column, registers) and of plane
+// P-1 at the four in-plane neighbours (LDS, written one plane earlier).
+// Planes x0-1 and x1 only supply the own column's Pi.  Tile cells beyond a
+// ragged lattice edge stand for the periodic images there: they form Pi but
+// store nothing.  phi of the box is pulled and summed as k_phi sums it (so
+// the values are bit-identical); the own cell's phi goes to `phi` (the next
+// level's phi_c in FP32 mode; the caller's phi field in FP64 mode, or
+// nowhere if it is null).  Each population is read and written once per step.  G1 (omega_g
 // = 1): the collision takes g* = g^eq and loads no g.  SUMS: block partials
 // of [rho, phi, j + F/2] of the state stepped from go to `partials`, as
 // k_moments sums them with the force (a separate instantiation: the sums'
