@@ -105,8 +105,10 @@ def time_steps(lb, steps: int, warmup: int, sums=None):
 
 
 def adjoint_ratio(shape, T, interval, precision, phi0, tgt, params, order_param="lb",
-                  coupling="stress"):
-    """(forward ms for T plain steps, backward ms incl. recompute, grads)."""
+                  coupling="stress", extra=None):
+    """(forward ms for T plain steps, backward ms incl. recompute, grads);
+    extra (a dict, optional) receives the checkpoint interval used and the
+    rollout's own forward time (the T steps, writing its checkpoints)."""
     import torch
     from paper_1609_01479_amd import LB
     from paper_1609_01479_amd.rollout import rollout
@@ -119,19 +121,26 @@ def adjoint_ratio(shape, T, interval, precision, phi0, tgt, params, order_param=
     rest = {k: params[k] for k in ("gamma", "tau_f", "tau_g", "rho0")}
     tgt_t = torch.tensor(tgt, device=dev)
 
+    info = {}
+
     def forward():
         p0 = torch.tensor(phi0, dtype=torch.float64, device=dev, requires_grad=True)
         th = [torch.tensor(params[k], dtype=torch.float64, device=dev, requires_grad=True)
               for k in ("A", "B", "kappa")]
         phiT = rollout(p0, *th, T, interval=interval, precision=precision,
-                       order_param=order_param, coupling=coupling, **rest)
+                       order_param=order_param, coupling=coupling, info=info, **rest)
         return p0, th, 0.5 * ((phiT - tgt_t) ** 2).sum()
 
     # one untimed rollout first (kernel loading, allocator), as every timed
     # region here has its warm-up
     forward()[2].backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     p0, th, loss = forward()
     torch.cuda.synchronize()
+    if extra is not None:
+        extra["interval"] = info.get("interval")
+        extra["rollout_forward_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
     t0 = time.perf_counter()
     loss.backward()
     torch.cuda.synchronize()
@@ -619,18 +628,24 @@ def main():
                 ("fd_128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "fd", "stress"),
                 ("force_64^3_fp64_T200", 64, 200, 15, "fp64", "lb", "force"),
                 ("force_128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "lb", "force"),
-                ("fd_force_128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "fd", "force")):
+                ("fd_force_128^3_fp32_T1000", 128, 1000, 32, "fp32_dev", "fd", "force"),
+                # as many checkpoints as HBM holds (at most 90% of the free
+                # memory): k = 2 for these 336 MB states, 168 GB of them
+                ("128^3_fp32_T1000_hbm_checkpoints", 128, 1000, "auto", "fp32_dev", "lb",
+                 "stress")):
             if args.adjoint_legs and name not in args.adjoint_legs.split(","):
                 continue
             sh = (nn, nn, nn)
             ph0 = lbinputs.spinodal_phi0(sh)
             tgt = lbinputs.lamellar_target(sh, 32, xi)
             log(f"adjoint {name}")
-            fwd, bwd, g = adjoint_ratio(sh, T, k, prec, ph0, tgt, params, op, cp)
+            ex = {}
+            fwd, bwd, g = adjoint_ratio(sh, T, k, prec, ph0, tgt, params, op, cp, extra=ex)
             entry = {"forward_ms": round(fwd, 2), "backward_ms": round(bwd, 2),
-                     "adjoint_over_forward": round(bwd / fwd, 3), "interval": k,
+                     "adjoint_over_forward": round(bwd / fwd, 3), "interval": ex["interval"],
+                     "rollout_forward_ms": ex["rollout_forward_ms"],
                      "order_param": op, "coupling": cp, "warmup_rollouts": 1}
-            if prec == "fp32_dev":
+            if prec == "fp32_dev" and k != "auto":
                 _, _, g64 = adjoint_ratio(sh, T, k, "fp64", ph0, tgt, params, op, cp)
                 entry["grad_rel_err_vs_fp64"] = {
                     "phi0_l2": float(np.linalg.norm(g[0] - g64[0]) / np.linalg.norm(g64[0])),

@@ -9,7 +9,11 @@ recomputes the k - 1 later states of its segment with lb_step_from (each
 written once, straight into its segment buffer), and walks the adjoint back
 through them.  Memory: ceil(T/k) + k - 1 states instead of T, plus, for the
 LB order parameter in FP64 storage, k - 1 FP64 phi fields (8 bytes per site
-each) that hand phi of each recomputed level to its reverse step.
+each) that hand phi of each recomputed level to its reverse step.  The
+forward writes each checkpoint with the step that produces it, so a small k
+costs no copies.  interval="auto" sizes k to the device's memory: on a
+288 GB MI355X the 128^3 FP32-storage rollout of 1000 steps keeps every
+second state (168 GB) instead of every 32nd.
 
 All state copies are lossless (lb_get_state / lb_set_state), and the forward
 step is deterministic, so the recomputed states are bit-identical to the
@@ -28,29 +32,82 @@ def default_interval(nsteps: int) -> int:
     return max(1, math.ceil(math.sqrt(nsteps)))
 
 
+def backward_bytes(nsteps: int, k: int, state_bytes: int, phi_bytes: int = 0) -> int:
+    """Device memory the rollout holds for its backward at checkpoint interval
+    k: ceil(T/k) checkpoints and k - 1 segment buffers of state_bytes each,
+    plus k - 1 phi fields of phi_bytes (FP64 storage of the LB order
+    parameter).  The forward holds no more: the checkpoints and at most two
+    scratch levels."""
+    k = max(1, min(int(k), nsteps))
+    return (math.ceil(nsteps / k) + k - 1) * state_bytes + (k - 1) * phi_bytes
+
+
+def interval_for_budget(nsteps: int, state_bytes: int, budget_bytes: int,
+                        phi_bytes: int = 0) -> int:
+    """The smallest checkpoint interval (fewest recomputed steps) whose
+    backward fits in budget_bytes; ValueError if none does (the memory is
+    least near k = sqrt(T))."""
+    for k in range(1, max(1, nsteps) + 1):
+        if backward_bytes(nsteps, k, state_bytes, phi_bytes) <= budget_bytes:
+            return k
+        if k > 2 * default_interval(nsteps):
+            break  # past the minimum of the memory, near sqrt(T)
+    raise ValueError(f"no checkpoint interval fits {budget_bytes} bytes "
+                     f"({nsteps} steps of {state_bytes}-byte states)")
+
+
 class _Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, phi0, A, B, kappa, cfg):
         T = int(cfg["nsteps"])
-        k = int(cfg.get("interval") or default_interval(T))
         lb = LB(phi0.shape, A=float(A), B=float(B), kappa=float(kappa),
                 gamma=cfg.get("gamma", 0.5), tau_f=cfg.get("tau_f", 1.0),
                 tau_g=cfg.get("tau_g", 1.0), rho0=cfg.get("rho0", 1.0),
                 precision=cfg.get("precision", "fp64"), adjoint=True, device=phi0.device,
                 order_param=cfg.get("order_param", "lb"), coupling=cfg.get("coupling", "stress"))
+        interval = cfg.get("interval")
+        if interval == "auto":
+            # as few recomputed steps as the memory allows: the caller's
+            # budget, else 90% of what the device has free now (including
+            # what torch's allocator holds cached, which it can hand out)
+            budget = cfg.get("memory_budget")
+            if budget is None:
+                dev = phi0.device
+                cached = torch.cuda.memory_reserved(dev) - torch.cuda.memory_allocated(dev)
+                budget = int(0.9 * (torch.cuda.mem_get_info(dev)[0] + cached))
+            phi_b = lb.nsites * 8 if (lb.sizes.elem_bytes == 8 and not lb.fd) else 0
+            k = interval_for_budget(T, int(lb.sizes.state_bytes), int(budget), phi_b)
+        else:
+            k = int(interval or default_interval(T))
         lb.init_phi(phi0.detach())
-        ckpts = []
+        # each step writes a caller buffer (lb_step_from): a segment's last
+        # step straight into the next checkpoint, its others into two scratch
+        # levels, so the checkpoints cost no copies; the rollout's final step
+        # goes to the context's own level, which phi() reads
+        ckpts = [lb.get_state()]
+        work = [lb.new_state() for _ in range(min(k - 1, 2))]
         t = 0
         while t < T:
-            ckpts.append(lb.get_state())
             n = min(k, T - t)
-            lb.step(n)
+            src = ckpts[-1]
+            for j in range(n):
+                if t + j == T - 1:
+                    lb.set_state(src)
+                    lb.step(1)
+                    break
+                dst = lb.new_state() if j == n - 1 else work[j & 1]
+                lb.step_from(src, dst)
+                src = dst
+            else:
+                ckpts.append(src)
             t += n
+        del work
         phiT = lb.phi()
         ctx.lb = lb
         ctx.ckpts = ckpts
         ctx.T = T
         ctx.k = k
+        cfg["interval_used"] = k
         return phiT
 
     @staticmethod
@@ -91,16 +148,27 @@ class _Rollout(torch.autograd.Function):
         return dphi0, dtheta[0], dtheta[1], dtheta[2], None
 
 
-def rollout(phi0: torch.Tensor, A, B, kappa, nsteps: int, *, interval: int | None = None,
-            gamma=0.5, tau_f=1.0, tau_g=1.0, rho0=1.0, precision="fp64",
-            order_param="lb", coupling="stress") -> torch.Tensor:
+def rollout(phi0: torch.Tensor, A, B, kappa, nsteps: int, *, interval: int | str | None = None,
+            memory_budget: int | None = None, gamma=0.5, tau_f=1.0, tau_g=1.0, rho0=1.0,
+            precision="fp64", order_param="lb", coupling="stress",
+            info: dict | None = None) -> torch.Tensor:
     """phi after `nsteps` steps from the state (rho0, u = 0, phi0); differentiable
     in phi0 (FP64 device tensor (nx, ny, nz)) and in A, B, kappa (tensors or
     floats).  order_param: "lb" (distribution g) or "fd" (finite-difference
-    phi field); coupling: "stress" (Pi in f^eq) or "force" (F = -div Pi)."""
+    phi field); coupling: "stress" (Pi in f^eq) or "force" (F = -div Pi).
+    interval: the checkpoint interval k (default ceil(sqrt(T))), or "auto":
+    the smallest k whose backward fits in memory_budget bytes (default 90% of
+    the device's free memory, counting what torch's allocator holds cached),
+    i.e. as many checkpoints as HBM holds and as few recomputed steps.  The gradients do not depend on k (the recomputed
+    states are bit-identical).  info (a dict, optional) receives
+    "interval", the k used."""
     dev = phi0.device
     as_t = lambda v: v if torch.is_tensor(v) else torch.tensor(float(v), dtype=torch.float64,  # noqa: E731
                                                                device=dev)
-    cfg = dict(nsteps=nsteps, interval=interval, gamma=gamma, tau_f=tau_f, tau_g=tau_g,
-               rho0=rho0, precision=precision, order_param=order_param, coupling=coupling)
-    return _Rollout.apply(phi0, as_t(A), as_t(B), as_t(kappa), cfg)
+    cfg = dict(nsteps=nsteps, interval=interval, memory_budget=memory_budget, gamma=gamma,
+               tau_f=tau_f, tau_g=tau_g, rho0=rho0, precision=precision,
+               order_param=order_param, coupling=coupling)
+    out = _Rollout.apply(phi0, as_t(A), as_t(B), as_t(kappa), cfg)
+    if info is not None:
+        info["interval"] = cfg.get("interval_used")
+    return out

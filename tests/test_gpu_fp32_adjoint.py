@@ -204,3 +204,36 @@ def test_adjoint_step_phi_bit_exact(coupling, kernel, shape):
         lb.adjoint_seed(dphi)
         with pytest.raises(LbError):
             lb.adjoint_step(s0, None, phi=ph)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_dev"])
+def test_rollout_auto_interval_fits_the_budget_and_keeps_the_gradients(prec):
+    """interval="auto" takes the smallest checkpoint interval whose backward
+    fits memory_budget; the gradients equal those of the default interval
+    bit for bit (the recomputed states are the forward's)."""
+    from paper_1609_01479_amd.rollout import backward_bytes, rollout
+    shape, T = (8, 8, 8), 20
+    pr = dict(lbinputs.SPINODAL_PARAMS)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=41)
+    tgt = lbinputs.lamellar_target(shape, 8, lbinputs.interface_width(pr["A"], pr["kappa"]))
+    probe = make_lb(shape, precision=prec, adjoint=True)
+    sb = int(probe.sizes.state_bytes)
+    phib = probe.nsites * 8 if prec == "fp64" else 0
+    del probe
+    budget = backward_bytes(T, 3, sb, phib)
+    print(f"[rollout auto] {prec} state {sb} B, budget {budget} B", flush=True)
+    dev = torch.device("cuda:0")
+    out = []
+    for interval, info in ((None, {}), ("auto", {})):
+        p0 = torch.tensor(phi0, dtype=torch.float64, device=dev, requires_grad=True)
+        th = [torch.tensor(pr[k], dtype=torch.float64, device=dev, requires_grad=True)
+              for k in ("A", "B", "kappa")]
+        phiT = rollout(p0, *th, T, interval=interval, memory_budget=budget, precision=prec,
+                       gamma=pr["gamma"], tau_f=pr["tau_f"], tau_g=pr["tau_g"], rho0=pr["rho0"],
+                       info=info)
+        loss = 0.5 * ((phiT - torch.tensor(tgt, device=dev)) ** 2).sum()
+        loss.backward()
+        out.append((info["interval"], p0.grad.cpu().numpy(), [float(t.grad) for t in th]))
+    assert out[0][0] == 5 and out[1][0] == 3
+    assert np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
