@@ -35,10 +35,11 @@ def log(msg):
 # single-pass kernel processes every site once).  The method must read and
 # write the 19 f and 19 g populations once: 76 words of the storage type,
 # 304 B (FP32 storage) or 608 B (FP64) -- the roofline's basis.  In FP32 mode
-# the stored time level also carries the FP64 reference order parameter
-# (read once, written once: 16 B), which the kernel moves on top of that.
+# the stored time level also carries the reference order parameter phi_c
+# (one 32-bit word, read once and written once: 8 B), which the kernel moves
+# on top of that.
 def step_bytes_per_site(elem_bytes: int) -> dict:
-    extra = 16 if elem_bytes == 4 else 0
+    extra = 8 if elem_bytes == 4 else 0
     return {"method_min": 76 * elem_bytes, "kernel": 76 * elem_bytes + extra}
 
 
@@ -51,7 +52,7 @@ def step_bytes_per_site(elem_bytes: int) -> dict:
 # They hold only for the kernel sources they were taken on (the hash below);
 # after any change to those sources the traffic is reported as null.
 TRAFFIC_SOURCES = ("lb_kernels.hip", "lb_device.h", "lb_internal.h")
-TRAFFIC_SHA256 = "358c260f167fbf734bd14c58fcd545258d1f83e31b0a07589f43e3e2f9638287"
+TRAFFIC_SHA256 = None
 TRAFFIC_BYTES = {"fp32_dev": 5479843961, "fp64": 10367339415}
 
 
@@ -195,7 +196,7 @@ def footprint_sweep(args):
     streaming copy (read B, write B) and the single-pass step and its
     memory-only twin (read one time level, write the other) on droplet
     lattices of growing size.  GB/s count the kernels' own bytes (FP32
-    storage: 320 B per site with phi_c; FP64: 608)."""
+    storage: 312 B per site with phi_c; FP64: 608)."""
     import torch
 
     import lbinputs
@@ -205,7 +206,7 @@ def footprint_sweep(args):
     xi = lbinputs.interface_width(params["A"], params["kappa"])
     steps = max(args.steps, 20)
     out = {"metric": "bandwidth against footprint", "copy": [], "lattice": []}
-    for gb in (0.25, 0.5, 1.0, 2.0, 2.68, 4.0, 8.0):
+    for gb in (0.25, 0.5, 1.0, 2.0, 2.62, 4.0, 8.0):
         nbytes = int(gb * 1e9)
         log(f"copy probe {gb} GB")
         out["copy"].append({"read_GB": gb, "footprint_GB": 2 * gb,
@@ -457,11 +458,11 @@ def main():
     # force coupling (body force -div Pi) on the same 256^3 droplet: one
     # marching kernel per step (phi from its own pulls), f and g read and
     # written once: the method's 608 B per site in FP64 and 304 in FP32
-    # storage (the kernel's own 320 with its FP64 reference field phi_c)
+    # storage (the kernel's own 312 with its reference field phi_c)
     if args.force_steps > 0:
         out["force_coupling"] = {}
         force_phi = {}
-        for prec, minimum, kbytes in (("fp32_dev", 304, 320), ("fp64", 608, 608)):
+        for prec, minimum, kbytes in (("fp32_dev", 304, 312), ("fp64", 608, 608)):
             lb = LB(shape, precision=prec, coupling="force", device="cuda:0", **lay, **params)
             lb.init_phi(phi0)
             log(f"{prec} force coupling {shape}: {args.force_steps} steps")
@@ -608,8 +609,8 @@ def main():
         out["fp64"]["roofline"]["kernel_frac_of_copy_probe"] = round(
             out["fp64"]["roofline"]["achieved_kernel_bytes_GBps"] / probe, 4)
     # the same copy at the footprint of the FP32 step (read one time level,
-    # write another: 2 x 320/2 B per site)
-    probe_fp = copy_probe_gbps(160 * nsites, reps=10)
+    # write another: 2 x 312/2 B per site)
+    probe_fp = copy_probe_gbps(156 * nsites, reps=10)
     out["copy_probe_same_footprint_GBps"] = round(probe_fp, 1)
     out["roofline"]["kernel_frac_of_copy_probe_same_footprint"] = round(
         out["roofline"]["achieved_kernel_bytes_GBps"] / probe_fp, 4)

@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 4
+#define LB_ABI_VERSION 5
 #define LB_NVEL 19
 
 typedef enum {
@@ -75,10 +75,12 @@ typedef enum {
     LB_FP64 = 0,    /* distributions stored and collided in FP64            */
     LB_FP32_DEV = 1 /* FP32 storage of deviations and FP32 collision:
                        f_i - w_i rho0, and g_i - r_i phi_c, where phi_c is
-                       the FP64 order parameter of the last collision at
-                       the site the population moves TO (r_i phi = the
-                       order-parameter equilibrium at rest with mu = 0);
-                       FP64 phi, reductions and parameter gradients          */
+                       the order parameter of the last collision at the
+                       site the population moves TO, truncated to the high
+                       32-bit word of its binary64 encoding and stored as
+                       that word (r_i phi = the order-parameter equilibrium
+                       at rest with mu = 0); FP64 phi, reductions and
+                       parameter gradients                                   */
 } lb_precision;
 
 typedef enum {
@@ -178,7 +180,7 @@ typedef struct {
     size_t elem_bytes;        /* 8 (LB_FP64) or 4 (LB_FP32_DEV)                         */
     size_t stride_elems;      /* padded elements per component of a distribution        */
     size_t state_bytes;       /* one time level: f, g (2*19*stride elements) and, in
-                                 LB_FP32_DEV, phi_c (stride FP64 values); LB_OP_FD:
+                                 LB_FP32_DEV, phi_c (stride 32-bit words); LB_OP_FD:
                                  f (19*stride elements), then phi (stride FP64)        */
     size_t phi_bytes;         /* FP64 work fields of stride values each: phi;
                                  LB_OP_FD: mu, u_x, u_y, u_z                           */
@@ -284,9 +286,8 @@ lb_status lb_step_from(lb_ctx *ctx, const void *src_dev, void *dst_dev);
 /* lb_step_from that also stores phi of src_dev in phi_dev (device, N FP64
  * values in dense (x, y, z) order, 256-byte aligned), as the step forms it
  * (bit-identical to the phi lb_adjoint_step would form), for
- * lb_adjoint_step_phi.  LB_FP64 with LB_OP_LB only (LB_EINVAL otherwise: FP32
- * storage keeps phi of the previous level in each level, see
- * lb_adjoint_step_next; LB_OP_FD holds phi in the level).  Passage: none
+ * lb_adjoint_step_phi.  LB_OP_LB only (LB_EINVAL otherwise: LB_OP_FD holds
+ * phi in the level).  Passage: none
  * beyond lb_step_from's (a project extension for the reverse mode). */
 lb_status lb_step_from_phi(lb_ctx *ctx, const void *src_dev, void *dst_dev, double *phi_dev);
 
@@ -321,9 +322,9 @@ lb_status lb_set_state(lb_ctx *ctx, const void *src_dev);
 lb_status lb_export_dist(lb_ctx *ctx, double *f_dev, double *g_dev);
 
 /* Set the current state from dense FP64 post-propagation distributions
- * (19, nx, ny, nz).  In LB_FP32_DEV phi_c(x) becomes sum_i g_i(x) and the
- * values are rounded to FP32 after subtracting w_i rho0 from f_i and
- * r_i phi_c(x) from g_i(x).  LB_OP_FD: g_dev must be NULL and only f is set
+ * (19, nx, ny, nz).  In LB_FP32_DEV phi_c(x) becomes sum_i g_i(x) (truncated
+ * as above) and the values are rounded to FP32 after subtracting w_i rho0
+ * from f_i and r_i phi_c(x) from g_i(x).  LB_OP_FD: g_dev must be NULL and only f is set
  * (the phi field keeps its values).  Passage: Sec. 3.2.3, Fig. 2
  * (copyToTarget), dense in, internal layout (Sec. 3.1) stored. */
 lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
@@ -340,7 +341,7 @@ lb_status lb_import_dist(lb_ctx *ctx, const double *f_dev, const double *g_dev);
  * parameter:
  *   lb_adjoint_seed(dL/dphi_T)  then, for t = T-1 .. 0,
  *   lb_adjoint_step(state_t)    (state_t as saved by lb_get_state at time t;
- *                                or lb_adjoint_step_next with level t+1 too)
+ *                                or lb_adjoint_step_phi with its phi too)
  * and lb_adjoint_phi0 gives dL/dphi0.  Requires adj[0], adj[1] and
  * adj_scratch (LB_ESTATE otherwise); covers both couplings and both
  * order-parameter schemes.  With LB_OP_FD the level holds dL/df_i and
@@ -369,20 +370,10 @@ lb_status lb_adjoint_seed(lb_ctx *ctx, const double *dphi_dev);
  * [dL/dA, dL/dB, dL/dkappa]; it may be NULL. */
 lb_status lb_adjoint_step(lb_ctx *ctx, const void *state_t_dev, double *dtheta3_dev);
 
-/* lb_adjoint_step with the level that one step from state_t produced
- * (state_next_dev, as saved by lb_get_state or written by lb_step_from; may be
- * NULL).  In LB_FP32_DEV that level's reference field holds phi of state_t,
- * bit-identical to what the step would recompute, so the phi pass is skipped;
- * LB_FP64 and LB_OP_FD (whose level holds phi) ignore it.  The result is identical to lb_adjoint_step's only if
- * state_next_dev really is that level.  LB_EINVAL if it equals state_t_dev,
- * LB_EALIGN if it is not 256-byte aligned. */
-lb_status lb_adjoint_step_next(lb_ctx *ctx, const void *state_t_dev, const void *state_next_dev,
-                               double *dtheta3_dev);
-
 /* lb_adjoint_step with phi of state_t_dev given (phi_t_dev, as stored by
  * lb_step_from_phi from state_t_dev), so that no phi pass runs; the result
  * is identical to lb_adjoint_step's only if phi_t_dev really is that field.
- * LB_FP64 with LB_OP_LB only (LB_EINVAL otherwise). */
+ * LB_OP_LB only (LB_EINVAL otherwise: LB_OP_FD holds phi in the level). */
 lb_status lb_adjoint_step_phi(lb_ctx *ctx, const void *state_t_dev, const double *phi_t_dev,
                               double *dtheta3_dev);
 
@@ -414,7 +405,7 @@ lb_status lb_adjoint_export(lb_ctx *ctx, double *df_dev, double *dg_dev);
  * populations moving across it, f and g of the boundary plane, the g that
  * form phi at the neighbour's boundary plane (its stencil neighbour) and,
  * in LB_FP32_DEV, that plane's phi_c: 24 * ny * nz values of the storage
- * type (+ ny * nz FP64), face_bytes bytes; the layout is internal and the
+ * type (+ ny * nz 32-bit words), face_bytes bytes; the layout is internal and the
  * buffers are opaque.  A shard that receives its own faces (recv_lo =
  * send_hi, recv_hi = send_lo) steps exactly like the periodic lattice of
  * the same extents, bit for bit.  Buffers are device memory of face_bytes,

@@ -16,13 +16,13 @@ NVEL = 19
 LB_OK, LB_EINVAL, LB_ESHAPE, LB_EALIGN, LB_EHIP, LB_ESTATE = range(6)
 LB_FP64, LB_FP32_DEV = 0, 1
 LB_KERNEL_FUSED, LB_KERNEL_TWO_PASS, LB_KERNEL_STREAM = 0, 1, 2
-ABI_VERSION = 4
+ABI_VERSION = 5
 NOALLOC_MAX_PARTIALS = 4096  # LB_NOALLOC_MAX_PARTIALS
 
 # Every symbol include/lb.h declares.
 EXPORTS = ("lb_abi_version", "lb_query_sizes", "lb_create", "lb_destroy", "lb_set_stream",
            "lb_init_phi", "lb_step", "lb_step_sums", "lb_step_sums_noalloc", "lb_step_from", "lb_step_from_phi", "lb_moments", "lb_sums", "lb_get_state", "lb_set_state",
-           "lb_export_dist", "lb_import_dist", "lb_adjoint_seed", "lb_adjoint_step", "lb_adjoint_step_next",
+           "lb_export_dist", "lb_import_dist", "lb_adjoint_seed", "lb_adjoint_step",
            "lb_adjoint_step_phi", "lb_adjoint_phi0", "lb_adjoint_export", "lb_pack_faces",
            "lb_unpack_faces", "lb_copy_probe",
            "lb_status_string", "lb_last_error")
@@ -92,7 +92,6 @@ def lib():
         "lb_import_dist": ([vp, dp, dp], ctypes.c_int),
         "lb_adjoint_seed": ([vp, dp], ctypes.c_int),
         "lb_adjoint_step": ([vp, vp, dp], ctypes.c_int),
-        "lb_adjoint_step_next": ([vp, vp, vp, dp], ctypes.c_int),
         "lb_adjoint_step_phi": ([vp, vp, dp, dp], ctypes.c_int),
         "lb_adjoint_phi0": ([vp, dp], ctypes.c_int),
         "lb_adjoint_export": ([vp, dp, dp], ctypes.c_int),

@@ -571,18 +571,13 @@ hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, void* other, 
 }
 
 hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
-                           const void* state_next, const double* phi_given, double* phi,
+                           const double* phi_given, double* phi,
                            const void* adj_next, void* adj_prev, void* adj_scratch,
                            double* partials, double* dtheta, hipStream_t s)
 {
     if (phi_given) {
         // phi of state stored by the step that made its successor
         phi = const_cast<double*>(phi_given);
-    } else if (fp32 && state_next) {
-        // the step that made state_next stored phi(state) as its reference
-        // field (bit-identical to launch_phi's sum)
-        phi = const_cast<double*>(reinterpret_cast<const double*>(
-            static_cast<const float*>(state_next) + size_t(2 * NV) * p.stride));
     } else {
         hipError_t e = launch_phi(p, fp32, state, phi, s);
         if (e != hipSuccess) return e;

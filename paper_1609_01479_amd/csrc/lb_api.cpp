@@ -204,8 +204,8 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
         out->state_bytes = LB_NVEL * stride * e + stride * 8;
         out->phi_bytes = 4 * stride * 8;
     } else {
-        // f and g, plus the FP64 reference order parameter in FP32 mode
-        out->state_bytes = 2 * LB_NVEL * stride * e + (p->precision == LB_FP32_DEV ? stride * 8 : 0);
+        // f and g, plus the 32-bit reference order parameter in FP32 mode
+        out->state_bytes = 2 * LB_NVEL * stride * e + (p->precision == LB_FP32_DEV ? stride * 4 : 0);
         // FP64 work field: phi
         out->phi_bytes = stride * 8;
     }
@@ -372,9 +372,9 @@ lb_status lb_step_from_phi(lb_ctx* ctx, const void* src_dev, void* dst_dev, doub
 {
     if (!ctx || !phi_dev) return fail(LB_EINVAL, "ctx and phi_dev are required");
     if (ctx->kp.xh) return fail(LB_ESTATE, "lb_step_from_phi is not available on a shard");
-    if (ctx->fp32 || ctx->kp.fd)
-        return fail(LB_EINVAL, "lb_step_from_phi is for LB_FP64 with LB_OP_LB (FP32 storage "
-                               "keeps phi in the next level; LB_OP_FD in the level itself)");
+    if (ctx->kp.fd)
+        return fail(LB_EINVAL, "lb_step_from_phi is for LB_OP_LB (LB_OP_FD holds phi in the "
+                               "level itself)");
     if (!aligned(phi_dev)) return fail(LB_EALIGN, "phi_dev is not 256-byte aligned");
     if (!src_dev || !dst_dev) return fail(LB_EINVAL, "src_dev and dst_dev are required");
     if (src_dev == dst_dev) return fail(LB_EINVAL, "src_dev and dst_dev must differ");
@@ -473,32 +473,25 @@ lb_status lb_adjoint_seed(lb_ctx* ctx, const double* dphi_dev)
     return e == hipSuccess ? LB_OK : hip_fail(e, "lb_adjoint_seed");
 }
 
+static lb_status adjoint_step(lb_ctx* ctx, const void* state_t_dev, const double* phi_t_dev,
+                              double* dtheta3_dev);
+
 lb_status lb_adjoint_step(lb_ctx* ctx, const void* state_t_dev, double* dtheta3_dev)
 {
-    return lb_adjoint_step_next(ctx, state_t_dev, nullptr, dtheta3_dev);
-}
-
-static lb_status adjoint_step(lb_ctx* ctx, const void* state_t_dev, const void* state_next_dev,
-                              const double* phi_t_dev, double* dtheta3_dev);
-
-lb_status lb_adjoint_step_next(lb_ctx* ctx, const void* state_t_dev, const void* state_next_dev,
-                               double* dtheta3_dev)
-{
-    return adjoint_step(ctx, state_t_dev, state_next_dev, nullptr, dtheta3_dev);
+    return adjoint_step(ctx, state_t_dev, nullptr, dtheta3_dev);
 }
 
 lb_status lb_adjoint_step_phi(lb_ctx* ctx, const void* state_t_dev, const double* phi_t_dev,
                               double* dtheta3_dev)
 {
     if (!ctx || !phi_t_dev) return fail(LB_EINVAL, "ctx and phi_t_dev are required");
-    if (ctx->fp32 || ctx->kp.fd)
-        return fail(LB_EINVAL, "lb_adjoint_step_phi is for LB_FP64 with LB_OP_LB");
+    if (ctx->kp.fd) return fail(LB_EINVAL, "lb_adjoint_step_phi is for LB_OP_LB");
     if (!aligned(phi_t_dev)) return fail(LB_EALIGN, "phi_t_dev is not 256-byte aligned");
-    return adjoint_step(ctx, state_t_dev, nullptr, phi_t_dev, dtheta3_dev);
+    return adjoint_step(ctx, state_t_dev, phi_t_dev, dtheta3_dev);
 }
 
-static lb_status adjoint_step(lb_ctx* ctx, const void* state_t_dev, const void* state_next_dev,
-                              const double* phi_t_dev, double* dtheta3_dev)
+static lb_status adjoint_step(lb_ctx* ctx, const void* state_t_dev, const double* phi_t_dev,
+                              double* dtheta3_dev)
 {
     if (!ctx || !state_t_dev) return fail(LB_EINVAL, "ctx and state_t_dev are required");
     if (!ctx->has_adj) return fail(LB_ESTATE, "context was created without adjoint buffers");
@@ -506,19 +499,15 @@ static lb_status adjoint_step(lb_ctx* ctx, const void* state_t_dev, const void* 
         return fail(LB_ESTATE, "LB_KERNEL_STREAM (free streaming) has no reverse mode");
     if (ctx->kp.xh) return fail(LB_ESTATE, "x-slab shards have no reverse mode");
     if (!aligned(state_t_dev)) return fail(LB_EALIGN, "state_t_dev is not 256-byte aligned");
-    if (state_next_dev && !aligned(state_next_dev))
-        return fail(LB_EALIGN, "state_next_dev is not 256-byte aligned");
-    if (state_next_dev == state_t_dev)
-        return fail(LB_EINVAL, "state_next_dev must be the level after state_t_dev");
     double* part = static_cast<double*>(ctx->b.scratch);
-    // FD scheme: phi is part of the level, so state_next is not needed
+    // FD scheme: phi is part of the level
     hipError_t e =
         ctx->kp.fd ? lbk::launch_fd_adj_step(ctx->kp, ctx->fp32, state_t_dev,
                                              static_cast<double*>(ctx->b.phi),
                                              ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
                                              ctx->b.adj_scratch, part, dtheta3_dev, ctx->stream)
-                   : lbk::launch_adj_step(ctx->kp, ctx->fp32, state_t_dev, state_next_dev,
-                                          phi_t_dev, static_cast<double*>(ctx->b.phi),
+                   : lbk::launch_adj_step(ctx->kp, ctx->fp32, state_t_dev, phi_t_dev,
+                                          static_cast<double*>(ctx->b.phi),
                                           ctx->b.adj[ctx->adj_cur], ctx->b.adj[1 - ctx->adj_cur],
                                           ctx->b.adj_scratch, part, dtheta3_dev, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "lb_adjoint_step");

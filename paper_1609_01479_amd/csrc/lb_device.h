@@ -9,7 +9,8 @@
 //   FP32 mode  (T = float,  DEV = REF = true):
 //       F_i(y) = f*_i(y) - w_i rho0                          (FP32)
 //       G_i(y) = g*_i(y) - r_i phi_c(y + c_i)                (FP32)
-//       phi_c(x) = the order parameter of x's last collision (FP64)
+//       phi_c(x) = the order parameter of x's last collision with the low
+//                  32 bits of its binary64 encoding cleared      (32 bits)
 //   with r_i = w_i (1 - 3/2 (|c_i|^2 - 1)) = (5/6, 1/18, -1/72): r_i phi is
 //   the order-parameter equilibrium of a fluid at rest with mu = 0 and
 //   sum_i r_i = 1.  Each stored g deviation is referenced to the order
@@ -17,10 +18,14 @@
 //   own phi_c:  g_i(x) = G_i(x - c_i) + r_i phi_c(x),
 //   phi(x) = phi_c(x) + sum_i G_i(x - c_i).  Both stored deviations are small
 //   in the bulk phases, so FP32 rounding does not accumulate into the O(1)
-//   order parameter.
+//   order parameter.  The reference need not be phi itself, only a value
+//   writer and reader share exactly: phi truncated to its high word (20
+//   mantissa bits, stored as that word) leaves at most 2^-20 |phi| in the
+//   deviations, whose FP32 rounding then stays ~2^-44 |phi|, and halves the
+//   reference's traffic against an FP64 phi_c.
 // Post-propagation values at x are the pull  f_i(x) = f*_i(x - c_i).
-// Memory layout of F and G: didx() below; phi_c is one value per site in
-// site order (x*ny + y)*nz + z.
+// Memory layout of F and G: didx() below; phi_c is one 32-bit word per site
+// in site order (x*ny + y)*nz + z.
 #pragma once
 
 #include "lb_internal.h"
@@ -86,6 +91,13 @@ __device__ __forceinline__ int phic_site(const KParams& p, int x, int y, int z)
     return site_of(p, x + (p.xh >> 1), y, z);
 }
 
+// phi_c as stored (the high word of phi's binary64 encoding) and as used
+// (that word with a zero low word); phic_round(phi) is the reference the
+// store of phi_c(x) = phic_word(phi(x)) stands for.
+__device__ __forceinline__ unsigned phic_word(double phi) { return unsigned(__double2hiint(phi)); }
+__device__ __forceinline__ double phic_value(unsigned w) { return __hiloint2double(int(w), 0); }
+__device__ __forceinline__ double phic_round(double phi) { return phic_value(phic_word(phi)); }
+
 __device__ __forceinline__ int minus_c(int c, int v, int vm, int vp) { return c > 0 ? vm : (c < 0 ? vp : v); }
 __device__ __forceinline__ int plus_c(int c, int v, int vm, int vp) { return c > 0 ? vp : (c < 0 ? vm : v); }
 
@@ -147,10 +159,10 @@ __device__ __forceinline__ unsigned dist_own(const KParams& p, const Geo& q, int
 // everywhere.
 template <typename T, bool REF>
 __device__ __forceinline__ double pull_g(const KParams& p, const Geo& q, const T* __restrict__ G,
-                                         const double* __restrict__ phic, double* d)
+                                         const unsigned* __restrict__ phic, double* d)
 {
     double acc = 0.0;
-    const double pc = REF ? phic[phic_site(p, q.x, q.y, q.z)] : 0.0;
+    const double pc = REF ? phic_value(phic[phic_site(p, q.x, q.y, q.z)]) : 0.0;
 #pragma unroll
     for (int i = 0; i < NV; i++) {
         const double gv = double(G[dist_pull(p, q, i)]);
@@ -162,7 +174,7 @@ __device__ __forceinline__ double pull_g(const KParams& p, const Geo& q, const T
 
 template <typename T, bool REF>
 __device__ __forceinline__ double phi_at(const KParams& p, const Geo& q, const T* __restrict__ G,
-                                         const double* __restrict__ phic)
+                                         const unsigned* __restrict__ phic)
 {
     return pull_g<T, REF>(p, q, G, phic, nullptr);
 }
@@ -176,12 +188,13 @@ __device__ __forceinline__ T pre_collision_dev(int i, T G, double dphi)
 }
 
 // FP32 mode: the stored value of direction i at y from the collided
-// deviation h* = g* - r_i phi(y) and the order parameter at y and at the
-// destination y + c_i:  G_i(y) = h* + r_i (phi(y) - phi(y + c_i)).
+// deviation h* = g* - r_i phi(y), the order parameter at y and that at the
+// destination y + c_i, whose reference the store at y + c_i forms alike:
+// G_i(y) = h* + r_i (phi(y) - phi_c(y + c_i)).
 template <typename T>
 __device__ __forceinline__ T to_dest_ref(int i, T hstar, double phi_here, double phi_dest)
 {
-    return T(__builtin_fma(rweight(i), phi_here - phi_dest, double(hstar)));
+    return T(__builtin_fma(rweight(i), phi_here - phic_round(phi_dest), double(hstar)));
 }
 
 // ---------------------------------------------------------------------------

@@ -28,12 +28,11 @@ using namespace dev;
 namespace {
 
 // The force-coupling collision and propagation, one site per thread; phi of
-// the source level (all sites) comes from k_phi.  In FP32 mode phi is the
-// destination level's phi_c field (as in k_step_2s).
+// the source level (all sites) comes from k_phi.
 template <typename T, bool DEV, bool REF, bool G1>
 __global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const T* __restrict__ sF,
                                                        const T* __restrict__ sG,
-                                                       const double* __restrict__ sphic,
+                                                       const unsigned* __restrict__ sphic,
                                                        const double* __restrict__ phi,
                                                        T* __restrict__ dF, T* __restrict__ dG)
 {
@@ -52,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_step_force(KParams p, const T* __res
                      + (phi[site_of(p, q.x, q.y, q.zp)] + phi[site_of(p, q.x, q.y, q.zm)] - 2.0 * c);
     const double mu = p.A * c + p.B * c * c * c - p.kappa * lap;
     if (REF && !G1) {
-        const double dphi = c - sphic[s];
+        const double dphi = c - phic_value(sphic[phic_site(p, q.x, q.y, q.z)]);
 #pragma unroll
         for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, g[i], dphi);
     }
@@ -94,10 +93,10 @@ __device__ __forceinline__ int wrap_any(int v, int n)
 // Planes x0-1 and x1 only supply the own column's Pi.  Tile cells beyond a
 // ragged lattice edge stand for the periodic images there: they form Pi but
 // store nothing.  phi of the box is pulled and summed as k_phi sums it (so
-// the values are bit-identical); the own cell's phi goes to `phi` (the next
-// level's phi_c in FP32 mode; the caller's phi field in FP64 mode, or
-// nowhere if it is null).  Each population is read and written once per step.  G1 (omega_g
-// = 1): the collision takes g* = g^eq and loads no g.  SUMS: block partials
+// the values are bit-identical); the own cell's phi goes to the next
+// level's phi_c (FP32 mode) and to the caller's phi field `phi_out` if that
+// is not null.  Each population is read and written once per step.  G1
+// (omega_g = 1): the collision takes g* = g^eq and loads no g.  SUMS: block partials
 // of [rho, phi, j + F/2] of the state stepped from go to `partials`, as
 // k_moments sums them with the force (a separate instantiation: the sums'
 // registers would otherwise make the plain step spill).
@@ -105,8 +104,9 @@ template <typename T, bool DEV, bool REF, int TZ, bool G1, bool SUMS>
 __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg tc,
                                                              const T* __restrict__ sF,
                                                              const T* __restrict__ sG,
-                                                             const double* __restrict__ sphic,
-                                                             double* __restrict__ phi,
+                                                             const unsigned* __restrict__ sphic,
+                                                             unsigned* __restrict__ dphic,
+                                                             double* __restrict__ phi_out,
                                                              T* __restrict__ dF, T* __restrict__ dG,
                                                              double* __restrict__ partials)
 {
@@ -152,11 +152,12 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
     const int rro = (rly + 1) * RZ + (rlz + 1);
 
     // the box of plane xp in flight: with FP32 storage the pulled g and phi_c
-    // of each box cell, summed when stored; FP64 storage sums its pulls at
-    // once (carrying them would take 76 more VGPRs)
+    // word of each box cell, summed when stored; FP64 storage sums its pulls
+    // at once (carrying them would take 76 more VGPRs)
     constexpr bool CARRY = std::is_same<T, float>::value;
     struct BoxLoads {
-        double v[G::BOXPT];
+        double v[CARRY ? 1 : G::BOXPT];
+        unsigned w[CARRY ? G::BOXPT : 1];
         T g[CARRY ? G::BOXPT : 1][NV];
     };
     // phi_at's sum: the pulled values in index order, then phi_c
@@ -175,13 +176,12 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
             T g[NV];
 #pragma unroll
             for (int i = 0; i < NV; i++) g[i] = sG[dist_pull(p, q, i)];
-            const double pc = REF ? sphic[xw * plane + boff[k]] : 0.0;
             if constexpr (CARRY) {
 #pragma unroll
                 for (int i = 0; i < NV; i++) b.g[k][i] = g[i];
-                b.v[k] = pc;
+                b.w[k] = sphic[xw * plane + boff[k]];
             } else {
-                b.v[k] = sum_g(g, pc);
+                b.v[k] = sum_g(g, 0.0);
             }
         }
     };
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
         for (int k = 0; k < G::BOXPT; k++) {
             if (boff[k] < 0) continue;
             if constexpr (CARRY)
-                dst[bcell[k]] = sum_g(b.g[k], b.v[k]);
+                dst[bcell[k]] = sum_g(b.g[k], phic_value(b.w[k]));
             else
                 dst[bcell[k]] = b.v[k];
         }
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
         // (a)
         store_box(P + 1, pre);
         T f[NV], g[NV];
-        double pc_src = 0.0;
+        unsigned pc_src = 0;
         const Geo q = geo_xyz(p, wrap_any(X, p.nx), yg, zg);
         if (collide_x) {
 #pragma unroll
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
                              + (xc[bo + 1] + xc[bo - 1] - 2.0 * c);
             const double mu = p.A * c + p.B * c * c * c - p.kappa * lap;
             if (REF && !G1) {
-                const double dphi = c - pc_src;
+                const double dphi = c - phic_value(pc_src);
 #pragma unroll
                 for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, g[i], dphi);
             }
@@ -305,7 +305,8 @@ __global__ __launch_bounds__(kForceFused) void k_force_fused(KParams p, TileCfg 
                 acc[4] += jz + 0.5 * F[2];
             }
             collide_force<T, DEV, REF, G1>(p, f, g, c, mu, F);
-            if (phi) phi[X * plane + yg * p.nz + zg] = c;
+            if (REF) dphic[X * plane + yg * p.nz + zg] = phic_word(c);
+            if (phi_out) phi_out[X * plane + yg * p.nz + zg] = c;
 #pragma unroll
             for (int i = 0; i < NV; i++) {
                 __builtin_nontemporal_store(f[i], &dF[dist_own(p, q, i)]);
@@ -385,7 +386,7 @@ hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, 
                                     : k_force_fused<float, true, true, 64, true, false>)
                         : (partials ? k_force_fused<float, true, true, 64, false, true>
                                     : k_force_fused<float, true, true, 64, false, false>);
-            k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, a.phic, d.phic, d.F, d.G, partials);
+            k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, a.phic, d.phic, phi, d.F, d.G, partials);
         } else {
             auto k = g1 ? k_step_force<float, true, true, true> : k_step_force<float, true, true, false>;
             k<<<force_grid(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phi, d.F, d.G);
@@ -398,7 +399,8 @@ hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, 
                                     : k_force_fused<double, false, false, 64, true, false>)
                         : (partials ? k_force_fused<double, false, false, 64, false, true>
                                     : k_force_fused<double, false, false, 64, false, false>);
-            k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, a.phic, phi, d.F, d.G, partials);
+            k<<<nft, kForceFused, 0, s>>>(p, ft, a.F, a.G, nullptr, nullptr, phi, d.F, d.G,
+                                          partials);
         } else {
             auto k = g1 ? k_step_force<double, false, false, true>
                         : k_step_force<double, false, false, false>;

@@ -11,8 +11,8 @@
 // c_x = +1 at plane -2 and, with FP32 storage, phi_c of plane -1.  (The g
 // with c_x = -1 come from plane 0, the shard's own.)  Mirror images above.
 // One face buffer carries exactly that, 24 component planes of ny*nz values
-// of the storage type in site order y*nz + z, then (FP32 storage) the phi_c
-// plane in FP64:
+// of the storage type in site order y*nz + z, then (FP32 storage) the plane
+// of phi_c words:
 //   slots 0..4    f_i with c_x = s of the boundary plane
 //   slots 5..18   g_i with c_x in {0, s} of the boundary plane
 //   slots 19..23  g_i with c_x = s of the plane behind it (one further in)
@@ -56,7 +56,7 @@ __device__ __forceinline__ int face_comp(int k, int s, bool* is_f, bool* behind)
 // pack = false: level <- buffer (into halo planes xb and xb - s).
 template <typename T, bool REF>
 __global__ __launch_bounds__(kBlock) void k_face(KParams p, T* __restrict__ F, T* __restrict__ G,
-                                                 double* __restrict__ phic, T* __restrict__ buf,
+                                                 unsigned* __restrict__ phic, T* __restrict__ buf,
                                                  int s, int xb, int pack)
 {
     const int a = p.ny * p.nz;
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_face(KParams p, T* __restrict__ F, T
     const int y = yz / p.nz, z = yz - y * p.nz;
     if (k == kFaceSlots) {
         if (!REF) return;
-        double* pb = reinterpret_cast<double*>(buf + size_t(kFaceSlots) * a);
+        unsigned* pb = reinterpret_cast<unsigned*>(buf + size_t(kFaceSlots) * a);
         const int c = phic_site(p, xb, y, z);
         if (pack) pb[yz] = phic[c];
         else phic[c] = pb[yz];
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_face(KParams p, T* __restrict__ F, T
 size_t face_bytes(const KParams& p, bool fp32)
 {
     const size_t a = size_t(p.ny) * p.nz;
-    const size_t b = kFaceSlots * a * (fp32 ? 4 : 8) + (fp32 ? a * 8 : 0);
+    const size_t b = fp32 ? (kFaceSlots + 1) * a * 4 : kFaceSlots * a * 8;
     return (b + 255) / 256 * 256;
 }
 

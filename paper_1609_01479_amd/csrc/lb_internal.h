@@ -39,12 +39,13 @@ struct TileCfg {
 };
 
 // A time level's regions (LB order parameter): F and G of 19*stride
-// elements of T each and, in FP32 mode, phi_c (stride FP64 values).
+// elements of T each and, in FP32 mode, phi_c (stride 32-bit words: the high
+// word of each site's reference order parameter, see lb_device.h).
 template <typename T>
 struct Lvl {
     T* F;
     T* G;
-    double* phic;  // FP32 mode only
+    unsigned* phic;  // FP32 mode only
 };
 
 template <typename T>
@@ -54,7 +55,7 @@ inline Lvl<T> level(void* state, const KParams& p, bool ref)
     Lvl<T> l;
     l.F = base;
     l.G = base + size_t(NV) * p.stride;
-    l.phic = ref ? reinterpret_cast<double*>(base + size_t(2 * NV) * p.stride) : nullptr;
+    l.phic = ref ? reinterpret_cast<unsigned*>(base + size_t(2 * NV) * p.stride) : nullptr;
     return l;
 }
 
@@ -67,19 +68,17 @@ void set_layout(KParams& k, int layout, int aosoa_len);
 // All launchers enqueue on `s` and return hipGetLastError().
 // `fp32` selects the FP32 deviation-storage instantiation; otherwise FP64.
 // A time level (`state`) is an F region and a G region of 19*stride elements
-// each (laid out per KParams) and, in FP32 mode, phi_c[stride] (FP64, site
-// order).  Order-parameter fields (`phi`) are FP64.
+// each (laid out per KParams) and, in FP32 mode, phi_c[stride] (32-bit
+// words, site order).  Order-parameter fields (`phi`) are FP64.
 hipError_t launch_init(const KParams& p, bool fp32, void* state, const double* phi0, hipStream_t s);
-// variant 0: single-pass fused step; 1: phi pass + collision pass.  The force
-// coupling always runs a phi pass and a collision pass (Pi formed on the fly
-// at the face neighbours), with phi in phi_work (FP64 mode; FP32 mode writes
-// the new level's phi_c).
+// variant 0: single-pass fused step; 1: phi pass (phi into phi_work, and in
+// FP32 mode the new level's phi_c) + collision pass.
 // If sums_out is non-null, also writes the 5 FP64 conserved sums
 // [rho, phi, jx, jy, jz] of the source level to sums_out, through block
 // partials in `partials` (at least 5 * max(tc.ntiles * tc.nseg,
 // kMaxPartialBlocks) doubles).
-// phi_src_out (FP64 mode, may be null): also store phi of src there (N
-// FP64 values in site order, bit-identical to launch_phi's).
+// phi_src_out (may be null): also store phi of src there (N FP64 values in
+// site order, bit-identical to launch_phi's).
 // The number of partial blocks the LB-scheme step of `variant` reduces over.
 int step_sums_blocks(const KParams& p, const TileCfg& tc, int variant);
 hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int variant,
@@ -88,12 +87,12 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
 // Force coupling: the forcing collision from src to dst.  variant 0: the
 // whole step in one pass over (y, z) tiles marching along x (its own 8 x 64
 // tiling, segments as tc.seg_req asks), phi summed from the pulled g, Pi in
-// LDS; phi of src goes to dst's phi_c field (FP32 mode) or to `phi` if not
-// null (FP64 mode); with `partials`, the pass also leaves block partials of
+// LDS; phi of src goes to dst's phi_c field (FP32 mode) and to `phi` if not
+// null; with `partials`, the pass also leaves block partials of
 // [rho, phi, j + F/2] of src there (force_sums_blocks(p, tc.seg_req) blocks
 // of 5).  variant 1: after the phi pass, which left phi (all sites, FP64) of
-// src in `phi`, one site per thread, Pi formed at each face neighbour
-// (`partials` unused).  Bit-identical levels.
+// src in `phi` and dst's phi_c, one site per thread, Pi formed at each face
+// neighbour (`partials` unused).  Bit-identical levels.
 hipError_t launch_force_collide(const KParams& p, const TileCfg& tc, bool fp32, int variant,
                                 const void* src, void* dst, double* phi, double* partials,
                                 hipStream_t s);
@@ -117,8 +116,6 @@ hipError_t launch_import(const KParams& p, bool fp32, void* state, const double*
 // whose lg is zeroed too when tau_g = 1 (the steps then never touch lg).
 hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, void* other, const double* dphi,
                            hipStream_t s);
-// state_next (may be null): the level one step after `state`; in FP32 mode
-// its reference field is phi of `state`, so the phi pass is skipped.
 // dtheta (may be null): FP64[3] incremented by the step's d/d(A, B, kappa),
 // reduced from block partials in `partials` (3 * 1024 doubles; 6 * 1024
 // with the force coupling).  The force coupling needs 8 components of
@@ -126,7 +123,7 @@ hipError_t launch_adj_seed(const KParams& p, bool fp32, void* adj, void* other, 
 // phi_given (may be null): phi of `state` (N FP64 values in site order), so
 // that no phi pass is needed.
 hipError_t launch_adj_step(const KParams& p, bool fp32, const void* state,
-                           const void* state_next, const double* phi_given, double* phi,
+                           const double* phi_given, double* phi,
                            const void* adj_next, void* adj_prev, void* adj_scratch,
                            double* partials, double* dtheta, hipStream_t s);
 // lp of adj_prev from the stencil cotangents in adj_scratch (a, b_x, b_y,

@@ -41,12 +41,12 @@ static_assert(2 * 64 + 2 * (kFused / 64) + 4 <= kFused, "halo ring larger than t
 // ---------------------------------------------------------------------------
 
 // Post-propagation state rho = rho0, u = 0, g_0 = phi0, g_{i>0} = 0.  In FP32
-// mode phi_c = phi0, and the stored deviation of direction i at y is
-// g_i(y + c_i) - r_i phi0(y + c_i).  In an x-slab shard phi0 also holds the
-// planes -1 and nx (the neighbours'), first and last.
+// mode phi_c is phi0's reference, and the stored deviation of direction i at
+// y is g_i(y + c_i) - r_i phi_c(y + c_i).  In an x-slab shard phi0 also holds
+// the planes -1 and nx (the neighbours'), first and last.
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_init(KParams p, T* __restrict__ F, T* __restrict__ G,
-                                                 double* __restrict__ phic,
+                                                 unsigned* __restrict__ phic,
                                                  const double* __restrict__ phi0)
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
@@ -59,23 +59,28 @@ __global__ __launch_bounds__(kBlock) void k_init(KParams p, T* __restrict__ F, T
         F[d] = DEV ? T(0) : T(weight(i) * p.rho0);
         if (REF) {
             const double pd = ph[push_site(p, q, i)];
-            G[d] = T((i == 0 ? pd : 0.0) - rweight(i) * pd);
+            G[d] = T((i == 0 ? pd : 0.0) - rweight(i) * phic_round(pd));
         } else {
             G[d] = i == 0 ? T(ph[s]) : T(0);
         }
     }
-    if (REF) phic[phic_site(p, q.x, q.y, q.z)] = ph[s];
+    if (REF) phic[phic_site(p, q.x, q.y, q.z)] = phic_word(ph[s]);
 }
 
-// phi(x) = sum_i g_i(x) of the post-propagation state (FP64).
+// phi(x) = sum_i g_i(x) of the post-propagation state (FP64); with dphic
+// (FP32 mode) also the reference field phi_c of the level a step makes.
 template <typename T, bool REF>
 __global__ __launch_bounds__(kBlock) void k_phi(KParams p, const T* __restrict__ G,
-                                                const double* __restrict__ phic,
-                                                double* __restrict__ phi)
+                                                const unsigned* __restrict__ phic,
+                                                double* __restrict__ phi,
+                                                unsigned* __restrict__ dphic)
 {
     const int s = xcd_block() * kBlock + threadIdx.x;
     if (s >= p.nsites) return;
-    phi[s] = phi_at<T, REF>(p, geo_of(p, s), G, phic);
+    const Geo q = geo_of(p, s);
+    const double v = phi_at<T, REF>(p, q, G, phic);
+    phi[s] = v;
+    if (REF && dphic) dphic[phic_site(p, q.x, q.y, q.z)] = phic_word(v);
 }
 
 // Two-pass variant, second pass: stencil + chemical stress + collision, one
@@ -84,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_phi(KParams p, const T* __restrict__
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_step_2s(KParams p, const T* __restrict__ sF,
                                                     const T* __restrict__ sG,
-                                                    const double* __restrict__ sphic,
+                                                    const unsigned* __restrict__ sphic,
                                                     const double* __restrict__ phi,
                                                     T* __restrict__ dF, T* __restrict__ dG)
 {
@@ -102,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_step_2s(KParams p, const T* __restri
                                phi[site_of(p, q.x, q.yp, q.z)], phi[site_of(p, q.x, q.ym, q.z)],
                                phi[site_of(p, q.x, q.y, q.zp)], phi[site_of(p, q.x, q.y, q.zm)]);
     if (REF) {
-        const double dphi = c - sphic[s];
+        const double dphi = c - phic_value(sphic[phic_site(p, q.x, q.y, q.z)]);
 #pragma unroll
         for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, g[i], dphi);
     }
@@ -120,6 +125,12 @@ __global__ __launch_bounds__(kBlock) void k_step_2s(KParams p, const T* __restri
 __device__ __forceinline__ float vcopy(float v)
 {
     float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v) : "memory");
+    return r;
+}
+__device__ __forceinline__ unsigned vcopy(unsigned v)
+{
+    unsigned r;
     asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v) : "memory");
     return r;
 }
@@ -195,8 +206,8 @@ __device__ __forceinline__ Yz9 yz9(const KParams& p, int y, int z)
 // z-shifted pulls and the halo columns share with the z-neighbouring tile,
 // and the halo rows shared with y-neighbours, are fetched into the same L2.
 //
-// FP32 mode: the pull of a site needs only its own phi_c (one FP64 load per
-// site); the store of direction i needs phi at the destination y + c_i, which
+// FP32 mode: the pull of a site needs only its own phi_c (one 32-bit load
+// per site); the store of direction i needs phi at the destination y + c_i, which
 // the LDS phi ring already holds (its halo then includes the tile's 4 corner
 // cells, for the directions with c_x = 0 and c_y, c_z != 0).
 // COLL = false is the kernel's memory-only twin (LB_KERNEL_STREAM): every
@@ -206,9 +217,10 @@ template <typename T, bool DEV, bool REF, bool SMALL, bool PIPE, int TZ, bool CO
 __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg& tc,
                                                 const T* __restrict__ sF,
                                                 const T* __restrict__ sG,
-                                                const double* __restrict__ sphic,
+                                                const unsigned* __restrict__ sphic,
                                                 T* __restrict__ dF, T* __restrict__ dG,
-                                                double* __restrict__ dphic,
+                                                unsigned* __restrict__ dphic,
+                                                double* __restrict__ phi_out,
                                                 double* __restrict__ partials)
 {
     constexpr int TY = kFused / TZ;
@@ -274,9 +286,9 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     auto pbase = [&](int X) { return O(xf(X)) * planeb; };
     auto pcbase = [&](int X) { return unsigned(xc(X) * plane); };
     // pull of plane X for a site with row offsets yz and in-plane index
-    // `site`: kept values into kv[] and the site's phi_c into *pc (if
+    // `site`: kept values into kv[] and the site's phi_c word into *pc (if
     // non-null); returns phi
-    auto pull_phi = [&](int X, const Yz9& yz, unsigned site, K* kv, double* pc)
+    auto pull_phi = [&](int X, const Yz9& yz, unsigned site, K* kv, unsigned* pc)
                         __attribute__((always_inline)) -> double {
         const O pb[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
         double acc = 0.0;
@@ -287,9 +299,9 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
             acc += double(v);
         }
         if (REF) {
-            const double c = sphic[pcbase(X) + site];
-            if (pc) *pc = c;
-            return c + acc;
+            const unsigned w = sphic[pcbase(X) + site];
+            if (pc) *pc = w;
+            return phic_value(w) + acc;
         }
         return acc;
     };
@@ -299,8 +311,8 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
 
     // collision of this thread's site at plane x and the stores of its new
     // values, from the pulled f[], the kept g values kc[] (and the site's
-    // phi_c pcc), with phi of planes x-1, x, x+1 in LDS slots sp, sc, sn
-    auto update = [&](int x, T* f, const K* kc, double pcc, int sp, int sc, int sn)
+    // phi_c word pcc), with phi of planes x-1, x, x+1 in LDS slots sp, sc, sn
+    auto update = [&](int x, T* f, const K* kc, unsigned pcc, int sp, int sc, int sn)
                       __attribute__((always_inline)) {
         const int psl[3] = {sp, sc, sn};
         const double c = ph[sc][ly + 1][lz + 1];
@@ -309,7 +321,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
                                    ph[sc][ly + 1][lz + 2], ph[sc][ly + 1][lz]);
         T g[NV];
         if (REF) {
-            const double dphi = c - pcc;
+            const double dphi = c - phic_value(pcc);
 #pragma unroll
             for (int i = 0; i < NV; i++) g[i] = pre_collision_dev(i, T(kc[i]), dphi);
         } else {
@@ -344,9 +356,10 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
                              : g[i];
             stc<SMALL>(dG, pso, i, compb, so, gi);
         }
-        // FP32: the new level's reference field; FP64: phi of the source
-        // level, if asked for (dphic non-null)
-        if (REF || dphic) dphic[pcbase(x) + rowsite] = c;
+        // FP32: the new level's reference field; phi of the source level,
+        // if asked for
+        if (REF) dphic[pcbase(x) + rowsite] = phic_word(c);
+        if (phi_out) phi_out[unsigned(x * plane) + rowsite] = c;
     };
 
     // Software-pipelined march (full tiles): the loads of plane x+2's g
@@ -372,7 +385,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
 
         T fq[NV], fc[NV];
         K gq[NV], rq[NV], kn[NV], kcur[NV];
-        double pq = 0.0, rpq = 0.0, pcn = 0.0, pccur = 0.0;
+        unsigned pq = 0, rpq = 0, pcn = 0, pccur = 0;
         // g and phi_c of plane X+1 (interior, ring); f(X)
         auto issue = [&](int X) __attribute__((always_inline)) {
             const O pf[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
@@ -415,10 +428,10 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
             double a = 0.0, b = 0.0;
 #pragma unroll
             for (int i = 0; i < NV; i++) a += double(gq[i]);
-            ph[sn][ly + 1][lz + 1] = REF ? pq + a : a;
+            ph[sn][ly + 1][lz + 1] = REF ? phic_value(pq) + a : a;
 #pragma unroll
             for (int i = 0; i < NV; i++) b += double(rq[i]);
-            ph[sn][qly][qlz] = REF ? rpq + b : b;
+            ph[sn][qly][qlz] = REF ? phic_value(rpq) + b : b;
             lds_barrier();
 #pragma unroll
             for (int i = 0; i < NV; i++) {
@@ -442,7 +455,7 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
         // 1% of the memory-only twin.
         K kcur[NV], knext[NV];
         __shared__ K kst[NV][kFused];
-        double pccur = 0.0, pcnext = 0.0;
+        unsigned pccur = 0, pcnext = 0;
         // warm-up: phi at planes x0-1 (slot 0) and x0 (slot 1), keeping
         // plane x0's populations
         if (active) ph[0][ly + 1][lz + 1] = pull_phi(x0 - 1, row, rowsite, nullptr, nullptr);
@@ -485,21 +498,21 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
 template <bool SMALL, int TZ, bool COLL>
 __global__ __launch_bounds__(kFused) void k_step_fused_f32(
     KParams p, TileCfg tc, const float* __restrict__ sF, const float* __restrict__ sG,
-    const double* __restrict__ sphic, float* __restrict__ dF, float* __restrict__ dG,
-    double* __restrict__ dphic, double* __restrict__ partials)
+    const unsigned* __restrict__ sphic, float* __restrict__ dF, float* __restrict__ dG,
+    unsigned* __restrict__ dphic, double* __restrict__ phi_out, double* __restrict__ partials)
 {
     step_fused_body<float, true, true, SMALL, true, TZ, COLL>(p, tc, sF, sG, sphic, dF, dG, dphic,
-                                                              partials);
+                                                              phi_out, partials);
 }
 
 template <bool SMALL, int TZ, bool COLL>
 __global__ __launch_bounds__(kFused) void k_step_fused_f64(
     KParams p, TileCfg tc, const double* __restrict__ sF, const double* __restrict__ sG,
-    const double* __restrict__ sphic, double* __restrict__ dF, double* __restrict__ dG,
-    double* __restrict__ dphic, double* __restrict__ partials)
+    const unsigned* __restrict__ sphic, double* __restrict__ dF, double* __restrict__ dG,
+    unsigned* __restrict__ dphic, double* __restrict__ phi_out, double* __restrict__ partials)
 {
     step_fused_body<double, false, false, SMALL, false, TZ, COLL>(p, tc, sF, sG, sphic, dF, dG,
-                                                                  dphic, partials);
+                                                                  dphic, phi_out, partials);
 }
 
 // the single-pass kernel (or, coll = false, its free-streaming twin) for an
@@ -543,7 +556,7 @@ struct Fused<double> {
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_moments(KParams p, const T* __restrict__ F,
                                                     const T* __restrict__ G,
-                                                    const double* __restrict__ phic,
+                                                    const unsigned* __restrict__ phic,
                                                     const double* __restrict__ fphi,
                                                     double* __restrict__ rho_out,
                                                     double* __restrict__ u_out,
@@ -603,7 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_sums_final(const double* __restrict_
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_export(KParams p, const T* __restrict__ F,
                                                    const T* __restrict__ G,
-                                                   const double* __restrict__ phic,
+                                                   const unsigned* __restrict__ phic,
                                                    double* __restrict__ f, double* __restrict__ g)
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
@@ -622,9 +635,9 @@ __global__ __launch_bounds__(kBlock) void k_export(KParams p, const T* __restric
     }
 }
 
-// FP32 mode, first half of an import: the reference phi_c(x) = sum_i g_i(x)
-// of the dense post-propagation input.
-__global__ __launch_bounds__(kBlock) void k_import_ref(KParams p, double* __restrict__ phic,
+// FP32 mode, first half of an import: the reference phi_c(x) of
+// phi(x) = sum_i g_i(x) of the dense post-propagation input.
+__global__ __launch_bounds__(kBlock) void k_import_ref(KParams p, unsigned* __restrict__ phic,
                                                        const double* __restrict__ g)
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
@@ -632,14 +645,14 @@ __global__ __launch_bounds__(kBlock) void k_import_ref(KParams p, double* __rest
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < NV; i++) acc += g[(long long)i * p.nsites + s];
-    phic[s] = acc;
+    phic[s] = phic_word(acc);
 }
 
 // The stored value of direction i at y is the post-propagation value at
 // y + c_i (FP32 mode: minus w_i rho0 for f, minus r_i phi_c(y + c_i) for g).
 template <typename T, bool DEV, bool REF>
 __global__ __launch_bounds__(kBlock) void k_import(KParams p, T* __restrict__ F, T* __restrict__ G,
-                                                   const double* __restrict__ phic,
+                                                   const unsigned* __restrict__ phic,
                                                    const double* __restrict__ f,
                                                    const double* __restrict__ g)
 {
@@ -651,7 +664,7 @@ __global__ __launch_bounds__(kBlock) void k_import(KParams p, T* __restrict__ F,
         const int d = push_site(p, q, i);
         const long long n = d + (long long)i * p.nsites;
         F[dist_own(p, q, i)] = T(f[n] - (DEV ? weight(i) * p.rho0 : 0.0));
-        G[dist_own(p, q, i)] = T(REF ? g[n] - rweight(i) * phic[d] : g[n]);
+        G[dist_own(p, q, i)] = T(REF ? g[n] - rweight(i) * phic_value(phic[d]) : g[n]);
     }
 }
 
@@ -787,25 +800,24 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
                        const void* src, void* dst, double* phi_work, double* partials,
                        double* sums_out, double* phi_src_out, hipStream_t s)
 {
-    // FP64 mode: phi of src goes to phi_src_out if given (the work field
-    // otherwise, where a pass needs one)
+    // phi of src goes to phi_src_out if given (the work field otherwise,
+    // where a pass needs one)
     double* phi64 = phi_src_out ? phi_src_out : phi_work;
     int nparts = 0;
     if (p.force) {
-        // the two-pass variant first forms phi (the new level's phi_c in FP32
-        // mode), and with sums the moments pass (momentum sums of j + F/2
-        // from that phi); the single pass sums phi from its own pulls and
-        // leaves the block partials itself
+        // the two-pass variant first forms phi (and in FP32 mode the new
+        // level's phi_c), and with sums the moments pass (momentum sums of
+        // j + F/2 from that phi); the single pass sums phi from its own pulls
+        // and leaves the block partials itself
 #define CALL                                                                                   \
     {                                                                                          \
         Lvl<T> a = level<T>(const_cast<void*>(src), p, REF);                                   \
         Lvl<T> d = level<T>(dst, p, REF);                                                      \
-        double* phin = REF ? d.phic : phi64;                                                   \
         if (variant == 1) {                                                                    \
-            k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);                \
+            k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phi64, d.phic);       \
             if (sums_out) {                                                                    \
                 nparts = reduction_grid(p);                                                    \
-                k_moments<T, DEV, REF><<<nparts, kBlock, 0, s>>>(p, a.F, a.G, a.phic, phin,    \
+                k_moments<T, DEV, REF><<<nparts, kBlock, 0, s>>>(p, a.F, a.G, a.phic, phi64,   \
                                                                  nullptr, nullptr, nullptr,    \
                                                                  partials);                    \
             }                                                                                  \
@@ -815,10 +827,9 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
 #undef CALL
         if (variant != 1 && sums_out) nparts = force_sums_blocks(p, tc.seg_req);
         {
-            hipError_t e = launch_force_collide(
-                p, tc, fp32, variant, src, dst,
-                fp32 ? level<float>(dst, p, true).phic : (variant == 1 ? phi64 : phi_src_out),
-                sums_out ? partials : nullptr, s);
+            hipError_t e = launch_force_collide(p, tc, fp32, variant, src, dst,
+                                                variant == 1 ? phi64 : phi_src_out,
+                                                sums_out ? partials : nullptr, s);
             if (e != hipSuccess) return e;
         }
         if (sums_out) k_sums_final<<<1, kBlock, 0, s>>>(partials, nparts, 5, sums_out, 0);
@@ -831,9 +842,8 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
         if (variant != 1) {                                                                     \
             nparts = tc.ntiles * tc.nseg;                                                       \
             auto kern = Fused<T>::get(small_arrays(p, sizeof(T)), tc.tz, variant == 0);        \
-            kern<<<nparts, kFused, 0, s>>>(p, tc, a.F, a.G, a.phic, d.F, d.G,                   \
-                                           REF ? d.phic : phi_src_out,                          \
-                                           sums_out ? partials : nullptr);                      \
+            kern<<<nparts, kFused, 0, s>>>(p, tc, a.F, a.G, a.phic, d.F, d.G, d.phic,           \
+                                           phi_src_out, sums_out ? partials : nullptr);         \
         } else {                                                                                \
             if (sums_out) {                                                                     \
                 nparts = reduction_grid(p);                                                     \
@@ -841,9 +851,8 @@ hipError_t launch_step(const KParams& p, const TileCfg& tc, bool fp32, int varia
                                                                  nullptr, nullptr, nullptr,     \
                                                                  partials);                     \
             }                                                                                   \
-            double* phin = REF ? d.phic : phi64;                                                \
-            k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phin);                 \
-            k_step_2s<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phin,    \
+            k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phi64, d.phic);        \
+            k_step_2s<T, DEV, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.F, a.G, a.phic, phi64,   \
                                                                   d.F, d.G);                    \
         }                                                                                       \
     }
@@ -858,7 +867,7 @@ hipError_t launch_phi(const KParams& p, bool fp32, const void* state, double* ph
 #define CALL                                                                              \
     {                                                                                     \
         Lvl<T> a = level<T>(const_cast<void*>(state), p, REF);                            \
-        k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phi);                \
+        k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, phi, nullptr);       \
     }
     LB_DISPATCH(fp32, CALL, CALL);
 #undef CALL
@@ -878,7 +887,7 @@ hipError_t launch_moments(const KParams& p, bool fp32, const void* state, double
 #define CALL                                                                                  \
     {                                                                                         \
         Lvl<T> a = level<T>(const_cast<void*>(state), p, REF);                                \
-        k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, work);                   \
+        k_phi<T, REF><<<grid_for(p), kBlock, 0, s>>>(p, a.G, a.phic, work, nullptr);          \
     }
         LB_DISPATCH(fp32, CALL, CALL);
 #undef CALL

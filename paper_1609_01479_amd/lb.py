@@ -210,7 +210,7 @@ class LB:
     def step_from(self, src: torch.Tensor, dst: torch.Tensor,
                   phi_out: torch.Tensor | None = None) -> None:
         """One step from the time level in `src` into `dst` (caller buffers);
-        phi_out (FP64 storage, LB order parameter): an FP64 device tensor of
+        phi_out (LB order parameter): an FP64 device tensor of
         the lattice's shape that receives phi of `src`, for adjoint_step."""
         for t in (src, dst):
             if t.numel() * t.element_size() != self.sizes.state_bytes:
@@ -284,19 +284,15 @@ class LB:
         t.record_stream(self.stream)
 
     def adjoint_step(self, state_t: torch.Tensor, dtheta: torch.Tensor | None = None,
-                     next_state: torch.Tensor | None = None,
                      phi: torch.Tensor | None = None) -> None:
-        """One reverse step at state_t; next_state, the level one step later,
-        lets FP32 storage skip recomputing phi (lb_adjoint_step_next); phi,
-        phi of state_t from step_from(..., phi_out=), does the same in FP64
+        """One reverse step at state_t; phi, phi of state_t from
+        step_from(..., phi_out=), spares the step its phi pass
         (lb_adjoint_step_phi)."""
         if phi is not None:
             self._check_phi(phi)
             self._call("lb_adjoint_step_phi", _ptr(state_t), _ptr(phi), _ptr(dtheta))
-        elif next_state is None:
-            self._call("lb_adjoint_step", _ptr(state_t), _ptr(dtheta))
         else:
-            self._call("lb_adjoint_step_next", _ptr(state_t), _ptr(next_state), _ptr(dtheta))
+            self._call("lb_adjoint_step", _ptr(state_t), _ptr(dtheta))
 
     def adjoint_dist(self):
         """(dL/df, dL/dg) of the current adjoint level as FP64 (19, nx, ny, nz)

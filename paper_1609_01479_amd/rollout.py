@@ -8,12 +8,13 @@ by default); the backward takes each checkpoint in reverse order,
 recomputes the k - 1 later states of its segment with lb_step_from (each
 written once, straight into its segment buffer), and walks the adjoint back
 through them.  Memory: ceil(T/k) + k - 1 states instead of T, plus, for the
-LB order parameter in FP64 storage, k - 1 FP64 phi fields (8 bytes per site
-each) that hand phi of each recomputed level to its reverse step.  The
-forward writes each checkpoint with the step that produces it, so a small k
-costs no copies.  interval="auto" sizes k to the device's memory: on a
-288 GB MI355X the 128^3 FP32-storage rollout of 1000 steps keeps every
-second state (168 GB) instead of every 32nd.
+LB order parameter, FP64 phi fields (8 bytes per site each) that hand phi of
+each level to its reverse step, so that none runs a phi pass: k - 1 for the
+recomputed levels, and one per segment for its last level, stored by the
+forward step that leaves it.  The forward writes each checkpoint with the
+step that produces it, so a small k costs no copies.  interval="auto" sizes k
+to the device's memory: on a 288 GB MI355X the 128^3 FP32-storage rollout of
+1000 steps keeps every second state instead of every 32nd.
 
 All state copies are lossless (lb_get_state / lb_set_state), and the forward
 step is deterministic, so the recomputed states are bit-identical to the
@@ -33,13 +34,14 @@ def default_interval(nsteps: int) -> int:
 
 
 def backward_bytes(nsteps: int, k: int, state_bytes: int, phi_bytes: int = 0) -> int:
-    """Device memory the rollout holds for its backward at checkpoint interval
-    k: ceil(T/k) checkpoints and k - 1 segment buffers of state_bytes each,
-    plus k - 1 phi fields of phi_bytes (FP64 storage of the LB order
-    parameter).  The forward holds no more: the checkpoints and at most two
-    scratch levels."""
+    """Device memory the rollout holds at checkpoint interval k, at its
+    peak: ceil(T/k) checkpoints, and k - 1 segment buffers (backward) or two
+    scratch levels (forward), of state_bytes each; ceil(T/k) + k - 1 phi
+    fields of phi_bytes (the LB order parameter's: one per segment from the
+    forward, one per recomputed level)."""
     k = max(1, min(int(k), nsteps))
-    return (math.ceil(nsteps / k) + k - 1) * state_bytes + (k - 1) * phi_bytes
+    c = math.ceil(nsteps / k)
+    return (c + max(k - 1, 2)) * state_bytes + (c + k - 1) * phi_bytes
 
 
 def interval_for_budget(nsteps: int, state_bytes: int, budget_bytes: int,
@@ -66,6 +68,9 @@ class _Rollout(torch.autograd.Function):
                 precision=cfg.get("precision", "fp64"), adjoint=True, device=phi0.device,
                 order_param=cfg.get("order_param", "lb"), coupling=cfg.get("coupling", "stress"))
         interval = cfg.get("interval")
+        # phi fields of the LB order parameter (the finite-difference level
+        # holds phi itself)
+        phi_b = 0 if lb.fd else lb.nsites * 8
         if interval == "auto":
             # as few recomputed steps as the memory allows: the caller's
             # budget, else 90% of what the device has free now (including
@@ -75,36 +80,47 @@ class _Rollout(torch.autograd.Function):
                 dev = phi0.device
                 cached = torch.cuda.memory_reserved(dev) - torch.cuda.memory_allocated(dev)
                 budget = int(0.9 * (torch.cuda.mem_get_info(dev)[0] + cached))
-            phi_b = lb.nsites * 8 if (lb.sizes.elem_bytes == 8 and not lb.fd) else 0
             k = interval_for_budget(T, int(lb.sizes.state_bytes), int(budget), phi_b)
         else:
             k = int(interval or default_interval(T))
         lb.init_phi(phi0.detach())
         # each step writes a caller buffer (lb_step_from): a segment's last
         # step straight into the next checkpoint, its others into two scratch
-        # levels, so the checkpoints cost no copies; the rollout's final step
-        # goes to the context's own level, which phi() reads
+        # levels, so the checkpoints cost no copies; the rollout's final
+        # step goes to a scratch level that becomes the context's, which
+        # phi() reads.  The last step of each segment also stores phi of the
+        # level it leaves (lb_step_from_phi), which that level's reverse step
+        # needs and no recomputation forms.
         ckpts = [lb.get_state()]
-        work = [lb.new_state() for _ in range(min(k - 1, 2))]
+        ends = []
+        work = [lb.new_state(), lb.new_state()] if T > 0 else []
         t = 0
         while t < T:
             n = min(k, T - t)
             src = ckpts[-1]
             for j in range(n):
+                ph = None
+                if j == n - 1 and phi_b:
+                    ph = torch.empty(lb.shape, dtype=torch.float64, device=lb.device)
+                    ends.append(ph)
                 if t + j == T - 1:
-                    lb.set_state(src)
-                    lb.step(1)
-                    break
-                dst = lb.new_state() if j == n - 1 else work[j & 1]
-                lb.step_from(src, dst)
+                    dst = work[1] if src is work[0] else work[0]
+                elif j == n - 1:
+                    dst = lb.new_state()
+                else:
+                    dst = work[j & 1]
+                lb.step_from(src, dst, phi_out=ph)
                 src = dst
-            else:
+            if t + n < T:
                 ckpts.append(src)
             t += n
+        if T > 0:
+            lb.set_state(src)
         del work
         phiT = lb.phi()
         ctx.lb = lb
         ctx.ckpts = ckpts
+        ctx.ends = ends
         ctx.T = T
         ctx.k = k
         cfg["interval_used"] = k
@@ -112,39 +128,36 @@ class _Rollout(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gphi):
-        lb, ckpts, T, k = ctx.lb, ctx.ckpts, ctx.T, ctx.k
+        lb, ckpts, ends, T, k = ctx.lb, ctx.ckpts, ctx.ends, ctx.T, ctx.k
         dtheta = torch.zeros(3, dtype=torch.float64, device=lb.device)
         lb.adjoint_seed(gphi.detach())
         # segment buffers: the checkpoint itself is the segment's first state;
         # the others are recomputed in place by one step each (no copies)
         seg = [None] + [lb.new_state() for _ in range(min(k, T) - 1)]
-        # FP64 storage of the LB order parameter: the recomputing steps also
-        # store phi of each level they start from, so the reverse steps of
-        # those levels skip their phi pass (FP32 storage finds it in the
-        # next level; the finite-difference level holds phi)
+        # LB order parameter: the recomputing steps also store phi of each
+        # level they start from, and the forward stored phi of each segment's
+        # last level, so no reverse step runs a phi pass (the
+        # finite-difference level holds phi)
         phis = None
-        if lb.sizes.elem_bytes == 8 and not lb.fd:
+        if not lb.fd:
             phis = [torch.empty(lb.shape, dtype=torch.float64, device=lb.device)
                     for _ in range(min(k, T) - 1)]
-        for si in reversed(range(len(ckpts))):
+        for si in reversed(range(len(ckpts) if T > 0 else 0)):
             t0 = si * k
             t1 = min(T, t0 + k)
             seg[0] = ckpts[si]
             for j in range(1, t1 - t0):
                 lb.step_from(seg[j - 1], seg[j], phi_out=phis[j - 1] if phis else None)
             for t in reversed(range(t0, t1)):
-                # level t+1: the next buffer of this segment, else the next
-                # segment's checkpoint (none after the last step)
                 if t + 1 < t1:
-                    nxt = seg[t + 1 - t0]
                     phi = phis[t - t0] if phis else None
                 else:
-                    nxt = ckpts[si + 1] if si + 1 < len(ckpts) else None
-                    phi = None
-                lb.adjoint_step(seg[t - t0], dtheta, next_state=nxt, phi=phi)
+                    phi = ends[si] if ends else None
+                lb.adjoint_step(seg[t - t0], dtheta, phi=phi)
         dphi0 = lb.adjoint_phi0()
         ctx.lb = None
         ctx.ckpts = None
+        ctx.ends = None
         return dphi0, dtheta[0], dtheta[1], dtheta[2], None
 
 

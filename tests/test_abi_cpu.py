@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(abi):
     L = abi.lib()
     for name in _declared_functions():
         assert hasattr(L, name), name
-    assert L.lb_abi_version() == abi.ABI_VERSION == 4
+    assert L.lb_abi_version() == abi.ABI_VERSION == 5
 
 
 def _params(abi, **kw):
@@ -57,8 +57,8 @@ def test_query_sizes(abi):
     assert s.state_bytes == 2 * 19 * s.stride_elems * 8
     st, s32 = _query(abi, nx=16, ny=16, nz=16, precision=abi.LB_FP32_DEV)
     assert st == abi.LB_OK and s32.elem_bytes == 4
-    # FP32: f and g in FP32 plus the FP64 reference order parameter
-    assert s32.state_bytes == 2 * 19 * s32.stride_elems * 4 + s32.stride_elems * 8
+    # FP32: f and g in FP32 plus the 32-bit words of the reference order parameter
+    assert s32.state_bytes == 2 * 19 * s32.stride_elems * 4 + s32.stride_elems * 4
     assert s32.phi_bytes == s32.stride_elems * 8
 
 
@@ -194,29 +194,40 @@ def test_step_sums_noalloc_validates_without_launching(abi):
         L.lb_destroy(ctx)
 
 
-def test_adjoint_step_next_validates_without_launching(abi):
-    """lb_adjoint_step_next rejects a missing adjoint, a successor equal to
-    state_t and a misaligned successor before any HIP call."""
+@pytest.mark.parametrize("prec", [0, 1])
+def test_phi_taking_calls_validate_without_launching(abi, prec):
+    """lb_step_from_phi and lb_adjoint_step_phi (either storage) reject a
+    missing context, phi field or adjoint, misaligned pointers, equal levels
+    and the finite-difference scheme before any HIP call."""
     L = abi.lib()
-    p = _params(abi)
-    ctx = ctypes.c_void_p()
-    b = abi.LbBuffers()
-    b.state[0], b.state[1], b.phi, b.scratch = 0x1000, 0x2000, 0x3000, 0x4000
-    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
-    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000),
-                                  None) == abi.LB_ESTATE
-    L.lb_destroy(ctx)
-    b.adj[0], b.adj[1], b.adj_scratch = 0x5000, 0x6000, 0x7000
-    assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
-    assert L.lb_adjoint_step_next(None, ctypes.c_void_p(0x1000), None, None) == abi.LB_EINVAL
-    assert L.lb_adjoint_step_next(ctx, None, ctypes.c_void_p(0x2000), None) == abi.LB_EINVAL
-    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000),
-                                  None) == abi.LB_EINVAL
-    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2010),
-                                  None) == abi.LB_EALIGN
-    assert L.lb_adjoint_step_next(ctx, ctypes.c_void_p(0x1010), ctypes.c_void_p(0x2000),
-                                  None) == abi.LB_EALIGN
-    L.lb_destroy(ctx)
+    a1, a2, bad = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x2010)
+    phi = ctypes.c_void_p(0x3000)
+    for fd in (0, 1):
+        p = _params(abi, precision=prec, order_param=fd)
+        ctx = ctypes.c_void_p()
+        b = abi.LbBuffers()
+        b.state[0], b.state[1], b.phi, b.scratch = 0x1000, 0x2000, 0x3000, 0x4000
+        assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
+        if fd:
+            assert L.lb_step_from_phi(ctx, a1, a2, phi) == abi.LB_EINVAL
+            assert L.lb_adjoint_step_phi(ctx, a1, phi, None) == abi.LB_EINVAL
+            L.lb_destroy(ctx)
+            continue
+        assert L.lb_adjoint_step_phi(ctx, a1, phi, None) == abi.LB_ESTATE  # no adjoint buffers
+        assert L.lb_step_from_phi(None, a1, a2, phi) == abi.LB_EINVAL
+        assert L.lb_step_from_phi(ctx, a1, a2, None) == abi.LB_EINVAL
+        assert L.lb_step_from_phi(ctx, a1, a2, bad) == abi.LB_EALIGN
+        assert L.lb_step_from_phi(ctx, a1, a1, phi) == abi.LB_EINVAL
+        assert L.lb_step_from_phi(ctx, a1, bad, phi) == abi.LB_EALIGN
+        L.lb_destroy(ctx)
+        b.adj[0], b.adj[1], b.adj_scratch = 0x5000, 0x6000, 0x7000
+        assert L.lb_create(ctypes.byref(p), ctypes.byref(b), None, ctypes.byref(ctx)) == abi.LB_OK
+        assert L.lb_adjoint_step_phi(None, a1, phi, None) == abi.LB_EINVAL
+        assert L.lb_adjoint_step_phi(ctx, a1, None, None) == abi.LB_EINVAL
+        assert L.lb_adjoint_step_phi(ctx, None, phi, None) == abi.LB_EINVAL
+        assert L.lb_adjoint_step_phi(ctx, a1, bad, None) == abi.LB_EALIGN
+        assert L.lb_adjoint_step_phi(ctx, bad, phi, None) == abi.LB_EALIGN
+        L.lb_destroy(ctx)
 
 
 def test_struct_layouts_and_enums_match_the_header(abi, tmp_path):
@@ -273,14 +284,14 @@ def test_status_strings(abi):
 
 def test_shard_sizes_and_validation(abi):
     """An x-slab shard (halo_x): levels hold two halo planes on each side, a
-    face buffer is 24 component planes (+ the FP64 phi_c plane in FP32
+    face buffer is 24 component planes (+ the plane of phi_c words in FP32
     storage); shards reject what they do not support, before any HIP call."""
     for prec, e in ((0, 8), (1, 4)):
         st, s = _query(abi, nx=6, ny=10, nz=12, precision=prec, halo_x=1)
         assert st == abi.LB_OK
         assert s.stride_elems >= (6 + 4) * 10 * 12
         a = 10 * 12
-        assert s.face_bytes == (24 * a * e + (a * 8 if e == 4 else 0) + 255) // 256 * 256
+        assert s.face_bytes == (24 * a * e + (a * 4 if e == 4 else 0) + 255) // 256 * 256
         st, s0 = _query(abi, nx=6, ny=10, nz=12, precision=prec)
         assert st == abi.LB_OK and s0.face_bytes == 0
     for kw, code in ((dict(nx=1), "LB_ESHAPE"), (dict(coupling=1), "LB_EINVAL"),

@@ -185,14 +185,13 @@ def test_fd_adjoint_fp32_flowing_state(coupling):
 @pytest.mark.parametrize("layout,v", [("soa", 0), ("aos", 0), ("aosoa", 32)])
 def test_fd_adjoint_layouts_bit_identical(precision, layout, v, coupling):
     """The adjoint reads the saved levels through the context's layout: dL/dphi0
-    and dL/d(A, B, kappa) are bit-identical to the row-blocked default's, and
-    lb_adjoint_step_next (which this scheme does not need) changes nothing."""
+    and dL/d(A, B, kappa) are bit-identical to the row-blocked default's."""
     shape, T = (6, 5, 64), 4
     phi0 = lbinputs.spinodal_phi0(shape, seed=23, amp=0.3)
     f0 = _flowing_f0(shape, 24)
     dphi = torch.tensor(lbinputs.random_field(shape, 4), device="cuda:0")
     out = []
-    for lay, vv, use_next in (("rows", 0, False), (layout, v, True)):
+    for lay, vv in (("rows", 0), (layout, v)):
         lb = make_lb(shape, precision=precision, adjoint=True, order_param="fd", layout=lay,
                      aosoa_len=vv, coupling=coupling)
         lb.init_phi(phi0)
@@ -204,6 +203,6 @@ def test_fd_adjoint_layouts_bit_identical(precision, layout, v, coupling):
         dth = torch.zeros(3, dtype=torch.float64, device="cuda:0")
         lb.adjoint_seed(dphi)
         for t in reversed(range(T)):
-            lb.adjoint_step(states[t], dth, next_state=states[t + 1] if use_next else None)
+            lb.adjoint_step(states[t], dth)
         out.append((lb.adjoint_phi0().cpu().numpy(), dth.cpu().numpy()))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])

@@ -185,25 +185,28 @@ def test_force_adjoint_fp32_close_to_fp64():
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_dev"])
 @pytest.mark.parametrize("layout,v", [("rows", 0), ("soa", 0), ("aosoa", 32)])
-def test_force_adjoint_step_next_and_layouts_bit_identical(prec, layout, v):
-    """lb_adjoint_step_next (FP32: phi of level t from level t+1's reference
-    field) and every layout give gradients bit-identical to lb_adjoint_step
-    on the row-blocked default, over 5 reverse steps."""
+def test_force_adjoint_step_phi_and_layouts_bit_identical(prec, layout, v):
+    """lb_adjoint_step_phi (phi of level t stored by the forward's
+    lb_step_from_phi) and every layout give gradients bit-identical to
+    lb_adjoint_step on the row-blocked default, over 5 reverse steps."""
     shape, T = (6, 5, 64), 5
     phi0 = lbinputs.spinodal_phi0(shape, seed=23, amp=0.3)
     dphi = torch.tensor(lbinputs.random_field(shape, 4), device="cuda:0")
     out = []
-    for lay, vv, use_next in (("rows", 0, False), (layout, v, True)):
+    for lay, vv, use_phi in (("rows", 0, False), (layout, v, True)):
         lb = make_lb(shape, precision=prec, adjoint=True, coupling="force", layout=lay,
                      aosoa_len=vv)
         lb.init_phi(phi0)
-        states = [lb.get_state()]
+        states, phis = [lb.get_state()], []
         for _ in range(T):
-            lb.step(1)
-            states.append(lb.get_state())
+            nxt = lb.new_state()
+            ph = torch.empty(shape, dtype=torch.float64, device="cuda:0")
+            lb.step_from(states[-1], nxt, phi_out=ph)
+            states.append(nxt)
+            phis.append(ph)
         dth = torch.zeros(3, dtype=torch.float64, device="cuda:0")
         lb.adjoint_seed(dphi)
         for t in reversed(range(T)):
-            lb.adjoint_step(states[t], dth, next_state=states[t + 1] if use_next else None)
+            lb.adjoint_step(states[t], dth, phi=phis[t] if use_phi else None)
         out.append((lb.adjoint_phi0().cpu().numpy(), dth.cpu().numpy()))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])

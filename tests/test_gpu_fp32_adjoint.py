@@ -129,49 +129,25 @@ def test_adjoint_fp32_close_to_fp64():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_dev"])
-@pytest.mark.parametrize("shape", [(6, 5, 7), (5, 4, 128)])
-def test_adjoint_step_next_bit_exact(prec, shape):
-    """lb_adjoint_step_next (phi of level t taken from level t+1's reference
-    field in FP32 storage) gives bit-identical adjoint levels and parameter
-    gradients to lb_adjoint_step (phi recomputed), over 6 reverse steps.
-    (5, 4, 128) is made of one full tile, which the FP32 kernel marches with
-    its pipelined path."""
-    print(f"[adjoint next] {prec} {shape}", flush=True)
-    T = 6
-    phi0 = lbinputs.spinodal_phi0(shape, seed=5, amp=0.3)
-    dphi = torch.tensor(lbinputs.random_field(shape, 9), device="cuda:0")
-    lb = make_lb(shape, precision=prec, adjoint=True, tau_f=0.8, tau_g=1.3)
-    lb.init_phi(phi0)
-    states = [lb.get_state()]
-    for _ in range(T):
-        lb.step(1)
-        states.append(lb.get_state())
-    out = []
-    for use_next in (False, True):
-        dth = torch.zeros(3, dtype=torch.float64, device="cuda:0")
-        lb.adjoint_seed(dphi)
-        for t in reversed(range(T)):
-            lb.adjoint_step(states[t], dth, next_state=states[t + 1] if use_next else None)
-        out.append((lb.adjoint_phi0().cpu().numpy(), dth.cpu().numpy()))
-    assert np.array_equal(out[0][0], out[1][0])
-    assert np.array_equal(out[0][1], out[1][1])
-
-
 @pytest.mark.parametrize("coupling", ["stress", "force"])
 @pytest.mark.parametrize("kernel", ["fused", "two_pass"])
+@pytest.mark.parametrize("taus", [(1.0, 1.0), (0.8, 1.3)])
 @pytest.mark.parametrize("shape", [(6, 5, 7), (5, 4, 128)])
-def test_adjoint_step_phi_bit_exact(coupling, kernel, shape):
-    """FP64: phi stored by lb_step_from_phi is the level's phi bit for bit,
-    and lb_adjoint_step_phi with it gives the adjoint levels and parameter
-    gradients of lb_adjoint_step bit for bit, over 5 reverse steps."""
+def test_adjoint_step_phi_bit_exact(prec, coupling, kernel, taus, shape):
+    """phi stored by lb_step_from_phi is the level's phi bit for bit, and
+    lb_adjoint_step_phi with it gives the adjoint levels and parameter
+    gradients of lb_adjoint_step (phi recomputed) bit for bit, over 5 reverse
+    steps.  (5, 4, 128) is made of one full tile, which the FP32 kernel
+    marches with its pipelined path."""
     from paper_1609_01479_amd._abi import LbError
-    print(f"[adjoint phi] {coupling} {kernel} {shape}", flush=True)
+    print(f"[adjoint phi] {prec} {coupling} {kernel} tau {taus} {shape}", flush=True)
     T = 5
     phi0 = lbinputs.spinodal_phi0(shape, seed=29, amp=0.3)
     dphi = torch.tensor(lbinputs.random_field(shape, 6), device="cuda:0")
     out = []
     for use_phi in (False, True):
-        lb = make_lb(shape, adjoint=True, coupling=coupling, kernel=kernel)
+        lb = make_lb(shape, precision=prec, adjoint=True, coupling=coupling, kernel=kernel,
+                     tau_f=taus[0], tau_g=taus[1])
         lb.init_phi(phi0)
         states = [lb.get_state()]
         phis = []
@@ -193,17 +169,16 @@ def test_adjoint_step_phi_bit_exact(coupling, kernel, shape):
                     lg.cpu().numpy()))
     for a, b in zip(*out):
         assert np.array_equal(a, b)
-    # FP32 storage and the finite-difference scheme reject the calls
-    for kw in (dict(precision="fp32_dev"), dict(order_param="fd")):
-        lb = make_lb(shape, adjoint=True, **kw)
-        lb.init_phi(phi0)
-        s0, s1 = lb.get_state(), lb.new_state()
-        ph = torch.empty(shape, dtype=torch.float64, device="cuda:0")
-        with pytest.raises(LbError):
-            lb.step_from(s0, s1, phi_out=ph)
-        lb.adjoint_seed(dphi)
-        with pytest.raises(LbError):
-            lb.adjoint_step(s0, None, phi=ph)
+    # the finite-difference scheme (phi held in the level) rejects the calls
+    lb = make_lb(shape, precision=prec, adjoint=True, order_param="fd")
+    lb.init_phi(phi0)
+    s0, s1 = lb.get_state(), lb.new_state()
+    ph = torch.empty(shape, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(LbError):
+        lb.step_from(s0, s1, phi_out=ph)
+    lb.adjoint_seed(dphi)
+    with pytest.raises(LbError):
+        lb.adjoint_step(s0, None, phi=ph)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_dev"])
@@ -218,7 +193,7 @@ def test_rollout_auto_interval_fits_the_budget_and_keeps_the_gradients(prec):
     tgt = lbinputs.lamellar_target(shape, 8, lbinputs.interface_width(pr["A"], pr["kappa"]))
     probe = make_lb(shape, precision=prec, adjoint=True)
     sb = int(probe.sizes.state_bytes)
-    phib = probe.nsites * 8 if prec == "fp64" else 0
+    phib = probe.nsites * 8
     del probe
     budget = backward_bytes(T, 3, sb, phib)
     print(f"[rollout auto] {prec} state {sb} B, budget {budget} B", flush=True)

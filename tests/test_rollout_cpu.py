@@ -10,10 +10,13 @@ from paper_1609_01479_amd.rollout import backward_bytes, default_interval, inter
 
 def test_backward_bytes_counts_checkpoints_and_segment_buffers():
     s = 1000
-    assert backward_bytes(200, 1, s) == 200 * s                  # every state kept
+    assert backward_bytes(200, 1, s) == (200 + 2) * s            # every state kept, 2 scratch
+    assert backward_bytes(200, 2, s) == (100 + 2) * s
     assert backward_bytes(200, 200, s) == (1 + 199) * s          # one checkpoint, 199 buffers
     assert backward_bytes(200, 15, s) == (14 + 14) * s
-    assert backward_bytes(200, 15, s, phi_bytes=7) == 28 * s + 14 * 7
+    # phi fields: one per segment, one per recomputed level
+    assert backward_bytes(200, 15, s, phi_bytes=7) == 28 * s + (14 + 14) * 7
+    assert backward_bytes(200, 1, s, phi_bytes=7) == 202 * s + 200 * 7
     assert backward_bytes(10, 50, s) == backward_bytes(10, 10, s)  # k is capped at T
 
 
@@ -22,7 +25,7 @@ def test_interval_for_budget_is_the_smallest_fitting_interval(T):
     s = 336 << 20
     least = min(backward_bytes(T, k, s) for k in range(1, T + 1)) // s
     prev = None
-    for states in sorted({T, max(least, T // 2 + 1), max(least, 3 * math.isqrt(T)), least},
+    for states in sorted({T + 2, max(least, T // 2 + 2), max(least, 3 * math.isqrt(T)), least},
                          reverse=True):
         budget = states * s
         k = interval_for_budget(T, s, budget)
@@ -32,7 +35,7 @@ def test_interval_for_budget_is_the_smallest_fitting_interval(T):
         if prev is not None:
             assert k >= prev  # less memory, more recomputation
         prev = k
-    assert interval_for_budget(T, s, T * s) == 1
+    assert interval_for_budget(T, s, backward_bytes(T, 1, s)) == 1
 
 
 def test_interval_for_budget_refuses_a_budget_below_the_minimum():
