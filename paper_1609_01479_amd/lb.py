@@ -345,8 +345,19 @@ def copy_probe_gbps(nbytes: int, reps: int = 20, device="cuda:0") -> float:
     call = lambda: check(L.lb_copy_probe(ctypes.c_void_p(a.data_ptr()),  # noqa: E731
                                          ctypes.c_void_p(b.data_ptr()), ctypes.c_size_t(nbytes),
                                          ctypes.c_void_p(stream.cuda_stream)), "lb_copy_probe")
-    for _ in range(3):
-        call()
+    # warm-up: at least 3 calls and 30 ms of copying (after host work or an
+    # idle spell the GPU runs its first tens of milliseconds of work slowly)
+    w0 = torch.cuda.Event(enable_timing=True)
+    w1 = torch.cuda.Event(enable_timing=True)
+    n, done = 3, 0.0
+    while done < 30.0:
+        w0.record(stream)
+        for _ in range(n):
+            call()
+        w1.record(stream)
+        w1.synchronize()
+        done += w0.elapsed_time(w1)
+        n *= 2
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
