@@ -29,6 +29,50 @@ def test_fp32_dev_matches_oracle_short():
     assert np.abs(u - ru).max() <= 1e-7
 
 
+def _phic_words(lb, state):
+    """The reference field of an FP32-storage level as stored: one 32-bit
+    word per site, after the f and g regions."""
+    st = int(lb.sizes.stride_elems)
+    off = 2 * 19 * st * 4
+    return state[off:off + 4 * lb.nsites].view(torch.int32).cpu().numpy()
+
+
+def _high_words(phi):
+    """The high 32 bits of each value's binary64 encoding."""
+    a = np.ascontiguousarray(np.asarray(phi, dtype=np.float64)).reshape(-1)
+    return (a.view(np.int64) >> 32).astype(np.int32)
+
+
+@pytest.mark.parametrize("coupling,kernel", [("stress", "fused"), ("stress", "two_pass"),
+                                             ("force", "fused"), ("force", "two_pass")])
+@pytest.mark.parametrize("shape", [(7, 6, 130), (5, 4, 256)])
+def test_fp32_reference_field_is_the_high_word_of_phi(coupling, kernel, shape):
+    """The 32-bit reference order parameter of FP32 storage: after
+    lb_init_phi it holds the high word of each site's phi0, after
+    lb_import_dist that of sum_i g_i, and every step (either coupling, either
+    kernel, full and ragged tiles) writes the high word of the phi it forms
+    for the level it leaves, the field lb_moments returns bit for bit.
+    (7, 6, 130) has ragged tiles only; (5, 4, 256) two full 4 x 128 tiles,
+    which the FP32 step marches with its pipelined path."""
+    print(f"[phi_c] {coupling} {kernel} {shape}", flush=True)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=8, amp=0.4)
+    lb = make_lb(shape, precision="fp32_dev", coupling=coupling, kernel=kernel, tau_f=0.8,
+                 tau_g=1.3)
+    lb.init_phi(phi0)
+    assert np.array_equal(_phic_words(lb, lb.get_state()), _high_words(phi0))
+    for _ in range(3):
+        phi_t = lb.phi().cpu().numpy()
+        lb.step(1)
+        assert np.array_equal(_phic_words(lb, lb.get_state()), _high_words(phi_t))
+    f, g = lb.export_dist()
+    lb.import_dist(f, g)
+    gh = g.cpu().numpy()
+    gsum = gh[0].copy()
+    for i in range(1, 19):
+        gsum += gh[i]  # index order, as the import sums
+    assert np.array_equal(_phic_words(lb, lb.get_state()), _high_words(gsum))
+
+
 def test_fp32_dev_droplet_phi_error_vs_fp64():
     """A tanh droplet with noise, 400 steps: max |phi32 - phi64| <= 1e-5."""
     shape = (48, 48, 48)
