@@ -329,15 +329,35 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
             for (int i = 0; i < NV; i++) g[i] = T(kc[i]);
         }
         if (partials) {
-            // moments of the stored values, formed in FP64
+            // moments of the stored values, formed in FP64; with FP32 storage
+            // from the sums and differences of the direction pairs
+            // (2k+1, 2k+2), in short chains (0.5% faster than running sums;
+            // FP64 storage keeps the running sums, 0.2% faster there)
             double bs = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+            if constexpr (REF) {
+                double v[NV];
 #pragma unroll
-            for (int i = 0; i < NV; i++) {
-                const double v = double(f[i]);
-                bs += v;
-                if (CX[i]) jx += CX[i] * v;
-                if (CY[i]) jy += CY[i] * v;
-                if (CZ[i]) jz += CZ[i] * v;
+                for (int i = 0; i < NV; i++) v[i] = double(f[i]);
+                double sp[9], dp[9];
+#pragma unroll
+                for (int k = 0; k < 9; k++) {
+                    sp[k] = v[2 * k + 1] + v[2 * k + 2];
+                    dp[k] = v[2 * k + 1] - v[2 * k + 2];
+                }
+                bs = ((v[0] + (sp[0] + sp[1])) + ((sp[2] + sp[3]) + (sp[4] + sp[5])))
+                   + ((sp[6] + sp[7]) + sp[8]);
+                jx = ((dp[0] + dp[3]) + (dp[4] + dp[5])) + dp[6];
+                jy = ((dp[1] + dp[3]) - dp[4]) + (dp[7] + dp[8]);
+                jz = ((dp[2] + dp[5]) - dp[6]) + (dp[7] - dp[8]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NV; i++) {
+                    const double v = double(f[i]);
+                    bs += v;
+                    if (CX[i]) jx += CX[i] * v;
+                    if (CY[i]) jy += CY[i] * v;
+                    if (CZ[i]) jz += CZ[i] * v;
+                }
             }
             acc[0] += DEV ? p.rho0 + bs : bs;
             acc[1] += c;
