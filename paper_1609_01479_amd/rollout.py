@@ -7,8 +7,9 @@ recomputation: the forward keeps the state every k steps (k = ceil(sqrt(T))
 by default); the backward takes each checkpoint in reverse order,
 recomputes the k - 1 later states of its segment with lb_step_from (each
 written once, straight into its segment buffer), and walks the adjoint back
-through them.  Memory: ceil(T/k) + k - 1 states instead of T, plus, for the
-LB order parameter, FP64 phi fields (8 bytes per site each) that hand phi of
+through them.  Memory: ceil(T/k) + max(k - 1, 2) states instead of T (the
+checkpoints, and the segment buffers or the forward's two scratch levels),
+plus, for the LB order parameter, FP64 phi fields (8 bytes per site each) that hand phi of
 each level to its reverse step, so that none runs a phi pass: k - 1 for the
 recomputed levels, and one per segment for its last level, stored by the
 forward step that leaves it.  The forward writes each checkpoint with the
@@ -170,11 +171,12 @@ def rollout(phi0: torch.Tensor, A, B, kappa, nsteps: int, *, interval: int | str
     floats).  order_param: "lb" (distribution g) or "fd" (finite-difference
     phi field); coupling: "stress" (Pi in f^eq) or "force" (F = -div Pi).
     interval: the checkpoint interval k (default ceil(sqrt(T))), or "auto":
-    the smallest k whose backward fits in memory_budget bytes (default 90% of
-    the device's free memory, counting what torch's allocator holds cached),
-    i.e. as many checkpoints as HBM holds and as few recomputed steps.  The gradients do not depend on k (the recomputed
-    states are bit-identical).  info (a dict, optional) receives
-    "interval", the k used."""
+    the smallest k whose peak memory (backward_bytes) fits in memory_budget
+    bytes (default 90% of the device's free memory, counting what torch's
+    allocator holds cached), i.e. as many checkpoints as HBM holds and as
+    few recomputed steps.  The gradients do not depend on k (the recomputed
+    states are bit-identical).  info (a dict, optional) receives "interval",
+    the k used."""
     dev = phi0.device
     as_t = lambda v: v if torch.is_tensor(v) else torch.tensor(float(v), dtype=torch.float64,  # noqa: E731
                                                                device=dev)
