@@ -142,6 +142,33 @@ def test_adjoint_matches_oracle_reverse_mode_8cubed(interval):
         assert abs(a - b) <= 1e-9 * abs(b), (name, a, b)
 
 
+@pytest.mark.parametrize("T,interval", [(0, None), (1, None), (1, 1), (2, 1), (2, 2), (3, 2),
+                                        (3, 5), (3, "auto")])
+def test_adjoint_short_rollouts(T, interval):
+    """Rollouts of 0 to 3 steps, with intervals below, at and above T and
+    "auto": the rollout's own first and last segments (a final step into a
+    scratch level, the forward's phi of each segment's last level) against
+    the oracle's reverse mode; with no step, dL/dphi0 = phi0 - target and no
+    parameter gradient."""
+    shape = (6, 5, 7)
+    kw = dict(tau_f=0.8, tau_g=1.3)
+    pr = dict(lbinputs.SPINODAL_PARAMS, **kw)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=61)
+    tgt = lbinputs.lamellar_target(shape, 6, lbinputs.interface_width(pr["A"], pr["kappa"]))
+    print(f"[adjoint] short rollout T={T} interval={interval}", flush=True)
+    L, gphi, gA, gB, gk = _gpu_grads(shape, T, phi0, tgt, interval=interval, **kw)
+    if T == 0:
+        assert np.array_equal(gphi, phi0 - tgt)
+        assert gA == gB == gk == 0.0
+        return
+    rL, rphi, rA, rB, rk = R.loss_and_grads(phi0, tgt, pr["A"], pr["B"], pr["kappa"], T,
+                                            pr["gamma"], pr["tau_f"], pr["tau_g"], pr["rho0"])
+    assert abs(L - rL) <= 1e-12 * abs(rL)
+    assert rel_err(gphi, rphi) <= 1e-10, rel_err(gphi, rphi)
+    for name, a, b in (("A", gA, rA), ("B", gB, rB), ("kappa", gk, rk)):
+        assert abs(a - b) <= 1e-9 * abs(b), (name, a, b)
+
+
 def test_adjoint_noncubic_default_taus():
     shape = (6, 5, 7)
     T = 12
