@@ -234,6 +234,38 @@ def test_step_from_matches_step_bit_exact(prec):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_dev"])
+@pytest.mark.parametrize("op,coupling", [("lb", "stress"), ("lb", "force"), ("fd", "stress"),
+                                         ("fd", "force")])
+def test_zero_steps_change_nothing(prec, op, coupling):
+    """nsteps = 0 is a no-op for lb_step, lb_step_sums and
+    lb_step_sums_noalloc: the state stays bit for bit, no sums are written,
+    and the next step is the step it would have been."""
+    def snap(lb):
+        f, g = lb.export_dist()
+        return [t.cpu().numpy() for t in (f, g, *lb.moments()) if t is not None]
+
+    shape = (6, 5, 70)
+    phi0 = lbinputs.spinodal_phi0(shape, seed=4, amp=0.3)
+    a = make_lb(shape, precision=prec, order_param=op, coupling=coupling)
+    b = make_lb(shape, precision=prec, order_param=op, coupling=coupling)
+    for lb in (a, b):
+        lb.init_phi(phi0)
+        lb.step(3)
+    ref = snap(a)
+    out = torch.full((2, 5), 7.0, dtype=torch.float64, device="cuda:0")
+    a.step(0)
+    a.step_sums(0, out)
+    a.step_sums_noalloc(0, out)
+    for x, y in zip(snap(a), ref):
+        assert np.array_equal(x, y)
+    assert bool((out == 7.0).all())
+    a.step(1)
+    b.step(1)
+    for x, y in zip(snap(a), snap(b)):
+        assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("prec,kernel", [("fp64", "fused"), ("fp64", "two_pass"),
                                          ("fp32_dev", "fused"), ("fp32_dev", "two_pass")])
 def test_step_sums_history(prec, kernel):
