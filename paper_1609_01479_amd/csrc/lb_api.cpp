@@ -214,6 +214,7 @@ lb_status lb_query_sizes(const lb_params* p, lb_sizes* out)
     k.nx = p->nx;
     k.ny = p->ny;
     k.nz = p->nz;
+    k.fd = fd;
     const lbk::TileCfg tc = lbk::tile_config(k, p->segment_x, p->precision == LB_FP32_DEV);
     k.nsites = int(n);
     size_t nparts = std::max<size_t>(size_t(tc.ntiles) * tc.nseg, lbk::kMaxPartialBlocks);

@@ -3,7 +3,7 @@
 // The step of the paper's Ludwig timestep (Sec. 2.1.1) -- order-parameter
 // gradients, chemical stress, collision, propagation -- runs as ONE kernel,
 // k_step_fused_f32 / _f64: each workgroup owns a (y, z) tile of 4 x 128 (or
-// 8 x 64) sites and marches along x over a segment of planes.  For plane x it needs phi at
+// 8 x 64, or 2 x 256) sites and marches along x over a segment of planes.  For plane x it needs phi at
 // planes x-1, x, x+1 (7-point stencil); phi(x+1) is formed from the pulled g
 // of plane x+1, which the same threads keep in registers for plane x+1's own
 // collision one iteration later.  phi on the tile's (y, z) halo ring is
@@ -32,9 +32,11 @@ namespace {
 // site per thread of a kFused-thread workgroup: 4 x 128 (measured on MI355X at
 // 256^3 against 4 x 64 and 8 x 64: the longer z runs give each component
 // stream 512-byte (FP32) contiguous pieces), or 8 x 64 where that covers nz
-// with fewer idle lanes (e.g. nz = 192: 64 + 64 + 64 instead of 128 + 64).
+// with fewer idle lanes (e.g. nz = 192: 64 + 64 + 64 instead of 128 + 64), or
+// with FP32 storage and nz = 256, 2 x 256: whole rows (tile_config).
 constexpr int kFused = 512;
-// one thread per halo-ring cell (2 rows, 2 columns, 4 corners)
+// one thread per halo-ring cell (2 rows, 2 columns, 4 corners; a 2 x 256
+// tile spans the periodic z extent and pulls the 2 rows only)
 static_assert(2 * 128 + 2 * (kFused / 128) + 4 <= kFused, "halo ring larger than the workgroup");
 static_assert(2 * 64 + 2 * (kFused / 64) + 4 <= kFused, "halo ring larger than the workgroup");
 
@@ -248,9 +250,14 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     const unsigned rowsite = unsigned(sy * p.nz + sz);
 
     // halo ring: rows y0-1 and y0+tya, columns z0-1 and z0+tza, and in FP32
-    // mode the 4 corners; cell r at LDS position (rly, rlz)
-    const int nside = 2 * tza + 2 * tya;
-    const int nring = nside + (REF ? 4 : 0);
+    // mode the 4 corners; cell r at LDS position (rly, rlz).  A tile that
+    // spans the whole periodic z extent pulls only the two rows: its halo
+    // columns are its own last and first columns, which put() below copies
+    // into LDS columns 0 and tza + 1 as it stores them (the corners with
+    // the rows' cells).
+    const bool fullz = tza == p.nz;
+    const int nside = fullz ? 2 * tza : 2 * tza + 2 * tya;
+    const int nring = nside + (REF && !fullz ? 4 : 0);
     auto ring_cell = [&](int r, int& a, int& c) {
         if (r < tza) { a = 0; c = r + 1; }
         else if (r < 2 * tza) { a = tya + 1; c = r - tza + 1; }
@@ -265,6 +272,15 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     const int ry = wrapg(y0 + rly - 1, p.ny), rz = wrapg(z0 + rlz - 1, p.nz);
     const Yz9 rrow = yz9<T>(p, ring ? ry : 0, ring ? rz : 0);
     const unsigned rsite = unsigned((ring ? ry : 0) * p.nz + (ring ? rz : 0));
+    // phi into LDS cell (a, c) of slot sl, and into the wrap column of a
+    // full-z tile
+    auto put = [&](int sl, int a, int c, double v) __attribute__((always_inline)) {
+        ph[sl][a][c] = v;
+        if (fullz) {
+            if (c == tza) ph[sl][a][0] = v;
+            if (c == 1) ph[sl][a][tza + 1] = v;
+        }
+    };
 
     // plane indices run from x0-2 to x1+2 (nx may be 1): wrap without
     // division or branches (valid on [-2nx, 4nx)).  An x-slab shard has no
@@ -395,7 +411,11 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
     const bool full = tya == TY && tza == TZ;
     if (PIPE && full) {
         constexpr int NW = kFused / 64;
-        constexpr int RPW = (2 * TZ + 2 * TY + 4 + NW - 1) / NW;  // ring cells per wave
+        // ring cells per wave (a 2 x 256 tile is always full-z: its ring is
+        // the two rows, one cell per lane)
+        constexpr int RPW_ALL = (2 * TZ + 2 * TY + 4 + NW - 1) / NW;
+        constexpr int RPW = RPW_ALL <= 64 ? RPW_ALL : 2 * TZ / NW;
+        static_assert(RPW <= 64, "more ring cells than lanes");
         const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
         int qly, qlz;
         ring_cell(min(w * RPW + (lane < RPW ? lane : 0), nring - 1), qly, qlz);
@@ -428,10 +448,10 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
                 fq[i] = ldc<SMALL>(sF, pf[1 - CX[i]], i, compb, row.o[1 - CY[i]][1 - CZ[i]]);
             __builtin_amdgcn_sched_barrier(0);
         };
-        ph[0][ly + 1][lz + 1] = pull_phi(x0 - 1, row, rowsite, nullptr, nullptr);
-        ph[0][qly][qlz] = pull_phi(x0 - 1, qrow, qsite, nullptr, nullptr);
-        ph[1][ly + 1][lz + 1] = pull_phi(x0, row, rowsite, kcur, &pccur);
-        ph[1][qly][qlz] = pull_phi(x0, qrow, qsite, nullptr, nullptr);
+        put(0, ly + 1, lz + 1, pull_phi(x0 - 1, row, rowsite, nullptr, nullptr));
+        put(0, qly, qlz, pull_phi(x0 - 1, qrow, qsite, nullptr, nullptr));
+        put(1, ly + 1, lz + 1, pull_phi(x0, row, rowsite, kcur, &pccur));
+        put(1, qly, qlz, pull_phi(x0, qrow, qsite, nullptr, nullptr));
         issue(x0);
         // enter the loop with these loads completed (an empty asm reading
         // each register makes the compiler wait for it here): the waits at
@@ -448,10 +468,10 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
             double a = 0.0, b = 0.0;
 #pragma unroll
             for (int i = 0; i < NV; i++) a += double(gq[i]);
-            ph[sn][ly + 1][lz + 1] = REF ? phic_value(pq) + a : a;
+            put(sn, ly + 1, lz + 1, REF ? phic_value(pq) + a : a);
 #pragma unroll
             for (int i = 0; i < NV; i++) b += double(rq[i]);
-            ph[sn][qly][qlz] = REF ? phic_value(rpq) + b : b;
+            put(sn, qly, qlz, REF ? phic_value(rpq) + b : b);
             lds_barrier();
 #pragma unroll
             for (int i = 0; i < NV; i++) {
@@ -478,10 +498,10 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
         unsigned pccur = 0, pcnext = 0;
         // warm-up: phi at planes x0-1 (slot 0) and x0 (slot 1), keeping
         // plane x0's populations
-        if (active) ph[0][ly + 1][lz + 1] = pull_phi(x0 - 1, row, rowsite, nullptr, nullptr);
-        if (ring) ph[0][rly][rlz] = pull_phi(x0 - 1, rrow, rsite, nullptr, nullptr);
-        if (active) ph[1][ly + 1][lz + 1] = pull_phi(x0, row, rowsite, kcur, &pccur);
-        if (ring) ph[1][rly][rlz] = pull_phi(x0, rrow, rsite, nullptr, nullptr);
+        if (active) put(0, ly + 1, lz + 1, pull_phi(x0 - 1, row, rowsite, nullptr, nullptr));
+        if (ring) put(0, rly, rlz, pull_phi(x0 - 1, rrow, rsite, nullptr, nullptr));
+        if (active) put(1, ly + 1, lz + 1, pull_phi(x0, row, rowsite, kcur, &pccur));
+        if (ring) put(1, rly, rlz, pull_phi(x0, rrow, rsite, nullptr, nullptr));
         T fn[NV];
         auto pull_f = [&](int X) __attribute__((always_inline)) {
             const O pbx[3] = {pbase(X - 1), pbase(X), pbase(X + 1)};
@@ -495,11 +515,11 @@ __device__ __forceinline__ void step_fused_body(const KParams& p, const TileCfg&
             const int sn = kk & 3, sc = (kk - 1) & 3, sp = (kk - 2) & 3;
             T f[NV];
             if (active) {
-                ph[sn][ly + 1][lz + 1] = pull_phi(x + 1, row, rowsite, knext, &pcnext);
+                put(sn, ly + 1, lz + 1, pull_phi(x + 1, row, rowsite, knext, &pcnext));
 #pragma unroll
                 for (int i = 0; i < NV; i++) kst[i][threadIdx.x] = knext[i];
             }
-            if (ring) ph[sn][rly][rlz] = pull_phi(x + 1, rrow, rsite, nullptr, nullptr);
+            if (ring) put(sn, rly, rlz, pull_phi(x + 1, rrow, rsite, nullptr, nullptr));
             lds_barrier();
             if (active) {
 #pragma unroll
@@ -545,6 +565,7 @@ struct Fused<float> {
     template <bool COLL>
     static K pick(bool small, int tz)
     {
+        if (tz == 256) return small ? k_step_fused_f32<true, 256, COLL> : k_step_fused_f32<false, 256, COLL>;
         if (tz == 64) return small ? k_step_fused_f32<true, 64, COLL> : k_step_fused_f32<false, 64, COLL>;
         return small ? k_step_fused_f32<true, 128, COLL> : k_step_fused_f32<false, 128, COLL>;
     }
@@ -763,11 +784,17 @@ constexpr int kCUs = 256;
 
 TileCfg tile_config(const KParams& p, int segment_x, bool fp32)
 {
-    (void)fp32;  // same tiling for both storage modes
     TileCfg tc;
     // tile width: 128 unless 64 leaves fewer idle lanes along z
     const long long w128 = 128LL * ((p.nz + 127) / 128), w64 = 64LL * ((p.nz + 63) / 64);
     tc.tz = w64 < w128 ? 64 : 128;
+    // FP32 storage with z-rows of 256 sites (the LB step; the
+    // finite-difference kernel has its own widths): 2 x 256 tiles, each a
+    // pair of whole rows, which need no z halo and read every component's
+    // row in one contiguous piece.  Measured at 256^3, same buffers: 2.5%
+    // faster than 4 x 128 (the memory-only twin 3.4%); in FP64 storage 3.8%
+    // slower, so FP64 keeps 4 x 128.
+    if (fp32 && p.nz == 256 && !p.fd) tc.tz = 256;
     const int ty = kFused / tc.tz;
     tc.nty = (p.ny + ty - 1) / ty;
     tc.ntz = (p.nz + tc.tz - 1) / tc.tz;
