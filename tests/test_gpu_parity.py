@@ -156,13 +156,14 @@ def test_conservation_and_sums_match_oracle():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_dev"])
-@pytest.mark.parametrize("shape", [(13, 10, 70), (13, 8, 256)])
+@pytest.mark.parametrize("shape", [(13, 10, 70), (13, 8, 256), (13, 7, 256)])
 def test_kernel_variants_and_segments_agree(prec, shape):
     """The single-pass kernel is independent of its x-segment length (bit for
     bit: every site's arithmetic is the same), and agrees with the two-pass
-    variant.  (13, 8, 256) is made of full 4 x 128 tiles only, which the FP32
-    kernel marches with its software-pipelined path; (13, 10, 70) of ragged
-    tiles only."""
+    variant.  (13, 8, 256) is made of full tiles only (FP64 4 x 128; FP32
+    2 x 256, whole rows), which the FP32 kernel marches with its
+    software-pipelined path; (13, 7, 256) adds a one-row tail tile to those;
+    (13, 10, 70) has ragged tiles only, each spanning the z extent."""
     print(f"[variants] {prec} {shape}", flush=True)
     phi0 = lbinputs.spinodal_phi0(shape, seed=21, amp=0.3)
     out = {}
@@ -179,7 +180,7 @@ def test_kernel_variants_and_segments_agree(prec, shape):
     assert max(errs.values()) <= (1e-14 if prec == "fp64" else 1e-6), errs
 
 
-@pytest.mark.parametrize("shape", [(12, 8, 128), (10, 6, 320), (3, 4, 128)])
+@pytest.mark.parametrize("shape", [(12, 8, 128), (10, 6, 320), (3, 4, 128), (6, 5, 256)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32_dev"])
 def test_full_and_mixed_tiles(prec, shape):
     """Lattices made of full 4 x 128 tiles (the FP32 kernel's pipelined,
