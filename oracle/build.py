@@ -22,7 +22,7 @@ def build(verbose: bool = False) -> str:
 
 
 def build_sanitize_check(verbose: bool = False) -> str:
-    """The oracle and a driver of all its entry points, built with
+    """The oracle and a program calling all its entry points, built with
     AddressSanitizer and UndefinedBehaviorSanitizer (host code only; any
     report aborts the run with a nonzero exit)."""
     cmd = ["gcc", "-O1", "-g", "-fopenmp", "-std=c11", "-fno-omit-frame-pointer",

@@ -1,7 +1,8 @@
 """The CPU oracle under AddressSanitizer and UndefinedBehaviorSanitizer: a
-driver of every oracle entry point (oracle/sanitize_check.c) on small
-lattices, extents 1 and 2 included, both couplings and both order-parameter
-schemes, one and four threads.  Any sanitizer report aborts the driver."""
+program that calls every oracle entry point (oracle/sanitize_check.c) on
+small lattices, extents 1 and 2 included, both couplings and both
+order-parameter schemes, one and four threads.  Any sanitizer report aborts
+the program."""
 from __future__ import annotations
 
 import subprocess
